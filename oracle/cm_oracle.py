@@ -1,0 +1,678 @@
+"""FP64 CPU oracle for smooth contact-manifold generation.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import or call this
+module; only ``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s CPU
+baseline leg use it.  It shares no code with the HIP library.
+
+It is a plain, slow, obviously-correct transcription of the method of
+"Smoothly Differentiable and Efficiently Vectorizable Contact Manifold
+Generation" (arXiv 2602.20304) in float64 PyTorch CPU ops, one body pair at a
+time.  Gradients come from PyTorch autograd of this forward (the analytic
+gradient of exactly this function).
+
+Sections of the paper followed (cited per function below):
+  * Sec. III           smooth operators (sigmoid comparison, tanh sign,
+                       softplus, softclip, soft argmin, LSE, SoftSort top-K)
+  * Sec. IV-A          problem statement: poses in, K x (p, d, n) out
+  * Sec. IV-B          SDF primitives (convex polyhedron = LSE over planes)
+  * Sec. IV-C          vertex-SDF contacts
+  * Sec. IV-D          E-E witness QP with L2 regularisation, analytic active
+                       set, sign assignment, penetration / nearest-neighbour /
+                       clashing indicators, activity indicator
+  * Supp. C            smooth operator and E-E routine pseudo-code (used as a
+                       description of what is computed, not transcribed)
+
+Readings where the paper is silent or garbled (each is listed in the design doc):
+  R1  unconstrained minimiser is -Q^{-1} c (the text drops the sign)
+  R2  edge minimiser on alpha1 = 1 is -(Q12 + c2)/Q22 (text has a sign slip)
+  R3  the cost of the (alpha1, 0) edge point is J evaluated there (the
+      supplementary pseudo-code multiplies c1 by the wrong variable)
+  R4  the second witness uses the reversed unsigned normal (-n_bar) for its
+      sign test ("vice-versa"), so separated bodies give d1 = d2 = +d_bar
+  R5  every soft temperature is tau; lambda = 0.01 absolute; eps_n = tau^2
+  R6  V-S activity w = sigma(-d/tau) (the penetration test applied to vertices)
+  R7  the fixed-size K manifold: score s = -d + tau log w, hard top-K values
+      of s, SoftSort rows softmax(-|s_[k] - s_i| / tau) over all candidates
+  R8  output normals use the pair convention (pointing from body A to body B)
+  R9  analytic-body meshes: box = 8 corners / 12 edges; sphere = 26 vertices
+      (poles + 3 latitude rings of 8) / 56 edges; capsule = 34 vertices / 72
+      edges; all vertices on the exact surface
+  R10 rounded box: outer half-extents h, rounding radius rho (exact SDF)
+  R11 V-S output normal grad(phi)/sqrt(tau + |grad(phi)|^2); sign and clash
+      tests use the raw SDF gradient
+  R12 broadphase (not in the paper): keep a pair iff its bounding spheres
+      overlap within a margin (default 10 tau), defined in float32
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch
+from scipy.spatial import ConvexHull
+
+DT = torch.float64
+SPHERE, CAPSULE, BOX, POLYTOPE = 0, 1, 2, 3
+LAMBDA_DEFAULT = 0.01
+
+
+def _t(x, requires_grad=False):
+    return torch.as_tensor(np.asarray(x, dtype=np.float64), dtype=DT).clone().requires_grad_(requires_grad)
+
+
+# ============================================================== Sec. III operators
+# Each operator is its plain definition; logaddexp / logsumexp / softmax are the
+# library routines for log(e^a + e^b), log sum exp and normalised exponentials.
+
+def sigmoid(z):
+    """Soft comparison [z > 0] ~ sigma(z) (Sec. III)."""
+    return torch.sigmoid(z)
+
+
+def log_sigmoid(z):
+    """log sigma(z) = -log(1 + e^{-z})."""
+    return -torch.logaddexp(torch.zeros_like(z), -z)
+
+
+def softplus_t(x, tau):
+    """s_+(x) = tau log(1 + exp(x / tau)) (Sec. III)."""
+    return tau * torch.logaddexp(torch.zeros_like(x), x / tau)
+
+
+def clip_s(x, lo, hi, tau):
+    """Soft clip: lo + s_+(x - lo) - s_+(x - hi) (Sec. III)."""
+    return lo + softplus_t(x - lo, tau) - softplus_t(x - hi, tau)
+
+
+def within_s(x, lo, hi, tau):
+    """Soft [lo <= x <= hi] as a product of two soft comparisons (Supp. C)."""
+    return sigmoid((x - lo) / tau) * sigmoid((hi - x) / tau)
+
+
+def log_within_s(x, lo, hi, tau):
+    return log_sigmoid((x - lo) / tau) + log_sigmoid((hi - x) / tau)
+
+
+def argmin_s(c, tau, dim=-1):
+    """Soft argmin: softmax(-c / tau) (Sec. III)."""
+    return torch.softmax(-c / tau, dim=dim)
+
+
+def lse_t(y, tau, dim=-1):
+    """LSE(y) = tau log sum exp(y / tau) (Sec. III)."""
+    return tau * torch.logsumexp(y / tau, dim=dim)
+
+
+def sign_s(x, tau):
+    """Soft sign tanh(x / tau) (Sec. III)."""
+    return torch.tanh(x / tau)
+
+
+# ============================================================== geometry (Sec. IV-A/B)
+
+def _ring_dirs(lat_deg: float):
+    la = math.radians(lat_deg)
+    return [(math.cos(la) * math.cos(2 * math.pi * j / 8), math.cos(la) * math.sin(2 * math.pi * j / 8),
+             math.sin(la)) for j in range(8)]
+
+
+def sphere_mesh_topology():
+    """Reading R9: sphere mesh = south pole, rings at -45, 0, +45 deg, north pole.
+
+    Returns unit directions [26, 3] and edges [56, 2].
+    """
+    dirs = [(0.0, 0.0, -1.0)] + _ring_dirs(-45) + _ring_dirs(0) + _ring_dirs(45) + [(0.0, 0.0, 1.0)]
+    E = []
+    rings = [1, 9, 17]
+    for j in range(8):
+        E.append((0, 1 + j))
+    for r in rings:
+        for j in range(8):
+            E.append((r + j, r + (j + 1) % 8))
+    for r0, r1 in ((1, 9), (9, 17)):
+        for j in range(8):
+            E.append((r0 + j, r1 + j))
+    for j in range(8):
+        E.append((17 + j, 25))
+    return np.array(dirs), np.array(E, dtype=np.int64)
+
+
+def capsule_mesh_topology():
+    """Reading R9: capsule mesh = two hemispheres (pole, 45-deg ring, equator ring).
+
+    Returns unit directions [34, 3], hemisphere side (+1 upper / -1 lower)
+    [34] and edges [72, 2].  Vertex = r * dir + side * h * z.
+    """
+    dirs = [(0.0, 0.0, -1.0)] + _ring_dirs(-45) + _ring_dirs(0) + _ring_dirs(0) + _ring_dirs(45) + [(0.0, 0.0, 1.0)]
+    side = [-1.0] * 17 + [1.0] * 17
+    E = []
+    for j in range(8):
+        E.append((0, 1 + j))
+    for r in (1, 9, 17, 25):
+        for j in range(8):
+            E.append((r + j, r + (j + 1) % 8))
+    for r0, r1 in ((1, 9), (9, 17), (17, 25)):
+        for j in range(8):
+            E.append((r0 + j, r1 + j))
+    for j in range(8):
+        E.append((25 + j, 33))
+    return np.array(dirs), np.array(side), np.array(E, dtype=np.int64)
+
+
+def box_mesh_topology():
+    """Reading R9: 8 corners (bit b of the index selects +h along axis b), 12 edges."""
+    signs = np.array([[1.0 if (i >> a) & 1 else -1.0 for a in range(3)] for i in range(8)])
+    E = [(i, i | bit) for bit in (1, 2, 4) for i in range(8) if not i & bit]
+    return signs, np.array(E, dtype=np.int64)
+
+
+def hull_topology(points: np.ndarray):
+    """Convex hull of the polytope points (Qhull via scipy, a library step).
+
+    Returns (vertex ids into points, sorted ascending), triangles [F, 3] as
+    indices into that vertex list oriented counter-clockwise seen from
+    outside, and unique edges [E, 2] (i < j).
+    """
+    P = np.asarray(points, dtype=np.float64)
+    hull = ConvexHull(P)
+    vid = np.array(sorted(hull.vertices.tolist()), dtype=np.int64)
+    remap = -np.ones(len(P), dtype=np.int64)
+    remap[vid] = np.arange(len(vid))
+    tris = []
+    for simp, eq in zip(hull.simplices, hull.equations):
+        a, b, c = P[simp[0]], P[simp[1]], P[simp[2]]
+        n = np.cross(b - a, c - a)
+        if np.dot(n, eq[:3]) < 0:
+            simp = simp[[0, 2, 1]]
+        tris.append(remap[simp])
+    tris = np.array(tris, dtype=np.int64)
+    es = set()
+    for t in tris:
+        for i, j in ((t[0], t[1]), (t[1], t[2]), (t[2], t[0])):
+            es.add((min(i, j), max(i, j)))
+    edges = np.array(sorted(es), dtype=np.int64)
+    return vid, tris, edges
+
+
+@dataclass
+class OGeom:
+    """Oracle geometry: type, differentiable parameters and mesh topology.
+
+    ``params`` (analytic) or ``points`` (polytope, hull vertices only) are
+    float64 leaf tensors; the mesh vertices and face planes are functions of
+    them, so autograd reaches the geometry parameters.
+    """
+    kind: int
+    params: Optional[torch.Tensor] = None   # [4]
+    points: Optional[torch.Tensor] = None   # [V, 3] hull vertices (polytope)
+    vertex_ids: Optional[np.ndarray] = None # input point index of each hull vertex
+    edges: Optional[np.ndarray] = None      # [E, 2]
+    tris: Optional[np.ndarray] = None       # [F, 3]
+    _aux: Optional[np.ndarray] = None
+
+    def vertices(self) -> torch.Tensor:
+        """Mesh vertices in the body frame (Sec. IV-A: every surface has a mesh)."""
+        if self.kind == POLYTOPE:
+            return self.points
+        p = self.params
+        if self.kind == SPHERE:
+            return p[0] * _t(self._aux)
+        if self.kind == CAPSULE:
+            dirs, side = self._aux
+            return p[0] * _t(dirs) + p[1] * _t(side)[:, None] * _t([0.0, 0.0, 1.0])[None, :]
+        if self.kind == BOX:
+            return _t(self._aux) * p[:3][None, :]
+        raise ValueError(self.kind)
+
+    def planes(self):
+        """Outward unit face normals n_f and offsets o_f = n_f . v (Sec. IV-B, CP)."""
+        V = self.points
+        t = torch.as_tensor(self.tris)
+        v0, v1, v2 = V[t[:, 0]], V[t[:, 1]], V[t[:, 2]]
+        n = torch.linalg.cross(v1 - v0, v2 - v0)
+        n = n / torch.sqrt((n * n).sum(-1, keepdim=True))
+        o = (n * v0).sum(-1)
+        return n, o
+
+
+def make_geom(kind: int, params=None, points=None, requires_grad=False) -> OGeom:
+    if kind == POLYTOPE:
+        vid, tris, edges = hull_topology(points)
+        pts = _t(np.asarray(points, dtype=np.float64)[vid], requires_grad)
+        return OGeom(kind, points=pts, vertex_ids=vid, edges=edges, tris=tris)
+    prm = _t(np.asarray(params, dtype=np.float64)[:4], requires_grad)
+    if kind == SPHERE:
+        dirs, edges = sphere_mesh_topology()
+        return OGeom(kind, params=prm, edges=edges, _aux=dirs)
+    if kind == CAPSULE:
+        dirs, side, edges = capsule_mesh_topology()
+        return OGeom(kind, params=prm, edges=edges, _aux=(dirs, side))
+    if kind == BOX:
+        signs, edges = box_mesh_topology()
+        return OGeom(kind, params=prm, edges=edges, _aux=signs)
+    raise ValueError(kind)
+
+
+def geom_from_set(gs, g: int, requires_grad=False) -> OGeom:
+    return make_geom(int(gs.types[g]), params=gs.params[g], points=gs.points_of(g), requires_grad=requires_grad)
+
+
+def _sgn(x):
+    return torch.where(x >= 0, torch.ones_like(x), -torch.ones_like(x))
+
+
+def sdf_local(G: OGeom, x: torch.Tensor, tau, planes=None, chunk: int = 1 << 22):
+    """Smooth SDF phi and its gradient at body-frame points x [..., 3].
+
+    sphere  |x| - r
+    capsule |x - clamp(x_z, -h, h) z| - r
+    box     rounded box with outer half-extents h and rounding rho (R10)
+    polytope LSE_tau over face planes n_f . x - o_f (Sec. IV-B, CP primitive);
+             gradient = softmax-weighted sum of face normals.
+    """
+    if G.kind == SPHERE:
+        nrm = torch.sqrt((x * x).sum(-1))
+        return nrm - G.params[0], x / nrm[..., None]
+    if G.kind == CAPSULE:
+        r, h = G.params[0], G.params[1]
+        zc = torch.minimum(torch.maximum(x[..., 2], -h), h)
+        y = torch.stack([x[..., 0], x[..., 1], x[..., 2] - zc], dim=-1)
+        nrm = torch.sqrt((y * y).sum(-1))
+        return nrm - r, y / nrm[..., None]
+    if G.kind == BOX:
+        h, rho = G.params[:3], G.params[3]
+        q = torch.abs(x) - (h - rho)
+        qp = torch.clamp(q, min=0.0)
+        s = (qp * qp).sum(-1)
+        outside = (q > 0).any(-1)
+        n_out = torch.sqrt(torch.where(outside, s, torch.ones_like(s)))
+        qmax, jmax = q.max(-1)
+        phi = torch.where(outside, n_out, torch.zeros_like(s)) + torch.clamp(qmax, max=0.0) - rho
+        g_out = _sgn(x) * qp / n_out[..., None]
+        g_in = _sgn(x) * torch.nn.functional.one_hot(jmax, 3).to(DT)
+        g = torch.where(outside[..., None], g_out, g_in)
+        return phi, g
+    if G.kind == POLYTOPE:
+        n, o = planes if planes is not None else G.planes()
+        shp = x.shape[:-1]
+        xf = x.reshape(-1, 3)
+        F = n.shape[0]
+        step = max(1, chunk // max(F, 1))
+        phis, grads = [], []
+        for i in range(0, xf.shape[0], step):
+            y = xf[i:i + step] @ n.T - o[None, :]
+            phis.append(lse_t(y, tau, dim=-1))
+            grads.append(torch.softmax(y / tau, dim=-1) @ n)
+        if not phis:
+            return xf.new_zeros(shp), xf.new_zeros(shp + (3,))
+        return torch.cat(phis).reshape(shp), torch.cat(grads).reshape(shp + (3,))
+    raise ValueError(G.kind)
+
+
+# ============================================================== poses (Sec. IV-A)
+
+def quat_to_R(q: torch.Tensor) -> torch.Tensor:
+    """Rotation matrix of a (w, x, y, z) quaternion after normalisation."""
+    q = q / torch.sqrt((q * q).sum())
+    w, x, y, z = q[0], q[1], q[2], q[3]
+    return torch.stack([
+        torch.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)]),
+        torch.stack([2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)]),
+        torch.stack([2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]),
+    ])
+
+
+def hat(w):
+    z = torch.zeros((), dtype=DT)
+    return torch.stack([torch.stack([z, -w[2], w[1]]), torch.stack([w[2], z, -w[0]]),
+                        torch.stack([-w[1], w[0], z])])
+
+
+def so3_exp(w):
+    th = torch.sqrt((w * w).sum())
+    if float(th) < 1e-12:
+        return torch.eye(3, dtype=DT) + hat(w)
+    K = hat(w / th)
+    return torch.eye(3, dtype=DT) + torch.sin(th) * K + (1 - torch.cos(th)) * (K @ K)
+
+
+def se3_exp(xi):
+    """Exp of a twist (rho, omega) -> (R, t) with t = V(omega) rho."""
+    rho, w = xi[:3], xi[3:]
+    th = torch.sqrt((w * w).sum())
+    R = so3_exp(w)
+    if float(th) < 1e-12:
+        V = torch.eye(3, dtype=DT) + 0.5 * hat(w)
+    else:
+        K = hat(w / th)
+        V = torch.eye(3, dtype=DT) + (1 - torch.cos(th)) / th * K + (th - torch.sin(th)) / th * (K @ K)
+    return R, V @ rho
+
+
+def pose_Rt(pose7, xi=None, exact=False):
+    """(R, t) of a pose given as (qw, qx, qy, qz, tx, ty, tz).
+
+    With a twist xi = (rho, omega) the pose is left-perturbed, T' = Exp(xi) T.
+    ``exact=False`` uses the first-order form (I + [omega]x) which has the same
+    derivative at xi = 0 (used with autograd); ``exact=True`` uses Exp (used
+    for finite differences).
+    """
+    p = torch.as_tensor(np.asarray(pose7, dtype=np.float64), dtype=DT)
+    R = quat_to_R(p[:4])
+    t = p[4:7]
+    if xi is None:
+        return R, t
+    if exact:
+        Rx, tx = se3_exp(xi)
+        return Rx @ R, Rx @ t + tx
+    W = hat(xi[3:])
+    return R + W @ R, t + xi[:3] + W @ t
+
+
+# ============================================================== one body pair
+
+def sdf_world(G: OGeom, R, t, X, tau, planes=None):
+    """phi_G and grad phi_G (world frame) at world points X [..., 3]."""
+    xl = (X - t) @ R
+    phi, gl = sdf_local(G, xl, tau, planes)
+    return phi, gl @ R.T
+
+
+def _dot(u, v):
+    return (u * v).sum(-1)
+
+
+def ee_qp(a0, a1, b0, b1, tau, lam=LAMBDA_DEFAULT):
+    """Smoothed analytic active-set solution of the regularised E-E QP (Sec. IV-D-2).
+
+    Edges e1(al1) = a0 + al1 (a1 - a0), e2(al2) = b0 + al2 (b1 - b0); objective
+    |e1 - e2|^2 + lam [(al1 - 1/2)^2 + (al2 - 1/2)^2], written (up to a constant
+    and a factor 2) as J(al) = 1/2 al^T Q al + c^T al with A = [t1, -t2],
+    b = a0 - b0, Q = A^T A + lam I, c = A^T b - lam/2 (1, 1).
+    Steps: (i) unconstrained minimiser, (ii) the four soft-clipped box-edge
+    minimisers blended by a soft argmin of their costs, (iii) soft indicator
+    that the unconstrained minimiser is inside [0,1]^2, (iv) blend.
+    Broadcasts over leading dimensions.
+    """
+    t1 = a1 - a0
+    t2 = b1 - b0
+    bv = a0 - b0
+    Q11 = _dot(t1, t1) + lam
+    Q12 = -_dot(t1, t2)
+    Q22 = _dot(t2, t2) + lam
+    c1 = _dot(bv, t1) - 0.5 * lam
+    c2 = -_dot(bv, t2) - 0.5 * lam
+    Q11, Q12, Q22, c1, c2 = torch.broadcast_tensors(Q11, Q12, Q22, c1, c2)
+
+    def J(x1, x2):
+        q11, q12, q22, k1, k2 = (v[..., None] for v in (Q11, Q12, Q22, c1, c2))
+        return 0.5 * (q11 * x1 * x1 + 2.0 * q12 * x1 * x2 + q22 * x2 * x2) + k1 * x1 + k2 * x2
+
+    # (i) unconstrained minimiser al_u = -Q^{-1} c   (reading R1)
+    det = Q11 * Q22 - Q12 * Q12
+    au1 = (-c1 * Q22 + Q12 * c2) / det
+    au2 = (-c2 * Q11 + Q12 * c1) / det
+    # (ii) minimisers along the four box edges, soft-clipped (reading R2)
+    one, zero = torch.ones_like(Q12), torch.zeros_like(Q12)
+    x_a = clip_s(-(Q12 + c2) / Q22, 0.0, 1.0, tau)     # on al1 = 1
+    x_b = clip_s(-c2 / Q22, 0.0, 1.0, tau)             # on al1 = 0
+    x_c = clip_s(-(Q12 + c1) / Q11, 0.0, 1.0, tau)     # on al2 = 1
+    x_d = clip_s(-c1 / Q11, 0.0, 1.0, tau)             # on al2 = 0
+    cand1 = torch.stack([one, zero, x_c, x_d], dim=-1)
+    cand2 = torch.stack([x_a, x_b, one, zero], dim=-1)
+    costs = J(cand1, cand2)                              # (reading R3)
+    pi = argmin_s(costs, tau, dim=-1)
+    ac1 = (pi * cand1).sum(-1)
+    ac2 = (pi * cand2).sum(-1)
+    # (iii) soft indicator that al_u is inside the box; (iv) blend
+    con = within_s(au1, 0.0, 1.0, tau) * within_s(au2, 0.0, 1.0, tau)
+    log_con = log_within_s(au1, 0.0, 1.0, tau) + log_within_s(au2, 0.0, 1.0, tau)
+    al1 = con * au1 + (1.0 - con) * ac1
+    al2 = con * au2 + (1.0 - con) * ac2
+    return dict(al1=al1, al2=al2, au1=au1, au2=au2, con=con, log_con=log_con, costs=costs)
+
+
+def ee_witness(a0, a1, b0, b1, al1, al2, eps_n):
+    """Witness points, unsigned distance and unsigned normal (Sec. IV-D-3).
+
+    e_b = edge_b(al_b); de = e1 - e2; d_bar = |de|; n_bar = de / sqrt(|de|^2 + eps).
+    """
+    e1 = a0 + al1[..., None] * (a1 - a0)
+    e2 = b0 + al2[..., None] * (b1 - b0)
+    de = e1 - e2
+    dsq = _dot(de, de)
+    return e1, e2, torch.sqrt(dsq), de / torch.sqrt(dsq + eps_n)[..., None]
+
+
+def ee_sign(gA_e1, gB_e2, nbar, tau):
+    """Soft signs of the two witnesses (Sec. IV-D-3, reading R4).
+
+    gamma1 = softsign(grad phi_B(e2) . n_bar), gamma2 = softsign(grad phi_A(e1) . (-n_bar)).
+    """
+    return sign_s(_dot(gB_e2, nbar), tau), sign_s(_dot(gA_e1, -nbar), tau)
+
+
+def vs_normal(g, tau):
+    """V-S normal grad(phi) / sqrt(tau + |grad(phi)|^2) (Sec. IV-B, reading R11)."""
+    return g / torch.sqrt(tau + _dot(g, g))[..., None]
+
+
+def nn_log_indicators(dbar, tau):
+    """log of the nearest-neighbour soft indicators (eq. nn_check).
+
+    Row-wise soft argmin over l of -D[k, :] / tau and column-wise over k.
+    """
+    return torch.log_softmax(-dbar / tau, dim=1), torch.log_softmax(-dbar / tau, dim=0)
+
+
+def pair_candidates(GA: OGeom, RA, tA, GB: OGeom, RB, tB, tau, lam=LAMBDA_DEFAULT, eps_n=None):
+    """All contact candidates of one body pair (A, B) in world coordinates.
+
+    Returns dict of p [C,3], nu [C,3] (pair convention, A -> B), d [C],
+    logw [C] with the candidate order: A's vertices, B's vertices, then E-E
+    pairs (k, l) row-major with witness 1 before witness 2.
+    """
+    if eps_n is None:
+        eps_n = tau * tau
+    planesA = GA.planes() if GA.kind == POLYTOPE else None
+    planesB = GB.planes() if GB.kind == POLYTOPE else None
+    vA = GA.vertices() @ RA.T + tA
+    vB = GB.vertices() @ RB.T + tB
+
+    # ---- vertex-SDF contacts (Sec. IV-C; normals R11; weights R6)
+    phiB_v, gB_v = sdf_world(GB, RB, tB, vA, tau, planesB)
+    phiA_v, gA_v = sdf_world(GA, RA, tA, vB, tau, planesA)
+    vs_p = torch.cat([vA, vB])
+    vs_nu = torch.cat([-vs_normal(gB_v, tau), vs_normal(gA_v, tau)])   # pair convention (R8)
+    vs_d = torch.cat([phiB_v, phiA_v])
+    vs_logw = log_sigmoid(-vs_d / tau)
+
+    # ---- edge-edge contacts over all |E_A| x |E_B| edge pairs (Sec. IV-D)
+    eA, eB = GA.edges, GB.edges
+    a0, a1 = vA[eA[:, 0]][:, None, :], vA[eA[:, 1]][:, None, :]
+    b0, b1 = vB[eB[:, 0]][None, :, :], vB[eB[:, 1]][None, :, :]
+    qp = ee_qp(a0, a1, b0, b1, tau, lam)
+    e1, e2, dbar, nbar = ee_witness(a0, a1, b0, b1, qp["al1"], qp["al2"], eps_n)
+
+    # SDF queries at the witness points
+    phiB_e1, _ = sdf_world(GB, RB, tB, e1, tau, planesB)
+    _, gA_e1 = sdf_world(GA, RA, tA, e1, tau, planesA)
+    phiA_e2, _ = sdf_world(GA, RA, tA, e2, tau, planesA)
+    _, gB_e2 = sdf_world(GB, RB, tB, e2, tau, planesB)
+
+    gam1, gam2 = ee_sign(gA_e1, gB_e2, nbar, tau)
+    d1, d2 = gam1 * dbar, gam2 * dbar
+    n1 = gam1[..., None] * nbar           # pushes A away from B
+    n2 = gam2[..., None] * (-nbar)        # pushes B away from A
+    # penetration (eq. sdf_check), clashing, nearest neighbours (eq. nn_check)
+    log_pen1 = log_sigmoid(-phiB_e1 / tau)
+    log_pen2 = log_sigmoid(-phiA_e2 / tau)
+    log_cl = log_sigmoid(-_dot(gA_e1, gB_e2) / tau)
+    log_nn1, log_nn2 = nn_log_indicators(dbar, tau)
+    # activity indicator Gamma_b = con * pen_b * nn_b * cl, in the log domain
+    logG1 = qp["log_con"] + log_pen1 + log_nn1 + log_cl
+    logG2 = qp["log_con"] + log_pen2 + log_nn2 + log_cl
+
+    ee_p = torch.stack([e1, e2], dim=2).reshape(-1, 3)
+    ee_nu = torch.stack([-n1, n2], dim=2).reshape(-1, 3)   # pair convention (R8)
+    ee_d = torch.stack([d1, d2], dim=2).reshape(-1)
+    ee_logw = torch.stack([logG1, logG2], dim=2).reshape(-1)
+    out = dict(p=torch.cat([vs_p, ee_p]), nu=torch.cat([vs_nu, ee_nu]),
+               d=torch.cat([vs_d, ee_d]), logw=torch.cat([vs_logw, ee_logw]))
+    out["extra"] = dict(qp=qp, dbar=dbar, e1=e1, e2=e2, gam1=gam1, gam2=gam2, log_pen1=log_pen1,
+                        log_pen2=log_pen2, log_cl=log_cl, log_nn1=log_nn1, log_nn2=log_nn2,
+                        n_vs=vs_d.shape[0])
+    return out
+
+
+def manifold(c, tau, K: int):
+    """Fixed-size K-contact manifold from candidates (reading R7, SoftSort Sec. III).
+
+    s_i = -d_i + tau log w_i; s_[1] >= ... >= s_[K] the K largest scores;
+    Gamma_ki = softmax_i(-|s_[k] - s_i| / tau); outputs are Gamma @ (p, nu, d, w).
+    """
+    s = -c["d"] + tau * c["logw"]
+    top = torch.topk(s, K, sorted=True).values
+    G = torch.softmax(-torch.abs(top[:, None] - s[None, :]) / tau, dim=1)
+    w = torch.exp(c["logw"])
+    return dict(p=G @ c["p"], nu=G @ c["nu"], d=G @ c["d"], w=G @ w, s_top=top)
+
+
+def collide_pair(GA, poseA, GB, poseB, tau, K, lam=LAMBDA_DEFAULT, eps_n=None, xiA=None, xiB=None,
+                 exact_exp=False):
+    """Contact manifold g_{A,B} of one pair (Sec. IV-A): K x (p, nu, d, w)."""
+    RA, tA = pose_Rt(poseA, xiA, exact_exp)
+    RB, tB = pose_Rt(poseB, xiB, exact_exp)
+    c = pair_candidates(GA, RA, tA, GB, RB, tB, tau, lam, eps_n)
+    return manifold(c, tau, K)
+
+
+# ============================================================== broadphase (R12, float32)
+
+def bound_radius_f32(kind: int, params, points) -> np.float32:
+    """Bounding radius about the body origin, in float32 arithmetic.
+
+    sphere r; capsule h + r; box sqrt((hx^2 + hy^2) + hz^2);
+    polytope sqrt(max_v ((x^2 + y^2) + z^2)).
+    """
+    f = np.float32
+    p = np.asarray(params, dtype=np.float32)
+    if kind == SPHERE:
+        return f(p[0])
+    if kind == CAPSULE:
+        return f(p[1]) + f(p[0])
+    if kind == BOX:
+        return np.sqrt((p[0] * p[0] + p[1] * p[1]) + p[2] * p[2], dtype=np.float32)
+    P = np.asarray(points, dtype=np.float32)
+    n2 = (P[:, 0] * P[:, 0] + P[:, 1] * P[:, 1]) + P[:, 2] * P[:, 2]
+    return np.sqrt(n2.max(), dtype=np.float32)
+
+
+def default_margin_f32(tau) -> np.float32:
+    return np.float32(10.0) * np.float32(tau)
+
+
+def broadphase(batch, margin=None):
+    """Kept pairs and per-scene offsets (R12).
+
+    Keep (a, b) iff d2 <= r*r with dx = tb_x - ta_x etc.,
+    d2 = (dx*dx + dy*dy) + dz*dz and r = (R_a + R_b) + margin, every operation
+    rounded to float32.  Scene-major order; all i<j pairs per scene unless an
+    explicit candidate list is given (kept in its order).
+    Returns pairs int32 [2, n] and offsets int32 [S+1].
+    """
+    f = np.float32
+    m = default_margin_f32(batch.tau) if margin is None or margin < 0 else f(margin)
+    gs = batch.geoms
+    Rg = np.array([bound_radius_f32(int(gs.types[g]), gs.params[g], gs.points_of(g)) for g in range(gs.n)],
+                  dtype=np.float32)
+    sc, a, b = batch.candidate_pairs()
+    Rb = Rg[batch.body_geom]
+    T = batch.pose[4:7].astype(np.float32)
+    dx = T[0, b] - T[0, a]
+    dy = T[1, b] - T[1, a]
+    dz = T[2, b] - T[2, a]
+    d2 = (dx * dx + dy * dy) + dz * dz
+    r = (Rb[a] + Rb[b]) + m
+    keep = d2 <= r * r
+    cnt = np.bincount(sc[keep], minlength=batch.n_scenes) if len(sc) else np.zeros(batch.n_scenes, np.int64)
+    off = np.zeros(batch.n_scenes + 1, dtype=np.int64)
+    off[1:] = np.cumsum(cnt)
+    pairs = np.stack([a[keep], b[keep]]).astype(np.int32)
+    return pairs, off.astype(np.int32)
+
+
+# ============================================================== batch helpers
+
+class GeomCache:
+    def __init__(self, gs, requires_grad=False):
+        self.gs = gs
+        self.rg = requires_grad
+        self.cache = {}
+
+    def __getitem__(self, g):
+        g = int(g)
+        if g not in self.cache:
+            self.cache[g] = geom_from_set(self.gs, g, self.rg)
+        return self.cache[g]
+
+
+def collide_batch(batch, pair_list=None, lam=LAMBDA_DEFAULT, eps_n=None, margin=None, cache=None):
+    """Forward manifold for the kept pairs of a batch (or a given pair subset).
+
+    Returns (pairs [2,n], offsets [S+1], outputs dict of numpy float64 arrays
+    p [n,K,3], nu [n,K,3], d [n,K], w [n,K]).
+    """
+    if pair_list is None:
+        pairs, offsets = broadphase(batch, margin)
+    else:
+        pairs, offsets = np.asarray(pair_list, dtype=np.int32), None
+    cache = cache or GeomCache(batch.geoms)
+    n, K = pairs.shape[1], batch.K
+    out = dict(p=np.zeros((n, K, 3)), nu=np.zeros((n, K, 3)), d=np.zeros((n, K)), w=np.zeros((n, K)))
+    with torch.no_grad():
+        for i in range(n):
+            a, b = int(pairs[0, i]), int(pairs[1, i])
+            GA, GB = cache[batch.body_geom[a]], cache[batch.body_geom[b]]
+            m = collide_pair(GA, batch.pose[:, a], GB, batch.pose[:, b], batch.tau, K, lam, eps_n)
+            for k in ("p", "nu", "d", "w"):
+                out[k][i] = m[k].numpy()
+    return pairs, offsets, out
+
+
+def pair_grad(GA, poseA, GB, poseB, tau, K, cot, lam=LAMBDA_DEFAULT, eps_n=None):
+    """Gradient of L = <cot, outputs> for one pair by autograd of the forward.
+
+    cot: dict with any of p [K,3], nu [K,3], d [K], w [K] (numpy).
+    Returns dict: xiA [6], xiB [6] (left tangents (rho, omega)), geomA, geomB
+    (params [4] or hull-vertex points [V,3]), tau, and the forward values.
+    GA / GB must have been built with requires_grad=True (they may be the same
+    object when a geometry is shared).
+    """
+    xiA = torch.zeros(6, dtype=DT, requires_grad=True)
+    xiB = torch.zeros(6, dtype=DT, requires_grad=True)
+    tau_t = torch.tensor(float(tau), dtype=DT, requires_grad=True)
+    m = collide_pair(GA, poseA, GB, poseB, tau_t, K, lam, eps_n, xiA, xiB)
+    L = torch.zeros((), dtype=DT)
+    for k, v in cot.items():
+        L = L + (m[k] * torch.as_tensor(np.asarray(v, dtype=np.float64))).sum()
+    leaves = [xiA, xiB, tau_t]
+    ga = GA.points if GA.kind == POLYTOPE else GA.params
+    gb = GB.points if GB.kind == POLYTOPE else GB.params
+    geo = [x for x in ([ga] if gb is ga else [ga, gb]) if x.requires_grad]
+    grads = torch.autograd.grad(L, leaves + geo, allow_unused=True)
+    z = lambda g, ref: torch.zeros_like(ref) if g is None else g
+    out = dict(xiA=z(grads[0], xiA).numpy(), xiB=z(grads[1], xiB).numpy(), tau=float(z(grads[2], tau_t)),
+               L=float(L.detach()), fwd={k: v.detach().numpy() for k, v in m.items()})
+    gmap = {id(x): z(g, x).detach().numpy() for x, g in zip(geo, grads[3:])}
+    out["geomA"] = gmap.get(id(ga), np.zeros(tuple(ga.shape)))
+    out["geomB"] = gmap.get(id(gb), np.zeros(tuple(gb.shape)))
+    return out
+
+
+def pose_tangent_to_world(xi):
+    """Split a (rho, omega) tangent gradient into its two 3-vectors."""
+    xi = np.asarray(xi)
+    return xi[:3], xi[3:]

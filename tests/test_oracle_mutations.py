@@ -1,0 +1,95 @@
+"""Plant plausible mistakes in the oracle (on the CPU) and check that the pins
+catch every one of them.
+
+Each mutation rewrites one line of one oracle function (source-level, in
+memory) and monkeypatches the mutant in; at least one of the listed pins must
+then fail.  This is what makes the pins evidence: a dropped term, a wrong sign,
+a swapped index or a transposed operand in the oracle does not go unnoticed.
+"""
+import inspect
+import textwrap
+
+import pytest
+
+from oracle import cm_oracle as O
+from tests import oracle_pins as P
+
+# (oracle function, original text, mutated text, pins expected to catch it)
+MUTATIONS = [
+    ("ee_qp", "au1 = (-c1 * Q22 + Q12 * c2) / det", "au1 = (c1 * Q22 - Q12 * c2) / det",
+     [P.pin_qp_hard_limit_segments, P.pin_qp_regularised_limit]),                      # text's sign slip
+    ("ee_qp", "x_a = clip_s(-(Q12 + c2) / Q22, 0.0, 1.0, tau)", "x_a = clip_s(-(Q12 - c2) / Q22, 0.0, 1.0, tau)",
+     [P.pin_qp_hard_limit_segments, P.pin_qp_regularised_limit]),                      # text's edge minimiser
+    ("ee_qp", "costs = J(cand1, cand2)",
+     "costs = J(cand1, cand2) + torch.stack([zero, zero, zero, c1 * (x_b - x_d)], dim=-1)",
+     [P.pin_qp_hard_limit_segments, P.pin_qp_regularised_limit, P.pin_qp_edge_swap_symmetry]),  # listing cost bug
+    ("ee_qp", "Q11 = _dot(t1, t1) + lam", "Q11 = _dot(t1, t1)",
+     [P.pin_qp_regularised_limit, P.pin_qp_edge_swap_symmetry]),                      # dropped regulariser
+    ("ee_qp", "con = within_s(au1, 0.0, 1.0, tau) * within_s(au2, 0.0, 1.0, tau)",
+     "con = within_s(au1, 0.0, 1.0, tau) * within_s(au1, 0.0, 1.0, tau)",
+     [P.pin_qp_hard_limit_segments, P.pin_qp_edge_swap_symmetry]),                    # wrong index
+    ("ee_qp", "pi = argmin_s(costs, tau, dim=-1)", "pi = argmin_s(-costs, tau, dim=-1)",
+     [P.pin_qp_hard_limit_segments, P.pin_qp_regularised_limit]),                      # soft argmax
+    ("ee_sign", "sign_s(_dot(gA_e1, -nbar), tau)", "sign_s(_dot(gA_e1, nbar), tau)",
+     [P.pin_crossing_edges_sign]),                                                     # literal "vice versa"
+    ("ee_sign", "return sign_s(_dot(gB_e2, nbar), tau)", "return sign_s(_dot(gB_e2, -nbar), tau)",
+     [P.pin_crossing_edges_sign]),
+    ("nn_log_indicators", "torch.log_softmax(-dbar / tau, dim=1), torch.log_softmax(-dbar / tau, dim=0)",
+     "torch.log_softmax(-dbar / tau, dim=0), torch.log_softmax(-dbar / tau, dim=1)",
+     [P.pin_nn_rows_columns]),                                                         # transposed nn
+    ("vs_normal", "torch.sqrt(tau + _dot(g, g))", "torch.sqrt(_dot(g, g))",
+     [P.pin_vs_normal_sphere]),                                                        # dropped tau
+    ("pair_candidates", "vs_nu = torch.cat([-vs_normal(gB_v, tau), vs_normal(gA_v, tau)])",
+     "vs_nu = torch.cat([vs_normal(gB_v, tau), vs_normal(gA_v, tau)])",
+     [P.pin_vs_normal_sphere, P.pin_pair_swap_antisymmetry]),                          # V-S normal sign
+    ("pair_candidates", "vs_logw = log_sigmoid(-vs_d / tau)", "vs_logw = log_sigmoid(vs_d / tau)",
+     [P.pin_vs_weights_point_in_polytope]),                                            # inverted pen test
+    ("pair_candidates", "log_pen1 = log_sigmoid(-phiB_e1 / tau)", "log_pen1 = log_sigmoid(-phiA_e2 / tau)",
+     [P.pin_pair_swap_antisymmetry]),                                                  # wrong SDF for pen
+    ("manifold", "torch.softmax(-torch.abs(top[:, None] - s[None, :]) / tau, dim=1)",
+     "torch.softmax(-(top[:, None] - s[None, :]) / tau, dim=1)",
+     [P.pin_manifold_properties]),                                                     # SoftSort without |.|
+    ("manifold", "top = torch.topk(s, K, sorted=True).values", "top = torch.topk(s, K, largest=False).values",
+     [P.pin_manifold_properties]),                                                     # bottom-K
+    ("quat_to_R", "[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)]",
+     "[1 - 2 * (y * y + z * z), 2 * (x * y + w * z), 2 * (x * z + w * y)]",
+     [P.pin_quaternion_rotation]),                                                     # sign in R
+    ("pose_Rt", "return R + W @ R, t + xi[:3] + W @ t", "return R + R @ W, t + R @ xi[:3]",
+     [P.pin_gradient_joint_motion_identities]),                                        # body-frame twist
+    ("sdf_local", "return nrm - r, y / nrm[..., None]", "return nrm - r, -y / nrm[..., None]",
+     [P.pin_sdf_gradients_fd]),                                                        # capsule normal sign
+    ("sdf_local", "zc = torch.minimum(torch.maximum(x[..., 2], -h), h)", "zc = torch.maximum(x[..., 2], -h)",
+     [P.pin_analytic_sdf_brute_force]),                                                # capsule clamp
+    ("sdf_local", "phi = torch.where(outside, n_out, torch.zeros_like(s)) + torch.clamp(qmax, max=0.0) - rho",
+     "phi = torch.where(outside, n_out, torch.zeros_like(s)) + torch.clamp(qmax, max=0.0) + rho",
+     [P.pin_analytic_sdf_brute_force]),                                                # rounding sign
+    ("planes", "o = (n * v0).sum(-1)", "o = (n * (v0 - v1)).sum(-1)",
+     [P.pin_hull_counts, P.pin_polytope_inside_delaunay]),                             # plane offset
+    ("hull_topology", "if np.dot(n, eq[:3]) < 0:", "if np.dot(n, eq[:3]) > 0:",
+     [P.pin_hull_counts, P.pin_polytope_inside_delaunay]),                             # inward normals
+    ("broadphase", "keep = d2 <= r * r", "keep = d2 <= r",
+     [P.pin_broadphase_f32]),                                                          # missing square
+]
+
+
+def _mutant(fn_name, old, new):
+    owner = O.OGeom if fn_name == "planes" else O
+    src = textwrap.dedent(inspect.getsource(getattr(owner, fn_name)))
+    assert src.count(old) == 1, (fn_name, old)
+    ns = {}
+    exec(compile(src.replace(old, new), f"<mutant {fn_name}>", "exec"), O.__dict__, ns)
+    return owner, ns[fn_name]
+
+
+@pytest.mark.parametrize("mut", MUTATIONS, ids=[f"{m[0]}:{i}" for i, m in enumerate(MUTATIONS)])
+def test_mutation_is_caught(mut, monkeypatch):
+    fn_name, old, new, pins = mut
+    owner, fn = _mutant(fn_name, old, new)
+    monkeypatch.setattr(owner, fn_name, fn)
+    caught = []
+    for pin in pins:
+        try:
+            pin()
+        except (AssertionError, RuntimeError, ValueError, IndexError):
+            caught.append(pin.__name__)
+    assert caught, f"mutation of {fn_name} ({new!r}) was not caught by {[p.__name__ for p in pins]}"
