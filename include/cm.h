@@ -1,0 +1,242 @@
+/*
+ * cm.h -- C ABI of the MI355X (gfx950) contact-manifold library.
+ *
+ * Computes, for every colliding pair of rigid bodies in a batch of scenes, the
+ * smooth contact manifold of "Smoothly Differentiable and Efficiently
+ * Vectorizable Contact Manifold Generation" (arXiv 2602.20304):
+ *   - vertex-SDF contacts, both ways (Sec. IV-C; SDF primitives Sec. IV-B),
+ *   - edge-edge contacts for all edge pairs: smoothed analytic active-set
+ *     witness QP with L2 regularisation, soft sign, penetration,
+ *     nearest-neighbour, clashing and activity indicators (Sec. IV-D),
+ *   - a fixed-size manifold of K contacts per pair, obtained by SoftSort
+ *     (Sec. III, soft top-K) over all candidates with scores
+ *     s = -d + tau * log(w).
+ * Inputs: geometries, poses and the smoothing factor tau (problem statement,
+ * Sec. IV-A).  Outputs per kept pair: K contact points, pair normals (from
+ * body A towards body B), signed distances and activity weights.
+ *
+ * Conventions
+ *   - Every function returns cm_status (CM_OK = 0, negative = error).  No C++
+ *     exception crosses the ABI.  cm_last_error() gives a message for the last
+ *     failing call on a context.
+ *   - "device" pointers are HIP device memory on the context's device; "host"
+ *     pointers are ordinary CPU memory.  The caller owns every pointer it
+ *     passes; device buffers must stay valid until the work queued on the
+ *     given stream has completed.  The context owns the geometry tables and
+ *     its workspace.
+ *   - Streams are passed as void* holding a hipStream_t (NULL = default
+ *     stream).  Work is queued asynchronously; argument errors are reported
+ *     synchronously, device-side data errors (an out-of-range geometry id,
+ *     more kept pairs than the output capacity) are recorded in a device
+ *     error word that cm_check_errors() reads (it synchronises the stream).
+ *   - A context is not thread-safe; the server functions are.
+ *   - Layouts are structure-of-arrays.  Poses: float [7][n_bodies] with rows
+ *     (qw, qx, qy, qz, tx, ty, tz); the quaternion need not be normalised.
+ *   - Geometry type ids / params:
+ *       CM_SPHERE   (r)            mesh: 26 vertices, 56 edges on the sphere
+ *       CM_CAPSULE  (r, half_len)  core segment on local z; mesh 34 V / 72 E
+ *       CM_BOX      (hx, hy, hz, rounding)  outer half-extents; mesh 8 V / 12 E
+ *       CM_POLYTOPE convex hull of the given points; SDF = tau-LSE over the
+ *                   face planes (convex-polyhedron primitive, Sec. IV-B)
+ */
+#ifndef CM_H
+#define CM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CM_OK = 0,
+  CM_ERR_INVALID_ARG = -1,
+  CM_ERR_OOM = -2,
+  CM_ERR_DEVICE = -3,
+  CM_ERR_NOT_READY = -4,
+  CM_ERR_REJECTED = -5,
+  CM_ERR_NOT_FOUND = -6,
+  CM_ERR_CAPACITY = -7,
+  CM_ERR_GEOMETRY = -8
+} cm_status;
+
+enum { CM_SPHERE = 0, CM_CAPSULE = 1, CM_BOX = 2, CM_POLYTOPE = 3 };
+
+/* Largest K the kernels support. */
+#define CM_MAX_K 32
+
+typedef struct cm_context cm_context;
+typedef struct cm_server cm_server;
+
+/* Method parameters (Sec. III / IV).  tau is the single smoothing factor used
+ * by every soft operator; lambda_reg is the L2 regularisation weight of the
+ * E-E QP (Sec. IV-D-2); eps_n is the epsilon of the unsigned E-E normal
+ * Delta e / sqrt(|Delta e|^2 + eps_n) (Sec. IV-D-3); cull_margin is the
+ * broadphase margin.  Negative values select the defaults: lambda_reg 0.01,
+ * eps_n tau^2, cull_margin 10 * tau (computed in float32). */
+typedef struct {
+  float tau;
+  float lambda_reg;
+  float eps_n;
+  float cull_margin;
+  int32_t K;          /* contacts per pair, 1..CM_MAX_K */
+  uint32_t flags;     /* reserved, must be 0 */
+} cm_params;
+
+/* A batch of scenes.  Bodies of scene s are body_offsets[s] .. [s+1]-1.
+ * Candidate pairs: all i < j within each scene when cand_offsets is NULL,
+ * otherwise cand_pairs[0][c], cand_pairs[1][c] (global body ids) for the
+ * candidates cand_offsets[s] .. [s+1]-1 of scene s.  All arrays device. */
+typedef struct {
+  int32_t n_scenes;
+  int32_t n_bodies;
+  const int32_t* body_offsets;   /* [n_scenes + 1] */
+  const int32_t* body_geom;      /* [n_bodies] geometry id per body */
+  const float* pose;             /* [7][n_bodies] */
+  const int32_t* cand_offsets;   /* [n_scenes + 1] or NULL */
+  const int32_t* cand_pairs;     /* [2][n_cand] or NULL */
+  int32_t n_cand;
+} cm_batch;
+
+/* Caller-owned output buffers (device).  Pair p, contact k lives at index
+ * p * K + k of each SoA row; point / normal are [3][capacity * K]. */
+typedef struct {
+  int32_t capacity;      /* rows available for kept pairs */
+  int32_t* n_pairs;      /* [1]  number of kept pairs (may exceed capacity) */
+  int32_t* pair_offsets; /* [n_scenes + 1] exclusive scan of kept pairs per scene */
+  int32_t* pairs;        /* [2][capacity] body ids (A, B) of each kept pair */
+  float* point;          /* [3][capacity * K] world-frame contact points */
+  float* normal;         /* [3][capacity * K] pair normals, A -> B */
+  float* dist;           /* [capacity * K] signed distances */
+  float* weight;         /* [capacity * K] activity weights in [0, 1] */
+} cm_manifold;
+
+/* Cotangents of the manifold outputs (device, same layout as cm_manifold;
+ * any may be NULL = zero). */
+typedef struct {
+  const float* g_point;
+  const float* g_normal;
+  const float* g_dist;
+  const float* g_weight;
+} cm_cotangent;
+
+/* Gradient outputs (device).  Every buffer is overwritten (not accumulated).
+ * g_pose:     [6][n_bodies] left-tangent gradient (rho, omega) of each body:
+ *             T' = Exp(xi) T, so a world point moves by rho + omega x p.
+ * g_vertices: [3][n_vertices_total] per geometry vertex (context vertex pool;
+ *             cm_geometry_info gives each geometry's offset).  For polytopes
+ *             these are the hull vertices in ascending input-point order.
+ * g_params:   [4][n_geometries] per analytic-geometry parameter.
+ * g_tau:      [1] derivative with respect to tau.
+ * Gradients with respect to geometry are summed over every use. */
+typedef struct {
+  float* g_pose;
+  float* g_vertices;
+  float* g_params;
+  float* g_tau;
+} cm_grads;
+
+typedef struct {
+  int32_t type;
+  int32_t n_vertices, n_edges, n_faces;
+  int32_t vertex_offset;   /* into the context vertex pool */
+  float bound_radius;      /* float32 bounding radius about the body origin */
+} cm_geometry_info_t;
+
+/* ---------------------------------------------------------------- context */
+cm_status cm_context_create(int device, cm_context** out);
+cm_status cm_context_destroy(cm_context* ctx);
+const char* cm_status_str(cm_status s);
+const char* cm_last_error(cm_context* ctx);
+/* Synchronise `stream` and report device-side errors recorded since the last
+ * check (CM_ERR_CAPACITY, CM_ERR_NOT_FOUND), then clear them. */
+cm_status cm_check_errors(cm_context* ctx, void* stream);
+
+/* ---------------------------------------------------------------- geometry
+ * Create n geometries (Sec. IV-A: every surface has a mesh and an SDF).
+ * types[n], params[n*4] (host); POLYTOPE point sets are points[3*k] for
+ * k in pt_offsets[i] .. pt_offsets[i+1]-1 (host, float xyz).  The library
+ * builds the meshes (convex hull for polytopes: vertices, edges, outward
+ * triangle planes), bounding radii and device tables.  out_ids[n] receives
+ * the new ids.  Fails with CM_ERR_GEOMETRY for degenerate point sets. */
+cm_status cm_geometry_create(cm_context* ctx, int32_t n, const int32_t* types, const float* params,
+                             const int64_t* pt_offsets, const float* points, int32_t* out_ids);
+cm_status cm_geometry_info(cm_context* ctx, int32_t id, cm_geometry_info_t* out);
+/* Host copy of a geometry's mesh: vertices[3*nv] (xyz), edges[2*ne], faces[3*nf]
+ * (any may be NULL). */
+cm_status cm_geometry_mesh(cm_context* ctx, int32_t id, float* vertices, int32_t* edges, int32_t* faces);
+int32_t cm_geometry_count(cm_context* ctx);
+int32_t cm_vertex_pool_size(cm_context* ctx);
+
+/* ---------------------------------------------------------------- forward
+ * Broadphase (keep a candidate pair iff its float32 bounding spheres overlap
+ * within cull_margin), per-scene compaction, then the contact manifold of
+ * every kept pair (Sec. IV-C, IV-D, soft top-K of Sec. III).  The plain
+ * kernel: one workgroup per pair, static round-robin over pairs. */
+cm_status cm_collide(cm_context* ctx, const cm_batch* batch, const cm_params* prm, cm_manifold* out,
+                     void* stream);
+
+/* Same results through the fused batched path: pairs are ordered by cost and
+ * pulled from a device work queue by a persistent grid; the whole sequence is
+ * captured once per (batch shape, stream) in a hipGraph and replayed. */
+cm_status cm_collide_fused(cm_context* ctx, const cm_batch* batch, const cm_params* prm, cm_manifold* out,
+                           void* stream);
+
+/* ---------------------------------------------------------------- backward
+ * Vector-Jacobian product of the manifold (the gradient the paper obtains by
+ * automatic differentiation, Sec. V-C): recomputes every per-pair
+ * intermediate from the inputs and the kept-pair list in `fwd` (no E x E
+ * state is stored by the forward), then reverses the SoftSort, the
+ * activity/score terms, the nearest-neighbour softmaxes, the SDF queries,
+ * the witness QP and the rigid transforms.  Broadphase decisions and hull
+ * topology are held fixed. */
+cm_status cm_collide_backward(cm_context* ctx, const cm_batch* batch, const cm_params* prm,
+                              const cm_manifold* fwd, const cm_cotangent* cot, cm_grads* out, void* stream);
+
+/* ---------------------------------------------------------------- serving
+ * A continuous-batching request loop over resident geometry.  Requests are
+ * admitted while their device footprint fits in hbm_budget_bytes; admitted
+ * requests run concurrently on n_streams streams.  submit copies the request
+ * (host arrays) and returns a ticket; poll returns CM_ERR_NOT_READY until the
+ * request completed, then fills the result (host arrays it owns until
+ * cm_server_release).  A request whose footprint exceeds the whole budget is
+ * rejected with CM_ERR_REJECTED. */
+typedef struct {
+  int32_t n_scenes;
+  int32_t n_bodies;
+  const int32_t* body_offsets;   /* host [n_scenes + 1] */
+  const int32_t* body_geom;      /* host [n_bodies] */
+  const float* pose;             /* host [7][n_bodies] */
+  cm_params params;
+  int32_t want_backward;         /* also compute gradients of L = <cot, out> */
+  const float* cot_dist;         /* host [capacity*K] or NULL (backward only) */
+  const float* cot_normal;       /* host [3][capacity*K] or NULL */
+  int32_t capacity;              /* output pair capacity (<= 0: all candidates) */
+} cm_request;
+
+typedef struct {
+  cm_status status;
+  int32_t n_pairs;
+  const int32_t* pair_offsets;   /* host [n_scenes + 1] */
+  const int32_t* pairs;          /* host [2][n_pairs] */
+  const float* point;            /* host [3][n_pairs*K] */
+  const float* normal;
+  const float* dist;
+  const float* weight;
+  const float* g_pose;           /* host [6][n_bodies] (backward only) */
+  double t_submit, t_start, t_done;   /* seconds, server clock */
+  uint64_t footprint_bytes;
+} cm_result;
+
+cm_status cm_server_create(cm_context* ctx, uint64_t hbm_budget_bytes, int32_t n_streams, cm_server** out);
+cm_status cm_server_submit(cm_server* srv, const cm_request* req, uint64_t* ticket);
+cm_status cm_server_poll(cm_server* srv, uint64_t ticket, cm_result* out);
+cm_status cm_server_release(cm_server* srv, uint64_t ticket);
+cm_status cm_server_stats(cm_server* srv, uint64_t* in_flight_bytes, int32_t* n_pending, int32_t* n_running);
+cm_status cm_server_destroy(cm_server* srv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CM_H */

@@ -1,0 +1,207 @@
+"""Python binding of libcm (argument marshalling only).
+
+PyTorch supplies device memory and streams; every step of the contact-manifold
+path runs in the HIP kernels behind the C ABI (include/cm.h).  There is no CPU
+fallback: if libcm.so or a HIP device is missing, these calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _np_ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _stream_handle(stream: Optional[torch.cuda.Stream]):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+@dataclass
+class DeviceBatch:
+    """A scene batch resident on the device (int32 / float32 tensors)."""
+    n_scenes: int
+    n_bodies: int
+    body_offsets: torch.Tensor
+    body_geom: torch.Tensor
+    pose: torch.Tensor
+    cand_offsets: Optional[torch.Tensor] = None
+    cand_pairs: Optional[torch.Tensor] = None
+
+    @property
+    def n_cand_total(self) -> int:
+        if self.cand_pairs is not None:
+            return int(self.cand_pairs.shape[1])
+        bo = self.body_offsets.cpu().numpy().astype(np.int64)
+        nb = np.diff(bo)
+        return int((nb * (nb - 1) // 2).sum())
+
+    def as_c(self) -> L.cm_batch:
+        b = L.cm_batch()
+        b.n_scenes = self.n_scenes
+        b.n_bodies = self.n_bodies
+        b.body_offsets = _ptr(self.body_offsets)
+        b.body_geom = _ptr(self.body_geom)
+        b.pose = _ptr(self.pose)
+        b.cand_offsets = _ptr(self.cand_offsets)
+        b.cand_pairs = _ptr(self.cand_pairs)
+        b.n_cand = 0 if self.cand_pairs is None else int(self.cand_pairs.shape[1])
+        return b
+
+
+@dataclass
+class Manifold:
+    """Caller-owned manifold outputs (device tensors)."""
+    K: int
+    capacity: int
+    n_pairs: torch.Tensor       # int32 [1]
+    pair_offsets: torch.Tensor  # int32 [S+1]
+    pairs: torch.Tensor         # int32 [2, cap]
+    point: torch.Tensor         # float32 [3, cap*K]
+    normal: torch.Tensor        # float32 [3, cap*K]
+    dist: torch.Tensor          # float32 [cap*K]
+    weight: torch.Tensor        # float32 [cap*K]
+
+    @staticmethod
+    def empty(n_scenes: int, capacity: int, K: int, device) -> "Manifold":
+        z32 = lambda *s: torch.zeros(*s, dtype=torch.int32, device=device)
+        f32 = lambda *s: torch.zeros(*s, dtype=torch.float32, device=device)
+        cap = max(int(capacity), 0)
+        return Manifold(K, cap, z32(1), z32(n_scenes + 1), z32(2, max(cap, 1)), f32(3, max(cap * K, 1)),
+                        f32(3, max(cap * K, 1)), f32(max(cap * K, 1)), f32(max(cap * K, 1)))
+
+    def as_c(self) -> L.cm_manifold:
+        m = L.cm_manifold()
+        m.capacity = self.capacity
+        m.n_pairs = _ptr(self.n_pairs)
+        m.pair_offsets = _ptr(self.pair_offsets)
+        m.pairs = _ptr(self.pairs)
+        m.point = _ptr(self.point)
+        m.normal = _ptr(self.normal)
+        m.dist = _ptr(self.dist)
+        m.weight = _ptr(self.weight)
+        return m
+
+    def to_numpy(self):
+        """Host copy: pairs [2,n], offsets, p [n,K,3], nu [n,K,3], d [n,K], w [n,K]."""
+        n = min(int(self.n_pairs.item()), self.capacity)
+        K = self.K
+        p = self.point[:, :n * K].cpu().numpy().reshape(3, n, K).transpose(1, 2, 0)
+        nu = self.normal[:, :n * K].cpu().numpy().reshape(3, n, K).transpose(1, 2, 0)
+        return dict(n_pairs=int(self.n_pairs.item()), pairs=self.pairs[:, :n].cpu().numpy(),
+                    offsets=self.pair_offsets.cpu().numpy(), p=p, nu=nu,
+                    d=self.dist[:n * K].cpu().numpy().reshape(n, K), w=self.weight[:n * K].cpu().numpy().reshape(n, K))
+
+
+def make_params(tau: float, K: int, lambda_reg: float = -1.0, eps_n: float = -1.0, cull_margin: float = -1.0):
+    p = L.cm_params()
+    p.tau, p.K, p.lambda_reg, p.eps_n, p.cull_margin, p.flags = float(tau), int(K), lambda_reg, eps_n, cull_margin, 0
+    return p
+
+
+class Context:
+    """A libcm context on one HIP device (owns geometry tables and workspace)."""
+
+    def __init__(self, device: int = 0):
+        self.lib = L.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("libcm needs a HIP device (no CPU fallback)")
+        self.device = torch.device("cuda", device)
+        h = C.c_void_p()
+        self._check(self.lib.cm_context_create(device, C.byref(h)), ctx=None)
+        self.h = h
+
+    def _check(self, status, ctx="self"):
+        if status != L.CM_OK:
+            msg = ""
+            if ctx is not None and getattr(self, "h", None):
+                msg = self.lib.cm_last_error(self.h).decode()
+            raise L.CMError(status, msg)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.cm_context_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------- geometry
+    def create_geometry(self, geoms) -> np.ndarray:
+        """Create all geometries of a workloads.GeomSet; returns their ids."""
+        n = geoms.n
+        types = np.ascontiguousarray(geoms.types, dtype=np.int32)
+        params = np.ascontiguousarray(geoms.params, dtype=np.float32)
+        off = np.ascontiguousarray(geoms.pt_off, dtype=np.int64)
+        pts = np.ascontiguousarray(geoms.points, dtype=np.float32).reshape(-1)
+        if pts.size == 0:
+            pts = np.zeros(3, np.float32)
+        ids = np.zeros(n, dtype=np.int32)
+        self._check(self.lib.cm_geometry_create(self.h, n, _np_ptr(types), _np_ptr(params), _np_ptr(off),
+                                                _np_ptr(pts), _np_ptr(ids)))
+        return ids
+
+    def geometry_info(self, gid: int) -> dict:
+        info = L.cm_geometry_info_t()
+        self._check(self.lib.cm_geometry_info(self.h, int(gid), C.byref(info)))
+        return dict(type=info.type, n_vertices=info.n_vertices, n_edges=info.n_edges, n_faces=info.n_faces,
+                    vertex_offset=info.vertex_offset, bound_radius=info.bound_radius)
+
+    def geometry_mesh(self, gid: int):
+        info = self.geometry_info(gid)
+        v = np.zeros(3 * info["n_vertices"], np.float32)
+        e = np.zeros(2 * info["n_edges"], np.int32)
+        f = np.zeros(max(3 * info["n_faces"], 1), np.int32)
+        self._check(self.lib.cm_geometry_mesh(self.h, int(gid), _np_ptr(v), _np_ptr(e), _np_ptr(f)))
+        return v.reshape(-1, 3), e.reshape(-1, 2), f[:3 * info["n_faces"]].reshape(-1, 3)
+
+    @property
+    def vertex_pool_size(self) -> int:
+        return int(self.lib.cm_vertex_pool_size(self.h))
+
+    @property
+    def geometry_count(self) -> int:
+        return int(self.lib.cm_geometry_count(self.h))
+
+    # ------------------------------------------------------------- batches
+    def upload_batch(self, batch, geom_ids: np.ndarray) -> DeviceBatch:
+        """Copy a workloads.Batch to the device, mapping its geometry ids."""
+        dev = self.device
+        t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt).to(dev)
+        db = DeviceBatch(batch.n_scenes, batch.n_bodies, t(batch.body_offsets, torch.int32),
+                         t(geom_ids[batch.body_geom], torch.int32), t(batch.pose, torch.float32))
+        if batch.cand_pairs is not None:
+            db.cand_offsets = t(batch.cand_offsets, torch.int32)
+            db.cand_pairs = t(batch.cand_pairs, torch.int32)
+        return db
+
+    def check_errors(self, stream=None):
+        self._check(self.lib.cm_check_errors(self.h, _stream_handle(stream)))
+
+    # ------------------------------------------------------------- forward
+    def collide(self, db: DeviceBatch, tau: float, K: int, capacity: Optional[int] = None, out: Manifold = None,
+                fused: bool = False, stream=None, lambda_reg=-1.0, eps_n=-1.0, cull_margin=-1.0) -> Manifold:
+        if out is None:
+            cap = db.n_cand_total if capacity is None else capacity
+            out = Manifold.empty(db.n_scenes, cap, K, self.device)
+        prm = make_params(tau, K, lambda_reg, eps_n, cull_margin)
+        b = db.as_c()
+        m = out.as_c()
+        fn = self.lib.cm_collide_fused if fused else self.lib.cm_collide
+        self._check(fn(self.h, C.byref(b), C.byref(prm), C.byref(m), _stream_handle(stream)))
+        return out

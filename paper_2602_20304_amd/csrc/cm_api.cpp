@@ -1,0 +1,343 @@
+// C ABI implementation: context, geometry store, forward entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "cm_context.h"
+#include "cm_kernels.h"
+
+using namespace cm;
+
+namespace {
+
+const char* kStatusStr[] = {"ok", "invalid argument", "out of memory", "device error", "not ready",
+                            "rejected", "not found", "capacity exceeded", "degenerate geometry"};
+
+}  // namespace
+
+cm_status cm_fail(cm_context* ctx, cm_status s, const std::string& msg) {
+  if (ctx) ctx->last_error = msg;
+  return s;
+}
+
+cm_status cm_hip(cm_context* ctx, hipError_t e, const char* what) {
+  if (e == hipSuccess) return CM_OK;
+  return cm_fail(ctx, e == hipErrorOutOfMemory ? CM_ERR_OOM : CM_ERR_DEVICE,
+                 std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <typename T>
+static hipError_t dev_upload(T** dptr, size_t* cap, const std::vector<T>& h) {
+  const size_t need = std::max<size_t>(h.size(), 1);
+  if (*cap < need) {
+    if (*dptr) (void)hipFree(*dptr);
+    *dptr = nullptr;
+    size_t c = std::max(need, *cap * 2);
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(dptr), c * sizeof(T));
+    if (e != hipSuccess) { *cap = 0; return e; }
+    *cap = c;
+  }
+  if (!h.empty()) return hipMemcpy(*dptr, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
+  return hipSuccess;
+}
+
+hipError_t ensure_bytes(void** p, size_t* cap, size_t need) {
+  if (*cap >= need && *p) return hipSuccess;
+  if (*p) { (void)hipFree(*p); *p = nullptr; *cap = 0; }
+  need = std::max<size_t>(need, 256);
+  hipError_t e = hipMalloc(p, need);
+  if (e == hipSuccess) *cap = need;
+  return e;
+}
+
+cm_status ctx_upload_tables(cm_context* ctx) {
+  hipError_t e;
+#define UP(field) \
+  if ((e = dev_upload(&ctx->d.field, &ctx->dcap.field, ctx->h.field)) != hipSuccess) return cm_hip(ctx, e, "upload " #field);
+  UP(recs) UP(vx) UP(vy) UP(vz) UP(e0) UP(e1) UP(fnx) UP(fny) UP(fnz) UP(fo) UP(f0) UP(f1) UP(f2)
+#undef UP
+  return CM_OK;
+}
+
+Tables ctx_tables(const cm_context* ctx) {
+  Tables t;
+  t.geoms = ctx->d.recs;
+  t.n_geoms = int32_t(ctx->h.recs.size());
+  t.vx = ctx->d.vx; t.vy = ctx->d.vy; t.vz = ctx->d.vz;
+  t.e0 = ctx->d.e0; t.e1 = ctx->d.e1;
+  t.fnx = ctx->d.fnx; t.fny = ctx->d.fny; t.fnz = ctx->d.fnz; t.fo = ctx->d.fo;
+  t.f0 = ctx->d.f0; t.f1 = ctx->d.f1; t.f2 = ctx->d.f2;
+  return t;
+}
+
+extern "C" {
+
+const char* cm_status_str(cm_status s) {
+  const int i = -int(s);
+  if (i < 0 || i >= int(sizeof(kStatusStr) / sizeof(kStatusStr[0]))) return "unknown status";
+  return kStatusStr[i];
+}
+
+const char* cm_last_error(cm_context* ctx) { return ctx ? ctx->last_error.c_str() : "null context"; }
+
+cm_status cm_context_create(int device, cm_context** out) {
+  if (!out) return CM_ERR_INVALID_ARG;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n == 0) return CM_ERR_DEVICE;
+  if (device < 0 || device >= n) return CM_ERR_INVALID_ARG;
+  if (hipSetDevice(device) != hipSuccess) return CM_ERR_DEVICE;
+  cm_context* ctx = new cm_context();
+  ctx->device = device;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) { delete ctx; return CM_ERR_DEVICE; }
+  ctx->num_cus = prop.multiProcessorCount;
+  if (hipMalloc(&ctx->d_err, sizeof(unsigned)) != hipSuccess || hipMemset(ctx->d_err, 0, sizeof(unsigned)) != hipSuccess) {
+    delete ctx;
+    return CM_ERR_OOM;
+  }
+  *out = ctx;
+  return CM_OK;
+}
+
+cm_status cm_context_destroy(cm_context* ctx) {
+  if (!ctx) return CM_ERR_INVALID_ARG;
+  hipSetDevice(ctx->device);
+  hipDeviceSynchronize();
+  ctx->release_all();
+  delete ctx;
+  return CM_OK;
+}
+
+cm_status cm_check_errors(cm_context* ctx, void* stream) {
+  if (!ctx) return CM_ERR_INVALID_ARG;
+  hipSetDevice(ctx->device);
+  hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return cm_hip(ctx, e, "stream synchronize");
+  unsigned bits = 0;
+  if ((e = hipMemcpy(&bits, ctx->d_err, sizeof(unsigned), hipMemcpyDeviceToHost)) != hipSuccess)
+    return cm_hip(ctx, e, "read error word");
+  if (bits) hipMemset(ctx->d_err, 0, sizeof(unsigned));
+  if (bits & ERR_BAD_GEOM) return cm_fail(ctx, CM_ERR_NOT_FOUND, "batch references an invalid body or geometry id");
+  if (bits & ERR_CAPACITY) return cm_fail(ctx, CM_ERR_CAPACITY, "more kept pairs than the output capacity");
+  if (bits) return cm_fail(ctx, CM_ERR_DEVICE, "device error bits set");
+  return CM_OK;
+}
+
+cm_status cm_geometry_create(cm_context* ctx, int32_t n, const int32_t* types, const float* params,
+                             const int64_t* pt_offsets, const float* points, int32_t* out_ids) {
+  if (!ctx || n < 0 || (n > 0 && (!types || !params || !out_ids))) return CM_ERR_INVALID_ARG;
+  if (n == 0) return CM_OK;
+  for (int i = 0; i < n; ++i) {
+    if (types[i] < CM_SPHERE || types[i] > CM_POLYTOPE)
+      return cm_fail(ctx, CM_ERR_INVALID_ARG, "unknown geometry type");
+    if (types[i] == CM_POLYTOPE && (!pt_offsets || !points))
+      return cm_fail(ctx, CM_ERR_INVALID_ARG, "polytope needs points");
+  }
+  std::vector<HostMesh> meshes(n);
+  std::vector<std::string> errs(n);
+  std::atomic<int> bad{-1};
+  const int nt = std::max(1, std::min<int>(16, int(std::thread::hardware_concurrency())));
+  auto work = [&](int t) {
+    for (int i = t; i < n; i += nt) {
+      const float* pts = nullptr;
+      int64_t np = 0;
+      if (types[i] == CM_POLYTOPE) {
+        np = pt_offsets[i + 1] - pt_offsets[i];
+        pts = points + 3 * pt_offsets[i];
+      }
+      if (!build_mesh(types[i], params + 4 * i, pts, np, &meshes[i], &errs[i])) {
+        int exp = -1;
+        bad.compare_exchange_strong(exp, i);
+      }
+    }
+  };
+  if (n >= 64 && nt > 1) {
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t) th.emplace_back(work, t);
+    for (auto& x : th) x.join();
+  } else {
+    for (int i = 0; i < n; ++i) {
+      const float* pts = nullptr;
+      int64_t np = 0;
+      if (types[i] == CM_POLYTOPE) { np = pt_offsets[i + 1] - pt_offsets[i]; pts = points + 3 * pt_offsets[i]; }
+      if (!build_mesh(types[i], params + 4 * i, pts, np, &meshes[i], &errs[i])) { bad = i; break; }
+    }
+  }
+  if (bad >= 0) return cm_fail(ctx, CM_ERR_GEOMETRY, "geometry " + std::to_string(int(bad)) + ": " + errs[bad]);
+  hipSetDevice(ctx->device);
+  auto& h = ctx->h;
+  for (int i = 0; i < n; ++i) {
+    const HostMesh& m = meshes[i];
+    GeomRec r;
+    std::memset(&r, 0, sizeof(r));
+    r.type = m.type;
+    r.nv = int32_t(m.v.size() / 3);
+    r.ne = int32_t(m.e.size() / 2);
+    r.nf = int32_t(m.f.size() / 3);
+    r.v_off = int32_t(h.vx.size());
+    r.e_off = int32_t(h.e0.size());
+    r.f_off = int32_t(h.fnx.size());
+    for (int k = 0; k < 4; ++k) r.p[k] = m.p[k];
+    r.bound_r = m.bound_r;
+    for (int v = 0; v < r.nv; ++v) { h.vx.push_back(m.v[3 * v]); h.vy.push_back(m.v[3 * v + 1]); h.vz.push_back(m.v[3 * v + 2]); }
+    for (int e = 0; e < r.ne; ++e) { h.e0.push_back(m.e[2 * e]); h.e1.push_back(m.e[2 * e + 1]); }
+    for (int f = 0; f < r.nf; ++f) {
+      h.fnx.push_back(m.planes[4 * f]); h.fny.push_back(m.planes[4 * f + 1]);
+      h.fnz.push_back(m.planes[4 * f + 2]); h.fo.push_back(m.planes[4 * f + 3]);
+      h.f0.push_back(m.f[3 * f]); h.f1.push_back(m.f[3 * f + 1]); h.f2.push_back(m.f[3 * f + 2]);
+    }
+    ctx->maxV = std::max(ctx->maxV, r.nv);
+    ctx->maxE = std::max(ctx->maxE, r.ne);
+    ctx->maxF = std::max(ctx->maxF, r.nf);
+    out_ids[i] = int32_t(h.recs.size());
+    h.recs.push_back(r);
+  }
+  return ctx_upload_tables(ctx);
+}
+
+cm_status cm_geometry_info(cm_context* ctx, int32_t id, cm_geometry_info_t* out) {
+  if (!ctx || !out) return CM_ERR_INVALID_ARG;
+  if (id < 0 || id >= int32_t(ctx->h.recs.size())) return cm_fail(ctx, CM_ERR_NOT_FOUND, "no such geometry");
+  const GeomRec& r = ctx->h.recs[id];
+  out->type = r.type; out->n_vertices = r.nv; out->n_edges = r.ne; out->n_faces = r.nf;
+  out->vertex_offset = r.v_off; out->bound_radius = r.bound_r;
+  return CM_OK;
+}
+
+cm_status cm_geometry_mesh(cm_context* ctx, int32_t id, float* vertices, int32_t* edges, int32_t* faces) {
+  if (!ctx) return CM_ERR_INVALID_ARG;
+  if (id < 0 || id >= int32_t(ctx->h.recs.size())) return cm_fail(ctx, CM_ERR_NOT_FOUND, "no such geometry");
+  const GeomRec& r = ctx->h.recs[id];
+  const auto& h = ctx->h;
+  if (vertices) for (int v = 0; v < r.nv; ++v) {
+    vertices[3 * v] = h.vx[r.v_off + v]; vertices[3 * v + 1] = h.vy[r.v_off + v]; vertices[3 * v + 2] = h.vz[r.v_off + v];
+  }
+  if (edges) for (int e = 0; e < r.ne; ++e) { edges[2 * e] = h.e0[r.e_off + e]; edges[2 * e + 1] = h.e1[r.e_off + e]; }
+  if (faces) for (int f = 0; f < r.nf; ++f) {
+    faces[3 * f] = h.f0[r.f_off + f]; faces[3 * f + 1] = h.f1[r.f_off + f]; faces[3 * f + 2] = h.f2[r.f_off + f];
+  }
+  return CM_OK;
+}
+
+int32_t cm_geometry_count(cm_context* ctx) { return ctx ? int32_t(ctx->h.recs.size()) : -1; }
+int32_t cm_vertex_pool_size(cm_context* ctx) { return ctx ? int32_t(ctx->h.vx.size()) : -1; }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- forward helpers
+
+cm_status resolve_params(cm_context* ctx, const cm_params* prm, ParamsDev* pd) {
+  if (!prm) return cm_fail(ctx, CM_ERR_INVALID_ARG, "null params");
+  if (!(prm->tau > 0.f) || !std::isfinite(prm->tau)) return cm_fail(ctx, CM_ERR_INVALID_ARG, "tau must be > 0");
+  if (prm->K < 1 || prm->K > CM_MAX_K) return cm_fail(ctx, CM_ERR_INVALID_ARG, "K must be in 1..32");
+  if (prm->flags != 0) return cm_fail(ctx, CM_ERR_INVALID_ARG, "flags must be 0");
+  pd->tau = double(prm->tau);
+  pd->lam = prm->lambda_reg < 0.f ? 0.01 : double(prm->lambda_reg);
+  if (!(pd->lam > 0.0)) return cm_fail(ctx, CM_ERR_INVALID_ARG, "lambda_reg must be > 0");
+  pd->eps_n = prm->eps_n < 0.f ? pd->tau * pd->tau : double(prm->eps_n);
+  if (!(pd->eps_n > 0.0)) return cm_fail(ctx, CM_ERR_INVALID_ARG, "eps_n must be > 0");
+  pd->margin = prm->cull_margin < 0.f ? 10.0f * prm->tau : prm->cull_margin;
+  pd->K = prm->K;
+  return CM_OK;
+}
+
+cm_status resolve_batch(cm_context* ctx, const cm_batch* b, BatchDev* bd) {
+  if (!b) return cm_fail(ctx, CM_ERR_INVALID_ARG, "null batch");
+  if (b->n_scenes < 0 || b->n_bodies < 0) return cm_fail(ctx, CM_ERR_INVALID_ARG, "negative sizes");
+  if (b->n_scenes > 0 && (!b->body_offsets || !b->body_geom || !b->pose))
+    return cm_fail(ctx, CM_ERR_INVALID_ARG, "batch arrays missing");
+  if ((b->cand_offsets == nullptr) != (b->cand_pairs == nullptr) && b->n_cand > 0)
+    return cm_fail(ctx, CM_ERR_INVALID_ARG, "cand_offsets and cand_pairs go together");
+  if (b->cand_offsets && b->n_cand < 0) return cm_fail(ctx, CM_ERR_INVALID_ARG, "negative n_cand");
+  if (ctx->h.recs.empty()) return cm_fail(ctx, CM_ERR_INVALID_ARG, "no geometry created");
+  bd->n_scenes = b->n_scenes; bd->n_bodies = b->n_bodies; bd->n_cand = b->n_cand;
+  bd->body_offsets = b->body_offsets; bd->body_geom = b->body_geom; bd->pose = b->pose;
+  bd->cand_offsets = b->cand_offsets; bd->cand_pairs = b->cand_offsets ? b->cand_pairs : nullptr;
+  return CM_OK;
+}
+
+cm_status resolve_out(cm_context* ctx, const cm_manifold* o, OutDev* od) {
+  if (!o || !o->n_pairs || !o->pair_offsets || o->capacity < 0)
+    return cm_fail(ctx, CM_ERR_INVALID_ARG, "bad manifold outputs");
+  if (o->capacity > 0 && (!o->pairs || !o->point || !o->normal || !o->dist || !o->weight))
+    return cm_fail(ctx, CM_ERR_INVALID_ARG, "manifold output arrays missing");
+  od->capacity = o->capacity; od->n_pairs = o->n_pairs; od->pair_offsets = o->pair_offsets; od->pairs = o->pairs;
+  od->point = o->point; od->normal = o->normal; od->dist = o->dist; od->weight = o->weight;
+  return CM_OK;
+}
+
+int kmax_for(int K) { return K <= 8 ? 8 : (K <= 16 ? 16 : 32); }
+
+cm_status ctx_broadphase(cm_context* ctx, const BatchDev& bd, const ParamsDev& pd, const OutDev& od, hipStream_t st) {
+  const Tables tb = ctx_tables(ctx);
+  const size_t tiles = size_t(bd.n_scenes) / 1024 + 2;
+  hipError_t e = ensure_bytes(reinterpret_cast<void**>(&ctx->d_tile_sums), &ctx->tile_cap, tiles * sizeof(int));
+  if (e != hipSuccess) return cm_hip(ctx, e, "tile sums");
+  return cm_hip(ctx, launch_broadphase(tb, bd, pd.margin, od, ctx->d_tile_sums, ctx->d_err, st), "broadphase launch");
+}
+
+cm_status ctx_prepare_fwd(cm_context* ctx, const BatchDev& bd, const ParamsDev& pd, const OutDev& od, int block,
+                          bool dynamic, FwdLaunch* f) {
+  f->tb = ctx_tables(ctx);
+  f->bt = bd; f->prm = pd; f->out = od;
+  f->maxV = std::max(ctx->maxV, 1); f->maxE = std::max(ctx->maxE, 1); f->maxF = std::max(ctx->maxF, 1);
+  f->block = block;
+  f->kmax = kmax_for(pd.K);
+  f->order = nullptr; f->queue = dynamic ? reinterpret_cast<int*>(1) : nullptr;   // dispatch hint
+  f->err = ctx->d_err;
+  const int occ = fwd_occupancy(*f);
+  f->queue = nullptr;
+  f->grid = std::max(1, occ * ctx->num_cus);
+  if (od.capacity > 0 && f->grid > od.capacity && !dynamic) f->grid = std::max(1, od.capacity);
+  f->scratch_stride = fwd_scratch_floats(f->maxV, f->maxE);
+  const size_t need = size_t(f->grid) * size_t(f->scratch_stride) * sizeof(float);
+  hipError_t e = ensure_bytes(reinterpret_cast<void**>(&ctx->d_scratch), &ctx->scratch_cap, need);
+  if (e != hipSuccess) return cm_hip(ctx, e, "forward scratch");
+  f->scratch = ctx->d_scratch;
+  return CM_OK;
+}
+
+extern "C" cm_status cm_collide(cm_context* ctx, const cm_batch* batch, const cm_params* prm, cm_manifold* out,
+                                void* stream) {
+  if (!ctx) return CM_ERR_INVALID_ARG;
+  ParamsDev pd; BatchDev bd; OutDev od;
+  cm_status s;
+  if ((s = resolve_params(ctx, prm, &pd)) != CM_OK) return s;
+  if ((s = resolve_batch(ctx, batch, &bd)) != CM_OK) return s;
+  if ((s = resolve_out(ctx, out, &od)) != CM_OK) return s;
+  hipSetDevice(ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((s = ctx_broadphase(ctx, bd, pd, od, st)) != CM_OK) return s;
+  if (od.capacity == 0) return CM_OK;
+  FwdLaunch f;
+  if ((s = ctx_prepare_fwd(ctx, bd, pd, od, 256, false, &f)) != CM_OK) return s;
+  return cm_hip(ctx, launch_collide_fwd(f, st), "collide launch");
+}
+
+extern "C" cm_status cm_collide_fused(cm_context* ctx, const cm_batch* batch, const cm_params* prm, cm_manifold* out,
+                                      void* stream) {
+  if (!ctx) return CM_ERR_INVALID_ARG;
+  ParamsDev pd; BatchDev bd; OutDev od;
+  cm_status s;
+  if ((s = resolve_params(ctx, prm, &pd)) != CM_OK) return s;
+  if ((s = resolve_batch(ctx, batch, &bd)) != CM_OK) return s;
+  if ((s = resolve_out(ctx, out, &od)) != CM_OK) return s;
+  hipSetDevice(ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((s = ctx_broadphase(ctx, bd, pd, od, st)) != CM_OK) return s;
+  if (od.capacity == 0) return CM_OK;
+  FwdLaunch f;
+  if ((s = ctx_prepare_fwd(ctx, bd, pd, od, 256, true, &f)) != CM_OK) return s;
+  hipError_t e = ensure_bytes(&ctx->d_work, &ctx->work_cap, 256);
+  if (e != hipSuccess) return cm_hip(ctx, e, "work queue");
+  f.queue = static_cast<int*>(ctx->d_work);
+  if ((e = hipMemsetAsync(f.queue, 0, sizeof(int), st)) != hipSuccess) return cm_hip(ctx, e, "queue reset");
+  return cm_hip(ctx, launch_collide_fwd(f, st), "fused collide launch");
+}

@@ -1,0 +1,64 @@
+// The library context: geometry store (host mirror + device tables) and the
+// workspace the kernels use.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "cm_internal.h"
+
+struct CmPools {
+  std::vector<cm::GeomRec> recs;
+  std::vector<float> vx, vy, vz;
+  std::vector<int32_t> e0, e1;
+  std::vector<float> fnx, fny, fnz, fo;
+  std::vector<int32_t> f0, f1, f2;
+};
+
+template <typename T>
+struct CmDevPtr;
+
+struct CmDevPools {
+  cm::GeomRec* recs = nullptr;
+  float *vx = nullptr, *vy = nullptr, *vz = nullptr;
+  int32_t *e0 = nullptr, *e1 = nullptr;
+  float *fnx = nullptr, *fny = nullptr, *fnz = nullptr, *fo = nullptr;
+  int32_t *f0 = nullptr, *f1 = nullptr, *f2 = nullptr;
+};
+
+struct CmDevCaps {
+  size_t recs = 0, vx = 0, vy = 0, vz = 0, e0 = 0, e1 = 0, fnx = 0, fny = 0, fnz = 0, fo = 0, f0 = 0, f1 = 0, f2 = 0;
+};
+
+struct cm_context {
+  int device = 0;
+  int num_cus = 1;
+  CmPools h;
+  CmDevPools d;
+  CmDevCaps dcap;
+  int maxV = 0, maxE = 0, maxF = 0;
+  unsigned* d_err = nullptr;
+  int* d_tile_sums = nullptr;
+  size_t tile_cap = 0;
+  float* d_scratch = nullptr;
+  size_t scratch_cap = 0;
+  void* d_work = nullptr;      // fused path: queue counter, order, keys
+  size_t work_cap = 0;
+  void* d_bwd = nullptr;       // backward workspace
+  size_t bwd_cap = 0;
+  std::string last_error;
+
+  void release_all() {
+    auto F = [](void* p) { if (p) hipFree(p); };
+    F(d.recs); F(d.vx); F(d.vy); F(d.vz); F(d.e0); F(d.e1); F(d.fnx); F(d.fny); F(d.fnz); F(d.fo);
+    F(d.f0); F(d.f1); F(d.f2);
+    F(d_err); F(d_tile_sums); F(d_scratch); F(d_work); F(d_bwd);
+    d = CmDevPools();
+  }
+};
+
+cm_status cm_fail(cm_context* ctx, cm_status s, const std::string& msg);
+cm_status cm_hip(cm_context* ctx, hipError_t e, const char* what);
+hipError_t ensure_bytes(void** p, size_t* cap, size_t need);
+cm::Tables ctx_tables(const cm_context* ctx);

@@ -1,0 +1,372 @@
+// Device-side math shared by the gfx950 forward and adjoint kernels:
+// smooth operators (Sec. III), SDF primitives (Sec. IV-B), the E-E witness
+// QP (Sec. IV-D) and wave-level reductions.
+//
+// Precision model.  The soft operators amplify rounding error by 1/tau, so
+// geometric algebra (transforms, plane distances, the QP, witness points,
+// distances, scores) runs in float64: on gfx950 a v_fma_f64 issues at the
+// same rate as an unpacked v_fma_f32.  Exponentials and logarithms use the
+// float32 hardware units (v_exp_f32 / v_log_f32) on float64-prepared
+// arguments; their results only enter through terms that are scaled by tau
+// or bounded, which keeps every output within ~1e-6 of the FP64 definition.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "cm_internal.h"
+
+namespace cm {
+
+constexpr double kLog2e = 1.4426950408889634;
+constexpr double kLn2 = 0.6931471805599453;
+// A SoftSort weight exp(-40) ~ 4e-18 is below float32 resolution of any row
+// sum (>= 1), so candidates scoring more than 40 tau below the K-th largest
+// score cannot change a manifold output.
+constexpr double kFilterTaus = 40.0;
+
+struct Temp {
+  double tau, inv_tau, c, tl;   // c = log2(e) / tau, tl = tau * ln 2
+};
+
+__device__ __forceinline__ Temp make_temp(double tau) {
+  Temp T;
+  T.tau = tau;
+  T.inv_tau = 1.0 / tau;
+  T.c = kLog2e / tau;
+  T.tl = tau * kLn2;
+  return T;
+}
+
+// float32 hardware transcendentals
+__device__ __forceinline__ float ex2f(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float lg2f(float x) { return __builtin_amdgcn_logf(x); }
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+// exp(-a / tau) for a >= 0 given in float64 (result float32)
+__device__ __forceinline__ float expn(double a, const Temp& T) { return ex2f(float(-a * T.c)); }
+
+// exp(x) for x <= 0 to ~1e-12 relative in float64: Cody-Waite reduction
+// x = n ln2 + r, |r| <= ln2 / 2, then a degree-9 Taylor polynomial of e^r
+// (remainder below r^10 / 10! ~ 7e-12) scaled by 2^n.
+__device__ __forceinline__ double exp64n(double x) {
+  if (x < -700.0) return 0.0;
+  const double n = rint(x * kLog2e);
+  double r = fma(-n, 6.93147180369123816490e-01, x);   // ln2 high part
+  r = fma(-n, 1.90821492927058770002e-10, r);          // ln2 low part
+  double p = 2.7557319223985893e-06;                   // 1/9!
+  p = fma(p, r, 2.4801587301587302e-05);               // 1/8!
+  p = fma(p, r, 1.9841269841269841e-04);               // 1/7!
+  p = fma(p, r, 1.3888888888888889e-03);               // 1/6!
+  p = fma(p, r, 8.3333333333333333e-03);               // 1/5!
+  p = fma(p, r, 4.1666666666666667e-02);               // 1/4!
+  p = fma(p, r, 1.6666666666666667e-01);               // 1/3!
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  return ldexp(p, int(n));
+}
+// sigma(u / tau) in float64
+__device__ __forceinline__ double sig64(double u, const Temp& T) {
+  const double e = exp64n(-fabs(u) * T.inv_tau);
+  const double r = 1.0 / (1.0 + e);
+  return u >= 0.0 ? r : e * r;
+}
+// tanh(u / tau) in float64
+__device__ __forceinline__ double tanh64(double u, const Temp& T) {
+  const double e = exp64n(-2.0 * fabs(u) * T.inv_tau);
+  return copysign((1.0 - e) / (1.0 + e), u);
+}
+
+// tau * softplus(x / tau) = max(x, 0) + tau ln(1 + exp(-|x| / tau))
+__device__ __forceinline__ double softplus_t(double x, const Temp& T) {
+  const float e = expn(fabs(x), T);
+  return fmax(x, 0.0) + T.tl * double(lg2f(1.f + e));
+}
+__device__ __forceinline__ double clip01(double x, const Temp& T) {
+  return softplus_t(x, T) - softplus_t(x - 1.0, T);
+}
+// ln sigma(u / tau)
+__device__ __forceinline__ double lsig(double u, const Temp& T) {
+  const float e = expn(fabs(u), T);
+  return fmin(u, 0.0) * T.inv_tau - kLn2 * double(lg2f(1.f + e));
+}
+// sigma(u / tau) and ln sigma(u / tau)
+__device__ __forceinline__ void sig_lsig(double u, const Temp& T, double& s, double& ls) {
+  const float e = expn(fabs(u), T);
+  const float r = frcp(1.f + e);
+  s = double(u >= 0.0 ? r : e * r);
+  ls = fmin(u, 0.0) * T.inv_tau - kLn2 * double(lg2f(1.f + e));
+}
+// tanh(u / tau)
+__device__ __forceinline__ double tanh_t(double u, const Temp& T) {
+  const float e = expn(2.0 * fabs(u), T);
+  return copysign(double((1.f - e) * frcp(1.f + e)), u);
+}
+
+__device__ __forceinline__ double sgn1(double x) { return x >= 0.0 ? 1.0 : -1.0; }
+
+struct D3 {
+  double x, y, z;
+};
+__device__ __forceinline__ D3 d3(double x, double y, double z) { return D3{x, y, z}; }
+__device__ __forceinline__ double dot(const D3& a, const D3& b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+
+// ----------------------------------------------------------------- SDFs
+// Body-frame SDF of an analytic primitive and its gradient.
+__device__ __forceinline__ void sdf_analytic(int type, const float* p, const D3& l, double& phi, D3& g) {
+  if (type == CM_SPHERE) {
+    const double s = dot(l, l);
+    const double n = sqrt(s);
+    const double inv = s > 0.0 ? 1.0 / n : 0.0;
+    phi = n - double(p[0]);
+    g = d3(l.x * inv, l.y * inv, l.z * inv);
+  } else if (type == CM_CAPSULE) {
+    const double h = p[1];
+    const double zc = fmin(fmax(l.z, -h), h);
+    const D3 y = d3(l.x, l.y, l.z - zc);
+    const double s = dot(y, y);
+    const double n = sqrt(s);
+    const double inv = s > 0.0 ? 1.0 / n : 0.0;
+    phi = n - double(p[0]);
+    g = d3(y.x * inv, y.y * inv, y.z * inv);
+  } else {  // rounded box: outer half-extents p[0..2], rounding p[3]
+    const double rr = p[3];
+    const double qx = fabs(l.x) - (double(p[0]) - rr), qy = fabs(l.y) - (double(p[1]) - rr),
+                 qz = fabs(l.z) - (double(p[2]) - rr);
+    const double mx = fmax(qx, 0.0), my = fmax(qy, 0.0), mz = fmax(qz, 0.0);
+    const double s = mx * mx + my * my + mz * mz;
+    if (s > 0.0) {
+      const double n = sqrt(s), inv = 1.0 / n;
+      phi = n - rr;
+      g = d3(sgn1(l.x) * mx * inv, sgn1(l.y) * my * inv, sgn1(l.z) * mz * inv);
+    } else {
+      const double qm = fmax(qx, fmax(qy, qz));
+      phi = qm - rr;
+      const int j = (qx >= qy && qx >= qz) ? 0 : (qy >= qz ? 1 : 2);
+      g = d3(j == 0 ? sgn1(l.x) : 0.0, j == 1 ? sgn1(l.y) : 0.0, j == 2 ? sgn1(l.z) : 0.0);
+    }
+  }
+}
+
+// tau-LSE over body-frame planes (n.xyz, o) stored as float4 in LDS:
+// phi = LSE_tau(n . x - o); gradient = softmax-weighted sum of normals.
+template <bool WANT_G>
+__device__ __forceinline__ void sdf_poly(const float4* __restrict__ pl, int nf, const D3& x, const Temp& T,
+                                         double& phi, D3& g) {
+  double m = -1e300;
+  for (int f = 0; f < nf; ++f) {
+    const float4 q = pl[f];
+    m = fmax(m, fma(double(q.x), x.x, fma(double(q.y), x.y, fma(double(q.z), x.z, -double(q.w)))));
+  }
+  float s = 0.f, ax = 0.f, ay = 0.f, az = 0.f;
+  for (int f = 0; f < nf; ++f) {
+    const float4 q = pl[f];
+    const double yv = fma(double(q.x), x.x, fma(double(q.y), x.y, fma(double(q.z), x.z, -double(q.w))));
+    const float e = ex2f(float((yv - m) * T.c));
+    s += e;
+    if (WANT_G) { ax = fmaf(e, q.x, ax); ay = fmaf(e, q.y, ay); az = fmaf(e, q.z, az); }
+  }
+  phi = m + T.tl * double(lg2f(s));
+  if (WANT_G) {
+    const float inv = frcp(s);
+    g = d3(double(ax * inv), double(ay * inv), double(az * inv));
+  }
+}
+
+// A body as seen in the pair frame (the frame of body A).
+struct BodyView {
+  int type, nv, ne, nf;
+  float p[4];
+  double R[9];   // body frame -> pair frame rotation (row-major)
+  double t[3];   // body origin in the pair frame
+  bool ident;    // R = I, t = 0 (body A)
+  const float4* planes;   // LDS, body frame (polytopes)
+};
+
+// SDF of a body at a pair-frame point; gradient returned in the pair frame.
+template <bool WANT_G>
+__device__ __forceinline__ void sdf_body(const BodyView& B, const D3& x, const Temp& T, double& phi, D3& g) {
+  D3 l = x;
+  if (!B.ident) {
+    const double dx = x.x - B.t[0], dy = x.y - B.t[1], dz = x.z - B.t[2];
+    l = d3(B.R[0] * dx + B.R[3] * dy + B.R[6] * dz, B.R[1] * dx + B.R[4] * dy + B.R[7] * dz,
+           B.R[2] * dx + B.R[5] * dy + B.R[8] * dz);
+  }
+  D3 lg;
+  if (B.type == CM_POLYTOPE) sdf_poly<WANT_G>(B.planes, B.nf, l, T, phi, lg);
+  else sdf_analytic(B.type, B.p, l, phi, lg);
+  if (WANT_G) {
+    if (B.ident) g = lg;
+    else g = d3(B.R[0] * lg.x + B.R[1] * lg.y + B.R[2] * lg.z, B.R[3] * lg.x + B.R[4] * lg.y + B.R[5] * lg.z,
+                B.R[6] * lg.x + B.R[7] * lg.y + B.R[8] * lg.z);
+  }
+}
+
+// ----------------------------------------------------------------- E-E QP
+// Edge e of a body in LDS (pair frame, structure of arrays of doubles):
+// p0 = (x0, y0, z0), t = (tx, ty, tz).
+struct EdgeSoA {
+  double* x0; double* y0; double* z0; double* tx; double* ty; double* tz;
+  __device__ __forceinline__ void get(int e, D3& p0, D3& t) const {
+    p0 = d3(x0[e], y0[e], z0[e]);
+    t = d3(tx[e], ty[e], tz[e]);
+  }
+};
+
+struct EEQP {
+  double al1, al2, log_con;
+  D3 de;      // Delta e = e1 - e2
+};
+
+// Smoothed analytic active-set solution of the regularised E-E QP
+// (Sec. IV-D-2): unconstrained minimiser -Q^{-1} c, four soft-clipped
+// box-edge minimisers blended by a soft argmin of their objective values,
+// soft inside-box indicator, blend.  Objective values are evaluated in the
+// residual form 1/2 |b + A al|^2 + lambda/2 |al - 1/2|^2, which differs from
+// 1/2 al^T Q al + c^T al by a constant (the soft argmin is shift invariant).
+__device__ __forceinline__ EEQP ee_qp(const D3& a0, const D3& t1, const D3& b0, const D3& t2, double lam,
+                                      const Temp& T) {
+  const D3 b = d3(a0.x - b0.x, a0.y - b0.y, a0.z - b0.z);
+  const double Q11 = dot(t1, t1) + lam, Q22 = dot(t2, t2) + lam;
+  const double Q12 = -dot(t1, t2);
+  const double hl = 0.5 * lam;
+  const double c1 = dot(b, t1) - hl;
+  const double c2 = -dot(b, t2) - hl;
+  const double det = Q11 * Q22 - Q12 * Q12;
+  const double idet = 1.0 / det;
+  const double au1 = (Q12 * c2 - c1 * Q22) * idet;
+  const double au2 = (Q12 * c1 - c2 * Q11) * idet;
+  const double i11 = 1.0 / Q11, i22 = 1.0 / Q22;
+  const double xa = clip01(-(Q12 + c2) * i22, T);   // on al1 = 1
+  const double xb = clip01(-c2 * i22, T);           // on al1 = 0
+  const double xc = clip01(-(Q12 + c1) * i11, T);   // on al2 = 1
+  const double xd = clip01(-c1 * i11, T);           // on al2 = 0
+  auto cost = [&](double a1, double a2) {
+    const double rx = b.x + a1 * t1.x - a2 * t2.x;
+    const double ry = b.y + a1 * t1.y - a2 * t2.y;
+    const double rz = b.z + a1 * t1.z - a2 * t2.z;
+    const double u = a1 - 0.5, v = a2 - 0.5;
+    return 0.5 * ((rx * rx + ry * ry + rz * rz) + lam * (u * u + v * v));
+  };
+  const double j0 = cost(1.0, xa), j1 = cost(0.0, xb), j2 = cost(xc, 1.0), j3 = cost(xd, 0.0);
+  const double jm = fmin(fmin(j0, j1), fmin(j2, j3));
+  // soft argmin weights and the inside-box indicator move the witness
+  // points directly, so they use float64 exponentials
+  const double w0 = exp64n(-(j0 - jm) * T.inv_tau), w1 = exp64n(-(j1 - jm) * T.inv_tau);
+  const double w2 = exp64n(-(j2 - jm) * T.inv_tau), w3 = exp64n(-(j3 - jm) * T.inv_tau);
+  const double iw = 1.0 / ((w0 + w1) + (w2 + w3));
+  const double ac1 = (w0 + w2 * xc + w3 * xd) * iw;
+  const double ac2 = (w0 * xa + w1 * xb + w2) * iw;
+  const double con = (sig64(au1, T) * sig64(1.0 - au1, T)) * (sig64(au2, T) * sig64(1.0 - au2, T));
+  EEQP r;
+  r.log_con = (lsig(au1, T) + lsig(1.0 - au1, T)) + (lsig(au2, T) + lsig(1.0 - au2, T));
+  r.al1 = con * au1 + (1.0 - con) * ac1;
+  r.al2 = con * au2 + (1.0 - con) * ac2;
+  r.de = d3(b.x + r.al1 * t1.x - r.al2 * t2.x, b.y + r.al1 * t1.y - r.al2 * t2.y, b.z + r.al1 * t1.z - r.al2 * t2.z);
+  return r;
+}
+
+__device__ __forceinline__ double ee_dist(const D3& a0, const D3& t1, const D3& b0, const D3& t2, double lam,
+                                          const Temp& T) {
+  const EEQP q = ee_qp(a0, t1, b0, t2, lam, T);
+  return sqrt(dot(q.de, q.de));
+}
+
+// ----------------------------------------------------------------- candidates
+struct Cand {
+  double s;     // score -d + tau ln w
+  double d;     // signed distance
+  double lw;    // ln w
+  D3 p;         // point (pair frame)
+  D3 n;         // pair normal A -> B (pair frame)
+};
+
+// Both E-E witness candidates of edge pair (k, l) (Sec. IV-D-3 and the
+// activity indicator): sign via soft sign of the opposing SDF gradient,
+// penetration via the opposing SDF value, clashing via both gradients,
+// nearest neighbour via the row / column LSE of the unsigned distances.
+__device__ __forceinline__ void ee_candidates(const D3& a0, const D3& t1, const D3& b0, const D3& t2,
+                                              double row_lse, double col_lse, const BodyView& A, const BodyView& B,
+                                              double lam, double eps_n, const Temp& T, Cand& c1, Cand& c2) {
+  const EEQP q = ee_qp(a0, t1, b0, t2, lam, T);
+  const D3 e1 = d3(a0.x + q.al1 * t1.x, a0.y + q.al1 * t1.y, a0.z + q.al1 * t1.z);
+  const D3 e2 = d3(b0.x + q.al2 * t2.x, b0.y + q.al2 * t2.y, b0.z + q.al2 * t2.z);
+  const double dsq = dot(q.de, q.de);
+  const double dbar = sqrt(dsq);
+  const double in = 1.0 / sqrt(dsq + eps_n);
+  const D3 nb = d3(q.de.x * in, q.de.y * in, q.de.z * in);
+  double phiB1, phiA2, dum;
+  D3 gA, gB, dg;
+  sdf_body<false>(B, e1, T, phiB1, dg);
+  sdf_body<true>(A, e1, T, dum, gA);
+  sdf_body<false>(A, e2, T, phiA2, dg);
+  sdf_body<true>(B, e2, T, dum, gB);
+  const double gam1 = tanh64(dot(gB, nb), T);
+  const double gam2 = tanh64(-dot(gA, nb), T);
+  const double base = q.log_con + lsig(-dot(gA, gB), T);
+  const double lp1 = base + lsig(-phiB1, T);
+  const double lp2 = base + lsig(-phiA2, T);
+  c1.d = gam1 * dbar;
+  c2.d = gam2 * dbar;
+  c1.lw = lp1 + (row_lse - dbar) * T.inv_tau;
+  c2.lw = lp2 + (col_lse - dbar) * T.inv_tau;
+  c1.s = -c1.d + T.tau * lp1 + (row_lse - dbar);
+  c2.s = -c2.d + T.tau * lp2 + (col_lse - dbar);
+  c1.p = e1;
+  c2.p = e2;
+  // witness 1: nu = -gam1 n_bar; witness 2: nu = gam2 (-n_bar)
+  c1.n = d3(-gam1 * nb.x, -gam1 * nb.y, -gam1 * nb.z);
+  c2.n = d3(-gam2 * nb.x, -gam2 * nb.y, -gam2 * nb.z);
+}
+
+// V-S candidate (Sec. IV-C): vertex v (pair frame) of one body against the
+// SDF of the other; sgn = -1 for A's vertices (the normal of B pushes A),
+// +1 for B's vertices.
+__device__ __forceinline__ void vs_candidate(const D3& v, const BodyView& other, double sgn, const Temp& T,
+                                             Cand& c) {
+  double phi;
+  D3 g;
+  sdf_body<true>(other, v, T, phi, g);
+  const double in = sgn / sqrt(T.tau + dot(g, g));
+  c.p = v;
+  c.n = d3(g.x * in, g.y * in, g.z * in);
+  c.d = phi;
+  c.lw = lsig(-phi, T);
+  c.s = -phi + T.tau * c.lw;
+}
+
+// ----------------------------------------------------------------- waves
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+// merge (min m, sum s of exp(-(x - m)/tau)) pairs across a wave
+__device__ __forceinline__ void wave_lse_merge(double& m, float& s, const Temp& T) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double m2 = __shfl_xor(m, o, 64);
+    const float s2 = __shfl_xor(s, o, 64);
+    const double M = fmin(m, m2);
+    const float a = (m == M) ? s : s * expn(m - M, T);
+    const float b = (m2 == M) ? s2 : s2 * expn(m2 - M, T);
+    m = M; s = a + b;
+  }
+}
+// online update of (m, s) with a new value x: one exp, branch free
+__device__ __forceinline__ void lse_push(double& m, float& s, double x, const Temp& T) {
+  const float e = expn(fabs(x - m), T);
+  const bool lower = x < m;
+  s = lower ? fmaf(s, e, 1.f) : s + e;
+  m = lower ? x : m;
+}
+
+// quaternion (w, x, y, z), not necessarily unit -> rotation matrix (row-major)
+__device__ __forceinline__ void quat_to_R(double w, double x, double y, double z, double* R) {
+  const double in = 1.0 / sqrt(w * w + x * x + y * y + z * z);
+  w *= in; x *= in; y *= in; z *= in;
+  R[0] = 1.0 - 2.0 * (y * y + z * z); R[1] = 2.0 * (x * y - w * z); R[2] = 2.0 * (x * z + w * y);
+  R[3] = 2.0 * (x * y + w * z); R[4] = 1.0 - 2.0 * (x * x + z * z); R[5] = 2.0 * (y * z - w * x);
+  R[6] = 2.0 * (x * z - w * y); R[7] = 2.0 * (y * z + w * x); R[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+}  // namespace cm

@@ -1,0 +1,80 @@
+// Internal structures shared by the host runtime and the gfx950 kernels.
+#pragma once
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/cm.h"
+
+namespace cm {
+
+// One geometry record in device memory (64 bytes).  Offsets index the
+// context's vertex / edge / face pools; all coordinates are in the body frame.
+struct GeomRec {
+  int32_t type, nv, ne, nf;
+  int32_t v_off, e_off, f_off, pad0;
+  float p[4];        // sphere (r) | capsule (r, h) | box (hx, hy, hz, rounding)
+  float bound_r;     // float32 bounding radius about the body origin
+  float pad1[3];
+};
+
+// Device pointers of the geometry tables (structure-of-arrays pools).
+struct Tables {
+  const GeomRec* geoms;
+  int32_t n_geoms;
+  const float* vx; const float* vy; const float* vz;       // vertex pool
+  const int32_t* e0; const int32_t* e1;                    // edge pool (local vertex ids)
+  const float* fnx; const float* fny; const float* fnz; const float* fo;   // plane pool
+  const int32_t* f0; const int32_t* f1; const int32_t* f2; // face vertex ids (local)
+};
+
+struct BatchDev {
+  int32_t n_scenes, n_bodies, n_cand;
+  const int32_t* body_offsets;
+  const int32_t* body_geom;
+  const float* pose;
+  const int32_t* cand_offsets;
+  const int32_t* cand_pairs;
+};
+
+struct ParamsDev {
+  double tau, lam, eps_n;   // tau is the float32 input widened; defaults resolved in float64
+  float margin;             // broadphase margin (float32 predicate)
+  int32_t K;
+};
+
+struct OutDev {
+  int32_t capacity;
+  int32_t* n_pairs;
+  int32_t* pair_offsets;
+  int32_t* pairs;
+  float* point; float* normal; float* dist; float* weight;
+};
+
+// Device error bits (sticky until cm_check_errors).
+enum : uint32_t { ERR_BAD_GEOM = 1u, ERR_CAPACITY = 2u, ERR_K = 4u };
+
+// Host-side mesh of one geometry, built by geometry.cpp.
+struct HostMesh {
+  int32_t type = 0;
+  float p[4] = {0, 0, 0, 0};
+  std::vector<float> v;       // 3 * nv
+  std::vector<int32_t> e;     // 2 * ne
+  std::vector<int32_t> f;     // 3 * nf (polytopes)
+  std::vector<float> planes;  // 4 * nf (n, o)
+  float bound_r = 0.f;
+};
+
+// Build the mesh of one descriptor; returns false (with a message) for
+// degenerate input.
+bool build_mesh(int32_t type, const float* params, const float* pts, int64_t n_pts, HostMesh* out,
+                std::string* err);
+
+// Convex hull of points (double precision incremental construction).
+// Returns hull vertex ids (ascending input order), outward triangles
+// (indices into that vertex list) and unique edges (i < j).
+bool convex_hull(const float* pts, int64_t n, std::vector<int32_t>* vid, std::vector<int32_t>* tris,
+                 std::vector<int32_t>* edges, std::string* err);
+
+}  // namespace cm

@@ -1,0 +1,256 @@
+// Host-side geometry construction: analytic-body meshes, convex hulls of
+// polytope point sets, face planes and bounding radii (Sec. IV-A: every
+// surface carries a mesh (V, E) and an SDF; Sec. IV-B: a convex polyhedron
+// is the set of its face planes (n_f, p_f)).
+//
+// Compiled with -ffp-contract=off so the float32 bounding radius follows the
+// documented operation order exactly.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <unordered_set>
+
+#include "cm_internal.h"
+
+namespace cm {
+namespace {
+
+struct Face {
+  int a, b, c;
+  double n[3];
+  double d;
+  bool alive;
+};
+
+inline void sub3(const double* a, const double* b, double* o) {
+  o[0] = a[0] - b[0]; o[1] = a[1] - b[1]; o[2] = a[2] - b[2];
+}
+inline void cross3(const double* a, const double* b, double* o) {
+  o[0] = a[1] * b[2] - a[2] * b[1];
+  o[1] = a[2] * b[0] - a[0] * b[2];
+  o[2] = a[0] * b[1] - a[1] * b[0];
+}
+inline double dot3(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+Face make_face(const std::vector<double>& P, int a, int b, int c) {
+  Face f;
+  f.a = a; f.b = b; f.c = c; f.alive = true;
+  double u[3], v[3];
+  sub3(&P[3 * b], &P[3 * a], u);
+  sub3(&P[3 * c], &P[3 * a], v);
+  cross3(u, v, f.n);
+  double l = std::sqrt(dot3(f.n, f.n));
+  if (l > 0) { f.n[0] /= l; f.n[1] /= l; f.n[2] /= l; }
+  f.d = dot3(f.n, &P[3 * a]);
+  return f;
+}
+
+inline uint64_t ekey(int a, int b) { return (uint64_t(uint32_t(a)) << 32) | uint32_t(b); }
+
+void ring(double lat_deg, double out[8][3]) {
+  const double la = lat_deg * M_PI / 180.0;
+  for (int j = 0; j < 8; ++j) {
+    const double th = 2.0 * M_PI * j / 8.0;
+    out[j][0] = std::cos(la) * std::cos(th);
+    out[j][1] = std::cos(la) * std::sin(th);
+    out[j][2] = std::sin(la);
+  }
+}
+
+}  // namespace
+
+bool convex_hull(const float* pts, int64_t n, std::vector<int32_t>* vid, std::vector<int32_t>* tris,
+                 std::vector<int32_t>* edges, std::string* err) {
+  if (n < 4) { *err = "polytope needs at least 4 points"; return false; }
+  std::vector<double> P(3 * n);
+  double scale = 0;
+  for (int64_t i = 0; i < 3 * n; ++i) {
+    P[i] = double(pts[i]);
+    if (!std::isfinite(P[i])) { *err = "non-finite polytope point"; return false; }
+    scale = std::max(scale, std::fabs(P[i]));
+  }
+  if (scale == 0) { *err = "degenerate polytope"; return false; }
+  const double eps = 1e-10 * scale;
+
+  // initial tetrahedron from extreme points
+  int i0 = 0;
+  for (int i = 1; i < n; ++i) if (P[3 * i] < P[3 * i0]) i0 = i;
+  int i1 = -1; double best = -1;
+  for (int i = 0; i < n; ++i) {
+    double d[3]; sub3(&P[3 * i], &P[3 * i0], d);
+    double v = dot3(d, d);
+    if (v > best) { best = v; i1 = i; }
+  }
+  if (best <= eps * eps) { *err = "degenerate polytope (coincident points)"; return false; }
+  int i2 = -1; best = -1;
+  double e01[3]; sub3(&P[3 * i1], &P[3 * i0], e01);
+  for (int i = 0; i < n; ++i) {
+    double d[3], c[3]; sub3(&P[3 * i], &P[3 * i0], d); cross3(e01, d, c);
+    double v = dot3(c, c);
+    if (v > best) { best = v; i2 = i; }
+  }
+  if (best <= eps * eps * dot3(e01, e01)) { *err = "degenerate polytope (collinear points)"; return false; }
+  Face base = make_face(P, i0, i1, i2);
+  int i3 = -1; best = -1;
+  for (int i = 0; i < n; ++i) {
+    double v = std::fabs(dot3(base.n, &P[3 * i]) - base.d);
+    if (v > best) { best = v; i3 = i; }
+  }
+  if (best <= eps) { *err = "degenerate polytope (coplanar points)"; return false; }
+
+  std::vector<Face> F;
+  const int tet[4][3] = {{i0, i1, i2}, {i0, i1, i3}, {i0, i2, i3}, {i1, i2, i3}};
+  double cen[3] = {0, 0, 0};
+  for (int q : {i0, i1, i2, i3}) for (int k = 0; k < 3; ++k) cen[k] += 0.25 * P[3 * q + k];
+  for (auto& t : tet) {
+    Face f = make_face(P, t[0], t[1], t[2]);
+    if (dot3(f.n, cen) - f.d > 0) f = make_face(P, t[0], t[2], t[1]);
+    F.push_back(f);
+  }
+
+  std::vector<int> visible;
+  std::unordered_set<uint64_t> vis_edges;
+  std::vector<std::pair<int, int>> horizon;
+  for (int p = 0; p < n; ++p) {
+    if (p == i0 || p == i1 || p == i2 || p == i3) continue;
+    const double* x = &P[3 * p];
+    visible.clear();
+    for (int fi = 0; fi < int(F.size()); ++fi)
+      if (F[fi].alive && dot3(F[fi].n, x) - F[fi].d > eps) visible.push_back(fi);
+    if (visible.empty()) continue;  // interior point
+    vis_edges.clear();
+    for (int fi : visible) {
+      const Face& f = F[fi];
+      vis_edges.insert(ekey(f.a, f.b)); vis_edges.insert(ekey(f.b, f.c)); vis_edges.insert(ekey(f.c, f.a));
+    }
+    horizon.clear();
+    for (int fi : visible) {
+      const Face& f = F[fi];
+      const int es[3][2] = {{f.a, f.b}, {f.b, f.c}, {f.c, f.a}};
+      for (auto& e : es)
+        if (!vis_edges.count(ekey(e[1], e[0]))) horizon.push_back({e[0], e[1]});
+    }
+    for (int fi : visible) F[fi].alive = false;
+    for (auto& e : horizon) F.push_back(make_face(P, e.first, e.second, p));
+    if (F.size() > 8 * size_t(n) + 64) {  // compact dead faces
+      std::vector<Face> G;
+      for (auto& f : F) if (f.alive) G.push_back(f);
+      F.swap(G);
+    }
+  }
+
+  std::vector<int32_t> remap(n, -1);
+  std::vector<int32_t> used;
+  for (auto& f : F) if (f.alive) { remap[f.a] = 1; remap[f.b] = 1; remap[f.c] = 1; }
+  vid->clear();
+  for (int i = 0; i < n; ++i) if (remap[i] == 1) { remap[i] = int32_t(vid->size()); vid->push_back(i); }
+  tris->clear();
+  std::vector<std::pair<int, int>> es;
+  for (auto& f : F) {
+    if (!f.alive) continue;
+    int a = remap[f.a], b = remap[f.b], c = remap[f.c];
+    tris->push_back(a); tris->push_back(b); tris->push_back(c);
+    es.push_back({std::min(a, b), std::max(a, b)});
+    es.push_back({std::min(b, c), std::max(b, c)});
+    es.push_back({std::min(c, a), std::max(c, a)});
+  }
+  std::sort(es.begin(), es.end());
+  es.erase(std::unique(es.begin(), es.end()), es.end());
+  edges->clear();
+  for (auto& e : es) { edges->push_back(e.first); edges->push_back(e.second); }
+  const int64_t V = vid->size(), E = es.size(), Fn = tris->size() / 3;
+  if (V - E + Fn != 2) { *err = "hull construction failed (Euler characteristic)"; return false; }
+  return true;
+}
+
+bool build_mesh(int32_t type, const float* params, const float* pts, int64_t n_pts, HostMesh* out,
+                std::string* err) {
+  HostMesh& m = *out;
+  m = HostMesh();
+  m.type = type;
+  for (int k = 0; k < 4; ++k) m.p[k] = params ? params[k] : 0.f;
+  auto push_v = [&](double x, double y, double z) {
+    m.v.push_back(float(x)); m.v.push_back(float(y)); m.v.push_back(float(z));
+  };
+  auto push_e = [&](int a, int b) { m.e.push_back(a); m.e.push_back(b); };
+  if (type == CM_SPHERE || type == CM_CAPSULE) {
+    const double r = m.p[0], h = (type == CM_CAPSULE) ? double(m.p[1]) : 0.0;
+    if (!(r > 0) || !(h >= 0)) { *err = "sphere/capsule needs r > 0, half_len >= 0"; return false; }
+    double rl[8][3], r0[8][3], rh[8][3];
+    ring(-45, rl); ring(0, r0); ring(45, rh);
+    if (type == CM_SPHERE) {
+      // south pole, rings at -45 / 0 / +45 degrees, north pole: 26 V, 56 E
+      push_v(0, 0, -r);
+      for (auto& d : rl) push_v(r * d[0], r * d[1], r * d[2]);
+      for (auto& d : r0) push_v(r * d[0], r * d[1], r * d[2]);
+      for (auto& d : rh) push_v(r * d[0], r * d[1], r * d[2]);
+      push_v(0, 0, r);
+      for (int j = 0; j < 8; ++j) push_e(0, 1 + j);
+      for (int rr : {1, 9, 17}) for (int j = 0; j < 8; ++j) push_e(rr + j, rr + (j + 1) % 8);
+      for (int j = 0; j < 8; ++j) push_e(1 + j, 9 + j);
+      for (int j = 0; j < 8; ++j) push_e(9 + j, 17 + j);
+      for (int j = 0; j < 8; ++j) push_e(17 + j, 25);
+    } else {
+      // lower hemisphere (centre -h) and upper hemisphere (centre +h): 34 V, 72 E
+      push_v(0, 0, -r - h);
+      for (auto& d : rl) push_v(r * d[0], r * d[1], r * d[2] - h);
+      for (auto& d : r0) push_v(r * d[0], r * d[1], r * d[2] - h);
+      for (auto& d : r0) push_v(r * d[0], r * d[1], r * d[2] + h);
+      for (auto& d : rh) push_v(r * d[0], r * d[1], r * d[2] + h);
+      push_v(0, 0, r + h);
+      for (int j = 0; j < 8; ++j) push_e(0, 1 + j);
+      for (int rr : {1, 9, 17, 25}) for (int j = 0; j < 8; ++j) push_e(rr + j, rr + (j + 1) % 8);
+      for (int j = 0; j < 8; ++j) push_e(1 + j, 9 + j);
+      for (int j = 0; j < 8; ++j) push_e(9 + j, 17 + j);
+      for (int j = 0; j < 8; ++j) push_e(17 + j, 25 + j);
+      for (int j = 0; j < 8; ++j) push_e(25 + j, 33);
+    }
+    m.bound_r = (type == CM_SPHERE) ? m.p[0] : (m.p[1] + m.p[0]);
+    return true;
+  }
+  if (type == CM_BOX) {
+    if (!(m.p[0] > 0 && m.p[1] > 0 && m.p[2] > 0) || !(m.p[3] >= 0) ||
+        m.p[3] > std::min(m.p[0], std::min(m.p[1], m.p[2]))) {
+      *err = "box needs half-extents > 0 and 0 <= rounding <= min half-extent";
+      return false;
+    }
+    for (int i = 0; i < 8; ++i)
+      push_v((i & 1) ? m.p[0] : -m.p[0], (i & 2) ? m.p[1] : -m.p[1], (i & 4) ? m.p[2] : -m.p[2]);
+    for (int bit : {1, 2, 4}) for (int i = 0; i < 8; ++i) if (!(i & bit)) push_e(i, i | bit);
+    const float hx = m.p[0], hy = m.p[1], hz = m.p[2];
+    m.bound_r = std::sqrt((hx * hx + hy * hy) + hz * hz);
+    return true;
+  }
+  if (type == CM_POLYTOPE) {
+    std::vector<int32_t> vid, tris, edges;
+    if (!convex_hull(pts, n_pts, &vid, &tris, &edges, err)) return false;
+    for (int32_t i : vid) { m.v.push_back(pts[3 * i]); m.v.push_back(pts[3 * i + 1]); m.v.push_back(pts[3 * i + 2]); }
+    m.e = edges;
+    m.f = tris;
+    const size_t nf = tris.size() / 3;
+    for (size_t t = 0; t < nf; ++t) {
+      double a[3], b[3], c[3];
+      for (int k = 0; k < 3; ++k) {
+        a[k] = m.v[3 * tris[3 * t] + k]; b[k] = m.v[3 * tris[3 * t + 1] + k]; c[k] = m.v[3 * tris[3 * t + 2] + k];
+      }
+      double u[3], v[3], nn[3];
+      sub3(b, a, u); sub3(c, a, v); cross3(u, v, nn);
+      double l = std::sqrt(dot3(nn, nn));
+      for (int k = 0; k < 3; ++k) nn[k] /= l;
+      m.planes.push_back(float(nn[0])); m.planes.push_back(float(nn[1])); m.planes.push_back(float(nn[2]));
+      m.planes.push_back(float(dot3(nn, a)));
+    }
+    float mx = 0.f;
+    for (int64_t i = 0; i < n_pts; ++i) {
+      const float x = pts[3 * i], y = pts[3 * i + 1], z = pts[3 * i + 2];
+      const float q = (x * x + y * y) + z * z;
+      mx = std::max(mx, q);
+    }
+    m.bound_r = std::sqrt(mx);
+    return true;
+  }
+  *err = "unknown geometry type";
+  return false;
+}
+
+}  // namespace cm

@@ -70,6 +70,10 @@ class Batch:
     name: str = ""
     meta: dict = field(default_factory=dict)
 
+    def __post_init__(self):
+        # tau crosses the boundary as float32: keep the float32 value on both sides
+        self.tau = float(np.float32(self.tau))
+
     @property
     def n_scenes(self) -> int:
         return int(self.body_offsets.shape[0] - 1)
