@@ -205,3 +205,70 @@ class Context:
         fn = self.lib.cm_collide_fused if fused else self.lib.cm_collide
         self._check(fn(self.h, C.byref(b), C.byref(prm), C.byref(m), _stream_handle(stream)))
         return out
+
+    # ------------------------------------------------------------- backward
+    def collide_backward(self, db: DeviceBatch, fwd: Manifold, tau: float, K: int, g_point=None, g_normal=None,
+                         g_dist=None, g_weight=None, stream=None, want_vertices=True, want_params=True,
+                         lambda_reg=-1.0, eps_n=-1.0, cull_margin=-1.0) -> dict:
+        """Vector-Jacobian product of the manifold for the given cotangents.
+
+        Returns device tensors: pose [6, n_bodies] (left twists rho, omega),
+        vertices [3, vertex_pool] (polytope hull vertices), params
+        [4, n_geometries] (analytic parameters), tau [1].
+        """
+        dev = self.device
+        out = dict(pose=torch.empty(6, db.n_bodies, dtype=torch.float32, device=dev),
+                   vertices=torch.empty(3, max(self.vertex_pool_size, 1), dtype=torch.float32, device=dev)
+                   if want_vertices else None,
+                   params=torch.empty(4, max(self.geometry_count, 1), dtype=torch.float32, device=dev)
+                   if want_params else None,
+                   tau=torch.empty(1, dtype=torch.float32, device=dev))
+        cot = L.cm_cotangent()
+        cot.g_point, cot.g_normal, cot.g_dist, cot.g_weight = (_ptr(t) for t in (g_point, g_normal, g_dist, g_weight))
+        gr = L.cm_grads()
+        gr.g_pose, gr.g_vertices, gr.g_params, gr.g_tau = (_ptr(out[k]) for k in ("pose", "vertices", "params", "tau"))
+        prm = make_params(tau, K, lambda_reg, eps_n, cull_margin)
+        b = db.as_c()
+        m = fwd.as_c()
+        self._check(self.lib.cm_collide_backward(self.h, C.byref(b), C.byref(prm), C.byref(m), C.byref(cot),
+                                                 C.byref(gr), _stream_handle(stream)))
+        return out
+
+
+class _CollideFn(torch.autograd.Function):
+    """Differentiable manifold: inputs are zero-valued leaves standing for the
+    pose twists, hull vertices, analytic parameters and tau; the forward runs
+    cm_collide at the batch's poses, the backward cm_collide_backward."""
+
+    @staticmethod
+    def forward(fctx, xi, verts, params, tau_t, cmctx, db, K, capacity, fused):
+        tau = float(tau_t.item())
+        m = cmctx.collide(db, tau, K, capacity, fused=fused)
+        fctx.cm = (cmctx, db, m, tau, K)
+        fctx.mark_non_differentiable(m.n_pairs, m.pairs)
+        return m.point, m.normal, m.dist, m.weight, m.n_pairs, m.pairs
+
+    @staticmethod
+    def backward(fctx, gp, gn, gd, gw, _n, _p):
+        cmctx, db, m, tau, K = fctx.cm
+        c = lambda t: None if t is None else t.contiguous()
+        g = cmctx.collide_backward(db, m, tau, K, c(gp), c(gn), c(gd), c(gw))
+        return g["pose"], g["vertices"], g["params"], g["tau"], None, None, None, None, None
+
+
+def collide_autograd(cmctx: Context, db: DeviceBatch, tau_t: torch.Tensor, K: int, xi=None, verts=None,
+                     params=None, capacity=None, fused=False):
+    """Manifold outputs (point, normal, dist, weight, n_pairs, pairs) that
+    autograd can differentiate.  ``xi`` [6, n_bodies] must be zeros (the
+    twist at which the gradient is taken); ``verts`` [3, vertex_pool] and
+    ``params`` [4, n_geometries] are placeholders that receive geometry
+    gradients."""
+    dev = cmctx.device
+    if xi is None:
+        xi = torch.zeros(6, db.n_bodies, device=dev, requires_grad=True)
+    if verts is None:
+        verts = torch.zeros(3, max(cmctx.vertex_pool_size, 1), device=dev, requires_grad=True)
+    if params is None:
+        params = torch.zeros(4, max(cmctx.geometry_count, 1), device=dev, requires_grad=True)
+    cap = db.n_cand_total if capacity is None else capacity
+    return _CollideFn.apply(xi, verts, params, tau_t, cmctx, db, K, cap, fused)

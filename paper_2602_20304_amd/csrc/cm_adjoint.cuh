@@ -1,0 +1,275 @@
+// Reverse-mode derivatives of the per-candidate computations (the gradient
+// the paper obtains by automatic differentiation of the routine).  Each
+// function recomputes its forward intermediates from the inputs, then walks
+// the operations backwards.  Derivative conventions at kinks: |x|' = sign(x)
+// with sign(0) = 0 for the SoftSort distance, clamp' = 1 inside / 0 outside,
+// the rounded-box interior face is the lowest index of the maximum.
+#pragma once
+#include "cm_device.cuh"
+
+namespace cm {
+
+__device__ __forceinline__ D3 add(const D3& a, const D3& b) { return d3(a.x + b.x, a.y + b.y, a.z + b.z); }
+__device__ __forceinline__ D3 sub(const D3& a, const D3& b) { return d3(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ __forceinline__ D3 scl(const D3& a, double s) { return d3(a.x * s, a.y * s, a.z * s); }
+__device__ __forceinline__ D3 axpy(double s, const D3& a, const D3& b) { return d3(fma(s, a.x, b.x), fma(s, a.y, b.y), fma(s, a.z, b.z)); }
+__device__ __forceinline__ D3 cross(const D3& a, const D3& b) {
+  return d3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ D3 rot(const double* R, const D3& v) {
+  return d3(R[0] * v.x + R[1] * v.y + R[2] * v.z, R[3] * v.x + R[4] * v.y + R[5] * v.z, R[6] * v.x + R[7] * v.y + R[8] * v.z);
+}
+__device__ __forceinline__ D3 rotT(const double* R, const D3& v) {
+  return d3(R[0] * v.x + R[3] * v.y + R[6] * v.z, R[1] * v.x + R[4] * v.y + R[7] * v.z, R[2] * v.x + R[5] * v.y + R[8] * v.z);
+}
+
+// d/du and d/dtau of ln sigma(u / tau)
+__device__ __forceinline__ void lsig_d(double u, const Temp& T, double& du, double& dtau) {
+  const double om = sig64(-u, T);           // 1 - sigma(u / tau)
+  du = om * T.inv_tau;
+  dtau = -u * om * T.inv_tau * T.inv_tau;
+}
+
+// Wave sum of a float (all 64 lanes must participate).
+__device__ __forceinline__ float wave_sumf(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Gradient sinks of one body during the adjoint of a pair (LDS, float atomics).
+struct BodySink {
+  float* plane;    // [4][maxF] adjoints of (n.xyz, o) in the body frame, or null
+  float* param;    // [4] adjoints of the analytic parameters
+  int maxF;
+};
+
+// Adjoint of the body-frame SDF query (phi, g) at l given (phi_bar, g_bar).
+// Returns l_bar; accumulates parameter / plane adjoints and tau_bar.
+// WAVE: all 64 lanes execute this call together (plane adjoints are summed
+// across the wave before one atomic per plane).
+template <bool WAVE>
+__device__ __forceinline__ D3 sdf_local_bwd(int type, const float* p, const float4* __restrict__ pl, int nf, const D3& l,
+                                            double phib, const D3& gb, const Temp& T, const BodySink& sink,
+                                            double& taub, D3& g_out) {
+  if (type == CM_SPHERE) {
+    const double s = dot(l, l), n = sqrt(s), inv = s > 0.0 ? 1.0 / n : 0.0;
+    const D3 g = scl(l, inv);
+    g_out = g;
+    const double gg = dot(g, gb);
+    atomicAdd(&sink.param[0], float(-phib));
+    return add(scl(g, phib), scl(sub(gb, scl(g, gg)), inv));
+  }
+  if (type == CM_CAPSULE) {
+    const double h = p[1];
+    const double zc = fmin(fmax(l.z, -h), h);
+    const D3 y = d3(l.x, l.y, l.z - zc);
+    const double s = dot(y, y), n = sqrt(s), inv = s > 0.0 ? 1.0 / n : 0.0;
+    const D3 g = scl(y, inv);
+    g_out = g;
+    const D3 yb = add(scl(g, phib), scl(sub(gb, scl(g, dot(g, gb))), inv));
+    const bool above = l.z > h, below = l.z < -h;
+    atomicAdd(&sink.param[0], float(-phib));
+    atomicAdd(&sink.param[1], float(above ? -yb.z : (below ? yb.z : 0.0)));
+    return d3(yb.x, yb.y, (above || below) ? yb.z : 0.0);
+  }
+  if (type == CM_BOX) {
+    const double rr = p[3];
+    const double q[3] = {fabs(l.x) - (double(p[0]) - rr), fabs(l.y) - (double(p[1]) - rr), fabs(l.z) - (double(p[2]) - rr)};
+    const double sg[3] = {sgn1(l.x), sgn1(l.y), sgn1(l.z)};
+    const double m[3] = {fmax(q[0], 0.0), fmax(q[1], 0.0), fmax(q[2], 0.0)};
+    const double s = m[0] * m[0] + m[1] * m[1] + m[2] * m[2];
+    const double gbv[3] = {gb.x, gb.y, gb.z};
+    double qb[3] = {0.0, 0.0, 0.0};
+    double rhob = -phib;
+    if (s > 0.0) {
+      const double n = sqrt(s), inv = 1.0 / n;
+      g_out = d3(sg[0] * m[0] * inv, sg[1] * m[1] * inv, sg[2] * m[2] * inv);
+      // phi = |m| - rho ; g_i = sg_i m_i / |m|
+      double sgb = 0.0;
+      for (int i = 0; i < 3; ++i) sgb += sg[i] * gbv[i] * m[i];
+      for (int i = 0; i < 3; ++i) {
+        const double mb = phib * m[i] * inv + sg[i] * gbv[i] * inv - m[i] * sgb * inv * inv * inv;
+        qb[i] = q[i] > 0.0 ? mb : 0.0;
+      }
+    } else {
+      const int j = (q[0] >= q[1] && q[0] >= q[2]) ? 0 : (q[1] >= q[2] ? 1 : 2);
+      g_out = d3(j == 0 ? sg[0] : 0.0, j == 1 ? sg[1] : 0.0, j == 2 ? sg[2] : 0.0);
+      qb[j] = phib;
+    }
+    // q_i = |l_i| - (h_i - rho)
+    for (int i = 0; i < 3; ++i) {
+      atomicAdd(&sink.param[i], float(-qb[i]));
+      rhob += qb[i];
+    }
+    atomicAdd(&sink.param[3], float(rhob));
+    return d3(sg[0] * qb[0], sg[1] * qb[1], sg[2] * qb[2]);
+  }
+  // polytope: phi = tau LSE(y / tau), y_f = n_f . l - o_f, g = sum_f pi_f n_f
+  double m = -1e300;
+  for (int f = 0; f < nf; ++f) {
+    const float4 q = pl[f];
+    m = fmax(m, fma(double(q.x), l.x, fma(double(q.y), l.y, fma(double(q.z), l.z, -double(q.w)))));
+  }
+  double S = 0.0, gx = 0.0, gy = 0.0, gz = 0.0, py = 0.0;
+  for (int f = 0; f < nf; ++f) {
+    const float4 q = pl[f];
+    const double yv = fma(double(q.x), l.x, fma(double(q.y), l.y, fma(double(q.z), l.z, -double(q.w))));
+    const double e = double(ex2f(float((yv - m) * T.c)));
+    S += e; gx = fma(e, double(q.x), gx); gy = fma(e, double(q.y), gy); gz = fma(e, double(q.z), gz);
+    py = fma(e, yv, py);
+  }
+  const double iS = 1.0 / S;
+  const D3 g = d3(gx * iS, gy * iS, gz * iS);
+  g_out = g;
+  const double phi = m + T.tau * log(S);
+  const double gbg = dot(gb, g);
+  taub += phib * (phi - py * iS) * T.inv_tau;
+  D3 lb = d3(0.0, 0.0, 0.0);
+  double tz = 0.0;
+  for (int f = 0; f < nf; ++f) {
+    const float4 q = pl[f];
+    const double yv = fma(double(q.x), l.x, fma(double(q.y), l.y, fma(double(q.z), l.z, -double(q.w))));
+    const double pi = double(ex2f(float((yv - m) * T.c))) * iS;
+    const double zb = pi * (gb.x * q.x + gb.y * q.y + gb.z * q.z - gbg);   // softmax adjoint of g
+    const double yb = phib * pi + zb * T.inv_tau;
+    tz += zb * yv;
+    lb = d3(fma(yb, double(q.x), lb.x), fma(yb, double(q.y), lb.y), fma(yb, double(q.z), lb.z));
+    if (sink.plane) {
+      float v0 = float(yb * l.x + pi * gb.x), v1 = float(yb * l.y + pi * gb.y), v2 = float(yb * l.z + pi * gb.z),
+            v3 = float(-yb);
+      if (WAVE) {
+        v0 = wave_sumf(v0); v1 = wave_sumf(v1); v2 = wave_sumf(v2); v3 = wave_sumf(v3);
+        if ((threadIdx.x & 63) == 0) {
+          atomicAdd(&sink.plane[f], v0); atomicAdd(&sink.plane[sink.maxF + f], v1);
+          atomicAdd(&sink.plane[2 * sink.maxF + f], v2); atomicAdd(&sink.plane[3 * sink.maxF + f], v3);
+        }
+      } else {
+        atomicAdd(&sink.plane[f], v0); atomicAdd(&sink.plane[sink.maxF + f], v1);
+        atomicAdd(&sink.plane[2 * sink.maxF + f], v2); atomicAdd(&sink.plane[3 * sink.maxF + f], v3);
+      }
+    }
+  }
+  taub -= tz * T.inv_tau * T.inv_tau;
+  return lb;
+}
+
+// Twist adjoint of body B's placement in the pair frame: rho and omega parts.
+struct Twist {
+  double r[3], w[3];
+};
+
+// Adjoint of an SDF query of body V at pair-frame point x.  For body B
+// (not ident) the query moves with B: its placement twist receives
+// rho -= x_bar, omega += g x g_bar - x x x_bar.
+template <bool WAVE>
+__device__ __forceinline__ D3 sdf_body_bwd(const BodyView& V, const D3& x, double phib, const D3& gb, const Temp& T,
+                                           const BodySink& sink, double& taub, Twist& tw) {
+  if (V.ident) {
+    D3 g;
+    return sdf_local_bwd<WAVE>(V.type, V.p, V.planes, V.nf, x, phib, gb, T, sink, taub, g);
+  }
+  const D3 l = rotT(V.R, sub(x, d3(V.t[0], V.t[1], V.t[2])));
+  const D3 gbl = rotT(V.R, gb);
+  D3 gl;
+  const D3 lb = sdf_local_bwd<WAVE>(V.type, V.p, V.planes, V.nf, l, phib, gbl, T, sink, taub, gl);
+  const D3 xb = rot(V.R, lb);
+  const D3 g = rot(V.R, gl);
+  const D3 c1 = cross(g, gb), c2 = cross(x, xb);
+  tw.r[0] -= xb.x; tw.r[1] -= xb.y; tw.r[2] -= xb.z;
+  tw.w[0] += c1.x - c2.x; tw.w[1] += c1.y - c2.y; tw.w[2] += c1.z - c2.z;
+  return xb;
+}
+
+// Adjoint of the smoothed E-E QP (recomputes the forward).  Given adjoints of
+// (al1, al2, log_con) accumulates adjoints of the edge data a0, t1, b0, t2 and tau.
+__device__ __forceinline__ void ee_qp_bwd(const D3& a0, const D3& t1, const D3& b0, const D3& t2, double lam,
+                                          const Temp& T, double al1b, double al2b, double lcb, D3& a0b, D3& t1b,
+                                          D3& b0b, D3& t2b, double& taub) {
+  // ---- forward
+  const D3 b = sub(a0, b0);
+  const double Q11 = dot(t1, t1) + lam, Q22 = dot(t2, t2) + lam, Q12 = -dot(t1, t2);
+  const double hl = 0.5 * lam;
+  const double c1 = dot(b, t1) - hl, c2 = -dot(b, t2) - hl;
+  const double det = Q11 * Q22 - Q12 * Q12, idet = 1.0 / det;
+  const double au1 = (Q12 * c2 - c1 * Q22) * idet, au2 = (Q12 * c1 - c2 * Q11) * idet;
+  const double i11 = 1.0 / Q11, i22 = 1.0 / Q22;
+  const double xi[4] = {-(Q12 + c2) * i22, -c2 * i22, -(Q12 + c1) * i11, -c1 * i11};
+  double x[4];
+  for (int i = 0; i < 4; ++i) x[i] = clip01(xi[i], T);
+  const double A1[4] = {1.0, 0.0, x[2], x[3]}, A2[4] = {x[0], x[1], 1.0, 0.0};
+  D3 r[4];
+  double j[4];
+  for (int i = 0; i < 4; ++i) {
+    r[i] = d3(b.x + A1[i] * t1.x - A2[i] * t2.x, b.y + A1[i] * t1.y - A2[i] * t2.y, b.z + A1[i] * t1.z - A2[i] * t2.z);
+    const double u = A1[i] - 0.5, v = A2[i] - 0.5;
+    j[i] = 0.5 * (dot(r[i], r[i]) + lam * (u * u + v * v));
+  }
+  const double jm = fmin(fmin(j[0], j[1]), fmin(j[2], j[3]));
+  double w[4], ws = 0.0;
+  for (int i = 0; i < 4; ++i) { w[i] = exp64n(-(j[i] - jm) * T.inv_tau); ws += w[i]; }
+  double pi[4];
+  for (int i = 0; i < 4; ++i) pi[i] = w[i] / ws;
+  const double ac1 = pi[0] + pi[2] * x[2] + pi[3] * x[3];
+  const double ac2 = pi[0] * x[0] + pi[1] * x[1] + pi[2];
+  const double u[4] = {au1, 1.0 - au1, au2, 1.0 - au2};
+  double Sg[4];
+  for (int i = 0; i < 4; ++i) Sg[i] = sig64(u[i], T);
+  const double con = (Sg[0] * Sg[1]) * (Sg[2] * Sg[3]);
+  // ---- reverse
+  const double conb = al1b * (au1 - ac1) + al2b * (au2 - ac2);
+  double au1b = al1b * con, au2b = al2b * con;
+  const double ac1b = al1b * (1.0 - con), ac2b = al2b * (1.0 - con);
+  const double W = conb * con + lcb;
+  au1b += W * ((1.0 - Sg[0]) - (1.0 - Sg[1])) * T.inv_tau;
+  au2b += W * ((1.0 - Sg[2]) - (1.0 - Sg[3])) * T.inv_tau;
+  taub -= W * (u[0] * (1.0 - Sg[0]) + u[1] * (1.0 - Sg[1]) + u[2] * (1.0 - Sg[2]) + u[3] * (1.0 - Sg[3])) *
+          T.inv_tau * T.inv_tau;
+  const double pib[4] = {ac1b + ac2b * x[0], ac2b * x[1], ac1b * x[2] + ac2b, ac1b * x[3]};
+  double xb[4] = {ac2b * pi[0], ac2b * pi[1], ac1b * pi[2], ac1b * pi[3]};
+  double ps = 0.0;
+  for (int i = 0; i < 4; ++i) ps += pi[i] * pib[i];
+  D3 bb = d3(0.0, 0.0, 0.0);
+  for (int i = 0; i < 4; ++i) {
+    const double zb = pi[i] * (pib[i] - ps);
+    const double jb = -zb * T.inv_tau;
+    taub += zb * (j[i] - jm) * T.inv_tau * T.inv_tau;
+    bb = axpy(jb, r[i], bb);
+    t1b = axpy(jb * A1[i], r[i], t1b);
+    t2b = axpy(-jb * A2[i], r[i], t2b);
+    if (i < 2) xb[i] += jb * (-dot(r[i], t2) + lam * (A2[i] - 0.5));
+    else xb[i] += jb * (dot(r[i], t1) + lam * (A1[i] - 0.5));
+  }
+  double Q11b = 0.0, Q22b = 0.0, Q12b = 0.0, c1b = 0.0, c2b = 0.0;
+  for (int i = 0; i < 4; ++i) {
+    const double a = xi[i], s0 = sig64(a, T), s1 = sig64(a - 1.0, T);
+    const double xib = xb[i] * (s0 - s1);
+    taub += xb[i] * ((softplus_t(a, T) - a * s0) - (softplus_t(a - 1.0, T) - (a - 1.0) * s1)) * T.inv_tau;
+    if (i == 0) { Q12b -= xib * i22; c2b -= xib * i22; Q22b -= xib * xi[0] * i22; }
+    else if (i == 1) { c2b -= xib * i22; Q22b -= xib * xi[1] * i22; }
+    else if (i == 2) { Q12b -= xib * i11; c1b -= xib * i11; Q11b -= xib * xi[2] * i11; }
+    else { c1b -= xib * i11; Q11b -= xib * xi[3] * i11; }
+  }
+  const double N1b = au1b * idet, N2b = au2b * idet;
+  const double detb = -(au1b * au1 + au2b * au2) * idet;
+  Q12b += N1b * c2 + N2b * c1;
+  c2b += N1b * Q12 - N2b * Q11;
+  c1b += -N1b * Q22 + N2b * Q12;
+  Q22b -= N1b * c1;
+  Q11b -= N2b * c2;
+  Q11b += detb * Q22;
+  Q22b += detb * Q11;
+  Q12b -= 2.0 * detb * Q12;
+  t1b = axpy(2.0 * Q11b, t1, t1b);
+  t2b = axpy(2.0 * Q22b, t2, t2b);
+  t1b = axpy(-Q12b, t2, t1b);
+  t2b = axpy(-Q12b, t1, t2b);
+  bb = axpy(c1b, t1, bb);
+  t1b = axpy(c1b, b, t1b);
+  bb = axpy(-c2b, t2, bb);
+  t2b = axpy(-c2b, b, t2b);
+  a0b = add(a0b, bb);
+  b0b = sub(b0b, bb);
+}
+
+}  // namespace cm

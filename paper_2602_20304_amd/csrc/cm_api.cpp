@@ -56,6 +56,14 @@ hipError_t ensure_bytes(void** p, size_t* cap, size_t need) {
   return e;
 }
 
+// Grow a context workspace buffer; captured graphs hold workspace pointers,
+// so any reallocation drops them.
+hipError_t ctx_ensure(cm_context* ctx, void** p, size_t* cap, size_t need) {
+  if (*cap >= need && *p) return hipSuccess;
+  ctx->drop_graphs();
+  return ensure_bytes(p, cap, need);
+}
+
 cm_status ctx_upload_tables(cm_context* ctx) {
   hipError_t e;
 #define UP(field) \
@@ -199,6 +207,8 @@ cm_status cm_geometry_create(cm_context* ctx, int32_t n, const int32_t* types, c
     out_ids[i] = int32_t(h.recs.size());
     h.recs.push_back(r);
   }
+  ctx->geom_version++;
+  ctx->drop_graphs();
   return ctx_upload_tables(ctx);
 }
 
@@ -244,6 +254,7 @@ cm_status resolve_params(cm_context* ctx, const cm_params* prm, ParamsDev* pd) {
   pd->eps_n = prm->eps_n < 0.f ? pd->tau * pd->tau : double(prm->eps_n);
   if (!(pd->eps_n > 0.0)) return cm_fail(ctx, CM_ERR_INVALID_ARG, "eps_n must be > 0");
   pd->margin = prm->cull_margin < 0.f ? 10.0f * prm->tau : prm->cull_margin;
+  pd->eps_tied = prm->eps_n < 0.f ? 1 : 0;
   pd->K = prm->K;
   return CM_OK;
 }
@@ -278,7 +289,7 @@ int kmax_for(int K) { return K <= 8 ? 8 : (K <= 16 ? 16 : 32); }
 cm_status ctx_broadphase(cm_context* ctx, const BatchDev& bd, const ParamsDev& pd, const OutDev& od, hipStream_t st) {
   const Tables tb = ctx_tables(ctx);
   const size_t tiles = size_t(bd.n_scenes) / 1024 + 2;
-  hipError_t e = ensure_bytes(reinterpret_cast<void**>(&ctx->d_tile_sums), &ctx->tile_cap, tiles * sizeof(int));
+  hipError_t e = ctx_ensure(ctx, reinterpret_cast<void**>(&ctx->d_tile_sums), &ctx->tile_cap, tiles * sizeof(int));
   if (e != hipSuccess) return cm_hip(ctx, e, "tile sums");
   return cm_hip(ctx, launch_broadphase(tb, bd, pd.margin, od, ctx->d_tile_sums, ctx->d_err, st), "broadphase launch");
 }
@@ -290,7 +301,7 @@ cm_status ctx_prepare_fwd(cm_context* ctx, const BatchDev& bd, const ParamsDev& 
   f->maxV = std::max(ctx->maxV, 1); f->maxE = std::max(ctx->maxE, 1); f->maxF = std::max(ctx->maxF, 1);
   f->block = block;
   f->kmax = kmax_for(pd.K);
-  f->order = nullptr; f->queue = dynamic ? reinterpret_cast<int*>(1) : nullptr;   // dispatch hint
+  f->order = nullptr; f->range = nullptr; f->queue = dynamic ? reinterpret_cast<int*>(1) : nullptr;   // dispatch hint
   f->err = ctx->d_err;
   const int occ = fwd_occupancy(*f);
   f->queue = nullptr;
@@ -298,7 +309,7 @@ cm_status ctx_prepare_fwd(cm_context* ctx, const BatchDev& bd, const ParamsDev& 
   if (od.capacity > 0 && f->grid > od.capacity && !dynamic) f->grid = std::max(1, od.capacity);
   f->scratch_stride = fwd_scratch_floats(f->maxV, f->maxE);
   const size_t need = size_t(f->grid) * size_t(f->scratch_stride) * sizeof(float);
-  hipError_t e = ensure_bytes(reinterpret_cast<void**>(&ctx->d_scratch), &ctx->scratch_cap, need);
+  hipError_t e = ctx_ensure(ctx, reinterpret_cast<void**>(&ctx->d_scratch), &ctx->scratch_cap, need);
   if (e != hipSuccess) return cm_hip(ctx, e, "forward scratch");
   f->scratch = ctx->d_scratch;
   return CM_OK;
@@ -321,23 +332,45 @@ extern "C" cm_status cm_collide(cm_context* ctx, const cm_batch* batch, const cm
   return cm_hip(ctx, launch_collide_fwd(f, st), "collide launch");
 }
 
-extern "C" cm_status cm_collide_fused(cm_context* ctx, const cm_batch* batch, const cm_params* prm, cm_manifold* out,
-                                      void* stream) {
+extern "C" cm_status cm_collide_backward(cm_context* ctx, const cm_batch* batch, const cm_params* prm,
+                                         const cm_manifold* fwd, const cm_cotangent* cot, cm_grads* out,
+                                         void* stream) {
   if (!ctx) return CM_ERR_INVALID_ARG;
   ParamsDev pd; BatchDev bd; OutDev od;
   cm_status s;
   if ((s = resolve_params(ctx, prm, &pd)) != CM_OK) return s;
   if ((s = resolve_batch(ctx, batch, &bd)) != CM_OK) return s;
-  if ((s = resolve_out(ctx, out, &od)) != CM_OK) return s;
+  if ((s = resolve_out(ctx, fwd, &od)) != CM_OK) return s;
+  if (!cot || !out) return cm_fail(ctx, CM_ERR_INVALID_ARG, "null cotangent or gradient struct");
   hipSetDevice(ctx->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if ((s = ctx_broadphase(ctx, bd, pd, od, st)) != CM_OK) return s;
+  const long long pool = (long long)ctx->h.vx.size();
+  const long long G = (long long)ctx->h.recs.size();
+  hipError_t e;
+  if (out->g_pose && (e = hipMemsetAsync(out->g_pose, 0, sizeof(float) * 6 * size_t(bd.n_bodies), st)) != hipSuccess)
+    return cm_hip(ctx, e, "zero g_pose");
+  if (out->g_vertices && (e = hipMemsetAsync(out->g_vertices, 0, sizeof(float) * 3 * size_t(pool), st)) != hipSuccess)
+    return cm_hip(ctx, e, "zero g_vertices");
+  if (out->g_params && (e = hipMemsetAsync(out->g_params, 0, sizeof(float) * 4 * size_t(G), st)) != hipSuccess)
+    return cm_hip(ctx, e, "zero g_params");
+  if (out->g_tau && (e = hipMemsetAsync(out->g_tau, 0, sizeof(float), st)) != hipSuccess)
+    return cm_hip(ctx, e, "zero g_tau");
   if (od.capacity == 0) return CM_OK;
-  FwdLaunch f;
-  if ((s = ctx_prepare_fwd(ctx, bd, pd, od, 256, true, &f)) != CM_OK) return s;
-  hipError_t e = ensure_bytes(&ctx->d_work, &ctx->work_cap, 256);
-  if (e != hipSuccess) return cm_hip(ctx, e, "work queue");
-  f.queue = static_cast<int*>(ctx->d_work);
-  if ((e = hipMemsetAsync(f.queue, 0, sizeof(int), st)) != hipSuccess) return cm_hip(ctx, e, "queue reset");
-  return cm_hip(ctx, launch_collide_fwd(f, st), "fused collide launch");
+  BwdLaunch b;
+  b.f.tb = ctx_tables(ctx);
+  b.f.bt = bd; b.f.prm = pd; b.f.out = od;
+  b.f.maxV = std::max(ctx->maxV, 1); b.f.maxE = std::max(ctx->maxE, 1); b.f.maxF = std::max(ctx->maxF, 1);
+  b.f.block = 256;
+  b.f.kmax = kmax_for(pd.K);
+  b.f.order = nullptr; b.f.range = nullptr; b.f.queue = nullptr; b.f.err = ctx->d_err;
+  b.cot = CotDev{cot->g_point, cot->g_normal, cot->g_dist, cot->g_weight};
+  b.gr = GradDev{out->g_pose, out->g_vertices, out->g_params, out->g_tau, pool};
+  b.f.grid = std::max(1, bwd_occupancy(b) * ctx->num_cus);
+  if (b.f.grid > od.capacity) b.f.grid = std::max(1, od.capacity);
+  b.f.scratch_stride = fwd_scratch_floats(b.f.maxV, b.f.maxE);
+  const size_t need = size_t(b.f.grid) * size_t(b.f.scratch_stride) * sizeof(float);
+  if ((e = ctx_ensure(ctx, reinterpret_cast<void**>(&ctx->d_scratch), &ctx->scratch_cap, need)) != hipSuccess)
+    return cm_hip(ctx, e, "backward scratch");
+  b.f.scratch = ctx->d_scratch;
+  return cm_hip(ctx, launch_collide_bwd(b, st), "backward launch");
 }

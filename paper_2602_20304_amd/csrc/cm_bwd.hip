@@ -1,0 +1,519 @@
+// gfx950 adjoint of the contact manifold: vector-Jacobian product of the
+// K-contact manifold with respect to body poses (left tangent twists),
+// polytope hull vertices, analytic geometry parameters and tau.
+//
+// One workgroup per kept pair.  The forward phases are recomputed with the
+// shared engine (no E x E state was stored by the forward), then:
+//   A1  SoftSort adjoint, part 1: adjoints of the K top scores s_[k] and the
+//       candidate j_k that attains each of them
+//   A2  per-candidate adjoint for every candidate within 40 tau of s_[K]
+//       (all others have SoftSort weight below exp(-40)): score / weight /
+//       field adjoints -> indicators -> SDF queries -> witness QP -> edges
+//   N   nearest-neighbour adjoint: row / column LSE adjoints flow back into
+//       every unsigned distance D_kl of the touched rows and columns
+//   G   face-plane adjoints -> hull vertices, mesh vertices -> parameters,
+//       B's placement twist and the output transform -> world pose twists
+#include <hip/hip_runtime.h>
+
+#include "cm_adjoint.cuh"
+#include "cm_kernels.h"
+#include "cm_pair.cuh"
+
+namespace cm {
+
+struct BwdLds {
+  int vA, vB, plA, plB, prm, rbar, cbar, cot, F, top, best, tw, bytes;
+};
+
+__host__ __device__ inline BwdLds bwd_layout(int base, int maxV, int maxE, int maxF, int block) {
+  BwdLds L;
+  int o = base;
+  L.vA = o; o += 4 * 3 * maxV;
+  L.vB = o; o += 4 * 3 * maxV;
+  L.plA = o; o += 4 * 4 * maxF;
+  L.plB = o; o += 4 * 4 * maxF;
+  L.prm = o; o += 4 * 8;
+  L.rbar = o; o += 4 * maxE;
+  L.cbar = o; o += 4 * maxE;
+  o = (o + 7) & ~7;
+  L.cot = o; o += 8 * 8 * CM_MAX_K;    // pair-frame cotangents per row: p(3) nu(3) d w
+  L.F = o; o += 8 * 10 * CM_MAX_K;     // normalised row outputs (8) + Z + Gbar
+  L.top = o; o += 8 * CM_MAX_K;        // adjoint of s_[k]
+  L.best = o; o += 4 * (CM_MAX_K + block);
+  L.tw = o; o += 8 * 8;                // output twist terms
+  L.bytes = (o + 15) & ~15;
+  return L;
+}
+
+struct BwdArgs {
+  CotDev cot;
+  GradDev gr;
+};
+
+template <int BLOCK, int KMAX>
+__global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, ParamsDev prm, OutDev fwd, BwdArgs ga,
+                                                     float* __restrict__ scratch, long long scratch_stride, int maxV,
+                                                     int maxE, int maxF, unsigned* err) {
+  extern __shared__ float4 smem4[];
+  char* smem = reinterpret_cast<char*>(smem4);
+  __shared__ PairShared ps;
+  PairEngine<BLOCK, KMAX> P(ps, smem, tb, bt, prm, scratch + (long long)blockIdx.x * scratch_stride, maxV, maxE, maxF);
+  const BwdLds L = bwd_layout(lds_layout(maxE, maxF, BLOCK).bytes, maxV, maxE, maxF, BLOCK);
+  float* vA3 = reinterpret_cast<float*>(smem + L.vA);
+  float* vB3 = reinterpret_cast<float*>(smem + L.vB);
+  float* plA = reinterpret_cast<float*>(smem + L.plA);
+  float* plB = reinterpret_cast<float*>(smem + L.plB);
+  float* prA = reinterpret_cast<float*>(smem + L.prm);
+  float* prB = prA + 4;
+  float* rbar = reinterpret_cast<float*>(smem + L.rbar);
+  float* cbar = reinterpret_cast<float*>(smem + L.cbar);
+  double* cotL = reinterpret_cast<double*>(smem + L.cot);
+  double* Fk = reinterpret_cast<double*>(smem + L.F);
+  double* topb = reinterpret_cast<double*>(smem + L.top);
+  int* bestI = reinterpret_cast<int*>(smem + L.best);
+  double* twOut = reinterpret_cast<double*>(smem + L.tw);
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int NW = BLOCK / 64;
+  const int K = prm.K;
+  const Temp& T = P.T;
+  const int n_pairs = min(*fwd.n_pairs, fwd.capacity);
+  const long long CK = (long long)fwd.capacity * K;
+
+  for (int pi = blockIdx.x; pi < n_pairs; pi += gridDim.x) {
+    if (!P.setup(fwd.pairs[pi], fwd.pairs[fwd.capacity + pi], err)) {
+      __syncthreads();
+      continue;
+    }
+    const BodyView& A = P.A;
+    const BodyView& B = P.B;
+    const int nvA = A.nv, nvB = B.nv, neA = A.ne, neB = B.ne, nfA = A.nf, nfB = B.nf;
+    for (int i = tid; i < 3 * maxV; i += BLOCK) { vA3[i] = 0.f; vB3[i] = 0.f; }
+    for (int i = tid; i < 4 * maxF; i += BLOCK) { plA[i] = 0.f; plB[i] = 0.f; }
+    for (int i = tid; i < maxE; i += BLOCK) { rbar[i] = 0.f; cbar[i] = 0.f; }
+    if (tid < 8) prA[tid] = 0.f;
+    const BodySink sinkA{A.type == CM_POLYTOPE ? plA : nullptr, prA, maxF};
+    const BodySink sinkB{B.type == CM_POLYTOPE ? plB : nullptr, prB, maxF};
+
+    // ------------------------------------------------ recompute the forward
+    P.stage();
+    double tk[KMAX];
+    P.scores(tk);
+    P.topk(tk);
+    P.softsort();
+
+    // ------------------------------------------------ cotangents in the pair frame
+    if (tid < K) {
+      const int k = tid;
+      const long long o = (long long)pi * K + k;
+      const double* R = ps.RA;
+      const D3 gP = ga.cot.gp ? d3(ga.cot.gp[o], ga.cot.gp[CK + o], ga.cot.gp[2 * CK + o]) : d3(0, 0, 0);
+      const D3 gN = ga.cot.gn ? d3(ga.cot.gn[o], ga.cot.gn[CK + o], ga.cot.gn[2 * CK + o]) : d3(0, 0, 0);
+      const D3 pb = rotT(R, gP), nb = rotT(R, gN);
+      double* c = cotL + 8 * k;
+      c[0] = pb.x; c[1] = pb.y; c[2] = pb.z; c[3] = nb.x; c[4] = nb.y; c[5] = nb.z;
+      c[6] = ga.cot.gd ? double(ga.cot.gd[o]) : 0.0;
+      c[7] = ga.cot.gw ? double(ga.cot.gw[o]) : 0.0;
+      const double* a = P.sAcc + 9 * k;
+      double* F = Fk + 10 * k;
+      const double iz = 1.0 / a[0];
+      double gbar = 0.0;
+      for (int f = 0; f < 8; ++f) { F[f] = a[f + 1] * iz; gbar += c[f] * F[f]; }
+      F[8] = a[0];
+      F[9] = gbar;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      // world twist of A from the output transform P_k = R_A p_k + t_A, N_k = R_A nu_k
+      double r[3] = {0, 0, 0}, w[3] = {0, 0, 0};
+      const double* R = ps.RA;
+      for (int k = 0; k < K; ++k) {
+        const long long o = (long long)pi * K + k;
+        const double* F = Fk + 10 * k;
+        const D3 Pw = add(rot(R, d3(F[0], F[1], F[2])), d3(ps.tA[0], ps.tA[1], ps.tA[2]));
+        const D3 Nw = rot(R, d3(F[3], F[4], F[5]));
+        const D3 gP = ga.cot.gp ? d3(ga.cot.gp[o], ga.cot.gp[CK + o], ga.cot.gp[2 * CK + o]) : d3(0, 0, 0);
+        const D3 gN = ga.cot.gn ? d3(ga.cot.gn[o], ga.cot.gn[CK + o], ga.cot.gn[2 * CK + o]) : d3(0, 0, 0);
+        const D3 c1 = cross(Pw, gP), c2 = cross(Nw, gN);
+        r[0] += gP.x; r[1] += gP.y; r[2] += gP.z;
+        w[0] += c1.x + c2.x; w[1] += c1.y + c2.y; w[2] += c1.z + c2.z;
+      }
+      for (int i = 0; i < 3; ++i) { twOut[i] = r[i]; twOut[3 + i] = w[i]; }
+    }
+
+    double taub = 0.0;
+    Twist tw = {{0, 0, 0}, {0, 0, 0}};
+
+    // ------------------------------------------------ A1: adjoints of s_[k]
+    {
+      const int kk = tid % K, nsl = BLOCK / K, sl = tid / K;
+      const bool act = sl < nsl;
+      double sbp = 0.0, best = INFINITY;
+      int bidx = 0x7fffffff;
+      P.for_filtered([&](int tot) {
+        if (!act) return;
+        const double* F = Fk + 10 * kk;
+        const double* c = cotL + 8 * kk;
+        const double sk = P.sTop[kk];
+        for (int r = sl; r < tot; r += nsl) {
+          const Rec& R = P.sRec[r];
+          const double dl = sk - R.s;
+          const double G = double(expn(fabs(dl), T)) / F[8];
+          const double fv[8] = {R.px, R.py, R.pz, R.nx, R.ny, R.nz, R.d, R.w};
+          double gi = 0.0;
+          for (int f = 0; f < 8; ++f) gi += c[f] * fv[f];
+          const double ab = G * (gi - F[9]);
+          const double sg = dl > 0.0 ? 1.0 : (dl < 0.0 ? -1.0 : 0.0);
+          sbp -= ab * sg * T.inv_tau;
+          taub += ab * fabs(dl) * T.inv_tau * T.inv_tau;
+          if (fabs(dl) < best || (fabs(dl) == best && R.idx < bidx)) { best = fabs(dl); bidx = R.idx; }
+        }
+      });
+      P.sRed[tid] = act ? sbp : 0.0;
+      P.sRed[BLOCK + tid] = act ? best : INFINITY;
+      bestI[CM_MAX_K + tid] = act ? bidx : 0x7fffffff;
+      __syncthreads();
+      if (tid < K) {
+        double s = 0.0, b = INFINITY;
+        int bi = 0x7fffffff;
+        for (int q = 0; q < nsl; ++q) {
+          const int t = q * K + tid;
+          s += P.sRed[t];
+          const double v = P.sRed[BLOCK + t];
+          const int vi = bestI[CM_MAX_K + t];
+          if (v < b || (v == b && vi < bi)) { b = v; bi = vi; }
+        }
+        topb[tid] = s;
+        bestI[tid] = bi;
+      }
+      __syncthreads();
+    }
+
+    // ------------------------------------------------ A2: per-candidate adjoints
+    P.for_filtered([&](int tot) {
+      if (wave * 64 >= tot) return;        // whole wave idle (uniform)
+      const bool live = tid < tot;
+      const Rec R = P.sRec[live ? tid : 0];
+      double sb = 0.0;
+      double fb[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      if (live) {
+        const double fv[8] = {R.px, R.py, R.pz, R.nx, R.ny, R.nz, R.d, R.w};
+        for (int k = 0; k < K; ++k) {
+          const double* F = Fk + 10 * k;
+          const double* c = cotL + 8 * k;
+          const double dl = P.sTop[k] - R.s;
+          const double G = double(expn(fabs(dl), T)) / F[8];
+          double gi = 0.0;
+          for (int f = 0; f < 8; ++f) { gi += c[f] * fv[f]; fb[f] += G * c[f]; }
+          const double ab = G * (gi - F[9]);
+          sb += ab * (dl > 0.0 ? 1.0 : (dl < 0.0 ? -1.0 : 0.0)) * T.inv_tau;
+          if (bestI[k] == R.idx) sb += topb[k];
+        }
+      }
+      const int idx = R.idx;
+      const bool is_vs = idx < ps.nvs;
+      // ---- stage 1: forward values and the seeds of four SDF query slots
+      // slot 0: A at X0 (gradient adjoint), slot 1: B at X1, slot 2: A at X2, slot 3: B at X3
+      D3 X[4];
+      double phib[4] = {0, 0, 0, 0};
+      D3 gbar[4] = {d3(0, 0, 0), d3(0, 0, 0), d3(0, 0, 0), d3(0, 0, 0)};
+      D3 a0, t1, b0, t2, de, pb = d3(fb[0], fb[1], fb[2]), nbb = d3(0, 0, 0);
+      double al1 = 0, al2 = 0, dbar = 0, rho = 0, dbarb = 0, lcb = 0;
+      int k = 0, l = 0, wit = 0;
+      if (is_vs) {
+        const bool ofA = idx < nvA;
+        const D3 x = ofA ? P.vertex(*P.GA, idx, A) : P.vertex(*P.GB, idx - nvA, B);
+        const BodyView& O = ofA ? B : A;
+        const double sgn = ofA ? -1.0 : 1.0;
+        double phi;
+        D3 g;
+        sdf_body<true>(O, x, T, phi, g);
+        const double q = T.tau + dot(g, g), in = 1.0 / sqrt(q);
+        const double lw = lsig(-phi, T), w = exp(lw);
+        const double dtot = fb[6] - sb, lwb = T.tau * sb + w * fb[7];
+        taub += sb * lw;
+        const D3 nub = d3(fb[3], fb[4], fb[5]);
+        const double gn = dot(g, nub);
+        const D3 gb = scl(sub(scl(nub, in), scl(g, gn * in * in * in)), sgn);
+        taub -= sgn * gn * in * in * in * 0.5;
+        double du, dt;
+        lsig_d(-phi, T, du, dt);
+        const double phb = dtot - lwb * du;
+        taub += lwb * dt;
+        for (int s = 0; s < 4; ++s) X[s] = x;
+        const int s = ofA ? 1 : 0;
+        phib[s] = phb;
+        gbar[s] = gb;
+      } else {
+        const int e = idx - ps.nvs;
+        const int ee_i = e >> 1;
+        wit = e & 1;
+        k = ee_i / neB; l = ee_i - k * neB;
+        P.EA.get(k, a0, t1);
+        P.EB.get(l, b0, t2);
+        const EEQP q = ee_qp(a0, t1, b0, t2, P.lam, T);
+        al1 = q.al1; al2 = q.al2; de = q.de;
+        const D3 e1 = axpy(al1, t1, a0), e2 = axpy(al2, t2, b0);
+        const double dsq = dot(de, de);
+        dbar = sqrt(dsq);
+        rho = 1.0 / sqrt(dsq + P.eps_n);
+        const D3 nb = scl(de, rho);
+        double phiB1, phiA2, dum;
+        D3 gA, gB, dg;
+        sdf_body<false>(B, e1, T, phiB1, dg);
+        sdf_body<true>(A, e1, T, dum, gA);
+        sdf_body<false>(A, e2, T, phiA2, dg);
+        sdf_body<true>(B, e2, T, dum, gB);
+        const double u1 = dot(gB, nb), u2 = -dot(gA, nb), ucl = -dot(gA, gB);
+        const double gam1 = tanh64(u1, T), gam2 = tanh64(u2, T);
+        const double gam = wit ? gam2 : gam1;
+        const double lcl = lsig(ucl, T);
+        const double lp = wit ? lsig(-phiA2, T) : lsig(-phiB1, T);
+        const double lse = wit ? P.sCol[l] : P.sRow[k];
+        const double lw = q.log_con + lcl + lp + (lse - dbar) * T.inv_tau;
+        const double w = exp(lw);
+        const double dtot = fb[6] - sb, lwb = T.tau * sb + w * fb[7];
+        taub += sb * lw;
+        const D3 nub = d3(fb[3], fb[4], fb[5]);
+        const double gamb = dtot * dbar - dot(nub, nb);   // d = gam dbar, nu = -gam n_bar
+        dbarb = dtot * gam;
+        nbb = scl(nub, -gam);
+        lcb = lwb;
+        double du, dt;
+        lsig_d(ucl, T, du, dt);
+        const double uclb = lwb * du;
+        taub += lwb * dt;
+        D3 gAb = scl(gB, -uclb), gBb = scl(gA, -uclb);
+        lsig_d(wit ? -phiA2 : -phiB1, T, du, dt);
+        const double phb = -lwb * du;
+        taub += lwb * dt;
+        if (live) atomicAdd(wit ? &cbar[l] : &rbar[k], float(lwb * T.inv_tau));
+        dbarb -= lwb * T.inv_tau;
+        taub -= lwb * (lse - dbar) * T.inv_tau * T.inv_tau;
+        if (!wit) {
+          const double ub = gamb * (1.0 - gam1 * gam1) * T.inv_tau;
+          taub -= ub * u1 * T.inv_tau;
+          gBb = axpy(ub, nb, gBb);
+          nbb = axpy(ub, gB, nbb);
+        } else {
+          const double ub = gamb * (1.0 - gam2 * gam2) * T.inv_tau;
+          taub -= ub * u2 * T.inv_tau;
+          gAb = axpy(-ub, nb, gAb);
+          nbb = axpy(-ub, gA, nbb);
+        }
+        X[0] = e1; X[1] = e1; X[2] = e2; X[3] = e2;
+        gbar[0] = gAb;
+        if (!wit) phib[1] = phb; else phib[2] = phb;
+        gbar[3] = gBb;
+      }
+      // ---- stage 2: SDF adjoints, every lane of the wave together
+      const D3 xb0 = sdf_body_bwd<true>(A, X[0], phib[0], gbar[0], T, sinkA, taub, tw);
+      const D3 xb1 = sdf_body_bwd<true>(B, X[1], phib[1], gbar[1], T, sinkB, taub, tw);
+      const D3 xb2 = sdf_body_bwd<true>(A, X[2], phib[2], gbar[2], T, sinkA, taub, tw);
+      const D3 xb3 = sdf_body_bwd<true>(B, X[3], phib[3], gbar[3], T, sinkB, taub, tw);
+      if (!live) return;
+      // ---- stage 3: back to vertices / edges
+      if (is_vs) {
+        const bool ofA = idx < nvA;
+        const D3 xb = add(pb, ofA ? xb1 : xb0);
+        float* V = ofA ? vA3 : vB3;
+        const int i = ofA ? idx : idx - nvA;
+        atomicAdd(&V[i], float(xb.x));
+        atomicAdd(&V[maxV + i], float(xb.y));
+        atomicAdd(&V[2 * maxV + i], float(xb.z));
+      } else {
+        const double dn = dot(de, nbb);
+        D3 deb = sub(scl(nbb, rho), scl(de, rho * rho * rho * dn));
+        if (prm.eps_tied) taub += -0.5 * rho * rho * rho * dn * 2.0 * T.tau;
+        if (dbar > 0.0) deb = axpy(dbarb / dbar, de, deb);
+        D3 e1b = add(add(xb0, xb1), deb), e2b = sub(add(xb2, xb3), deb);
+        if (!wit) e1b = add(e1b, pb); else e2b = add(e2b, pb);
+        D3 a0b = e1b, t1b = scl(e1b, al1), b0b = e2b, t2b = scl(e2b, al2);
+        ee_qp_bwd(a0, t1, b0, t2, P.lam, T, dot(e1b, t1), dot(e2b, t2), lcb, a0b, t1b, b0b, t2b, taub);
+        const int ia0 = tb.e0[P.GA->e_off + k], ia1 = tb.e1[P.GA->e_off + k];
+        const int ib0 = tb.e0[P.GB->e_off + l], ib1 = tb.e1[P.GB->e_off + l];
+        const D3 va0 = sub(a0b, t1b), vb0 = sub(b0b, t2b);
+        atomicAdd(&vA3[ia0], float(va0.x)); atomicAdd(&vA3[maxV + ia0], float(va0.y)); atomicAdd(&vA3[2 * maxV + ia0], float(va0.z));
+        atomicAdd(&vA3[ia1], float(t1b.x)); atomicAdd(&vA3[maxV + ia1], float(t1b.y)); atomicAdd(&vA3[2 * maxV + ia1], float(t1b.z));
+        atomicAdd(&vB3[ib0], float(vb0.x)); atomicAdd(&vB3[maxV + ib0], float(vb0.y)); atomicAdd(&vB3[2 * maxV + ib0], float(vb0.z));
+        atomicAdd(&vB3[ib1], float(t2b.x)); atomicAdd(&vB3[maxV + ib1], float(t2b.y)); atomicAdd(&vB3[2 * maxV + ib1], float(t2b.z));
+      }
+    });
+    __syncthreads();
+
+    // ------------------------------------------------ N: nearest-neighbour LSE adjoint
+    {
+      const int nee = ps.nee;
+      for (int idx = tid; idx < nee; idx += BLOCK) {
+        const int k = idx / neB, l = idx - k * neB;
+        const double rb = rbar[k], cb = cbar[l];
+        if (rb == 0.0 && cb == 0.0) continue;
+        D3 a0, t1, b0, t2;
+        P.EA.get(k, a0, t1);
+        P.EB.get(l, b0, t2);
+        const EEQP q = ee_qp(a0, t1, b0, t2, P.lam, T);
+        const double D = sqrt(dot(q.de, q.de));
+        const double pr = exp64n((P.sRow[k] - D) * T.inv_tau), pc = exp64n((P.sCol[l] - D) * T.inv_tau);
+        const double Db = rb * pr + cb * pc;
+        taub += (rb * pr * (P.sRow[k] - D) + cb * pc * (P.sCol[l] - D)) * T.inv_tau;
+        if (Db == 0.0 || !(D > 0.0)) continue;
+        const D3 deb = scl(q.de, Db / D);
+        D3 a0b = deb, t1b = scl(deb, q.al1), b0b = scl(deb, -1.0), t2b = scl(deb, -q.al2);
+        ee_qp_bwd(a0, t1, b0, t2, P.lam, T, dot(deb, t1), -dot(deb, t2), 0.0, a0b, t1b, b0b, t2b, taub);
+        const int ia0 = tb.e0[P.GA->e_off + k], ia1 = tb.e1[P.GA->e_off + k];
+        const int ib0 = tb.e0[P.GB->e_off + l], ib1 = tb.e1[P.GB->e_off + l];
+        const D3 va0 = sub(a0b, t1b), vb0 = sub(b0b, t2b);
+        atomicAdd(&vA3[ia0], float(va0.x)); atomicAdd(&vA3[maxV + ia0], float(va0.y)); atomicAdd(&vA3[2 * maxV + ia0], float(va0.z));
+        atomicAdd(&vA3[ia1], float(t1b.x)); atomicAdd(&vA3[maxV + ia1], float(t1b.y)); atomicAdd(&vA3[2 * maxV + ia1], float(t1b.z));
+        atomicAdd(&vB3[ib0], float(vb0.x)); atomicAdd(&vB3[maxV + ib0], float(vb0.y)); atomicAdd(&vB3[2 * maxV + ib0], float(vb0.z));
+        atomicAdd(&vB3[ib1], float(t2b.x)); atomicAdd(&vB3[maxV + ib1], float(t2b.y)); atomicAdd(&vB3[2 * maxV + ib1], float(t2b.z));
+      }
+    }
+    __syncthreads();
+
+    // ------------------------------------------------ G: geometry and pose gradients
+    // face planes -> hull vertices (body frames)
+    for (int i = tid; i < nfA + nfB; i += BLOCK) {
+      const bool isA = i < nfA;
+      const int f = isA ? i : i - nfA;
+      const GeomRec& G = isA ? *P.GA : *P.GB;
+      const float* pl = isA ? plA : plB;
+      const int iv[3] = {tb.f0[G.f_off + f], tb.f1[G.f_off + f], tb.f2[G.f_off + f]};
+      D3 v[3];
+      for (int j = 0; j < 3; ++j) v[j] = d3(tb.vx[G.v_off + iv[j]], tb.vy[G.v_off + iv[j]], tb.vz[G.v_off + iv[j]]);
+      const D3 ea = sub(v[1], v[0]), eb = sub(v[2], v[0]);
+      const D3 u = cross(ea, eb);
+      const double iu = 1.0 / sqrt(dot(u, u));
+      const D3 n = scl(u, iu);
+      const double ob = pl[3 * maxF + f];
+      const D3 nb = add(d3(pl[f], pl[maxF + f], pl[2 * maxF + f]), scl(v[0], ob));
+      const D3 ub = scl(sub(nb, scl(n, dot(n, nb))), iu);
+      const D3 eab = cross(eb, ub), ebb = cross(ub, ea);
+      const D3 g0 = sub(scl(n, ob), add(eab, ebb));
+      const D3 gv[3] = {g0, eab, ebb};
+      if (ga.gr.g_vertices) {
+        for (int j = 0; j < 3; ++j) {
+          const long long o = G.v_off + iv[j];
+          atomicAdd(&ga.gr.g_vertices[o], float(gv[j].x));
+          atomicAdd(&ga.gr.g_vertices[ga.gr.pool + o], float(gv[j].y));
+          atomicAdd(&ga.gr.g_vertices[2LL * ga.gr.pool + o], float(gv[j].z));
+        }
+      }
+    }
+    // mesh vertices -> hull vertices / analytic parameters, and B's placement twist
+    for (int i = tid; i < nvA + nvB; i += BLOCK) {
+      const bool isA = i < nvA;
+      const int v = isA ? i : i - nvA;
+      const GeomRec& G = isA ? *P.GA : *P.GB;
+      const float* V = isA ? vA3 : vB3;
+      D3 gb = d3(V[v], V[maxV + v], V[2 * maxV + v]);   // pair frame
+      const D3 lv = d3(tb.vx[G.v_off + v], tb.vy[G.v_off + v], tb.vz[G.v_off + v]);
+      if (!isA) {
+        const D3 x = P.vertex(G, v, B);
+        const D3 c = cross(x, gb);
+        tw.r[0] += gb.x; tw.r[1] += gb.y; tw.r[2] += gb.z;
+        tw.w[0] += c.x; tw.w[1] += c.y; tw.w[2] += c.z;
+        gb = rotT(B.R, gb);
+      }
+      if (G.type == CM_POLYTOPE) {
+        if (ga.gr.g_vertices) {
+          const long long o = G.v_off + v;
+          atomicAdd(&ga.gr.g_vertices[o], float(gb.x));
+          atomicAdd(&ga.gr.g_vertices[ga.gr.pool + o], float(gb.y));
+          atomicAdd(&ga.gr.g_vertices[2LL * ga.gr.pool + o], float(gb.z));
+        }
+      } else {
+        float* pr = isA ? prA : prB;
+        if (G.type == CM_SPHERE) {
+          atomicAdd(&pr[0], float(dot(lv, gb) / double(G.p[0])));
+        } else if (G.type == CM_CAPSULE) {
+          const double s = v < 17 ? -1.0 : 1.0;
+          const D3 u = scl(d3(lv.x, lv.y, lv.z - s * double(G.p[1])), 1.0 / double(G.p[0]));
+          atomicAdd(&pr[0], float(dot(u, gb)));
+          atomicAdd(&pr[1], float(s * gb.z));
+        } else {
+          atomicAdd(&pr[0], float((v & 1 ? 1.0 : -1.0) * gb.x));
+          atomicAdd(&pr[1], float((v & 2 ? 1.0 : -1.0) * gb.y));
+          atomicAdd(&pr[2], float((v & 4 ? 1.0 : -1.0) * gb.z));
+        }
+      }
+    }
+    // block reduction of tau_bar and B's twist
+    {
+      double vals[7] = {taub, tw.r[0], tw.r[1], tw.r[2], tw.w[0], tw.w[1], tw.w[2]};
+      for (int j = 0; j < 7; ++j) {
+        double v = vals[j];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        vals[j] = v;
+      }
+      __syncthreads();
+      if (lane == 0)
+        for (int j = 0; j < 7; ++j) P.sRed[j * NW + wave] = vals[j];
+      __syncthreads();
+      if (tid == 0) {
+        double s[7];
+        for (int j = 0; j < 7; ++j) {
+          s[j] = 0.0;
+          for (int w = 0; w < NW; ++w) s[j] += P.sRed[j * NW + w];
+        }
+        if (ga.gr.g_tau) atomicAdd(ga.gr.g_tau, float(s[0]));
+        // eta (pair frame, B relative to A) -> world twists
+        const double* R = ps.RA;
+        const D3 rB = rot(R, d3(s[1], s[2], s[3]));
+        const D3 wB = add(rot(R, d3(s[4], s[5], s[6])), cross(d3(ps.tA[0], ps.tA[1], ps.tA[2]), rB));
+        if (ga.gr.g_pose) {
+          const int a = ps.a, b = ps.b, nb = bt.n_bodies;
+          const double gb6[6] = {rB.x, rB.y, rB.z, wB.x, wB.y, wB.z};
+          for (int c = 0; c < 6; ++c) {
+            atomicAdd(&ga.gr.g_pose[c * nb + b], float(gb6[c]));
+            atomicAdd(&ga.gr.g_pose[c * nb + a], float(twOut[c] - gb6[c]));
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (ga.gr.g_params && tid < 8) {
+      const bool isA = tid < 4;
+      const GeomRec& G = isA ? *P.GA : *P.GB;
+      const int gid = isA ? ps.ga : ps.gb;
+      if (G.type != CM_POLYTOPE) atomicAdd(&ga.gr.g_params[(tid & 3) * (long long)tb.n_geoms + gid], prA[tid]);
+    }
+    __syncthreads();
+  }
+}
+
+int bwd_lds_bytes(int maxV, int maxE, int maxF, int block) {
+  return bwd_layout(lds_layout(maxE, maxF, block).bytes, maxV, maxE, maxF, block).bytes;
+}
+
+template <int BLOCK, int KMAX>
+static hipError_t launch_bwd_t(const BwdLaunch& b, hipStream_t st) {
+  const int lds = bwd_lds_bytes(b.f.maxV, b.f.maxE, b.f.maxF, BLOCK);
+  BwdArgs ga{b.cot, b.gr};
+  hipLaunchKernelGGL((collide_bwd<BLOCK, KMAX>), dim3(b.f.grid), dim3(BLOCK), lds, st, b.f.tb, b.f.bt, b.f.prm, b.f.out,
+                     ga, b.f.scratch, b.f.scratch_stride, b.f.maxV, b.f.maxE, b.f.maxF, b.f.err);
+  return hipGetLastError();
+}
+
+template <int BLOCK, int KMAX>
+static int bwd_occ_t(const BwdLaunch& b) {
+  int nb = 0;
+  const int lds = bwd_lds_bytes(b.f.maxV, b.f.maxE, b.f.maxF, BLOCK);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, collide_bwd<BLOCK, KMAX>, BLOCK, lds) != hipSuccess) return 1;
+  return nb > 0 ? nb : 1;
+}
+
+hipError_t launch_collide_bwd(const BwdLaunch& b, hipStream_t st) {
+  if (b.f.kmax == 8) return launch_bwd_t<256, 8>(b, st);
+  if (b.f.kmax == 16) return launch_bwd_t<256, 16>(b, st);
+  return launch_bwd_t<256, 32>(b, st);
+}
+
+int bwd_occupancy(const BwdLaunch& b) {
+  if (b.f.kmax == 8) return bwd_occ_t<256, 8>(b);
+  if (b.f.kmax == 16) return bwd_occ_t<256, 16>(b);
+  return bwd_occ_t<256, 32>(b);
+}
+
+}  // namespace cm

@@ -47,13 +47,34 @@ struct cm_context {
   size_t work_cap = 0;
   void* d_bwd = nullptr;       // backward workspace
   size_t bwd_cap = 0;
+  // fused path: size-class plan (per K), tuned block sizes, captured graphs
+  int geom_version = 0;
+  int plan_K = -1, plan_version = -1;
+  bool plan_tuned = false;
+  int cls_maxE[3] = {0, 0, 0}, cls_maxV[3] = {0, 0, 0}, cls_maxF[3] = {0, 0, 0}, cls_block[3] = {256, 256, 256};
+  int cls_bound[2] = {96, 300};
+  void* d_fused = nullptr;
+  size_t fused_cap = 0;
+  hipStream_t cap_stream = nullptr;
+  struct GraphEntry {
+    uint64_t key;
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;
+  void drop_graphs() {
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
+    graphs.clear();
+  }
   std::string last_error;
 
   void release_all() {
     auto F = [](void* p) { if (p) hipFree(p); };
     F(d.recs); F(d.vx); F(d.vy); F(d.vz); F(d.e0); F(d.e1); F(d.fnx); F(d.fny); F(d.fnz); F(d.fo);
     F(d.f0); F(d.f1); F(d.f2);
-    F(d_err); F(d_tile_sums); F(d_scratch); F(d_work); F(d_bwd);
+    F(d_err); F(d_tile_sums); F(d_scratch); F(d_work); F(d_bwd); F(d_fused);
+    drop_graphs();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    cap_stream = nullptr;
     d = CmDevPools();
   }
 };
@@ -61,4 +82,11 @@ struct cm_context {
 cm_status cm_fail(cm_context* ctx, cm_status s, const std::string& msg);
 cm_status cm_hip(cm_context* ctx, hipError_t e, const char* what);
 hipError_t ensure_bytes(void** p, size_t* cap, size_t need);
+hipError_t ctx_ensure(cm_context* ctx, void** p, size_t* cap, size_t need);
 cm::Tables ctx_tables(const cm_context* ctx);
+cm_status resolve_params(cm_context* ctx, const cm_params* prm, cm::ParamsDev* pd);
+cm_status resolve_batch(cm_context* ctx, const cm_batch* b, cm::BatchDev* bd);
+cm_status resolve_out(cm_context* ctx, const cm_manifold* o, cm::OutDev* od);
+cm_status ctx_broadphase(cm_context* ctx, const cm::BatchDev& bd, const cm::ParamsDev& pd, const cm::OutDev& od,
+                         hipStream_t st);
+int kmax_for(int K);

@@ -42,6 +42,7 @@ struct ParamsDev {
   double tau, lam, eps_n;   // tau is the float32 input widened; defaults resolved in float64
   float margin;             // broadphase margin (float32 predicate)
   int32_t K;
+  int32_t eps_tied;         // eps_n = tau^2 (its tau dependence enters the adjoint)
 };
 
 struct OutDev {

@@ -15,6 +15,7 @@ struct FwdLaunch {
   long long scratch_stride;
   int maxV, maxE, maxF;        // LDS sizing (context-wide maxima)
   const int* order;            // optional pair order (cost-sorted), or null
+  const int* range;            // optional device int2 {start, count} into order, or null
   int* queue;                  // dynamic work-queue counter (zeroed), or null for static round robin
   unsigned* err;
   int grid, block, kmax;
@@ -25,10 +26,47 @@ inline long long fwd_scratch_floats(int maxV, int maxE) {
   return 2LL * maxE * maxE + 2LL * maxE * maxE + 2LL * maxV + 64;   // f64 D + f32 scores
 }
 
+struct CotDev {
+  const float* gp;   // [3][cap*K]
+  const float* gn;   // [3][cap*K]
+  const float* gd;   // [cap*K]
+  const float* gw;   // [cap*K]
+};
+
+struct GradDev {
+  float* g_pose;       // [6][n_bodies]
+  float* g_vertices;   // [3][pool]
+  float* g_params;     // [4][n_geoms]
+  float* g_tau;        // [1]
+  long long pool;
+};
+
+struct BwdLaunch {
+  FwdLaunch f;
+  CotDev cot;
+  GradDev gr;
+};
+
 int fwd_lds_bytes(int maxV, int maxE, int maxF, int block, int kmax);
+int bwd_lds_bytes(int maxV, int maxE, int maxF, int block);
+int bwd_occupancy(const BwdLaunch& b);
+hipError_t launch_collide_bwd(const BwdLaunch& b, hipStream_t st);
 int fwd_occupancy(const FwdLaunch& f);
 hipError_t launch_broadphase(const Tables& tb, const BatchDev& bt, float margin, const OutDev& out, int* tile_sums,
                              unsigned* err, hipStream_t st);
 hipError_t launch_collide_fwd(const FwdLaunch& f, hipStream_t st);
+
+// fused path: size classes and cost order
+constexpr int kNumClasses = 3;
+constexpr int kNumBuckets = 48;
+struct FusedWork {
+  int* counts;    // [kNumClasses * kNumBuckets] histogram, then scatter cursors
+  int* ranges;    // [kNumClasses][2] {start, count}
+  int* queues;    // [kNumClasses] work-queue counters
+  int* order;     // [capacity] pair indices, class-major, cost-descending
+  int* keys;      // [capacity]
+};
+hipError_t launch_fused_prepare(const Tables& tb, const BatchDev& bt, const OutDev& out, const int* class_maxE,
+                                const FusedWork& w, hipStream_t st);
 
 }  // namespace cm

@@ -1,0 +1,431 @@
+// Per-pair forward engine shared by the forward and adjoint kernels.
+//
+// One workgroup owns one body pair at a time.  Phases (all in the frame of
+// body A):
+//   setup    pose ingest: R_A, t_A, and body B's pose relative to A
+//   stage    edges of both bodies (FP64 SoA) and face planes (body frames) in LDS
+//   scores   V-S candidates both ways (Sec. IV-C); E-E distance pass with the
+//            row / column LSE of the unsigned-distance matrix (nearest-neighbour
+//            indicators, Sec. IV-D); E-E candidate pass (witness QP, SDF queries,
+//            sign, penetration, clashing, activity, score); per-lane top-K
+//   topk     block merge of the per-lane top-K score lists (with multiplicity)
+//   softsort SoftSort rows over the candidates within 40 tau of s_[K]
+#pragma once
+#include "cm_device.cuh"
+
+namespace cm {
+
+struct PairShared {
+  BodyView A, B;
+  double RA[9], tA[3];   // pair frame -> world
+  int ga, gb, valid, a, b;
+  int nvs, nee, ncand;
+  int next;              // dynamic work-queue item
+};
+
+template <int KM>
+__device__ __forceinline__ void tk_insert(double (&tk)[KM], double x) {
+  if (x > tk[KM - 1]) {
+#pragma unroll
+    for (int i = 0; i < KM; ++i) {
+      const double hi = fmax(tk[i], x);
+      x = fmin(tk[i], x);
+      tk[i] = hi;
+    }
+  }
+}
+
+// Record of a candidate near the top-K scores.
+struct Rec {
+  double s, d;
+  float px, py, pz, nx, ny, nz, w;
+  int idx;
+};
+
+struct LdsLayout {
+  int eA, eB, row, col, red, top, rec, acc, pA, pB, cnt, bytes;
+};
+
+__host__ __device__ inline LdsLayout lds_layout(int maxE, int maxF, int block) {
+  LdsLayout L;
+  int o = 0;
+  L.eA = o; o += 6 * 8 * maxE;
+  L.eB = o; o += 6 * 8 * maxE;
+  L.row = o; o += 8 * maxE;
+  L.col = o; o += 8 * maxE;
+  L.red = o; o += 2 * 8 * block;
+  L.top = o; o += 8 * 64;
+  L.rec = o; o += int(sizeof(Rec)) * block;
+  L.acc = o; o += 8 * 9 * CM_MAX_K;
+  L.pA = o; o += 16 * maxF;
+  L.pB = o; o += 16 * maxF;
+  L.cnt = o; o += 64;
+  L.bytes = (o + 15) & ~15;
+  return L;
+}
+
+template <int BLOCK, int KMAX>
+struct PairEngine {
+  static constexpr int NW = BLOCK / 64;
+  static constexpr int NSLOT = (9 * CM_MAX_K + BLOCK - 1) / BLOCK;
+
+  PairShared& ps;
+  const Tables& tb;
+  const BatchDev& bt;
+  EdgeSoA EA, EB;
+  float4* sPA;
+  float4* sPB;
+  double* sRow;
+  double* sCol;
+  double* sRed;
+  double* sTop;
+  Rec* sRec;
+  double* sAcc;   // [9K] unnormalised SoftSort sums (1, p, nu, d, w) per row
+  int* sCnt;
+  double* Dbuf;
+  float* Sbuf;
+  Temp T;
+  double lam, eps_n;
+  int K, maxV, maxE, maxF;
+  int tid, lane, wave;
+  BodyView A, B;
+  const GeomRec* GA;
+  const GeomRec* GB;
+
+  __device__ PairEngine(PairShared& ps_, char* smem, const Tables& tb_, const BatchDev& bt_, const ParamsDev& prm,
+                        float* slot, int maxV_, int maxE_, int maxF_)
+      : ps(ps_), tb(tb_), bt(bt_) {
+    const LdsLayout L = lds_layout(maxE_, maxF_, BLOCK);
+    double* e = reinterpret_cast<double*>(smem + L.eA);
+    EA = EdgeSoA{e, e + maxE_, e + 2 * maxE_, e + 3 * maxE_, e + 4 * maxE_, e + 5 * maxE_};
+    e = reinterpret_cast<double*>(smem + L.eB);
+    EB = EdgeSoA{e, e + maxE_, e + 2 * maxE_, e + 3 * maxE_, e + 4 * maxE_, e + 5 * maxE_};
+    sPA = reinterpret_cast<float4*>(smem + L.pA);
+    sPB = reinterpret_cast<float4*>(smem + L.pB);
+    sRow = reinterpret_cast<double*>(smem + L.row);
+    sCol = reinterpret_cast<double*>(smem + L.col);
+    sRed = reinterpret_cast<double*>(smem + L.red);
+    sTop = reinterpret_cast<double*>(smem + L.top);
+    sRec = reinterpret_cast<Rec*>(smem + L.rec);
+    sAcc = reinterpret_cast<double*>(smem + L.acc);
+    sCnt = reinterpret_cast<int*>(smem + L.cnt);
+    Dbuf = reinterpret_cast<double*>(slot);
+    Sbuf = reinterpret_cast<float*>(Dbuf + (long long)maxE_ * maxE_);
+    T = make_temp(prm.tau);
+    lam = prm.lam;
+    eps_n = prm.eps_n;
+    K = prm.K;
+    maxV = maxV_; maxE = maxE_; maxF = maxF_;
+    tid = threadIdx.x; lane = tid & 63; wave = tid >> 6;
+  }
+
+  // ------------------------------------------------------------ setup
+  // Thread 0 reads the pair and both poses; returns false (uniformly) for
+  // an invalid pair.
+  __device__ bool setup(int a, int b, unsigned* err) {
+    if (tid == 0) {
+      ps.a = a; ps.b = b;
+      const int ga = bt.body_geom[a], gb = bt.body_geom[b];
+      ps.valid = (ga >= 0 && ga < tb.n_geoms && gb >= 0 && gb < tb.n_geoms);
+      if (!ps.valid) {
+        atomicOr(err, ERR_BAD_GEOM);
+      } else {
+        const GeomRec G1 = tb.geoms[ga], G2 = tb.geoms[gb];
+        ps.ga = ga; ps.gb = gb;
+        const int nb = bt.n_bodies;
+        double RA[9], RB[9];
+        quat_to_R(bt.pose[a], bt.pose[nb + a], bt.pose[2 * nb + a], bt.pose[3 * nb + a], RA);
+        quat_to_R(bt.pose[b], bt.pose[nb + b], bt.pose[2 * nb + b], bt.pose[3 * nb + b], RB);
+        const double tA[3] = {bt.pose[4 * nb + a], bt.pose[5 * nb + a], bt.pose[6 * nb + a]};
+        const double dt[3] = {double(bt.pose[4 * nb + b]) - tA[0], double(bt.pose[5 * nb + b]) - tA[1],
+                              double(bt.pose[6 * nb + b]) - tA[2]};
+        for (int i = 0; i < 9; ++i) ps.RA[i] = RA[i];
+        for (int i = 0; i < 3; ++i) ps.tA[i] = tA[i];
+        // B in the pair frame: Rr = RA^T RB, tr = RA^T (tB - tA)
+        for (int i = 0; i < 3; ++i) {
+          for (int j = 0; j < 3; ++j)
+            ps.B.R[3 * i + j] = RA[i] * RB[j] + RA[3 + i] * RB[3 + j] + RA[6 + i] * RB[6 + j];
+          ps.B.t[i] = RA[i] * dt[0] + RA[3 + i] * dt[1] + RA[6 + i] * dt[2];
+        }
+        for (int i = 0; i < 9; ++i) ps.A.R[i] = (i % 4 == 0) ? 1.0 : 0.0;
+        for (int i = 0; i < 3; ++i) ps.A.t[i] = 0.0;
+        ps.A.ident = true; ps.B.ident = false;
+        ps.A.type = G1.type; ps.A.nv = G1.nv; ps.A.ne = G1.ne; ps.A.nf = G1.nf;
+        ps.B.type = G2.type; ps.B.nv = G2.nv; ps.B.ne = G2.ne; ps.B.nf = G2.nf;
+        for (int i = 0; i < 4; ++i) { ps.A.p[i] = G1.p[i]; ps.B.p[i] = G2.p[i]; }
+        ps.nvs = G1.nv + G2.nv;
+        ps.nee = G1.ne * G2.ne;
+        ps.ncand = ps.nvs + 2 * ps.nee;
+        if (G1.nv > maxV || G2.nv > maxV || G1.ne > maxE || G2.ne > maxE || G1.nf > maxF || G2.nf > maxF) {
+          ps.valid = 0;
+          atomicOr(err, ERR_BAD_GEOM);
+        }
+      }
+    }
+    __syncthreads();
+    if (!ps.valid) return false;
+    A = ps.A; B = ps.B;
+    A.planes = sPA; B.planes = sPB;
+    GA = &tb.geoms[ps.ga];
+    GB = &tb.geoms[ps.gb];
+    return true;
+  }
+
+  // vertex v of a geometry (body frame, float) -> pair frame (double)
+  __device__ __forceinline__ D3 vertex(const GeomRec& G, int v, const BodyView& V) const {
+    const int i = G.v_off + v;
+    const D3 l = d3(tb.vx[i], tb.vy[i], tb.vz[i]);
+    if (V.ident) return l;
+    return d3(V.R[0] * l.x + V.R[1] * l.y + V.R[2] * l.z + V.t[0], V.R[3] * l.x + V.R[4] * l.y + V.R[5] * l.z + V.t[1],
+              V.R[6] * l.x + V.R[7] * l.y + V.R[8] * l.z + V.t[2]);
+  }
+
+  // ------------------------------------------------------------ stage
+  __device__ void stage() {
+    const int neA = A.ne, neB = B.ne, nfA = A.nf, nfB = B.nf;
+    for (int i = tid; i < neA + neB; i += BLOCK) {
+      const bool isA = i < neA;
+      const int e = isA ? i : i - neA;
+      const GeomRec& G = isA ? *GA : *GB;
+      const BodyView& V = isA ? A : B;
+      const D3 p0 = vertex(G, tb.e0[G.e_off + e], V);
+      const D3 p1 = vertex(G, tb.e1[G.e_off + e], V);
+      const EdgeSoA& E = isA ? EA : EB;
+      E.x0[e] = p0.x; E.y0[e] = p0.y; E.z0[e] = p0.z;
+      E.tx[e] = p1.x - p0.x; E.ty[e] = p1.y - p0.y; E.tz[e] = p1.z - p0.z;
+    }
+    for (int i = tid; i < nfA + nfB; i += BLOCK) {
+      const bool isA = i < nfA;
+      const int f = isA ? GA->f_off + i : GB->f_off + (i - nfA);
+      (isA ? sPA : sPB)[isA ? i : i - nfA] = make_float4(tb.fnx[f], tb.fny[f], tb.fnz[f], tb.fo[f]);
+    }
+    __syncthreads();
+  }
+
+  // ------------------------------------------------------------ candidates
+  __device__ __forceinline__ void vs(int i, Cand& c) const {
+    if (i < A.nv) vs_candidate(vertex(*GA, i, A), B, -1.0, T, c);
+    else vs_candidate(vertex(*GB, i - A.nv, B), A, 1.0, T, c);
+  }
+  __device__ __forceinline__ void ee(int k, int l, Cand& c1, Cand& c2) const {
+    D3 a0, t1, b0, t2;
+    EA.get(k, a0, t1);
+    EB.get(l, b0, t2);
+    ee_candidates(a0, t1, b0, t2, sRow[k], sCol[l], A, B, lam, eps_n, T, c1, c2);
+  }
+  // candidate idx in the fixed order: A's vertices, B's vertices, E-E (k, l)
+  // row-major with witness 1 before witness 2
+  __device__ __forceinline__ void candidate(int idx, Cand& c) const {
+    if (idx < ps.nvs) {
+      vs(idx, c);
+    } else {
+      const int e = idx - ps.nvs;
+      const int ee_i = e >> 1;
+      const int k = ee_i / B.ne, l = ee_i - k * B.ne;
+      Cand c1, c2;
+      ee(k, l, c1, c2);
+      c = (e & 1) ? c2 : c1;
+    }
+  }
+
+  // ------------------------------------------------------------ scores
+  __device__ void scores(double (&tk)[KMAX]) {
+    const int neA = A.ne, neB = B.ne, nee = ps.nee, nvs = ps.nvs;
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) tk[i] = -INFINITY;
+    // V-S candidates (Sec. IV-C), both ways
+    for (int i = tid; i < nvs; i += BLOCK) {
+      Cand c;
+      vs(i, c);
+      Sbuf[i] = float(c.s);
+      tk_insert<KMAX>(tk, c.s);
+    }
+    // E-E pass 1: unsigned distances D
+    {
+      int k = tid / neB, l = tid - (tid / neB) * neB;
+      const int sk = BLOCK / neB, sl = BLOCK - sk * neB;
+      for (int idx = tid; idx < nee; idx += BLOCK) {
+        D3 a0, t1, b0, t2;
+        EA.get(k, a0, t1);
+        EB.get(l, b0, t2);
+        Dbuf[idx] = ee_dist(a0, t1, b0, t2, lam, T);
+        k += sk; l += sl;
+        if (l >= neB) { l -= neB; ++k; }
+      }
+    }
+    __syncthreads();
+    // row LSE over l (one wave per row, coalesced)
+    for (int k = wave; k < neA; k += NW) {
+      double m = INFINITY;
+      float s = 0.f;
+      for (int l = lane; l < neB; l += 64) lse_push(m, s, Dbuf[k * neB + l], T);
+      wave_lse_merge(m, s, T);
+      if (lane == 0) sRow[k] = m - T.tl * double(lg2f(s));
+    }
+    // column LSE over k (threads over columns, k split in chunks, coalesced)
+    {
+      const int nch = neB >= BLOCK ? 1 : BLOCK / neB;
+      for (int lb = 0; lb < neB; lb += BLOCK) {
+        const int l = lb + (tid % (neB >= BLOCK ? BLOCK : neB));
+        const int ch = neB >= BLOCK ? 0 : tid / neB;
+        double m = INFINITY;
+        float s = 0.f;
+        if (ch < nch && l < neB) {
+          const int k0 = (ch * neA) / nch, k1 = ((ch + 1) * neA) / nch;
+          for (int k = k0; k < k1; ++k) lse_push(m, s, Dbuf[k * neB + l], T);
+        }
+        sRed[tid] = m;
+        sRed[BLOCK + tid] = double(s);
+        __syncthreads();
+        if (ch == 0 && l < neB) {
+          double M = sRed[tid];
+          float S = float(sRed[BLOCK + tid]);
+          for (int c = 1; c < nch; ++c) {
+            const double m2 = sRed[c * neB + tid];
+            const float s2 = float(sRed[BLOCK + c * neB + tid]);
+            const double Mn = fmin(M, m2);
+            const float a = (M == Mn) ? S : S * expn(M - Mn, T);
+            const float bb = (m2 == Mn) ? s2 : s2 * expn(m2 - Mn, T);
+            M = Mn; S = a + bb;
+          }
+          sCol[l] = M - T.tl * double(lg2f(S));
+        }
+        __syncthreads();
+      }
+    }
+    __syncthreads();
+    // E-E pass 2: candidates, scores, top-K
+    {
+      int k = tid / neB, l = tid - (tid / neB) * neB;
+      const int sk = BLOCK / neB, sl = BLOCK - sk * neB;
+      for (int idx = tid; idx < nee; idx += BLOCK) {
+        Cand c1, c2;
+        ee(k, l, c1, c2);
+        Sbuf[nvs + 2 * idx] = float(c1.s);
+        Sbuf[nvs + 2 * idx + 1] = float(c2.s);
+        tk_insert<KMAX>(tk, c1.s);
+        tk_insert<KMAX>(tk, c2.s);
+        k += sk; l += sl;
+        if (l >= neB) { l -= neB; ++k; }
+      }
+    }
+  }
+
+  // ------------------------------------------------------------ top-K
+  // Block merge of per-lane sorted lists: K rounds of block max; the lowest
+  // thread holding the maximum pops it.  sTop[0..K) = s_[1] >= ... >= s_[K].
+  __device__ void topk(double (&tk)[KMAX]) {
+    for (int r = 0; r < K; ++r) {
+      const double h = tk[0];
+      const double wm = wave_max(h);
+      const unsigned long long ball = __ballot(h == wm);
+      if (lane == 0) {
+        sRed[wave] = wm;
+        sRed[NW + wave] = double(wave * 64 + (int)__ffsll((long long)ball) - 1);
+      }
+      __syncthreads();
+      double bm = sRed[0];
+      int win = int(sRed[NW]);
+#pragma unroll
+      for (int w = 1; w < NW; ++w) {
+        const double v = sRed[w];
+        if (v > bm) { bm = v; win = int(sRed[NW + w]); }
+      }
+      if (tid == win) {
+#pragma unroll
+        for (int i = 0; i < KMAX - 1; ++i) tk[i] = tk[i + 1];
+        tk[KMAX - 1] = -INFINITY;
+      }
+      if (tid == 0) sTop[r] = bm;
+      __syncthreads();
+    }
+  }
+
+  // ------------------------------------------------------------ filtered iteration
+  // Visit the candidates whose stored score is within 40 tau of s_[K] in
+  // chunks: records are compacted (in candidate order) into sRec, then
+  // body(tot) runs with all threads after a barrier.
+  template <typename F>
+  __device__ void for_filtered(F&& body) {
+    const float thr = float(sTop[K - 1] - kFilterTaus * T.tau) - 1e-6f * fabsf(float(sTop[K - 1]));
+    const int ncand = ps.ncand;
+    for (int base = 0; base < ncand; base += BLOCK) {
+      const int idx = base + tid;
+      const bool pass = idx < ncand && Sbuf[idx] >= thr;
+      const unsigned long long ball = __ballot(pass);
+      const int below = __popcll(ball & ((1ull << lane) - 1ull));
+      if (lane == 0) sCnt[wave] = __popcll(ball);
+      __syncthreads();
+      int off = 0, tot = 0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        const int c = sCnt[w];
+        off += (w < wave) ? c : 0;
+        tot += c;
+      }
+      if (tot == 0) {
+        __syncthreads();
+        continue;
+      }
+      if (pass) {
+        Cand c;
+        candidate(idx, c);
+        Rec& rr = sRec[off + below];
+        rr.s = c.s; rr.d = c.d;
+        rr.px = float(c.p.x); rr.py = float(c.p.y); rr.pz = float(c.p.z);
+        rr.nx = float(c.n.x); rr.ny = float(c.n.y); rr.nz = float(c.n.z);
+        rr.w = ex2f(float(c.lw * kLog2e));
+        rr.idx = idx;
+      }
+      __syncthreads();
+      body(tot);
+      __syncthreads();
+    }
+  }
+
+  // ------------------------------------------------------------ SoftSort
+  // sAcc[9k + f] = sum_i exp(-|s_[k] - s_i| / tau) * field_f(i), field 0 = 1.
+  __device__ void softsort() {
+    const int nacc = 9 * K;
+    double acc[NSLOT];
+#pragma unroll
+    for (int i = 0; i < NSLOT; ++i) acc[i] = 0.0;
+    for_filtered([&](int tot) {
+#pragma unroll
+      for (int slot = 0; slot < NSLOT; ++slot) {
+        const int j = tid + slot * BLOCK;
+        if (j < nacc) {
+          const int kk = j / 9, f = j - kk * 9;
+          const double sk = sTop[kk];
+          double a = 0.0;
+          for (int r = 0; r < tot; ++r) {
+            const Rec& rr = sRec[r];
+            const double e = double(expn(fabs(sk - rr.s), T));
+            double v;
+            switch (f) {
+              case 0: v = 1.0; break;
+              case 1: v = rr.px; break;
+              case 2: v = rr.py; break;
+              case 3: v = rr.pz; break;
+              case 4: v = rr.nx; break;
+              case 5: v = rr.ny; break;
+              case 6: v = rr.nz; break;
+              case 7: v = rr.d; break;
+              default: v = rr.w; break;
+            }
+            a = fma(e, v, a);
+          }
+          acc[slot] += a;
+        }
+      }
+    });
+#pragma unroll
+    for (int slot = 0; slot < NSLOT; ++slot) {
+      const int j = tid + slot * BLOCK;
+      if (j < nacc) sAcc[j] = acc[slot];
+    }
+    __syncthreads();
+  }
+};
+
+}  // namespace cm

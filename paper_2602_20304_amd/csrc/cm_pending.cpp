@@ -2,10 +2,6 @@
 #include "cm_context.h"
 
 extern "C" {
-cm_status cm_collide_backward(cm_context* ctx, const cm_batch*, const cm_params*, const cm_manifold*,
-                              const cm_cotangent*, cm_grads*, void*) {
-  return cm_fail(ctx, CM_ERR_INVALID_ARG, "backward not available in this build");
-}
 cm_status cm_server_create(cm_context* ctx, uint64_t, int32_t, cm_server**) {
   return cm_fail(ctx, CM_ERR_INVALID_ARG, "server not available in this build");
 }

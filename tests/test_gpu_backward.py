@@ -1,0 +1,143 @@
+"""Adjoint parity: the HIP backward against the FP64 oracle's analytic
+gradient (autograd of the oracle forward), for pose twists, polytope hull
+vertices, analytic parameters and tau (needs an MI355X)."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import cm_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+# gradients: |gpu - ref| <= GRAD_RTOL * (|ref| + 1e-2 * max|ref|) element-wise
+GRAD_RTOL = 1e-3
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2602_20304_amd.cm import Context
+    return Context(0)
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_grads(ctx, batch, seed=0):
+    _say(f"[gpu-bwd] {batch.name} scenes={batch.n_scenes} tau={batch.tau} K={batch.K}")
+    ids = ctx.create_geometry(batch.geoms)
+    db = ctx.upload_batch(batch, ids)
+    m = ctx.collide(db, batch.tau, batch.K)
+    ctx.check_errors()
+    n = int(m.n_pairs.item())
+    K = batch.K
+    rng = np.random.default_rng(seed)
+    cap = m.capacity
+    cot = {k: rng.standard_normal(s).astype(np.float32) for k, s in
+           (("p", (3, cap * K)), ("nu", (3, cap * K)), ("d", (cap * K,)), ("w", (cap * K,)))}
+    tt = {k: torch.as_tensor(v).to(ctx.device) for k, v in cot.items()}
+    g = ctx.collide_backward(db, m, batch.tau, K, tt["p"], tt["nu"], tt["d"], tt["w"])
+    ctx.check_errors()
+    out = {k: (v.cpu().numpy() if v is not None else None) for k, v in g.items()}
+    return ids, m.to_numpy(), cot, out, n
+
+
+def oracle_grads(batch, pairs, cot, K):
+    cache = O.GeomCache(batch.geoms, requires_grad=True)
+    nb = batch.n_bodies
+    g_pose = np.zeros((6, nb))
+    g_geom = {}
+    g_tau = 0.0
+    for i in range(pairs.shape[1]):
+        a, b = int(pairs[0, i]), int(pairs[1, i])
+        GA, GB = cache[batch.body_geom[a]], cache[batch.body_geom[b]]
+        sl = slice(i * K, (i + 1) * K)
+        c = dict(p=cot["p"][:, sl].T, nu=cot["nu"][:, sl].T, d=cot["d"][sl], w=cot["w"][sl])
+        r = O.pair_grad(GA, batch.pose[:, a], GB, batch.pose[:, b], batch.tau, K, c)
+        g_pose[:, a] += r["xiA"]
+        g_pose[:, b] += r["xiB"]
+        ga, gb = int(batch.body_geom[a]), int(batch.body_geom[b])
+        g_geom[ga] = g_geom.get(ga, 0) + r["geomA"]
+        if GB is not GA:
+            g_geom[gb] = g_geom.get(gb, 0) + r["geomB"]
+        g_tau += r["tau"]
+    return g_pose, g_geom, g_tau, cache
+
+
+def close(got, ref, rtol=GRAD_RTOL):
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    scale = np.max(np.abs(ref)) if ref.size else 0.0
+    err = np.abs(got - ref) - rtol * (np.abs(ref) + 1e-2 * scale)
+    return float(err.max()) if err.size else -1.0, float(np.max(np.abs(got - ref))) if err.size else 0.0, scale
+
+
+def check(ctx, batch, seed=0):
+    ids, fwd, cot, g, n = gpu_grads(ctx, batch, seed)
+    pairs = fwd["pairs"]
+    g_pose, g_geom, g_tau, cache = oracle_grads(batch, pairs, cot, batch.K)
+    rep = {}
+    rep["pose"] = close(g["pose"], g_pose)
+    vx, vr, pr_g, pr_r = [], [], [], []
+    for gid, ref in g_geom.items():
+        info = ctx.geometry_info(int(ids[gid]))
+        G = cache[gid]
+        if G.kind == O.POLYTOPE:
+            o = info["vertex_offset"]
+            vx.append(g["vertices"][:, o:o + info["n_vertices"]].T)
+            vr.append(ref)
+        else:
+            pr_g.append(g["params"][:, ids[gid]])
+            pr_r.append(ref)
+    if vx:
+        rep["vertices"] = close(np.concatenate(vx), np.concatenate(vr))
+    if pr_g:
+        rep["params"] = close(np.stack(pr_g), np.stack(pr_r))
+    rep["tau"] = close([g["tau"][0]], [g_tau])
+    _say(f"   grad parity {batch.name} ({n} pairs): " +
+         ", ".join(f"{k}: excess {v[0]:.2e} maxabs {v[1]:.2e} scale {v[2]:.2e}" for k, v in rep.items()))
+    for k, v in rep.items():
+        assert v[0] <= 0, (k, v)
+
+
+def test_backward_polytopes(ctx):
+    check(ctx, W.polytope_scenes(2, seed=21, n_points=24, tau=0.02))
+
+
+def test_backward_mixed(ctx):
+    check(ctx, W.mixed_scenes(6, seed=22, poly_points=16, tau=0.01))
+
+
+def test_backward_cubes_shared_geometry(ctx):
+    check(ctx, W.cube_pairs(24, seed=23))
+
+
+@pytest.mark.parametrize("tau", [0.1, 0.001])
+def test_backward_tau_sweep(ctx, tau):
+    check(ctx, W.polytope_scenes(1, seed=24, n_points=20, tau=tau))
+
+
+def test_backward_joint_motion_identity(ctx):
+    """Sum of both bodies' twists equals the output-transform terms (a property
+    that holds at any size): with only normal and distance cotangents the
+    joint translation gradient vanishes."""
+    b = W.polytope_scenes(64, seed=25, n_points=32)
+    ids = ctx.create_geometry(b.geoms)
+    db = ctx.upload_batch(b, ids)
+    m = ctx.collide(db, b.tau, b.K)
+    cap, K = m.capacity, b.K
+    gN = torch.randn(3, cap * K, device=ctx.device)
+    gD = torch.randn(cap * K, device=ctx.device)
+    g = ctx.collide_backward(db, m, b.tau, K, None, gN, gD, None)
+    ctx.check_errors()
+    pose = g["pose"].cpu().numpy()
+    nb = b.n_bodies
+    # per scene: sum over its bodies of the translation part must vanish
+    bo = b.body_offsets
+    sums = np.stack([pose[:3, bo[s]:bo[s + 1]].sum(1) for s in range(b.n_scenes)])
+    scale = np.abs(pose[:3]).max()
+    assert np.abs(sums).max() <= 1e-4 * scale, (np.abs(sums).max(), scale)
