@@ -217,9 +217,10 @@ typedef struct {
 typedef struct {
   cm_status status;
   int32_t n_pairs;
+  int32_t capacity;              /* row stride of the arrays below */
   const int32_t* pair_offsets;   /* host [n_scenes + 1] */
-  const int32_t* pairs;          /* host [2][n_pairs] */
-  const float* point;            /* host [3][n_pairs*K] */
+  const int32_t* pairs;          /* host [2][capacity] */
+  const float* point;            /* host [3][capacity*K] */
   const float* normal;
   const float* dist;
   const float* weight;

@@ -54,7 +54,7 @@ class cm_request(C.Structure):
 
 
 class cm_result(C.Structure):
-    _fields_ = [("status", i32), ("n_pairs", i32), ("pair_offsets", i32p), ("pairs", i32p), ("point", f32p),
+    _fields_ = [("status", i32), ("n_pairs", i32), ("capacity", i32), ("pair_offsets", i32p), ("pairs", i32p), ("point", f32p),
                 ("normal", f32p), ("dist", f32p), ("weight", f32p), ("g_pose", f32p), ("t_submit", C.c_double),
                 ("t_start", C.c_double), ("t_done", C.c_double), ("footprint_bytes", C.c_uint64)]
 

@@ -272,3 +272,85 @@ def collide_autograd(cmctx: Context, db: DeviceBatch, tau_t: torch.Tensor, K: in
         params = torch.zeros(4, max(cmctx.geometry_count, 1), device=dev, requires_grad=True)
     cap = db.n_cand_total if capacity is None else capacity
     return _CollideFn.apply(xi, verts, params, tau_t, cmctx, db, K, cap, fused)
+
+
+class Server:
+    """Continuous-batching request loop over a context's resident geometry
+    (cm_server_*).  Requests carry host arrays; results come back as numpy
+    copies.  Thread-safe submit / poll."""
+
+    def __init__(self, cmctx: Context, budget_bytes: int, n_streams: int = 4):
+        self.ctx = cmctx
+        self.lib = cmctx.lib
+        h = C.c_void_p()
+        cmctx._check(self.lib.cm_server_create(cmctx.h, C.c_uint64(int(budget_bytes)), int(n_streams), C.byref(h)))
+        self.h = h
+        self._keep = {}
+
+    def submit(self, body_offsets, body_geom, pose, tau: float, K: int, want_backward=False, cot_dist=None,
+               cot_normal=None, capacity: int = 0) -> int:
+        """body_geom are context geometry ids; pose float32 [7, n_bodies]."""
+        bo = np.ascontiguousarray(body_offsets, np.int32)
+        bg = np.ascontiguousarray(body_geom, np.int32)
+        ps = np.ascontiguousarray(pose, np.float32)
+        q = L.cm_request()
+        q.n_scenes, q.n_bodies = len(bo) - 1, len(bg)
+        q.body_offsets, q.body_geom, q.pose = _np_ptr(bo), _np_ptr(bg), _np_ptr(ps)
+        q.params = make_params(tau, K)
+        q.want_backward = int(bool(want_backward))
+        cd = None if cot_dist is None else np.ascontiguousarray(cot_dist, np.float32)
+        cn = None if cot_normal is None else np.ascontiguousarray(cot_normal, np.float32)
+        q.cot_dist, q.cot_normal = _np_ptr(cd), _np_ptr(cn)
+        q.capacity = int(capacity)
+        t = C.c_uint64()
+        st = self.lib.cm_server_submit(self.h, C.byref(q), C.byref(t))
+        if st != L.CM_OK:
+            raise L.CMError(st, self.lib.cm_last_error(self.ctx.h).decode())
+        self._keep[t.value] = (K, q.n_scenes, q.n_bodies, bool(want_backward))
+        return t.value
+
+    def poll(self, ticket: int):
+        """None while pending / running, else a dict of numpy results."""
+        r = L.cm_result()
+        st = self.lib.cm_server_poll(self.h, C.c_uint64(ticket), C.byref(r))
+        if st == -4:
+            return None
+        K, S, nb, bwd = self._keep[ticket]
+        n, cap = r.n_pairs, r.capacity
+        m = min(n, cap)
+        arr = lambda p, cnt: np.ctypeslib.as_array(p, shape=(cnt,)).copy()
+        out = dict(status=st, n_pairs=n, capacity=cap, t_submit=r.t_submit, t_start=r.t_start, t_done=r.t_done,
+                   footprint=r.footprint_bytes, offsets=arr(r.pair_offsets, S + 1))
+        pr = arr(r.pairs, 2 * max(cap, 1))
+        out["pairs"] = np.stack([pr[:m], pr[cap:cap + m]])
+        pt = arr(r.point, 3 * max(cap, 1) * K).reshape(3, -1)[:, :m * K]
+        nv = arr(r.normal, 3 * max(cap, 1) * K).reshape(3, -1)[:, :m * K]
+        out["p"] = pt.reshape(3, m, K).transpose(1, 2, 0)
+        out["nu"] = nv.reshape(3, m, K).transpose(1, 2, 0)
+        out["d"] = arr(r.dist, max(cap, 1) * K)[:m * K].reshape(m, K)
+        out["w"] = arr(r.weight, max(cap, 1) * K)[:m * K].reshape(m, K)
+        if bwd:
+            out["g_pose"] = arr(r.g_pose, 6 * max(nb, 1)).reshape(6, -1)[:, :nb]
+        return out
+
+    def release(self, ticket: int):
+        self.lib.cm_server_release(self.h, C.c_uint64(ticket))
+        self._keep.pop(ticket, None)
+
+    def stats(self):
+        b = C.c_uint64()
+        p = C.c_int32()
+        r = C.c_int32()
+        self.lib.cm_server_stats(self.h, C.byref(b), C.byref(p), C.byref(r))
+        return dict(in_flight_bytes=b.value, pending=p.value, running=r.value)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.cm_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -49,7 +49,7 @@ struct BodySink {
 // WAVE: all 64 lanes execute this call together (plane adjoints are summed
 // across the wave before one atomic per plane).
 template <bool WAVE>
-__device__ __forceinline__ D3 sdf_local_bwd(int type, const float* p, const float4* __restrict__ pl, int nf, const D3& l,
+__device__ __forceinline__ D3 sdf_local_bwd(int type, const float* p, const double4* __restrict__ pl, int nf, const D3& l,
                                             double phib, const D3& gb, const Temp& T, const BodySink& sink,
                                             double& taub, D3& g_out) {
   if (type == CM_SPHERE) {
@@ -108,15 +108,15 @@ __device__ __forceinline__ D3 sdf_local_bwd(int type, const float* p, const floa
   // polytope: phi = tau LSE(y / tau), y_f = n_f . l - o_f, g = sum_f pi_f n_f
   double m = -1e300;
   for (int f = 0; f < nf; ++f) {
-    const float4 q = pl[f];
-    m = fmax(m, fma(double(q.x), l.x, fma(double(q.y), l.y, fma(double(q.z), l.z, -double(q.w)))));
+    const double4 q = pl[f];
+    m = fmax(m, fma(q.x, l.x, fma(q.y, l.y, fma(q.z, l.z, -q.w))));
   }
   double S = 0.0, gx = 0.0, gy = 0.0, gz = 0.0, py = 0.0;
   for (int f = 0; f < nf; ++f) {
-    const float4 q = pl[f];
-    const double yv = fma(double(q.x), l.x, fma(double(q.y), l.y, fma(double(q.z), l.z, -double(q.w))));
+    const double4 q = pl[f];
+    const double yv = fma(q.x, l.x, fma(q.y, l.y, fma(q.z, l.z, -q.w)));
     const double e = double(ex2f(float((yv - m) * T.c)));
-    S += e; gx = fma(e, double(q.x), gx); gy = fma(e, double(q.y), gy); gz = fma(e, double(q.z), gz);
+    S += e; gx = fma(e, q.x, gx); gy = fma(e, q.y, gy); gz = fma(e, q.z, gz);
     py = fma(e, yv, py);
   }
   const double iS = 1.0 / S;
@@ -128,8 +128,8 @@ __device__ __forceinline__ D3 sdf_local_bwd(int type, const float* p, const floa
   D3 lb = d3(0.0, 0.0, 0.0);
   double tz = 0.0;
   for (int f = 0; f < nf; ++f) {
-    const float4 q = pl[f];
-    const double yv = fma(double(q.x), l.x, fma(double(q.y), l.y, fma(double(q.z), l.z, -double(q.w))));
+    const double4 q = pl[f];
+    const double yv = fma(q.x, l.x, fma(q.y, l.y, fma(q.z, l.z, -q.w)));
     const double pi = double(ex2f(float((yv - m) * T.c))) * iS;
     const double zb = pi * (gb.x * q.x + gb.y * q.y + gb.z * q.z - gbg);   // softmax adjoint of g
     const double yb = phib * pi + zb * T.inv_tau;

@@ -142,6 +142,7 @@ cm_status cm_geometry_create(cm_context* ctx, int32_t n, const int32_t* types, c
                              const int64_t* pt_offsets, const float* points, int32_t* out_ids) {
   if (!ctx || n < 0 || (n > 0 && (!types || !params || !out_ids))) return CM_ERR_INVALID_ARG;
   if (n == 0) return CM_OK;
+  if (ctx->servers > 0) return cm_fail(ctx, CM_ERR_INVALID_ARG, "geometry is frozen while a server is running");
   for (int i = 0; i < n; ++i) {
     if (types[i] < CM_SPHERE || types[i] > CM_POLYTOPE)
       return cm_fail(ctx, CM_ERR_INVALID_ARG, "unknown geometry type");

@@ -49,6 +49,7 @@ struct cm_context {
   size_t bwd_cap = 0;
   // fused path: size-class plan (per K), tuned block sizes, captured graphs
   int geom_version = 0;
+  int servers = 0;             // live servers (geometry is frozen while > 0)
   int plan_K = -1, plan_version = -1;
   bool plan_tuned = false;
   int cls_maxE[3] = {0, 0, 0}, cls_maxV[3] = {0, 0, 0}, cls_maxF[3] = {0, 0, 0}, cls_block[3] = {256, 256, 256};

@@ -44,6 +44,18 @@ __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x)
 // exp(-a / tau) for a >= 0 given in float64 (result float32)
 __device__ __forceinline__ float expn(double a, const Temp& T) { return ex2f(float(-a * T.c)); }
 
+// 1/x in float64 for finite x with |x| well inside the normal range:
+// v_rcp_f64 (about 26 correct bits) plus two Newton steps.  Used where the
+// operand is bounded away from zero by construction (Q11, Q22, det Q >= lambda
+// terms, sums >= 1, sqrt(|d|^2 + eps)).
+__device__ __forceinline__ double rcp64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
 // exp(x) for x <= 0 to ~1e-12 relative in float64: Cody-Waite reduction
 // x = n ln2 + r, |r| <= ln2 / 2, then a degree-9 Taylor polynomial of e^r
 // (remainder below r^10 / 10! ~ 7e-12) scaled by 2^n.
@@ -67,13 +79,13 @@ __device__ __forceinline__ double exp64n(double x) {
 // sigma(u / tau) in float64
 __device__ __forceinline__ double sig64(double u, const Temp& T) {
   const double e = exp64n(-fabs(u) * T.inv_tau);
-  const double r = 1.0 / (1.0 + e);
+  const double r = rcp64(1.0 + e);
   return u >= 0.0 ? r : e * r;
 }
 // tanh(u / tau) in float64
 __device__ __forceinline__ double tanh64(double u, const Temp& T) {
   const double e = exp64n(-2.0 * fabs(u) * T.inv_tau);
-  return copysign((1.0 - e) / (1.0 + e), u);
+  return copysign((1.0 - e) * rcp64(1.0 + e), u);
 }
 
 // tau * softplus(x / tau) = max(x, 0) + tau ln(1 + exp(-|x| / tau))
@@ -147,23 +159,27 @@ __device__ __forceinline__ void sdf_analytic(int type, const float* p, const D3&
   }
 }
 
-// tau-LSE over body-frame planes (n.xyz, o) stored as float4 in LDS:
+// tau-LSE over body-frame planes: pd[f] = (n.xyz, o) in float64, pf[f] =
+// n.xyz in float32 (gradient accumulation), both in LDS.
 // phi = LSE_tau(n . x - o); gradient = softmax-weighted sum of normals.
 template <bool WANT_G>
-__device__ __forceinline__ void sdf_poly(const float4* __restrict__ pl, int nf, const D3& x, const Temp& T,
-                                         double& phi, D3& g) {
+__device__ __forceinline__ void sdf_poly(const double4* __restrict__ pd, const float4* __restrict__ pf, int nf,
+                                         const D3& x, const Temp& T, double& phi, D3& g) {
   double m = -1e300;
   for (int f = 0; f < nf; ++f) {
-    const float4 q = pl[f];
-    m = fmax(m, fma(double(q.x), x.x, fma(double(q.y), x.y, fma(double(q.z), x.z, -double(q.w)))));
+    const double4 q = pd[f];
+    m = fmax(m, fma(q.x, x.x, fma(q.y, x.y, fma(q.z, x.z, -q.w))));
   }
   float s = 0.f, ax = 0.f, ay = 0.f, az = 0.f;
   for (int f = 0; f < nf; ++f) {
-    const float4 q = pl[f];
-    const double yv = fma(double(q.x), x.x, fma(double(q.y), x.y, fma(double(q.z), x.z, -double(q.w))));
+    const double4 q = pd[f];
+    const double yv = fma(q.x, x.x, fma(q.y, x.y, fma(q.z, x.z, -q.w)));
     const float e = ex2f(float((yv - m) * T.c));
     s += e;
-    if (WANT_G) { ax = fmaf(e, q.x, ax); ay = fmaf(e, q.y, ay); az = fmaf(e, q.z, az); }
+    if (WANT_G) {
+      const float4 n = pf[f];
+      ax = fmaf(e, n.x, ax); ay = fmaf(e, n.y, ay); az = fmaf(e, n.z, az);
+    }
   }
   phi = m + T.tl * double(lg2f(s));
   if (WANT_G) {
@@ -179,7 +195,8 @@ struct BodyView {
   double R[9];   // body frame -> pair frame rotation (row-major)
   double t[3];   // body origin in the pair frame
   bool ident;    // R = I, t = 0 (body A)
-  const float4* planes;   // LDS, body frame (polytopes)
+  const double4* planes;  // LDS, body frame (polytopes): (n.xyz, o) in float64
+  const float4* normals;  // LDS, the same normals in float32
 };
 
 // SDF of a body at a pair-frame point; gradient returned in the pair frame.
@@ -192,7 +209,7 @@ __device__ __forceinline__ void sdf_body(const BodyView& B, const D3& x, const T
            B.R[2] * dx + B.R[5] * dy + B.R[8] * dz);
   }
   D3 lg;
-  if (B.type == CM_POLYTOPE) sdf_poly<WANT_G>(B.planes, B.nf, l, T, phi, lg);
+  if (B.type == CM_POLYTOPE) sdf_poly<WANT_G>(B.planes, B.normals, B.nf, l, T, phi, lg);
   else sdf_analytic(B.type, B.p, l, phi, lg);
   if (WANT_G) {
     if (B.ident) g = lg;
@@ -232,10 +249,10 @@ __device__ __forceinline__ EEQP ee_qp(const D3& a0, const D3& t1, const D3& b0, 
   const double c1 = dot(b, t1) - hl;
   const double c2 = -dot(b, t2) - hl;
   const double det = Q11 * Q22 - Q12 * Q12;
-  const double idet = 1.0 / det;
+  const double idet = rcp64(det);
   const double au1 = (Q12 * c2 - c1 * Q22) * idet;
   const double au2 = (Q12 * c1 - c2 * Q11) * idet;
-  const double i11 = 1.0 / Q11, i22 = 1.0 / Q22;
+  const double i11 = rcp64(Q11), i22 = rcp64(Q22);
   const double xa = clip01(-(Q12 + c2) * i22, T);   // on al1 = 1
   const double xb = clip01(-c2 * i22, T);           // on al1 = 0
   const double xc = clip01(-(Q12 + c1) * i11, T);   // on al2 = 1
@@ -253,7 +270,7 @@ __device__ __forceinline__ EEQP ee_qp(const D3& a0, const D3& t1, const D3& b0, 
   // points directly, so they use float64 exponentials
   const double w0 = exp64n(-(j0 - jm) * T.inv_tau), w1 = exp64n(-(j1 - jm) * T.inv_tau);
   const double w2 = exp64n(-(j2 - jm) * T.inv_tau), w3 = exp64n(-(j3 - jm) * T.inv_tau);
-  const double iw = 1.0 / ((w0 + w1) + (w2 + w3));
+  const double iw = rcp64((w0 + w1) + (w2 + w3));
   const double ac1 = (w0 + w2 * xc + w3 * xd) * iw;
   const double ac2 = (w0 * xa + w1 * xb + w2) * iw;
   const double con = (sig64(au1, T) * sig64(1.0 - au1, T)) * (sig64(au2, T) * sig64(1.0 - au2, T));
@@ -292,7 +309,7 @@ __device__ __forceinline__ void ee_candidates(const D3& a0, const D3& t1, const 
   const D3 e2 = d3(b0.x + q.al2 * t2.x, b0.y + q.al2 * t2.y, b0.z + q.al2 * t2.z);
   const double dsq = dot(q.de, q.de);
   const double dbar = sqrt(dsq);
-  const double in = 1.0 / sqrt(dsq + eps_n);
+  const double in = rcp64(sqrt(dsq + eps_n));
   const D3 nb = d3(q.de.x * in, q.de.y * in, q.de.z * in);
   double phiB1, phiA2, dum;
   D3 gA, gB, dg;
@@ -326,7 +343,7 @@ __device__ __forceinline__ void vs_candidate(const D3& v, const BodyView& other,
   double phi;
   D3 g;
   sdf_body<true>(other, v, T, phi, g);
-  const double in = sgn / sqrt(T.tau + dot(g, g));
+  const double in = sgn * rcp64(sqrt(T.tau + dot(g, g)));
   c.p = v;
   c.n = d3(g.x * in, g.y * in, g.z * in);
   c.d = phi;

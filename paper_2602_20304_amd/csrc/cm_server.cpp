@@ -1,0 +1,379 @@
+// Serving loop: continuous batching of collision requests over resident
+// geometry.
+//
+// A scheduler thread admits pending requests in arrival order while their
+// device footprint fits in the HBM budget and a stream slot is free; every
+// admitted request gets its own stream and workspace (stream-ordered
+// allocations), so requests that arrive while others run are admitted as
+// soon as memory and a slot free up, and their kernels overlap on the GPU.
+// Results (and gradients for backward requests) are copied to pinned host
+// memory owned by the server until cm_server_release.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "cm_context.h"
+#include "cm_kernels.h"
+
+using namespace cm;
+
+namespace {
+
+double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct Request {
+  uint64_t ticket = 0;
+  // host copies
+  std::vector<int32_t> body_offsets, body_geom;
+  std::vector<float> pose, cot_dist, cot_normal;
+  cm_params params{};
+  bool want_bwd = false;
+  int32_t n_scenes = 0, n_bodies = 0, capacity = 0;
+  uint64_t footprint = 0;
+  double t_submit = 0, t_start = 0, t_done = 0;
+  enum State { PENDING, RUNNING, DONE, FAILED } state = PENDING;
+  cm_status status = CM_OK;
+  int slot = -1;
+  // device workspace (one allocation, carved)
+  void* dev = nullptr;
+  // pinned host results
+  int32_t* h_n_pairs = nullptr;
+  int32_t* h_offsets = nullptr;
+  int32_t* h_pairs = nullptr;
+  float* h_out = nullptr;      // point(3) normal(3) dist weight, each [cap*K]
+  float* h_gpose = nullptr;
+  hipEvent_t done_ev = nullptr;
+};
+
+}  // namespace
+
+struct cm_server {
+  cm_context* ctx = nullptr;
+  uint64_t budget = 0;
+  uint64_t in_flight = 0;
+  int n_slots = 1;
+  std::vector<hipStream_t> streams;
+  std::vector<int> slot_busy;
+  std::map<uint64_t, std::unique_ptr<Request>> reqs;
+  std::deque<uint64_t> pending;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::thread worker;
+  std::atomic<bool> stop{false};
+  uint64_t next_ticket = 1;
+  int n_running = 0;
+};
+
+namespace {
+
+struct Carve {
+  char* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t n) {
+    off = (off + 255) & ~size_t(255);
+    T* p = reinterpret_cast<T*>(base + off);
+    off += sizeof(T) * std::max<size_t>(n, 1);
+    return p;
+  }
+};
+
+// Device bytes one request needs (inputs, outputs, scratch, gradients).
+uint64_t footprint(cm_context* ctx, const Request& r, long long grid, long long stride) {
+  const int K = r.params.K;
+  const uint64_t cap = uint64_t(std::max(r.capacity, 1));
+  uint64_t b = 0;
+  b += 4ull * (r.n_scenes + 1) * 2 + 4ull * r.n_bodies + 28ull * r.n_bodies;      // offsets, geom ids, poses
+  b += 4ull + 8ull * cap + 32ull * cap * K;                                        // n_pairs, pairs, outputs
+  b += 4ull * (r.n_scenes / 1024 + 2);                                             // scan tiles
+  b += 4ull * uint64_t(grid) * uint64_t(stride);                                   // per-workgroup scratch
+  if (r.want_bwd) b += 16ull * cap * K + 24ull * r.n_bodies + 4ull;                // cotangents, g_pose, g_tau
+  return b + 64 * 256;
+}
+
+void launch_request(cm_server* srv, Request& r) {
+  cm_context* ctx = srv->ctx;
+  hipStream_t st = srv->streams[r.slot];
+  ParamsDev pd;
+  if (resolve_params(ctx, &r.params, &pd) != CM_OK) { r.status = CM_ERR_INVALID_ARG; return; }
+  const int K = pd.K;
+  const size_t cap = size_t(std::max(r.capacity, 1));
+  FwdLaunch f;
+  f.tb = ctx_tables(ctx);
+  f.maxV = std::max(ctx->maxV, 1); f.maxE = std::max(ctx->maxE, 1); f.maxF = std::max(ctx->maxF, 1);
+  f.block = 256; f.kmax = kmax_for(K); f.order = nullptr; f.range = nullptr; f.queue = nullptr; f.err = ctx->d_err;
+  // grid already folded into the footprint: recompute the same value
+  f.prm = pd;
+  const int occ = fwd_occupancy(f);
+  f.grid = std::max(1, occ * ctx->num_cus / std::max(1, srv->n_slots));
+  f.scratch_stride = fwd_scratch_floats(f.maxV, f.maxE);
+  if (hipMallocAsync(&r.dev, size_t(r.footprint), st) != hipSuccess) { r.status = CM_ERR_OOM; return; }
+  Carve c{static_cast<char*>(r.dev)};
+  int32_t* d_bo = c.take<int32_t>(r.n_scenes + 1);
+  int32_t* d_bg = c.take<int32_t>(r.n_bodies);
+  float* d_pose = c.take<float>(7 * size_t(r.n_bodies));
+  int32_t* d_np = c.take<int32_t>(1);
+  int32_t* d_off = c.take<int32_t>(r.n_scenes + 1);
+  int32_t* d_pairs = c.take<int32_t>(2 * cap);
+  float* d_out = c.take<float>(8 * cap * K);
+  int32_t* d_tiles = c.take<int32_t>(r.n_scenes / 1024 + 2);
+  float* d_scr = c.take<float>(size_t(f.grid) * size_t(f.scratch_stride));
+  (void)hipMemcpyAsync(d_bo, r.body_offsets.data(), 4 * r.body_offsets.size(), hipMemcpyHostToDevice, st);
+  (void)hipMemcpyAsync(d_bg, r.body_geom.data(), 4 * r.body_geom.size(), hipMemcpyHostToDevice, st);
+  (void)hipMemcpyAsync(d_pose, r.pose.data(), 4 * r.pose.size(), hipMemcpyHostToDevice, st);
+  BatchDev bd{r.n_scenes, r.n_bodies, 0, d_bo, d_bg, d_pose, nullptr, nullptr};
+  OutDev od{int32_t(cap), d_np, d_off, d_pairs, d_out, d_out + 3 * cap * K, d_out + 6 * cap * K, d_out + 7 * cap * K};
+  f.bt = bd; f.out = od; f.scratch = d_scr;
+  if (launch_broadphase(f.tb, bd, pd.margin, od, d_tiles, ctx->d_err, st) != hipSuccess ||
+      launch_collide_fwd(f, st) != hipSuccess) {
+    r.status = CM_ERR_DEVICE;
+    return;
+  }
+  if (r.want_bwd) {
+    float* d_cd = c.take<float>(cap * K);
+    float* d_cn = c.take<float>(3 * cap * K);
+    float* d_gpose = c.take<float>(6 * size_t(r.n_bodies));
+    float* d_gtau = c.take<float>(1);
+    (void)hipMemsetAsync(d_cd, 0, 4 * cap * K, st);
+    (void)hipMemsetAsync(d_cn, 0, 12 * cap * K, st);
+    if (!r.cot_dist.empty())
+      (void)hipMemcpyAsync(d_cd, r.cot_dist.data(), 4 * std::min(r.cot_dist.size(), cap * K), hipMemcpyHostToDevice, st);
+    if (!r.cot_normal.empty())
+      (void)hipMemcpyAsync(d_cn, r.cot_normal.data(), 4 * std::min(r.cot_normal.size(), 3 * cap * K),
+                           hipMemcpyHostToDevice, st);
+    (void)hipMemsetAsync(d_gpose, 0, 24 * size_t(r.n_bodies), st);
+    (void)hipMemsetAsync(d_gtau, 0, 4, st);
+    BwdLaunch b;
+    b.f = f;
+    b.cot = CotDev{nullptr, d_cn, d_cd, nullptr};
+    b.gr = GradDev{d_gpose, nullptr, nullptr, d_gtau, (long long)ctx->h.vx.size()};
+    b.f.grid = std::max(1, bwd_occupancy(b) * ctx->num_cus / std::max(1, srv->n_slots));
+    b.f.grid = std::min(b.f.grid, f.grid);   // fits the scratch carved for the forward grid
+    if (launch_collide_bwd(b, st) != hipSuccess) { r.status = CM_ERR_DEVICE; return; }
+    (void)hipMemcpyAsync(r.h_gpose, d_gpose, 24 * size_t(r.n_bodies), hipMemcpyDeviceToHost, st);
+  }
+  (void)hipMemcpyAsync(r.h_n_pairs, d_np, 4, hipMemcpyDeviceToHost, st);
+  (void)hipMemcpyAsync(r.h_offsets, d_off, 4 * size_t(r.n_scenes + 1), hipMemcpyDeviceToHost, st);
+  (void)hipMemcpyAsync(r.h_pairs, d_pairs, 8 * cap, hipMemcpyDeviceToHost, st);
+  (void)hipMemcpyAsync(r.h_out, d_out, 32 * cap * K, hipMemcpyDeviceToHost, st);
+  (void)hipFreeAsync(r.dev, st);
+  r.dev = nullptr;
+  (void)hipEventCreateWithFlags(&r.done_ev, hipEventDisableTiming);
+  (void)hipEventRecord(r.done_ev, st);
+}
+
+void worker_loop(cm_server* srv) {
+  hipSetDevice(srv->ctx->device);
+  while (!srv->stop.load()) {
+    std::vector<Request*> to_launch;
+    {
+      std::unique_lock<std::mutex> lk(srv->mu);
+      // admit in arrival order while memory and a slot are free
+      while (!srv->pending.empty()) {
+        Request& r = *srv->reqs[srv->pending.front()];
+        const auto it = std::find(srv->slot_busy.begin(), srv->slot_busy.end(), 0);
+        if (it == srv->slot_busy.end() || srv->in_flight + r.footprint > srv->budget) break;
+        r.slot = int(it - srv->slot_busy.begin());
+        *it = 1;
+        srv->in_flight += r.footprint;
+        r.state = Request::RUNNING;
+        r.t_start = now_s();
+        srv->n_running++;
+        srv->pending.pop_front();
+        to_launch.push_back(&r);
+      }
+    }
+    for (Request* r : to_launch) launch_request(srv, *r);
+    // retire finished requests
+    {
+      std::unique_lock<std::mutex> lk(srv->mu);
+      for (auto& kv : srv->reqs) {
+        Request& r = *kv.second;
+        if (r.state != Request::RUNNING) continue;
+        bool done = false;
+        if (r.status != CM_OK) {
+          if (r.slot >= 0) (void)hipStreamSynchronize(srv->streams[r.slot]);
+          if (r.dev) { (void)hipFree(r.dev); r.dev = nullptr; }
+          done = true;
+        } else if (r.done_ev && hipEventQuery(r.done_ev) == hipSuccess) {
+          done = true;
+        }
+        if (done) {
+          r.t_done = now_s();
+          r.state = r.status == CM_OK ? Request::DONE : Request::FAILED;
+          srv->in_flight -= r.footprint;
+          srv->slot_busy[r.slot] = 0;
+          srv->n_running--;
+          if (r.done_ev) { (void)hipEventDestroy(r.done_ev); r.done_ev = nullptr; }
+          srv->cv.notify_all();
+        }
+      }
+      if (srv->pending.empty() && srv->n_running == 0)
+        srv->cv.wait_for(lk, std::chrono::milliseconds(2));
+    }
+    std::this_thread::sleep_for(std::chrono::microseconds(100));
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+cm_status cm_server_create(cm_context* ctx, uint64_t hbm_budget_bytes, int32_t n_streams, cm_server** out) {
+  if (!ctx || !out || n_streams < 1 || n_streams > 32 || hbm_budget_bytes == 0) return CM_ERR_INVALID_ARG;
+  hipSetDevice(ctx->device);
+  cm_server* srv = new cm_server();
+  srv->ctx = ctx;
+  srv->budget = hbm_budget_bytes;
+  srv->n_slots = n_streams;
+  srv->streams.resize(n_streams);
+  srv->slot_busy.assign(n_streams, 0);
+  for (auto& s : srv->streams) {
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+      delete srv;
+      return cm_fail(ctx, CM_ERR_DEVICE, "server stream");
+    }
+  }
+  ctx->servers++;
+  srv->worker = std::thread(worker_loop, srv);
+  *out = srv;
+  return CM_OK;
+}
+
+cm_status cm_server_submit(cm_server* srv, const cm_request* q, uint64_t* ticket) {
+  if (!srv || !q || !ticket) return CM_ERR_INVALID_ARG;
+  if (q->n_scenes < 0 || q->n_bodies < 0 || (q->n_scenes > 0 && (!q->body_offsets || !q->body_geom || !q->pose)))
+    return CM_ERR_INVALID_ARG;
+  if (q->params.K < 1 || q->params.K > CM_MAX_K || !(q->params.tau > 0.f) || q->params.flags != 0)
+    return CM_ERR_INVALID_ARG;
+  auto r = std::make_unique<Request>();
+  r->n_scenes = q->n_scenes;
+  r->n_bodies = q->n_bodies;
+  r->body_offsets.assign(q->body_offsets, q->body_offsets + q->n_scenes + 1);
+  r->body_geom.assign(q->body_geom, q->body_geom + q->n_bodies);
+  r->pose.assign(q->pose, q->pose + 7 * size_t(q->n_bodies));
+  const int32_t G = int32_t(srv->ctx->h.recs.size());
+  for (int32_t g : r->body_geom)
+    if (g < 0 || g >= G) return CM_ERR_NOT_FOUND;
+  long long ncand = 0;
+  for (int s = 0; s < q->n_scenes; ++s) {
+    const long long nb = r->body_offsets[s + 1] - r->body_offsets[s];
+    if (nb < 0 || r->body_offsets[s + 1] > q->n_bodies) return CM_ERR_INVALID_ARG;
+    ncand += nb * (nb - 1) / 2;
+  }
+  r->capacity = q->capacity > 0 ? q->capacity : int32_t(std::min<long long>(ncand, 1LL << 30));
+  r->params = q->params;
+  r->want_bwd = q->want_backward != 0;
+  const int K = q->params.K;
+  const size_t cap = size_t(std::max(r->capacity, 1));
+  if (r->want_bwd && q->cot_dist) r->cot_dist.assign(q->cot_dist, q->cot_dist + cap * K);
+  if (r->want_bwd && q->cot_normal) r->cot_normal.assign(q->cot_normal, q->cot_normal + 3 * cap * K);
+  // footprint with the grid this request will use
+  FwdLaunch f;
+  f.tb = ctx_tables(srv->ctx);
+  f.maxV = std::max(srv->ctx->maxV, 1); f.maxE = std::max(srv->ctx->maxE, 1); f.maxF = std::max(srv->ctx->maxF, 1);
+  f.block = 256; f.kmax = kmax_for(K); f.queue = nullptr;
+  const long long grid = std::max(1, fwd_occupancy(f) * srv->ctx->num_cus / std::max(1, srv->n_slots));
+  r->footprint = footprint(srv->ctx, *r, grid, fwd_scratch_floats(f.maxV, f.maxE));
+  if (r->footprint > srv->budget) return cm_fail(srv->ctx, CM_ERR_REJECTED, "request exceeds the HBM budget");
+  if (hipHostMalloc(reinterpret_cast<void**>(&r->h_n_pairs), 4) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&r->h_offsets), 4 * size_t(r->n_scenes + 1)) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&r->h_pairs), 8 * cap) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&r->h_out), 32 * cap * K) != hipSuccess ||
+      (r->want_bwd && hipHostMalloc(reinterpret_cast<void**>(&r->h_gpose), 24 * size_t(std::max(r->n_bodies, 1))) != hipSuccess))
+    return CM_ERR_OOM;
+  r->t_submit = now_s();
+  std::lock_guard<std::mutex> lk(srv->mu);
+  r->ticket = srv->next_ticket++;
+  *ticket = r->ticket;
+  srv->pending.push_back(r->ticket);
+  srv->reqs[r->ticket] = std::move(r);
+  srv->cv.notify_all();
+  return CM_OK;
+}
+
+cm_status cm_server_poll(cm_server* srv, uint64_t ticket, cm_result* out) {
+  if (!srv || !out) return CM_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(srv->mu);
+  auto it = srv->reqs.find(ticket);
+  if (it == srv->reqs.end()) return CM_ERR_NOT_FOUND;
+  Request& r = *it->second;
+  if (r.state == Request::PENDING || r.state == Request::RUNNING) return CM_ERR_NOT_READY;
+  const size_t cap = size_t(std::max(r.capacity, 1));
+  const int K = r.params.K;
+  out->status = r.status;
+  out->n_pairs = *r.h_n_pairs;
+  out->capacity = r.capacity;
+  out->pair_offsets = r.h_offsets;
+  out->pairs = r.h_pairs;
+  out->point = r.h_out;
+  out->normal = r.h_out + 3 * cap * K;
+  out->dist = r.h_out + 6 * cap * K;
+  out->weight = r.h_out + 7 * cap * K;
+  out->g_pose = r.h_gpose;
+  out->t_submit = r.t_submit;
+  out->t_start = r.t_start;
+  out->t_done = r.t_done;
+  out->footprint_bytes = r.footprint;
+  return r.status == CM_OK && *r.h_n_pairs > r.capacity ? CM_ERR_CAPACITY : r.status;
+}
+
+cm_status cm_server_release(cm_server* srv, uint64_t ticket) {
+  if (!srv) return CM_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(srv->mu);
+  auto it = srv->reqs.find(ticket);
+  if (it == srv->reqs.end()) return CM_ERR_NOT_FOUND;
+  Request& r = *it->second;
+  if (r.state == Request::PENDING || r.state == Request::RUNNING) return CM_ERR_NOT_READY;
+  (void)hipHostFree(r.h_n_pairs); (void)hipHostFree(r.h_offsets); (void)hipHostFree(r.h_pairs);
+  (void)hipHostFree(r.h_out);
+  if (r.h_gpose) (void)hipHostFree(r.h_gpose);
+  srv->reqs.erase(it);
+  return CM_OK;
+}
+
+cm_status cm_server_stats(cm_server* srv, uint64_t* in_flight_bytes, int32_t* n_pending, int32_t* n_running) {
+  if (!srv) return CM_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(srv->mu);
+  if (in_flight_bytes) *in_flight_bytes = srv->in_flight;
+  if (n_pending) *n_pending = int32_t(srv->pending.size());
+  if (n_running) *n_running = srv->n_running;
+  return CM_OK;
+}
+
+cm_status cm_server_destroy(cm_server* srv) {
+  if (!srv) return CM_ERR_INVALID_ARG;
+  {
+    // drain: wait for every admitted or pending request to finish
+    std::unique_lock<std::mutex> lk(srv->mu);
+    srv->cv.wait(lk, [&] { return srv->pending.empty() && srv->n_running == 0; });
+  }
+  srv->stop.store(true);
+  srv->cv.notify_all();
+  if (srv->worker.joinable()) srv->worker.join();
+  for (auto& s : srv->streams) (void)hipStreamDestroy(s);
+  srv->ctx->servers--;
+  for (auto& kv : srv->reqs) {
+    Request& r = *kv.second;
+    (void)hipHostFree(r.h_n_pairs); (void)hipHostFree(r.h_offsets); (void)hipHostFree(r.h_pairs);
+    (void)hipHostFree(r.h_out);
+    if (r.h_gpose) (void)hipHostFree(r.h_gpose);
+  }
+  delete srv;
+  return CM_OK;
+}
+
+}  // extern "C"
