@@ -9,13 +9,22 @@ Default workload: 65,536 scenes x 8 bodies (2 spheres, 2 capsules, 2 rounded
 boxes, 2 convex polytopes of 32 points), all 28 pairs per scene are
 candidates, tau = 0.005, K = 8.
 
-Prints ONE JSON line (see the repository's measurement notes for the fields).
+Legs, all in one process on the same inputs:
+  plain     cm_collide (broadphase + one forward pair kernel)
+  fused     cm_collide_fused (cost-ordered work queue, replayed hipGraph)
+  fwd_bwd   cm_collide + cm_collide_backward with random cotangents
+  serving   a short Poisson request stream through cm_server_* (p50 / p99)
+The headline value is the forward throughput of --path (fused by default).
+
+Prints ONE JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -24,6 +33,10 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
+
+METRIC = "geom-pair contact evals/s (fwd, fwd+bwd) vs plain kernel; p50/p99 query latency"
+FWD_KERNEL = "collide_fwd"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "collide_fwd_mixed65536_traffic.md")
 
 
 def log(msg):
@@ -52,27 +65,117 @@ def build_workload(name: str, scenes: int | None):
     return b, desc
 
 
+def source_hash() -> str:
+    """Hash of the kernel sources (a stored traffic figure is void once they change)."""
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2602_20304_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".cuh", ".h")):
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(workload: str):
+    """HBM bytes per forward launch from the committed PMC summary, or None
+    when it is absent, for another workload, or taken on other sources."""
+    if workload != "mixed" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    txt = open(TRAFFIC_FILE).read()
+    m_hash = re.search(r"source_hash:\s*([0-9a-f]+)", txt)
+    m_bytes = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m_hash or not m_bytes or m_hash.group(1) != source_hash():
+        return None
+    return float(m_bytes.group(1))
+
+
 def cpu_baseline(batch, budget_s: float):
-    """Time the FP64 oracle on the host for a bounded prefix of the scenes."""
+    """Time the FP64 oracle on the host over whole scenes in scene order until
+    the time budget is spent."""
     import torch
-    import workloads as W
     from oracle import cm_oracle as O
-    pairs, _ = O.broadphase(batch)
+    pairs, offsets = O.broadphase(batch)
     cache = O.GeomCache(batch.geoms)
+    threads = int(torch.get_num_threads())
     t0 = time.perf_counter()
     done = 0
+    scenes = 0
     with torch.no_grad():
-        for i in range(pairs.shape[1]):
-            a, b = int(pairs[0, i]), int(pairs[1, i])
-            O.collide_pair(cache[batch.body_geom[a]], batch.pose[:, a], cache[batch.body_geom[b]], batch.pose[:, b],
-                           batch.tau, batch.K)
-            done += 1
+        for s in range(batch.n_scenes):
+            for i in range(int(offsets[s]), int(offsets[s + 1])):
+                a, b = int(pairs[0, i]), int(pairs[1, i])
+                O.collide_pair(cache[batch.body_geom[a]], batch.pose[:, a], cache[batch.body_geom[b]],
+                               batch.pose[:, b], batch.tau, batch.K)
+                done += 1
+            scenes += 1
             if time.perf_counter() - t0 > budget_s:
                 break
     dt = time.perf_counter() - t0
-    return dict(value=done / dt, unit="pairs/s", cores=int(torch.get_num_threads()), kind="oracle",
-                sample=f"first {done} kept pairs of the same workload in pair order ({dt:.1f} s, FP64 oracle, "
-                       f"geometry build excluded)")
+    return dict(value=done / dt, unit="pairs/s", cores=threads, kind="oracle",
+                sample=f"first {scenes} scenes ({done} kept pairs) of the same workload, FP64 oracle, "
+                       f"{dt:.1f} s wall, torch intra-op threads={threads}, mesh builds excluded")
+
+
+def serving_leg(ctx_cls, n_requests: int, seed: int = 11):
+    """Short Poisson stream through the serving loop; returns latency stats."""
+    import workloads as W
+    from paper_2602_20304_amd.cm import Server
+    ctx = ctx_cls(0)
+    pool = W.polytope_pool(64, seed=1, n_points=64)
+    ids = ctx.create_geometry(pool)
+    tau, K = 0.01, 8
+    reqs = W.serving_requests(n_requests=n_requests, seed=seed, rate_hz=40.0, env_min=256, env_max=4096,
+                              bodies_min=2, bodies_max=6, pool_size=64)
+    rng = np.random.default_rng(seed)
+    payload = []
+    for q in reqs:
+        nbe = np.diff(q.body_offsets.astype(np.int64))
+        cap = int((nbe * (nbe - 1) // 2).sum())
+        cd = cn = None
+        if q.want_bwd:
+            cd = rng.standard_normal(cap * K).astype(np.float32)
+            cn = rng.standard_normal(3 * cap * K).astype(np.float32)
+        payload.append((q, cd, cn, cap))
+    srv = Server(ctx, 64 << 30, n_streams=4)
+    tickets = []
+    t0 = time.perf_counter()
+    for q, cd, cn, _ in payload:
+        wait = q.arrival_s - (time.perf_counter() - t0)
+        if wait > 0:
+            time.sleep(wait)
+        tickets.append(srv.submit(q.body_offsets, ids[q.body_geom], q.pose, tau, K, q.want_bwd, cd, cn))
+    done = {}
+    while len(done) < len(tickets):
+        for t in tickets:
+            if t not in done:
+                r = srv.poll(t)
+                if r is not None:
+                    if r["status"] != 0:
+                        raise RuntimeError(f"request {t} failed with status {r['status']}")
+                    done[t] = (r["t_submit"], r["t_start"], r["t_done"], r["n_pairs"])
+                    srv.release(t)
+        time.sleep(0.001)
+    wall = time.perf_counter() - t0
+    srv.close()
+    lat = np.array([d[2] - d[0] for d in done.values()])
+    pairs = sum(d[3] for d in done.values())
+    return dict(requests=len(tickets), p50_ms=float(np.percentile(lat, 50) * 1e3),
+                p99_ms=float(np.percentile(lat, 99) * 1e3), pairs_per_s=pairs / wall, wall_s=wall,
+                config=f"{n_requests} Poisson requests at 40/s, 256-4096 envs (log-uniform), 2-6 bodies/env "
+                       f"from a resident pool of 64 hull-of-64 polytopes, fwd or fwd+bwd 50/50, tau={tau}, K={K}, "
+                       f"4 streams, 64 GiB budget")
+
+
+def copy_calibration(n_bytes: int, reps: int):
+    """Plain device copy of a known size (for scaling PMC byte counters)."""
+    import torch
+    n = n_bytes // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read": 4 * n, "bytes_written": 4 * n, "reps": reps}), flush=True)
 
 
 def main():
@@ -85,12 +188,22 @@ def main():
     ap.add_argument("--path", default="fused", choices=["plain", "fused"])
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-bwd", action="store_true")
+    ap.add_argument("--serve", type=int, default=24, help="requests in the serving leg (0 = skip)")
+    ap.add_argument("--only", default=None, choices=[None, "plain", "fused", "fwd_bwd"],
+                    help="run one leg only (for profiling)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of this many MiB (PMC byte calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "this implementation runs on exactly one GPU; --gpus must be 1"}), flush=True)
         raise SystemExit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration << 20, 5)
+        return
 
     import torch
+    import workloads as W
     from paper_2602_20304_amd.cm import Context, Manifold
     from paper_2602_20304_amd import opmodel
 
@@ -105,41 +218,77 @@ def main():
     out = Manifold.empty(db.n_scenes, cap, batch.K, ctx.device)
     log(f"geometry build {t_geom:.1f}s; {batch.n_bodies} bodies, {cap} candidate pairs")
     stream = torch.cuda.current_stream()
+    cot_d = cot_n = None
+    if not args.no_bwd:
+        a, b = W.cotangents(cap, batch.K, seed=1)
+        cot_d = torch.as_tensor(a).to(ctx.device)
+        cot_n = torch.as_tensor(b).to(ctx.device)
 
-    def step(path):
-        ctx.collide(db, batch.tau, batch.K, out=out, fused=(path == "fused"), stream=stream)
+    def step(leg):
+        ctx.collide(db, batch.tau, batch.K, out=out, fused=(leg == "fused"), stream=stream)
+        if leg == "fwd_bwd":
+            ctx.collide_backward(db, out, batch.tau, batch.K, None, cot_n, cot_d, None, stream=stream)
 
+    legs = ["plain", "fused"] + ([] if args.no_bwd else ["fwd_bwd"])
+    if args.only:
+        legs = [args.only]
     results = {}
-    for path in ("plain", "fused"):
+    kernel = {}
+    for leg in legs:
         for _ in range(args.warmup):
-            step(path)
+            step(leg)
         torch.cuda.synchronize()
         ctx.check_errors()
+        ctx.set_kernel_timing(True)
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         ev0.record(stream)
         for _ in range(args.steps):
-            step(path)
+            step(leg)
         ev1.record(stream)
         torch.cuda.synchronize()
         ms = ev0.elapsed_time(ev1) / args.steps
+        kernel[leg] = {t: ctx.kernel_time(t) for t in ("broadphase", "forward", "backward", "fused")}
+        ctx.set_kernel_timing(False)
+        ctx.check_errors()
         n_pairs = int(out.n_pairs.item())
-        results[path] = dict(ms=ms, n_pairs=n_pairs)
-        log(f"{path}: {ms:.3f} ms/step, {n_pairs} kept pairs, {n_pairs / (ms * 1e-3):.4g} pairs/s")
-    ctx.check_errors()
+        results[leg] = dict(ms=ms, n_pairs=n_pairs)
+        log(f"{leg}: {ms:.3f} ms/step, {n_pairs} kept pairs, {n_pairs / (ms * 1e-3):.4g} pairs/s; "
+            + ", ".join(f"{k} {v[0] / max(v[1], 1):.3f} ms x{v[1]}" for k, v in kernel[leg].items() if v[1]))
 
-    main_path = args.path
-    ms = results[main_path]["ms"]
-    n_pairs = results[main_path]["n_pairs"]
-    pairs = out.pairs[:, :n_pairs].cpu().numpy()
+    main_leg = args.path if args.path in results else legs[0]
+    ms = results[main_leg]["ms"]
+    n_pairs = results[main_leg]["n_pairs"]
+    kept = min(n_pairs, cap)
+    pairs = out.pairs[:, :kept].cpu().numpy()
     G = ctx.geometry_count
     sizes = np.array([[ctx.geometry_info(int(g))[k] for k in ("type", "n_vertices", "n_edges", "n_faces")]
                       for g in range(G)], dtype=np.int64)
     body_geom = ids[batch.body_geom]
     ops = opmodel.batch_ops(sizes[:, 0], sizes[:, 1], sizes[:, 2], sizes[:, 3], pairs[0], pairs[1], body_geom)
-    roof = opmodel.roofline(ops, ms * 1e-3)
+
+    # roofline of the dominant kernel: the forward pair kernel, timed with HIP
+    # events on its own stream during the plain leg (one launch = all kept pairs)
+    roof_leg = "plain" if "plain" in kernel else main_leg
+    k_ms, k_n = kernel[roof_leg]["forward"]
+    roofline = None
+    if k_n:
+        kms = k_ms / k_n
+        roof = opmodel.roofline(ops, kms * 1e-3)
+        traffic = stored_traffic(args.workload)
+        roofline = {"bound": "alu", "kernel": FWD_KERNEL, "achieved": roof["achieved_flops"] / 1e12,
+                    "peak": roof["peak_flops"] / 1e12, "unit": "TFLOP/s", "frac": roof["frac"],
+                    "traffic": traffic, "kernel_ms": kms, "launches": k_n,
+                    "ops_per_launch": {"fma": int(ops[0]), "alu": int(ops[1]), "trans": int(ops[2])}}
+
+    legs_out = {}
+    for k, v in results.items():
+        legs_out[k] = {"ms_per_step": v["ms"], "pairs_per_s": v["n_pairs"] / (v["ms"] * 1e-3)}
+        for t, (tms, tn) in kernel[k].items():
+            if tn:
+                legs_out[k][f"{t}_kernel_ms"] = tms / tn
     line = {
-        "metric": "geom-pair contact evals/s (fwd)",
+        "metric": METRIC,
         "value": n_pairs / (ms * 1e-3),
         "unit": "pairs/s",
         "n_gpus": 1,
@@ -152,14 +301,20 @@ def main():
         "dtype": "f64+f32",
         "data": "synthetic",
         "config": {"workload": desc, "scenes": batch.n_scenes, "candidate_pairs": cap, "kept_pairs": n_pairs,
-                   "tau": batch.tau, "K": batch.K, "path": main_path, "parallelism": "single-gpu"},
-        "paths": {k: {"ms_per_step": v["ms"], "pairs_per_s": v["n_pairs"] / (v["ms"] * 1e-3)}
-                  for k, v in results.items()},
-        "roofline": {"bound": "alu", "achieved": roof["achieved_flops"] / 1e12, "peak": roof["peak_flops"] / 1e12,
-                     "unit": "TFLOP/s", "frac": roof["frac"], "traffic": None,
-                     "ops_per_step": {"fma": int(ops[0]), "alu": int(ops[1]), "trans": int(ops[2])}},
+                   "tau": batch.tau, "K": batch.K, "path": main_leg, "parallelism": "single-gpu"},
+        "legs": legs_out,
+        "roofline": roofline,
     }
-    if not args.no_cpu_baseline:
+    if "fwd_bwd" in results:
+        v = results["fwd_bwd"]
+        line["fwd_bwd_pairs_per_s"] = v["n_pairs"] / (v["ms"] * 1e-3)
+    if "plain" in results and main_leg != "plain":
+        line["speedup_vs_plain"] = results["plain"]["ms"] / ms
+    if args.serve and not args.only:
+        log(f"serving leg: {args.serve} requests ...")
+        line["serving"] = serving_leg(Context, args.serve)
+        log(f"serving: p50 {line['serving']['p50_ms']:.1f} ms, p99 {line['serving']['p99_ms']:.1f} ms")
+    if not args.no_cpu_baseline and not args.only:
         log("timing the FP64 oracle on the host ...")
         line["cpu_baseline"] = cpu_baseline(batch, args.cpu_budget)
     print(json.dumps(line), flush=True)

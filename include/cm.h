@@ -184,7 +184,7 @@ cm_status cm_collide_fused(cm_context* ctx, const cm_batch* batch, const cm_para
 
 /* ---------------------------------------------------------------- backward
  * Vector-Jacobian product of the manifold (the gradient the paper obtains by
- * automatic differentiation, Sec. V-C): recomputes every per-pair
+ * automatic differentiation and times in Sec. V): recomputes every per-pair
  * intermediate from the inputs and the kept-pair list in `fwd` (no E x E
  * state is stored by the forward), then reverses the SoftSort, the
  * activity/score terms, the nearest-neighbour softmaxes, the SDF queries,
@@ -228,6 +228,19 @@ typedef struct {
   double t_submit, t_start, t_done;   /* seconds, server clock */
   uint64_t footprint_bytes;
 } cm_result;
+
+/* ---------------------------------------------------------------- timing
+ * Opt-in kernel timing for measurement.  While enabled, every cm_collide /
+ * cm_collide_fused / cm_collide_backward call records a pair of HIP events on
+ * the caller's stream around each timed unit: CM_TIMER_BROADPHASE (broadphase
+ * and compaction), CM_TIMER_FORWARD (the forward pair kernel),
+ * CM_TIMER_BACKWARD (the adjoint kernel), CM_TIMER_FUSED (one replay of the
+ * fused graph).  cm_kernel_time waits for the recorded events and returns the
+ * summed milliseconds and the number of timed launches since timing was
+ * enabled.  Enabling resets the sums.  Not for use under stream capture. */
+enum { CM_TIMER_BROADPHASE = 0, CM_TIMER_FORWARD = 1, CM_TIMER_BACKWARD = 2, CM_TIMER_FUSED = 3, CM_N_TIMERS = 4 };
+cm_status cm_set_kernel_timing(cm_context* ctx, int32_t enable);
+cm_status cm_kernel_time(cm_context* ctx, int32_t timer, double* total_ms, int64_t* launches);
 
 cm_status cm_server_create(cm_context* ctx, uint64_t hbm_budget_bytes, int32_t n_streams, cm_server** out);
 cm_status cm_server_submit(cm_server* srv, const cm_request* req, uint64_t* ticket);

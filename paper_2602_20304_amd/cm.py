@@ -193,6 +193,18 @@ class Context:
     def check_errors(self, stream=None):
         self._check(self.lib.cm_check_errors(self.h, _stream_handle(stream)))
 
+    # -------------------------------------------------------------- timing
+    def set_kernel_timing(self, enable: bool):
+        """Record HIP events around every timed launch (resets the sums)."""
+        self._check(self.lib.cm_set_kernel_timing(self.h, 1 if enable else 0))
+
+    def kernel_time(self, timer: str):
+        """(summed milliseconds, launches) of one timer since timing was enabled."""
+        ms = C.c_double(0.0)
+        n = C.c_int64(0)
+        self._check(self.lib.cm_kernel_time(self.h, L.TIMERS[timer], C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
     # ------------------------------------------------------------- forward
     def collide(self, db: DeviceBatch, tau: float, K: int, capacity: Optional[int] = None, out: Manifold = None,
                 fused: bool = False, stream=None, lambda_reg=-1.0, eps_n=-1.0, cull_margin=-1.0) -> Manifold:

@@ -326,11 +326,79 @@ extern "C" cm_status cm_collide(cm_context* ctx, const cm_batch* batch, const cm
   if ((s = resolve_out(ctx, out, &od)) != CM_OK) return s;
   hipSetDevice(ctx->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
+  hipEvent_t t0 = timer_begin(ctx, st);
   if ((s = ctx_broadphase(ctx, bd, pd, od, st)) != CM_OK) return s;
+  timer_end(ctx, CM_TIMER_BROADPHASE, t0, st);
   if (od.capacity == 0) return CM_OK;
   FwdLaunch f;
   if ((s = ctx_prepare_fwd(ctx, bd, pd, od, 256, false, &f)) != CM_OK) return s;
-  return cm_hip(ctx, launch_collide_fwd(f, st), "collide launch");
+  t0 = timer_begin(ctx, st);
+  if ((s = cm_hip(ctx, launch_collide_fwd(f, st), "collide launch")) != CM_OK) return s;
+  timer_end(ctx, CM_TIMER_FORWARD, t0, st);
+  return CM_OK;
+}
+
+hipEvent_t timer_begin(cm_context* ctx, hipStream_t st) {
+  if (!ctx->timing) return nullptr;
+  hipEvent_t ev = nullptr;
+  if (!ctx->spare_events.empty()) {
+    ev = ctx->spare_events.back();
+    ctx->spare_events.pop_back();
+  } else if (hipEventCreate(&ev) != hipSuccess) {
+    return nullptr;
+  }
+  if (hipEventRecord(ev, st) != hipSuccess) {
+    ctx->spare_events.push_back(ev);
+    return nullptr;
+  }
+  return ev;
+}
+
+void timer_end(cm_context* ctx, int timer, hipEvent_t start, hipStream_t st) {
+  if (!start) return;
+  hipEvent_t ev = timer_begin(ctx, st);
+  if (!ev) {
+    ctx->spare_events.push_back(start);
+    return;
+  }
+  ctx->timers[timer].pending.push_back({start, ev});
+}
+
+extern "C" cm_status cm_set_kernel_timing(cm_context* ctx, int32_t enable) {
+  if (!ctx) return CM_ERR_INVALID_ARG;
+  hipSetDevice(ctx->device);
+  for (auto& t : ctx->timers) {
+    for (auto& pr : t.pending) {
+      (void)hipEventSynchronize(pr.second);
+      ctx->spare_events.push_back(pr.first);
+      ctx->spare_events.push_back(pr.second);
+    }
+    t.pending.clear();
+    t.ms = 0.0;
+    t.launches = 0;
+  }
+  ctx->timing = enable != 0;
+  return CM_OK;
+}
+
+extern "C" cm_status cm_kernel_time(cm_context* ctx, int32_t timer, double* total_ms, int64_t* launches) {
+  if (!ctx || timer < 0 || timer >= CM_N_TIMERS) return CM_ERR_INVALID_ARG;
+  hipSetDevice(ctx->device);
+  auto& t = ctx->timers[timer];
+  for (auto& pr : t.pending) {
+    hipError_t e = hipEventSynchronize(pr.second);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, pr.first, pr.second);
+    if (e != hipSuccess) return cm_hip(ctx, e, "kernel timing");
+    t.ms += ms;
+    t.launches += 1;
+    ctx->spare_events.push_back(pr.first);
+    ctx->spare_events.push_back(pr.second);
+  }
+  t.pending.clear();
+  if (total_ms) *total_ms = t.ms;
+  if (launches) *launches = t.launches;
+  return CM_OK;
 }
 
 extern "C" cm_status cm_collide_backward(cm_context* ctx, const cm_batch* batch, const cm_params* prm,
@@ -373,5 +441,8 @@ extern "C" cm_status cm_collide_backward(cm_context* ctx, const cm_batch* batch,
   if ((e = ctx_ensure(ctx, reinterpret_cast<void**>(&ctx->d_scratch), &ctx->scratch_cap, need)) != hipSuccess)
     return cm_hip(ctx, e, "backward scratch");
   b.f.scratch = ctx->d_scratch;
-  return cm_hip(ctx, launch_collide_bwd(b, st), "backward launch");
+  hipEvent_t t0 = timer_begin(ctx, st);
+  if ((s = cm_hip(ctx, launch_collide_bwd(b, st), "backward launch")) != CM_OK) return s;
+  timer_end(ctx, CM_TIMER_BACKWARD, t0, st);
+  return CM_OK;
 }

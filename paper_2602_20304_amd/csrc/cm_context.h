@@ -67,6 +67,15 @@ struct cm_context {
     graphs.clear();
   }
   std::string last_error;
+  // opt-in event timing (cm_set_kernel_timing)
+  struct Timer {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+    double ms = 0.0;
+    long long launches = 0;
+  };
+  bool timing = false;
+  Timer timers[CM_N_TIMERS];
+  std::vector<hipEvent_t> spare_events;
 
   void release_all() {
     auto F = [](void* p) { if (p) hipFree(p); };
@@ -74,6 +83,12 @@ struct cm_context {
     F(d.f0); F(d.f1); F(d.f2);
     F(d_err); F(d_tile_sums); F(d_scratch); F(d_work); F(d_bwd); F(d_fused);
     drop_graphs();
+    for (auto& t : timers) {
+      for (auto& pr : t.pending) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
+      t.pending.clear();
+    }
+    for (auto ev : spare_events) (void)hipEventDestroy(ev);
+    spare_events.clear();
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     cap_stream = nullptr;
     d = CmDevPools();
@@ -91,3 +106,7 @@ cm_status resolve_out(cm_context* ctx, const cm_manifold* o, cm::OutDev* od);
 cm_status ctx_broadphase(cm_context* ctx, const cm::BatchDev& bd, const cm::ParamsDev& pd, const cm::OutDev& od,
                          hipStream_t st);
 int kmax_for(int K);
+// Timing brackets: begin returns the start event (or null when timing is off)
+// and end records the stop event and queues the pair for cm_kernel_time.
+hipEvent_t timer_begin(cm_context* ctx, hipStream_t st);
+void timer_end(cm_context* ctx, int timer, hipEvent_t start, hipStream_t st);

@@ -159,7 +159,12 @@ extern "C" cm_status cm_collide_fused(cm_context* ctx, const cm_batch* batch, co
   double dv[4] = {pd.tau, pd.lam, pd.eps_n, double(pd.margin)};
   for (double d : dv) { uint64_t b; std::memcpy(&b, &d, 8); key = mix(key, b); }
   for (auto& g : ctx->graphs)
-    if (g.key == key) return cm_hip(ctx, hipGraphLaunch(g.exec, st), "graph replay");
+    if (g.key == key) {
+      hipEvent_t t0 = timer_begin(ctx, st);
+      if ((s = cm_hip(ctx, hipGraphLaunch(g.exec, st), "graph replay")) != CM_OK) return s;
+      timer_end(ctx, CM_TIMER_FUSED, t0, st);
+      return CM_OK;
+    }
 
   if (!ctx->cap_stream && (e = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking)) != hipSuccess)
     return cm_hip(ctx, e, "capture stream");
@@ -179,5 +184,8 @@ extern "C" cm_status cm_collide_fused(cm_context* ctx, const cm_batch* batch, co
     ctx->graphs.erase(ctx->graphs.begin());
   }
   ctx->graphs.push_back({key, exec});
-  return cm_hip(ctx, hipGraphLaunch(exec, st), "graph launch");
+  hipEvent_t t0 = timer_begin(ctx, st);
+  if ((s = cm_hip(ctx, hipGraphLaunch(exec, st), "graph launch")) != CM_OK) return s;
+  timer_end(ctx, CM_TIMER_FUSED, t0, st);
+  return CM_OK;
 }
