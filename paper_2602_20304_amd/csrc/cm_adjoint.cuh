@@ -159,13 +159,13 @@ struct Twist {
   double r[3], w[3];
 };
 
-// Adjoint of an SDF query of body V at pair-frame point x.  For body B
-// (not ident) the query moves with B: its placement twist receives
-// rho -= x_bar, omega += g x g_bar - x x x_bar.
-template <bool WAVE>
+// Adjoint of an SDF query of body V at pair-frame point x.  IDENT: the body
+// is A (pair frame).  For body B the query moves with B: its placement twist
+// receives rho -= x_bar, omega += g x g_bar - x x x_bar.
+template <bool WAVE, bool IDENT>
 __device__ __forceinline__ D3 sdf_body_bwd(const BodyView& V, const D3& x, double phib, const D3& gb, const Temp& T,
                                            const BodySink& sink, double& taub, Twist& tw) {
-  if (V.ident) {
+  if (IDENT) {
     D3 g;
     return sdf_local_bwd<WAVE>(V.type, V.p, V.planes, V.nf, x, phib, gb, T, sink, taub, g);
   }

@@ -250,6 +250,9 @@ cm_status resolve_params(cm_context* ctx, const cm_params* prm, ParamsDev* pd) {
   if (prm->K < 1 || prm->K > CM_MAX_K) return cm_fail(ctx, CM_ERR_INVALID_ARG, "K must be in 1..32");
   if (prm->flags != 0) return cm_fail(ctx, CM_ERR_INVALID_ARG, "flags must be 0");
   pd->tau = double(prm->tau);
+  pd->inv_tau = 1.0 / pd->tau;
+  pd->c_log2 = kLog2e / pd->tau;
+  pd->tl = pd->tau * kLn2;
   pd->lam = prm->lambda_reg < 0.f ? 0.01 : double(prm->lambda_reg);
   if (!(pd->lam > 0.0)) return cm_fail(ctx, CM_ERR_INVALID_ARG, "lambda_reg must be > 0");
   pd->eps_n = prm->eps_n < 0.f ? pd->tau * pd->tau : double(prm->eps_n);

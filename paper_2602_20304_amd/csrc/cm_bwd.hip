@@ -222,12 +222,12 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
       int k = 0, l = 0, wit = 0;
       if (is_vs) {
         const bool ofA = idx < nvA;
-        const D3 x = ofA ? P.vertex(*P.GA, idx, A) : P.vertex(*P.GB, idx - nvA, B);
-        const BodyView& O = ofA ? B : A;
+        const D3 x = ofA ? P.template vertex<true>(*P.GA, idx, A) : P.template vertex<false>(*P.GB, idx - nvA, B);
         const double sgn = ofA ? -1.0 : 1.0;
         double phi;
         D3 g;
-        sdf_body<true>(O, x, T, phi, g);
+        if (ofA) sdf_body<true, false>(B, x, T, phi, g);
+        else sdf_body<true, true>(A, x, T, phi, g);
         const double q = T.tau + dot(g, g), in = 1.0 / sqrt(q);
         const double lw = lsig(-phi, T), w = exp(lw);
         const double dtot = fb[6] - sb, lwb = T.tau * sb + w * fb[7];
@@ -260,10 +260,10 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
         const D3 nb = scl(de, rho);
         double phiB1, phiA2, dum;
         D3 gA, gB, dg;
-        sdf_body<false>(B, e1, T, phiB1, dg);
-        sdf_body<true>(A, e1, T, dum, gA);
-        sdf_body<false>(A, e2, T, phiA2, dg);
-        sdf_body<true>(B, e2, T, dum, gB);
+        sdf_body<false, false>(B, e1, T, phiB1, dg);
+        sdf_body<true, true>(A, e1, T, dum, gA);
+        sdf_body<false, true>(A, e2, T, phiA2, dg);
+        sdf_body<true, false>(B, e2, T, dum, gB);
         const double u1 = dot(gB, nb), u2 = -dot(gA, nb), ucl = -dot(gA, gB);
         const double gam1 = tanh64(u1, T), gam2 = tanh64(u2, T);
         const double gam = wit ? gam2 : gam1;
@@ -307,10 +307,10 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
         gbar[3] = gBb;
       }
       // ---- stage 2: SDF adjoints, every lane of the wave together
-      const D3 xb0 = sdf_body_bwd<true>(A, X[0], phib[0], gbar[0], T, sinkA, taub, tw);
-      const D3 xb1 = sdf_body_bwd<true>(B, X[1], phib[1], gbar[1], T, sinkB, taub, tw);
-      const D3 xb2 = sdf_body_bwd<true>(A, X[2], phib[2], gbar[2], T, sinkA, taub, tw);
-      const D3 xb3 = sdf_body_bwd<true>(B, X[3], phib[3], gbar[3], T, sinkB, taub, tw);
+      const D3 xb0 = sdf_body_bwd<true, true>(A, X[0], phib[0], gbar[0], T, sinkA, taub, tw);
+      const D3 xb1 = sdf_body_bwd<true, false>(B, X[1], phib[1], gbar[1], T, sinkB, taub, tw);
+      const D3 xb2 = sdf_body_bwd<true, true>(A, X[2], phib[2], gbar[2], T, sinkA, taub, tw);
+      const D3 xb3 = sdf_body_bwd<true, false>(B, X[3], phib[3], gbar[3], T, sinkB, taub, tw);
       if (!live) return;
       // ---- stage 3: back to vertices / edges
       if (is_vs) {
@@ -409,7 +409,7 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
       D3 gb = d3(V[v], V[maxV + v], V[2 * maxV + v]);   // pair frame
       const D3 lv = d3(tb.vx[G.v_off + v], tb.vy[G.v_off + v], tb.vz[G.v_off + v]);
       if (!isA) {
-        const D3 x = P.vertex(G, v, B);
+        const D3 x = P.template vertex<false>(G, v, B);
         const D3 c = cross(x, gb);
         tw.r[0] += gb.x; tw.r[1] += gb.y; tw.r[2] += gb.z;
         tw.w[0] += c.x; tw.w[1] += c.y; tw.w[2] += c.z;

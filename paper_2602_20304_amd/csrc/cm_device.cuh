@@ -17,8 +17,6 @@
 
 namespace cm {
 
-constexpr double kLog2e = 1.4426950408889634;
-constexpr double kLn2 = 0.6931471805599453;
 // A SoftSort weight exp(-40) ~ 4e-18 is below float32 resolution of any row
 // sum (>= 1), so candidates scoring more than 40 tau below the K-th largest
 // score cannot change a manifold output.
@@ -28,13 +26,28 @@ struct Temp {
   double tau, inv_tau, c, tl;   // c = log2(e) / tau, tl = tau * ln 2
 };
 
-__device__ __forceinline__ Temp make_temp(double tau) {
+// The constants come precomputed in the kernel arguments, so they stay in
+// scalar registers.
+__device__ __forceinline__ Temp make_temp(const ParamsDev& prm) {
   Temp T;
-  T.tau = tau;
-  T.inv_tau = 1.0 / tau;
-  T.c = kLog2e / tau;
-  T.tl = tau * kLn2;
+  T.tau = prm.tau;
+  T.inv_tau = prm.inv_tau;
+  T.c = prm.c_log2;
+  T.tl = prm.tl;
   return T;
+}
+
+// Wave-uniform copies (v_readfirstlane): values every lane holds equal, so
+// the compiler can keep them in scalar registers.
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ float uni(float x) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+__device__ __forceinline__ double uni(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readfirstlane(int(b & 0xffffffffll));
+  const int hi = __builtin_amdgcn_readfirstlane(int(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
 // float32 hardware transcendentals
@@ -192,18 +205,36 @@ __device__ __forceinline__ void sdf_poly(const double4* __restrict__ pd, const f
 struct BodyView {
   int type, nv, ne, nf;
   float p[4];
-  double R[9];   // body frame -> pair frame rotation (row-major)
-  double t[3];   // body origin in the pair frame
-  bool ident;    // R = I, t = 0 (body A)
+  double R[9];   // body frame -> pair frame rotation (row-major); unused for A
+  double t[3];   // body origin in the pair frame; unused for A
   const double4* planes;  // LDS, body frame (polytopes): (n.xyz, o) in float64
   const float4* normals;  // LDS, the same normals in float32
 };
 
+// Load a body view that every lane of the workgroup shares from LDS into
+// wave-uniform registers.
+__device__ __forceinline__ BodyView load_uniform(const BodyView& src, bool with_pose) {
+  BodyView v;
+  v.type = uni(src.type); v.nv = uni(src.nv); v.ne = uni(src.ne); v.nf = uni(src.nf);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v.p[i] = uni(src.p[i]);
+  if (with_pose) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) v.R[i] = uni(src.R[i]);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) v.t[i] = uni(src.t[i]);
+  }
+  v.planes = nullptr;
+  v.normals = nullptr;
+  return v;
+}
+
 // SDF of a body at a pair-frame point; gradient returned in the pair frame.
-template <bool WANT_G>
+// IDENT: the body is A, whose frame is the pair frame (no transform).
+template <bool WANT_G, bool IDENT>
 __device__ __forceinline__ void sdf_body(const BodyView& B, const D3& x, const Temp& T, double& phi, D3& g) {
   D3 l = x;
-  if (!B.ident) {
+  if (!IDENT) {
     const double dx = x.x - B.t[0], dy = x.y - B.t[1], dz = x.z - B.t[2];
     l = d3(B.R[0] * dx + B.R[3] * dy + B.R[6] * dz, B.R[1] * dx + B.R[4] * dy + B.R[7] * dz,
            B.R[2] * dx + B.R[5] * dy + B.R[8] * dz);
@@ -212,7 +243,7 @@ __device__ __forceinline__ void sdf_body(const BodyView& B, const D3& x, const T
   if (B.type == CM_POLYTOPE) sdf_poly<WANT_G>(B.planes, B.normals, B.nf, l, T, phi, lg);
   else sdf_analytic(B.type, B.p, l, phi, lg);
   if (WANT_G) {
-    if (B.ident) g = lg;
+    if (IDENT) g = lg;
     else g = d3(B.R[0] * lg.x + B.R[1] * lg.y + B.R[2] * lg.z, B.R[3] * lg.x + B.R[4] * lg.y + B.R[5] * lg.z,
                 B.R[6] * lg.x + B.R[7] * lg.y + B.R[8] * lg.z);
   }
@@ -313,10 +344,10 @@ __device__ __forceinline__ void ee_candidates(const D3& a0, const D3& t1, const 
   const D3 nb = d3(q.de.x * in, q.de.y * in, q.de.z * in);
   double phiB1, phiA2, dum;
   D3 gA, gB, dg;
-  sdf_body<false>(B, e1, T, phiB1, dg);
-  sdf_body<true>(A, e1, T, dum, gA);
-  sdf_body<false>(A, e2, T, phiA2, dg);
-  sdf_body<true>(B, e2, T, dum, gB);
+  sdf_body<false, false>(B, e1, T, phiB1, dg);
+  sdf_body<true, true>(A, e1, T, dum, gA);
+  sdf_body<false, true>(A, e2, T, phiA2, dg);
+  sdf_body<true, false>(B, e2, T, dum, gB);
   const double gam1 = tanh64(dot(gB, nb), T);
   const double gam2 = tanh64(-dot(gA, nb), T);
   const double base = q.log_con + lsig(-dot(gA, gB), T);
@@ -337,12 +368,13 @@ __device__ __forceinline__ void ee_candidates(const D3& a0, const D3& t1, const 
 
 // V-S candidate (Sec. IV-C): vertex v (pair frame) of one body against the
 // SDF of the other; sgn = -1 for A's vertices (the normal of B pushes A),
-// +1 for B's vertices.
+// +1 for B's vertices.  OTHER_IS_A: the SDF is A's (identity frame).
+template <bool OTHER_IS_A>
 __device__ __forceinline__ void vs_candidate(const D3& v, const BodyView& other, double sgn, const Temp& T,
                                              Cand& c) {
   double phi;
   D3 g;
-  sdf_body<true>(other, v, T, phi, g);
+  sdf_body<true, OTHER_IS_A>(other, v, T, phi, g);
   const double in = sgn * rcp64(sqrt(T.tau + dot(g, g)));
   c.p = v;
   c.n = d3(g.x * in, g.y * in, g.z * in);

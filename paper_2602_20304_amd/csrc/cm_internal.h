@@ -38,8 +38,14 @@ struct BatchDev {
   const int32_t* cand_pairs;
 };
 
+constexpr double kLog2e = 1.4426950408889634;
+constexpr double kLn2 = 0.6931471805599453;
+
 struct ParamsDev {
   double tau, lam, eps_n;   // tau is the float32 input widened; defaults resolved in float64
+  double inv_tau;           // 1 / tau
+  double c_log2;            // log2(e) / tau
+  double tl;                // tau ln 2
   float margin;             // broadphase margin (float32 predicate)
   int32_t K;
   int32_t eps_tied;         // eps_n = tau^2 (its tau dependence enters the adjoint)

@@ -115,7 +115,7 @@ struct PairEngine {
     sCnt = reinterpret_cast<int*>(smem + L.cnt);
     Dbuf = reinterpret_cast<double*>(slot);
     Sbuf = reinterpret_cast<float*>(Dbuf + (long long)maxE_ * maxE_);
-    T = make_temp(prm.tau);
+    T = make_temp(prm);
     lam = prm.lam;
     eps_n = prm.eps_n;
     K = prm.K;
@@ -153,7 +153,6 @@ struct PairEngine {
         }
         for (int i = 0; i < 9; ++i) ps.A.R[i] = (i % 4 == 0) ? 1.0 : 0.0;
         for (int i = 0; i < 3; ++i) ps.A.t[i] = 0.0;
-        ps.A.ident = true; ps.B.ident = false;
         ps.A.type = G1.type; ps.A.nv = G1.nv; ps.A.ne = G1.ne; ps.A.nf = G1.nf;
         ps.B.type = G2.type; ps.B.nv = G2.nv; ps.B.ne = G2.ne; ps.B.nf = G2.nf;
         for (int i = 0; i < 4; ++i) { ps.A.p[i] = G1.p[i]; ps.B.p[i] = G2.p[i]; }
@@ -168,7 +167,8 @@ struct PairEngine {
     }
     __syncthreads();
     if (!ps.valid) return false;
-    A = ps.A; B = ps.B;
+    A = load_uniform(ps.A, false);
+    B = load_uniform(ps.B, true);
     A.planes = sPA; B.planes = sPB;
     A.normals = sNA; B.normals = sNB;
     GA = &tb.geoms[ps.ga];
@@ -176,11 +176,13 @@ struct PairEngine {
     return true;
   }
 
-  // vertex v of a geometry (body frame, float) -> pair frame (double)
+  // vertex v of a geometry (body frame, float) -> pair frame (double);
+  // IDENT: the body is A (its frame is the pair frame)
+  template <bool IDENT>
   __device__ __forceinline__ D3 vertex(const GeomRec& G, int v, const BodyView& V) const {
     const int i = G.v_off + v;
     const D3 l = d3(tb.vx[i], tb.vy[i], tb.vz[i]);
-    if (V.ident) return l;
+    if (IDENT) return l;
     return d3(V.R[0] * l.x + V.R[1] * l.y + V.R[2] * l.z + V.t[0], V.R[3] * l.x + V.R[4] * l.y + V.R[5] * l.z + V.t[1],
               V.R[6] * l.x + V.R[7] * l.y + V.R[8] * l.z + V.t[2]);
   }
@@ -192,12 +194,19 @@ struct PairEngine {
       const bool isA = i < neA;
       const int e = isA ? i : i - neA;
       const GeomRec& G = isA ? *GA : *GB;
-      const BodyView& V = isA ? A : B;
-      const D3 p0 = vertex(G, tb.e0[G.e_off + e], V);
-      const D3 p1 = vertex(G, tb.e1[G.e_off + e], V);
-      const EdgeSoA& E = isA ? EA : EB;
-      E.x0[e] = p0.x; E.y0[e] = p0.y; E.z0[e] = p0.z;
-      E.tx[e] = p1.x - p0.x; E.ty[e] = p1.y - p0.y; E.tz[e] = p1.z - p0.z;
+      const int i0 = tb.e0[G.e_off + e], i1 = tb.e1[G.e_off + e];
+      const D3 p0 = isA ? vertex<true>(G, i0, A) : vertex<false>(G, i0, B);
+      const D3 p1 = isA ? vertex<true>(G, i1, A) : vertex<false>(G, i1, B);
+      // select the destination pointers by value (a reference select would
+      // force the engine object into scratch memory)
+      double* x0 = isA ? EA.x0 : EB.x0;
+      double* y0 = isA ? EA.y0 : EB.y0;
+      double* z0 = isA ? EA.z0 : EB.z0;
+      double* tx = isA ? EA.tx : EB.tx;
+      double* ty = isA ? EA.ty : EB.ty;
+      double* tz = isA ? EA.tz : EB.tz;
+      x0[e] = p0.x; y0[e] = p0.y; z0[e] = p0.z;
+      tx[e] = p1.x - p0.x; ty[e] = p1.y - p0.y; tz[e] = p1.z - p0.z;
     }
     for (int i = tid; i < nfA + nfB; i += BLOCK) {
       const bool isA = i < nfA;
@@ -212,8 +221,8 @@ struct PairEngine {
 
   // ------------------------------------------------------------ candidates
   __device__ __forceinline__ void vs(int i, Cand& c) const {
-    if (i < A.nv) vs_candidate(vertex(*GA, i, A), B, -1.0, T, c);
-    else vs_candidate(vertex(*GB, i - A.nv, B), A, 1.0, T, c);
+    if (i < A.nv) vs_candidate<false>(vertex<true>(*GA, i, A), B, -1.0, T, c);
+    else vs_candidate<true>(vertex<false>(*GB, i - A.nv, B), A, 1.0, T, c);
   }
   __device__ __forceinline__ void ee(int k, int l, Cand& c1, Cand& c2) const {
     D3 a0, t1, b0, t2;

@@ -166,3 +166,29 @@ def test_fused_graph_replays_match_plain(ctx):
         shift = (0.02 * torch.randn(3, db.n_bodies, generator=gen)).to(ctx.device)
         db.pose[4:7] += shift
     torch.cuda.synchronize()
+
+
+def test_kernel_timing_counts_launches(ctx):
+    """Opt-in event timing: one forward launch per cm_collide, one graph
+    replay per cm_collide_fused, sums reset on enable."""
+    b = W.cube_pairs(256, seed=2)
+    _say(f"[gpu] kernel timing: {b.n_scenes} scenes")
+    ids = ctx.create_geometry(b.geoms)
+    db = ctx.upload_batch(b, ids)
+    ctx.collide(db, b.tau, b.K, fused=True)        # capture outside the timed calls
+    ctx.set_kernel_timing(True)
+    for _ in range(3):
+        ctx.collide(db, b.tau, b.K)
+    ctx.collide(db, b.tau, b.K, fused=True)
+    ms, n = ctx.kernel_time("forward")
+    assert n == 3 and ms > 0.0
+    bp_ms, bp_n = ctx.kernel_time("broadphase")
+    assert bp_n == 3 and bp_ms > 0.0
+    f_ms, f_n = ctx.kernel_time("fused")
+    assert f_n == 1 and f_ms > 0.0
+    ctx.set_kernel_timing(True)
+    assert ctx.kernel_time("forward") == (0.0, 0)
+    ctx.set_kernel_timing(False)
+    ctx.collide(db, b.tau, b.K)
+    assert ctx.kernel_time("forward") == (0.0, 0)
+    ctx.check_errors()
