@@ -265,6 +265,18 @@ struct EEQP {
   D3 de;      // Delta e = e1 - e2
 };
 
+// The QP result from its solution: Delta e = (a0 - b0) + al1 t1 - al2 t2.
+__device__ __forceinline__ EEQP ee_from_alpha(const D3& a0, const D3& t1, const D3& b0, const D3& t2, double al1,
+                                              double al2, double log_con) {
+  const D3 b = d3(a0.x - b0.x, a0.y - b0.y, a0.z - b0.z);
+  EEQP r;
+  r.al1 = al1;
+  r.al2 = al2;
+  r.log_con = log_con;
+  r.de = d3(b.x + al1 * t1.x - al2 * t2.x, b.y + al1 * t1.y - al2 * t2.y, b.z + al1 * t1.z - al2 * t2.z);
+  return r;
+}
+
 // Smoothed analytic active-set solution of the regularised E-E QP
 // (Sec. IV-D-2): unconstrained minimiser -Q^{-1} c, four soft-clipped
 // box-edge minimisers blended by a soft argmin of their objective values,
@@ -305,18 +317,8 @@ __device__ __forceinline__ EEQP ee_qp(const D3& a0, const D3& t1, const D3& b0, 
   const double ac1 = (w0 + w2 * xc + w3 * xd) * iw;
   const double ac2 = (w0 * xa + w1 * xb + w2) * iw;
   const double con = (sig64(au1, T) * sig64(1.0 - au1, T)) * (sig64(au2, T) * sig64(1.0 - au2, T));
-  EEQP r;
-  r.log_con = (lsig(au1, T) + lsig(1.0 - au1, T)) + (lsig(au2, T) + lsig(1.0 - au2, T));
-  r.al1 = con * au1 + (1.0 - con) * ac1;
-  r.al2 = con * au2 + (1.0 - con) * ac2;
-  r.de = d3(b.x + r.al1 * t1.x - r.al2 * t2.x, b.y + r.al1 * t1.y - r.al2 * t2.y, b.z + r.al1 * t1.z - r.al2 * t2.z);
-  return r;
-}
-
-__device__ __forceinline__ double ee_dist(const D3& a0, const D3& t1, const D3& b0, const D3& t2, double lam,
-                                          const Temp& T) {
-  const EEQP q = ee_qp(a0, t1, b0, t2, lam, T);
-  return sqrt(dot(q.de, q.de));
+  const double log_con = (lsig(au1, T) + lsig(1.0 - au1, T)) + (lsig(au2, T) + lsig(1.0 - au2, T));
+  return ee_from_alpha(a0, t1, b0, t2, con * au1 + (1.0 - con) * ac1, con * au2 + (1.0 - con) * ac2, log_con);
 }
 
 // ----------------------------------------------------------------- candidates
@@ -332,10 +334,10 @@ struct Cand {
 // activity indicator): sign via soft sign of the opposing SDF gradient,
 // penetration via the opposing SDF value, clashing via both gradients,
 // nearest neighbour via the row / column LSE of the unsigned distances.
-__device__ __forceinline__ void ee_candidates(const D3& a0, const D3& t1, const D3& b0, const D3& t2,
+// q is the edge pair's QP solution (ee_qp).
+__device__ __forceinline__ void ee_candidates(const D3& a0, const D3& t1, const D3& b0, const D3& t2, const EEQP& q,
                                               double row_lse, double col_lse, const BodyView& A, const BodyView& B,
-                                              double lam, double eps_n, const Temp& T, Cand& c1, Cand& c2) {
-  const EEQP q = ee_qp(a0, t1, b0, t2, lam, T);
+                                              double eps_n, const Temp& T, Cand& c1, Cand& c2) {
   const D3 e1 = d3(a0.x + q.al1 * t1.x, a0.y + q.al1 * t1.y, a0.z + q.al1 * t1.z);
   const D3 e2 = d3(b0.x + q.al2 * t2.x, b0.y + q.al2 * t2.y, b0.z + q.al2 * t2.z);
   const double dsq = dot(q.de, q.de);

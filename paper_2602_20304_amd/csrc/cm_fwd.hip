@@ -143,8 +143,12 @@ __global__ __launch_bounds__(256) void bp_emit(Tables tb, BatchDev bt, float mar
 
 // ============================================================ per-pair manifold
 
+// Occupancy target: 3 waves per SIMD (<= 168 VGPRs) for K <= 8, where the
+// per-lane top-K list is short enough to fit with a handful of spills; 2
+// otherwise.
 template <int BLOCK, int KMAX, bool DYN>
-__global__ __launch_bounds__(BLOCK) void collide_fwd(Tables tb, BatchDev bt, ParamsDev prm, OutDev out,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(KMAX <= 8 ? 3 : 2)))
+void collide_fwd(Tables tb, BatchDev bt, ParamsDev prm, OutDev out,
                                                      float* __restrict__ scratch, long long scratch_stride, int maxV,
                                                      int maxE, int maxF, const int* __restrict__ order,
                                                      const int* __restrict__ range, int* __restrict__ queue,

@@ -21,9 +21,10 @@ struct FwdLaunch {
   int grid, block, kmax;
 };
 
-// Scratch floats per workgroup: unsigned-distance matrix + candidate scores.
+// Scratch floats per workgroup: per edge pair the unsigned distance and the
+// QP solution (al1, al2, ln con) in float64, then the float32 candidate scores.
 inline long long fwd_scratch_floats(int maxV, int maxE) {
-  return 2LL * maxE * maxE + 2LL * maxE * maxE + 2LL * maxV + 64;   // f64 D + f32 scores
+  return 8LL * maxE * maxE + 2LL * maxE * maxE + 2LL * maxV + 64;
 }
 
 struct CotDev {

@@ -84,8 +84,11 @@ struct PairEngine {
   Rec* sRec;
   double* sAcc;   // [9K] unnormalised SoftSort sums (1, p, nu, d, w) per row
   int* sCnt;
-  double* Dbuf;
-  float* Sbuf;
+  double* Dbuf;   // [maxE^2] unsigned distance of edge pair (k, l) at k * neB + l
+  double* Al1;    // [maxE^2] QP solution al1, al2 and ln con of the same edge pair
+  double* Al2;
+  double* Lcon;
+  float* Sbuf;    // [nvs + 2 nee] candidate scores (float32, filter only)
   Temp T;
   double lam, eps_n;
   int K, maxV, maxE, maxF;
@@ -113,8 +116,12 @@ struct PairEngine {
     sRec = reinterpret_cast<Rec*>(smem + L.rec);
     sAcc = reinterpret_cast<double*>(smem + L.acc);
     sCnt = reinterpret_cast<int*>(smem + L.cnt);
+    const long long mm = (long long)maxE_ * maxE_;
     Dbuf = reinterpret_cast<double*>(slot);
-    Sbuf = reinterpret_cast<float*>(Dbuf + (long long)maxE_ * maxE_);
+    Al1 = Dbuf + mm;
+    Al2 = Al1 + mm;
+    Lcon = Al2 + mm;
+    Sbuf = reinterpret_cast<float*>(Lcon + mm);
     T = make_temp(prm);
     lam = prm.lam;
     eps_n = prm.eps_n;
@@ -224,11 +231,15 @@ struct PairEngine {
     if (i < A.nv) vs_candidate<false>(vertex<true>(*GA, i, A), B, -1.0, T, c);
     else vs_candidate<true>(vertex<false>(*GB, i - A.nv, B), A, 1.0, T, c);
   }
+  // both candidates of edge pair (k, l) from the QP solution stored by the
+  // distance pass
   __device__ __forceinline__ void ee(int k, int l, Cand& c1, Cand& c2) const {
     D3 a0, t1, b0, t2;
     EA.get(k, a0, t1);
     EB.get(l, b0, t2);
-    ee_candidates(a0, t1, b0, t2, sRow[k], sCol[l], A, B, lam, eps_n, T, c1, c2);
+    const int i = k * B.ne + l;
+    const EEQP q = ee_from_alpha(a0, t1, b0, t2, Al1[i], Al2[i], Lcon[i]);
+    ee_candidates(a0, t1, b0, t2, q, sRow[k], sCol[l], A, B, eps_n, T, c1, c2);
   }
   // candidate idx in the fixed order: A's vertices, B's vertices, E-E (k, l)
   // row-major with witness 1 before witness 2
@@ -265,7 +276,11 @@ struct PairEngine {
         D3 a0, t1, b0, t2;
         EA.get(k, a0, t1);
         EB.get(l, b0, t2);
-        Dbuf[idx] = ee_dist(a0, t1, b0, t2, lam, T);
+        const EEQP q = ee_qp(a0, t1, b0, t2, lam, T);
+        Dbuf[idx] = sqrt(dot(q.de, q.de));
+        Al1[idx] = q.al1;
+        Al2[idx] = q.al2;
+        Lcon[idx] = q.log_con;
         k += sk; l += sl;
         if (l >= neB) { l -= neB; ++k; }
       }
