@@ -48,7 +48,28 @@ class DeviceBatch:
         nb = np.diff(bo)
         return int((nb * (nb - 1) // 2).sum())
 
+    def validate(self):
+        """Check dtypes, shapes and placement before the pointers cross the C ABI."""
+        def need(t, name, dtype, shape):
+            if not isinstance(t, torch.Tensor):
+                raise TypeError(f"{name} must be a torch tensor")
+            if t.dtype != dtype:
+                raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+            if tuple(t.shape) != shape:
+                raise ValueError(f"{name} must have shape {shape}, got {tuple(t.shape)}")
+            if not t.is_cuda or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous device tensor")
+        need(self.body_offsets, "body_offsets", torch.int32, (self.n_scenes + 1,))
+        need(self.body_geom, "body_geom", torch.int32, (self.n_bodies,))
+        need(self.pose, "pose", torch.float32, (7, self.n_bodies))
+        if (self.cand_offsets is None) != (self.cand_pairs is None):
+            raise ValueError("cand_offsets and cand_pairs go together")
+        if self.cand_pairs is not None:
+            need(self.cand_offsets, "cand_offsets", torch.int32, (self.n_scenes + 1,))
+            need(self.cand_pairs, "cand_pairs", torch.int32, (2, int(self.cand_pairs.shape[1])))
+
     def as_c(self) -> L.cm_batch:
+        self.validate()
         b = L.cm_batch()
         b.n_scenes = self.n_scenes
         b.n_bodies = self.n_bodies

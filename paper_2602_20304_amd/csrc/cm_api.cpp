@@ -195,11 +195,11 @@ cm_status cm_geometry_create(cm_context* ctx, int32_t n, const int32_t* types, c
     r.f_off = int32_t(h.fnx.size());
     for (int k = 0; k < 4; ++k) r.p[k] = m.p[k];
     r.bound_r = m.bound_r;
-    for (int v = 0; v < r.nv; ++v) { h.vx.push_back(m.v[3 * v]); h.vy.push_back(m.v[3 * v + 1]); h.vz.push_back(m.v[3 * v + 2]); }
+    for (int v = 0; v < r.nv; ++v) { h.vx.push_back(m.vd[3 * v]); h.vy.push_back(m.vd[3 * v + 1]); h.vz.push_back(m.vd[3 * v + 2]); }
     for (int e = 0; e < r.ne; ++e) { h.e0.push_back(m.e[2 * e]); h.e1.push_back(m.e[2 * e + 1]); }
     for (int f = 0; f < r.nf; ++f) {
-      h.fnx.push_back(m.planes[4 * f]); h.fny.push_back(m.planes[4 * f + 1]);
-      h.fnz.push_back(m.planes[4 * f + 2]); h.fo.push_back(m.planes[4 * f + 3]);
+      h.fnx.push_back(m.pd[4 * f]); h.fny.push_back(m.pd[4 * f + 1]);
+      h.fnz.push_back(m.pd[4 * f + 2]); h.fo.push_back(m.pd[4 * f + 3]);
       h.f0.push_back(m.f[3 * f]); h.f1.push_back(m.f[3 * f + 1]); h.f2.push_back(m.f[3 * f + 2]);
     }
     ctx->maxV = std::max(ctx->maxV, r.nv);
@@ -228,7 +228,9 @@ cm_status cm_geometry_mesh(cm_context* ctx, int32_t id, float* vertices, int32_t
   const GeomRec& r = ctx->h.recs[id];
   const auto& h = ctx->h;
   if (vertices) for (int v = 0; v < r.nv; ++v) {
-    vertices[3 * v] = h.vx[r.v_off + v]; vertices[3 * v + 1] = h.vy[r.v_off + v]; vertices[3 * v + 2] = h.vz[r.v_off + v];
+    vertices[3 * v] = float(h.vx[r.v_off + v]);
+    vertices[3 * v + 1] = float(h.vy[r.v_off + v]);
+    vertices[3 * v + 2] = float(h.vz[r.v_off + v]);
   }
   if (edges) for (int e = 0; e < r.ne; ++e) { edges[2 * e] = h.e0[r.e_off + e]; edges[2 * e + 1] = h.e1[r.e_off + e]; }
   if (faces) for (int f = 0; f < r.nf; ++f) {

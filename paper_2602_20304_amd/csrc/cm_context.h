@@ -10,9 +10,9 @@
 
 struct CmPools {
   std::vector<cm::GeomRec> recs;
-  std::vector<float> vx, vy, vz;
+  std::vector<double> vx, vy, vz;
   std::vector<int32_t> e0, e1;
-  std::vector<float> fnx, fny, fnz, fo;
+  std::vector<double> fnx, fny, fnz, fo;
   std::vector<int32_t> f0, f1, f2;
 };
 
@@ -21,9 +21,9 @@ struct CmDevPtr;
 
 struct CmDevPools {
   cm::GeomRec* recs = nullptr;
-  float *vx = nullptr, *vy = nullptr, *vz = nullptr;
+  double *vx = nullptr, *vy = nullptr, *vz = nullptr;
   int32_t *e0 = nullptr, *e1 = nullptr;
-  float *fnx = nullptr, *fny = nullptr, *fnz = nullptr, *fo = nullptr;
+  double *fnx = nullptr, *fny = nullptr, *fnz = nullptr, *fo = nullptr;
   int32_t *f0 = nullptr, *f1 = nullptr, *f2 = nullptr;
 };
 

@@ -172,32 +172,41 @@ __device__ __forceinline__ void sdf_analytic(int type, const float* p, const D3&
   }
 }
 
-// tau-LSE over body-frame planes: pd[f] = (n.xyz, o) in float64, pf[f] =
-// n.xyz in float32 (gradient accumulation), both in LDS.
+// tau-LSE over body-frame planes pd[f] = (n.xyz, o) (float64, LDS):
 // phi = LSE_tau(n . x - o); gradient = softmax-weighted sum of normals.
+// The value sums float32 exponentials (its error is tau times their relative
+// error).  The gradient enters the clashing indicator divided by tau, so its
+// softmax weights are float64; a plane whose weight is below e^-25 relative
+// to the largest for every lane of the wave is skipped (contribution < 2e-11
+// per plane).
 template <bool WANT_G>
-__device__ __forceinline__ void sdf_poly(const double4* __restrict__ pd, const float4* __restrict__ pf, int nf,
-                                         const D3& x, const Temp& T, double& phi, D3& g) {
+__device__ __forceinline__ void sdf_poly(const double4* __restrict__ pd, int nf, const D3& x, const Temp& T,
+                                         double& phi, D3& g) {
   double m = -1e300;
   for (int f = 0; f < nf; ++f) {
     const double4 q = pd[f];
     m = fmax(m, fma(q.x, x.x, fma(q.y, x.y, fma(q.z, x.z, -q.w))));
   }
-  float s = 0.f, ax = 0.f, ay = 0.f, az = 0.f;
+  float s = 0.f;
+  double S = 0.0, ax = 0.0, ay = 0.0, az = 0.0;
   for (int f = 0; f < nf; ++f) {
     const double4 q = pd[f];
     const double yv = fma(q.x, x.x, fma(q.y, x.y, fma(q.z, x.z, -q.w)));
-    const float e = ex2f(float((yv - m) * T.c));
-    s += e;
+    s += ex2f(float((yv - m) * T.c));
     if (WANT_G) {
-      const float4 n = pf[f];
-      ax = fmaf(e, n.x, ax); ay = fmaf(e, n.y, ay); az = fmaf(e, n.z, az);
+      const double z = (yv - m) * T.inv_tau;
+      const bool sig = z > -25.0;
+      if (__any(sig)) {
+        const double e = sig ? exp64n(z) : 0.0;
+        S += e;
+        ax = fma(e, q.x, ax); ay = fma(e, q.y, ay); az = fma(e, q.z, az);
+      }
     }
   }
   phi = m + T.tl * double(lg2f(s));
   if (WANT_G) {
-    const float inv = frcp(s);
-    g = d3(double(ax * inv), double(ay * inv), double(az * inv));
+    const double inv = rcp64(S);
+    g = d3(ax * inv, ay * inv, az * inv);
   }
 }
 
@@ -208,7 +217,6 @@ struct BodyView {
   double R[9];   // body frame -> pair frame rotation (row-major); unused for A
   double t[3];   // body origin in the pair frame; unused for A
   const double4* planes;  // LDS, body frame (polytopes): (n.xyz, o) in float64
-  const float4* normals;  // LDS, the same normals in float32
 };
 
 // Load a body view that every lane of the workgroup shares from LDS into
@@ -225,7 +233,6 @@ __device__ __forceinline__ BodyView load_uniform(const BodyView& src, bool with_
     for (int i = 0; i < 3; ++i) v.t[i] = uni(src.t[i]);
   }
   v.planes = nullptr;
-  v.normals = nullptr;
   return v;
 }
 
@@ -240,7 +247,7 @@ __device__ __forceinline__ void sdf_body(const BodyView& B, const D3& x, const T
            B.R[2] * dx + B.R[5] * dy + B.R[8] * dz);
   }
   D3 lg;
-  if (B.type == CM_POLYTOPE) sdf_poly<WANT_G>(B.planes, B.normals, B.nf, l, T, phi, lg);
+  if (B.type == CM_POLYTOPE) sdf_poly<WANT_G>(B.planes, B.nf, l, T, phi, lg);
   else sdf_analytic(B.type, B.p, l, phi, lg);
   if (WANT_G) {
     if (IDENT) g = lg;

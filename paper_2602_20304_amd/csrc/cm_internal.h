@@ -23,9 +23,9 @@ struct GeomRec {
 struct Tables {
   const GeomRec* geoms;
   int32_t n_geoms;
-  const float* vx; const float* vy; const float* vz;       // vertex pool
+  const double* vx; const double* vy; const double* vz;    // vertex pool (float64)
   const int32_t* e0; const int32_t* e1;                    // edge pool (local vertex ids)
-  const float* fnx; const float* fny; const float* fnz; const float* fo;   // plane pool
+  const double* fnx; const double* fny; const double* fnz; const double* fo;   // plane pool (float64)
   const int32_t* f0; const int32_t* f1; const int32_t* f2; // face vertex ids (local)
 };
 
@@ -66,10 +66,12 @@ enum : uint32_t { ERR_BAD_GEOM = 1u, ERR_CAPACITY = 2u, ERR_K = 4u };
 struct HostMesh {
   int32_t type = 0;
   float p[4] = {0, 0, 0, 0};
-  std::vector<float> v;       // 3 * nv
+  std::vector<float> v;       // 3 * nv (float32 copy for the mesh query API)
+  std::vector<double> vd;     // 3 * nv vertices in float64 (what the kernels use)
   std::vector<int32_t> e;     // 2 * ne
   std::vector<int32_t> f;     // 3 * nf (polytopes)
-  std::vector<float> planes;  // 4 * nf (n, o)
+  std::vector<float> planes;  // 4 * nf (n, o), float32 copy
+  std::vector<double> pd;     // 4 * nf (n, o) in float64 (what the kernels use)
   float bound_r = 0.f;
 };
 

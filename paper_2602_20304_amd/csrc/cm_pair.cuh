@@ -57,8 +57,8 @@ __host__ __device__ inline LdsLayout lds_layout(int maxE, int maxF, int block) {
   L.top = o; o += 8 * 64;
   L.rec = o; o += int(sizeof(Rec)) * block;
   L.acc = o; o += 8 * 9 * CM_MAX_K;
-  L.pA = o; o += 48 * maxF;    // double4 planes + float4 normals
-  L.pB = o; o += 48 * maxF;
+  L.pA = o; o += 32 * maxF;    // double4 planes (n.xyz, o)
+  L.pB = o; o += 32 * maxF;
   L.cnt = o; o += 64;
   L.bytes = (o + 15) & ~15;
   return L;
@@ -75,8 +75,6 @@ struct PairEngine {
   EdgeSoA EA, EB;
   double4* sPA;
   double4* sPB;
-  float4* sNA;
-  float4* sNB;
   double* sRow;
   double* sCol;
   double* sRed;
@@ -107,8 +105,6 @@ struct PairEngine {
     EB = EdgeSoA{e, e + maxE_, e + 2 * maxE_, e + 3 * maxE_, e + 4 * maxE_, e + 5 * maxE_};
     sPA = reinterpret_cast<double4*>(smem + L.pA);
     sPB = reinterpret_cast<double4*>(smem + L.pB);
-    sNA = reinterpret_cast<float4*>(smem + L.pA + 32 * maxF_);
-    sNB = reinterpret_cast<float4*>(smem + L.pB + 32 * maxF_);
     sRow = reinterpret_cast<double*>(smem + L.row);
     sCol = reinterpret_cast<double*>(smem + L.col);
     sRed = reinterpret_cast<double*>(smem + L.red);
@@ -177,7 +173,6 @@ struct PairEngine {
     A = load_uniform(ps.A, false);
     B = load_uniform(ps.B, true);
     A.planes = sPA; B.planes = sPB;
-    A.normals = sNA; B.normals = sNB;
     GA = &tb.geoms[ps.ga];
     GB = &tb.geoms[ps.gb];
     return true;
@@ -219,9 +214,7 @@ struct PairEngine {
       const bool isA = i < nfA;
       const int f = isA ? GA->f_off + i : GB->f_off + (i - nfA);
       const int j = isA ? i : i - nfA;
-      const float nx = tb.fnx[f], ny = tb.fny[f], nz = tb.fnz[f], o = tb.fo[f];
-      (isA ? sPA : sPB)[j] = make_double4(nx, ny, nz, o);
-      (isA ? sNA : sNB)[j] = make_float4(nx, ny, nz, 0.f);
+      (isA ? sPA : sPB)[j] = make_double4(tb.fnx[f], tb.fny[f], tb.fnz[f], tb.fo[f]);
     }
     __syncthreads();
   }

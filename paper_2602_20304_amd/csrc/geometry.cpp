@@ -169,8 +169,11 @@ bool build_mesh(int32_t type, const float* params, const float* pts, int64_t n_p
   m = HostMesh();
   m.type = type;
   for (int k = 0; k < 4; ++k) m.p[k] = params ? params[k] : 0.f;
+  // analytic mesh vertices are functions of the float32 parameters, kept in
+  // float64 so that the kernels see the same mesh as the definition
   auto push_v = [&](double x, double y, double z) {
     m.v.push_back(float(x)); m.v.push_back(float(y)); m.v.push_back(float(z));
+    m.vd.push_back(x); m.vd.push_back(y); m.vd.push_back(z);
   };
   auto push_e = [&](int a, int b) { m.e.push_back(a); m.e.push_back(b); };
   if (type == CM_SPHERE || type == CM_CAPSULE) {
@@ -224,7 +227,11 @@ bool build_mesh(int32_t type, const float* params, const float* pts, int64_t n_p
   if (type == CM_POLYTOPE) {
     std::vector<int32_t> vid, tris, edges;
     if (!convex_hull(pts, n_pts, &vid, &tris, &edges, err)) return false;
-    for (int32_t i : vid) { m.v.push_back(pts[3 * i]); m.v.push_back(pts[3 * i + 1]); m.v.push_back(pts[3 * i + 2]); }
+    for (int32_t i : vid)
+      for (int k = 0; k < 3; ++k) {
+        m.v.push_back(pts[3 * i + k]);
+        m.vd.push_back(double(pts[3 * i + k]));
+      }
     m.e = edges;
     m.f = tris;
     const size_t nf = tris.size() / 3;
@@ -237,8 +244,10 @@ bool build_mesh(int32_t type, const float* params, const float* pts, int64_t n_p
       sub3(b, a, u); sub3(c, a, v); cross3(u, v, nn);
       double l = std::sqrt(dot3(nn, nn));
       for (int k = 0; k < 3; ++k) nn[k] /= l;
+      const double o = dot3(nn, a);
       m.planes.push_back(float(nn[0])); m.planes.push_back(float(nn[1])); m.planes.push_back(float(nn[2]));
-      m.planes.push_back(float(dot3(nn, a)));
+      m.planes.push_back(float(o));
+      m.pd.push_back(nn[0]); m.pd.push_back(nn[1]); m.pd.push_back(nn[2]); m.pd.push_back(o);
     }
     float mx = 0.f;
     for (int64_t i = 0; i < n_pts; ++i) {
