@@ -91,29 +91,32 @@ def stored_traffic(workload: str):
 
 def cpu_baseline(batch, budget_s: float):
     """Time the FP64 oracle on the host over whole scenes in scene order until
-    the time budget is spent."""
+    the time budget is spent.  Only the per-pair evaluations are timed (the
+    oracle's mesh and hull construction for a geometry happens before)."""
     import torch
     from oracle import cm_oracle as O
     pairs, offsets = O.broadphase(batch)
     cache = O.GeomCache(batch.geoms)
     threads = int(torch.get_num_threads())
-    t0 = time.perf_counter()
+    spent = 0.0
     done = 0
     scenes = 0
     with torch.no_grad():
         for s in range(batch.n_scenes):
             for i in range(int(offsets[s]), int(offsets[s + 1])):
                 a, b = int(pairs[0, i]), int(pairs[1, i])
-                O.collide_pair(cache[batch.body_geom[a]], batch.pose[:, a], cache[batch.body_geom[b]],
-                               batch.pose[:, b], batch.tau, batch.K)
+                GA, GB = cache[batch.body_geom[a]], cache[batch.body_geom[b]]
+                t0 = time.perf_counter()
+                O.collide_pair(GA, batch.pose[:, a], GB, batch.pose[:, b], batch.tau, batch.K)
+                spent += time.perf_counter() - t0
                 done += 1
             scenes += 1
-            if time.perf_counter() - t0 > budget_s:
+            if spent > budget_s:
                 break
-    dt = time.perf_counter() - t0
-    return dict(value=done / dt, unit="pairs/s", cores=threads, kind="oracle",
+    return dict(value=done / spent, unit="pairs/s", cores=threads, kind="oracle",
                 sample=f"first {scenes} scenes ({done} kept pairs) of the same workload, FP64 oracle, "
-                       f"{dt:.1f} s wall, torch intra-op threads={threads}, mesh builds excluded")
+                       f"{spent:.1f} s of pair evaluation, torch intra-op threads={threads}, "
+                       f"mesh builds excluded")
 
 
 def serving_leg(ctx_cls, n_requests: int, seed: int = 11):

@@ -32,7 +32,7 @@ def _alone(ctx, req, ids, tau, K, cot_d=None, cot_n=None):
     dev = ctx.device
     db = DeviceBatch(req.n_env, int(len(req.body_geom)), torch.as_tensor(req.body_offsets, dtype=torch.int32).to(dev),
                      torch.as_tensor(ids[req.body_geom], dtype=torch.int32).to(dev),
-                     torch.as_tensor(req.pose, dtype=torch.float32).to(dev))
+                     torch.as_tensor(req.pose, dtype=torch.float32).contiguous().to(dev))
     m = ctx.collide(db, tau, K)
     ctx.check_errors()
     out = m.to_numpy()
