@@ -168,7 +168,7 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
           taub += ab * fabs(dl) * T.inv_tau * T.inv_tau;
           if (fabs(dl) < best || (fabs(dl) == best && R.idx < bidx)) { best = fabs(dl); bidx = R.idx; }
         }
-      });
+      }, kAdjointTaus);
       P.sRed[tid] = act ? sbp : 0.0;
       P.sRed[BLOCK + tid] = act ? best : INFINITY;
       bestI[CM_MAX_K + tid] = act ? bidx : 0x7fffffff;
@@ -338,7 +338,7 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
         atomicAdd(&vB3[ib0], float(vb0.x)); atomicAdd(&vB3[maxV + ib0], float(vb0.y)); atomicAdd(&vB3[2 * maxV + ib0], float(vb0.z));
         atomicAdd(&vB3[ib1], float(t2b.x)); atomicAdd(&vB3[maxV + ib1], float(t2b.y)); atomicAdd(&vB3[2 * maxV + ib1], float(t2b.z));
       }
-    });
+    }, kAdjointTaus);
     __syncthreads();
 
     // ------------------------------------------------ N: nearest-neighbour LSE adjoint
@@ -348,15 +348,21 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
         const int k = idx / neB, l = idx - k * neB;
         const double rb = rbar[k], cb = cbar[l];
         if (rb == 0.0 && cb == 0.0) continue;
-        D3 a0, t1, b0, t2;
-        P.EA.get(k, a0, t1);
-        P.EB.get(l, b0, t2);
-        const EEQP q = ee_qp(a0, t1, b0, t2, P.lam, T);
-        const double D = sqrt(dot(q.de, q.de));
-        const double pr = exp64n((P.sRow[k] - D) * T.inv_tau), pc = exp64n((P.sCol[l] - D) * T.inv_tau);
+        // the row / column softmax weights from the stored distance; an
+        // entry whose weights are both below e^-28 (7e-13) is skipped before
+        // any QP work
+        const double D = P.Dbuf[idx];
+        const double zr = (P.sRow[k] - D) * T.inv_tau, zc = (P.sCol[l] - D) * T.inv_tau;
+        const bool sr = rb != 0.0 && zr > -28.0, sc = cb != 0.0 && zc > -28.0;
+        if (!sr && !sc) continue;
+        const double pr = sr ? exp64n(zr) : 0.0, pc = sc ? exp64n(zc) : 0.0;
         const double Db = rb * pr + cb * pc;
         taub += (rb * pr * (P.sRow[k] - D) + cb * pc * (P.sCol[l] - D)) * T.inv_tau;
         if (Db == 0.0 || !(D > 0.0)) continue;
+        D3 a0, t1, b0, t2;
+        P.EA.get(k, a0, t1);
+        P.EB.get(l, b0, t2);
+        const EEQP q = ee_from_alpha(a0, t1, b0, t2, P.Al1[idx], P.Al2[idx], P.Lcon[idx]);
         const D3 deb = scl(q.de, Db / D);
         D3 a0b = deb, t1b = scl(deb, q.al1), b0b = scl(deb, -1.0), t2b = scl(deb, -q.al2);
         ee_qp_bwd(a0, t1, b0, t2, P.lam, T, dot(deb, t1), -dot(deb, t2), 0.0, a0b, t1b, b0b, t2b, taub);

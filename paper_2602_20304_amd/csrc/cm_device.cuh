@@ -21,6 +21,10 @@ namespace cm {
 // sum (>= 1), so candidates scoring more than 40 tau below the K-th largest
 // score cannot change a manifold output.
 constexpr double kFilterTaus = 40.0;
+// The adjoint skips candidates whose largest SoftSort weight is below
+// exp(-18) ~ 1.5e-8 relative: their share of any gradient is far below the
+// float32 outputs' and the gradient tolerance's resolution.
+constexpr double kAdjointTaus = 18.0;
 
 struct Temp {
   double tau, inv_tau, c, tl;   // c = log2(e) / tau, tl = tau * ln 2

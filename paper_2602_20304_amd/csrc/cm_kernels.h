@@ -22,9 +22,10 @@ struct FwdLaunch {
 };
 
 // Scratch floats per workgroup: per edge pair the unsigned distance and the
-// QP solution (al1, al2, ln con) in float64, then the float32 candidate scores.
+// QP solution (al1, al2, ln con) in float64, then the float32 candidate
+// scores and the int32 list of filtered candidates (both nvs + 2 nee long).
 inline long long fwd_scratch_floats(int maxV, int maxE) {
-  return 8LL * maxE * maxE + 2LL * maxE * maxE + 2LL * maxV + 64;
+  return 8LL * maxE * maxE + 2 * (2LL * maxE * maxE + 2LL * maxV) + 128;
 }
 
 struct CotDev {

@@ -87,6 +87,7 @@ struct PairEngine {
   double* Al2;
   double* Lcon;
   float* Sbuf;    // [nvs + 2 nee] candidate scores (float32, filter only)
+  int* List;      // [nvs + 2 nee + 64] compacted indices of filtered candidates
   Temp T;
   double lam, eps_n;
   int K, maxV, maxE, maxF;
@@ -118,6 +119,7 @@ struct PairEngine {
     Al2 = Al1 + mm;
     Lcon = Al2 + mm;
     Sbuf = reinterpret_cast<float*>(Lcon + mm);
+    List = reinterpret_cast<int*>(Sbuf + 2 * mm + 2LL * maxV_);
     T = make_temp(prm);
     lam = prm.lam;
     eps_n = prm.eps_n;
@@ -367,35 +369,47 @@ struct PairEngine {
   }
 
   // ------------------------------------------------------------ filtered iteration
-  // Visit the candidates whose stored score is within 40 tau of s_[K] in
-  // chunks: records are compacted (in candidate order) into sRec, then
-  // body(tot) runs with all threads after a barrier.
+  // Visit the candidates whose stored score is within `taus` tau of s_[K].
+  // Each wave first compacts the passing indices of its contiguous share of
+  // the candidates into List (ballot prefix sums, candidate order kept);
+  // the concatenated list is then evaluated densely in chunks of BLOCK, one
+  // candidate record per thread in sRec, and body(n) runs with all threads
+  // after a barrier for each chunk of n records.
   template <typename F>
-  __device__ void for_filtered(F&& body) {
-    const float thr = float(sTop[K - 1] - kFilterTaus * T.tau) - 1e-6f * fabsf(float(sTop[K - 1]));
+  __device__ void for_filtered(F&& body, double taus = kFilterTaus) {
+    const float thr = float(sTop[K - 1] - taus * T.tau) - 1e-6f * fabsf(float(sTop[K - 1]));
     const int ncand = ps.ncand;
-    for (int base = 0; base < ncand; base += BLOCK) {
-      const int idx = base + tid;
-      const bool pass = idx < ncand && Sbuf[idx] >= thr;
+    const int seg = (ncand + NW - 1) / NW;
+    const int lo = min(ncand, wave * seg), hi = min(ncand, lo + seg);
+    int n = 0;
+    for (int b = lo; b < hi; b += 64) {
+      const int idx = b + lane;
+      const bool pass = idx < hi && Sbuf[idx] >= thr;
       const unsigned long long ball = __ballot(pass);
-      const int below = __popcll(ball & ((1ull << lane) - 1ull));
-      if (lane == 0) sCnt[wave] = __popcll(ball);
-      __syncthreads();
-      int off = 0, tot = 0;
+      if (pass) List[lo + n + __popcll(ball & ((1ull << lane) - 1ull))] = idx;
+      n += __popcll(ball);
+    }
+    if (lane == 0) sCnt[wave] = n;
+    __syncthreads();
+    int tot = 0;
 #pragma unroll
-      for (int w = 0; w < NW; ++w) {
-        const int c = sCnt[w];
-        off += (w < wave) ? c : 0;
-        tot += c;
-      }
-      if (tot == 0) {
-        __syncthreads();
-        continue;
-      }
-      if (pass) {
+    for (int w = 0; w < NW; ++w) tot += sCnt[w];
+    if (tot == 0) __syncthreads();   // sCnt is rewritten by the next call
+    for (int base = 0; base < tot; base += BLOCK) {
+      const int p = base + tid;
+      if (p < tot) {
+        // the wave region holding list position p: the last wave whose
+        // start is <= p (empty regions share the next region's start)
+        int reg = 0, off = 0, acc = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+          if (p >= acc) { reg = w; off = acc; }
+          acc += sCnt[w];
+        }
+        const int idx = List[min(ncand, reg * seg) + (p - off)];
         Cand c;
         candidate(idx, c);
-        Rec& rr = sRec[off + below];
+        Rec& rr = sRec[tid];
         rr.s = c.s; rr.d = c.d;
         rr.px = float(c.p.x); rr.py = float(c.p.y); rr.pz = float(c.p.z);
         rr.nx = float(c.n.x); rr.ny = float(c.n.y); rr.nz = float(c.n.z);
@@ -403,7 +417,7 @@ struct PairEngine {
         rr.idx = idx;
       }
       __syncthreads();
-      body(tot);
+      body(min(BLOCK, tot - base));
       __syncthreads();
     }
   }
