@@ -226,8 +226,8 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
         const double sgn = ofA ? -1.0 : 1.0;
         double phi;
         D3 g;
-        if (ofA) sdf_body<true, false>(B, x, T, phi, g);
-        else sdf_body<true, true>(A, x, T, phi, g);
+        if (ofA) sdf_body<kFull, false>(B, x, T, phi, g);
+        else sdf_body<kFull, true>(A, x, T, phi, g);
         const double q = T.tau + dot(g, g), in = 1.0 / sqrt(q);
         const double lw = lsig(-phi, T), w = exp(lw);
         const double dtot = fb[6] - sb, lwb = T.tau * sb + w * fb[7];
@@ -260,10 +260,10 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
         const D3 nb = scl(de, rho);
         double phiB1, phiA2, dum;
         D3 gA, gB, dg;
-        sdf_body<false, false>(B, e1, T, phiB1, dg);
-        sdf_body<true, true>(A, e1, T, dum, gA);
-        sdf_body<false, true>(A, e2, T, phiA2, dg);
-        sdf_body<true, false>(B, e2, T, dum, gB);
+        sdf_body<kValue, false>(B, e1, T, phiB1, dg);
+        sdf_body<kSurfGrad, true>(A, e1, T, dum, gA);
+        sdf_body<kValue, true>(A, e2, T, phiA2, dg);
+        sdf_body<kSurfGrad, false>(B, e2, T, dum, gB);
         const double u1 = dot(gB, nb), u2 = -dot(gA, nb), ucl = -dot(gA, gB);
         const double gam1 = tanh64(u1, T), gam2 = tanh64(u2, T);
         const double gam = wit ? gam2 : gam1;

@@ -73,7 +73,7 @@ __device__ __forceinline__ double rcp64(double x) {
   return fma(r, e, r);
 }
 
-// exp(x) for x <= 0 to ~1e-12 relative in float64: Cody-Waite reduction
+// exp(x) for x <= 700 to ~1e-12 relative in float64: Cody-Waite reduction
 // x = n ln2 + r, |r| <= ln2 / 2, then a degree-9 Taylor polynomial of e^r
 // (remainder below r^10 / 10! ~ 7e-12) scaled by 2^n.
 __device__ __forceinline__ double exp64n(double x) {
@@ -176,28 +176,45 @@ __device__ __forceinline__ void sdf_analytic(int type, const float* p, const D3&
   }
 }
 
+// SDF query kinds.  kValue: phi only.  kFull: phi and gradient at a
+// general point.  kSurfGrad: gradient only, at a point on the body's own
+// boundary (a witness point on one of its edges).
+enum SdfMode { kValue = 0, kFull = 1, kSurfGrad = 2 };
+
 // tau-LSE over body-frame planes pd[f] = (n.xyz, o) (float64, LDS):
 // phi = LSE_tau(n . x - o); gradient = softmax-weighted sum of normals.
-// The value sums float32 exponentials (its error is tau times their relative
-// error).  The gradient enters the clashing indicator divided by tau, so its
-// softmax weights are float64; a plane whose weight is below e^-25 relative
-// to the largest for every lane of the wave is skipped (contribution < 2e-11
-// per plane).
-template <bool WANT_G>
+// The value sums float32 exponentials shifted by the largest plane value
+// (its error is tau times their relative error); a plane more than 30
+// binary orders below the largest for every lane of the wave adds nothing
+// a float32 sum can hold (< 2^-30 per plane) and skips its exponential.
+// The gradient enters the clashing indicator divided by tau, so its softmax
+// weights are float64; a plane whose weight is below e^-25 relative to the
+// largest for every lane of the wave is skipped (< 2e-11 per plane).  At a
+// point on the polytope's own boundary the largest plane value is 0
+// (convexity), so kSurfGrad shifts by 0 and needs no max pass and no value
+// sum; a smoothed witness can sit past an edge's end by at most ~0.28 tau
+// times the edge length, which keeps every shifted exponent below ~0.3.
+template <int MODE>
 __device__ __forceinline__ void sdf_poly(const double4* __restrict__ pd, int nf, const D3& x, const Temp& T,
                                          double& phi, D3& g) {
-  double m = -1e300;
-  for (int f = 0; f < nf; ++f) {
-    const double4 q = pd[f];
-    m = fmax(m, fma(q.x, x.x, fma(q.y, x.y, fma(q.z, x.z, -q.w))));
+  double m = 0.0;
+  if (MODE != kSurfGrad) {
+    m = -1e300;
+    for (int f = 0; f < nf; ++f) {
+      const double4 q = pd[f];
+      m = fmax(m, fma(q.x, x.x, fma(q.y, x.y, fma(q.z, x.z, -q.w))));
+    }
   }
   float s = 0.f;
   double S = 0.0, ax = 0.0, ay = 0.0, az = 0.0;
   for (int f = 0; f < nf; ++f) {
     const double4 q = pd[f];
     const double yv = fma(q.x, x.x, fma(q.y, x.y, fma(q.z, x.z, -q.w)));
-    s += ex2f(float((yv - m) * T.c));
-    if (WANT_G) {
+    if (MODE != kSurfGrad) {
+      const double a = (yv - m) * T.c;
+      if (__any(a > -30.0)) s += ex2f(float(a));
+    }
+    if (MODE != kValue) {
       const double z = (yv - m) * T.inv_tau;
       const bool sig = z > -25.0;
       if (__any(sig)) {
@@ -207,9 +224,9 @@ __device__ __forceinline__ void sdf_poly(const double4* __restrict__ pd, int nf,
       }
     }
   }
-  phi = m + T.tl * double(lg2f(s));
-  if (WANT_G) {
-    const double inv = rcp64(S);
+  if (MODE != kSurfGrad) phi = m + T.tl * double(lg2f(s));
+  if (MODE != kValue) {
+    const double inv = S > 0.0 ? rcp64(S) : 0.0;
     g = d3(ax * inv, ay * inv, az * inv);
   }
 }
@@ -241,8 +258,9 @@ __device__ __forceinline__ BodyView load_uniform(const BodyView& src, bool with_
 }
 
 // SDF of a body at a pair-frame point; gradient returned in the pair frame.
-// IDENT: the body is A, whose frame is the pair frame (no transform).
-template <bool WANT_G, bool IDENT>
+// MODE: SdfMode (kValue leaves g untouched, kSurfGrad leaves phi untouched
+// for polytopes).  IDENT: the body is A, whose frame is the pair frame.
+template <int MODE, bool IDENT>
 __device__ __forceinline__ void sdf_body(const BodyView& B, const D3& x, const Temp& T, double& phi, D3& g) {
   D3 l = x;
   if (!IDENT) {
@@ -251,9 +269,9 @@ __device__ __forceinline__ void sdf_body(const BodyView& B, const D3& x, const T
            B.R[2] * dx + B.R[5] * dy + B.R[8] * dz);
   }
   D3 lg;
-  if (B.type == CM_POLYTOPE) sdf_poly<WANT_G>(B.planes, B.nf, l, T, phi, lg);
+  if (B.type == CM_POLYTOPE) sdf_poly<MODE>(B.planes, B.nf, l, T, phi, lg);
   else sdf_analytic(B.type, B.p, l, phi, lg);
-  if (WANT_G) {
+  if (MODE != kValue) {
     if (IDENT) g = lg;
     else g = d3(B.R[0] * lg.x + B.R[1] * lg.y + B.R[2] * lg.z, B.R[3] * lg.x + B.R[4] * lg.y + B.R[5] * lg.z,
                 B.R[6] * lg.x + B.R[7] * lg.y + B.R[8] * lg.z);
@@ -357,10 +375,10 @@ __device__ __forceinline__ void ee_candidates(const D3& a0, const D3& t1, const 
   const D3 nb = d3(q.de.x * in, q.de.y * in, q.de.z * in);
   double phiB1, phiA2, dum;
   D3 gA, gB, dg;
-  sdf_body<false, false>(B, e1, T, phiB1, dg);
-  sdf_body<true, true>(A, e1, T, dum, gA);
-  sdf_body<false, true>(A, e2, T, phiA2, dg);
-  sdf_body<true, false>(B, e2, T, dum, gB);
+  sdf_body<kValue, false>(B, e1, T, phiB1, dg);
+  sdf_body<kSurfGrad, true>(A, e1, T, dum, gA);     // e1 lies on an edge of A
+  sdf_body<kValue, true>(A, e2, T, phiA2, dg);
+  sdf_body<kSurfGrad, false>(B, e2, T, dum, gB);    // e2 lies on an edge of B
   const double gam1 = tanh64(dot(gB, nb), T);
   const double gam2 = tanh64(-dot(gA, nb), T);
   const double base = q.log_con + lsig(-dot(gA, gB), T);
@@ -387,7 +405,7 @@ __device__ __forceinline__ void vs_candidate(const D3& v, const BodyView& other,
                                              Cand& c) {
   double phi;
   D3 g;
-  sdf_body<true, OTHER_IS_A>(other, v, T, phi, g);
+  sdf_body<kFull, OTHER_IS_A>(other, v, T, phi, g);
   const double in = sgn * rcp64(sqrt(T.tau + dot(g, g)));
   c.p = v;
   c.n = d3(g.x * in, g.y * in, g.z * in);
