@@ -30,6 +30,11 @@ __device__ __forceinline__ void lsig_d(double u, const Temp& T, double& du, doub
   dtau = -u * om * T.inv_tau * T.inv_tau;
 }
 
+// A staged face plane (scaled by log2(e) / tau) back in length units.
+__device__ __forceinline__ double4 unscaled(const double4& q, const Temp& T) {
+  return make_double4(q.x * T.tl, q.y * T.tl, q.z * T.tl, q.w * T.tl);
+}
+
 // Wave sum of a float (all 64 lanes must participate).
 __device__ __forceinline__ float wave_sumf(float v) {
 #pragma unroll
@@ -108,12 +113,12 @@ __device__ __forceinline__ D3 sdf_local_bwd(int type, const float* p, const doub
   // polytope: phi = tau LSE(y / tau), y_f = n_f . l - o_f, g = sum_f pi_f n_f
   double m = -1e300;
   for (int f = 0; f < nf; ++f) {
-    const double4 q = pl[f];
+    const double4 q = unscaled(pl[f], T);
     m = fmax(m, fma(q.x, l.x, fma(q.y, l.y, fma(q.z, l.z, -q.w))));
   }
   double S = 0.0, gx = 0.0, gy = 0.0, gz = 0.0, py = 0.0;
   for (int f = 0; f < nf; ++f) {
-    const double4 q = pl[f];
+    const double4 q = unscaled(pl[f], T);
     const double yv = fma(q.x, l.x, fma(q.y, l.y, fma(q.z, l.z, -q.w)));
     const double e = double(ex2f(float((yv - m) * T.c)));
     S += e; gx = fma(e, q.x, gx); gy = fma(e, q.y, gy); gz = fma(e, q.z, gz);
@@ -128,7 +133,7 @@ __device__ __forceinline__ D3 sdf_local_bwd(int type, const float* p, const doub
   D3 lb = d3(0.0, 0.0, 0.0);
   double tz = 0.0;
   for (int f = 0; f < nf; ++f) {
-    const double4 q = pl[f];
+    const double4 q = unscaled(pl[f], T);
     const double yv = fma(q.x, l.x, fma(q.y, l.y, fma(q.z, l.z, -q.w)));
     const double pi = double(ex2f(float((yv - m) * T.c))) * iS;
     const double zb = pi * (gb.x * q.x + gb.y * q.y + gb.z * q.z - gbg);   // softmax adjoint of g

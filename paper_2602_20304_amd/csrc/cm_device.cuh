@@ -93,6 +93,25 @@ __device__ __forceinline__ double exp64n(double x) {
   p = fma(p, r, 1.0);
   return ldexp(p, int(n));
 }
+
+// 2^a for a <= 1000 to ~1e-15 relative in float64: a = n + r with r = a - n
+// exact, then the degree-9 Taylor polynomial of e^(r ln 2), |r ln 2| <= 0.35.
+__device__ __forceinline__ double exp2_64(double a) {
+  if (a < -1000.0) return 0.0;
+  const double n = rint(a);
+  const double t = (a - n) * kLn2;
+  double p = 2.7557319223985893e-06;
+  p = fma(p, t, 2.4801587301587302e-05);
+  p = fma(p, t, 1.9841269841269841e-04);
+  p = fma(p, t, 1.3888888888888889e-03);
+  p = fma(p, t, 8.3333333333333333e-03);
+  p = fma(p, t, 4.1666666666666667e-02);
+  p = fma(p, t, 1.6666666666666667e-01);
+  p = fma(p, t, 0.5);
+  p = fma(p, t, 1.0);
+  p = fma(p, t, 1.0);
+  return ldexp(p, int(n));
+}
 // sigma(u / tau) in float64
 __device__ __forceinline__ double sig64(double u, const Temp& T) {
   const double e = exp64n(-fabs(u) * T.inv_tau);
@@ -181,25 +200,26 @@ __device__ __forceinline__ void sdf_analytic(int type, const float* p, const D3&
 // boundary (a witness point on one of its edges).
 enum SdfMode { kValue = 0, kFull = 1, kSurfGrad = 2 };
 
-// tau-LSE over body-frame planes pd[f] = (n.xyz, o) (float64, LDS):
-// phi = LSE_tau(n . x - o); gradient = softmax-weighted sum of normals.
-// The value sums float32 exponentials shifted by the largest plane value
-// (its error is tau times their relative error); a plane more than 30
-// binary orders below the largest for every lane of the wave adds nothing
-// a float32 sum can hold (< 2^-30 per plane) and skips its exponential.
-// The gradient enters the clashing indicator divided by tau, so its softmax
-// weights are float64; a plane whose weight is below e^-25 relative to the
-// largest for every lane of the wave is skipped (< 2e-11 per plane).  At a
-// point on the polytope's own boundary the largest plane value is 0
-// (convexity), so kSurfGrad shifts by 0 and needs no max pass and no value
-// sum; a smoothed witness can sit past an edge's end by at most ~0.28 tau
-// times the edge length, which keeps every shifted exponent below ~0.3.
+// tau-LSE over body-frame planes, staged in LDS pre-scaled by c = log2(e)/tau:
+// pd[f] = c (n.xyz, o).  With y_f = n_f . x - o_f and y'_f = c y_f,
+// phi = LSE_tau(y) = tau ln 2 (m' + log2 sum_f 2^(y'_f - m')), m' = max y'_f,
+// and the gradient is the softmax-weighted sum of the normals (the scale c
+// cancels in the normalised weights).  The value sums float32 powers of two
+// (its error is tau times their relative error).  The gradient enters the
+// clashing indicator divided by tau, so its weights are float64; a plane
+// whose weight is below 2^-36 (~e^-25) relative to the largest for every lane
+// of the wave is skipped (< 2e-11 per plane).  At a point on the polytope's
+// own boundary the largest plane value is 0 (convexity), so kSurfGrad shifts
+// by 0 and needs no max pass and no value sum; a smoothed witness can sit
+// past an edge's end by at most ~0.28 tau times the edge length, which keeps
+// every shifted exponent below ~0.4.
 template <int MODE>
 __device__ __forceinline__ void sdf_poly(const double4* __restrict__ pd, int nf, const D3& x, const Temp& T,
                                          double& phi, D3& g) {
   double m = 0.0;
   if (MODE != kSurfGrad) {
     m = -1e300;
+#pragma unroll 2
     for (int f = 0; f < nf; ++f) {
       const double4 q = pd[f];
       m = fmax(m, fma(q.x, x.x, fma(q.y, x.y, fma(q.z, x.z, -q.w))));
@@ -207,26 +227,23 @@ __device__ __forceinline__ void sdf_poly(const double4* __restrict__ pd, int nf,
   }
   float s = 0.f;
   double S = 0.0, ax = 0.0, ay = 0.0, az = 0.0;
+#pragma unroll 2
   for (int f = 0; f < nf; ++f) {
     const double4 q = pd[f];
-    const double yv = fma(q.x, x.x, fma(q.y, x.y, fma(q.z, x.z, -q.w)));
-    if (MODE != kSurfGrad) {
-      const double a = (yv - m) * T.c;
-      if (__any(a > -30.0)) s += ex2f(float(a));
-    }
+    const double a = fma(q.x, x.x, fma(q.y, x.y, fma(q.z, x.z, -q.w))) - m;
+    if (MODE != kSurfGrad) s += ex2f(float(a));
     if (MODE != kValue) {
-      const double z = (yv - m) * T.inv_tau;
-      const bool sig = z > -25.0;
+      const bool sig = a > -36.0;
       if (__any(sig)) {
-        const double e = sig ? exp64n(z) : 0.0;
+        const double e = sig ? exp2_64(a) : 0.0;
         S += e;
         ax = fma(e, q.x, ax); ay = fma(e, q.y, ay); az = fma(e, q.z, az);
       }
     }
   }
-  if (MODE != kSurfGrad) phi = m + T.tl * double(lg2f(s));
+  if (MODE != kSurfGrad) phi = T.tl * (m + double(lg2f(s)));
   if (MODE != kValue) {
-    const double inv = S > 0.0 ? rcp64(S) : 0.0;
+    const double inv = S > 0.0 ? T.tl * rcp64(S) : 0.0;
     g = d3(ax * inv, ay * inv, az * inv);
   }
 }
@@ -237,7 +254,7 @@ struct BodyView {
   float p[4];
   double R[9];   // body frame -> pair frame rotation (row-major); unused for A
   double t[3];   // body origin in the pair frame; unused for A
-  const double4* planes;  // LDS, body frame (polytopes): (n.xyz, o) in float64
+  const double4* planes;  // LDS, body frame (polytopes): c (n.xyz, o), c = log2(e) / tau
 };
 
 // Load a body view that every lane of the workgroup shares from LDS into

@@ -3,7 +3,8 @@
 // One workgroup owns one body pair at a time.  Phases (all in the frame of
 // body A):
 //   setup    pose ingest: R_A, t_A, and body B's pose relative to A
-//   stage    edges of both bodies (FP64 SoA) and face planes (body frames) in LDS
+//   stage    edges of both bodies (FP64 SoA) and face planes (body frames,
+//            scaled by log2(e) / tau) in LDS
 //   scores   V-S candidates both ways (Sec. IV-C); E-E distance pass with the
 //            row / column LSE of the unsigned-distance matrix (nearest-neighbour
 //            indicators, Sec. IV-D); E-E candidate pass (witness QP, SDF queries,
@@ -216,7 +217,10 @@ struct PairEngine {
       const bool isA = i < nfA;
       const int f = isA ? GA->f_off + i : GB->f_off + (i - nfA);
       const int j = isA ? i : i - nfA;
-      (isA ? sPA : sPB)[j] = make_double4(tb.fnx[f], tb.fny[f], tb.fnz[f], tb.fo[f]);
+      // planes pre-scaled by c = log2(e) / tau (the polytope SDF works in
+      // binary-exponent units)
+      const double c = T.c;
+      (isA ? sPA : sPB)[j] = make_double4(c * tb.fnx[f], c * tb.fny[f], c * tb.fnz[f], c * tb.fo[f]);
     }
     __syncthreads();
   }
