@@ -51,7 +51,7 @@ struct BwdArgs {
 };
 
 template <int BLOCK, int KMAX>
-__global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, ParamsDev prm, OutDev fwd, BwdArgs ga,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void collide_bwd(Tables tb, BatchDev bt, ParamsDev prm, OutDev fwd, BwdArgs ga,
                                                      float* __restrict__ scratch, long long scratch_stride, int maxV,
                                                      int maxE, int maxF, unsigned* err) {
   extern __shared__ float4 smem4[];
@@ -97,6 +97,7 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
 
     // ------------------------------------------------ recompute the forward
     P.stage();
+    P.cull();
     double tk[KMAX];
     P.scores(tk);
     P.topk(tk);

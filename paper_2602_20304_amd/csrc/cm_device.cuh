@@ -274,11 +274,88 @@ __device__ __forceinline__ BodyView load_uniform(const BodyView& src, bool with_
   return v;
 }
 
+// A per-lane subset of a polytope's faces (bit f of word f / 64); n = 0
+// means all faces.
+struct FaceMask {
+  unsigned long long w[2];
+  int n;
+};
+
+__device__ __forceinline__ unsigned long long uni64(unsigned long long v) {
+  const int lo = __builtin_amdgcn_readfirstlane(int(v & 0xffffffffull));
+  const int hi = __builtin_amdgcn_readfirstlane(int(v >> 32));
+  return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+}
+
+// OR over the wave (inactive lanes may add stray bits; callers test each
+// lane's own bit).
+__device__ __forceinline__ unsigned long long wave_or64(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, 64);
+  return v;
+}
+
+// sdf_poly restricted to the faces of each lane's mask, visited in
+// increasing face order, so that a lane's result does not depend on the
+// other lanes.  UNI: every active lane of the wave holds the same mask.
+template <int MODE, bool UNI>
+__device__ __forceinline__ void sdf_poly_masked(const double4* __restrict__ pd, const FaceMask& mk, const D3& x,
+                                                const Temp& T, double& phi, D3& g) {
+  unsigned long long u[2];
+#pragma unroll
+  for (int w = 0; w < 2; ++w) u[w] = w < mk.n ? uni64(UNI ? mk.w[w] : wave_or64(mk.w[w])) : 0ull;
+  double m = 0.0;
+  if (MODE != kSurfGrad) {
+    m = -1e300;
+#pragma unroll
+    for (int w = 0; w < 2; ++w) {
+      unsigned long long bits = u[w];
+      while (bits) {
+        const int b = __builtin_ctzll(bits);
+        bits &= bits - 1ull;
+        const double4 q = pd[w * 64 + b];
+        const double y = fma(q.x, x.x, fma(q.y, x.y, fma(q.z, x.z, -q.w)));
+        if (UNI || ((mk.w[w] >> b) & 1ull)) m = fmax(m, y);
+      }
+    }
+  }
+  float s = 0.f;
+  double S = 0.0, ax = 0.0, ay = 0.0, az = 0.0;
+#pragma unroll
+  for (int w = 0; w < 2; ++w) {
+    unsigned long long bits = u[w];
+    while (bits) {
+      const int b = __builtin_ctzll(bits);
+      bits &= bits - 1ull;
+      const bool inc = UNI || ((mk.w[w] >> b) & 1ull);
+      const double4 q = pd[w * 64 + b];
+      const double a = fma(q.x, x.x, fma(q.y, x.y, fma(q.z, x.z, -q.w))) - m;
+      if (MODE != kSurfGrad) s += inc ? ex2f(float(a)) : 0.f;
+      if (MODE != kValue) {
+        const bool sig = inc && a > -36.0;
+        if (__any(sig)) {
+          const double e = sig ? exp2_64(a) : 0.0;
+          S += e;
+          ax = fma(e, q.x, ax); ay = fma(e, q.y, ay); az = fma(e, q.z, az);
+        }
+      }
+    }
+  }
+  if (MODE != kSurfGrad) phi = T.tl * (m + double(lg2f(s)));
+  if (MODE != kValue) {
+    const double inv = S > 0.0 ? T.tl * rcp64(S) : 0.0;
+    g = d3(ax * inv, ay * inv, az * inv);
+  }
+}
+
 // SDF of a body at a pair-frame point; gradient returned in the pair frame.
 // MODE: SdfMode (kValue leaves g untouched, kSurfGrad leaves phi untouched
 // for polytopes).  IDENT: the body is A, whose frame is the pair frame.
-template <int MODE, bool IDENT>
-__device__ __forceinline__ void sdf_body(const BodyView& B, const D3& x, const Temp& T, double& phi, D3& g) {
+// mk: face subset for polytopes (mk.n == 0: all faces); UNI as in
+// sdf_poly_masked.
+template <int MODE, bool IDENT, bool UNI = true>
+__device__ __forceinline__ void sdf_body(const BodyView& B, const D3& x, const Temp& T, double& phi, D3& g,
+                                         const FaceMask* mk = nullptr) {
   D3 l = x;
   if (!IDENT) {
     const double dx = x.x - B.t[0], dy = x.y - B.t[1], dz = x.z - B.t[2];
@@ -286,8 +363,12 @@ __device__ __forceinline__ void sdf_body(const BodyView& B, const D3& x, const T
            B.R[2] * dx + B.R[5] * dy + B.R[8] * dz);
   }
   D3 lg;
-  if (B.type == CM_POLYTOPE) sdf_poly<MODE>(B.planes, B.nf, l, T, phi, lg);
-  else sdf_analytic(B.type, B.p, l, phi, lg);
+  if (B.type == CM_POLYTOPE) {
+    if (mk && mk->n > 0) sdf_poly_masked<MODE, UNI>(B.planes, *mk, l, T, phi, lg);
+    else sdf_poly<MODE>(B.planes, B.nf, l, T, phi, lg);
+  } else {
+    sdf_analytic(B.type, B.p, l, phi, lg);
+  }
   if (MODE != kValue) {
     if (IDENT) g = lg;
     else g = d3(B.R[0] * lg.x + B.R[1] * lg.y + B.R[2] * lg.z, B.R[3] * lg.x + B.R[4] * lg.y + B.R[5] * lg.z,
@@ -380,10 +461,14 @@ struct Cand {
 // activity indicator): sign via soft sign of the opposing SDF gradient,
 // penetration via the opposing SDF value, clashing via both gradients,
 // nearest neighbour via the row / column LSE of the unsigned distances.
-// q is the edge pair's QP solution (ee_qp).
+// q is the edge pair's QP solution (ee_qp).  mA / mB: faces of A / B that
+// can matter on A's edge segment (the queries at e1); UNI as in
+// sdf_poly_masked.
+template <bool UNI>
 __device__ __forceinline__ void ee_candidates(const D3& a0, const D3& t1, const D3& b0, const D3& t2, const EEQP& q,
                                               double row_lse, double col_lse, const BodyView& A, const BodyView& B,
-                                              double eps_n, const Temp& T, Cand& c1, Cand& c2) {
+                                              double eps_n, const Temp& T, const FaceMask& mA, const FaceMask& mB,
+                                              Cand& c1, Cand& c2) {
   const D3 e1 = d3(a0.x + q.al1 * t1.x, a0.y + q.al1 * t1.y, a0.z + q.al1 * t1.z);
   const D3 e2 = d3(b0.x + q.al2 * t2.x, b0.y + q.al2 * t2.y, b0.z + q.al2 * t2.z);
   const double dsq = dot(q.de, q.de);
@@ -392,10 +477,10 @@ __device__ __forceinline__ void ee_candidates(const D3& a0, const D3& t1, const 
   const D3 nb = d3(q.de.x * in, q.de.y * in, q.de.z * in);
   double phiB1, phiA2, dum;
   D3 gA, gB, dg;
-  sdf_body<kValue, false>(B, e1, T, phiB1, dg);
-  sdf_body<kSurfGrad, true>(A, e1, T, dum, gA);     // e1 lies on an edge of A
+  sdf_body<kValue, false, UNI>(B, e1, T, phiB1, dg, &mB);
+  sdf_body<kSurfGrad, true, UNI>(A, e1, T, dum, gA, &mA);   // e1 lies on an edge of A
   sdf_body<kValue, true>(A, e2, T, phiA2, dg);
-  sdf_body<kSurfGrad, false>(B, e2, T, dum, gB);    // e2 lies on an edge of B
+  sdf_body<kSurfGrad, false>(B, e2, T, dum, gB);            // e2 lies on an edge of B
   const double gam1 = tanh64(dot(gB, nb), T);
   const double gam2 = tanh64(-dot(gA, nb), T);
   const double base = q.log_con + lsig(-dot(gA, gB), T);

@@ -175,6 +175,7 @@ void collide_fwd(Tables tb, BatchDev bt, ParamsDev prm, OutDev out,
     const int pi = ord ? ord[item] : item;
     if (P.setup(out.pairs[pi], out.pairs[out.capacity + pi], err)) {
       P.stage();
+      P.cull();
       double tk[KMAX];
       P.scores(tk);
       P.topk(tk);

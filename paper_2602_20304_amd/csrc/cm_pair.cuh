@@ -44,8 +44,14 @@ struct Rec {
 };
 
 struct LdsLayout {
-  int eA, eB, row, col, red, top, rec, acc, pA, pB, cnt, bytes;
+  int eA, eB, row, col, red, top, rec, acc, pA, pB, cnt, mA, mB, bytes;
 };
+
+// 64-bit words of a per-edge face mask (0: culling off, faces > 128).
+__host__ __device__ inline int mask_words(int maxF) {
+  const int w = (maxF + 63) / 64;
+  return w <= 2 ? w : 0;
+}
 
 __host__ __device__ inline LdsLayout lds_layout(int maxE, int maxF, int block) {
   LdsLayout L;
@@ -61,6 +67,9 @@ __host__ __device__ inline LdsLayout lds_layout(int maxE, int maxF, int block) {
   L.pA = o; o += 32 * maxF;    // double4 planes (n.xyz, o)
   L.pB = o; o += 32 * maxF;
   L.cnt = o; o += 64;
+  o = (o + 7) & ~7;
+  L.mA = o; o += 8 * mask_words(maxF) * maxE;   // A's faces near each edge segment of A
+  L.mB = o; o += 8 * mask_words(maxF) * maxE;   // B's faces near each edge segment of A
   L.bytes = (o + 15) & ~15;
   return L;
 }
@@ -83,6 +92,9 @@ struct PairEngine {
   Rec* sRec;
   double* sAcc;   // [9K] unnormalised SoftSort sums (1, p, nu, d, w) per row
   int* sCnt;
+  unsigned long long* sMA;   // [maxE][MW] face masks, see cull()
+  unsigned long long* sMB;
+  int MW;
   double* Dbuf;   // [maxE^2] unsigned distance of edge pair (k, l) at k * neB + l
   double* Al1;    // [maxE^2] QP solution al1, al2 and ln con of the same edge pair
   double* Al2;
@@ -114,6 +126,9 @@ struct PairEngine {
     sRec = reinterpret_cast<Rec*>(smem + L.rec);
     sAcc = reinterpret_cast<double*>(smem + L.acc);
     sCnt = reinterpret_cast<int*>(smem + L.cnt);
+    sMA = reinterpret_cast<unsigned long long*>(smem + L.mA);
+    sMB = reinterpret_cast<unsigned long long*>(smem + L.mB);
+    MW = mask_words(maxF_);
     const long long mm = (long long)maxE_ * maxE_;
     Dbuf = reinterpret_cast<double*>(slot);
     Al1 = Dbuf + mm;
@@ -225,20 +240,102 @@ struct PairEngine {
     __syncthreads();
   }
 
+  // ------------------------------------------------------------ cull
+  // Per edge segment k of A (extended to the witness range of the smoothed
+  // QP, alpha in [-0.3 tau, 1 + 0.3 tau]): the faces of each polytope whose
+  // plane can come within 38 binary orders (scaled units) of the largest
+  // plane value at some point of the segment.  Plane values are linear
+  // along the segment, so face g is dropped when
+  // max(y'_g(p0), y'_g(p1)) < max_f min(y'_f(p0), y'_f(p1)) - 38, which
+  // bounds its term in the LSE and in the gradient softmax below 2^-38.
+  __device__ void cull() {
+    if (MW == 0) return;
+    const double ext = 0.3 * T.tau;
+    for (int k = tid; k < A.ne; k += BLOCK) {
+      D3 a0, t1;
+      EA.get(k, a0, t1);
+      const D3 p0 = d3(a0.x - ext * t1.x, a0.y - ext * t1.y, a0.z - ext * t1.z);
+      const D3 p1 = d3(a0.x + (1.0 + ext) * t1.x, a0.y + (1.0 + ext) * t1.y, a0.z + (1.0 + ext) * t1.z);
+      seg_mask(A, false, p0, p1, sMA + k * MW);
+      seg_mask(B, true, p0, p1, sMB + k * MW);
+    }
+    __syncthreads();
+  }
+  __device__ __forceinline__ void seg_mask(const BodyView& V, bool moved, const D3& p0w, const D3& p1w,
+                                           unsigned long long* out) const {
+    if (V.type != CM_POLYTOPE) {
+      out[0] = ~0ull;
+      if (MW > 1) out[1] = ~0ull;
+      return;
+    }
+    D3 p0 = p0w, p1 = p1w;
+    if (moved) {
+      p0 = d3(V.R[0] * (p0w.x - V.t[0]) + V.R[3] * (p0w.y - V.t[1]) + V.R[6] * (p0w.z - V.t[2]),
+              V.R[1] * (p0w.x - V.t[0]) + V.R[4] * (p0w.y - V.t[1]) + V.R[7] * (p0w.z - V.t[2]),
+              V.R[2] * (p0w.x - V.t[0]) + V.R[5] * (p0w.y - V.t[1]) + V.R[8] * (p0w.z - V.t[2]));
+      p1 = d3(V.R[0] * (p1w.x - V.t[0]) + V.R[3] * (p1w.y - V.t[1]) + V.R[6] * (p1w.z - V.t[2]),
+              V.R[1] * (p1w.x - V.t[0]) + V.R[4] * (p1w.y - V.t[1]) + V.R[7] * (p1w.z - V.t[2]),
+              V.R[2] * (p1w.x - V.t[0]) + V.R[5] * (p1w.y - V.t[1]) + V.R[8] * (p1w.z - V.t[2]));
+    }
+    double L = -1e300;
+    for (int f = 0; f < V.nf; ++f) {
+      const double4 q = V.planes[f];
+      const double y0 = fma(q.x, p0.x, fma(q.y, p0.y, fma(q.z, p0.z, -q.w)));
+      const double y1 = fma(q.x, p1.x, fma(q.y, p1.y, fma(q.z, p1.z, -q.w)));
+      L = fmax(L, fmin(y0, y1));
+    }
+    unsigned long long m0 = 0ull, m1 = 0ull;
+    for (int f = 0; f < V.nf; ++f) {
+      const double4 q = V.planes[f];
+      const double y0 = fma(q.x, p0.x, fma(q.y, p0.y, fma(q.z, p0.z, -q.w)));
+      const double y1 = fma(q.x, p1.x, fma(q.y, p1.y, fma(q.z, p1.z, -q.w)));
+      const unsigned long long bit = fmax(y0, y1) >= L - 38.0 ? 1ull << (f & 63) : 0ull;
+      if (f < 64) m0 |= bit;
+      else m1 |= bit;
+    }
+    out[0] = m0;
+    if (MW > 1) out[1] = m1;
+  }
+
   // ------------------------------------------------------------ candidates
   __device__ __forceinline__ void vs(int i, Cand& c) const {
     if (i < A.nv) vs_candidate<false>(vertex<true>(*GA, i, A), B, -1.0, T, c);
     else vs_candidate<true>(vertex<false>(*GB, i - A.nv, B), A, 1.0, T, c);
   }
+  // Face masks of the block of 64 edge pairs holding edge pair i = k neB + l:
+  // the union of the per-edge masks over the rows the block spans (usually
+  // one or two), so that the face subset of every query depends on (k, l)
+  // only, whichever lanes evaluate it.
+  __device__ __forceinline__ void block_masks(int i, FaceMask& mA, FaceMask& mB) const {
+    const int neB = B.ne;
+    const int b0 = i & ~63;
+    const int k0 = b0 / neB, k1 = min(A.ne - 1, (b0 + 63) / neB);
+    mA.w[0] = mA.w[1] = mB.w[0] = mB.w[1] = 0ull;
+    mA.n = mB.n = MW;
+    for (int k = k0; k <= k1; ++k) {
+      mA.w[0] |= sMA[k * MW];
+      mB.w[0] |= sMB[k * MW];
+      if (MW > 1) {
+        mA.w[1] |= sMA[k * MW + 1];
+        mB.w[1] |= sMB[k * MW + 1];
+      }
+    }
+  }
+
   // both candidates of edge pair (k, l) from the QP solution stored by the
-  // distance pass
+  // distance pass.  UNI: all active lanes of the wave lie in the same block
+  // of 64 edge pairs (the candidate pass); otherwise faces are included per
+  // lane (the recomputes of filtered candidates), with identical results.
+  template <bool UNI>
   __device__ __forceinline__ void ee(int k, int l, Cand& c1, Cand& c2) const {
     D3 a0, t1, b0, t2;
     EA.get(k, a0, t1);
     EB.get(l, b0, t2);
     const int i = k * B.ne + l;
     const EEQP q = ee_from_alpha(a0, t1, b0, t2, Al1[i], Al2[i], Lcon[i]);
-    ee_candidates(a0, t1, b0, t2, q, sRow[k], sCol[l], A, B, eps_n, T, c1, c2);
+    FaceMask mA, mB;
+    block_masks(i, mA, mB);
+    ee_candidates<UNI>(a0, t1, b0, t2, q, sRow[k], sCol[l], A, B, eps_n, T, mA, mB, c1, c2);
   }
   // candidate idx in the fixed order: A's vertices, B's vertices, E-E (k, l)
   // row-major with witness 1 before witness 2
@@ -250,7 +347,7 @@ struct PairEngine {
       const int ee_i = e >> 1;
       const int k = ee_i / B.ne, l = ee_i - k * B.ne;
       Cand c1, c2;
-      ee(k, l, c1, c2);
+      ee<false>(k, l, c1, c2);
       c = (e & 1) ? c2 : c1;
     }
   }
@@ -331,7 +428,7 @@ struct PairEngine {
       const int sk = BLOCK / neB, sl = BLOCK - sk * neB;
       for (int idx = tid; idx < nee; idx += BLOCK) {
         Cand c1, c2;
-        ee(k, l, c1, c2);
+        ee<true>(k, l, c1, c2);
         Sbuf[nvs + 2 * idx] = float(c1.s);
         Sbuf[nvs + 2 * idx + 1] = float(c2.s);
         tk_insert<KMAX>(tk, c1.s);
