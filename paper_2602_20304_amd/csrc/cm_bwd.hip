@@ -51,13 +51,13 @@ struct BwdArgs {
 };
 
 template <int BLOCK, int KMAX>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void collide_bwd(Tables tb, BatchDev bt, ParamsDev prm, OutDev fwd, BwdArgs ga,
+__global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, ParamsDev prm, OutDev fwd, BwdArgs ga,
                                                      float* __restrict__ scratch, long long scratch_stride, int maxV,
                                                      int maxE, int maxF, unsigned* err) {
   extern __shared__ float4 smem4[];
   char* smem = reinterpret_cast<char*>(smem4);
   __shared__ PairShared ps;
-  PairEngine<BLOCK, KMAX> P(ps, smem, tb, bt, prm, scratch + (long long)blockIdx.x * scratch_stride, maxV, maxE, maxF);
+  PairEngine<BLOCK, KMAX, false> P(ps, smem, tb, bt, prm, scratch + (long long)blockIdx.x * scratch_stride, maxV, maxE, maxF);
   const BwdLds L = bwd_layout(lds_layout(maxE, maxF, BLOCK).bytes, maxV, maxE, maxF, BLOCK);
   float* vA3 = reinterpret_cast<float*>(smem + L.vA);
   float* vB3 = reinterpret_cast<float*>(smem + L.vB);

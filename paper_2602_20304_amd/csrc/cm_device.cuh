@@ -299,11 +299,15 @@ __device__ __forceinline__ unsigned long long wave_or64(unsigned long long v) {
 // increasing face order, so that a lane's result does not depend on the
 // other lanes.  UNI: every active lane of the wave holds the same mask.
 template <int MODE, bool UNI>
-__device__ __forceinline__ void sdf_poly_masked(const double4* __restrict__ pd, const FaceMask& mk, const D3& x,
-                                                const Temp& T, double& phi, D3& g) {
+__device__ __forceinline__ void sdf_poly_masked(const double4* __restrict__ pd, int nf, const FaceMask& mk,
+                                                const D3& x, const Temp& T, double& phi, D3& g) {
+  // the union visits existing faces only (inactive lanes can contribute
+  // stray bits to the wave OR)
+  const unsigned long long valid[2] = {nf >= 64 ? ~0ull : (1ull << nf) - 1ull,
+                                       nf >= 128 ? ~0ull : (nf > 64 ? (1ull << (nf - 64)) - 1ull : 0ull)};
   unsigned long long u[2];
 #pragma unroll
-  for (int w = 0; w < 2; ++w) u[w] = w < mk.n ? uni64(UNI ? mk.w[w] : wave_or64(mk.w[w])) : 0ull;
+  for (int w = 0; w < 2; ++w) u[w] = w < mk.n ? uni64(UNI ? mk.w[w] : wave_or64(mk.w[w])) & valid[w] : 0ull;
   double m = 0.0;
   if (MODE != kSurfGrad) {
     m = -1e300;
@@ -364,7 +368,7 @@ __device__ __forceinline__ void sdf_body(const BodyView& B, const D3& x, const T
   }
   D3 lg;
   if (B.type == CM_POLYTOPE) {
-    if (mk && mk->n > 0) sdf_poly_masked<MODE, UNI>(B.planes, *mk, l, T, phi, lg);
+    if (mk && mk->n > 0) sdf_poly_masked<MODE, UNI>(B.planes, B.nf, *mk, l, T, phi, lg);
     else sdf_poly<MODE>(B.planes, B.nf, l, T, phi, lg);
   } else {
     sdf_analytic(B.type, B.p, l, phi, lg);

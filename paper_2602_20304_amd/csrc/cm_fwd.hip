@@ -155,7 +155,7 @@ void collide_fwd(Tables tb, BatchDev bt, ParamsDev prm, OutDev out,
                                                      unsigned* err) {
   extern __shared__ float4 smem4[];
   __shared__ PairShared ps;
-  PairEngine<BLOCK, KMAX> P(ps, reinterpret_cast<char*>(smem4), tb, bt, prm,
+  PairEngine<BLOCK, KMAX, true> P(ps, reinterpret_cast<char*>(smem4), tb, bt, prm,
                             scratch + (long long)blockIdx.x * scratch_stride, maxV, maxE, maxF);
   const int tid = threadIdx.x;
   const int K = prm.K;

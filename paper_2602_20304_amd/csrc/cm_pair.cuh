@@ -74,7 +74,10 @@ __host__ __device__ inline LdsLayout lds_layout(int maxE, int maxF, int block) {
   return L;
 }
 
-template <int BLOCK, int KMAX>
+// CULL: the witness queries on A's edges use the per-segment face masks
+// (forward kernel); without it every face is visited (adjoint kernel, which
+// recomputes its own forward and stays self-consistent).
+template <int BLOCK, int KMAX, bool CULL>
 struct PairEngine {
   static constexpr int NW = BLOCK / 64;
   static constexpr int NSLOT = (9 * CM_MAX_K + BLOCK - 1) / BLOCK;
@@ -128,7 +131,7 @@ struct PairEngine {
     sCnt = reinterpret_cast<int*>(smem + L.cnt);
     sMA = reinterpret_cast<unsigned long long*>(smem + L.mA);
     sMB = reinterpret_cast<unsigned long long*>(smem + L.mB);
-    MW = mask_words(maxF_);
+    MW = CULL ? mask_words(maxF_) : 0;
     const long long mm = (long long)maxE_ * maxE_;
     Dbuf = reinterpret_cast<double*>(slot);
     Al1 = Dbuf + mm;
@@ -249,7 +252,7 @@ struct PairEngine {
   // max(y'_g(p0), y'_g(p1)) < max_f min(y'_f(p0), y'_f(p1)) - 38, which
   // bounds its term in the LSE and in the gradient softmax below 2^-38.
   __device__ void cull() {
-    if (MW == 0) return;
+    if (!CULL || MW == 0) return;
     const double ext = 0.3 * T.tau;
     for (int k = tid; k < A.ne; k += BLOCK) {
       D3 a0, t1;
@@ -307,11 +310,12 @@ struct PairEngine {
   // one or two), so that the face subset of every query depends on (k, l)
   // only, whichever lanes evaluate it.
   __device__ __forceinline__ void block_masks(int i, FaceMask& mA, FaceMask& mB) const {
+    mA.w[0] = mA.w[1] = mB.w[0] = mB.w[1] = 0ull;
+    mA.n = mB.n = MW;
+    if (!CULL || MW == 0) return;   // culling off: no mask storage
     const int neB = B.ne;
     const int b0 = i & ~63;
     const int k0 = b0 / neB, k1 = min(A.ne - 1, (b0 + 63) / neB);
-    mA.w[0] = mA.w[1] = mB.w[0] = mB.w[1] = 0ull;
-    mA.n = mB.n = MW;
     for (int k = k0; k <= k1; ++k) {
       mA.w[0] |= sMA[k * MW];
       mB.w[0] |= sMB[k * MW];
