@@ -274,8 +274,8 @@ __device__ __forceinline__ BodyView load_uniform(const BodyView& src, bool with_
   return v;
 }
 
-// A per-lane subset of a polytope's faces (bit f of word f / 64); n = 0
-// means all faces.
+// A subset of a polytope's faces (bit f of word f / 64); n = 0 means all
+// faces.
 struct FaceMask {
   unsigned long long w[2];
   int n;
@@ -287,27 +287,16 @@ __device__ __forceinline__ unsigned long long uni64(unsigned long long v) {
   return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
 }
 
-// OR over the wave (inactive lanes may add stray bits; callers test each
-// lane's own bit).
-__device__ __forceinline__ unsigned long long wave_or64(unsigned long long v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, 64);
-  return v;
-}
-
-// sdf_poly restricted to the faces of each lane's mask, visited in
-// increasing face order, so that a lane's result does not depend on the
-// other lanes.  UNI: every active lane of the wave holds the same mask.
-template <int MODE, bool UNI>
+// sdf_poly restricted to the faces of a mask that every active lane of the
+// wave shares (wave-uniform loop over its bits, increasing face order).
+template <int MODE>
 __device__ __forceinline__ void sdf_poly_masked(const double4* __restrict__ pd, int nf, const FaceMask& mk,
                                                 const D3& x, const Temp& T, double& phi, D3& g) {
-  // the union visits existing faces only (inactive lanes can contribute
-  // stray bits to the wave OR)
   const unsigned long long valid[2] = {nf >= 64 ? ~0ull : (1ull << nf) - 1ull,
                                        nf >= 128 ? ~0ull : (nf > 64 ? (1ull << (nf - 64)) - 1ull : 0ull)};
   unsigned long long u[2];
 #pragma unroll
-  for (int w = 0; w < 2; ++w) u[w] = w < mk.n ? uni64(UNI ? mk.w[w] : wave_or64(mk.w[w])) & valid[w] : 0ull;
+  for (int w = 0; w < 2; ++w) u[w] = w < mk.n ? uni64(mk.w[w]) & valid[w] : 0ull;
   double m = 0.0;
   if (MODE != kSurfGrad) {
     m = -1e300;
@@ -318,8 +307,7 @@ __device__ __forceinline__ void sdf_poly_masked(const double4* __restrict__ pd, 
         const int b = __builtin_ctzll(bits);
         bits &= bits - 1ull;
         const double4 q = pd[w * 64 + b];
-        const double y = fma(q.x, x.x, fma(q.y, x.y, fma(q.z, x.z, -q.w)));
-        if (UNI || ((mk.w[w] >> b) & 1ull)) m = fmax(m, y);
+        m = fmax(m, fma(q.x, x.x, fma(q.y, x.y, fma(q.z, x.z, -q.w))));
       }
     }
   }
@@ -331,12 +319,11 @@ __device__ __forceinline__ void sdf_poly_masked(const double4* __restrict__ pd, 
     while (bits) {
       const int b = __builtin_ctzll(bits);
       bits &= bits - 1ull;
-      const bool inc = UNI || ((mk.w[w] >> b) & 1ull);
       const double4 q = pd[w * 64 + b];
       const double a = fma(q.x, x.x, fma(q.y, x.y, fma(q.z, x.z, -q.w))) - m;
-      if (MODE != kSurfGrad) s += inc ? ex2f(float(a)) : 0.f;
+      if (MODE != kSurfGrad) s += ex2f(float(a));
       if (MODE != kValue) {
-        const bool sig = inc && a > -36.0;
+        const bool sig = a > -36.0;
         if (__any(sig)) {
           const double e = sig ? exp2_64(a) : 0.0;
           S += e;
@@ -355,9 +342,9 @@ __device__ __forceinline__ void sdf_poly_masked(const double4* __restrict__ pd, 
 // SDF of a body at a pair-frame point; gradient returned in the pair frame.
 // MODE: SdfMode (kValue leaves g untouched, kSurfGrad leaves phi untouched
 // for polytopes).  IDENT: the body is A, whose frame is the pair frame.
-// mk: face subset for polytopes (mk.n == 0: all faces); UNI as in
-// sdf_poly_masked.
-template <int MODE, bool IDENT, bool UNI = true>
+// mk: face subset for polytopes, shared by every active lane of the wave
+// (null or mk->n == 0: all faces).
+template <int MODE, bool IDENT>
 __device__ __forceinline__ void sdf_body(const BodyView& B, const D3& x, const Temp& T, double& phi, D3& g,
                                          const FaceMask* mk = nullptr) {
   D3 l = x;
@@ -368,7 +355,7 @@ __device__ __forceinline__ void sdf_body(const BodyView& B, const D3& x, const T
   }
   D3 lg;
   if (B.type == CM_POLYTOPE) {
-    if (mk && mk->n > 0) sdf_poly_masked<MODE, UNI>(B.planes, B.nf, *mk, l, T, phi, lg);
+    if (mk && mk->n > 0) sdf_poly_masked<MODE>(B.planes, B.nf, *mk, l, T, phi, lg);
     else sdf_poly<MODE>(B.planes, B.nf, l, T, phi, lg);
   } else {
     sdf_analytic(B.type, B.p, l, phi, lg);
@@ -466,12 +453,11 @@ struct Cand {
 // penetration via the opposing SDF value, clashing via both gradients,
 // nearest neighbour via the row / column LSE of the unsigned distances.
 // q is the edge pair's QP solution (ee_qp).  mA / mB: faces of A / B that
-// can matter on A's edge segment (the queries at e1); UNI as in
-// sdf_poly_masked.
-template <bool UNI>
+// can matter on A's edge segment (the queries at e1), shared by every
+// active lane of the wave, or null (all faces).
 __device__ __forceinline__ void ee_candidates(const D3& a0, const D3& t1, const D3& b0, const D3& t2, const EEQP& q,
                                               double row_lse, double col_lse, const BodyView& A, const BodyView& B,
-                                              double eps_n, const Temp& T, const FaceMask& mA, const FaceMask& mB,
+                                              double eps_n, const Temp& T, const FaceMask* mA, const FaceMask* mB,
                                               Cand& c1, Cand& c2) {
   const D3 e1 = d3(a0.x + q.al1 * t1.x, a0.y + q.al1 * t1.y, a0.z + q.al1 * t1.z);
   const D3 e2 = d3(b0.x + q.al2 * t2.x, b0.y + q.al2 * t2.y, b0.z + q.al2 * t2.z);
@@ -481,8 +467,8 @@ __device__ __forceinline__ void ee_candidates(const D3& a0, const D3& t1, const 
   const D3 nb = d3(q.de.x * in, q.de.y * in, q.de.z * in);
   double phiB1, phiA2, dum;
   D3 gA, gB, dg;
-  sdf_body<kValue, false, UNI>(B, e1, T, phiB1, dg, &mB);
-  sdf_body<kSurfGrad, true, UNI>(A, e1, T, dum, gA, &mA);   // e1 lies on an edge of A
+  sdf_body<kValue, false>(B, e1, T, phiB1, dg, mB);
+  sdf_body<kSurfGrad, true>(A, e1, T, dum, gA, mA);   // e1 lies on an edge of A
   sdf_body<kValue, true>(A, e2, T, phiA2, dg);
   sdf_body<kSurfGrad, false>(B, e2, T, dum, gB);            // e2 lies on an edge of B
   const double gam1 = tanh64(dot(gB, nb), T);

@@ -307,8 +307,7 @@ struct PairEngine {
   }
   // Face masks of the block of 64 edge pairs holding edge pair i = k neB + l:
   // the union of the per-edge masks over the rows the block spans (usually
-  // one or two), so that the face subset of every query depends on (k, l)
-  // only, whichever lanes evaluate it.
+  // one or two).
   __device__ __forceinline__ void block_masks(int i, FaceMask& mA, FaceMask& mB) const {
     mA.w[0] = mA.w[1] = mB.w[0] = mB.w[1] = 0ull;
     mA.n = mB.n = MW;
@@ -327,19 +326,25 @@ struct PairEngine {
   }
 
   // both candidates of edge pair (k, l) from the QP solution stored by the
-  // distance pass.  UNI: all active lanes of the wave lie in the same block
-  // of 64 edge pairs (the candidate pass); otherwise faces are included per
-  // lane (the recomputes of filtered candidates), with identical results.
-  template <bool UNI>
+  // distance pass.  CULLED: every active lane of the wave evaluates an edge
+  // pair of the same block of 64 (the candidate pass), so the block's face
+  // masks apply wave-wide; otherwise (recomputes of filtered candidates)
+  // every face is visited, which differs from the culled value by less
+  // than 2^-38 relative.
+  template <bool CULLED>
   __device__ __forceinline__ void ee(int k, int l, Cand& c1, Cand& c2) const {
     D3 a0, t1, b0, t2;
     EA.get(k, a0, t1);
     EB.get(l, b0, t2);
     const int i = k * B.ne + l;
     const EEQP q = ee_from_alpha(a0, t1, b0, t2, Al1[i], Al2[i], Lcon[i]);
-    FaceMask mA, mB;
-    block_masks(i, mA, mB);
-    ee_candidates<UNI>(a0, t1, b0, t2, q, sRow[k], sCol[l], A, B, eps_n, T, mA, mB, c1, c2);
+    if (CULLED && CULL) {
+      FaceMask mA, mB;
+      block_masks(i, mA, mB);
+      ee_candidates(a0, t1, b0, t2, q, sRow[k], sCol[l], A, B, eps_n, T, &mA, &mB, c1, c2);
+    } else {
+      ee_candidates(a0, t1, b0, t2, q, sRow[k], sCol[l], A, B, eps_n, T, nullptr, nullptr, c1, c2);
+    }
   }
   // candidate idx in the fixed order: A's vertices, B's vertices, E-E (k, l)
   // row-major with witness 1 before witness 2
