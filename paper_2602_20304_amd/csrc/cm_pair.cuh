@@ -47,10 +47,13 @@ struct LdsLayout {
   int eA, eB, row, col, red, top, rec, acc, pA, pB, cnt, mA, mB, bytes;
 };
 
-// 64-bit words of a per-edge face mask (0: culling off, faces > 128).
+// 64-bit words of a per-edge face mask (0: culling off).  Culling is used
+// for polytopes of at most 64 faces: measured on MI355X it speeds up the
+// 60-face hulls of the mixed workload and slows down 124-face hulls, whose
+// masked loops (one face per iteration) lose to the full loops unrolled by
+// two.
 __host__ __device__ inline int mask_words(int maxF) {
-  const int w = (maxF + 63) / 64;
-  return w <= 2 ? w : 0;
+  return maxF <= 64 ? 1 : 0;
 }
 
 __host__ __device__ inline LdsLayout lds_layout(int maxE, int maxF, int block) {
