@@ -45,6 +45,11 @@ __host__ __device__ inline BwdLds bwd_layout(int base, int maxV, int maxE, int m
   return L;
 }
 
+// LDS the adjoint needs beyond the engine (an upper bound for any base).
+__host__ __device__ inline int bwd_extra_bytes(int maxV, int maxE, int maxF, int block) {
+  return bwd_layout(0, maxV, maxE, maxF, block).bytes + 32;
+}
+
 struct BwdArgs {
   CotDev cot;
   GradDev gr;
@@ -57,8 +62,10 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
   extern __shared__ float4 smem4[];
   char* smem = reinterpret_cast<char*>(smem4);
   __shared__ PairShared ps;
-  PairEngine<BLOCK, KMAX, false> P(ps, smem, tb, bt, prm, scratch + (long long)blockIdx.x * scratch_stride, maxV, maxE, maxF);
-  const BwdLds L = bwd_layout(lds_layout(maxE, maxF, BLOCK).bytes, maxV, maxE, maxF, BLOCK);
+  const int extra = bwd_extra_bytes(maxV, maxE, maxF, BLOCK);
+  PairEngine<BLOCK, KMAX, false> P(ps, smem, tb, bt, prm, scratch + (long long)blockIdx.x * scratch_stride, maxV, maxE,
+                                   maxF, extra);
+  const BwdLds L = bwd_layout(lds_layout(maxE, maxF, BLOCK, extra).bytes, maxV, maxE, maxF, BLOCK);
   float* vA3 = reinterpret_cast<float*>(smem + L.vA);
   float* vB3 = reinterpret_cast<float*>(smem + L.vB);
   float* plA = reinterpret_cast<float*>(smem + L.plA);
@@ -491,7 +498,8 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
 }
 
 int bwd_lds_bytes(int maxV, int maxE, int maxF, int block) {
-  return bwd_layout(lds_layout(maxE, maxF, block).bytes, maxV, maxE, maxF, block).bytes;
+  const int extra = bwd_extra_bytes(maxV, maxE, maxF, block);
+  return bwd_layout(lds_layout(maxE, maxF, block, extra).bytes, maxV, maxE, maxF, block).bytes;
 }
 
 template <int BLOCK, int KMAX>

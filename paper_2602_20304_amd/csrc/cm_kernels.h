@@ -23,9 +23,14 @@ struct FwdLaunch {
 
 // Scratch floats per workgroup: per edge pair the unsigned distance and the
 // QP solution (al1, al2, ln con) in float64, then the float32 candidate
-// scores and the int32 list of filtered candidates (both nvs + 2 nee long).
-inline long long fwd_scratch_floats(int maxV, int maxE) {
+// scores and the int32 list of filtered candidates (both nvs + 2 nee long),
+// then room for both bodies' edge arrays (float64, used when they do not fit
+// in LDS).
+__host__ __device__ inline long long scratch_edges_offset(int maxV, int maxE) {
   return 8LL * maxE * maxE + 2 * (2LL * maxE * maxE + 2LL * maxV) + 128;
+}
+__host__ __device__ inline long long fwd_scratch_floats(int maxV, int maxE) {
+  return scratch_edges_offset(maxV, maxE) + 24LL * maxE;
 }
 
 struct CotDev {

@@ -13,6 +13,7 @@
 //   softsort SoftSort rows over the candidates within 40 tau of s_[K]
 #pragma once
 #include "cm_device.cuh"
+#include "cm_kernels.h"
 
 namespace cm {
 
@@ -45,7 +46,12 @@ struct Rec {
 
 struct LdsLayout {
   int eA, eB, row, col, red, top, rec, acc, pA, pB, cnt, mA, mB, bytes;
+  bool edges_lds;   // false: the edge arrays live in the workgroup's scratch slot
 };
+
+// Dynamic LDS a workgroup may use on gfx950 (160 KB per CU), leaving room for
+// the kernels' static shared variables.
+constexpr int kLdsBudget = 160 * 1024 - 1024;
 
 // 64-bit words of a per-edge face mask (0: culling off).  Culling is used
 // for polytopes of at most 64 faces: measured on MI355X it speeds up the
@@ -56,11 +62,27 @@ __host__ __device__ inline int mask_words(int maxF) {
   return maxF <= 64 ? 1 : 0;
 }
 
-__host__ __device__ inline LdsLayout lds_layout(int maxE, int maxF, int block) {
+// extra: LDS bytes the calling kernel needs beyond the engine.  When the
+// whole does not fit kLdsBudget, both bodies' edge arrays (96 B per edge)
+// move to the scratch slot.
+__host__ __device__ inline LdsLayout lds_layout(int maxE, int maxF, int block, int extra = 0) {
   LdsLayout L;
   int o = 0;
-  L.eA = o; o += 6 * 8 * maxE;
-  L.eB = o; o += 6 * 8 * maxE;
+  const int edge_bytes = 2 * 6 * 8 * maxE;
+  L.edges_lds = true;
+  {
+    // size with the edges in LDS (same sequence as below)
+    int t = edge_bytes + 16 * maxE + 16 * block + 8 * 64 + int(sizeof(Rec)) * block + 8 * 9 * CM_MAX_K +
+            64 * maxF + 64;
+    t = (t + 7) & ~7;
+    t += 16 * mask_words(maxF) * maxE;
+    if (((t + 15) & ~15) + extra > kLdsBudget) L.edges_lds = false;
+  }
+  L.eA = L.eB = -1;
+  if (L.edges_lds) {
+    L.eA = o; o += 6 * 8 * maxE;
+    L.eB = o; o += 6 * 8 * maxE;
+  }
   L.row = o; o += 8 * maxE;
   L.col = o; o += 8 * maxE;
   L.red = o; o += 2 * 8 * block;
@@ -116,12 +138,13 @@ struct PairEngine {
   const GeomRec* GB;
 
   __device__ PairEngine(PairShared& ps_, char* smem, const Tables& tb_, const BatchDev& bt_, const ParamsDev& prm,
-                        float* slot, int maxV_, int maxE_, int maxF_)
+                        float* slot, int maxV_, int maxE_, int maxF_, int lds_extra = 0)
       : ps(ps_), tb(tb_), bt(bt_) {
-    const LdsLayout L = lds_layout(maxE_, maxF_, BLOCK);
-    double* e = reinterpret_cast<double*>(smem + L.eA);
+    const LdsLayout L = lds_layout(maxE_, maxF_, BLOCK, lds_extra);
+    double* e = L.edges_lds ? reinterpret_cast<double*>(smem + L.eA)
+                            : reinterpret_cast<double*>(slot + scratch_edges_offset(maxV_, maxE_));
     EA = EdgeSoA{e, e + maxE_, e + 2 * maxE_, e + 3 * maxE_, e + 4 * maxE_, e + 5 * maxE_};
-    e = reinterpret_cast<double*>(smem + L.eB);
+    e = L.edges_lds ? reinterpret_cast<double*>(smem + L.eB) : e + 6 * maxE_;
     EB = EdgeSoA{e, e + maxE_, e + 2 * maxE_, e + 3 * maxE_, e + 4 * maxE_, e + 5 * maxE_};
     sPA = reinterpret_cast<double4*>(smem + L.pA);
     sPB = reinterpret_cast<double4*>(smem + L.pB);
