@@ -120,14 +120,19 @@ def cpu_baseline(batch, budget_s: float):
 
 
 def serving_leg(ctx_cls, n_requests: int, seed: int = 11):
-    """Short Poisson stream through the serving loop; returns latency stats."""
+    """Poisson request stream through the serving loop.
+
+    A burst of requests (all submitted at once) first measures the saturated
+    request throughput; the stream then arrives at 0.7 of it, so latencies
+    reflect service time rather than an ever-growing queue."""
     import workloads as W
     from paper_2602_20304_amd.cm import Server
     ctx = ctx_cls(0)
     pool = W.polytope_pool(64, seed=1, n_points=64)
     ids = ctx.create_geometry(pool)
     tau, K = 0.01, 8
-    reqs = W.serving_requests(n_requests=n_requests, seed=seed, rate_hz=40.0, env_min=256, env_max=4096,
+    n_cal = max(4, n_requests // 2)
+    reqs = W.serving_requests(n_requests=n_cal + n_requests, seed=seed, rate_hz=1.0, env_min=256, env_max=4096,
                               bodies_min=2, bodies_max=6, pool_size=64)
     rng = np.random.default_rng(seed)
     payload = []
@@ -138,35 +143,44 @@ def serving_leg(ctx_cls, n_requests: int, seed: int = 11):
         if q.want_bwd:
             cd = rng.standard_normal(cap * K).astype(np.float32)
             cn = rng.standard_normal(3 * cap * K).astype(np.float32)
-        payload.append((q, cd, cn, cap))
+        payload.append((q, cd, cn))
     srv = Server(ctx, 64 << 30, n_streams=4)
-    tickets = []
-    t0 = time.perf_counter()
-    for q, cd, cn, _ in payload:
-        wait = q.arrival_s - (time.perf_counter() - t0)
-        if wait > 0:
-            time.sleep(wait)
-        tickets.append(srv.submit(q.body_offsets, ids[q.body_geom], q.pose, tau, K, q.want_bwd, cd, cn))
-    done = {}
-    while len(done) < len(tickets):
-        for t in tickets:
-            if t not in done:
-                r = srv.poll(t)
-                if r is not None:
-                    if r["status"] != 0:
-                        raise RuntimeError(f"request {t} failed with status {r['status']}")
-                    done[t] = (r["t_submit"], r["t_start"], r["t_done"], r["n_pairs"])
-                    srv.release(t)
-        time.sleep(0.001)
-    wall = time.perf_counter() - t0
+
+    def run(items, arrivals):
+        tickets = []
+        t0 = time.perf_counter()
+        for (q, cd, cn), at in zip(items, arrivals):
+            wait = at - (time.perf_counter() - t0)
+            if wait > 0:
+                time.sleep(wait)
+            tickets.append(srv.submit(q.body_offsets, ids[q.body_geom], q.pose, tau, K, q.want_bwd, cd, cn))
+        done = {}
+        while len(done) < len(tickets):
+            for t in tickets:
+                if t not in done:
+                    r = srv.poll(t)
+                    if r is not None:
+                        if r["status"] != 0:
+                            raise RuntimeError(f"request {t} failed with status {r['status']}")
+                        done[t] = (r["t_submit"], r["t_start"], r["t_done"], r["n_pairs"])
+                        srv.release(t)
+            time.sleep(0.001)
+        return done, time.perf_counter() - t0
+
+    cal, cal_wall = run(payload[:n_cal], [0.0] * n_cal)
+    sat = n_cal / cal_wall
+    rate = 0.7 * sat
+    gaps = np.random.default_rng(seed + 1).exponential(1.0 / rate, size=n_requests)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    done, wall = run(payload[n_cal:], arrivals)
     srv.close()
     lat = np.array([d[2] - d[0] for d in done.values()])
     pairs = sum(d[3] for d in done.values())
-    return dict(requests=len(tickets), p50_ms=float(np.percentile(lat, 50) * 1e3),
+    return dict(requests=len(done), rate_per_s=rate, saturated_per_s=sat, p50_ms=float(np.percentile(lat, 50) * 1e3),
                 p99_ms=float(np.percentile(lat, 99) * 1e3), pairs_per_s=pairs / wall, wall_s=wall,
-                config=f"{n_requests} Poisson requests at 40/s, 256-4096 envs (log-uniform), 2-6 bodies/env "
-                       f"from a resident pool of 64 hull-of-64 polytopes, fwd or fwd+bwd 50/50, tau={tau}, K={K}, "
-                       f"4 streams, 64 GiB budget")
+                config=f"{n_requests} Poisson requests at 0.7 x the saturated rate measured on a burst of {n_cal}; "
+                       f"256-4096 envs (log-uniform), 2-6 bodies/env from a resident pool of 64 hull-of-64 polytopes, "
+                       f"fwd or fwd+bwd 50/50, tau={tau}, K={K}, 4 streams, 64 GiB budget")
 
 
 def copy_calibration(n_bytes: int, reps: int):
@@ -192,7 +206,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bwd", action="store_true")
-    ap.add_argument("--serve", type=int, default=24, help="requests in the serving leg (0 = skip)")
+    ap.add_argument("--serve", type=int, default=16, help="requests in the serving leg (0 = skip)")
     ap.add_argument("--only", default=None, choices=[None, "plain", "fused", "fwd_bwd"],
                     help="run one leg only (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -316,7 +330,8 @@ def main():
     if args.serve and not args.only:
         log(f"serving leg: {args.serve} requests ...")
         line["serving"] = serving_leg(Context, args.serve)
-        log(f"serving: p50 {line['serving']['p50_ms']:.1f} ms, p99 {line['serving']['p99_ms']:.1f} ms")
+        log(f"serving: {line['serving']['rate_per_s']:.2f} req/s (saturated {line['serving']['saturated_per_s']:.2f}), "
+            f"p50 {line['serving']['p50_ms']:.1f} ms, p99 {line['serving']['p99_ms']:.1f} ms")
     if not args.no_cpu_baseline and not args.only:
         log("timing the FP64 oracle on the host ...")
         line["cpu_baseline"] = cpu_baseline(batch, args.cpu_budget)
