@@ -36,6 +36,7 @@ if ROOT not in sys.path:
 
 METRIC = "geom-pair contact evals/s (fwd, fwd+bwd) vs plain kernel; p50/p99 query latency"
 FWD_KERNEL = "collide_fwd"
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "collide_fwd_mixed65536_traffic.md")
 
 
@@ -167,6 +168,26 @@ def serving_leg(ctx_cls, n_requests: int, seed: int = 11):
             time.sleep(0.001)
         return done, time.perf_counter() - t0
 
+    def run_plain(items):
+        # the same requests one at a time through cm_collide / cm_collide_backward
+        import torch
+        from paper_2602_20304_amd.cm import DeviceBatch
+        dev = ctx.device
+        t0 = time.perf_counter()
+        pairs = 0
+        for q, cd, cn in items:
+            db = DeviceBatch(q.n_env, len(q.body_geom), torch.as_tensor(q.body_offsets, dtype=torch.int32).to(dev),
+                             torch.as_tensor(ids[q.body_geom], dtype=torch.int32).to(dev),
+                             torch.as_tensor(q.pose, dtype=torch.float32).contiguous().to(dev))
+            m = ctx.collide(db, tau, K)
+            if q.want_bwd:
+                ctx.collide_backward(db, m, tau, K, None, torch.as_tensor(cn).to(dev), torch.as_tensor(cd).to(dev),
+                                     None, want_vertices=False, want_params=False)
+            out = m.to_numpy()
+            pairs += out["n_pairs"]
+        torch.cuda.synchronize()
+        return pairs / (time.perf_counter() - t0)
+
     cal, cal_wall = run(payload[:n_cal], [0.0] * n_cal)
     sat = n_cal / cal_wall
     rate = 0.7 * sat
@@ -174,13 +195,63 @@ def serving_leg(ctx_cls, n_requests: int, seed: int = 11):
     arrivals = np.cumsum(gaps) - gaps[0]
     done, wall = run(payload[n_cal:], arrivals)
     srv.close()
+    burst_pairs = sum(d[3] for d in cal.values()) / cal_wall
+    plain_pairs = run_plain(payload[:n_cal])
     lat = np.array([d[2] - d[0] for d in done.values()])
     pairs = sum(d[3] for d in done.values())
-    return dict(requests=len(done), rate_per_s=rate, saturated_per_s=sat, p50_ms=float(np.percentile(lat, 50) * 1e3),
+    return dict(requests=len(done), rate_per_s=rate, saturated_per_s=sat, burst_pairs_per_s=burst_pairs,
+                plain_sequential_pairs_per_s=plain_pairs, p50_ms=float(np.percentile(lat, 50) * 1e3),
                 p99_ms=float(np.percentile(lat, 99) * 1e3), pairs_per_s=pairs / wall, wall_s=wall,
                 config=f"{n_requests} Poisson requests at 0.7 x the saturated rate measured on a burst of {n_cal}; "
                        f"256-4096 envs (log-uniform), 2-6 bodies/env from a resident pool of 64 hull-of-64 polytopes, "
                        f"fwd or fwd+bwd 50/50, tau={tau}, K={K}, 4 streams, 64 GiB budget")
+
+
+EE_BYTES_PER_QUERY = 12 * 4 + 9 * 4   # float32 rows in (a0, a1, b0, b1) and out (alpha, con, e1, e2)
+
+
+def ee_witness_leg(ctx, trials: int = 100, max_n: int = 10_000_000, tau: float = 0.05):
+    """The witness-point speed experiment (Sec. V, Fig. 6): n edge pairs
+    uniform in the unit cube, n = 1 .. max_n by decades, `trials` timed
+    launches each (mean and standard deviation), smoothed and unsmoothed."""
+    import torch
+    import workloads as W
+    sizes = [10 ** k for k in range(0, 8) if 10 ** k <= max_n]
+    E = W.edge_pairs(max_n, seed=2)
+    rows = torch.as_tensor(np.ascontiguousarray(E.reshape(max_n, 12).T)).to(ctx.device)
+    del E
+    stream = torch.cuda.current_stream()
+    res = {"sizes": sizes, "trials": trials, "tau": tau}
+    for mode in ("smooth", "hard"):
+        hard = mode == "hard"
+        means, stds = [], []
+        for n in sizes:
+            ed = rows[:, :n].contiguous()
+            out = torch.empty(9, n, dtype=torch.float32, device=ctx.device)
+            for _ in range(3):
+                ctx.ee_witness(ed, tau, hard=hard, out=out, stream=stream)
+            evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(trials)]
+            torch.cuda.synchronize()
+            ctx.set_kernel_timing(True)
+            for a, b in evs:
+                a.record(stream)
+                ctx.ee_witness(ed, tau, hard=hard, out=out, stream=stream)
+                b.record(stream)
+            torch.cuda.synchronize()
+            k_ms, k_n = ctx.kernel_time("ee_witness")
+            ctx.set_kernel_timing(False)
+            t = np.array([a.elapsed_time(b) for a, b in evs])
+            means.append(k_ms / k_n)
+            stds.append(float(t.std()))
+            del ed, out
+        res[f"{mode}_ms"] = means
+        res[f"{mode}_std_ms"] = stds
+        kms = means[-1]
+        gbs = EE_BYTES_PER_QUERY * sizes[-1] / (kms * 1e-3) / 1e9
+        res[f"{mode}_queries_per_s"] = sizes[-1] / (kms * 1e-3)
+        res[f"{mode}_roofline"] = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                   "frac": gbs / HBM_PEAK_GBS, "bytes_per_query": EE_BYTES_PER_QUERY}
+    return res
 
 
 def copy_calibration(n_bytes: int, reps: int):
@@ -207,7 +278,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bwd", action="store_true")
     ap.add_argument("--serve", type=int, default=16, help="requests in the serving leg (0 = skip)")
-    ap.add_argument("--only", default=None, choices=[None, "plain", "fused", "fwd_bwd"],
+    ap.add_argument("--no-ee", action="store_true", help="skip the E-E witness microbenchmark")
+    ap.add_argument("--ee-only", action="store_true", help="run only the E-E witness microbenchmark")
+    ap.add_argument("--no-simplifications", action="store_true",
+                    help="skip the forward legs without E-E (ne) and with one-sided vertex contacts (ne_s)")
+    ap.add_argument("--only", default=None, choices=[None, "plain", "fused", "fwd_bwd", "plain_ne", "plain_ne_s"],
                     help="run one leg only (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (PMC byte calibration)")
@@ -221,8 +296,13 @@ def main():
 
     import torch
     import workloads as W
-    from paper_2602_20304_amd.cm import Context, Manifold
+    from paper_2602_20304_amd.cm import FLAG_NO_EE, FLAG_ONE_SIDED_VS, Context, Manifold
     from paper_2602_20304_amd import opmodel
+
+    if args.ee_only:
+        ctx = Context(0)
+        print(json.dumps({"ee_witness": ee_witness_leg(ctx)}), flush=True)
+        return
 
     batch, desc = build_workload(args.workload, args.scenes)
     log(f"workload: {desc}")
@@ -241,12 +321,16 @@ def main():
         cot_d = torch.as_tensor(a).to(ctx.device)
         cot_n = torch.as_tensor(b).to(ctx.device)
 
+    leg_flags = {"plain_ne": FLAG_NO_EE, "plain_ne_s": FLAG_NO_EE | FLAG_ONE_SIDED_VS}
+
     def step(leg):
-        ctx.collide(db, batch.tau, batch.K, out=out, fused=(leg == "fused"), stream=stream)
+        ctx.collide(db, batch.tau, batch.K, out=out, fused=(leg == "fused"), stream=stream,
+                    flags=leg_flags.get(leg, 0))
         if leg == "fwd_bwd":
             ctx.collide_backward(db, out, batch.tau, batch.K, None, cot_n, cot_d, None, stream=stream)
 
     legs = ["plain", "fused"] + ([] if args.no_bwd else ["fwd_bwd"])
+    legs += [] if args.no_simplifications else ["plain_ne", "plain_ne_s"]
     if args.only:
         legs = [args.only]
     results = {}
@@ -327,11 +411,21 @@ def main():
         line["fwd_bwd_pairs_per_s"] = v["n_pairs"] / (v["ms"] * 1e-3)
     if "plain" in results and main_leg != "plain":
         line["speedup_vs_plain"] = results["plain"]["ms"] / ms
+    if "plain" in results and "plain_ne" in results and "plain_ne_s" in results:
+        line["simplifications"] = {"ne_speedup": results["plain"]["ms"] / results["plain_ne"]["ms"],
+                                   "ne_s_speedup_over_ne": results["plain_ne"]["ms"] / results["plain_ne_s"]["ms"]}
     if args.serve and not args.only:
         log(f"serving leg: {args.serve} requests ...")
         line["serving"] = serving_leg(Context, args.serve)
         log(f"serving: {line['serving']['rate_per_s']:.2f} req/s (saturated {line['serving']['saturated_per_s']:.2f}), "
             f"p50 {line['serving']['p50_ms']:.1f} ms, p99 {line['serving']['p99_ms']:.1f} ms")
+    if not args.no_ee:
+        log("E-E witness microbenchmark ...")
+        ee = ee_witness_leg(ctx)
+        line["ee_witness"] = ee
+        log("ee_witness: " + ", ".join(f"n={n}: {a:.4f}/{b:.4f} ms" for n, a, b in
+                                       zip(ee["sizes"], ee["smooth_ms"], ee["hard_ms"])) +
+            f"; 1e7 smooth {ee['smooth_roofline']['achieved']:.0f} GB/s, hard {ee['hard_roofline']['achieved']:.0f} GB/s")
     if not args.no_cpu_baseline and not args.only:
         log("timing the FP64 oracle on the host ...")
         line["cpu_baseline"] = cpu_baseline(batch, args.cpu_budget)

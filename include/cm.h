@@ -80,8 +80,15 @@ typedef struct {
   float eps_n;
   float cull_margin;
   int32_t K;          /* contacts per pair, 1..CM_MAX_K */
-  uint32_t flags;     /* reserved, must be 0 */
+  uint32_t flags;     /* CM_FLAG_* below, 0 = the full method */
 } cm_params;
+
+/* Simplifications the paper evaluates for speed (supplementary material,
+ * possible simplifications): CM_FLAG_NO_EE drops the edge-edge candidates
+ * (vertex-SDF contacts only); CM_FLAG_ONE_SIDED_VS keeps only A's vertices
+ * against B's SDF.  Candidate order is unchanged otherwise. */
+#define CM_FLAG_NO_EE 1u
+#define CM_FLAG_ONE_SIDED_VS 2u
 
 /* A batch of scenes.  Bodies of scene s are body_offsets[s] .. [s+1]-1.
  * Candidate pairs: all i < j within each scene when cand_offsets is NULL,
@@ -193,6 +200,29 @@ cm_status cm_collide_fused(cm_context* ctx, const cm_batch* batch, const cm_para
 cm_status cm_collide_backward(cm_context* ctx, const cm_batch* batch, const cm_params* prm,
                               const cm_manifold* fwd, const cm_cotangent* cot, cm_grads* out, void* stream);
 
+/* ---------------------------------------------------------------- E-E witness points
+ * The edge-edge witness routine on its own, over n independent edge pairs:
+ * the regularised QP of Sec. IV-D-2 solved by the analytic active set, and
+ * the witness points of Sec. IV-D-3, as in the witness-point speed
+ * experiment of Sec. V (Fig. 6).  Edge 1 runs a0 -> a1, edge 2 b0 -> b1.
+ *   edges  device float32 [12][n], rows a0.x a0.y a0.z a1.x a1.y a1.z
+ *          b0.x b0.y b0.z b1.x b1.y b1.z, row stride n (read only)
+ *   out    device float32 [9][n], rows alpha1, alpha2, con, e1.x e1.y e1.z,
+ *          e2.x e2.y e2.z, row stride n; con is the indicator that the
+ *          unconstrained minimiser lies in [0,1]^2 (soft, or 0/1 with
+ *          CM_EE_HARD); e1 - e2 gives the unsigned distance and normal
+ *   tau        temperature of the smoothed solver (> 0; unused with CM_EE_HARD)
+ *   lambda_reg regulariser (< 0: 0.01; otherwise > 0)
+ *   mode       CM_EE_SMOOTH (the method) or CM_EE_HARD (no smoothing: the
+ *              exact minimiser over the box, the paper's Ours-NS)
+ * Computes in float64.  Both buffers stay the caller's; they must not
+ * overlap.  n = 0 does nothing; n < 0, a null buffer with n > 0 or an unknown
+ * mode returns CM_ERR_INVALID_ARG.  Asynchronous on stream. */
+#define CM_EE_SMOOTH 0
+#define CM_EE_HARD 1
+cm_status cm_ee_witness(cm_context* ctx, const float* edges, int64_t n, float tau, float lambda_reg, int32_t mode,
+                        float* out, void* stream);
+
 /* ---------------------------------------------------------------- serving
  * A continuous-batching request loop over resident geometry.  Requests are
  * admitted while their device footprint fits in hbm_budget_bytes; admitted
@@ -231,14 +261,21 @@ typedef struct {
 
 /* ---------------------------------------------------------------- timing
  * Opt-in kernel timing for measurement.  While enabled, every cm_collide /
- * cm_collide_fused / cm_collide_backward call records a pair of HIP events on
+ * cm_collide_fused / cm_collide_backward / cm_ee_witness call records a pair of HIP events on
  * the caller's stream around each timed unit: CM_TIMER_BROADPHASE (broadphase
  * and compaction), CM_TIMER_FORWARD (the forward pair kernel),
  * CM_TIMER_BACKWARD (the adjoint kernel), CM_TIMER_FUSED (one replay of the
- * fused graph).  cm_kernel_time waits for the recorded events and returns the
+ * fused graph), CM_TIMER_EE_WITNESS (one cm_ee_witness launch).  cm_kernel_time waits for the recorded events and returns the
  * summed milliseconds and the number of timed launches since timing was
  * enabled.  Enabling resets the sums.  Not for use under stream capture. */
-enum { CM_TIMER_BROADPHASE = 0, CM_TIMER_FORWARD = 1, CM_TIMER_BACKWARD = 2, CM_TIMER_FUSED = 3, CM_N_TIMERS = 4 };
+enum {
+  CM_TIMER_BROADPHASE = 0,
+  CM_TIMER_FORWARD = 1,
+  CM_TIMER_BACKWARD = 2,
+  CM_TIMER_FUSED = 3,
+  CM_TIMER_EE_WITNESS = 4,
+  CM_N_TIMERS = 5
+};
 cm_status cm_set_kernel_timing(cm_context* ctx, int32_t enable);
 cm_status cm_kernel_time(cm_context* ctx, int32_t timer, double* total_ms, int64_t* launches);
 

@@ -434,6 +434,60 @@ def ee_qp(a0, a1, b0, b1, tau, lam=LAMBDA_DEFAULT):
     return dict(al1=al1, al2=al2, au1=au1, au2=au2, con=con, log_con=log_con, costs=costs)
 
 
+def ee_qp_hard(a0, a1, b0, b1, lam=LAMBDA_DEFAULT):
+    """The E-E QP without smoothing (Ours-NS of the witness-point experiment, Sec. V, Fig. 6).
+
+    With lam > 0 the objective is strictly convex, so its minimiser over the
+    box [0,1]^2 is unique: the unconstrained minimiser when it lies in the
+    box, otherwise the best of the minimisers along the four box edges (each a
+    one-dimensional convex quadratic, minimised by clamping its stationary
+    point to [0, 1]).  Ties go to the lower edge index (order: al1 = 1,
+    al1 = 0, al2 = 1, al2 = 0).  Returns al1, al2 and con (1 inside, 0 not).
+    """
+    t1 = a1 - a0
+    t2 = b1 - b0
+    bv = a0 - b0
+    Q11 = _dot(t1, t1) + lam
+    Q12 = -_dot(t1, t2)
+    Q22 = _dot(t2, t2) + lam
+    c1 = _dot(bv, t1) - 0.5 * lam
+    c2 = -_dot(bv, t2) - 0.5 * lam
+    Q11, Q12, Q22, c1, c2 = torch.broadcast_tensors(Q11, Q12, Q22, c1, c2)
+    det = Q11 * Q22 - Q12 * Q12
+    au1 = (-c1 * Q22 + Q12 * c2) / det
+    au2 = (-c2 * Q11 + Q12 * c1) / det
+    inside = (au1 >= 0) & (au1 <= 1) & (au2 >= 0) & (au2 <= 1)
+    one, zero = torch.ones_like(Q12), torch.zeros_like(Q12)
+    cand1 = torch.stack([one, zero, torch.clamp(-(Q12 + c1) / Q11, 0.0, 1.0),
+                         torch.clamp(-c1 / Q11, 0.0, 1.0)], dim=-1)
+    cand2 = torch.stack([torch.clamp(-(Q12 + c2) / Q22, 0.0, 1.0), torch.clamp(-c2 / Q22, 0.0, 1.0),
+                         one, zero], dim=-1)
+    x1, x2 = cand1, cand2
+    q11, q12, q22, k1, k2 = (v[..., None] for v in (Q11, Q12, Q22, c1, c2))
+    costs = 0.5 * (q11 * x1 * x1 + 2.0 * q12 * x1 * x2 + q22 * x2 * x2) + k1 * x1 + k2 * x2
+    best = torch.argmin(costs, dim=-1, keepdim=True)    # first index of the minimum
+    b1_ = torch.gather(cand1, -1, best)[..., 0]
+    b2_ = torch.gather(cand2, -1, best)[..., 0]
+    al1 = torch.where(inside, au1, b1_)
+    al2 = torch.where(inside, au2, b2_)
+    return dict(al1=al1, al2=al2, con=inside.to(al1.dtype), costs=costs)
+
+
+def ee_witness_batch(edges, tau, lam=LAMBDA_DEFAULT, hard=False):
+    """Witness points of independent edge pairs (Sec. IV-D-2, IV-D-3): the
+    shape of the paper's witness-point vectorisation experiment (Sec. V, Fig. 6).
+
+    edges: [n, 4, 3] rows a0, a1, b0, b1.  Returns float64 numpy arrays al1,
+    al2, con [n] and e1, e2 [n, 3].
+    """
+    e = torch.as_tensor(np.asarray(edges, dtype=np.float64))
+    a0, a1, b0, b1 = e[:, 0], e[:, 1], e[:, 2], e[:, 3]
+    with torch.no_grad():
+        q = ee_qp_hard(a0, a1, b0, b1, lam) if hard else ee_qp(a0, a1, b0, b1, tau, lam)
+        e1, e2, _, _ = ee_witness(a0, a1, b0, b1, q["al1"], q["al2"], 1.0)
+    return dict(al1=q["al1"].numpy(), al2=q["al2"].numpy(), con=q["con"].numpy(), e1=e1.numpy(), e2=e2.numpy())
+
+
 def ee_witness(a0, a1, b0, b1, al1, al2, eps_n):
     """Witness points, unsigned distance and unsigned normal (Sec. IV-D-3).
 
@@ -467,12 +521,15 @@ def nn_log_indicators(dbar, tau):
     return torch.log_softmax(-dbar / tau, dim=1), torch.log_softmax(-dbar / tau, dim=0)
 
 
-def pair_candidates(GA: OGeom, RA, tA, GB: OGeom, RB, tB, tau, lam=LAMBDA_DEFAULT, eps_n=None):
+def pair_candidates(GA: OGeom, RA, tA, GB: OGeom, RB, tB, tau, lam=LAMBDA_DEFAULT, eps_n=None, no_ee=False,
+                    one_sided_vs=False):
     """All contact candidates of one body pair (A, B) in world coordinates.
 
     Returns dict of p [C,3], nu [C,3] (pair convention, A -> B), d [C],
     logw [C] with the candidate order: A's vertices, B's vertices, then E-E
-    pairs (k, l) row-major with witness 1 before witness 2.
+    pairs (k, l) row-major with witness 1 before witness 2.  no_ee drops the
+    E-E candidates and one_sided_vs B's vertices (the paper's simplifications,
+    supplementary material).
     """
     if eps_n is None:
         eps_n = tau * tau
@@ -519,6 +576,11 @@ def pair_candidates(GA: OGeom, RA, tA, GB: OGeom, RB, tB, tau, lam=LAMBDA_DEFAUL
     ee_nu = torch.stack([-n1, n2], dim=2).reshape(-1, 3)   # pair convention (R8)
     ee_d = torch.stack([d1, d2], dim=2).reshape(-1)
     ee_logw = torch.stack([logG1, logG2], dim=2).reshape(-1)
+    nA = vA.shape[0]
+    if one_sided_vs:
+        vs_p, vs_nu, vs_d, vs_logw = vs_p[:nA], vs_nu[:nA], vs_d[:nA], vs_logw[:nA]
+    if no_ee:
+        ee_p, ee_nu, ee_d, ee_logw = ee_p[:0], ee_nu[:0], ee_d[:0], ee_logw[:0]
     out = dict(p=torch.cat([vs_p, ee_p]), nu=torch.cat([vs_nu, ee_nu]),
                d=torch.cat([vs_d, ee_d]), logw=torch.cat([vs_logw, ee_logw]))
     out["extra"] = dict(qp=qp, dbar=dbar, e1=e1, e2=e2, gam1=gam1, gam2=gam2, log_pen1=log_pen1,
@@ -532,20 +594,32 @@ def manifold(c, tau, K: int):
 
     s_i = -d_i + tau log w_i; s_[1] >= ... >= s_[K] the K largest scores;
     Gamma_ki = softmax_i(-|s_[k] - s_i| / tau); outputs are Gamma @ (p, nu, d, w).
+    With fewer than K candidates the remaining rows are empty: zero point,
+    normal, distance and weight (reading R15).
     """
     s = -c["d"] + tau * c["logw"]
-    top = torch.topk(s, K, sorted=True).values
+    n = s.shape[0]
+    k = min(K, n)
+    top = torch.topk(s, k, sorted=True).values
     G = torch.softmax(-torch.abs(top[:, None] - s[None, :]) / tau, dim=1)
     w = torch.exp(c["logw"])
-    return dict(p=G @ c["p"], nu=G @ c["nu"], d=G @ c["d"], w=G @ w, s_top=top)
+    out = dict(p=G @ c["p"], nu=G @ c["nu"], d=G @ c["d"], w=G @ w, s_top=top)
+    if k < K:
+        pad = K - k
+        for key in ("p", "nu"):
+            out[key] = torch.cat([out[key], out[key].new_zeros(pad, 3)])
+        for key in ("d", "w"):
+            out[key] = torch.cat([out[key], out[key].new_zeros(pad)])
+        out["s_top"] = torch.cat([top, top.new_full((pad,), -float("inf"))])
+    return out
 
 
 def collide_pair(GA, poseA, GB, poseB, tau, K, lam=LAMBDA_DEFAULT, eps_n=None, xiA=None, xiB=None,
-                 exact_exp=False):
+                 exact_exp=False, no_ee=False, one_sided_vs=False):
     """Contact manifold g_{A,B} of one pair (Sec. IV-A): K x (p, nu, d, w)."""
     RA, tA = pose_Rt(poseA, xiA, exact_exp)
     RB, tB = pose_Rt(poseB, xiB, exact_exp)
-    c = pair_candidates(GA, RA, tA, GB, RB, tB, tau, lam, eps_n)
+    c = pair_candidates(GA, RA, tA, GB, RB, tB, tau, lam, eps_n, no_ee=no_ee, one_sided_vs=one_sided_vs)
     return manifold(c, tau, K)
 
 
@@ -619,7 +693,8 @@ class GeomCache:
         return self.cache[g]
 
 
-def collide_batch(batch, pair_list=None, lam=LAMBDA_DEFAULT, eps_n=None, margin=None, cache=None):
+def collide_batch(batch, pair_list=None, lam=LAMBDA_DEFAULT, eps_n=None, margin=None, cache=None, no_ee=False,
+                  one_sided_vs=False):
     """Forward manifold for the kept pairs of a batch (or a given pair subset).
 
     Returns (pairs [2,n], offsets [S+1], outputs dict of numpy float64 arrays
@@ -636,13 +711,14 @@ def collide_batch(batch, pair_list=None, lam=LAMBDA_DEFAULT, eps_n=None, margin=
         for i in range(n):
             a, b = int(pairs[0, i]), int(pairs[1, i])
             GA, GB = cache[batch.body_geom[a]], cache[batch.body_geom[b]]
-            m = collide_pair(GA, batch.pose[:, a], GB, batch.pose[:, b], batch.tau, K, lam, eps_n)
+            m = collide_pair(GA, batch.pose[:, a], GB, batch.pose[:, b], batch.tau, K, lam, eps_n,
+                             no_ee=no_ee, one_sided_vs=one_sided_vs)
             for k in ("p", "nu", "d", "w"):
                 out[k][i] = m[k].numpy()
     return pairs, offsets, out
 
 
-def pair_grad(GA, poseA, GB, poseB, tau, K, cot, lam=LAMBDA_DEFAULT, eps_n=None):
+def pair_grad(GA, poseA, GB, poseB, tau, K, cot, lam=LAMBDA_DEFAULT, eps_n=None, no_ee=False, one_sided_vs=False):
     """Gradient of L = <cot, outputs> for one pair by autograd of the forward.
 
     cot: dict with any of p [K,3], nu [K,3], d [K], w [K] (numpy).
@@ -654,7 +730,7 @@ def pair_grad(GA, poseA, GB, poseB, tau, K, cot, lam=LAMBDA_DEFAULT, eps_n=None)
     xiA = torch.zeros(6, dtype=DT, requires_grad=True)
     xiB = torch.zeros(6, dtype=DT, requires_grad=True)
     tau_t = torch.tensor(float(tau), dtype=DT, requires_grad=True)
-    m = collide_pair(GA, poseA, GB, poseB, tau_t, K, lam, eps_n, xiA, xiB)
+    m = collide_pair(GA, poseA, GB, poseB, tau_t, K, lam, eps_n, xiA, xiB, no_ee=no_ee, one_sided_vs=one_sided_vs)
     L = torch.zeros((), dtype=DT)
     for k, v in cot.items():
         L = L + (m[k] * torch.as_tensor(np.asarray(v, dtype=np.float64))).sum()

@@ -11,7 +11,7 @@ CM_OK = 0
 STATUS = {0: "CM_OK", -1: "CM_ERR_INVALID_ARG", -2: "CM_ERR_OOM", -3: "CM_ERR_DEVICE", -4: "CM_ERR_NOT_READY",
           -5: "CM_ERR_REJECTED", -6: "CM_ERR_NOT_FOUND", -7: "CM_ERR_CAPACITY", -8: "CM_ERR_GEOMETRY"}
 CM_MAX_K = 32
-TIMERS = {"broadphase": 0, "forward": 1, "backward": 2, "fused": 3}
+TIMERS = {"broadphase": 0, "forward": 1, "backward": 2, "fused": 3, "ee_witness": 4}
 
 vp = C.c_void_p
 i32 = C.c_int32
@@ -76,6 +76,7 @@ SIGNATURES = {
     "cm_collide_fused": (i32, [vp, C.POINTER(cm_batch), C.POINTER(cm_params), C.POINTER(cm_manifold), vp]),
     "cm_collide_backward": (i32, [vp, C.POINTER(cm_batch), C.POINTER(cm_params), C.POINTER(cm_manifold),
                                   C.POINTER(cm_cotangent), C.POINTER(cm_grads), vp]),
+    "cm_ee_witness": (i32, [vp, vp, C.c_int64, C.c_float, C.c_float, i32, vp, vp]),
     "cm_set_kernel_timing": (i32, [vp, i32]),
     "cm_kernel_time": (i32, [vp, i32, C.POINTER(C.c_double), i64p]),
     "cm_server_create": (i32, [vp, C.c_uint64, i32, C.POINTER(vp)]),

@@ -126,9 +126,15 @@ class Manifold:
                     d=self.dist[:n * K].cpu().numpy().reshape(n, K), w=self.weight[:n * K].cpu().numpy().reshape(n, K))
 
 
-def make_params(tau: float, K: int, lambda_reg: float = -1.0, eps_n: float = -1.0, cull_margin: float = -1.0):
+FLAG_NO_EE = 1          # no edge-edge candidates
+FLAG_ONE_SIDED_VS = 2   # vertex-SDF candidates of the first body only
+
+
+def make_params(tau: float, K: int, lambda_reg: float = -1.0, eps_n: float = -1.0, cull_margin: float = -1.0,
+                flags: int = 0):
     p = L.cm_params()
-    p.tau, p.K, p.lambda_reg, p.eps_n, p.cull_margin, p.flags = float(tau), int(K), lambda_reg, eps_n, cull_margin, 0
+    p.tau, p.K, p.lambda_reg, p.eps_n, p.cull_margin = float(tau), int(K), lambda_reg, eps_n, cull_margin
+    p.flags = int(flags)
     return p
 
 
@@ -228,21 +234,43 @@ class Context:
 
     # ------------------------------------------------------------- forward
     def collide(self, db: DeviceBatch, tau: float, K: int, capacity: Optional[int] = None, out: Manifold = None,
-                fused: bool = False, stream=None, lambda_reg=-1.0, eps_n=-1.0, cull_margin=-1.0) -> Manifold:
+                fused: bool = False, stream=None, lambda_reg=-1.0, eps_n=-1.0, cull_margin=-1.0,
+                flags: int = 0) -> Manifold:
         if out is None:
             cap = db.n_cand_total if capacity is None else capacity
             out = Manifold.empty(db.n_scenes, cap, K, self.device)
-        prm = make_params(tau, K, lambda_reg, eps_n, cull_margin)
+        prm = make_params(tau, K, lambda_reg, eps_n, cull_margin, flags)
         b = db.as_c()
         m = out.as_c()
         fn = self.lib.cm_collide_fused if fused else self.lib.cm_collide
         self._check(fn(self.h, C.byref(b), C.byref(prm), C.byref(m), _stream_handle(stream)))
         return out
 
+    # ------------------------------------------------------------- E-E witness points
+    def ee_witness(self, edges: torch.Tensor, tau: float, lambda_reg: float = -1.0, hard: bool = False,
+                   out: torch.Tensor = None, stream=None) -> torch.Tensor:
+        """Witness points of independent edge pairs (cm_ee_witness).
+
+        edges: float32 [12, n] on this device (rows a0, a1, b0, b1, xyz each);
+        returns float32 [9, n]: alpha1, alpha2, con, e1 xyz, e2 xyz.
+        """
+        if edges.dtype != torch.float32 or edges.dim() != 2 or edges.shape[0] != 12 or not edges.is_contiguous():
+            raise ValueError("edges must be a contiguous float32 [12, n] tensor")
+        if edges.device != self.device:
+            raise ValueError(f"edges must be on {self.device}")
+        n = edges.shape[1]
+        if out is None:
+            out = torch.empty(9, n, dtype=torch.float32, device=self.device)
+        elif out.dtype != torch.float32 or tuple(out.shape) != (9, n) or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float32 [9, n] tensor")
+        self._check(self.lib.cm_ee_witness(self.h, _ptr(edges), n, float(tau), float(lambda_reg),
+                                           1 if hard else 0, _ptr(out), _stream_handle(stream)))
+        return out
+
     # ------------------------------------------------------------- backward
     def collide_backward(self, db: DeviceBatch, fwd: Manifold, tau: float, K: int, g_point=None, g_normal=None,
                          g_dist=None, g_weight=None, stream=None, want_vertices=True, want_params=True,
-                         lambda_reg=-1.0, eps_n=-1.0, cull_margin=-1.0) -> dict:
+                         lambda_reg=-1.0, eps_n=-1.0, cull_margin=-1.0, flags: int = 0) -> dict:
         """Vector-Jacobian product of the manifold for the given cotangents.
 
         Returns device tensors: pose [6, n_bodies] (left twists rho, omega),
@@ -260,7 +288,7 @@ class Context:
         cot.g_point, cot.g_normal, cot.g_dist, cot.g_weight = (_ptr(t) for t in (g_point, g_normal, g_dist, g_weight))
         gr = L.cm_grads()
         gr.g_pose, gr.g_vertices, gr.g_params, gr.g_tau = (_ptr(out[k]) for k in ("pose", "vertices", "params", "tau"))
-        prm = make_params(tau, K, lambda_reg, eps_n, cull_margin)
+        prm = make_params(tau, K, lambda_reg, eps_n, cull_margin, flags)
         b = db.as_c()
         m = fwd.as_c()
         self._check(self.lib.cm_collide_backward(self.h, C.byref(b), C.byref(prm), C.byref(m), C.byref(cot),
@@ -274,23 +302,23 @@ class _CollideFn(torch.autograd.Function):
     cm_collide at the batch's poses, the backward cm_collide_backward."""
 
     @staticmethod
-    def forward(fctx, xi, verts, params, tau_t, cmctx, db, K, capacity, fused):
+    def forward(fctx, xi, verts, params, tau_t, cmctx, db, K, capacity, fused, flags):
         tau = float(tau_t.item())
-        m = cmctx.collide(db, tau, K, capacity, fused=fused)
-        fctx.cm = (cmctx, db, m, tau, K)
+        m = cmctx.collide(db, tau, K, capacity, fused=fused, flags=flags)
+        fctx.cm = (cmctx, db, m, tau, K, flags)
         fctx.mark_non_differentiable(m.n_pairs, m.pairs)
         return m.point, m.normal, m.dist, m.weight, m.n_pairs, m.pairs
 
     @staticmethod
     def backward(fctx, gp, gn, gd, gw, _n, _p):
-        cmctx, db, m, tau, K = fctx.cm
+        cmctx, db, m, tau, K, flags = fctx.cm
         c = lambda t: None if t is None else t.contiguous()
-        g = cmctx.collide_backward(db, m, tau, K, c(gp), c(gn), c(gd), c(gw))
-        return g["pose"], g["vertices"], g["params"], g["tau"], None, None, None, None, None
+        g = cmctx.collide_backward(db, m, tau, K, c(gp), c(gn), c(gd), c(gw), flags=flags)
+        return g["pose"], g["vertices"], g["params"], g["tau"], None, None, None, None, None, None
 
 
 def collide_autograd(cmctx: Context, db: DeviceBatch, tau_t: torch.Tensor, K: int, xi=None, verts=None,
-                     params=None, capacity=None, fused=False):
+                     params=None, capacity=None, fused=False, flags: int = 0):
     """Manifold outputs (point, normal, dist, weight, n_pairs, pairs) that
     autograd can differentiate.  ``xi`` [6, n_bodies] must be zeros (the
     twist at which the gradient is taken); ``verts`` [3, vertex_pool] and
@@ -304,7 +332,7 @@ def collide_autograd(cmctx: Context, db: DeviceBatch, tau_t: torch.Tensor, K: in
     if params is None:
         params = torch.zeros(4, max(cmctx.geometry_count, 1), device=dev, requires_grad=True)
     cap = db.n_cand_total if capacity is None else capacity
-    return _CollideFn.apply(xi, verts, params, tau_t, cmctx, db, K, cap, fused)
+    return _CollideFn.apply(xi, verts, params, tau_t, cmctx, db, K, cap, fused, flags)
 
 
 class Server:
@@ -321,7 +349,7 @@ class Server:
         self._keep = {}
 
     def submit(self, body_offsets, body_geom, pose, tau: float, K: int, want_backward=False, cot_dist=None,
-               cot_normal=None, capacity: int = 0) -> int:
+               cot_normal=None, capacity: int = 0, flags: int = 0) -> int:
         """body_geom are context geometry ids; pose float32 [7, n_bodies]."""
         bo = np.ascontiguousarray(body_offsets, np.int32)
         bg = np.ascontiguousarray(body_geom, np.int32)
@@ -329,7 +357,7 @@ class Server:
         q = L.cm_request()
         q.n_scenes, q.n_bodies = len(bo) - 1, len(bg)
         q.body_offsets, q.body_geom, q.pose = _np_ptr(bo), _np_ptr(bg), _np_ptr(ps)
-        q.params = make_params(tau, K)
+        q.params = make_params(tau, K, flags=flags)
         q.want_backward = int(bool(want_backward))
         cd = None if cot_dist is None else np.ascontiguousarray(cot_dist, np.float32)
         cn = None if cot_normal is None else np.ascontiguousarray(cot_normal, np.float32)

@@ -250,7 +250,8 @@ cm_status resolve_params(cm_context* ctx, const cm_params* prm, ParamsDev* pd) {
   if (!prm) return cm_fail(ctx, CM_ERR_INVALID_ARG, "null params");
   if (!(prm->tau > 0.f) || !std::isfinite(prm->tau)) return cm_fail(ctx, CM_ERR_INVALID_ARG, "tau must be > 0");
   if (prm->K < 1 || prm->K > CM_MAX_K) return cm_fail(ctx, CM_ERR_INVALID_ARG, "K must be in 1..32");
-  if (prm->flags != 0) return cm_fail(ctx, CM_ERR_INVALID_ARG, "flags must be 0");
+  if (prm->flags & ~(CM_FLAG_NO_EE | CM_FLAG_ONE_SIDED_VS))
+    return cm_fail(ctx, CM_ERR_INVALID_ARG, "unknown flags");
   pd->tau = double(prm->tau);
   pd->inv_tau = 1.0 / pd->tau;
   pd->c_log2 = kLog2e / pd->tau;
@@ -262,6 +263,7 @@ cm_status resolve_params(cm_context* ctx, const cm_params* prm, ParamsDev* pd) {
   pd->margin = prm->cull_margin < 0.f ? 10.0f * prm->tau : prm->cull_margin;
   pd->eps_tied = prm->eps_n < 0.f ? 1 : 0;
   pd->K = prm->K;
+  pd->flags = prm->flags;
   return CM_OK;
 }
 
@@ -340,6 +342,35 @@ extern "C" cm_status cm_collide(cm_context* ctx, const cm_batch* batch, const cm
   t0 = timer_begin(ctx, st);
   if ((s = cm_hip(ctx, launch_collide_fwd(f, st), "collide launch")) != CM_OK) return s;
   timer_end(ctx, CM_TIMER_FORWARD, t0, st);
+  return CM_OK;
+}
+
+extern "C" cm_status cm_ee_witness(cm_context* ctx, const float* edges, int64_t n, float tau, float lambda_reg,
+                                   int32_t mode, float* out, void* stream) {
+  if (!ctx) return CM_ERR_INVALID_ARG;
+  if (n < 0) return cm_fail(ctx, CM_ERR_INVALID_ARG, "negative query count");
+  if (mode != CM_EE_SMOOTH && mode != CM_EE_HARD) return cm_fail(ctx, CM_ERR_INVALID_ARG, "unknown mode");
+  if (mode == CM_EE_SMOOTH && (!(tau > 0.f) || !std::isfinite(tau)))
+    return cm_fail(ctx, CM_ERR_INVALID_ARG, "tau must be > 0");
+  if (n == 0) return CM_OK;
+  if (!edges || !out) return cm_fail(ctx, CM_ERR_INVALID_ARG, "null buffer");
+  const uintptr_t e0 = reinterpret_cast<uintptr_t>(edges), e1 = e0 + 12 * 4 * uint64_t(n);
+  const uintptr_t o0 = reinterpret_cast<uintptr_t>(out), o1 = o0 + 9 * 4 * uint64_t(n);
+  if (e0 < o1 && o0 < e1) return cm_fail(ctx, CM_ERR_INVALID_ARG, "edges and out overlap");
+  ParamsDev pd{};
+  const double t = mode == CM_EE_SMOOTH ? double(tau) : 1.0;
+  pd.tau = t;
+  pd.inv_tau = 1.0 / t;
+  pd.c_log2 = kLog2e / t;
+  pd.tl = t * kLn2;
+  pd.lam = lambda_reg < 0.f ? 0.01 : double(lambda_reg);
+  if (!(pd.lam > 0.0) || !std::isfinite(pd.lam)) return cm_fail(ctx, CM_ERR_INVALID_ARG, "lambda_reg must be > 0");
+  hipSetDevice(ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipEvent_t t0 = timer_begin(ctx, st);
+  cm_status s = cm_hip(ctx, launch_ee_witness(edges, n, pd, mode == CM_EE_HARD, out, st), "ee witness launch");
+  if (s != CM_OK) return s;
+  timer_end(ctx, CM_TIMER_EE_WITNESS, t0, st);
   return CM_OK;
 }
 

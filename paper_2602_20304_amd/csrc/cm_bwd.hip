@@ -99,8 +99,11 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
     for (int i = tid; i < 4 * maxF; i += BLOCK) { plA[i] = 0.f; plB[i] = 0.f; }
     for (int i = tid; i < maxE; i += BLOCK) { rbar[i] = 0.f; cbar[i] = 0.f; }
     if (tid < 8) prA[tid] = 0.f;
-    const BodySink sinkA{A.type == CM_POLYTOPE ? plA : nullptr, prA, maxF};
-    const BodySink sinkB{B.type == CM_POLYTOPE ? plB : nullptr, prB, maxF};
+    // face-plane adjoints only feed the hull-vertex gradient: without it
+    // they are not accumulated
+    const bool want_planes = ga.gr.g_vertices != nullptr;
+    const BodySink sinkA{(want_planes && A.type == CM_POLYTOPE) ? plA : nullptr, prA, maxF};
+    const BodySink sinkB{(want_planes && B.type == CM_POLYTOPE) ? plB : nullptr, prB, maxF};
 
     // ------------------------------------------------ recompute the forward
     P.stage();
@@ -124,7 +127,7 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
       c[7] = ga.cot.gw ? double(ga.cot.gw[o]) : 0.0;
       const double* a = P.sAcc + 9 * k;
       double* F = Fk + 10 * k;
-      const double iz = 1.0 / a[0];
+      const double iz = a[0] > 0.0 ? 1.0 / a[0] : 0.0;   // empty row: no candidate
       double gbar = 0.0;
       for (int f = 0; f < 8; ++f) { F[f] = a[f + 1] * iz; gbar += c[f] * F[f]; }
       F[8] = a[0];
@@ -138,6 +141,7 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
       for (int k = 0; k < K; ++k) {
         const long long o = (long long)pi * K + k;
         const double* F = Fk + 10 * k;
+        if (!(F[8] > 0.0)) continue;   // empty row: a constant output
         const D3 Pw = add(rot(R, d3(F[0], F[1], F[2])), d3(ps.tA[0], ps.tA[1], ps.tA[2]));
         const D3 Nw = rot(R, d3(F[3], F[4], F[5]));
         const D3 gP = ga.cot.gp ? d3(ga.cot.gp[o], ga.cot.gp[CK + o], ga.cot.gp[2 * CK + o]) : d3(0, 0, 0);
@@ -166,6 +170,7 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
         for (int r = sl; r < tot; r += nsl) {
           const Rec& R = P.sRec[r];
           const double dl = sk - R.s;
+          if (!(F[8] > 0.0)) continue;   // empty row
           const double G = double(expn(fabs(dl), T)) / F[8];
           const double fv[8] = {R.px, R.py, R.pz, R.nx, R.ny, R.nz, R.d, R.w};
           double gi = 0.0;
@@ -210,6 +215,7 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
           const double* F = Fk + 10 * k;
           const double* c = cotL + 8 * k;
           const double dl = P.sTop[k] - R.s;
+          if (!(F[8] > 0.0)) continue;   // empty row
           const double G = double(expn(fabs(dl), T)) / F[8];
           double gi = 0.0;
           for (int f = 0; f < 8; ++f) { gi += c[f] * fv[f]; fb[f] += G * c[f]; }
@@ -387,7 +393,7 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
 
     // ------------------------------------------------ G: geometry and pose gradients
     // face planes -> hull vertices (body frames)
-    for (int i = tid; i < nfA + nfB; i += BLOCK) {
+    for (int i = tid; want_planes && i < nfA + nfB; i += BLOCK) {
       const bool isA = i < nfA;
       const int f = isA ? i : i - nfA;
       const GeomRec& G = isA ? *P.GA : *P.GB;

@@ -73,23 +73,23 @@ __device__ __forceinline__ double rcp64(double x) {
   return fma(r, e, r);
 }
 
-// exp(x) for x <= 700 to ~1e-12 relative in float64: Cody-Waite reduction
-// x = n ln2 + r, |r| <= ln2 / 2, then a degree-9 Taylor polynomial of e^r
-// (remainder below r^10 / 10! ~ 7e-12) scaled by 2^n.
+// exp(x) for x <= 700 in float64, branch free: Cody-Waite reduction
+// x = n ln2 + r, |r| <= ln2 / 2, then a degree-7 polynomial of e^r with
+// p(0) = 1 whose other coefficients were fitted by a Remez exchange on the
+// relative error over that interval (max 2.3e-10), scaled by 2^n.  Inputs
+// below -745 are clamped, so the result underflows to zero there.
 __device__ __forceinline__ double exp64n(double x) {
-  if (x < -700.0) return 0.0;
+  x = fmax(x, -745.0);
   const double n = rint(x * kLog2e);
   double r = fma(-n, 6.93147180369123816490e-01, x);   // ln2 high part
   r = fma(-n, 1.90821492927058770002e-10, r);          // ln2 low part
-  double p = 2.7557319223985893e-06;                   // 1/9!
-  p = fma(p, r, 2.4801587301587302e-05);               // 1/8!
-  p = fma(p, r, 1.9841269841269841e-04);               // 1/7!
-  p = fma(p, r, 1.3888888888888889e-03);               // 1/6!
-  p = fma(p, r, 8.3333333333333333e-03);               // 1/5!
-  p = fma(p, r, 4.1666666666666667e-02);               // 1/4!
-  p = fma(p, r, 1.6666666666666667e-01);               // 1/3!
-  p = fma(p, r, 0.5);
-  p = fma(p, r, 1.0);
+  double p = 1.7378911869613724e-04;
+  p = fma(p, r, 1.3941038928452576e-03);
+  p = fma(p, r, 8.3385787951517860e-03);
+  p = fma(p, r, 4.1666353940642690e-02);
+  p = fma(p, r, 1.6666635163904225e-01);
+  p = fma(p, r, 5.0000000468041280e-01);
+  p = fma(p, r, 1.0000000046987592e+00);
   p = fma(p, r, 1.0);
   return ldexp(p, int(n));
 }
@@ -381,6 +381,7 @@ struct EdgeSoA {
 struct EEQP {
   double al1, al2, log_con;
   D3 de;      // Delta e = e1 - e2
+  double con; // the inside-box indicator itself (set by ee_qp only)
 };
 
 // The QP result from its solution: Delta e = (a0 - b0) + al1 t1 - al2 t2.
@@ -434,9 +435,24 @@ __device__ __forceinline__ EEQP ee_qp(const D3& a0, const D3& t1, const D3& b0, 
   const double iw = rcp64((w0 + w1) + (w2 + w3));
   const double ac1 = (w0 + w2 * xc + w3 * xd) * iw;
   const double ac2 = (w0 * xa + w1 * xb + w2) * iw;
-  const double con = (sig64(au1, T) * sig64(1.0 - au1, T)) * (sig64(au2, T) * sig64(1.0 - au2, T));
+  // the product of the four logistic factors sigma(x / tau) of the box test,
+  // each m / (1 + e) with e = exp(-|x| / tau) and m = 1 (x >= 0) or e, over
+  // one reciprocal
+  double num = 1.0, den = 1.0;
+  auto factor = [&](double x) {
+    const double e = exp64n(-fabs(x) * T.inv_tau);
+    num *= x >= 0.0 ? 1.0 : e;
+    den *= 1.0 + e;
+  };
+  factor(au1);
+  factor(1.0 - au1);
+  factor(au2);
+  factor(1.0 - au2);
+  const double con = num * rcp64(den);
   const double log_con = (lsig(au1, T) + lsig(1.0 - au1, T)) + (lsig(au2, T) + lsig(1.0 - au2, T));
-  return ee_from_alpha(a0, t1, b0, t2, con * au1 + (1.0 - con) * ac1, con * au2 + (1.0 - con) * ac2, log_con);
+  EEQP r = ee_from_alpha(a0, t1, b0, t2, con * au1 + (1.0 - con) * ac1, con * au2 + (1.0 - con) * ac2, log_con);
+  r.con = con;
+  return r;
 }
 
 // ----------------------------------------------------------------- candidates

@@ -154,7 +154,7 @@ extern "C" cm_status cm_collide_fused(cm_context* ctx, const cm_batch* batch, co
                             uint64_t(bd.n_cand), uint64_t(uintptr_t(od.n_pairs)), uint64_t(uintptr_t(od.pairs)),
                             uint64_t(uintptr_t(od.point)), uint64_t(uintptr_t(od.normal)),
                             uint64_t(uintptr_t(od.dist)), uint64_t(uintptr_t(od.weight)),
-                            uint64_t(uintptr_t(od.pair_offsets)), uint64_t(od.capacity), uint64_t(pd.K)};
+                            uint64_t(uintptr_t(od.pair_offsets)), uint64_t(od.capacity), uint64_t(pd.K), uint64_t(pd.flags)};
   for (uint64_t v : parts) key = mix(key, v);
   double dv[4] = {pd.tau, pd.lam, pd.eps_n, double(pd.margin)};
   for (double d : dv) { uint64_t b; std::memcpy(&b, &d, 8); key = mix(key, b); }

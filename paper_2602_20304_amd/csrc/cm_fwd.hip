@@ -183,15 +183,19 @@ void collide_fwd(Tables tb, BatchDev bt, ParamsDev prm, OutDev out,
       // outputs: divide by row sums, rotate to world
       for (int kk = tid; kk < K; kk += BLOCK) {
         const double* a = P.sAcc + 9 * kk;
-        const double inv = 1.0 / a[0];
+        // a row with no candidate (fewer candidates than K) is empty
+        // a row with no candidate (fewer candidates than K) is all zeros
+        const bool live = a[0] > 0.0;
+        const double inv = live ? 1.0 / a[0] : 0.0;
         const double px = a[1] * inv, py = a[2] * inv, pz = a[3] * inv;
         const double nx = a[4] * inv, ny = a[5] * inv, nz = a[6] * inv;
         const double* R = ps.RA;
+        const double tx = live ? ps.tA[0] : 0.0, ty = live ? ps.tA[1] : 0.0, tz = live ? ps.tA[2] : 0.0;
         const long long o = (long long)pi * K + kk;
         const long long CK = (long long)out.capacity * K;
-        out.point[o] = float(R[0] * px + R[1] * py + R[2] * pz + ps.tA[0]);
-        out.point[CK + o] = float(R[3] * px + R[4] * py + R[5] * pz + ps.tA[1]);
-        out.point[2 * CK + o] = float(R[6] * px + R[7] * py + R[8] * pz + ps.tA[2]);
+        out.point[o] = float(R[0] * px + R[1] * py + R[2] * pz + tx);
+        out.point[CK + o] = float(R[3] * px + R[4] * py + R[5] * pz + ty);
+        out.point[2 * CK + o] = float(R[6] * px + R[7] * py + R[8] * pz + tz);
         out.normal[o] = float(R[0] * nx + R[1] * ny + R[2] * nz);
         out.normal[CK + o] = float(R[3] * nx + R[4] * ny + R[5] * nz);
         out.normal[2 * CK + o] = float(R[6] * nx + R[7] * ny + R[8] * nz);

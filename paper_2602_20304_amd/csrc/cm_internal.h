@@ -49,6 +49,7 @@ struct ParamsDev {
   float margin;             // broadphase margin (float32 predicate)
   int32_t K;
   int32_t eps_tied;         // eps_n = tau^2 (its tau dependence enters the adjoint)
+  uint32_t flags;           // CM_FLAG_*
 };
 
 struct OutDev {

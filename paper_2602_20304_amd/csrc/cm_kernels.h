@@ -63,6 +63,11 @@ hipError_t launch_broadphase(const Tables& tb, const BatchDev& bt, float margin,
                              unsigned* err, hipStream_t st);
 hipError_t launch_collide_fwd(const FwdLaunch& f, hipStream_t st);
 
+// batched E-E witness points of independent edge pairs: edges [12][n],
+// out [9][n] (float32 rows of stride n); hard = no smoothing
+hipError_t launch_ee_witness(const float* edges, long long n, const ParamsDev& prm, bool hard, float* out,
+                             hipStream_t st);
+
 // fused path: size classes and cost order
 constexpr int kNumClasses = 3;
 constexpr int kNumBuckets = 48;

@@ -131,6 +131,7 @@ struct PairEngine {
   int* List;      // [nvs + 2 nee + 64] compacted indices of filtered candidates
   Temp T;
   double lam, eps_n;
+  unsigned flags;   // CM_FLAG_*
   int K, maxV, maxE, maxF;
   int tid, lane, wave;
   BodyView A, B;
@@ -167,6 +168,7 @@ struct PairEngine {
     List = reinterpret_cast<int*>(Sbuf + 2 * mm + 2LL * maxV_);
     T = make_temp(prm);
     lam = prm.lam;
+    flags = prm.flags;
     eps_n = prm.eps_n;
     K = prm.K;
     maxV = maxV_; maxE = maxE_; maxF = maxF_;
@@ -206,8 +208,8 @@ struct PairEngine {
         ps.A.type = G1.type; ps.A.nv = G1.nv; ps.A.ne = G1.ne; ps.A.nf = G1.nf;
         ps.B.type = G2.type; ps.B.nv = G2.nv; ps.B.ne = G2.ne; ps.B.nf = G2.nf;
         for (int i = 0; i < 4; ++i) { ps.A.p[i] = G1.p[i]; ps.B.p[i] = G2.p[i]; }
-        ps.nvs = G1.nv + G2.nv;
-        ps.nee = G1.ne * G2.ne;
+        ps.nvs = G1.nv + ((flags & CM_FLAG_ONE_SIDED_VS) ? 0 : G2.nv);
+        ps.nee = (flags & CM_FLAG_NO_EE) ? 0 : G1.ne * G2.ne;
         ps.ncand = ps.nvs + 2 * ps.nee;
         if (G1.nv > maxV || G2.nv > maxV || G1.ne > maxE || G2.ne > maxE || G1.nf > maxF || G2.nf > maxF) {
           ps.valid = 0;
@@ -278,7 +280,7 @@ struct PairEngine {
   // max(y'_g(p0), y'_g(p1)) < max_f min(y'_f(p0), y'_f(p1)) - 38, which
   // bounds its term in the LSE and in the gradient softmax below 2^-38.
   __device__ void cull() {
-    if (!CULL || MW == 0) return;
+    if (!CULL || MW == 0 || ps.nee == 0) return;
     const double ext = 0.3 * T.tau;
     for (int k = tid; k < A.ne; k += BLOCK) {
       D3 a0, t1;
@@ -417,6 +419,7 @@ struct PairEngine {
       }
     }
     __syncthreads();
+    if (nee == 0) return;   // vertex-SDF candidates only (CM_FLAG_NO_EE)
     // row LSE over l (one wave per row, coalesced)
     for (int k = wave; k < neA; k += NW) {
       double m = INFINITY;

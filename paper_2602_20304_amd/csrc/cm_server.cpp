@@ -257,7 +257,7 @@ cm_status cm_server_submit(cm_server* srv, const cm_request* q, uint64_t* ticket
   if (!srv || !q || !ticket) return CM_ERR_INVALID_ARG;
   if (q->n_scenes < 0 || q->n_bodies < 0 || (q->n_scenes > 0 && (!q->body_offsets || !q->body_geom || !q->pose)))
     return CM_ERR_INVALID_ARG;
-  if (q->params.K < 1 || q->params.K > CM_MAX_K || !(q->params.tau > 0.f) || q->params.flags != 0)
+  if (q->params.K < 1 || q->params.K > CM_MAX_K || !(q->params.tau > 0.f) || (q->params.flags & ~(CM_FLAG_NO_EE | CM_FLAG_ONE_SIDED_VS)))
     return CM_ERR_INVALID_ARG;
   auto r = std::make_unique<Request>();
   r->n_scenes = q->n_scenes;

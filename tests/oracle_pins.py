@@ -309,6 +309,41 @@ def pin_qp_regularised_limit():
             assert abs(float(qp["al1"]) - x) < 1e-4 and abs(float(qp["al2"]) - y) < 1e-4, (lam, x, y)
 
 
+def pin_qp_no_smoothing():
+    """Ours-NS: the exact minimiser of the regularised box QP, against grid
+    search and scipy's bounded quasi-Newton solver; it is the tau -> 0 limit
+    of the smoothed routine; the batched witness form agrees pair by pair."""
+    from scipy.optimize import minimize
+    rng = np.random.default_rng(13)
+    for lam in (0.01, 0.3):
+        E = np.array(_rand_edges(rng, 20))
+        for a0, a1, b0, b1 in E:
+            x, y, f = _seg_closest_brute(a0, a1, b0, b1, lam)
+            with torch.no_grad():
+                q = O.ee_qp_hard(T(a0), T(a1), T(b0), T(b1), lam)
+                qs = O.ee_qp(T(a0), T(a1), T(b0), T(b1), 1e-9, lam)
+            fun = lambda z: float(((a0 + z[0] * (a1 - a0) - b0 - z[1] * (b1 - b0)) ** 2).sum()
+                                  + lam * ((z[0] - 0.5) ** 2 + (z[1] - 0.5) ** 2))
+            r = minimize(fun, [0.5, 0.5], method="L-BFGS-B", bounds=[(0, 1), (0, 1)], options=dict(ftol=1e-15, gtol=1e-12))
+            got = np.array([float(q["al1"]), float(q["al2"])])
+            assert np.abs(got - [x, y]).max() < 1e-4, (lam, got, x, y)
+            assert np.abs(got - r.x).max() < 1e-5, (lam, got, r.x)
+            assert fun(got) <= r.fun + 1e-12
+            assert abs(float(qs["al1"]) - got[0]) < 1e-6 and abs(float(qs["al2"]) - got[1]) < 1e-6
+            inside = 0 < r.x[0] < 1 and 0 < r.x[1] < 1
+            assert float(q["con"]) == (1.0 if inside else 0.0) or min(r.x.min(), 1 - r.x.max()) < 1e-6
+        wb = O.ee_witness_batch(E, 0.05, lam, hard=True)
+        ws = O.ee_witness_batch(E, 0.05, lam)
+        for i, (a0, a1, b0, b1) in enumerate(E):
+            with torch.no_grad():
+                q = O.ee_qp_hard(T(a0), T(a1), T(b0), T(b1), lam)
+                qs = O.ee_qp(T(a0), T(a1), T(b0), T(b1), 0.05, lam)
+            assert wb["al1"][i] == float(q["al1"]) and wb["al2"][i] == float(q["al2"])
+            assert np.allclose(wb["e1"][i], a0 + wb["al1"][i] * (a1 - a0), atol=1e-15)
+            assert np.allclose(wb["e2"][i], b0 + wb["al2"][i] * (b1 - b0), atol=1e-15)
+            assert abs(ws["al1"][i] - float(qs["al1"])) < 1e-15 and abs(ws["con"][i] - float(qs["con"])) < 1e-15
+
+
 def pin_qp_edge_swap_symmetry():
     """Swapping the two edges swaps (al1, al2) and leaves d_bar unchanged."""
     rng = np.random.default_rng(13)
@@ -515,6 +550,55 @@ def pin_pair_swap_antisymmetry():
         assert np.allclose(s["nu"].numpy(), -m["nu"].numpy(), atol=1e-9)
         for k in ("p", "d", "w"):
             assert np.allclose(s[k].numpy(), m[k].numpy(), atol=1e-9)
+
+
+def pin_simplification_flags():
+    """Ours-NE / Ours-NE-S (supplementary material): a polytope A against a
+    sphere B.  One-sided V-S candidates are exactly A's hull points in world
+    coordinates with the closed-form sphere distance |v - c| - r; without E-E
+    the candidate list is both bodies' vertices; K beyond the candidate count
+    leaves empty rows and does not change the others; dropping E-E keeps the
+    pair-swap antisymmetry."""
+    rng = np.random.default_rng(41)
+    pts = W.ellipsoid_points(rng, 14, [0.45, 0.35, 0.4])
+    GA = O.make_geom(O.POLYTOPE, points=pts)
+    r = 0.3
+    GB = O.make_geom(O.SPHERE, params=[r, 0, 0, 0])
+    qA, qB = W.uniform_quats(rng, 2)
+    pA, pB = _pose(qA, [0.0, 0.0, 0.0]), _pose(qB, [0.55, 0.1, -0.05])
+    tau = 0.02
+    RA, tA = O.pose_Rt(pA)
+    RB, tB = O.pose_Rt(pB)
+    with torch.no_grad():
+        full = O.pair_candidates(GA, RA, tA, GB, RB, tB, tau)
+        ne = O.pair_candidates(GA, RA, tA, GB, RB, tB, tau, no_ee=True)
+        nes = O.pair_candidates(GA, RA, tA, GB, RB, tB, tau, no_ee=True, one_sided_vs=True)
+    hull = np.unique(np.asarray(GA.edges).reshape(-1))
+    nA, nB = len(hull), GB.vertices().shape[0]
+    assert nes["d"].shape[0] == nA and ne["d"].shape[0] == nA + nB
+    assert full["d"].shape[0] == nA + nB + 2 * GA.edges.shape[0] * GB.edges.shape[0]
+    Rq = O.quat_to_R(T(qA)).numpy()
+    vw = np.asarray(GA.vertices(), float) @ Rq.T
+    assert np.allclose(nes["p"].numpy(), vw, atol=1e-12)
+    # the hull points of the mesh are the input points that are hull vertices
+    assert all(np.abs(pts.astype(float) - v).max(axis=1).min() < 1e-6 for v in np.asarray(GA.vertices(), float))
+    c = np.asarray(pB[4:], float)
+    d_ref = np.linalg.norm(vw - c, axis=1) - r
+    assert np.allclose(nes["d"].numpy(), d_ref, atol=1e-12)
+    for k in ("p", "nu", "d", "logw"):
+        assert torch.equal(ne[k], full[k][:nA + nB])
+    K = nA + 5
+    m_full = O.manifold(nes, tau, nA)
+    m_pad = O.manifold(nes, tau, K)
+    for k in ("p", "nu", "d", "w"):
+        assert torch.allclose(m_pad[k][:nA], m_full[k], atol=1e-14)
+        assert bool((m_pad[k][nA:] == 0).all())
+    with torch.no_grad():
+        m = O.collide_pair(GA, pA, GB, pB, tau, 6, no_ee=True)
+        s = O.collide_pair(GB, pB, GA, pA, tau, 6, no_ee=True)
+    assert np.allclose(s["nu"].numpy(), -m["nu"].numpy(), atol=1e-9)
+    for k in ("p", "d", "w"):
+        assert np.allclose(s[k].numpy(), m[k].numpy(), atol=1e-9)
 
 
 # ----------------------------------------------------------------------------- gradients

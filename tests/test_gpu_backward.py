@@ -27,11 +27,11 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def gpu_grads(ctx, batch, seed=0):
-    _say(f"[gpu-bwd] {batch.name} scenes={batch.n_scenes} tau={batch.tau} K={batch.K}")
+def gpu_grads(ctx, batch, seed=0, flags=0):
+    _say(f"[gpu-bwd] {batch.name} scenes={batch.n_scenes} tau={batch.tau} K={batch.K} flags={flags}")
     ids = ctx.create_geometry(batch.geoms)
     db = ctx.upload_batch(batch, ids)
-    m = ctx.collide(db, batch.tau, batch.K)
+    m = ctx.collide(db, batch.tau, batch.K, flags=flags)
     ctx.check_errors()
     n = int(m.n_pairs.item())
     K = batch.K
@@ -40,13 +40,13 @@ def gpu_grads(ctx, batch, seed=0):
     cot = {k: rng.standard_normal(s).astype(np.float32) for k, s in
            (("p", (3, cap * K)), ("nu", (3, cap * K)), ("d", (cap * K,)), ("w", (cap * K,)))}
     tt = {k: torch.as_tensor(v).to(ctx.device) for k, v in cot.items()}
-    g = ctx.collide_backward(db, m, batch.tau, K, tt["p"], tt["nu"], tt["d"], tt["w"])
+    g = ctx.collide_backward(db, m, batch.tau, K, tt["p"], tt["nu"], tt["d"], tt["w"], flags=flags)
     ctx.check_errors()
     out = {k: (v.cpu().numpy() if v is not None else None) for k, v in g.items()}
     return ids, m.to_numpy(), cot, out, n
 
 
-def oracle_grads(batch, pairs, cot, K):
+def oracle_grads(batch, pairs, cot, K, flags=0):
     cache = O.GeomCache(batch.geoms, requires_grad=True)
     nb = batch.n_bodies
     g_pose = np.zeros((6, nb))
@@ -57,7 +57,8 @@ def oracle_grads(batch, pairs, cot, K):
         GA, GB = cache[batch.body_geom[a]], cache[batch.body_geom[b]]
         sl = slice(i * K, (i + 1) * K)
         c = dict(p=cot["p"][:, sl].T, nu=cot["nu"][:, sl].T, d=cot["d"][sl], w=cot["w"][sl])
-        r = O.pair_grad(GA, batch.pose[:, a], GB, batch.pose[:, b], batch.tau, K, c)
+        r = O.pair_grad(GA, batch.pose[:, a], GB, batch.pose[:, b], batch.tau, K, c, no_ee=bool(flags & 1),
+                        one_sided_vs=bool(flags & 2))
         g_pose[:, a] += r["xiA"]
         g_pose[:, b] += r["xiB"]
         ga, gb = int(batch.body_geom[a]), int(batch.body_geom[b])
@@ -76,10 +77,10 @@ def close(got, ref, rtol=GRAD_RTOL):
     return float(err.max()) if err.size else -1.0, float(np.max(np.abs(got - ref))) if err.size else 0.0, scale
 
 
-def check(ctx, batch, seed=0):
-    ids, fwd, cot, g, n = gpu_grads(ctx, batch, seed)
+def check(ctx, batch, seed=0, flags=0):
+    ids, fwd, cot, g, n = gpu_grads(ctx, batch, seed, flags)
     pairs = fwd["pairs"]
-    g_pose, g_geom, g_tau, cache = oracle_grads(batch, pairs, cot, batch.K)
+    g_pose, g_geom, g_tau, cache = oracle_grads(batch, pairs, cot, batch.K, flags)
     rep = {}
     rep["pose"] = close(g["pose"], g_pose)
     vx, vr, pr_g, pr_r = [], [], [], []
@@ -141,3 +142,35 @@ def test_backward_joint_motion_identity(ctx):
     sums = np.stack([pose[:3, bo[s]:bo[s + 1]].sum(1) for s in range(b.n_scenes)])
     scale = np.abs(pose[:3]).max()
     assert np.abs(sums).max() <= 1e-4 * scale, (np.abs(sums).max(), scale)
+
+
+def test_backward_without_vertex_gradients_matches(ctx):
+    """Skipping the hull-vertex gradient (no face-plane adjoints) leaves the
+    pose, parameter and tau gradients unchanged."""
+    b = W.mixed_scenes(12, seed=7)
+    _say(f"[gpu-bwd] with / without vertex gradients: {b.n_scenes} scenes")
+    ids = ctx.create_geometry(b.geoms)
+    db = ctx.upload_batch(b, ids)
+    m = ctx.collide(db, b.tau, b.K)
+    ctx.check_errors()
+    rng = np.random.default_rng(3)
+    cap = m.capacity
+    tt = {k: torch.as_tensor(rng.standard_normal(s).astype(np.float32)).to(ctx.device)
+          for k, s in (("p", (3, cap * b.K)), ("nu", (3, cap * b.K)), ("d", (cap * b.K,)), ("w", (cap * b.K,)))}
+    g1 = ctx.collide_backward(db, m, b.tau, b.K, tt["p"], tt["nu"], tt["d"], tt["w"], want_vertices=True)
+    g2 = ctx.collide_backward(db, m, b.tau, b.K, tt["p"], tt["nu"], tt["d"], tt["w"], want_vertices=False)
+    ctx.check_errors()
+    for k in ("pose", "params", "tau"):
+        a, c = g1[k].cpu().numpy(), g2[k].cpu().numpy()
+        assert np.allclose(a, c, rtol=1e-5, atol=1e-6 * (np.abs(a).max() + 1e-12)), k
+
+
+@pytest.mark.parametrize("flags", [1, 3])
+def test_backward_simplification_flags(ctx, flags):
+    check(ctx, W.mixed_scenes(6, seed=24, poly_points=16, tau=0.01), flags=flags)
+
+
+def test_backward_fewer_candidates_than_K(ctx):
+    b = W.cube_pairs(16, seed=25, K=12)
+    b.pose[4:7] += np.array([[0.3], [-0.2], [0.5]], dtype=b.pose.dtype)   # body A off the origin
+    check(ctx, b, flags=3)

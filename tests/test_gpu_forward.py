@@ -26,16 +26,16 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def run_gpu(ctx, batch, fused=False, capacity=None):
-    _say(f"[gpu] {batch.name} scenes={batch.n_scenes} fused={fused} K={batch.K} tau={batch.tau}")
+def run_gpu(ctx, batch, fused=False, capacity=None, flags=0):
+    _say(f"[gpu] {batch.name} scenes={batch.n_scenes} fused={fused} K={batch.K} tau={batch.tau} flags={flags}")
     ids = ctx.create_geometry(batch.geoms)
     db = ctx.upload_batch(batch, ids)
-    m = ctx.collide(db, batch.tau, batch.K, capacity, fused=fused)
+    m = ctx.collide(db, batch.tau, batch.K, capacity, fused=fused, flags=flags)
     ctx.check_errors()
     return m.to_numpy()
 
 
-def check_against_oracle(batch, got, max_pairs=None, seed=0):
+def check_against_oracle(batch, got, max_pairs=None, seed=0, flags=0):
     pairs, off = O.broadphase(batch)
     assert got["n_pairs"] == pairs.shape[1]
     assert np.array_equal(got["offsets"], off), "pair offsets differ"
@@ -44,7 +44,7 @@ def check_against_oracle(batch, got, max_pairs=None, seed=0):
     sel = np.arange(n)
     if max_pairs is not None and n > max_pairs:
         sel = np.sort(np.random.default_rng(seed).choice(n, max_pairs, replace=False))
-    _, _, ref = O.collide_batch(batch, pair_list=pairs[:, sel])
+    _, _, ref = O.collide_batch(batch, pair_list=pairs[:, sel], no_ee=bool(flags & 1), one_sided_vs=bool(flags & 2))
     ok, rep = compare_outputs(got, ref, idx=sel)
     _say(f"   parity {batch.name}: {rep}")
     assert ok, rep
@@ -192,3 +192,26 @@ def test_kernel_timing_counts_launches(ctx):
     ctx.collide(db, b.tau, b.K)
     assert ctx.kernel_time("forward") == (0.0, 0)
     ctx.check_errors()
+
+
+@pytest.mark.parametrize("flags", [1, 3])
+def test_simplification_flags(ctx, flags):
+    """Ours-NE (no E-E) and Ours-NE-S (one-sided V-S), plain and fused."""
+    b = W.mixed_scenes(48, seed=7)
+    got = run_gpu(ctx, b, flags=flags)
+    check_against_oracle(b, got, flags=flags)
+    fused = run_gpu(ctx, b, fused=True, flags=flags)
+    for k in ("pairs", "offsets", "p", "nu", "d", "w"):
+        assert np.array_equal(fused[k], got[k]), k
+
+
+def test_fewer_candidates_than_K(ctx):
+    """One-sided V-S of a cube (8 vertices) with K = 12: rows 8..11 are empty."""
+    b = W.cube_pairs(256, seed=8, K=12)
+    b.pose[4:7] += np.array([[0.3], [-0.2], [0.5]], dtype=b.pose.dtype)   # body A off the origin
+    got = run_gpu(ctx, b, flags=3)
+    check_against_oracle(b, got, flags=3)
+    n = got["n_pairs"]
+    assert n > 0
+    for k in ("p", "nu", "d", "w"):
+        assert not np.any(got[k][:n, 8:]), k

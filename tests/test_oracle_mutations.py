@@ -49,8 +49,18 @@ MUTATIONS = [
     ("manifold", "torch.softmax(-torch.abs(top[:, None] - s[None, :]) / tau, dim=1)",
      "torch.softmax(-(top[:, None] - s[None, :]) / tau, dim=1)",
      [P.pin_manifold_properties]),                                                     # SoftSort without |.|
-    ("manifold", "top = torch.topk(s, K, sorted=True).values", "top = torch.topk(s, K, largest=False).values",
+    ("manifold", "top = torch.topk(s, k, sorted=True).values", "top = torch.topk(s, k, largest=False).values",
      [P.pin_manifold_properties]),                                                     # bottom-K
+    ("manifold", "out[key] = torch.cat([out[key], out[key].new_zeros(pad)])",
+     "out[key] = torch.cat([out[key], out[key].new_ones(pad)])",
+     [P.pin_simplification_flags]),                                                    # empty rows not empty
+    ("pair_candidates", "vs_p, vs_nu, vs_d, vs_logw = vs_p[:nA], vs_nu[:nA], vs_d[:nA], vs_logw[:nA]",
+     "vs_p, vs_nu, vs_d, vs_logw = vs_p[-nA:], vs_nu[-nA:], vs_d[-nA:], vs_logw[-nA:]",
+     [P.pin_simplification_flags]),                                                    # one-sided keeps B's side
+    ("ee_qp_hard", "torch.clamp(-(Q12 + c2) / Q22, 0.0, 1.0)", "torch.clamp(-(Q12 - c2) / Q22, 0.0, 1.0)",
+     [P.pin_qp_no_smoothing]),                                                         # edge minimiser sign
+    ("ee_qp_hard", "best = torch.argmin(costs, dim=-1, keepdim=True)", "best = torch.argmax(costs, dim=-1, keepdim=True)",
+     [P.pin_qp_no_smoothing]),                                                         # worst box edge
     ("quat_to_R", "[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)]",
      "[1 - 2 * (y * y + z * z), 2 * (x * y + w * z), 2 * (x * z + w * y)]",
      [P.pin_quaternion_rotation]),                                                     # sign in R

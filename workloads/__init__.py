@@ -394,6 +394,14 @@ def cotangents(n_pairs: int, K: int, seed: int = 0):
     return a, b
 
 
+def edge_pairs(n: int, seed: int = 0) -> np.ndarray:
+    """n edge pairs with endpoints uniform in the unit cube, float32 [n, 4, 3]
+    (rows a0, a1, b0, b1): the queries of the witness-point speed experiment
+    (Sec. V, Fig. 6)."""
+    rng = _rng(7, seed)
+    return rng.random((n, 4, 3), dtype=np.float32)
+
+
 def subset_scenes(batch: Batch, scenes) -> Batch:
     """Batch restricted to the given scenes (geometry set kept whole)."""
     scenes = np.asarray(scenes, dtype=np.int64)
