@@ -66,26 +66,30 @@ def build_workload(name: str, scenes: int | None):
     return b, desc
 
 
-def source_hash() -> str:
-    """Hash of the kernel sources (a stored traffic figure is void once they change)."""
+FWD_SOURCES = ("cm_fwd.hip", "cm_pair.cuh", "cm_device.cuh", "cm_kernels.h", "cm_internal.h")
+EE_SOURCES = ("cm_ee.hip", "cm_device.cuh", "cm_kernels.h", "cm_internal.h")
+EE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ee_witness_1e7_traffic.md")
+
+
+def source_hash(files=FWD_SOURCES) -> str:
+    """Hash of a kernel's sources (a stored traffic figure is void once they change)."""
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2602_20304_amd", "csrc")
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".cuh", ".h")):
-            with open(os.path.join(d, f), "rb") as fh:
-                h.update(f.encode() + b"\0" + fh.read())
+    for f in sorted(files):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
     return h.hexdigest()[:16]
 
 
-def stored_traffic(workload: str):
-    """HBM bytes per forward launch from the committed PMC summary, or None
-    when it is absent, for another workload, or taken on other sources."""
-    if workload != "mixed" or not os.path.exists(TRAFFIC_FILE):
+def stored_traffic(path: str, files, key: str = "traffic_bytes_per_launch"):
+    """HBM bytes per launch from a committed PMC summary, or None when it is
+    absent or was taken on other kernel sources."""
+    if not os.path.exists(path):
         return None
-    txt = open(TRAFFIC_FILE).read()
+    txt = open(path).read()
     m_hash = re.search(r"source_hash:\s*([0-9a-f]+)", txt)
-    m_bytes = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
-    if not m_hash or not m_bytes or m_hash.group(1) != source_hash():
+    m_bytes = re.search(key + r":\s*([0-9.eE+]+)", txt)
+    if not m_hash or not m_bytes or m_hash.group(1) != source_hash(files):
         return None
     return float(m_bytes.group(1))
 
@@ -249,8 +253,10 @@ def ee_witness_leg(ctx, trials: int = 100, max_n: int = 10_000_000, tau: float =
         kms = means[-1]
         gbs = EE_BYTES_PER_QUERY * sizes[-1] / (kms * 1e-3) / 1e9
         res[f"{mode}_queries_per_s"] = sizes[-1] / (kms * 1e-3)
+        traffic = stored_traffic(EE_TRAFFIC_FILE, EE_SOURCES, f"{mode}_traffic_bytes_per_launch")
         res[f"{mode}_roofline"] = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                   "frac": gbs / HBM_PEAK_GBS, "bytes_per_query": EE_BYTES_PER_QUERY}
+                                   "frac": gbs / HBM_PEAK_GBS, "bytes_per_query": EE_BYTES_PER_QUERY,
+                                   "queries_per_launch": sizes[-1], "traffic": traffic}
     return res
 
 
@@ -280,6 +286,7 @@ def main():
     ap.add_argument("--serve", type=int, default=16, help="requests in the serving leg (0 = skip)")
     ap.add_argument("--no-ee", action="store_true", help="skip the E-E witness microbenchmark")
     ap.add_argument("--ee-only", action="store_true", help="run only the E-E witness microbenchmark")
+    ap.add_argument("--ee-trials", type=int, default=100, help="timed launches per size in the E-E sweep")
     ap.add_argument("--no-simplifications", action="store_true",
                     help="skip the forward legs without E-E (ne) and with one-sided vertex contacts (ne_s)")
     ap.add_argument("--only", default=None, choices=[None, "plain", "fused", "fwd_bwd", "plain_ne", "plain_ne_s"],
@@ -301,7 +308,7 @@ def main():
 
     if args.ee_only:
         ctx = Context(0)
-        print(json.dumps({"ee_witness": ee_witness_leg(ctx)}), flush=True)
+        print(json.dumps({"ee_witness": ee_witness_leg(ctx, trials=args.ee_trials)}), flush=True)
         return
 
     batch, desc = build_workload(args.workload, args.scenes)
@@ -376,7 +383,7 @@ def main():
     if k_n:
         kms = k_ms / k_n
         roof = opmodel.roofline(ops, kms * 1e-3)
-        traffic = stored_traffic(args.workload)
+        traffic = stored_traffic(TRAFFIC_FILE, FWD_SOURCES) if args.workload == "mixed" else None
         roofline = {"bound": "alu", "kernel": FWD_KERNEL, "achieved": roof["achieved_flops"] / 1e12,
                     "peak": roof["peak_flops"] / 1e12, "unit": "TFLOP/s", "frac": roof["frac"],
                     "traffic": traffic, "kernel_ms": kms, "launches": k_n,
