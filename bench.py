@@ -192,6 +192,8 @@ def serving_leg(ctx_cls, n_requests: int, seed: int = 11):
         torch.cuda.synchronize()
         return pairs / (time.perf_counter() - t0)
 
+    run(payload[:2], [0.0, 0.0])          # warm-up (module loads, first allocations), not timed
+    run_plain(payload[:2])
     cal, cal_wall = run(payload[:n_cal], [0.0] * n_cal)
     sat = n_cal / cal_wall
     rate = 0.7 * sat
@@ -286,6 +288,7 @@ def main():
     ap.add_argument("--serve", type=int, default=16, help="requests in the serving leg (0 = skip)")
     ap.add_argument("--no-ee", action="store_true", help="skip the E-E witness microbenchmark")
     ap.add_argument("--ee-only", action="store_true", help="run only the E-E witness microbenchmark")
+    ap.add_argument("--serve-only", action="store_true", help="run only the serving leg")
     ap.add_argument("--ee-trials", type=int, default=100, help="timed launches per size in the E-E sweep")
     ap.add_argument("--no-simplifications", action="store_true",
                     help="skip the forward legs without E-E (ne) and with one-sided vertex contacts (ne_s)")
@@ -306,6 +309,9 @@ def main():
     from paper_2602_20304_amd.cm import FLAG_NO_EE, FLAG_ONE_SIDED_VS, Context, Manifold
     from paper_2602_20304_amd import opmodel
 
+    if args.serve_only:
+        print(json.dumps({"serving": serving_leg(Context, args.serve or 16)}), flush=True)
+        return
     if args.ee_only:
         ctx = Context(0)
         print(json.dumps({"ee_witness": ee_witness_leg(ctx, trials=args.ee_trials)}), flush=True)

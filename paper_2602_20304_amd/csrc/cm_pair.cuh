@@ -105,7 +105,6 @@ __host__ __device__ inline LdsLayout lds_layout(int maxE, int maxF, int block, i
 template <int BLOCK, int KMAX, bool CULL>
 struct PairEngine {
   static constexpr int NW = BLOCK / 64;
-  static constexpr int NSLOT = (9 * CM_MAX_K + BLOCK - 1) / BLOCK;
 
   PairShared& ps;
   const Tables& tb;
@@ -563,44 +562,42 @@ struct PairEngine {
 
   // ------------------------------------------------------------ SoftSort
   // sAcc[9k + f] = sum_i exp(-|s_[k] - s_i| / tau) * field_f(i), field 0 = 1.
+  // G consecutive lanes own row k (G = BLOCK / K rounded down to a power of
+  // two, at most 64, so a row's lanes sit in one wave); lane j of the group
+  // takes records j, j + G, ... and the exponential once for all nine fields.
+  // The G partial sums of a row meet in a shuffle tree at the end.
   __device__ void softsort() {
-    const int nacc = 9 * K;
-    double acc[NSLOT];
+    int G = 64;
+    while (G * K > BLOCK) G >>= 1;
+    const int kk = tid / G, j0 = tid - kk * G;
+    const bool act = kk < K;
+    const double sk = act ? sTop[kk] : 0.0;
+    double a[9];
 #pragma unroll
-    for (int i = 0; i < NSLOT; ++i) acc[i] = 0.0;
+    for (int f = 0; f < 9; ++f) a[f] = 0.0;
     for_filtered([&](int tot) {
-#pragma unroll
-      for (int slot = 0; slot < NSLOT; ++slot) {
-        const int j = tid + slot * BLOCK;
-        if (j < nacc) {
-          const int kk = j / 9, f = j - kk * 9;
-          const double sk = sTop[kk];
-          double a = 0.0;
-          for (int r = 0; r < tot; ++r) {
-            const Rec& rr = sRec[r];
-            const double e = double(expn(fabs(sk - rr.s), T));
-            double v;
-            switch (f) {
-              case 0: v = 1.0; break;
-              case 1: v = rr.px; break;
-              case 2: v = rr.py; break;
-              case 3: v = rr.pz; break;
-              case 4: v = rr.nx; break;
-              case 5: v = rr.ny; break;
-              case 6: v = rr.nz; break;
-              case 7: v = rr.d; break;
-              default: v = rr.w; break;
-            }
-            a = fma(e, v, a);
-          }
-          acc[slot] += a;
-        }
+      if (!act) return;
+      for (int r = j0; r < tot; r += G) {
+        const Rec& rr = sRec[r];
+        const double e = double(expn(fabs(sk - rr.s), T));
+        a[0] += e;
+        a[1] = fma(e, double(rr.px), a[1]);
+        a[2] = fma(e, double(rr.py), a[2]);
+        a[3] = fma(e, double(rr.pz), a[3]);
+        a[4] = fma(e, double(rr.nx), a[4]);
+        a[5] = fma(e, double(rr.ny), a[5]);
+        a[6] = fma(e, double(rr.nz), a[6]);
+        a[7] = fma(e, rr.d, a[7]);
+        a[8] = fma(e, double(rr.w), a[8]);
       }
     });
+    for (int off = G >> 1; off > 0; off >>= 1) {
 #pragma unroll
-    for (int slot = 0; slot < NSLOT; ++slot) {
-      const int j = tid + slot * BLOCK;
-      if (j < nacc) sAcc[j] = acc[slot];
+      for (int f = 0; f < 9; ++f) a[f] += __shfl_xor(a[f], off);
+    }
+    if (act && j0 == 0) {
+#pragma unroll
+      for (int f = 0; f < 9; ++f) sAcc[9 * kk + f] = a[f];
     }
     __syncthreads();
   }

@@ -91,6 +91,13 @@ struct Carve {
   }
 };
 
+// Persistent grid of one request: the whole GPU at the kernel's occupancy
+// (requests on other streams take over CUs as this grid's workgroups
+// retire), but no more workgroups than candidate pairs.
+long long request_grid(const cm_context* ctx, int occupancy, size_t cap) {
+  return std::max<long long>(1, std::min<long long>((long long)occupancy * ctx->num_cus, (long long)cap));
+}
+
 // Device bytes one request needs (inputs, outputs, scratch, gradients).
 uint64_t footprint(cm_context* ctx, const Request& r, long long grid, long long stride) {
   const int K = r.params.K;
@@ -118,7 +125,7 @@ void launch_request(cm_server* srv, Request& r) {
   // grid already folded into the footprint: recompute the same value
   f.prm = pd;
   const int occ = fwd_occupancy(f);
-  f.grid = std::max(1, occ * ctx->num_cus / std::max(1, srv->n_slots));
+  f.grid = int(request_grid(ctx, occ, cap));
   f.scratch_stride = fwd_scratch_floats(f.maxV, f.maxE);
   if (hipMallocAsync(&r.dev, size_t(r.footprint), st) != hipSuccess) { r.status = CM_ERR_OOM; return; }
   Carve c{static_cast<char*>(r.dev)};
@@ -160,8 +167,7 @@ void launch_request(cm_server* srv, Request& r) {
     b.f = f;
     b.cot = CotDev{nullptr, d_cn, d_cd, nullptr};
     b.gr = GradDev{d_gpose, nullptr, nullptr, d_gtau, (long long)ctx->h.vx.size()};
-    b.f.grid = std::max(1, bwd_occupancy(b) * ctx->num_cus / std::max(1, srv->n_slots));
-    b.f.grid = std::min(b.f.grid, f.grid);   // fits the scratch carved for the forward grid
+    b.f.grid = int(std::min<long long>(request_grid(ctx, bwd_occupancy(b), cap), f.grid));   // fits the forward's scratch
     if (launch_collide_bwd(b, st) != hipSuccess) { r.status = CM_ERR_DEVICE; return; }
     (void)hipMemcpyAsync(r.h_gpose, d_gpose, 24 * size_t(r.n_bodies), hipMemcpyDeviceToHost, st);
   }
@@ -286,7 +292,7 @@ cm_status cm_server_submit(cm_server* srv, const cm_request* q, uint64_t* ticket
   f.tb = ctx_tables(srv->ctx);
   f.maxV = std::max(srv->ctx->maxV, 1); f.maxE = std::max(srv->ctx->maxE, 1); f.maxF = std::max(srv->ctx->maxF, 1);
   f.block = 256; f.kmax = kmax_for(K); f.queue = nullptr;
-  const long long grid = std::max(1, fwd_occupancy(f) * srv->ctx->num_cus / std::max(1, srv->n_slots));
+  const long long grid = request_grid(srv->ctx, fwd_occupancy(f), cap);
   r->footprint = footprint(srv->ctx, *r, grid, fwd_scratch_floats(f.maxV, f.maxE));
   if (r->footprint > srv->budget) return cm_fail(srv->ctx, CM_ERR_REJECTED, "request exceeds the HBM budget");
   if (hipHostMalloc(reinterpret_cast<void**>(&r->h_n_pairs), 4) != hipSuccess ||
