@@ -94,21 +94,21 @@ __device__ __forceinline__ double exp64n(double x) {
   return ldexp(p, int(n));
 }
 
-// 2^a for a <= 1000 to ~1e-15 relative in float64: a = n + r with r = a - n
-// exact, then the degree-9 Taylor polynomial of e^(r ln 2), |r ln 2| <= 0.35.
+// 2^a for a <= 1000 in float64, branch free: a = n + r with r = a - n
+// exact, then the polynomial of exp64n at r ln 2 (|r ln 2| <= 0.35; max
+// relative error 2.3e-10).  Inputs below -1075 are clamped (the result
+// underflows to zero).
 __device__ __forceinline__ double exp2_64(double a) {
-  if (a < -1000.0) return 0.0;
+  a = fmax(a, -1075.0);
   const double n = rint(a);
   const double t = (a - n) * kLn2;
-  double p = 2.7557319223985893e-06;
-  p = fma(p, t, 2.4801587301587302e-05);
-  p = fma(p, t, 1.9841269841269841e-04);
-  p = fma(p, t, 1.3888888888888889e-03);
-  p = fma(p, t, 8.3333333333333333e-03);
-  p = fma(p, t, 4.1666666666666667e-02);
-  p = fma(p, t, 1.6666666666666667e-01);
-  p = fma(p, t, 0.5);
-  p = fma(p, t, 1.0);
+  double p = 1.7378911869613724e-04;
+  p = fma(p, t, 1.3941038928452576e-03);
+  p = fma(p, t, 8.3385787951517860e-03);
+  p = fma(p, t, 4.1666353940642690e-02);
+  p = fma(p, t, 1.6666635163904225e-01);
+  p = fma(p, t, 5.0000000468041280e-01);
+  p = fma(p, t, 1.0000000046987592e+00);
   p = fma(p, t, 1.0);
   return ldexp(p, int(n));
 }
@@ -288,7 +288,9 @@ __device__ __forceinline__ unsigned long long uni64(unsigned long long v) {
 }
 
 // sdf_poly restricted to the faces of a mask that every active lane of the
-// wave shares (wave-uniform loop over its bits, increasing face order).
+// wave shares: a wave-uniform walk over its set bits in increasing face order,
+// two faces per step with both LDS loads issued before either is used (a
+// one-face step exposes the load latency).
 template <int MODE>
 __device__ __forceinline__ void sdf_poly_masked(const double4* __restrict__ pd, int nf, const FaceMask& mk,
                                                 const D3& x, const Temp& T, double& phi, D3& g) {
@@ -302,12 +304,22 @@ __device__ __forceinline__ void sdf_poly_masked(const double4* __restrict__ pd, 
     m = -1e300;
 #pragma unroll
     for (int w = 0; w < 2; ++w) {
+      const double4* pw = pd + 64 * w;
       unsigned long long bits = u[w];
       while (bits) {
-        const int b = __builtin_ctzll(bits);
+        const int b0 = __builtin_ctzll(bits);
         bits &= bits - 1ull;
-        const double4 q = pd[w * 64 + b];
-        m = fmax(m, fma(q.x, x.x, fma(q.y, x.y, fma(q.z, x.z, -q.w))));
+        if (bits) {
+          const int b1 = __builtin_ctzll(bits);
+          bits &= bits - 1ull;
+          const double4 q0 = pw[b0], q1 = pw[b1];
+          const double y0 = fma(q0.x, x.x, fma(q0.y, x.y, fma(q0.z, x.z, -q0.w)));
+          const double y1 = fma(q1.x, x.x, fma(q1.y, x.y, fma(q1.z, x.z, -q1.w)));
+          m = fmax(m, fmax(y0, y1));
+        } else {
+          const double4 q0 = pw[b0];
+          m = fmax(m, fma(q0.x, x.x, fma(q0.y, x.y, fma(q0.z, x.z, -q0.w))));
+        }
       }
     }
   }
@@ -315,19 +327,35 @@ __device__ __forceinline__ void sdf_poly_masked(const double4* __restrict__ pd, 
   double S = 0.0, ax = 0.0, ay = 0.0, az = 0.0;
 #pragma unroll
   for (int w = 0; w < 2; ++w) {
+    const double4* pw = pd + 64 * w;
     unsigned long long bits = u[w];
     while (bits) {
-      const int b = __builtin_ctzll(bits);
+      const int b0 = __builtin_ctzll(bits);
       bits &= bits - 1ull;
-      const double4 q = pd[w * 64 + b];
-      const double a = fma(q.x, x.x, fma(q.y, x.y, fma(q.z, x.z, -q.w))) - m;
-      if (MODE != kSurfGrad) s += ex2f(float(a));
+      // a second face, or the first again with zero weight
+      const bool two = bits != 0ull;
+      const int b1 = two ? __builtin_ctzll(bits) : b0;
+      if (two) bits &= bits - 1ull;
+      const double4 q0 = pw[b0], q1 = pw[b1];
+      const double a0 = fma(q0.x, x.x, fma(q0.y, x.y, fma(q0.z, x.z, -q0.w))) - m;
+      const double a1 = fma(q1.x, x.x, fma(q1.y, x.y, fma(q1.z, x.z, -q1.w))) - m;
+      // sums in face order, as in sdf_poly (the padding face adds exact
+      // zeros), so culled and full evaluations round alike
+      if (MODE != kSurfGrad) {
+        const float e0 = ex2f(float(a0));
+        const float e1 = two ? ex2f(float(a1)) : 0.f;
+        s += e0;
+        s += e1;
+      }
       if (MODE != kValue) {
-        const bool sig = a > -36.0;
-        if (__any(sig)) {
-          const double e = sig ? exp2_64(a) : 0.0;
-          S += e;
-          ax = fma(e, q.x, ax); ay = fma(e, q.y, ay); az = fma(e, q.z, az);
+        const bool sig0 = a0 > -36.0, sig1 = two && a1 > -36.0;
+        if (__any(sig0 || sig1)) {
+          const double e0 = sig0 ? exp2_64(a0) : 0.0;
+          const double e1 = sig1 ? exp2_64(a1) : 0.0;
+          S += e0;
+          ax = fma(e0, q0.x, ax); ay = fma(e0, q0.y, ay); az = fma(e0, q0.z, az);
+          S += e1;
+          ax = fma(e1, q1.x, ax); ay = fma(e1, q1.y, ay); az = fma(e1, q1.z, az);
         }
       }
     }

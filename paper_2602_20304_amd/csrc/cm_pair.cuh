@@ -53,13 +53,10 @@ struct LdsLayout {
 // the kernels' static shared variables.
 constexpr int kLdsBudget = 160 * 1024 - 1024;
 
-// 64-bit words of a per-edge face mask (0: culling off).  Culling is used
-// for polytopes of at most 64 faces: measured on MI355X it speeds up the
-// 60-face hulls of the mixed workload and slows down 124-face hulls, whose
-// masked loops (one face per iteration) lose to the full loops unrolled by
-// two.
+// 64-bit words of a per-edge face mask (0: culling off): one word up to 64
+// faces, two up to 128; larger polytopes are not culled.
 __host__ __device__ inline int mask_words(int maxF) {
-  return maxF <= 64 ? 1 : 0;
+  return maxF <= 64 ? 1 : (maxF <= 128 ? 2 : 0);
 }
 
 // extra: LDS bytes the calling kernel needs beyond the engine.  When the
@@ -69,13 +66,15 @@ __host__ __device__ inline LdsLayout lds_layout(int maxE, int maxF, int block, i
   LdsLayout L;
   int o = 0;
   const int edge_bytes = 2 * 6 * 8 * maxE;
+  // the face masks (cull to pass 2) and the SoftSort records (after pass 2)
+  // are never live together: they share one region
+  const int mask_bytes = 8 * mask_words(maxF) * maxE;
+  const int rec_bytes = int(sizeof(Rec)) * block;
+  const int shared_bytes = ((rec_bytes > 2 * mask_bytes ? rec_bytes : 2 * mask_bytes) + 7) & ~7;
   L.edges_lds = true;
   {
     // size with the edges in LDS (same sequence as below)
-    int t = edge_bytes + 16 * maxE + 16 * block + 8 * 64 + int(sizeof(Rec)) * block + 8 * 9 * CM_MAX_K +
-            64 * maxF + 64;
-    t = (t + 7) & ~7;
-    t += 16 * mask_words(maxF) * maxE;
+    int t = edge_bytes + 16 * maxE + 16 * block + 8 * 64 + shared_bytes + 8 * 9 * CM_MAX_K + 64 * maxF + 64;
     if (((t + 15) & ~15) + extra > kLdsBudget) L.edges_lds = false;
   }
   L.eA = L.eB = -1;
@@ -87,14 +86,14 @@ __host__ __device__ inline LdsLayout lds_layout(int maxE, int maxF, int block, i
   L.col = o; o += 8 * maxE;
   L.red = o; o += 2 * 8 * block;
   L.top = o; o += 8 * 64;
-  L.rec = o; o += int(sizeof(Rec)) * block;
+  L.rec = o;
+  L.mA = o;                   // A's faces near each edge segment of A
+  L.mB = o + mask_bytes;      // B's faces near each edge segment of A
+  o += shared_bytes;
   L.acc = o; o += 8 * 9 * CM_MAX_K;
   L.pA = o; o += 32 * maxF;    // double4 planes (n.xyz, o)
   L.pB = o; o += 32 * maxF;
   L.cnt = o; o += 64;
-  o = (o + 7) & ~7;
-  L.mA = o; o += 8 * mask_words(maxF) * maxE;   // A's faces near each edge segment of A
-  L.mB = o; o += 8 * mask_words(maxF) * maxE;   // B's faces near each edge segment of A
   L.bytes = (o + 15) & ~15;
   return L;
 }
