@@ -73,6 +73,16 @@ __device__ __forceinline__ double rcp64(double x) {
   return fma(r, e, r);
 }
 
+// a * b + c as one v_fma_f64 whose addend c is a wave-uniform constant in
+// scalar registers.  Written with fma(), the compiler picks the tied form
+// v_fmac_f64 (addend = destination) and first copies the coefficient into
+// a vector register: two VALU operations per Horner step instead of one.
+__device__ __forceinline__ double fma3(double a, double b, double c) {
+  double r;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+  return r;
+}
+
 // exp(x) for x <= 700 in float64, branch free: Cody-Waite reduction
 // x = n ln2 + r, |r| <= ln2 / 2, then a degree-7 polynomial of e^r with
 // p(0) = 1 whose other coefficients were fitted by a Remez exchange on the
@@ -84,13 +94,13 @@ __device__ __forceinline__ double exp64n(double x) {
   double r = fma(-n, 6.93147180369123816490e-01, x);   // ln2 high part
   r = fma(-n, 1.90821492927058770002e-10, r);          // ln2 low part
   double p = 1.7378911869613724e-04;
-  p = fma(p, r, 1.3941038928452576e-03);
-  p = fma(p, r, 8.3385787951517860e-03);
-  p = fma(p, r, 4.1666353940642690e-02);
-  p = fma(p, r, 1.6666635163904225e-01);
-  p = fma(p, r, 5.0000000468041280e-01);
-  p = fma(p, r, 1.0000000046987592e+00);
-  p = fma(p, r, 1.0);
+  p = fma3(p, r, 1.3941038928452576e-03);
+  p = fma3(p, r, 8.3385787951517860e-03);
+  p = fma3(p, r, 4.1666353940642690e-02);
+  p = fma3(p, r, 1.6666635163904225e-01);
+  p = fma3(p, r, 5.0000000468041280e-01);
+  p = fma3(p, r, 1.0000000046987592e+00);
+  p = fma3(p, r, 1.0);
   return ldexp(p, int(n));
 }
 
@@ -103,13 +113,13 @@ __device__ __forceinline__ double exp2_64(double a) {
   const double n = rint(a);
   const double t = (a - n) * kLn2;
   double p = 1.7378911869613724e-04;
-  p = fma(p, t, 1.3941038928452576e-03);
-  p = fma(p, t, 8.3385787951517860e-03);
-  p = fma(p, t, 4.1666353940642690e-02);
-  p = fma(p, t, 1.6666635163904225e-01);
-  p = fma(p, t, 5.0000000468041280e-01);
-  p = fma(p, t, 1.0000000046987592e+00);
-  p = fma(p, t, 1.0);
+  p = fma3(p, t, 1.3941038928452576e-03);
+  p = fma3(p, t, 8.3385787951517860e-03);
+  p = fma3(p, t, 4.1666353940642690e-02);
+  p = fma3(p, t, 1.6666635163904225e-01);
+  p = fma3(p, t, 5.0000000468041280e-01);
+  p = fma3(p, t, 1.0000000046987592e+00);
+  p = fma3(p, t, 1.0);
   return ldexp(p, int(n));
 }
 // sigma(u / tau) in float64
@@ -496,13 +506,12 @@ struct Cand {
 // activity indicator): sign via soft sign of the opposing SDF gradient,
 // penetration via the opposing SDF value, clashing via both gradients,
 // nearest neighbour via the row / column LSE of the unsigned distances.
-// q is the edge pair's QP solution (ee_qp).  mA / mB: faces of A / B that
-// can matter on A's edge segment (the queries at e1), shared by every
-// active lane of the wave, or null (all faces).
+// q is the edge pair's QP solution (ee_qp).  m: null (all faces), or the
+// face masks of the four queries, shared by every active lane of the wave:
+// m[0] / m[1] for A / B at e1, m[2] / m[3] for A / B at e2.
 __device__ __forceinline__ void ee_candidates(const D3& a0, const D3& t1, const D3& b0, const D3& t2, const EEQP& q,
                                               double row_lse, double col_lse, const BodyView& A, const BodyView& B,
-                                              double eps_n, const Temp& T, const FaceMask* mA, const FaceMask* mB,
-                                              Cand& c1, Cand& c2) {
+                                              double eps_n, const Temp& T, const FaceMask* m, Cand& c1, Cand& c2) {
   const D3 e1 = d3(a0.x + q.al1 * t1.x, a0.y + q.al1 * t1.y, a0.z + q.al1 * t1.z);
   const D3 e2 = d3(b0.x + q.al2 * t2.x, b0.y + q.al2 * t2.y, b0.z + q.al2 * t2.z);
   const double dsq = dot(q.de, q.de);
@@ -511,10 +520,10 @@ __device__ __forceinline__ void ee_candidates(const D3& a0, const D3& t1, const 
   const D3 nb = d3(q.de.x * in, q.de.y * in, q.de.z * in);
   double phiB1, phiA2, dum;
   D3 gA, gB, dg;
-  sdf_body<kValue, false>(B, e1, T, phiB1, dg, mB);
-  sdf_body<kSurfGrad, true>(A, e1, T, dum, gA, mA);   // e1 lies on an edge of A
-  sdf_body<kValue, true>(A, e2, T, phiA2, dg);
-  sdf_body<kSurfGrad, false>(B, e2, T, dum, gB);            // e2 lies on an edge of B
+  sdf_body<kValue, false>(B, e1, T, phiB1, dg, m ? m + 1 : nullptr);
+  sdf_body<kSurfGrad, true>(A, e1, T, dum, gA, m ? m + 0 : nullptr);    // e1 lies on an edge of A
+  sdf_body<kValue, true>(A, e2, T, phiA2, dg, m ? m + 2 : nullptr);
+  sdf_body<kSurfGrad, false>(B, e2, T, dum, gB, m ? m + 3 : nullptr);   // e2 lies on an edge of B
   const double gam1 = tanh64(dot(gB, nb), T);
   const double gam2 = tanh64(-dot(gA, nb), T);
   const double base = q.log_con + lsig(-dot(gA, gB), T);

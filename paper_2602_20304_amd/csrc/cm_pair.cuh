@@ -45,7 +45,7 @@ struct Rec {
 };
 
 struct LdsLayout {
-  int eA, eB, row, col, red, top, rec, acc, pA, pB, cnt, mA, mB, bytes;
+  int eA, eB, row, col, red, top, rec, acc, pA, pB, cnt, mA, mB, mA2, mB2, bytes;
   bool edges_lds;   // false: the edge arrays live in the workgroup's scratch slot
 };
 
@@ -70,7 +70,7 @@ __host__ __device__ inline LdsLayout lds_layout(int maxE, int maxF, int block, i
   // are never live together: they share one region
   const int mask_bytes = 8 * mask_words(maxF) * maxE;
   const int rec_bytes = int(sizeof(Rec)) * block;
-  const int shared_bytes = ((rec_bytes > 2 * mask_bytes ? rec_bytes : 2 * mask_bytes) + 7) & ~7;
+  const int shared_bytes = ((rec_bytes > 4 * mask_bytes ? rec_bytes : 4 * mask_bytes) + 7) & ~7;
   L.edges_lds = true;
   {
     // size with the edges in LDS (same sequence as below)
@@ -87,8 +87,10 @@ __host__ __device__ inline LdsLayout lds_layout(int maxE, int maxF, int block, i
   L.red = o; o += 2 * 8 * block;
   L.top = o; o += 8 * 64;
   L.rec = o;
-  L.mA = o;                   // A's faces near each edge segment of A
-  L.mB = o + mask_bytes;      // B's faces near each edge segment of A
+  L.mA = o;                      // A's faces near each edge segment of A
+  L.mB = o + mask_bytes;         // B's faces near each edge segment of A
+  L.mA2 = o + 2 * mask_bytes;    // A's faces near each edge segment of B
+  L.mB2 = o + 3 * mask_bytes;    // B's faces near each edge segment of B
   o += shared_bytes;
   L.acc = o; o += 8 * 9 * CM_MAX_K;
   L.pA = o; o += 32 * maxF;    // double4 planes (n.xyz, o)
@@ -118,8 +120,10 @@ struct PairEngine {
   Rec* sRec;
   double* sAcc;   // [9K] unnormalised SoftSort sums (1, p, nu, d, w) per row
   int* sCnt;
-  unsigned long long* sMA;   // [maxE][MW] face masks, see cull()
+  unsigned long long* sMA;   // [maxE][MW] face masks of A's edges, see cull()
   unsigned long long* sMB;
+  unsigned long long* sMA2;  // [maxE][MW] face masks of B's edges
+  unsigned long long* sMB2;
   int MW;
   double* Dbuf;   // [maxE^2] unsigned distance of edge pair (k, l) at k * neB + l
   double* Al1;    // [maxE^2] QP solution al1, al2 and ln con of the same edge pair
@@ -156,6 +160,8 @@ struct PairEngine {
     sCnt = reinterpret_cast<int*>(smem + L.cnt);
     sMA = reinterpret_cast<unsigned long long*>(smem + L.mA);
     sMB = reinterpret_cast<unsigned long long*>(smem + L.mB);
+    sMA2 = reinterpret_cast<unsigned long long*>(smem + L.mA2);
+    sMB2 = reinterpret_cast<unsigned long long*>(smem + L.mB2);
     MW = CULL ? mask_words(maxF_) : 0;
     const long long mm = (long long)maxE_ * maxE_;
     Dbuf = reinterpret_cast<double*>(slot);
@@ -270,23 +276,30 @@ struct PairEngine {
   }
 
   // ------------------------------------------------------------ cull
-  // Per edge segment k of A (extended to the witness range of the smoothed
-  // QP, alpha in [-0.3 tau, 1 + 0.3 tau]): the faces of each polytope whose
-  // plane can come within 38 binary orders (scaled units) of the largest
-  // plane value at some point of the segment.  Plane values are linear
-  // along the segment, so face g is dropped when
+  // Per edge segment of A and of B (extended to the witness range of the
+  // smoothed QP, alpha in [-0.3 tau, 1 + 0.3 tau]): the faces of each
+  // polytope whose plane can come within 38 binary orders (scaled units) of
+  // the largest plane value at some point of the segment.  Plane values are
+  // linear along the segment, so face g is dropped when
   // max(y'_g(p0), y'_g(p1)) < max_f min(y'_f(p0), y'_f(p1)) - 38, which
   // bounds its term in the LSE and in the gradient softmax below 2^-38.
+  // Witness 1 lies on an edge of A, witness 2 on an edge of B.
   __device__ void cull() {
     if (!CULL || MW == 0 || ps.nee == 0) return;
     const double ext = 0.3 * T.tau;
-    for (int k = tid; k < A.ne; k += BLOCK) {
+    const int neA = A.ne;
+    for (int i = tid; i < neA + B.ne; i += BLOCK) {
+      const bool onA = i < neA;
+      const int k = onA ? i : i - neA;
       D3 a0, t1;
-      EA.get(k, a0, t1);
+      if (onA) EA.get(k, a0, t1);
+      else EB.get(k, a0, t1);
       const D3 p0 = d3(a0.x - ext * t1.x, a0.y - ext * t1.y, a0.z - ext * t1.z);
       const D3 p1 = d3(a0.x + (1.0 + ext) * t1.x, a0.y + (1.0 + ext) * t1.y, a0.z + (1.0 + ext) * t1.z);
-      seg_mask(A, false, p0, p1, sMA + k * MW);
-      seg_mask(B, true, p0, p1, sMB + k * MW);
+      unsigned long long* oA = onA ? sMA : sMA2;
+      unsigned long long* oB = onA ? sMB : sMB2;
+      seg_mask(A, false, p0, p1, oA + k * MW);
+      seg_mask(B, true, p0, p1, oB + k * MW);
     }
     __syncthreads();
   }
@@ -331,46 +344,50 @@ struct PairEngine {
     if (i < A.nv) vs_candidate<false>(vertex<true>(*GA, i, A), B, -1.0, T, c);
     else vs_candidate<true>(vertex<false>(*GB, i - A.nv, B), A, 1.0, T, c);
   }
-  // Face masks of the block of 64 edge pairs holding edge pair i = k neB + l:
-  // the union of the per-edge masks over the rows the block spans (usually
-  // one or two).
-  __device__ __forceinline__ void block_masks(int i, FaceMask& mA, FaceMask& mB) const {
-    mA.w[0] = mA.w[1] = mB.w[0] = mB.w[1] = 0ull;
-    mA.n = mB.n = MW;
-    if (!CULL || MW == 0) return;   // culling off: no mask storage
-    const int neB = B.ne;
-    const int b0 = i & ~63;
-    const int k0 = b0 / neB, k1 = min(A.ne - 1, (b0 + 63) / neB);
-    for (int k = k0; k <= k1; ++k) {
-      mA.w[0] |= sMA[k * MW];
-      mB.w[0] |= sMB[k * MW];
-      if (MW > 1) {
-        mA.w[1] |= sMA[k * MW + 1];
-        mB.w[1] |= sMB[k * MW + 1];
-      }
+  // Face masks of an 8 x 8 tile of pass 2 (edges k0..k0+7 of A by
+  // l0..l0+7 of B): the union over the tile's edges of A of their masks for
+  // the queries at e1, and over its edges of B for the queries at e2, in
+  // the wave's LDS slot (m as in ee_candidates).  The slots sit in sRed past
+  // the words the top-K merge writes, since a wave may start that merge
+  // while others still run pass 2.  Wave-uniform (k0, l0).
+  __device__ __forceinline__ const FaceMask* tile_masks(int k0, int l0) const {
+    FaceMask* slot = reinterpret_cast<FaceMask*>(sRed + 2 * NW) + 4 * wave;
+    const int j = lane & 7, k = k0 + j, l = l0 + j;
+    unsigned long long v[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = 0ull;
+    if (MW > 0 && k < A.ne) {
+      v[0] = sMA[k * MW]; v[2] = sMB[k * MW];
+      if (MW > 1) { v[1] = sMA[k * MW + 1]; v[3] = sMB[k * MW + 1]; }
     }
+    if (MW > 0 && l < B.ne) {
+      v[4] = sMA2[l * MW]; v[6] = sMB2[l * MW];
+      if (MW > 1) { v[5] = sMA2[l * MW + 1]; v[7] = sMB2[l * MW + 1]; }
+    }
+#pragma unroll
+    for (int o = 4; o > 0; o >>= 1) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v[i] |= __shfl_xor(v[i], o);
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) { slot[q].w[0] = v[2 * q]; slot[q].w[1] = v[2 * q + 1]; slot[q].n = MW; }
+    }
+    return slot;
   }
 
   // both candidates of edge pair (k, l) from the QP solution stored by the
-  // distance pass.  CULLED: every active lane of the wave evaluates an edge
-  // pair of the same block of 64 (the candidate pass), so the block's face
-  // masks apply wave-wide; otherwise (recomputes of filtered candidates)
-  // every face is visited, which differs from the culled value by less
-  // than 2^-38 relative.
-  template <bool CULLED>
-  __device__ __forceinline__ void ee(int k, int l, Cand& c1, Cand& c2) const {
+  // distance pass.  m: the face masks of a pass-2 tile, shared by every
+  // active lane of the wave, or null (every face: recomputes of filtered
+  // candidates, whose lanes hold unrelated edge pairs; the two differ by
+  // less than 2^-38 relative).
+  __device__ __forceinline__ void ee(int k, int l, Cand& c1, Cand& c2, const FaceMask* m = nullptr) const {
     D3 a0, t1, b0, t2;
     EA.get(k, a0, t1);
     EB.get(l, b0, t2);
     const int i = k * B.ne + l;
     const EEQP q = ee_from_alpha(a0, t1, b0, t2, Al1[i], Al2[i], Lcon[i]);
-    if (CULLED && CULL) {
-      FaceMask mA, mB;
-      block_masks(i, mA, mB);
-      ee_candidates(a0, t1, b0, t2, q, sRow[k], sCol[l], A, B, eps_n, T, &mA, &mB, c1, c2);
-    } else {
-      ee_candidates(a0, t1, b0, t2, q, sRow[k], sCol[l], A, B, eps_n, T, nullptr, nullptr, c1, c2);
-    }
+    ee_candidates(a0, t1, b0, t2, q, sRow[k], sCol[l], A, B, eps_n, T, m, c1, c2);
   }
   // candidate idx in the fixed order: A's vertices, B's vertices, E-E (k, l)
   // row-major with witness 1 before witness 2
@@ -382,7 +399,7 @@ struct PairEngine {
       const int ee_i = e >> 1;
       const int k = ee_i / B.ne, l = ee_i - k * B.ne;
       Cand c1, c2;
-      ee<false>(k, l, c1, c2);
+      ee(k, l, c1, c2);
       c = (e & 1) ? c2 : c1;
     }
   }
@@ -458,13 +475,35 @@ struct PairEngine {
       }
     }
     __syncthreads();
-    // E-E pass 2: candidates, scores, top-K
-    {
+    // E-E pass 2: candidates, scores, top-K.  The forward kernel gives each
+    // wave 8 x 8 tiles of edge pairs (lane = 8 kk + ll), whose witness
+    // queries share the tile's face masks (polytope edges are stored in
+    // spatially compact runs of 8); the adjoint's recompute goes row-major
+    // over the block.  One inlined form of the candidate code per kernel
+    // keeps register pressure down.
+    if (CULL) {
+      const int ntl = (neB + 7) >> 3, ntiles = ((neA + 7) >> 3) * ntl;
+      const int kk = lane >> 3, ll = lane & 7;
+      for (int t = wave; t < ntiles; t += NW) {
+        const int k0 = (t / ntl) * 8, l0 = (t - (t / ntl) * ntl) * 8;
+        const FaceMask* m = tile_masks(k0, l0);
+        const int k = k0 + kk, l = l0 + ll;
+        if (k < neA && l < neB) {
+          const int idx = k * neB + l;
+          Cand c1, c2;
+          ee(k, l, c1, c2, m);
+          Sbuf[nvs + 2 * idx] = float(c1.s);
+          Sbuf[nvs + 2 * idx + 1] = float(c2.s);
+          tk_insert<KMAX>(tk, c1.s);
+          tk_insert<KMAX>(tk, c2.s);
+        }
+      }
+    } else {
       int k = tid / neB, l = tid - (tid / neB) * neB;
       const int sk = BLOCK / neB, sl = BLOCK - sk * neB;
       for (int idx = tid; idx < nee; idx += BLOCK) {
         Cand c1, c2;
-        ee<true>(k, l, c1, c2);
+        ee(k, l, c1, c2);
         Sbuf[nvs + 2 * idx] = float(c1.s);
         Sbuf[nvs + 2 * idx + 1] = float(c2.s);
         tk_insert<KMAX>(tk, c1.s);

@@ -163,6 +163,54 @@ bool convex_hull(const float* pts, int64_t n, std::vector<int32_t>* vid, std::ve
   return true;
 }
 
+// Reorder a polytope's edges so that each run of 8 consecutive edges is
+// spatially compact: recursive median splits of the edge midpoints along the
+// axis of largest extent, with the first part of every split a multiple of 8.
+// The pair kernels give one wave an 8 x 8 tile of (edge of A, edge of B)
+// pairs and skip, for the whole wave, the faces that are far from all 8
+// edges of each side; compact runs keep those unions small.
+static void order_edges_spatially(const std::vector<double>& vd, std::vector<int32_t>* edges) {
+  const int ne = int(edges->size() / 2);
+  if (ne <= 8) return;
+  std::vector<double> mid(3 * size_t(ne));
+  for (int e = 0; e < ne; ++e)
+    for (int k = 0; k < 3; ++k)
+      mid[3 * e + k] = 0.5 * (vd[3 * (*edges)[2 * e] + k] + vd[3 * (*edges)[2 * e + 1] + k]);
+  std::vector<int> ids(ne);
+  for (int e = 0; e < ne; ++e) ids[e] = e;
+  std::vector<int> out;
+  out.reserve(ne);
+  std::vector<std::pair<int, int>> stack = {{0, ne}};   // [lo, hi) ranges of ids, processed in order
+  while (!stack.empty()) {
+    const auto [lo, hi] = stack.back();
+    stack.pop_back();
+    if (hi - lo <= 8) {
+      out.insert(out.end(), ids.begin() + lo, ids.begin() + hi);
+      continue;
+    }
+    double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
+    for (int i = lo; i < hi; ++i)
+      for (int k = 0; k < 3; ++k) {
+        mn[k] = std::min(mn[k], mid[3 * ids[i] + k]);
+        mx[k] = std::max(mx[k], mid[3 * ids[i] + k]);
+      }
+    int ax = 0;
+    for (int k = 1; k < 3; ++k) if (mx[k] - mn[k] > mx[ax] - mn[ax]) ax = k;
+    std::stable_sort(ids.begin() + lo, ids.begin() + hi, [&](int a, int b) {
+      return mid[3 * a + ax] < mid[3 * b + ax];
+    });
+    const int half = std::min(hi - lo, ((hi - lo + 1) / 2 + 7) / 8 * 8);
+    stack.push_back({lo + half, hi});   // second part after the first
+    stack.push_back({lo, lo + half});
+  }
+  std::vector<int32_t> re(edges->size());
+  for (int i = 0; i < ne; ++i) {
+    re[2 * i] = (*edges)[2 * out[i]];
+    re[2 * i + 1] = (*edges)[2 * out[i] + 1];
+  }
+  edges->swap(re);
+}
+
 bool build_mesh(int32_t type, const float* params, const float* pts, int64_t n_pts, HostMesh* out,
                 std::string* err) {
   HostMesh& m = *out;
@@ -232,6 +280,7 @@ bool build_mesh(int32_t type, const float* params, const float* pts, int64_t n_p
         m.v.push_back(pts[3 * i + k]);
         m.vd.push_back(double(pts[3 * i + k]));
       }
+    order_edges_spatially(m.vd, &edges);
     m.e = edges;
     m.f = tris;
     const size_t nf = tris.size() / 3;
