@@ -63,7 +63,7 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
   char* smem = reinterpret_cast<char*>(smem4);
   __shared__ PairShared ps;
   const int extra = bwd_extra_bytes(maxV, maxE, maxF, BLOCK);
-  PairEngine<BLOCK, KMAX, false> P(ps, smem, tb, bt, prm, scratch + (long long)blockIdx.x * scratch_stride, maxV, maxE,
+  PairEngine<BLOCK, KMAX, true> P(ps, smem, tb, bt, prm, scratch + (long long)blockIdx.x * scratch_stride, maxV, maxE,
                                    maxF, extra);
   const BwdLds L = bwd_layout(lds_layout(maxE, maxF, BLOCK, extra).bytes, maxV, maxE, maxF, BLOCK);
   float* vA3 = reinterpret_cast<float*>(smem + L.vA);

@@ -100,9 +100,10 @@ __host__ __device__ inline LdsLayout lds_layout(int maxE, int maxF, int block, i
   return L;
 }
 
-// CULL: the witness queries on A's edges use the per-segment face masks
-// (forward kernel); without it every face is visited (adjoint kernel, which
-// recomputes its own forward and stays self-consistent).
+// CULL: the candidate pass visits edge pairs in 8 x 8 tiles whose witness
+// queries use the per-segment face masks (the forward kernel and the
+// adjoint's recompute of it, so both take the same path); without it the
+// edge pairs go row-major and every face is visited.
 template <int BLOCK, int KMAX, bool CULL>
 struct PairEngine {
   static constexpr int NW = BLOCK / 64;
