@@ -6,8 +6,8 @@
 // shared engine (no E x E state was stored by the forward), then:
 //   A1  SoftSort adjoint, part 1: adjoints of the K top scores s_[k] and the
 //       candidate j_k that attains each of them
-//   A2  per-candidate adjoint for every candidate within 40 tau of s_[K]
-//       (all others have SoftSort weight below exp(-40)): score / weight /
+//   A2  per-candidate adjoint for every candidate within 18 tau of s_[K]
+//       (all others have SoftSort weight below exp(-18)): score / weight /
 //       field adjoints -> indicators -> SDF queries -> witness QP -> edges
 //   N   nearest-neighbour adjoint: row / column LSE adjoints flow back into
 //       every unsigned distance D_kl of the touched rows and columns

@@ -17,10 +17,11 @@
 
 namespace cm {
 
-// A SoftSort weight exp(-40) ~ 4e-18 is below float32 resolution of any row
-// sum (>= 1), so candidates scoring more than 40 tau below the K-th largest
-// score cannot change a manifold output.
-constexpr double kFilterTaus = 40.0;
+// Candidates scoring more than 30 tau below the K-th largest score are left
+// out of the SoftSort sums: each has weight below exp(-30) ~ 9.4e-14 against
+// a row sum >= 1, so even 10^5 of them move a row's weighted mean by less
+// than 1e-8 of the spread of its fields, far below float32 resolution.
+constexpr double kFilterTaus = 30.0;
 // The adjoint skips candidates whose largest SoftSort weight is below
 // exp(-18) ~ 1.5e-8 relative: their share of any gradient is far below the
 // float32 outputs' and the gradient tolerance's resolution.

@@ -10,7 +10,7 @@
 //            indicators, Sec. IV-D); E-E candidate pass (witness QP, SDF queries,
 //            sign, penetration, clashing, activity, score); per-lane top-K
 //   topk     block merge of the per-lane top-K score lists (with multiplicity)
-//   softsort SoftSort rows over the candidates within 40 tau of s_[K]
+//   softsort SoftSort rows over the candidates within 30 tau of s_[K]
 #pragma once
 #include "cm_device.cuh"
 #include "cm_kernels.h"
