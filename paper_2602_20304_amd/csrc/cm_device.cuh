@@ -507,12 +507,13 @@ struct Cand {
 // activity indicator): sign via soft sign of the opposing SDF gradient,
 // penetration via the opposing SDF value, clashing via both gradients,
 // nearest neighbour via the row / column LSE of the unsigned distances.
-// q is the edge pair's QP solution (ee_qp).  m: null (all faces), or the
-// face masks of the four queries, shared by every active lane of the wave:
-// m[0] / m[1] for A / B at e1, m[2] / m[3] for A / B at e2.
+// q is the edge pair's QP solution (ee_qp).  m1 / m2: null (all faces), or
+// the face masks (A's faces, B's faces) for the queries at e1 / e2, shared by
+// every active lane of the wave.
 __device__ __forceinline__ void ee_candidates(const D3& a0, const D3& t1, const D3& b0, const D3& t2, const EEQP& q,
                                               double row_lse, double col_lse, const BodyView& A, const BodyView& B,
-                                              double eps_n, const Temp& T, const FaceMask* m, Cand& c1, Cand& c2) {
+                                              double eps_n, const Temp& T, const FaceMask* m1, const FaceMask* m2,
+                                              Cand& c1, Cand& c2) {
   const D3 e1 = d3(a0.x + q.al1 * t1.x, a0.y + q.al1 * t1.y, a0.z + q.al1 * t1.z);
   const D3 e2 = d3(b0.x + q.al2 * t2.x, b0.y + q.al2 * t2.y, b0.z + q.al2 * t2.z);
   const double dsq = dot(q.de, q.de);
@@ -521,10 +522,10 @@ __device__ __forceinline__ void ee_candidates(const D3& a0, const D3& t1, const 
   const D3 nb = d3(q.de.x * in, q.de.y * in, q.de.z * in);
   double phiB1, phiA2, dum;
   D3 gA, gB, dg;
-  sdf_body<kValue, false>(B, e1, T, phiB1, dg, m ? m + 1 : nullptr);
-  sdf_body<kSurfGrad, true>(A, e1, T, dum, gA, m ? m + 0 : nullptr);    // e1 lies on an edge of A
-  sdf_body<kValue, true>(A, e2, T, phiA2, dg, m ? m + 2 : nullptr);
-  sdf_body<kSurfGrad, false>(B, e2, T, dum, gB, m ? m + 3 : nullptr);   // e2 lies on an edge of B
+  sdf_body<kValue, false>(B, e1, T, phiB1, dg, m1 ? m1 + 1 : nullptr);
+  sdf_body<kSurfGrad, true>(A, e1, T, dum, gA, m1);                      // e1 lies on an edge of A
+  sdf_body<kValue, true>(A, e2, T, phiA2, dg, m2);
+  sdf_body<kSurfGrad, false>(B, e2, T, dum, gB, m2 ? m2 + 1 : nullptr);   // e2 lies on an edge of B
   const double gam1 = tanh64(dot(gB, nb), T);
   const double gam2 = tanh64(-dot(gA, nb), T);
   const double base = q.log_con + lsig(-dot(gA, gB), T);

@@ -45,7 +45,7 @@ struct Rec {
 };
 
 struct LdsLayout {
-  int eA, eB, row, col, red, top, rec, acc, pA, pB, cnt, mA, mB, mA2, mB2, bytes;
+  int eA, eB, row, col, red, top, rec, acc, pA, pB, cnt, mA, mB, mA2, mB2, g1, g2, bytes;
   bool edges_lds;   // false: the edge arrays live in the workgroup's scratch slot
 };
 
@@ -69,8 +69,12 @@ __host__ __device__ inline LdsLayout lds_layout(int maxE, int maxF, int block, i
   // the face masks (cull to pass 2) and the SoftSort records (after pass 2)
   // are never live together: they share one region
   const int mask_bytes = 8 * mask_words(maxF) * maxE;
+  // masks of the groups of 8 consecutive edges: per group of A's and of B's
+  // edges, the union over the group (faces of A, faces of B)
+  const int group_bytes = mask_words(maxF) > 0 ? 2 * 2 * ((maxE + 7) / 8) * int(sizeof(FaceMask)) : 0;
   const int rec_bytes = int(sizeof(Rec)) * block;
-  const int shared_bytes = ((rec_bytes > 4 * mask_bytes ? rec_bytes : 4 * mask_bytes) + 7) & ~7;
+  const int mask_total = 4 * mask_bytes + group_bytes;
+  const int shared_bytes = ((rec_bytes > mask_total ? rec_bytes : mask_total) + 7) & ~7;
   L.edges_lds = true;
   {
     // size with the edges in LDS (same sequence as below)
@@ -91,6 +95,8 @@ __host__ __device__ inline LdsLayout lds_layout(int maxE, int maxF, int block, i
   L.mB = o + mask_bytes;         // B's faces near each edge segment of A
   L.mA2 = o + 2 * mask_bytes;    // A's faces near each edge segment of B
   L.mB2 = o + 3 * mask_bytes;    // B's faces near each edge segment of B
+  L.g1 = o + 4 * mask_bytes;     // [group of A's edges][A's faces, B's faces]
+  L.g2 = L.g1 + group_bytes / 2; // [group of B's edges][A's faces, B's faces]
   o += shared_bytes;
   L.acc = o; o += 8 * 9 * CM_MAX_K;
   L.pA = o; o += 32 * maxF;    // double4 planes (n.xyz, o)
@@ -125,6 +131,8 @@ struct PairEngine {
   unsigned long long* sMB;
   unsigned long long* sMA2;  // [maxE][MW] face masks of B's edges
   unsigned long long* sMB2;
+  FaceMask* sG1;             // [ceil(maxE / 8)][2] unions over groups of 8 edges of A
+  FaceMask* sG2;             // [ceil(maxE / 8)][2] unions over groups of 8 edges of B
   int MW;
   double* Dbuf;   // [maxE^2] unsigned distance of edge pair (k, l) at k * neB + l
   double* Al1;    // [maxE^2] QP solution al1, al2 and ln con of the same edge pair
@@ -163,6 +171,8 @@ struct PairEngine {
     sMB = reinterpret_cast<unsigned long long*>(smem + L.mB);
     sMA2 = reinterpret_cast<unsigned long long*>(smem + L.mA2);
     sMB2 = reinterpret_cast<unsigned long long*>(smem + L.mB2);
+    sG1 = reinterpret_cast<FaceMask*>(smem + L.g1);
+    sG2 = reinterpret_cast<FaceMask*>(smem + L.g2);
     MW = CULL ? mask_words(maxF_) : 0;
     const long long mm = (long long)maxE_ * maxE_;
     Dbuf = reinterpret_cast<double*>(slot);
@@ -303,6 +313,25 @@ struct PairEngine {
       seg_mask(B, true, p0, p1, oB + k * MW);
     }
     __syncthreads();
+    // unions over the groups of 8 consecutive edges (the rows and columns of
+    // the candidate pass's tiles)
+    const int ngA = (neA + 7) >> 3, ngB = (B.ne + 7) >> 3;
+    for (int i = tid; i < ngA + ngB; i += BLOCK) {
+      const bool onA = i < ngA;
+      const int g = onA ? i : i - ngA;
+      const int e0 = 8 * g, e1 = min(onA ? neA : B.ne, e0 + 8);
+      const unsigned long long* iA = onA ? sMA : sMA2;
+      const unsigned long long* iB = onA ? sMB : sMB2;
+      unsigned long long a0 = 0ull, a1 = 0ull, b0 = 0ull, b1 = 0ull;
+      for (int e = e0; e < e1; ++e) {
+        a0 |= iA[e * MW]; b0 |= iB[e * MW];
+        if (MW > 1) { a1 |= iA[e * MW + 1]; b1 |= iB[e * MW + 1]; }
+      }
+      FaceMask* o = (onA ? sG1 : sG2) + 2 * g;
+      o[0].w[0] = a0; o[0].w[1] = a1; o[0].n = MW;
+      o[1].w[0] = b0; o[1].w[1] = b1; o[1].n = MW;
+    }
+    __syncthreads();
   }
   __device__ __forceinline__ void seg_mask(const BodyView& V, bool moved, const D3& p0w, const D3& p1w,
                                            unsigned long long* out) const {
@@ -345,50 +374,20 @@ struct PairEngine {
     if (i < A.nv) vs_candidate<false>(vertex<true>(*GA, i, A), B, -1.0, T, c);
     else vs_candidate<true>(vertex<false>(*GB, i - A.nv, B), A, 1.0, T, c);
   }
-  // Face masks of an 8 x 8 tile of pass 2 (edges k0..k0+7 of A by
-  // l0..l0+7 of B): the union over the tile's edges of A of their masks for
-  // the queries at e1, and over its edges of B for the queries at e2, in
-  // the wave's LDS slot (m as in ee_candidates).  The slots sit in sRed past
-  // the words the top-K merge writes, since a wave may start that merge
-  // while others still run pass 2.  Wave-uniform (k0, l0).
-  __device__ __forceinline__ const FaceMask* tile_masks(int k0, int l0) const {
-    FaceMask* slot = reinterpret_cast<FaceMask*>(sRed + 2 * NW) + 4 * wave;
-    const int j = lane & 7, k = k0 + j, l = l0 + j;
-    unsigned long long v[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) v[i] = 0ull;
-    if (MW > 0 && k < A.ne) {
-      v[0] = sMA[k * MW]; v[2] = sMB[k * MW];
-      if (MW > 1) { v[1] = sMA[k * MW + 1]; v[3] = sMB[k * MW + 1]; }
-    }
-    if (MW > 0 && l < B.ne) {
-      v[4] = sMA2[l * MW]; v[6] = sMB2[l * MW];
-      if (MW > 1) { v[5] = sMA2[l * MW + 1]; v[7] = sMB2[l * MW + 1]; }
-    }
-#pragma unroll
-    for (int o = 4; o > 0; o >>= 1) {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) v[i] |= __shfl_xor(v[i], o);
-    }
-    if (lane == 0) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) { slot[q].w[0] = v[2 * q]; slot[q].w[1] = v[2 * q + 1]; slot[q].n = MW; }
-    }
-    return slot;
-  }
-
   // both candidates of edge pair (k, l) from the QP solution stored by the
-  // distance pass.  m: the face masks of a pass-2 tile, shared by every
-  // active lane of the wave, or null (every face: recomputes of filtered
-  // candidates, whose lanes hold unrelated edge pairs; the two differ by
-  // less than 2^-38 relative).
-  __device__ __forceinline__ void ee(int k, int l, Cand& c1, Cand& c2, const FaceMask* m = nullptr) const {
+  // distance pass.  m1 / m2: the face masks of the groups holding edge k of
+  // A / edge l of B, shared by every active lane of the wave (a pass-2
+  // tile), or null (every face: recomputes of filtered candidates, whose
+  // lanes hold unrelated edge pairs; the two differ by less than 2^-38
+  // relative).
+  __device__ __forceinline__ void ee(int k, int l, Cand& c1, Cand& c2, const FaceMask* m1 = nullptr,
+                                     const FaceMask* m2 = nullptr) const {
     D3 a0, t1, b0, t2;
     EA.get(k, a0, t1);
     EB.get(l, b0, t2);
     const int i = k * B.ne + l;
     const EEQP q = ee_from_alpha(a0, t1, b0, t2, Al1[i], Al2[i], Lcon[i]);
-    ee_candidates(a0, t1, b0, t2, q, sRow[k], sCol[l], A, B, eps_n, T, m, c1, c2);
+    ee_candidates(a0, t1, b0, t2, q, sRow[k], sCol[l], A, B, eps_n, T, m1, m2, c1, c2);
   }
   // candidate idx in the fixed order: A's vertices, B's vertices, E-E (k, l)
   // row-major with witness 1 before witness 2
@@ -487,12 +486,13 @@ struct PairEngine {
       const int kk = lane >> 3, ll = lane & 7;
       for (int t = wave; t < ntiles; t += NW) {
         const int k0 = (t / ntl) * 8, l0 = (t - (t / ntl) * ntl) * 8;
-        const FaceMask* m = tile_masks(k0, l0);
+        const FaceMask* m1 = MW > 0 ? sG1 + 2 * (k0 >> 3) : nullptr;
+        const FaceMask* m2 = MW > 0 ? sG2 + 2 * (l0 >> 3) : nullptr;
         const int k = k0 + kk, l = l0 + ll;
         if (k < neA && l < neB) {
           const int idx = k * neB + l;
           Cand c1, c2;
-          ee(k, l, c1, c2, m);
+          ee(k, l, c1, c2, m1, m2);
           Sbuf[nvs + 2 * idx] = float(c1.s);
           Sbuf[nvs + 2 * idx + 1] = float(c2.s);
           tk_insert<KMAX>(tk, c1.s);
