@@ -38,6 +38,13 @@ Readings where the paper is silent or garbled (each is listed in the design doc):
       (poles + 3 latitude rings of 8) / 56 edges; capsule = 34 vertices / 72
       edges; all vertices on the exact surface
   R10 rounded box: outer half-extents h, rounding radius rho (exact SDF)
+  R17 soft top-K pre-selection (Sec. IV-A overview, Supp. "picking the top-K
+      numbers" and "safeguarding"): vertex metric = SDF of the other body at
+      the vertex, edge metric = mean of its two corners' metrics; the same K_V
+      and K_E for both bodies, clamped to each body's counts; the selection
+      SoftSort uses tau and ranks -metric (deepest first); the optional
+      safeguard multiplies both witnesses' activities by
+      sigma(-phi_A(e1)/tau) sigma(-phi_B(e2)/tau)
   R11 V-S output normal grad(phi)/sqrt(tau + |grad(phi)|^2); sign and clash
       tests use the raw SDF gradient
   R12 broadphase (not in the paper): keep a pair iff its bounding spheres
@@ -521,15 +528,50 @@ def nn_log_indicators(dbar, tau):
     return torch.log_softmax(-dbar / tau, dim=1), torch.log_softmax(-dbar / tau, dim=0)
 
 
+def soft_topk(x, K: int, tau):
+    """SoftSort soft top-K (Sec. III): Gamma [K, D] with rows
+    softmax_i(-|x_[k] - x_i| / tau), x_[k] the k-th largest entry of x."""
+    top = torch.topk(x, K, sorted=True).values
+    return torch.softmax(-torch.abs(top[:, None] - x[None, :]) / tau, dim=1)
+
+
+def preselect(GA, RA, tA, GB, RB, tB, tau, KV: int, KE: int, planesA=None, planesB=None):
+    """Soft top-K pre-selection of vertices and edges (Sec. IV-A overview;
+    Supp. on picking the top-K numbers and on safeguarding; reading R17).
+
+    Every vertex gets the SDF of the other body at it as its penetration
+    metric, every edge the mean of its corners' metrics; the K_V deepest
+    vertices and K_E deepest edges of each body are selected by SoftSort
+    rows over -metric, and the selected points are the Gamma-weighted
+    averages of the vertex positions (of the edge endpoints).  Returns world
+    arrays: soft vertices of A [KV_A, 3] and B, soft edge endpoints of A
+    (a0 [KE_A, 3], a1) and of B (b0, b1).
+    """
+    vA = GA.vertices() @ RA.T + tA
+    vB = GB.vertices() @ RB.T + tB
+    mA, _ = sdf_world(GB, RB, tB, vA, tau, planesB)
+    mB, _ = sdf_world(GA, RA, tA, vB, tau, planesA)
+    eA, eB = GA.edges, GB.edges
+    meA = 0.5 * (mA[eA[:, 0]] + mA[eA[:, 1]])
+    meB = 0.5 * (mB[eB[:, 0]] + mB[eB[:, 1]])
+    GvA = soft_topk(-mA, min(KV, vA.shape[0]), tau)
+    GvB = soft_topk(-mB, min(KV, vB.shape[0]), tau)
+    GeA = soft_topk(-meA, min(KE, eA.shape[0]), tau)
+    GeB = soft_topk(-meB, min(KE, eB.shape[0]), tau)
+    return (GvA @ vA, GvB @ vB, GeA @ vA[eA[:, 0]], GeA @ vA[eA[:, 1]], GeB @ vB[eB[:, 0]], GeB @ vB[eB[:, 1]])
+
+
 def pair_candidates(GA: OGeom, RA, tA, GB: OGeom, RB, tB, tau, lam=LAMBDA_DEFAULT, eps_n=None, no_ee=False,
-                    one_sided_vs=False):
+                    one_sided_vs=False, presel=None, safeguard=False):
     """All contact candidates of one body pair (A, B) in world coordinates.
 
     Returns dict of p [C,3], nu [C,3] (pair convention, A -> B), d [C],
     logw [C] with the candidate order: A's vertices, B's vertices, then E-E
     pairs (k, l) row-major with witness 1 before witness 2.  no_ee drops the
     E-E candidates and one_sided_vs B's vertices (the paper's simplifications,
-    supplementary material).
+    supplementary material).  presel = (K_V, K_E): the candidates are built
+    from the soft pre-selected vertices and edges instead (preselect), and
+    safeguard scales the E-E activities by the inside indicators (R17).
     """
     if eps_n is None:
         eps_n = tau * tau
@@ -537,6 +579,12 @@ def pair_candidates(GA: OGeom, RA, tA, GB: OGeom, RB, tB, tau, lam=LAMBDA_DEFAUL
     planesB = GB.planes() if GB.kind == POLYTOPE else None
     vA = GA.vertices() @ RA.T + tA
     vB = GB.vertices() @ RB.T + tB
+    eA, eB = GA.edges, GB.edges
+    a0, a1 = vA[eA[:, 0]][:, None, :], vA[eA[:, 1]][:, None, :]
+    b0, b1 = vB[eB[:, 0]][None, :, :], vB[eB[:, 1]][None, :, :]
+    if presel is not None:
+        vA, vB, sa0, sa1, sb0, sb1 = preselect(GA, RA, tA, GB, RB, tB, tau, presel[0], presel[1], planesA, planesB)
+        a0, a1, b0, b1 = sa0[:, None, :], sa1[:, None, :], sb0[None, :, :], sb1[None, :, :]
 
     # ---- vertex-SDF contacts (Sec. IV-C; normals R11; weights R6)
     phiB_v, gB_v = sdf_world(GB, RB, tB, vA, tau, planesB)
@@ -547,9 +595,6 @@ def pair_candidates(GA: OGeom, RA, tA, GB: OGeom, RB, tB, tau, lam=LAMBDA_DEFAUL
     vs_logw = log_sigmoid(-vs_d / tau)
 
     # ---- edge-edge contacts over all |E_A| x |E_B| edge pairs (Sec. IV-D)
-    eA, eB = GA.edges, GB.edges
-    a0, a1 = vA[eA[:, 0]][:, None, :], vA[eA[:, 1]][:, None, :]
-    b0, b1 = vB[eB[:, 0]][None, :, :], vB[eB[:, 1]][None, :, :]
     qp = ee_qp(a0, a1, b0, b1, tau, lam)
     e1, e2, dbar, nbar = ee_witness(a0, a1, b0, b1, qp["al1"], qp["al2"], eps_n)
 
@@ -571,6 +616,13 @@ def pair_candidates(GA: OGeom, RA, tA, GB: OGeom, RB, tB, tau, lam=LAMBDA_DEFAUL
     # activity indicator Gamma_b = con * pen_b * nn_b * cl, in the log domain
     logG1 = qp["log_con"] + log_pen1 + log_nn1 + log_cl
     logG2 = qp["log_con"] + log_pen2 + log_nn2 + log_cl
+    if safeguard:
+        # both averaged edges must lie inside their own bodies (R17)
+        phiA_e1, _ = sdf_world(GA, RA, tA, e1, tau, planesA)
+        phiB_e2, _ = sdf_world(GB, RB, tB, e2, tau, planesB)
+        log_sg = log_sigmoid(-phiA_e1 / tau) + log_sigmoid(-phiB_e2 / tau)
+        logG1 = logG1 + log_sg
+        logG2 = logG2 + log_sg
 
     ee_p = torch.stack([e1, e2], dim=2).reshape(-1, 3)
     ee_nu = torch.stack([-n1, n2], dim=2).reshape(-1, 3)   # pair convention (R8)
@@ -615,11 +667,12 @@ def manifold(c, tau, K: int):
 
 
 def collide_pair(GA, poseA, GB, poseB, tau, K, lam=LAMBDA_DEFAULT, eps_n=None, xiA=None, xiB=None,
-                 exact_exp=False, no_ee=False, one_sided_vs=False):
+                 exact_exp=False, no_ee=False, one_sided_vs=False, presel=None, safeguard=False):
     """Contact manifold g_{A,B} of one pair (Sec. IV-A): K x (p, nu, d, w)."""
     RA, tA = pose_Rt(poseA, xiA, exact_exp)
     RB, tB = pose_Rt(poseB, xiB, exact_exp)
-    c = pair_candidates(GA, RA, tA, GB, RB, tB, tau, lam, eps_n, no_ee=no_ee, one_sided_vs=one_sided_vs)
+    c = pair_candidates(GA, RA, tA, GB, RB, tB, tau, lam, eps_n, no_ee=no_ee, one_sided_vs=one_sided_vs,
+                        presel=presel, safeguard=safeguard)
     return manifold(c, tau, K)
 
 
@@ -694,7 +747,7 @@ class GeomCache:
 
 
 def collide_batch(batch, pair_list=None, lam=LAMBDA_DEFAULT, eps_n=None, margin=None, cache=None, no_ee=False,
-                  one_sided_vs=False):
+                  one_sided_vs=False, presel=None, safeguard=False):
     """Forward manifold for the kept pairs of a batch (or a given pair subset).
 
     Returns (pairs [2,n], offsets [S+1], outputs dict of numpy float64 arrays
@@ -712,7 +765,7 @@ def collide_batch(batch, pair_list=None, lam=LAMBDA_DEFAULT, eps_n=None, margin=
             a, b = int(pairs[0, i]), int(pairs[1, i])
             GA, GB = cache[batch.body_geom[a]], cache[batch.body_geom[b]]
             m = collide_pair(GA, batch.pose[:, a], GB, batch.pose[:, b], batch.tau, K, lam, eps_n,
-                             no_ee=no_ee, one_sided_vs=one_sided_vs)
+                             no_ee=no_ee, one_sided_vs=one_sided_vs, presel=presel, safeguard=safeguard)
             for k in ("p", "nu", "d", "w"):
                 out[k][i] = m[k].numpy()
     return pairs, offsets, out

@@ -601,6 +601,83 @@ def pin_simplification_flags():
         assert np.allclose(s[k].numpy(), m[k].numpy(), atol=1e-9)
 
 
+def pin_soft_topk():
+    """SoftSort selection rows: stochastic, invariant to reordering the
+    inputs (columns move with them), one-hot on the sorted top-K as tau -> 0,
+    Gamma x -> the K largest values in order."""
+    rng = np.random.default_rng(51)
+    x = T(rng.normal(size=40))
+    G = O.soft_topk(x, 7, 0.3)
+    assert torch.allclose(G.sum(1), torch.ones(7, dtype=DT), atol=1e-14)
+    perm = torch.as_tensor(rng.permutation(40))
+    Gp = O.soft_topk(x[perm], 7, 0.3)
+    assert torch.allclose(Gp, G[:, perm], atol=1e-14)
+    G0 = O.soft_topk(x, 7, 1e-6)
+    order = np.argsort(-x.numpy())[:7]
+    assert np.allclose(G0.numpy(), np.eye(40)[order], atol=1e-12)
+    assert np.allclose((G0 @ x).numpy(), np.sort(x.numpy())[::-1][:7], atol=1e-12)
+
+
+def pin_preselect_against_sphere():
+    """Pre-selection of a polytope's vertices and edges against a sphere: the
+    metrics are the closed-form distance |v - c| - r, so as tau -> 0 the soft
+    vertices are the K_V vertices nearest the sphere's surface (deepest first)
+    and the soft edges those with the smallest mean corner metric."""
+    rng = np.random.default_rng(52)
+    GA = O.make_geom(O.POLYTOPE, points=W.ellipsoid_points(rng, 20, [0.45, 0.35, 0.4]))
+    GB = O.make_geom(O.SPHERE, params=[0.3, 0, 0, 0])
+    qA, qB = W.uniform_quats(rng, 2)
+    pA, pB = _pose(qA, [0.0, 0.0, 0.0]), _pose(qB, [0.5, 0.1, -0.05])
+    tau = 1e-7
+    RA, tA = O.pose_Rt(pA)
+    RB, tB = O.pose_Rt(pB)
+    with torch.no_grad():
+        sVA, sVB, a0, a1, b0, b1 = O.preselect(GA, RA, tA, GB, RB, tB, tau, 5, 6)
+    vw = np.asarray(GA.vertices(), float) @ O.quat_to_R(T(qA)).numpy().T
+    m = np.linalg.norm(vw - np.asarray(pB[4:], float), axis=1) - 0.3
+    order = np.argsort(m)
+    assert np.allclose(sVA.numpy(), vw[order[:5]], atol=1e-9)
+    E = np.asarray(GA.edges)
+    me = 0.5 * (m[E[:, 0]] + m[E[:, 1]])
+    eo = np.argsort(me)[:6]
+    assert np.allclose(a0.numpy(), vw[E[eo, 0]], atol=1e-9) and np.allclose(a1.numpy(), vw[E[eo, 1]], atol=1e-9)
+    assert sVB.shape == (5, 3) and b0.shape == (6, 3)
+
+
+def pin_preselect_everything_limit():
+    """Selecting every vertex and edge with sharp SoftSort rows gives back the
+    full method: the same candidates in another order, hence the same
+    manifold (the manifold does not depend on candidate order)."""
+    for kind, seed in (("poly", 53), ("capbox", 54)):
+        GA, pA, GB, pB = _pair_case(kind, seed)
+        tau = 1e-5
+        nv = max(GA.vertices().shape[0], GB.vertices().shape[0])
+        ne = max(GA.edges.shape[0], GB.edges.shape[0])
+        with torch.no_grad():
+            full = O.collide_pair(GA, pA, GB, pB, tau, 6)
+            sel = O.collide_pair(GA, pA, GB, pB, tau, 6, presel=(nv, ne))
+        for k in ("p", "nu", "d", "w"):
+            assert np.allclose(sel[k].numpy(), full[k].numpy(), atol=1e-8), (kind, k)
+
+
+def pin_preselect_safeguard():
+    """Safeguard: edges taken from the bodies' own meshes have witnesses on
+    their own surfaces, where the smoothed SDF is >= 0, so both inside
+    indicators are <= 1/2 and every E-E log-activity drops by >= 2 ln 2;
+    vertex candidates are untouched."""
+    GA, pA, GB, pB = _pair_case("poly", 55)
+    tau = 1e-4   # sharp selection: the soft edges are mesh edges
+    RA, tA = O.pose_Rt(pA)
+    RB, tB = O.pose_Rt(pB)
+    with torch.no_grad():
+        c0 = O.pair_candidates(GA, RA, tA, GB, RB, tB, tau, presel=(4, 5))
+        c1 = O.pair_candidates(GA, RA, tA, GB, RB, tB, tau, presel=(4, 5), safeguard=True)
+    nvs = c0["extra"]["n_vs"]
+    assert torch.equal(c0["logw"][:nvs], c1["logw"][:nvs])
+    drop = (c1["logw"][nvs:] - c0["logw"][nvs:]).numpy()
+    assert drop.shape[0] == 2 * 5 * 5 and np.all(drop <= -2 * math.log(2) + 1e-6), drop.max()
+
+
 # ----------------------------------------------------------------------------- gradients
 
 def _loss_fd(GA, pA, GB, pB, tau, K, cot, xiA, xiB):

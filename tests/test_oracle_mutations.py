@@ -61,6 +61,12 @@ MUTATIONS = [
      [P.pin_qp_no_smoothing]),                                                         # edge minimiser sign
     ("ee_qp_hard", "best = torch.argmin(costs, dim=-1, keepdim=True)", "best = torch.argmax(costs, dim=-1, keepdim=True)",
      [P.pin_qp_no_smoothing]),                                                         # worst box edge
+    ("preselect", "meA = 0.5 * (mA[eA[:, 0]] + mA[eA[:, 1]])", "meA = torch.maximum(mA[eA[:, 0]], mA[eA[:, 1]])",
+     [P.pin_preselect_against_sphere]),                                                # edge metric not the mean
+    ("preselect", "GvA = soft_topk(-mA, min(KV, vA.shape[0]), tau)", "GvA = soft_topk(mA, min(KV, vA.shape[0]), tau)",
+     [P.pin_preselect_against_sphere]),                                                # shallowest selected
+    ("soft_topk", "top = torch.topk(x, K, sorted=True).values", "top = torch.topk(x, K, sorted=False).values",
+     [P.pin_soft_topk]),                                                               # rows out of order
     ("quat_to_R", "[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)]",
      "[1 - 2 * (y * y + z * z), 2 * (x * y + w * z), 2 * (x * z + w * y)]",
      [P.pin_quaternion_rotation]),                                                     # sign in R
