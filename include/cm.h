@@ -81,6 +81,8 @@ typedef struct {
   float cull_margin;
   int32_t K;          /* contacts per pair, 1..CM_MAX_K */
   uint32_t flags;     /* CM_FLAG_* below, 0 = the full method */
+  int32_t presel_vertices;  /* soft top-K pre-selection: K_V, K_E per body, */
+  int32_t presel_edges;     /* 1..CM_MAX_PRESEL each; both 0 = off (below)  */
 } cm_params;
 
 /* Simplifications the paper evaluates for speed (supplementary material,
@@ -89,6 +91,20 @@ typedef struct {
  * against B's SDF.  Candidate order is unchanged otherwise. */
 #define CM_FLAG_NO_EE 1u
 #define CM_FLAG_ONE_SIDED_VS 2u
+
+/* Soft top-K pre-selection (Sec. IV-A overview; supplementary material on
+ * picking the top-K numbers and on safeguarding).  With presel_vertices and
+ * presel_edges > 0, every vertex of a pair gets the other body's SDF at it as
+ * penetration metric and every edge the mean of its corners' metrics; SoftSort
+ * rows over -metric select min(K_V, |V|) vertices and min(K_E, |E|) edges per
+ * body as weighted averages, and the candidates are built from those only
+ * (V-S over the selected vertices, E-E over the selected edge pairs).
+ * CM_FLAG_SAFEGUARD additionally scales every E-E activity by the soft
+ * indicators that both witness points lie inside their own bodies.
+ * Forward only (cm_collide and served forward requests); cm_collide_fused and
+ * cm_collide_backward return CM_ERR_INVALID_ARG for it. */
+#define CM_MAX_PRESEL 64
+#define CM_FLAG_SAFEGUARD 4u
 
 /* A batch of scenes.  Bodies of scene s are body_offsets[s] .. [s+1]-1.
  * Candidate pairs: all i < j within each scene when cand_offsets is NULL,

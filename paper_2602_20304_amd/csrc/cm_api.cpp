@@ -250,8 +250,14 @@ cm_status resolve_params(cm_context* ctx, const cm_params* prm, ParamsDev* pd) {
   if (!prm) return cm_fail(ctx, CM_ERR_INVALID_ARG, "null params");
   if (!(prm->tau > 0.f) || !std::isfinite(prm->tau)) return cm_fail(ctx, CM_ERR_INVALID_ARG, "tau must be > 0");
   if (prm->K < 1 || prm->K > CM_MAX_K) return cm_fail(ctx, CM_ERR_INVALID_ARG, "K must be in 1..32");
-  if (prm->flags & ~(CM_FLAG_NO_EE | CM_FLAG_ONE_SIDED_VS))
+  if (prm->flags & ~(CM_FLAG_NO_EE | CM_FLAG_ONE_SIDED_VS | CM_FLAG_SAFEGUARD))
     return cm_fail(ctx, CM_ERR_INVALID_ARG, "unknown flags");
+  const bool presel = prm->presel_vertices != 0 || prm->presel_edges != 0;
+  if (presel && (prm->presel_vertices < 1 || prm->presel_vertices > CM_MAX_PRESEL || prm->presel_edges < 1 ||
+                 prm->presel_edges > CM_MAX_PRESEL))
+    return cm_fail(ctx, CM_ERR_INVALID_ARG, "presel_vertices / presel_edges must both be in 1..64 (or both 0)");
+  if ((prm->flags & CM_FLAG_SAFEGUARD) && !presel)
+    return cm_fail(ctx, CM_ERR_INVALID_ARG, "CM_FLAG_SAFEGUARD needs pre-selection");
   pd->tau = double(prm->tau);
   pd->inv_tau = 1.0 / pd->tau;
   pd->c_log2 = kLog2e / pd->tau;
@@ -264,6 +270,8 @@ cm_status resolve_params(cm_context* ctx, const cm_params* prm, ParamsDev* pd) {
   pd->eps_tied = prm->eps_n < 0.f ? 1 : 0;
   pd->K = prm->K;
   pd->flags = prm->flags;
+  pd->presel_v = presel ? prm->presel_vertices : 0;
+  pd->presel_e = presel ? prm->presel_edges : 0;
   return CM_OK;
 }
 
@@ -447,6 +455,7 @@ extern "C" cm_status cm_collide_backward(cm_context* ctx, const cm_batch* batch,
   if ((s = resolve_batch(ctx, batch, &bd)) != CM_OK) return s;
   if ((s = resolve_out(ctx, fwd, &od)) != CM_OK) return s;
   if (!cot || !out) return cm_fail(ctx, CM_ERR_INVALID_ARG, "null cotangent or gradient struct");
+  if (pd.presel_v > 0) return cm_fail(ctx, CM_ERR_INVALID_ARG, "the adjoint does not support pre-selection");
   hipSetDevice(ctx->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
   const long long pool = (long long)ctx->h.vx.size();

@@ -378,6 +378,56 @@ __device__ __forceinline__ void sdf_poly_masked(const double4* __restrict__ pd, 
   }
 }
 
+// log2(s) for a normal s > 0 in float64: s = f 2^e with f in [1/sqrt 2,
+// sqrt 2), then log2 f = (2 / ln 2) atanh(y), y = (f - 1) / (f + 1), |y| <=
+// 0.172, by the odd series through y^15 (next term below 4e-14 relative).
+__device__ __forceinline__ double log2_64(double s) {
+  int e;
+  double f = frexp(s, &e);
+  if (f < 0.70710678118654752) { f *= 2.0; e -= 1; }
+  const double y = (f - 1.0) / (f + 1.0), y2 = y * y;
+  double p = 1.0 / 15.0;
+  p = fma(p, y2, 1.0 / 13.0);
+  p = fma(p, y2, 1.0 / 11.0);
+  p = fma(p, y2, 1.0 / 9.0);
+  p = fma(p, y2, 1.0 / 7.0);
+  p = fma(p, y2, 1.0 / 5.0);
+  p = fma(p, y2, 1.0 / 3.0);
+  p = fma(p, y2, 1.0);
+  return double(e) + 2.0 * kLog2e * y * p;
+}
+
+// SDF value of a body at a pair-frame point with a float64 LSE for
+// polytopes (float64 weights and logarithm): the pre-selection metrics, whose
+// differences are divided by tau in the selection weights.  IDENT: the body
+// is A.
+template <bool IDENT>
+__device__ __forceinline__ double sdf_value64(const BodyView& B, const D3& x, const Temp& T) {
+  D3 l = x;
+  if (!IDENT) {
+    const double dx = x.x - B.t[0], dy = x.y - B.t[1], dz = x.z - B.t[2];
+    l = d3(B.R[0] * dx + B.R[3] * dy + B.R[6] * dz, B.R[1] * dx + B.R[4] * dy + B.R[7] * dz,
+           B.R[2] * dx + B.R[5] * dy + B.R[8] * dz);
+  }
+  if (B.type != CM_POLYTOPE) {
+    double phi;
+    D3 g;
+    sdf_analytic(B.type, B.p, l, phi, g);
+    return phi;
+  }
+  double m = -1e300;
+  for (int f = 0; f < B.nf; ++f) {
+    const double4 q = B.planes[f];
+    m = fmax(m, fma(q.x, l.x, fma(q.y, l.y, fma(q.z, l.z, -q.w))));
+  }
+  double S = 0.0;
+  for (int f = 0; f < B.nf; ++f) {
+    const double4 q = B.planes[f];
+    S += exp2_64(fma(q.x, l.x, fma(q.y, l.y, fma(q.z, l.z, -q.w))) - m);
+  }
+  return T.tl * (m + log2_64(S));
+}
+
 // SDF of a body at a pair-frame point; gradient returned in the pair frame.
 // MODE: SdfMode (kValue leaves g untouched, kSurfGrad leaves phi untouched
 // for polytopes).  IDENT: the body is A, whose frame is the pair frame.
@@ -509,11 +559,15 @@ struct Cand {
 // nearest neighbour via the row / column LSE of the unsigned distances.
 // q is the edge pair's QP solution (ee_qp).  m1 / m2: null (all faces), or
 // the face masks (A's faces, B's faces) for the queries at e1 / e2, shared by
-// every active lane of the wave.
+// every active lane of the wave.  OWN_FULL: the edges are soft pre-selected
+// averages, which need not lie on their own bodies' surfaces, so the
+// own-body queries are full ones; safeguard then multiplies both activities
+// by sigma(-phi_A(e1)/tau) sigma(-phi_B(e2)/tau).
+template <bool OWN_FULL = false>
 __device__ __forceinline__ void ee_candidates(const D3& a0, const D3& t1, const D3& b0, const D3& t2, const EEQP& q,
                                               double row_lse, double col_lse, const BodyView& A, const BodyView& B,
                                               double eps_n, const Temp& T, const FaceMask* m1, const FaceMask* m2,
-                                              Cand& c1, Cand& c2) {
+                                              Cand& c1, Cand& c2, bool safeguard = false) {
   const D3 e1 = d3(a0.x + q.al1 * t1.x, a0.y + q.al1 * t1.y, a0.z + q.al1 * t1.z);
   const D3 e2 = d3(b0.x + q.al2 * t2.x, b0.y + q.al2 * t2.y, b0.z + q.al2 * t2.z);
   const double dsq = dot(q.de, q.de);
@@ -522,13 +576,17 @@ __device__ __forceinline__ void ee_candidates(const D3& a0, const D3& t1, const 
   const D3 nb = d3(q.de.x * in, q.de.y * in, q.de.z * in);
   double phiB1, phiA2, dum;
   D3 gA, gB, dg;
+  double phiA1 = 0.0, phiB2 = 0.0;
   sdf_body<kValue, false>(B, e1, T, phiB1, dg, m1 ? m1 + 1 : nullptr);
-  sdf_body<kSurfGrad, true>(A, e1, T, dum, gA, m1);                      // e1 lies on an edge of A
+  if (OWN_FULL) sdf_body<kFull, true>(A, e1, T, phiA1, gA, m1);
+  else sdf_body<kSurfGrad, true>(A, e1, T, dum, gA, m1);                   // e1 lies on an edge of A
   sdf_body<kValue, true>(A, e2, T, phiA2, dg, m2);
-  sdf_body<kSurfGrad, false>(B, e2, T, dum, gB, m2 ? m2 + 1 : nullptr);   // e2 lies on an edge of B
+  if (OWN_FULL) sdf_body<kFull, false>(B, e2, T, phiB2, gB, m2 ? m2 + 1 : nullptr);
+  else sdf_body<kSurfGrad, false>(B, e2, T, dum, gB, m2 ? m2 + 1 : nullptr);   // e2 lies on an edge of B
   const double gam1 = tanh64(dot(gB, nb), T);
   const double gam2 = tanh64(-dot(gA, nb), T);
-  const double base = q.log_con + lsig(-dot(gA, gB), T);
+  double base = q.log_con + lsig(-dot(gA, gB), T);
+  if (OWN_FULL && safeguard) base += lsig(-phiA1, T) + lsig(-phiB2, T);
   const double lp1 = base + lsig(-phiB1, T);
   const double lp2 = base + lsig(-phiA2, T);
   c1.d = gam1 * dbar;

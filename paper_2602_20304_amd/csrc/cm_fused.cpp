@@ -71,6 +71,7 @@ extern "C" cm_status cm_collide_fused(cm_context* ctx, const cm_batch* batch, co
   ParamsDev pd; BatchDev bd; OutDev od;
   cm_status s;
   if ((s = resolve_params(ctx, prm, &pd)) != CM_OK) return s;
+  if (pd.presel_v > 0) return cm_fail(ctx, CM_ERR_INVALID_ARG, "the fused path does not support pre-selection");
   if ((s = resolve_batch(ctx, batch, &bd)) != CM_OK) return s;
   if ((s = resolve_out(ctx, out, &od)) != CM_OK) return s;
   hipSetDevice(ctx->device);
@@ -154,7 +155,8 @@ extern "C" cm_status cm_collide_fused(cm_context* ctx, const cm_batch* batch, co
                             uint64_t(bd.n_cand), uint64_t(uintptr_t(od.n_pairs)), uint64_t(uintptr_t(od.pairs)),
                             uint64_t(uintptr_t(od.point)), uint64_t(uintptr_t(od.normal)),
                             uint64_t(uintptr_t(od.dist)), uint64_t(uintptr_t(od.weight)),
-                            uint64_t(uintptr_t(od.pair_offsets)), uint64_t(od.capacity), uint64_t(pd.K), uint64_t(pd.flags)};
+                            uint64_t(uintptr_t(od.pair_offsets)), uint64_t(od.capacity), uint64_t(pd.K), uint64_t(pd.flags),
+                            uint64_t(pd.presel_v), uint64_t(pd.presel_e)};
   for (uint64_t v : parts) key = mix(key, v);
   double dv[4] = {pd.tau, pd.lam, pd.eps_n, double(pd.margin)};
   for (double d : dv) { uint64_t b; std::memcpy(&b, &d, 8); key = mix(key, b); }

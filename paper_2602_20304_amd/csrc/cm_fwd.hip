@@ -146,7 +146,7 @@ __global__ __launch_bounds__(256) void bp_emit(Tables tb, BatchDev bt, float mar
 // Occupancy target: 3 waves per SIMD (<= 168 VGPRs) for K <= 8, where the
 // per-lane top-K list is short enough to fit with a handful of spills; 2
 // otherwise.
-template <int BLOCK, int KMAX, bool DYN>
+template <int BLOCK, int KMAX, bool DYN, bool PRESEL = false>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(KMAX <= 8 ? 3 : 2)))
 void collide_fwd(Tables tb, BatchDev bt, ParamsDev prm, OutDev out,
                                                      float* __restrict__ scratch, long long scratch_stride, int maxV,
@@ -155,8 +155,9 @@ void collide_fwd(Tables tb, BatchDev bt, ParamsDev prm, OutDev out,
                                                      unsigned* err) {
   extern __shared__ float4 smem4[];
   __shared__ PairShared ps;
-  PairEngine<BLOCK, KMAX, true> P(ps, reinterpret_cast<char*>(smem4), tb, bt, prm,
-                            scratch + (long long)blockIdx.x * scratch_stride, maxV, maxE, maxF);
+  PairEngine<BLOCK, KMAX, true, PRESEL> P(ps, reinterpret_cast<char*>(smem4), tb, bt, prm,
+                                          scratch + (long long)blockIdx.x * scratch_stride, maxV, maxE, maxF,
+                                          PRESEL ? presel_lds_bytes(maxV, maxE) : 0);
   const int tid = threadIdx.x;
   const int K = prm.K;
   // items: all kept pairs, or the [start, start + count) slice of `order`
@@ -175,6 +176,7 @@ void collide_fwd(Tables tb, BatchDev bt, ParamsDev prm, OutDev out,
     const int pi = ord ? ord[item] : item;
     if (P.setup(out.pairs[pi], out.pairs[out.capacity + pi], err)) {
       P.stage();
+      if (PRESEL) P.select();
       P.cull();
       double tk[KMAX];
       P.scores(tk);
@@ -210,9 +212,10 @@ void collide_fwd(Tables tb, BatchDev bt, ParamsDev prm, OutDev out,
 
 // ============================================================ launchers
 
-int fwd_lds_bytes(int maxV, int maxE, int maxF, int block, int kmax) {
-  (void)maxV; (void)kmax;
-  return lds_layout(maxE, maxF, block).bytes;
+int fwd_lds_bytes(int maxV, int maxE, int maxF, int block, int kmax, bool presel) {
+  (void)kmax;
+  const int extra = presel ? presel_lds_bytes(maxV, maxE) : 0;
+  return lds_layout(maxE, maxF, block, extra).bytes + extra;
 }
 
 hipError_t launch_broadphase(const Tables& tb, const BatchDev& bt, float margin, const OutDev& out, int* tile_sums,
@@ -232,20 +235,20 @@ hipError_t launch_broadphase(const Tables& tb, const BatchDev& bt, float margin,
   return hipGetLastError();
 }
 
-template <int BLOCK, int KMAX, bool DYN>
+template <int BLOCK, int KMAX, bool DYN, bool PRESEL = false>
 static hipError_t launch_fwd_t(const FwdLaunch& f, hipStream_t st) {
-  auto kern = collide_fwd<BLOCK, KMAX, DYN>;
-  const int lds = fwd_lds_bytes(f.maxV, f.maxE, f.maxF, BLOCK, KMAX);
+  auto kern = collide_fwd<BLOCK, KMAX, DYN, PRESEL>;
+  const int lds = fwd_lds_bytes(f.maxV, f.maxE, f.maxF, BLOCK, KMAX, PRESEL);
   hipLaunchKernelGGL(kern, dim3(f.grid), dim3(BLOCK), lds, st, f.tb, f.bt, f.prm, f.out, f.scratch,
                      f.scratch_stride, f.maxV, f.maxE, f.maxF, f.order, f.range, f.queue, f.err);
   return hipGetLastError();
 }
 
-template <int BLOCK, int KMAX, bool DYN>
+template <int BLOCK, int KMAX, bool DYN, bool PRESEL = false>
 static int occ_t(int maxV, int maxE, int maxF) {
   int nb = 0;
-  const int lds = fwd_lds_bytes(maxV, maxE, maxF, BLOCK, KMAX);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, collide_fwd<BLOCK, KMAX, DYN>, BLOCK, lds) != hipSuccess)
+  const int lds = fwd_lds_bytes(maxV, maxE, maxF, BLOCK, KMAX, PRESEL);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, collide_fwd<BLOCK, KMAX, DYN, PRESEL>, BLOCK, lds) != hipSuccess)
     return 1;
   return nb > 0 ? nb : 1;
 }
@@ -262,7 +265,15 @@ static int occ_t(int maxV, int maxE, int maxF) {
       return FN<256, 32, DYNV>(__VA_ARGS__);                                           \
   }
 
+// Pre-selection runs in its own instantiations (block 256, static order).
 hipError_t launch_collide_fwd(const FwdLaunch& f, hipStream_t st) {
+  if (f.prm.presel_v > 0) {
+    // the selection tracks taken items in a 64-bit mask per lane: <= 4096 per set
+    if (f.queue || f.block != 256 || f.maxV > 4096 || f.maxE > 4096) return hipErrorInvalidValue;
+    if (f.kmax == 8) return launch_fwd_t<256, 8, false, true>(f, st);
+    if (f.kmax == 16) return launch_fwd_t<256, 16, false, true>(f, st);
+    return launch_fwd_t<256, 32, false, true>(f, st);
+  }
   if (f.queue) {
     constexpr bool DYNV = true;
     CM_FWD_DISPATCH(launch_fwd_t, f, st)
@@ -273,6 +284,11 @@ hipError_t launch_collide_fwd(const FwdLaunch& f, hipStream_t st) {
 }
 
 int fwd_occupancy(const FwdLaunch& f) {
+  if (f.prm.presel_v > 0) {
+    if (f.kmax == 8) return occ_t<256, 8, false, true>(f.maxV, f.maxE, f.maxF);
+    if (f.kmax == 16) return occ_t<256, 16, false, true>(f.maxV, f.maxE, f.maxF);
+    return occ_t<256, 32, false, true>(f.maxV, f.maxE, f.maxF);
+  }
   if (f.queue) {
     constexpr bool DYNV = true;
     CM_FWD_DISPATCH(occ_t, f.maxV, f.maxE, f.maxF)

@@ -50,6 +50,7 @@ struct ParamsDev {
   int32_t K;
   int32_t eps_tied;         // eps_n = tau^2 (its tau dependence enters the adjoint)
   uint32_t flags;           // CM_FLAG_*
+  int32_t presel_v, presel_e;   // soft top-K pre-selection sizes (0: off)
 };
 
 struct OutDev {

@@ -54,7 +54,7 @@ struct BwdLaunch {
   GradDev gr;
 };
 
-int fwd_lds_bytes(int maxV, int maxE, int maxF, int block, int kmax);
+int fwd_lds_bytes(int maxV, int maxE, int maxF, int block, int kmax, bool presel = false);
 int bwd_lds_bytes(int maxV, int maxE, int maxF, int block);
 int bwd_occupancy(const BwdLaunch& b);
 hipError_t launch_collide_bwd(const BwdLaunch& b, hipStream_t st);

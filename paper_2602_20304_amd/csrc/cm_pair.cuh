@@ -106,11 +106,20 @@ __host__ __device__ inline LdsLayout lds_layout(int maxE, int maxF, int block, i
   return L;
 }
 
+// LDS bytes of the pre-selection arrays (PRESEL engines): the metrics of
+// every vertex and edge of both bodies, the selected values x_[k] of the four
+// sets, the soft vertices [2][K][3] and soft edge endpoints [2][K][6].
+__host__ __device__ inline int presel_lds_bytes(int maxV, int maxE) {
+  return 8 * (2 * maxV + 2 * maxE) + 8 * 4 * CM_MAX_PRESEL + 8 * 2 * CM_MAX_PRESEL * 3 + 8 * 2 * CM_MAX_PRESEL * 6;
+}
+
 // CULL: the candidate pass visits edge pairs in 8 x 8 tiles whose witness
 // queries use the per-segment face masks (the forward kernel and the
 // adjoint's recompute of it, so both take the same path); without it the
-// edge pairs go row-major and every face is visited.
-template <int BLOCK, int KMAX, bool CULL>
+// edge pairs go row-major and every face is visited.  PRESEL: soft top-K
+// pre-selection (select()) replaces the bodies' vertices and edges by the
+// selected soft ones before the candidate passes.
+template <int BLOCK, int KMAX, bool CULL, bool PRESEL = false>
 struct PairEngine {
   static constexpr int NW = BLOCK / 64;
 
@@ -140,6 +149,10 @@ struct PairEngine {
   double* Lcon;
   float* Sbuf;    // [nvs + 2 nee] candidate scores (float32, filter only)
   int* List;      // [nvs + 2 nee + 64] compacted indices of filtered candidates
+  double* sMet;     // PRESEL: metrics [maxV] A's vertices, [maxV] B's, [maxE] A's edges, [maxE] B's
+  double* sSel;     // PRESEL: [4][CM_MAX_PRESEL] selected values of the four sets
+  double* sSoft;    // PRESEL: soft vertices [2][CM_MAX_PRESEL][3], then soft edges [2][CM_MAX_PRESEL][6]
+  int kv, ke;       // PRESEL: requested K_V, K_E
   Temp T;
   double lam, eps_n;
   unsigned flags;   // CM_FLAG_*
@@ -173,6 +186,11 @@ struct PairEngine {
     sMB2 = reinterpret_cast<unsigned long long*>(smem + L.mB2);
     sG1 = reinterpret_cast<FaceMask*>(smem + L.g1);
     sG2 = reinterpret_cast<FaceMask*>(smem + L.g2);
+    sMet = reinterpret_cast<double*>(smem + L.bytes);
+    sSel = sMet + 2 * maxV_ + 2 * maxE_;
+    sSoft = sSel + 4 * CM_MAX_PRESEL;
+    kv = prm.presel_v;
+    ke = prm.presel_e;
     MW = CULL ? mask_words(maxF_) : 0;
     const long long mm = (long long)maxE_ * maxE_;
     Dbuf = reinterpret_cast<double*>(slot);
@@ -286,6 +304,120 @@ struct PairEngine {
     __syncthreads();
   }
 
+  // ------------------------------------------------------------ pre-selection
+  // Soft top-K pre-selection (PRESEL): every vertex gets the other body's SDF
+  // at it as penetration metric (float64 LSE: the selection weights divide
+  // metric differences by tau), every edge the mean of its corners'; for
+  // each of the four sets (A's vertices, B's, A's edges, B's) the K largest
+  // values x_[k] of x = -metric are found (a wave per set), and each soft
+  // vertex / edge k is the average of the set's positions with SoftSort
+  // weights exp(-|x_[k] - x_i| / tau) (one thread per selected item; float64
+  // exponentials, as the weights move geometry).  The soft edges then replace
+  // the staged edges and the counts shrink to the selection sizes.
+  __device__ void select() {
+    const int nvA = A.nv, nvB = B.nv, neA = A.ne, neB = B.ne;
+    double* mVA = sMet;
+    double* mVB = sMet + maxV;
+    double* mEA = sMet + 2 * maxV;
+    double* mEB = mEA + maxE;
+    for (int i = tid; i < nvA + nvB; i += BLOCK) {
+      if (i < nvA) mVA[i] = sdf_value64<false>(B, vertex<true>(*GA, i, A), T);
+      else mVB[i - nvA] = sdf_value64<true>(A, vertex<false>(*GB, i - nvA, B), T);
+    }
+    __syncthreads();
+    for (int i = tid; i < neA + neB; i += BLOCK) {
+      const bool onA = i < neA;
+      const int e = onA ? i : i - neA;
+      const GeomRec* G = onA ? GA : GB;
+      const double* mv = onA ? mVA : mVB;
+      double* me = onA ? mEA : mEB;
+      me[e] = 0.5 * (mv[tb.e0[G->e_off + e]] + mv[tb.e1[G->e_off + e]]);
+    }
+    __syncthreads();
+    const int Kva = min(kv, nvA), Kvb = min(kv, nvB), Kea = min(ke, neA), Keb = min(ke, neB);
+    // hard top-K of -metric per set: K rounds of a wave-wide maximum; the
+    // lowest lane holding it removes its item (bit j of `taken`: item lane + 64 j)
+    for (int set = wave; set < 4; set += NW) {
+      const double* m = set == 0 ? mVA : set == 1 ? mVB : set == 2 ? mEA : mEB;
+      const int D = set == 0 ? nvA : set == 1 ? nvB : set == 2 ? neA : neB;
+      const int Ks = set == 0 ? Kva : set == 1 ? Kvb : set == 2 ? Kea : Keb;
+      unsigned long long taken = 0ull;
+      for (int r = 0; r < Ks; ++r) {
+        double best = -INFINITY;
+        int bj = -1;
+        for (int j = 0; lane + 64 * j < D; ++j) {
+          const double x = -m[lane + 64 * j];
+          if (!((taken >> j) & 1ull) && x > best) { best = x; bj = j; }
+        }
+        const double wm = wave_max(best);
+        const unsigned long long ball = __ballot(bj >= 0 && best == wm);
+        if (lane == __ffsll((long long)ball) - 1) taken |= 1ull << bj;
+        if (lane == 0) sSel[set * CM_MAX_PRESEL + r] = wm;
+      }
+    }
+    __syncthreads();
+    // soft items: thread t < Kva + Kvb + Kea + Keb builds one
+    double* softE = sSoft + 2 * CM_MAX_PRESEL * 3;
+    if (tid < Kva + Kvb + Kea + Keb) {
+      int set = 0, k = tid;
+      if (k >= Kva) { k -= Kva; set = 1;
+        if (k >= Kvb) { k -= Kvb; set = 2;
+          if (k >= Kea) { k -= Kea; set = 3; } } }
+      const double* m = set == 0 ? mVA : set == 1 ? mVB : set == 2 ? mEA : mEB;
+      const int D = set == 0 ? nvA : set == 1 ? nvB : set == 2 ? neA : neB;
+      const double xk = sSel[set * CM_MAX_PRESEL + k];
+      double sw = 0.0, a[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      for (int i = 0; i < D; ++i) {
+        const double w = exp64n(-fabs(xk + m[i]) * T.inv_tau);   // x_i = -m[i]
+        sw += w;
+        if (set < 2) {
+          const D3 v = set == 0 ? vertex<true>(*GA, i, A) : vertex<false>(*GB, i, B);
+          a[0] = fma(w, v.x, a[0]); a[1] = fma(w, v.y, a[1]); a[2] = fma(w, v.z, a[2]);
+        } else {
+          D3 p0, t;
+          if (set == 2) EA.get(i, p0, t);
+          else EB.get(i, p0, t);
+          a[0] = fma(w, p0.x, a[0]); a[1] = fma(w, p0.y, a[1]); a[2] = fma(w, p0.z, a[2]);
+          a[3] = fma(w, p0.x + t.x, a[3]); a[4] = fma(w, p0.y + t.y, a[4]); a[5] = fma(w, p0.z + t.z, a[5]);
+        }
+      }
+      const double inv = 1.0 / sw;   // sw >= 1: the row's own maximum has weight 1
+      if (set < 2) {
+        double* o = sSoft + 3 * (set * CM_MAX_PRESEL + k);
+        o[0] = a[0] * inv; o[1] = a[1] * inv; o[2] = a[2] * inv;
+      } else {
+        double* o = softE + 6 * ((set - 2) * CM_MAX_PRESEL + k);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) o[c] = a[c] * inv;
+      }
+    }
+    __syncthreads();
+    // the soft edges replace the staged ones; counts shrink
+    for (int i = tid; i < Kea + Keb; i += BLOCK) {
+      const bool onA = i < Kea;
+      const int k = onA ? i : i - Kea;
+      const double* o = softE + 6 * ((onA ? 0 : CM_MAX_PRESEL) + k);
+      double* x0 = onA ? EA.x0 : EB.x0;
+      double* y0 = onA ? EA.y0 : EB.y0;
+      double* z0 = onA ? EA.z0 : EB.z0;
+      double* tx = onA ? EA.tx : EB.tx;
+      double* ty = onA ? EA.ty : EB.ty;
+      double* tz = onA ? EA.tz : EB.tz;
+      x0[k] = o[0]; y0[k] = o[1]; z0[k] = o[2];
+      tx[k] = o[3] - o[0]; ty[k] = o[4] - o[1]; tz[k] = o[5] - o[2];
+    }
+    A.nv = Kva; A.ne = Kea;
+    B.nv = Kvb; B.ne = Keb;
+    if (tid == 0) {
+      ps.A.nv = Kva; ps.A.ne = Kea;
+      ps.B.nv = Kvb; ps.B.ne = Keb;
+      ps.nvs = Kva + ((flags & CM_FLAG_ONE_SIDED_VS) ? 0 : Kvb);
+      ps.nee = (flags & CM_FLAG_NO_EE) ? 0 : Kea * Keb;
+      ps.ncand = ps.nvs + 2 * ps.nee;
+    }
+    __syncthreads();
+  }
+
   // ------------------------------------------------------------ cull
   // Per edge segment of A and of B (extended to the witness range of the
   // smoothed QP, alpha in [-0.3 tau, 1 + 0.3 tau]): the faces of each
@@ -371,6 +503,12 @@ struct PairEngine {
 
   // ------------------------------------------------------------ candidates
   __device__ __forceinline__ void vs(int i, Cand& c) const {
+    if (PRESEL) {
+      const double* v = sSoft + 3 * (i < A.nv ? i : CM_MAX_PRESEL + (i - A.nv));
+      if (i < A.nv) vs_candidate<false>(d3(v[0], v[1], v[2]), B, -1.0, T, c);
+      else vs_candidate<true>(d3(v[0], v[1], v[2]), A, 1.0, T, c);
+      return;
+    }
     if (i < A.nv) vs_candidate<false>(vertex<true>(*GA, i, A), B, -1.0, T, c);
     else vs_candidate<true>(vertex<false>(*GB, i - A.nv, B), A, 1.0, T, c);
   }
@@ -387,7 +525,8 @@ struct PairEngine {
     EB.get(l, b0, t2);
     const int i = k * B.ne + l;
     const EEQP q = ee_from_alpha(a0, t1, b0, t2, Al1[i], Al2[i], Lcon[i]);
-    ee_candidates(a0, t1, b0, t2, q, sRow[k], sCol[l], A, B, eps_n, T, m1, m2, c1, c2);
+    ee_candidates<PRESEL>(a0, t1, b0, t2, q, sRow[k], sCol[l], A, B, eps_n, T, m1, m2, c1, c2,
+                          PRESEL && (flags & CM_FLAG_SAFEGUARD));
   }
   // candidate idx in the fixed order: A's vertices, B's vertices, E-E (k, l)
   // row-major with witness 1 before witness 2

@@ -263,8 +263,14 @@ cm_status cm_server_submit(cm_server* srv, const cm_request* q, uint64_t* ticket
   if (!srv || !q || !ticket) return CM_ERR_INVALID_ARG;
   if (q->n_scenes < 0 || q->n_bodies < 0 || (q->n_scenes > 0 && (!q->body_offsets || !q->body_geom || !q->pose)))
     return CM_ERR_INVALID_ARG;
-  if (q->params.K < 1 || q->params.K > CM_MAX_K || !(q->params.tau > 0.f) || (q->params.flags & ~(CM_FLAG_NO_EE | CM_FLAG_ONE_SIDED_VS)))
+  if (q->params.K < 1 || q->params.K > CM_MAX_K || !(q->params.tau > 0.f) ||
+      (q->params.flags & ~(CM_FLAG_NO_EE | CM_FLAG_ONE_SIDED_VS | CM_FLAG_SAFEGUARD)))
     return CM_ERR_INVALID_ARG;
+  const bool presel = q->params.presel_vertices != 0 || q->params.presel_edges != 0;
+  if (presel && (q->params.presel_vertices < 1 || q->params.presel_vertices > CM_MAX_PRESEL ||
+                 q->params.presel_edges < 1 || q->params.presel_edges > CM_MAX_PRESEL || q->want_backward))
+    return CM_ERR_INVALID_ARG;   // pre-selection: forward requests only
+  if ((q->params.flags & CM_FLAG_SAFEGUARD) && !presel) return CM_ERR_INVALID_ARG;
   auto r = std::make_unique<Request>();
   r->n_scenes = q->n_scenes;
   r->n_bodies = q->n_bodies;
@@ -288,10 +294,12 @@ cm_status cm_server_submit(cm_server* srv, const cm_request* q, uint64_t* ticket
   if (r->want_bwd && q->cot_dist) r->cot_dist.assign(q->cot_dist, q->cot_dist + cap * K);
   if (r->want_bwd && q->cot_normal) r->cot_normal.assign(q->cot_normal, q->cot_normal + 3 * cap * K);
   // footprint with the grid this request will use
-  FwdLaunch f;
+  FwdLaunch f{};
   f.tb = ctx_tables(srv->ctx);
   f.maxV = std::max(srv->ctx->maxV, 1); f.maxE = std::max(srv->ctx->maxE, 1); f.maxF = std::max(srv->ctx->maxF, 1);
   f.block = 256; f.kmax = kmax_for(K); f.queue = nullptr;
+  f.prm.presel_v = presel ? q->params.presel_vertices : 0;   // selects the kernel whose occupancy applies
+  f.prm.presel_e = presel ? q->params.presel_edges : 0;
   const long long grid = request_grid(srv->ctx, fwd_occupancy(f), cap);
   r->footprint = footprint(srv->ctx, *r, grid, fwd_scratch_floats(f.maxV, f.maxE));
   if (r->footprint > srv->budget) return cm_fail(srv->ctx, CM_ERR_REJECTED, "request exceeds the HBM budget");
