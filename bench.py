@@ -13,6 +13,8 @@ Legs, all in one process on the same inputs:
   plain     cm_collide (broadphase + one forward pair kernel)
   fused     cm_collide_fused (cost-ordered work queue, replayed hipGraph)
   fwd_bwd   cm_collide + cm_collide_backward with random cotangents
+  plain_ne, plain_ne_s     the no-E-E / one-sided simplification flags
+  plain_presel, fwd_bwd_presel   soft top-K pre-selection (K_V 64, K_E 18)
   serving   a short Poisson request stream through cm_server_* (p50 / p99)
 The headline value is the forward throughput of --path (fused by default).
 
@@ -294,7 +296,8 @@ def main():
                     help="skip the forward legs without E-E (ne), with one-sided vertex contacts (ne_s) and "
                          "with soft top-K pre-selection (presel)")
     ap.add_argument("--only", default=None,
-                    choices=[None, "plain", "fused", "fwd_bwd", "plain_ne", "plain_ne_s", "plain_presel"],
+                    choices=[None, "plain", "fused", "fwd_bwd", "plain_ne", "plain_ne_s", "plain_presel",
+                             "fwd_bwd_presel"],
                     help="run one leg only (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (PMC byte calibration)")
@@ -339,16 +342,18 @@ def main():
     leg_flags = {"plain_ne": FLAG_NO_EE, "plain_ne_s": FLAG_NO_EE | FLAG_ONE_SIDED_VS}
     # the paper's benchmark shape: every vertex (K_V at its cap of 64 covers the
     # meshes here) and the K_E = 18 deepest edges per body
-    leg_presel = {"plain_presel": (64, 18)}
+    leg_presel = {"plain_presel": (64, 18), "fwd_bwd_presel": (64, 18)}
 
     def step(leg):
         ctx.collide(db, batch.tau, batch.K, out=out, fused=(leg == "fused"), stream=stream,
                     flags=leg_flags.get(leg, 0), presel=leg_presel.get(leg))
-        if leg == "fwd_bwd":
-            ctx.collide_backward(db, out, batch.tau, batch.K, None, cot_n, cot_d, None, stream=stream)
+        if leg in ("fwd_bwd", "fwd_bwd_presel"):
+            ctx.collide_backward(db, out, batch.tau, batch.K, None, cot_n, cot_d, None, stream=stream,
+                                 presel=leg_presel.get(leg))
 
     legs = ["plain", "fused"] + ([] if args.no_bwd else ["fwd_bwd"])
     legs += [] if args.no_simplifications else ["plain_ne", "plain_ne_s", "plain_presel"]
+    legs += [] if (args.no_simplifications or args.no_bwd) else ["fwd_bwd_presel"]
     if args.only:
         legs = [args.only]
     results = {}
@@ -435,6 +440,9 @@ def main():
     if "plain" in results and "plain_presel" in results:
         line["preselection"] = {"presel": list(leg_presel["plain_presel"]),
                                 "speedup_vs_all_pairs": results["plain"]["ms"] / results["plain_presel"]["ms"]}
+        if "fwd_bwd" in results and "fwd_bwd_presel" in results:
+            line["preselection"]["fwd_bwd_speedup_vs_all_pairs"] = (results["fwd_bwd"]["ms"]
+                                                                    / results["fwd_bwd_presel"]["ms"])
     if args.serve and not args.only:
         log(f"serving leg: {args.serve} requests ...")
         line["serving"] = serving_leg(Context, args.serve)

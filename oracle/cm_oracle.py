@@ -771,8 +771,10 @@ def collide_batch(batch, pair_list=None, lam=LAMBDA_DEFAULT, eps_n=None, margin=
     return pairs, offsets, out
 
 
-def pair_grad(GA, poseA, GB, poseB, tau, K, cot, lam=LAMBDA_DEFAULT, eps_n=None, no_ee=False, one_sided_vs=False):
-    """Gradient of L = <cot, outputs> for one pair by autograd of the forward.
+def pair_grad(GA, poseA, GB, poseB, tau, K, cot, lam=LAMBDA_DEFAULT, eps_n=None, no_ee=False, one_sided_vs=False,
+              presel=None, safeguard=False):
+    """Gradient of L = <cot, outputs> for one pair by autograd of the forward
+    (with presel, also through the SoftSort selection weights and metrics).
 
     cot: dict with any of p [K,3], nu [K,3], d [K], w [K] (numpy).
     Returns dict: xiA [6], xiB [6] (left tangents (rho, omega)), geomA, geomB
@@ -783,7 +785,8 @@ def pair_grad(GA, poseA, GB, poseB, tau, K, cot, lam=LAMBDA_DEFAULT, eps_n=None,
     xiA = torch.zeros(6, dtype=DT, requires_grad=True)
     xiB = torch.zeros(6, dtype=DT, requires_grad=True)
     tau_t = torch.tensor(float(tau), dtype=DT, requires_grad=True)
-    m = collide_pair(GA, poseA, GB, poseB, tau_t, K, lam, eps_n, xiA, xiB, no_ee=no_ee, one_sided_vs=one_sided_vs)
+    m = collide_pair(GA, poseA, GB, poseB, tau_t, K, lam, eps_n, xiA, xiB, no_ee=no_ee, one_sided_vs=one_sided_vs,
+                     presel=presel, safeguard=safeguard)
     L = torch.zeros((), dtype=DT)
     for k, v in cot.items():
         L = L + (m[k] * torch.as_tensor(np.asarray(v, dtype=np.float64))).sum()

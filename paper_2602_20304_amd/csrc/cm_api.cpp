@@ -455,7 +455,8 @@ extern "C" cm_status cm_collide_backward(cm_context* ctx, const cm_batch* batch,
   if ((s = resolve_batch(ctx, batch, &bd)) != CM_OK) return s;
   if ((s = resolve_out(ctx, fwd, &od)) != CM_OK) return s;
   if (!cot || !out) return cm_fail(ctx, CM_ERR_INVALID_ARG, "null cotangent or gradient struct");
-  if (pd.presel_v > 0) return cm_fail(ctx, CM_ERR_INVALID_ARG, "the adjoint does not support pre-selection");
+  if (pd.presel_v > 0 && (ctx->maxV > 4096 || ctx->maxE > 4096))
+    return cm_fail(ctx, CM_ERR_INVALID_ARG, "pre-selection needs at most 4096 vertices and edges per body");
   hipSetDevice(ctx->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
   const long long pool = (long long)ctx->h.vx.size();

@@ -11,6 +11,11 @@
 //       field adjoints -> indicators -> SDF queries -> witness QP -> edges
 //   N   nearest-neighbour adjoint: row / column LSE adjoints flow back into
 //       every unsigned distance D_kl of the touched rows and columns
+//   S   (pre-selection only) SoftSort-selection adjoint: the soft vertices'
+//       and soft edges' adjoints flow to the mesh vertices through the
+//       normalised weights, and to the penetration metrics through the
+//       weights' dependence on x_i and x_[k]; the metrics' adjoints then run
+//       through the SDF queries that produced them
 //   G   face-plane adjoints -> hull vertices, mesh vertices -> parameters,
 //       B's placement twist and the output transform -> world pose twists
 #include <hip/hip_runtime.h>
@@ -22,10 +27,14 @@
 namespace cm {
 
 struct BwdLds {
-  int vA, vB, plA, plB, prm, rbar, cbar, cot, F, top, best, tw, bytes;
+  int vA, vB, plA, plB, prm, rbar, cbar, cot, F, top, best, tw, sv, se, si, mb, sk, bytes;
 };
 
-__host__ __device__ inline BwdLds bwd_layout(int base, int maxV, int maxE, int maxF, int block) {
+// presel: the selection adjoint's arrays follow (soft vertex adjoints
+// [2][CM_MAX_PRESEL][3], soft edge endpoint adjoints [2][CM_MAX_PRESEL][6],
+// selected indices [4][CM_MAX_PRESEL], metric adjoints of both bodies'
+// vertices [2][maxV], weight sums and <adjoint, soft item> per item [2][4][CM_MAX_PRESEL]).
+__host__ __device__ inline BwdLds bwd_layout(int base, int maxV, int maxE, int maxF, int block, bool presel) {
   BwdLds L;
   int o = base;
   L.vA = o; o += 4 * 3 * maxV;
@@ -41,13 +50,23 @@ __host__ __device__ inline BwdLds bwd_layout(int base, int maxV, int maxE, int m
   L.top = o; o += 8 * CM_MAX_K;        // adjoint of s_[k]
   L.best = o; o += 4 * (CM_MAX_K + block);
   L.tw = o; o += 8 * 8;                // output twist terms
+  L.sv = L.se = L.si = L.mb = L.sk = o;
+  if (presel) {
+    L.sv = o; o += 4 * 2 * CM_MAX_PRESEL * 3;
+    L.se = o; o += 4 * 2 * CM_MAX_PRESEL * 6;
+    L.si = o; o += 4 * 4 * CM_MAX_PRESEL;
+    L.mb = o; o += 4 * 2 * maxV;
+    o = (o + 7) & ~7;
+    L.sk = o; o += 8 * 2 * 4 * CM_MAX_PRESEL;
+  }
   L.bytes = (o + 15) & ~15;
   return L;
 }
 
-// LDS the adjoint needs beyond the engine (an upper bound for any base).
-__host__ __device__ inline int bwd_extra_bytes(int maxV, int maxE, int maxF, int block) {
-  return bwd_layout(0, maxV, maxE, maxF, block).bytes + 32;
+// LDS the adjoint needs beyond the engine (an upper bound for any base),
+// including the engine's pre-selection arrays when presel.
+__host__ __device__ inline int bwd_extra_bytes(int maxV, int maxE, int maxF, int block, bool presel) {
+  return bwd_layout(0, maxV, maxE, maxF, block, presel).bytes + 32 + (presel ? presel_lds_bytes(maxV, maxE) : 0);
 }
 
 struct BwdArgs {
@@ -55,17 +74,19 @@ struct BwdArgs {
   GradDev gr;
 };
 
-template <int BLOCK, int KMAX>
+template <int BLOCK, int KMAX, bool PRESEL>
 __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, ParamsDev prm, OutDev fwd, BwdArgs ga,
                                                      float* __restrict__ scratch, long long scratch_stride, int maxV,
                                                      int maxE, int maxF, unsigned* err) {
   extern __shared__ float4 smem4[];
   char* smem = reinterpret_cast<char*>(smem4);
   __shared__ PairShared ps;
-  const int extra = bwd_extra_bytes(maxV, maxE, maxF, BLOCK);
-  PairEngine<BLOCK, KMAX, true> P(ps, smem, tb, bt, prm, scratch + (long long)blockIdx.x * scratch_stride, maxV, maxE,
-                                   maxF, extra);
-  const BwdLds L = bwd_layout(lds_layout(maxE, maxF, BLOCK, extra).bytes, maxV, maxE, maxF, BLOCK);
+  const int extra = bwd_extra_bytes(maxV, maxE, maxF, BLOCK, PRESEL);
+  PairEngine<BLOCK, KMAX, true, PRESEL> P(ps, smem, tb, bt, prm, scratch + (long long)blockIdx.x * scratch_stride, maxV,
+                                          maxE, maxF, extra);
+  // the engine's pre-selection arrays sit right after its own layout
+  const BwdLds L = bwd_layout(lds_layout(maxE, maxF, BLOCK, extra).bytes + (PRESEL ? presel_lds_bytes(maxV, maxE) : 0),
+                              maxV, maxE, maxF, BLOCK, PRESEL);
   float* vA3 = reinterpret_cast<float*>(smem + L.vA);
   float* vB3 = reinterpret_cast<float*>(smem + L.vB);
   float* plA = reinterpret_cast<float*>(smem + L.plA);
@@ -79,6 +100,12 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
   double* topb = reinterpret_cast<double*>(smem + L.top);
   int* bestI = reinterpret_cast<int*>(smem + L.best);
   double* twOut = reinterpret_cast<double*>(smem + L.tw);
+  float* svb = reinterpret_cast<float*>(smem + L.sv);   // PRESEL: soft vertex adjoints
+  float* seb = reinterpret_cast<float*>(smem + L.se);   // PRESEL: soft edge endpoint adjoints
+  int* selI = reinterpret_cast<int*>(smem + L.si);
+  float* mbar = reinterpret_cast<float*>(smem + L.mb);  // PRESEL: metric adjoints, A's vertices then B's
+  double* sK = reinterpret_cast<double*>(smem + L.sk);
+  const bool safeguard = PRESEL && (prm.flags & CM_FLAG_SAFEGUARD);
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   constexpr int NW = BLOCK / 64;
@@ -94,8 +121,13 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
     }
     const BodyView& A = P.A;
     const BodyView& B = P.B;
-    const int nvA = A.nv, nvB = B.nv, neA = A.ne, neB = B.ne, nfA = A.nf, nfB = B.nf;
+    // mesh counts (pre-selection shrinks A.nv ... to the selection sizes)
+    const int nvA_m = A.nv, nvB_m = B.nv, nfA = A.nf, nfB = B.nf;
     for (int i = tid; i < 3 * maxV; i += BLOCK) { vA3[i] = 0.f; vB3[i] = 0.f; }
+    if (PRESEL) {
+      for (int i = tid; i < 2 * CM_MAX_PRESEL * 9; i += BLOCK) (i < 6 * CM_MAX_PRESEL ? svb[i] : seb[i - 6 * CM_MAX_PRESEL]) = 0.f;
+      for (int i = tid; i < 2 * maxV; i += BLOCK) mbar[i] = 0.f;
+    }
     for (int i = tid; i < 4 * maxF; i += BLOCK) { plA[i] = 0.f; plB[i] = 0.f; }
     for (int i = tid; i < maxE; i += BLOCK) { rbar[i] = 0.f; cbar[i] = 0.f; }
     if (tid < 8) prA[tid] = 0.f;
@@ -107,7 +139,10 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
 
     // ------------------------------------------------ recompute the forward
     P.stage();
+    if (PRESEL) P.select(selI);
     P.cull();
+    // candidate-space counts (the selection sizes under pre-selection)
+    const int nvA = A.nv, neB = B.ne;
     double tk[KMAX];
     P.scores(tk);
     P.topk(tk);
@@ -202,6 +237,26 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
       __syncthreads();
     }
 
+    // endpoint adjoints of edge pair (k, l): to the mesh vertices, or to the
+    // soft edges under pre-selection
+    auto edge_adj = [&](int k, int l, const D3& va0, const D3& va1, const D3& vb0, const D3& vb1) {
+      if (PRESEL) {
+        float* a = seb + 6 * k;
+        float* b = seb + 6 * (CM_MAX_PRESEL + l);
+        atomicAdd(&a[0], float(va0.x)); atomicAdd(&a[1], float(va0.y)); atomicAdd(&a[2], float(va0.z));
+        atomicAdd(&a[3], float(va1.x)); atomicAdd(&a[4], float(va1.y)); atomicAdd(&a[5], float(va1.z));
+        atomicAdd(&b[0], float(vb0.x)); atomicAdd(&b[1], float(vb0.y)); atomicAdd(&b[2], float(vb0.z));
+        atomicAdd(&b[3], float(vb1.x)); atomicAdd(&b[4], float(vb1.y)); atomicAdd(&b[5], float(vb1.z));
+        return;
+      }
+      const int ia0 = tb.e0[P.GA->e_off + k], ia1 = tb.e1[P.GA->e_off + k];
+      const int ib0 = tb.e0[P.GB->e_off + l], ib1 = tb.e1[P.GB->e_off + l];
+      atomicAdd(&vA3[ia0], float(va0.x)); atomicAdd(&vA3[maxV + ia0], float(va0.y)); atomicAdd(&vA3[2 * maxV + ia0], float(va0.z));
+      atomicAdd(&vA3[ia1], float(va1.x)); atomicAdd(&vA3[maxV + ia1], float(va1.y)); atomicAdd(&vA3[2 * maxV + ia1], float(va1.z));
+      atomicAdd(&vB3[ib0], float(vb0.x)); atomicAdd(&vB3[maxV + ib0], float(vb0.y)); atomicAdd(&vB3[2 * maxV + ib0], float(vb0.z));
+      atomicAdd(&vB3[ib1], float(vb1.x)); atomicAdd(&vB3[maxV + ib1], float(vb1.y)); atomicAdd(&vB3[2 * maxV + ib1], float(vb1.z));
+    };
+
     // ------------------------------------------------ A2: per-candidate adjoints
     P.for_filtered([&](int tot) {
       if (wave * 64 >= tot) return;        // whole wave idle (uniform)
@@ -236,7 +291,8 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
       int k = 0, l = 0, wit = 0;
       if (is_vs) {
         const bool ofA = idx < nvA;
-        const D3 x = ofA ? P.template vertex<true>(*P.GA, idx, A) : P.template vertex<false>(*P.GB, idx - nvA, B);
+        const D3 x = PRESEL ? P.soft_vertex(idx)
+                            : (ofA ? P.template vertex<true>(*P.GA, idx, A) : P.template vertex<false>(*P.GB, idx - nvA, B));
         const double sgn = ofA ? -1.0 : 1.0;
         double phi;
         D3 g;
@@ -272,19 +328,25 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
         dbar = sqrt(dsq);
         rho = 1.0 / sqrt(dsq + P.eps_n);
         const D3 nb = scl(de, rho);
-        double phiB1, phiA2, dum;
+        double phiB1, phiA2, dum, phiA1 = 0.0, phiB2 = 0.0;
         D3 gA, gB, dg;
         sdf_body<kValue, false>(B, e1, T, phiB1, dg);
-        sdf_body<kSurfGrad, true>(A, e1, T, dum, gA);
         sdf_body<kValue, true>(A, e2, T, phiA2, dg);
-        sdf_body<kSurfGrad, false>(B, e2, T, dum, gB);
+        if (PRESEL) {   // soft edges need not lie on their own bodies: full queries
+          sdf_body<kFull, true>(A, e1, T, phiA1, gA);
+          sdf_body<kFull, false>(B, e2, T, phiB2, gB);
+        } else {
+          sdf_body<kSurfGrad, true>(A, e1, T, dum, gA);
+          sdf_body<kSurfGrad, false>(B, e2, T, dum, gB);
+        }
         const double u1 = dot(gB, nb), u2 = -dot(gA, nb), ucl = -dot(gA, gB);
         const double gam1 = tanh64(u1, T), gam2 = tanh64(u2, T);
         const double gam = wit ? gam2 : gam1;
         const double lcl = lsig(ucl, T);
         const double lp = wit ? lsig(-phiA2, T) : lsig(-phiB1, T);
         const double lse = wit ? P.sCol[l] : P.sRow[k];
-        const double lw = q.log_con + lcl + lp + (lse - dbar) * T.inv_tau;
+        const double lsg = safeguard ? lsig(-phiA1, T) + lsig(-phiB2, T) : 0.0;
+        const double lw = q.log_con + lcl + lp + lsg + (lse - dbar) * T.inv_tau;
         const double w = exp(lw);
         const double dtot = fb[6] - sb, lwb = T.tau * sb + w * fb[7];
         taub += sb * lw;
@@ -301,6 +363,14 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
         lsig_d(wit ? -phiA2 : -phiB1, T, du, dt);
         const double phb = -lwb * du;
         taub += lwb * dt;
+        if (safeguard) {   // inside indicators of the soft witnesses on their own bodies
+          lsig_d(-phiA1, T, du, dt);
+          phib[0] = -lwb * du;
+          taub += lwb * dt;
+          lsig_d(-phiB2, T, du, dt);
+          phib[3] = -lwb * du;
+          taub += lwb * dt;
+        }
         if (live) atomicAdd(wit ? &cbar[l] : &rbar[k], float(lwb * T.inv_tau));
         dbarb -= lwb * T.inv_tau;
         taub -= lwb * (lse - dbar) * T.inv_tau * T.inv_tau;
@@ -330,11 +400,16 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
       if (is_vs) {
         const bool ofA = idx < nvA;
         const D3 xb = add(pb, ofA ? xb1 : xb0);
-        float* V = ofA ? vA3 : vB3;
         const int i = ofA ? idx : idx - nvA;
-        atomicAdd(&V[i], float(xb.x));
-        atomicAdd(&V[maxV + i], float(xb.y));
-        atomicAdd(&V[2 * maxV + i], float(xb.z));
+        if (PRESEL) {
+          float* V = svb + 3 * ((ofA ? 0 : CM_MAX_PRESEL) + i);
+          atomicAdd(&V[0], float(xb.x)); atomicAdd(&V[1], float(xb.y)); atomicAdd(&V[2], float(xb.z));
+        } else {
+          float* V = ofA ? vA3 : vB3;
+          atomicAdd(&V[i], float(xb.x));
+          atomicAdd(&V[maxV + i], float(xb.y));
+          atomicAdd(&V[2 * maxV + i], float(xb.z));
+        }
       } else {
         const double dn = dot(de, nbb);
         D3 deb = sub(scl(nbb, rho), scl(de, rho * rho * rho * dn));
@@ -344,13 +419,7 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
         if (!wit) e1b = add(e1b, pb); else e2b = add(e2b, pb);
         D3 a0b = e1b, t1b = scl(e1b, al1), b0b = e2b, t2b = scl(e2b, al2);
         ee_qp_bwd(a0, t1, b0, t2, P.lam, T, dot(e1b, t1), dot(e2b, t2), lcb, a0b, t1b, b0b, t2b, taub);
-        const int ia0 = tb.e0[P.GA->e_off + k], ia1 = tb.e1[P.GA->e_off + k];
-        const int ib0 = tb.e0[P.GB->e_off + l], ib1 = tb.e1[P.GB->e_off + l];
-        const D3 va0 = sub(a0b, t1b), vb0 = sub(b0b, t2b);
-        atomicAdd(&vA3[ia0], float(va0.x)); atomicAdd(&vA3[maxV + ia0], float(va0.y)); atomicAdd(&vA3[2 * maxV + ia0], float(va0.z));
-        atomicAdd(&vA3[ia1], float(t1b.x)); atomicAdd(&vA3[maxV + ia1], float(t1b.y)); atomicAdd(&vA3[2 * maxV + ia1], float(t1b.z));
-        atomicAdd(&vB3[ib0], float(vb0.x)); atomicAdd(&vB3[maxV + ib0], float(vb0.y)); atomicAdd(&vB3[2 * maxV + ib0], float(vb0.z));
-        atomicAdd(&vB3[ib1], float(t2b.x)); atomicAdd(&vB3[maxV + ib1], float(t2b.y)); atomicAdd(&vB3[2 * maxV + ib1], float(t2b.z));
+        edge_adj(k, l, sub(a0b, t1b), t1b, sub(b0b, t2b), t2b);
       }
     }, kAdjointTaus);
     __syncthreads();
@@ -380,16 +449,145 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
         const D3 deb = scl(q.de, Db / D);
         D3 a0b = deb, t1b = scl(deb, q.al1), b0b = scl(deb, -1.0), t2b = scl(deb, -q.al2);
         ee_qp_bwd(a0, t1, b0, t2, P.lam, T, dot(deb, t1), -dot(deb, t2), 0.0, a0b, t1b, b0b, t2b, taub);
-        const int ia0 = tb.e0[P.GA->e_off + k], ia1 = tb.e1[P.GA->e_off + k];
-        const int ib0 = tb.e0[P.GB->e_off + l], ib1 = tb.e1[P.GB->e_off + l];
-        const D3 va0 = sub(a0b, t1b), vb0 = sub(b0b, t2b);
-        atomicAdd(&vA3[ia0], float(va0.x)); atomicAdd(&vA3[maxV + ia0], float(va0.y)); atomicAdd(&vA3[2 * maxV + ia0], float(va0.z));
-        atomicAdd(&vA3[ia1], float(t1b.x)); atomicAdd(&vA3[maxV + ia1], float(t1b.y)); atomicAdd(&vA3[2 * maxV + ia1], float(t1b.z));
-        atomicAdd(&vB3[ib0], float(vb0.x)); atomicAdd(&vB3[maxV + ib0], float(vb0.y)); atomicAdd(&vB3[2 * maxV + ib0], float(vb0.z));
-        atomicAdd(&vB3[ib1], float(t2b.x)); atomicAdd(&vB3[maxV + ib1], float(t2b.y)); atomicAdd(&vB3[2 * maxV + ib1], float(t2b.z));
+        edge_adj(k, l, sub(a0b, t1b), t1b, sub(b0b, t2b), t2b);
       }
     }
     __syncthreads();
+
+    // ------------------------------------------------ S: selection adjoint
+    // Soft item k of a set is sum_i (w_ki / S_k) p_i with w_ki =
+    // exp(-|x_[k] - x_i| / tau), x_i = -metric_i, S_k = sum_i w_ki, and
+    // x_[k] = x_{j_k} for the item j_k the hard top-K picked.  With g_k the
+    // item's adjoint and c_ki = (w_ki / S_k) g_k . (p_i - soft_k):
+    //   p_i      += (w_ki / S_k) g_k
+    //   x_i      += c_ki sign(x_[k] - x_i) / tau
+    //   x_{j_k}  -= sum_i c_ki sign(x_[k] - x_i) / tau
+    //   tau      += c_ki |x_[k] - x_i| / tau^2
+    // and metric_bar = -x_bar; an edge's metric is the mean of its corners'.
+    if (PRESEL) {
+      const int Kv[2] = {P.A.nv, P.B.nv}, Ke[2] = {P.A.ne, P.B.ne};
+      const int nItems = Kv[0] + Kv[1] + Ke[0] + Ke[1];
+      const double* mVA = P.sMet;
+      const double* mEA = P.sMet + 2 * maxV;
+      // decode a flat index over the four sets (A's vertices, B's, A's edges, B's)
+      auto set_of = [&](int t, const int* cnt, int& set, int& k) {
+        set = 0; k = t;
+        while (set < 3 && k >= cnt[set]) { k -= cnt[set]; ++set; }
+      };
+      const int cntK[4] = {Kv[0], Kv[1], Ke[0], Ke[1]};
+      const int cntD[4] = {nvA_m, nvB_m, P.GA->ne, P.GB->ne};
+      // position of element i of a set (a vertex: 3 values, an edge: its two corners)
+      auto pos = [&](int set, int i, double* p) {
+        if (set == 0 || set == 1) {
+          const D3 v = set == 0 ? P.template vertex<true>(*P.GA, i, A) : P.template vertex<false>(*P.GB, i, B);
+          p[0] = v.x; p[1] = v.y; p[2] = v.z;
+        } else {
+          const GeomRec& G = set == 2 ? *P.GA : *P.GB;
+          const int c0 = tb.e0[G.e_off + i], c1 = tb.e1[G.e_off + i];
+          const D3 v0 = set == 2 ? P.template vertex<true>(G, c0, A) : P.template vertex<false>(G, c0, B);
+          const D3 v1 = set == 2 ? P.template vertex<true>(G, c1, A) : P.template vertex<false>(G, c1, B);
+          p[0] = v0.x; p[1] = v0.y; p[2] = v0.z; p[3] = v1.x; p[4] = v1.y; p[5] = v1.z;
+        }
+      };
+      auto metric = [&](int set, int i) { return set < 2 ? mVA[set * maxV + i] : mEA[(set - 2) * maxE + i]; };
+      auto item_adj = [&](int set, int k) -> const float* {
+        return set < 2 ? svb + 3 * (set * CM_MAX_PRESEL + k) : seb + 6 * ((set - 2) * CM_MAX_PRESEL + k);
+      };
+      auto item_val = [&](int set, int k) -> const double* {
+        return set < 2 ? P.sSoft + 3 * (set * CM_MAX_PRESEL + k)
+                       : P.sSoft + 2 * CM_MAX_PRESEL * 3 + 6 * ((set - 2) * CM_MAX_PRESEL + k);
+      };
+      // metric adjoint of element i of a set onto the vertex metrics
+      auto add_metric = [&](int set, int i, double xb) {
+        if (set < 2) {
+          atomicAdd(&mbar[set * maxV + i], float(-xb));
+        } else {
+          const GeomRec& G = set == 2 ? *P.GA : *P.GB;
+          float* mb = mbar + (set - 2) * maxV;
+          atomicAdd(&mb[tb.e0[G.e_off + i]], float(-0.5 * xb));
+          atomicAdd(&mb[tb.e1[G.e_off + i]], float(-0.5 * xb));
+        }
+      };
+      // S1: one thread per soft item: S_k, g_k . soft_k, and the x_[k] / tau terms
+      if (tid < nItems) {
+        int set, k;
+        set_of(tid, cntK, set, k);
+        const int D = cntD[set], nc = set < 2 ? 3 : 6;
+        const double xk = P.sSel[set * CM_MAX_PRESEL + k];
+        const float* g = item_adj(set, k);
+        const double* sv = item_val(set, k);
+        double Sk = 0.0, gs = 0.0;
+        for (int i = 0; i < D; ++i) Sk += exp64n(-fabs(xk + metric(set, i)) * T.inv_tau);
+        for (int c = 0; c < nc; ++c) gs += double(g[c]) * sv[c];
+        const double iS = 1.0 / Sk;
+        double xkb = 0.0, tb_ = 0.0;
+        for (int i = 0; i < D; ++i) {
+          const double dl = xk + metric(set, i);
+          const double wn = exp64n(-fabs(dl) * T.inv_tau) * iS;
+          double p[6];
+          pos(set, i, p);
+          double gp = 0.0;
+          for (int c = 0; c < nc; ++c) gp += double(g[c]) * p[c];
+          const double cki = wn * (gp - gs);
+          xkb -= cki * (dl > 0.0 ? 1.0 : (dl < 0.0 ? -1.0 : 0.0)) * T.inv_tau;
+          tb_ += cki * fabs(dl) * T.inv_tau * T.inv_tau;
+        }
+        taub += tb_;
+        sK[set * CM_MAX_PRESEL + k] = iS;
+        sK[4 * CM_MAX_PRESEL + set * CM_MAX_PRESEL + k] = gs;
+        add_metric(set, selI[set * CM_MAX_PRESEL + k], xkb);
+      }
+      __syncthreads();
+      // S2: one thread per set element: position and x_i adjoints
+      const int nElem = cntD[0] + cntD[1] + cntD[2] + cntD[3];
+      for (int t = tid; t < nElem; t += BLOCK) {
+        int set, i;
+        set_of(t, cntD, set, i);
+        const int Ks = cntK[set], nc = set < 2 ? 3 : 6;
+        const double xi = -metric(set, i);
+        double p[6], pb[6] = {0, 0, 0, 0, 0, 0}, xib = 0.0;
+        pos(set, i, p);
+        for (int k = 0; k < Ks; ++k) {
+          const double dl = P.sSel[set * CM_MAX_PRESEL + k] - xi;
+          const double wn = exp64n(-fabs(dl) * T.inv_tau) * sK[set * CM_MAX_PRESEL + k];
+          const float* g = item_adj(set, k);
+          double gp = 0.0;
+          for (int c = 0; c < nc; ++c) { gp += double(g[c]) * p[c]; pb[c] = fma(wn, double(g[c]), pb[c]); }
+          const double cki = wn * (gp - sK[4 * CM_MAX_PRESEL + set * CM_MAX_PRESEL + k]);
+          xib += cki * (dl > 0.0 ? 1.0 : (dl < 0.0 ? -1.0 : 0.0)) * T.inv_tau;
+        }
+        add_metric(set, i, xib);
+        if (set == 0 || set == 1) {
+          float* V = set == 0 ? vA3 : vB3;
+          atomicAdd(&V[i], float(pb[0])); atomicAdd(&V[maxV + i], float(pb[1])); atomicAdd(&V[2 * maxV + i], float(pb[2]));
+        } else {
+          const GeomRec& G = set == 2 ? *P.GA : *P.GB;
+          float* V = set == 2 ? vA3 : vB3;
+          const int c0 = tb.e0[G.e_off + i], c1 = tb.e1[G.e_off + i];
+          atomicAdd(&V[c0], float(pb[0])); atomicAdd(&V[maxV + c0], float(pb[1])); atomicAdd(&V[2 * maxV + c0], float(pb[2]));
+          atomicAdd(&V[c1], float(pb[3])); atomicAdd(&V[maxV + c1], float(pb[4])); atomicAdd(&V[2 * maxV + c1], float(pb[5]));
+        }
+      }
+      __syncthreads();
+      // S3: the metrics are SDF queries of the other body at every mesh
+      // vertex; whole waves per block of 64 vertices (the plane adjoints are
+      // summed across the wave)
+      for (int base = wave * 64; base < nvA_m; base += BLOCK) {
+        const int v = base + lane;
+        const bool live = v < nvA_m;
+        const D3 x = P.template vertex<true>(*P.GA, live ? v : 0, A);
+        const D3 xb = sdf_body_bwd<true, false>(B, x, live ? double(mbar[v]) : 0.0, d3(0, 0, 0), T, sinkB, taub, tw);
+        if (live) { atomicAdd(&vA3[v], float(xb.x)); atomicAdd(&vA3[maxV + v], float(xb.y)); atomicAdd(&vA3[2 * maxV + v], float(xb.z)); }
+      }
+      for (int base = wave * 64; base < nvB_m; base += BLOCK) {
+        const int v = base + lane;
+        const bool live = v < nvB_m;
+        const D3 x = P.template vertex<false>(*P.GB, live ? v : 0, B);
+        const D3 xb = sdf_body_bwd<true, true>(A, x, live ? double(mbar[maxV + v]) : 0.0, d3(0, 0, 0), T, sinkA, taub, tw);
+        if (live) { atomicAdd(&vB3[v], float(xb.x)); atomicAdd(&vB3[maxV + v], float(xb.y)); atomicAdd(&vB3[2 * maxV + v], float(xb.z)); }
+      }
+      __syncthreads();
+    }
 
     // ------------------------------------------------ G: geometry and pose gradients
     // face planes -> hull vertices (body frames)
@@ -421,9 +619,9 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
       }
     }
     // mesh vertices -> hull vertices / analytic parameters, and B's placement twist
-    for (int i = tid; i < nvA + nvB; i += BLOCK) {
-      const bool isA = i < nvA;
-      const int v = isA ? i : i - nvA;
+    for (int i = tid; i < nvA_m + nvB_m; i += BLOCK) {
+      const bool isA = i < nvA_m;
+      const int v = isA ? i : i - nvA_m;
       const GeomRec& G = isA ? *P.GA : *P.GB;
       const float* V = isA ? vA3 : vB3;
       D3 gb = d3(V[v], V[maxV + v], V[2 * maxV + v]);   // pair frame
@@ -503,38 +701,53 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
   }
 }
 
-int bwd_lds_bytes(int maxV, int maxE, int maxF, int block) {
-  const int extra = bwd_extra_bytes(maxV, maxE, maxF, block);
-  return bwd_layout(lds_layout(maxE, maxF, block, extra).bytes, maxV, maxE, maxF, block).bytes;
+int bwd_lds_bytes(int maxV, int maxE, int maxF, int block, bool presel) {
+  const int extra = bwd_extra_bytes(maxV, maxE, maxF, block, presel);
+  const int pre = presel ? presel_lds_bytes(maxV, maxE) : 0;
+  return bwd_layout(lds_layout(maxE, maxF, block, extra).bytes + pre, maxV, maxE, maxF, block, presel).bytes;
 }
 
-template <int BLOCK, int KMAX>
+template <int BLOCK, int KMAX, bool PRESEL>
 static hipError_t launch_bwd_t(const BwdLaunch& b, hipStream_t st) {
-  const int lds = bwd_lds_bytes(b.f.maxV, b.f.maxE, b.f.maxF, BLOCK);
+  const int lds = bwd_lds_bytes(b.f.maxV, b.f.maxE, b.f.maxF, BLOCK, PRESEL);
   BwdArgs ga{b.cot, b.gr};
-  hipLaunchKernelGGL((collide_bwd<BLOCK, KMAX>), dim3(b.f.grid), dim3(BLOCK), lds, st, b.f.tb, b.f.bt, b.f.prm, b.f.out,
-                     ga, b.f.scratch, b.f.scratch_stride, b.f.maxV, b.f.maxE, b.f.maxF, b.f.err);
+  hipLaunchKernelGGL((collide_bwd<BLOCK, KMAX, PRESEL>), dim3(b.f.grid), dim3(BLOCK), lds, st, b.f.tb, b.f.bt, b.f.prm,
+                     b.f.out, ga, b.f.scratch, b.f.scratch_stride, b.f.maxV, b.f.maxE, b.f.maxF, b.f.err);
   return hipGetLastError();
 }
 
-template <int BLOCK, int KMAX>
+template <int BLOCK, int KMAX, bool PRESEL>
 static int bwd_occ_t(const BwdLaunch& b) {
   int nb = 0;
-  const int lds = bwd_lds_bytes(b.f.maxV, b.f.maxE, b.f.maxF, BLOCK);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, collide_bwd<BLOCK, KMAX>, BLOCK, lds) != hipSuccess) return 1;
+  const int lds = bwd_lds_bytes(b.f.maxV, b.f.maxE, b.f.maxF, BLOCK, PRESEL);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, collide_bwd<BLOCK, KMAX, PRESEL>, BLOCK, lds) != hipSuccess)
+    return 1;
   return nb > 0 ? nb : 1;
 }
 
+// Pre-selection runs in its own instantiations (the selection tracks taken
+// items in a 64-bit mask per lane: <= 4096 per set).
 hipError_t launch_collide_bwd(const BwdLaunch& b, hipStream_t st) {
-  if (b.f.kmax == 8) return launch_bwd_t<256, 8>(b, st);
-  if (b.f.kmax == 16) return launch_bwd_t<256, 16>(b, st);
-  return launch_bwd_t<256, 32>(b, st);
+  if (b.f.prm.presel_v > 0) {
+    if (b.f.maxV > 4096 || b.f.maxE > 4096) return hipErrorInvalidValue;
+    if (b.f.kmax == 8) return launch_bwd_t<256, 8, true>(b, st);
+    if (b.f.kmax == 16) return launch_bwd_t<256, 16, true>(b, st);
+    return launch_bwd_t<256, 32, true>(b, st);
+  }
+  if (b.f.kmax == 8) return launch_bwd_t<256, 8, false>(b, st);
+  if (b.f.kmax == 16) return launch_bwd_t<256, 16, false>(b, st);
+  return launch_bwd_t<256, 32, false>(b, st);
 }
 
 int bwd_occupancy(const BwdLaunch& b) {
-  if (b.f.kmax == 8) return bwd_occ_t<256, 8>(b);
-  if (b.f.kmax == 16) return bwd_occ_t<256, 16>(b);
-  return bwd_occ_t<256, 32>(b);
+  if (b.f.prm.presel_v > 0) {
+    if (b.f.kmax == 8) return bwd_occ_t<256, 8, true>(b);
+    if (b.f.kmax == 16) return bwd_occ_t<256, 16, true>(b);
+    return bwd_occ_t<256, 32, true>(b);
+  }
+  if (b.f.kmax == 8) return bwd_occ_t<256, 8, false>(b);
+  if (b.f.kmax == 16) return bwd_occ_t<256, 16, false>(b);
+  return bwd_occ_t<256, 32, false>(b);
 }
 
 }  // namespace cm

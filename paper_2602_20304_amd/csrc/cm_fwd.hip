@@ -185,7 +185,6 @@ void collide_fwd(Tables tb, BatchDev bt, ParamsDev prm, OutDev out,
       // outputs: divide by row sums, rotate to world
       for (int kk = tid; kk < K; kk += BLOCK) {
         const double* a = P.sAcc + 9 * kk;
-        // a row with no candidate (fewer candidates than K) is empty
         // a row with no candidate (fewer candidates than K) is all zeros
         const bool live = a[0] > 0.0;
         const double inv = live ? 1.0 / a[0] : 0.0;

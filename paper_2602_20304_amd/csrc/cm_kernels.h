@@ -55,7 +55,7 @@ struct BwdLaunch {
 };
 
 int fwd_lds_bytes(int maxV, int maxE, int maxF, int block, int kmax, bool presel = false);
-int bwd_lds_bytes(int maxV, int maxE, int maxF, int block);
+int bwd_lds_bytes(int maxV, int maxE, int maxF, int block, bool presel = false);
 int bwd_occupancy(const BwdLaunch& b);
 hipError_t launch_collide_bwd(const BwdLaunch& b, hipStream_t st);
 int fwd_occupancy(const FwdLaunch& f);

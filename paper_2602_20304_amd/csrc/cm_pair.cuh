@@ -314,7 +314,9 @@ struct PairEngine {
   // weights exp(-|x_[k] - x_i| / tau) (one thread per selected item; float64
   // exponentials, as the weights move geometry).  The soft edges then replace
   // the staged edges and the counts shrink to the selection sizes.
-  __device__ void select() {
+  // sel_idx (optional, [4][CM_MAX_PRESEL]): receives the index within its set
+  // of the item whose value is x_[k] (the adjoint routes x_[k]'s gradient there).
+  __device__ void select(int* sel_idx = nullptr) {
     const int nvA = A.nv, nvB = B.nv, neA = A.ne, neB = B.ne;
     double* mVA = sMet;
     double* mVB = sMet + maxV;
@@ -351,7 +353,10 @@ struct PairEngine {
         }
         const double wm = wave_max(best);
         const unsigned long long ball = __ballot(bj >= 0 && best == wm);
-        if (lane == __ffsll((long long)ball) - 1) taken |= 1ull << bj;
+        if (lane == __ffsll((long long)ball) - 1) {
+          taken |= 1ull << bj;
+          if (sel_idx) sel_idx[set * CM_MAX_PRESEL + r] = lane + 64 * bj;
+        }
         if (lane == 0) sSel[set * CM_MAX_PRESEL + r] = wm;
       }
     }
@@ -502,11 +507,15 @@ struct PairEngine {
   }
 
   // ------------------------------------------------------------ candidates
+  // soft vertex i of the selection (A's first, then B's), pair frame
+  __device__ __forceinline__ D3 soft_vertex(int i) const {
+    const double* v = sSoft + 3 * (i < A.nv ? i : CM_MAX_PRESEL + (i - A.nv));
+    return d3(v[0], v[1], v[2]);
+  }
   __device__ __forceinline__ void vs(int i, Cand& c) const {
     if (PRESEL) {
-      const double* v = sSoft + 3 * (i < A.nv ? i : CM_MAX_PRESEL + (i - A.nv));
-      if (i < A.nv) vs_candidate<false>(d3(v[0], v[1], v[2]), B, -1.0, T, c);
-      else vs_candidate<true>(d3(v[0], v[1], v[2]), A, 1.0, T, c);
+      if (i < A.nv) vs_candidate<false>(soft_vertex(i), B, -1.0, T, c);
+      else vs_candidate<true>(soft_vertex(i), A, 1.0, T, c);
       return;
     }
     if (i < A.nv) vs_candidate<false>(vertex<true>(*GA, i, A), B, -1.0, T, c);

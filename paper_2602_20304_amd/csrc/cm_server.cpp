@@ -268,8 +268,8 @@ cm_status cm_server_submit(cm_server* srv, const cm_request* q, uint64_t* ticket
     return CM_ERR_INVALID_ARG;
   const bool presel = q->params.presel_vertices != 0 || q->params.presel_edges != 0;
   if (presel && (q->params.presel_vertices < 1 || q->params.presel_vertices > CM_MAX_PRESEL ||
-                 q->params.presel_edges < 1 || q->params.presel_edges > CM_MAX_PRESEL || q->want_backward))
-    return CM_ERR_INVALID_ARG;   // pre-selection: forward requests only
+                 q->params.presel_edges < 1 || q->params.presel_edges > CM_MAX_PRESEL))
+    return CM_ERR_INVALID_ARG;
   if ((q->params.flags & CM_FLAG_SAFEGUARD) && !presel) return CM_ERR_INVALID_ARG;
   auto r = std::make_unique<Request>();
   r->n_scenes = q->n_scenes;

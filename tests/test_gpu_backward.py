@@ -27,11 +27,11 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def gpu_grads(ctx, batch, seed=0, flags=0):
-    _say(f"[gpu-bwd] {batch.name} scenes={batch.n_scenes} tau={batch.tau} K={batch.K} flags={flags}")
+def gpu_grads(ctx, batch, seed=0, flags=0, presel=None):
+    _say(f"[gpu-bwd] {batch.name} scenes={batch.n_scenes} tau={batch.tau} K={batch.K} flags={flags} presel={presel}")
     ids = ctx.create_geometry(batch.geoms)
     db = ctx.upload_batch(batch, ids)
-    m = ctx.collide(db, batch.tau, batch.K, flags=flags)
+    m = ctx.collide(db, batch.tau, batch.K, flags=flags, presel=presel)
     ctx.check_errors()
     n = int(m.n_pairs.item())
     K = batch.K
@@ -40,13 +40,13 @@ def gpu_grads(ctx, batch, seed=0, flags=0):
     cot = {k: rng.standard_normal(s).astype(np.float32) for k, s in
            (("p", (3, cap * K)), ("nu", (3, cap * K)), ("d", (cap * K,)), ("w", (cap * K,)))}
     tt = {k: torch.as_tensor(v).to(ctx.device) for k, v in cot.items()}
-    g = ctx.collide_backward(db, m, batch.tau, K, tt["p"], tt["nu"], tt["d"], tt["w"], flags=flags)
+    g = ctx.collide_backward(db, m, batch.tau, K, tt["p"], tt["nu"], tt["d"], tt["w"], flags=flags, presel=presel)
     ctx.check_errors()
     out = {k: (v.cpu().numpy() if v is not None else None) for k, v in g.items()}
     return ids, m.to_numpy(), cot, out, n
 
 
-def oracle_grads(batch, pairs, cot, K, flags=0):
+def oracle_grads(batch, pairs, cot, K, flags=0, presel=None):
     cache = O.GeomCache(batch.geoms, requires_grad=True)
     nb = batch.n_bodies
     g_pose = np.zeros((6, nb))
@@ -58,7 +58,7 @@ def oracle_grads(batch, pairs, cot, K, flags=0):
         sl = slice(i * K, (i + 1) * K)
         c = dict(p=cot["p"][:, sl].T, nu=cot["nu"][:, sl].T, d=cot["d"][sl], w=cot["w"][sl])
         r = O.pair_grad(GA, batch.pose[:, a], GB, batch.pose[:, b], batch.tau, K, c, no_ee=bool(flags & 1),
-                        one_sided_vs=bool(flags & 2))
+                        one_sided_vs=bool(flags & 2), presel=presel, safeguard=bool(flags & 4))
         g_pose[:, a] += r["xiA"]
         g_pose[:, b] += r["xiB"]
         ga, gb = int(batch.body_geom[a]), int(batch.body_geom[b])
@@ -77,10 +77,10 @@ def close(got, ref, rtol=GRAD_RTOL):
     return float(err.max()) if err.size else -1.0, float(np.max(np.abs(got - ref))) if err.size else 0.0, scale
 
 
-def check(ctx, batch, seed=0, flags=0):
-    ids, fwd, cot, g, n = gpu_grads(ctx, batch, seed, flags)
+def check(ctx, batch, seed=0, flags=0, presel=None):
+    ids, fwd, cot, g, n = gpu_grads(ctx, batch, seed, flags, presel)
     pairs = fwd["pairs"]
-    g_pose, g_geom, g_tau, cache = oracle_grads(batch, pairs, cot, batch.K, flags)
+    g_pose, g_geom, g_tau, cache = oracle_grads(batch, pairs, cot, batch.K, flags, presel)
     rep = {}
     rep["pose"] = close(g["pose"], g_pose)
     vx, vr, pr_g, pr_r = [], [], [], []
@@ -174,3 +174,21 @@ def test_backward_fewer_candidates_than_K(ctx):
     b = W.cube_pairs(16, seed=25, K=12)
     b.pose[4:7] += np.array([[0.3], [-0.2], [0.5]], dtype=b.pose.dtype)   # body A off the origin
     check(ctx, b, flags=3)
+
+
+# ---- through soft top-K pre-selection: the gradient also runs through the
+# SoftSort selection weights into every vertex's penetration metric
+
+@pytest.mark.parametrize("presel", [(8, 12), (3, 5)])
+def test_backward_presel_mixed(ctx, presel):
+    check(ctx, W.mixed_scenes(6, seed=26, poly_points=16, tau=0.01), presel=presel)
+
+
+def test_backward_presel_polytopes_safeguard(ctx):
+    check(ctx, W.polytope_scenes(2, seed=27, n_points=24, tau=0.02), flags=4, presel=(6, 10))
+
+
+def test_backward_presel_with_simplifications(ctx):
+    b = W.cube_pairs(16, seed=28, K=12)
+    b.pose[4:7] += np.array([[0.3], [-0.2], [0.5]], dtype=b.pose.dtype)   # body A off the origin
+    check(ctx, b, flags=2, presel=(4, 6))

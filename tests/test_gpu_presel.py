@@ -113,4 +113,41 @@ def test_presel_rejected_where_unsupported(ctx):
     m = ctx.collide(db, b.tau, b.K, presel=(4, 4))
     g = torch.zeros(m.dist.shape, device=ctx.device)
     with pytest.raises(CMError):
-        ctx.collide_backward(db, m, b.tau, b.K, None, None, g, None, presel=(4, 4))
+        ctx.collide_backward(db, m, b.tau, b.K, None, None, g, None, presel=(4, 65))
+    with pytest.raises(CMError):
+        ctx.collide_backward(db, m, b.tau, b.K, None, None, g, None, flags=4)
+
+
+def test_presel_served_backward_matches_direct(ctx):
+    """A served request with pre-selection and a backward pass returns the
+    same pose gradient as the direct forward + adjoint calls."""
+    import time
+    import torch
+    from paper_2602_20304_amd.cm import Server
+    b = W.mixed_scenes(24, seed=67)
+    ids = ctx.create_geometry(b.geoms)
+    db = ctx.upload_batch(b, ids)
+    presel = (6, 10)
+    _say(f"[gpu-presel] served backward presel={presel} scenes={b.n_scenes}")
+    m = ctx.collide(db, b.tau, b.K, presel=presel)
+    cap, K = m.capacity, b.K
+    rng = np.random.default_rng(5)
+    cd = rng.standard_normal(cap * K).astype(np.float32)
+    cn = rng.standard_normal(3 * cap * K).astype(np.float32)
+    g = ctx.collide_backward(db, m, b.tau, K, None, torch.as_tensor(cn).to(ctx.device),
+                             torch.as_tensor(cd).to(ctx.device), None, want_vertices=False, want_params=False,
+                             presel=presel)
+    ctx.check_errors()
+    ga = g["pose"].cpu().numpy()
+    srv = Server(ctx, 1 << 32, n_streams=2)
+    t = srv.submit(b.body_offsets, ids[b.body_geom], b.pose, b.tau, K, True, cd, cn, capacity=cap, presel=presel)
+    r = None
+    for _ in range(4000):
+        r = srv.poll(t)
+        if r is not None:
+            break
+        time.sleep(0.005)
+    assert r is not None and r["status"] == 0
+    assert np.abs(r["g_pose"] - ga).max() <= 1e-4 * (np.abs(ga).max() + 1e-6)
+    srv.release(t)
+    srv.close()
