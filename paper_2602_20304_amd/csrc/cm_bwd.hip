@@ -69,6 +69,10 @@ __host__ __device__ inline int bwd_extra_bytes(int maxV, int maxE, int maxF, int
   return bwd_layout(0, maxV, maxE, maxF, block, presel).bytes + 32 + (presel ? presel_lds_bytes(maxV, maxE) : 0);
 }
 
+struct Six {
+  double c[6];
+};
+
 struct BwdArgs {
   CotDev cot;
   GradDev gr;
@@ -239,7 +243,7 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
 
     // endpoint adjoints of edge pair (k, l): to the mesh vertices, or to the
     // soft edges under pre-selection
-    auto edge_adj = [&](int k, int l, const D3& va0, const D3& va1, const D3& vb0, const D3& vb1) {
+    auto edge_adj = [&](int k, int l, const D3& va0, const D3& va1, const D3& vb0, const D3& vb1) __attribute__((always_inline)) {
       if (PRESEL) {
         float* a = seb + 6 * k;
         float* b = seb + 6 * (CM_MAX_PRESEL + l);
@@ -465,40 +469,46 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
     //   tau      += c_ki |x_[k] - x_i| / tau^2
     // and metric_bar = -x_bar; an edge's metric is the mean of its corners'.
     if (PRESEL) {
-      const int Kv[2] = {P.A.nv, P.B.nv}, Ke[2] = {P.A.ne, P.B.ne};
-      const int nItems = Kv[0] + Kv[1] + Ke[0] + Ke[1];
+      const int Kva = P.A.nv, Kvb = P.B.nv, Kea = P.A.ne, Keb = P.B.ne;
+      const int neA_m = P.GA->ne, neB_m = P.GB->ne;
       const double* mVA = P.sMet;
       const double* mEA = P.sMet + 2 * maxV;
-      // decode a flat index over the four sets (A's vertices, B's, A's edges, B's)
-      auto set_of = [&](int t, const int* cnt, int& set, int& k) {
-        set = 0; k = t;
-        while (set < 3 && k >= cnt[set]) { k -= cnt[set]; ++set; }
-      };
-      const int cntK[4] = {Kv[0], Kv[1], Ke[0], Ke[1]};
-      const int cntD[4] = {nvA_m, nvB_m, P.GA->ne, P.GB->ne};
-      // position of element i of a set (a vertex: 3 values, an edge: its two corners)
-      auto pos = [&](int set, int i, double* p) {
-        if (set == 0 || set == 1) {
-          const D3 v = set == 0 ? P.template vertex<true>(*P.GA, i, A) : P.template vertex<false>(*P.GB, i, B);
-          p[0] = v.x; p[1] = v.y; p[2] = v.z;
-        } else {
+      // sets: 0 A's vertices, 1 B's, 2 A's edges, 3 B's (selects, not arrays:
+      // a runtime index into a private array would live in scratch memory)
+      auto nsel = [&](int set) __attribute__((always_inline)) { return set == 0 ? Kva : set == 1 ? Kvb : set == 2 ? Kea : Keb; };
+      auto nall = [&](int set) __attribute__((always_inline)) { return set == 0 ? nvA_m : set == 1 ? nvB_m : set == 2 ? neA_m : neB_m; };
+      // position of element i of a set: a vertex (c[3..5] = 0) or an edge's
+      // two corners (values, not array references: a referenced array stays
+      // in scratch memory)
+      auto pos = [&](int set, int i) __attribute__((always_inline)) -> Six {
+        Six p;
+        int c0 = i, c1 = -1;
+        if (set >= 2) {
           const GeomRec& G = set == 2 ? *P.GA : *P.GB;
-          const int c0 = tb.e0[G.e_off + i], c1 = tb.e1[G.e_off + i];
-          const D3 v0 = set == 2 ? P.template vertex<true>(G, c0, A) : P.template vertex<false>(G, c0, B);
-          const D3 v1 = set == 2 ? P.template vertex<true>(G, c1, A) : P.template vertex<false>(G, c1, B);
-          p[0] = v0.x; p[1] = v0.y; p[2] = v0.z; p[3] = v1.x; p[4] = v1.y; p[5] = v1.z;
+          c0 = tb.e0[G.e_off + i];
+          c1 = tb.e1[G.e_off + i];
         }
+        const bool onA = (set & 1) == 0;
+        const D3 v0 = onA ? P.template vertex<true>(*P.GA, c0, A) : P.template vertex<false>(*P.GB, c0, B);
+        D3 v1 = d3(0, 0, 0);
+        if (c1 >= 0) v1 = onA ? P.template vertex<true>(*P.GA, c1, A) : P.template vertex<false>(*P.GB, c1, B);
+        p.c[0] = v0.x; p.c[1] = v0.y; p.c[2] = v0.z; p.c[3] = v1.x; p.c[4] = v1.y; p.c[5] = v1.z;
+        return p;
       };
-      auto metric = [&](int set, int i) { return set < 2 ? mVA[set * maxV + i] : mEA[(set - 2) * maxE + i]; };
-      auto item_adj = [&](int set, int k) -> const float* {
-        return set < 2 ? svb + 3 * (set * CM_MAX_PRESEL + k) : seb + 6 * ((set - 2) * CM_MAX_PRESEL + k);
-      };
-      auto item_val = [&](int set, int k) -> const double* {
-        return set < 2 ? P.sSoft + 3 * (set * CM_MAX_PRESEL + k)
-                       : P.sSoft + 2 * CM_MAX_PRESEL * 3 + 6 * ((set - 2) * CM_MAX_PRESEL + k);
+      auto metric = [&](int set, int i) __attribute__((always_inline)) { return set < 2 ? mVA[set * maxV + i] : mEA[(set - 2) * maxE + i]; };
+      // adjoint (g) or value (!g) of soft item k (a vertex: entries 3..5 are 0)
+      auto item = [&](int set, int k, bool adj) __attribute__((always_inline)) -> Six {
+        Six r;
+        const bool vert = set < 2;
+        const float* ga = vert ? svb + 3 * (set * CM_MAX_PRESEL + k) : seb + 6 * ((set - 2) * CM_MAX_PRESEL + k);
+        const double* sv = vert ? P.sSoft + 3 * (set * CM_MAX_PRESEL + k)
+                                : P.sSoft + 2 * CM_MAX_PRESEL * 3 + 6 * ((set - 2) * CM_MAX_PRESEL + k);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) r.c[c] = (c < 3 || !vert) ? (adj ? double(ga[c]) : sv[c]) : 0.0;
+        return r;
       };
       // metric adjoint of element i of a set onto the vertex metrics
-      auto add_metric = [&](int set, int i, double xb) {
+      auto add_metric = [&](int set, int i, double xb) __attribute__((always_inline)) {
         if (set < 2) {
           atomicAdd(&mbar[set * maxV + i], float(-xb));
         } else {
@@ -509,25 +519,27 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
         }
       };
       // S1: one thread per soft item: S_k, g_k . soft_k, and the x_[k] / tau terms
-      if (tid < nItems) {
-        int set, k;
-        set_of(tid, cntK, set, k);
-        const int D = cntD[set], nc = set < 2 ? 3 : 6;
+      if (tid < Kva + Kvb + Kea + Keb) {
+        int set = 0, k = tid;
+        if (k >= Kva) { k -= Kva; set = 1;
+          if (k >= Kvb) { k -= Kvb; set = 2;
+            if (k >= Kea) { k -= Kea; set = 3; } } }
+        const int D = nall(set);
         const double xk = P.sSel[set * CM_MAX_PRESEL + k];
-        const float* g = item_adj(set, k);
-        const double* sv = item_val(set, k);
+        const Six g = item(set, k, true), sv = item(set, k, false);
         double Sk = 0.0, gs = 0.0;
         for (int i = 0; i < D; ++i) Sk += exp64n(-fabs(xk + metric(set, i)) * T.inv_tau);
-        for (int c = 0; c < nc; ++c) gs += double(g[c]) * sv[c];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) gs = fma(g.c[c], sv.c[c], gs);
         const double iS = 1.0 / Sk;
         double xkb = 0.0, tb_ = 0.0;
         for (int i = 0; i < D; ++i) {
           const double dl = xk + metric(set, i);
           const double wn = exp64n(-fabs(dl) * T.inv_tau) * iS;
-          double p[6];
-          pos(set, i, p);
+          const Six p = pos(set, i);
           double gp = 0.0;
-          for (int c = 0; c < nc; ++c) gp += double(g[c]) * p[c];
+#pragma unroll
+          for (int c = 0; c < 6; ++c) gp = fma(g.c[c], p.c[c], gp);
           const double cki = wn * (gp - gs);
           xkb -= cki * (dl > 0.0 ? 1.0 : (dl < 0.0 ? -1.0 : 0.0)) * T.inv_tau;
           tb_ += cki * fabs(dl) * T.inv_tau * T.inv_tau;
@@ -539,32 +551,37 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
       }
       __syncthreads();
       // S2: one thread per set element: position and x_i adjoints
-      const int nElem = cntD[0] + cntD[1] + cntD[2] + cntD[3];
+      const int nElem = nvA_m + nvB_m + neA_m + neB_m;
       for (int t = tid; t < nElem; t += BLOCK) {
-        int set, i;
-        set_of(t, cntD, set, i);
-        const int Ks = cntK[set], nc = set < 2 ? 3 : 6;
+        int set = 0, i = t;
+        if (i >= nvA_m) { i -= nvA_m; set = 1;
+          if (i >= nvB_m) { i -= nvB_m; set = 2;
+            if (i >= neA_m) { i -= neA_m; set = 3; } } }
+        const int Ks = nsel(set);
         const double xi = -metric(set, i);
-        double p[6], pb[6] = {0, 0, 0, 0, 0, 0}, xib = 0.0;
-        pos(set, i, p);
+        const Six p = pos(set, i);
+        double pb[6] = {0, 0, 0, 0, 0, 0}, xib = 0.0;
         for (int k = 0; k < Ks; ++k) {
           const double dl = P.sSel[set * CM_MAX_PRESEL + k] - xi;
           const double wn = exp64n(-fabs(dl) * T.inv_tau) * sK[set * CM_MAX_PRESEL + k];
-          const float* g = item_adj(set, k);
+          const Six g = item(set, k, true);
           double gp = 0.0;
-          for (int c = 0; c < nc; ++c) { gp += double(g[c]) * p[c]; pb[c] = fma(wn, double(g[c]), pb[c]); }
+#pragma unroll
+          for (int c = 0; c < 6; ++c) { gp = fma(g.c[c], p.c[c], gp); pb[c] = fma(wn, g.c[c], pb[c]); }
           const double cki = wn * (gp - sK[4 * CM_MAX_PRESEL + set * CM_MAX_PRESEL + k]);
           xib += cki * (dl > 0.0 ? 1.0 : (dl < 0.0 ? -1.0 : 0.0)) * T.inv_tau;
         }
         add_metric(set, i, xib);
-        if (set == 0 || set == 1) {
-          float* V = set == 0 ? vA3 : vB3;
-          atomicAdd(&V[i], float(pb[0])); atomicAdd(&V[maxV + i], float(pb[1])); atomicAdd(&V[2 * maxV + i], float(pb[2]));
-        } else {
-          const GeomRec& G = set == 2 ? *P.GA : *P.GB;
-          float* V = set == 2 ? vA3 : vB3;
-          const int c0 = tb.e0[G.e_off + i], c1 = tb.e1[G.e_off + i];
-          atomicAdd(&V[c0], float(pb[0])); atomicAdd(&V[maxV + c0], float(pb[1])); atomicAdd(&V[2 * maxV + c0], float(pb[2]));
+        const bool onA = (set & 1) == 0;
+        float* V = onA ? vA3 : vB3;
+        int c0 = i, c1 = -1;
+        if (set >= 2) {
+          const GeomRec& G = onA ? *P.GA : *P.GB;
+          c0 = tb.e0[G.e_off + i];
+          c1 = tb.e1[G.e_off + i];
+        }
+        atomicAdd(&V[c0], float(pb[0])); atomicAdd(&V[maxV + c0], float(pb[1])); atomicAdd(&V[2 * maxV + c0], float(pb[2]));
+        if (c1 >= 0) {
           atomicAdd(&V[c1], float(pb[3])); atomicAdd(&V[maxV + c1], float(pb[4])); atomicAdd(&V[2 * maxV + c1], float(pb[5]));
         }
       }

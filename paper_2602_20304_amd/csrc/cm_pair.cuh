@@ -162,7 +162,7 @@ struct PairEngine {
   const GeomRec* GA;
   const GeomRec* GB;
 
-  __device__ PairEngine(PairShared& ps_, char* smem, const Tables& tb_, const BatchDev& bt_, const ParamsDev& prm,
+  __device__ __forceinline__ PairEngine(PairShared& ps_, char* smem, const Tables& tb_, const BatchDev& bt_, const ParamsDev& prm,
                         float* slot, int maxV_, int maxE_, int maxF_, int lds_extra = 0)
       : ps(ps_), tb(tb_), bt(bt_) {
     const LdsLayout L = lds_layout(maxE_, maxF_, BLOCK, lds_extra);
@@ -211,7 +211,7 @@ struct PairEngine {
   // ------------------------------------------------------------ setup
   // Thread 0 reads the pair and both poses; returns false (uniformly) for
   // an invalid pair.
-  __device__ bool setup(int a, int b, unsigned* err) {
+  __device__ __forceinline__ bool setup(int a, int b, unsigned* err) {
     if (tid == 0) {
       ps.a = a; ps.b = b;
       const int ga = bt.body_geom[a], gb = bt.body_geom[b];
@@ -272,7 +272,7 @@ struct PairEngine {
   }
 
   // ------------------------------------------------------------ stage
-  __device__ void stage() {
+  __device__ __forceinline__ void stage() {
     const int neA = A.ne, neB = B.ne, nfA = A.nf, nfB = B.nf;
     for (int i = tid; i < neA + neB; i += BLOCK) {
       const bool isA = i < neA;
@@ -316,7 +316,7 @@ struct PairEngine {
   // the staged edges and the counts shrink to the selection sizes.
   // sel_idx (optional, [4][CM_MAX_PRESEL]): receives the index within its set
   // of the item whose value is x_[k] (the adjoint routes x_[k]'s gradient there).
-  __device__ void select(int* sel_idx = nullptr) {
+  __device__ __forceinline__ void select(int* sel_idx = nullptr) {
     const int nvA = A.nv, nvB = B.nv, neA = A.ne, neB = B.ne;
     double* mVA = sMet;
     double* mVB = sMet + maxV;
@@ -432,7 +432,7 @@ struct PairEngine {
   // max(y'_g(p0), y'_g(p1)) < max_f min(y'_f(p0), y'_f(p1)) - 38, which
   // bounds its term in the LSE and in the gradient softmax below 2^-38.
   // Witness 1 lies on an edge of A, witness 2 on an edge of B.
-  __device__ void cull() {
+  __device__ __forceinline__ void cull() {
     if (!CULL || MW == 0 || ps.nee == 0) return;
     const double ext = 0.3 * T.tau;
     const int neA = A.ne;
@@ -553,7 +553,7 @@ struct PairEngine {
   }
 
   // ------------------------------------------------------------ scores
-  __device__ void scores(double (&tk)[KMAX]) {
+  __device__ __forceinline__ void scores(double (&tk)[KMAX]) {
     const int neA = A.ne, neB = B.ne, nee = ps.nee, nvs = ps.nvs;
 #pragma unroll
     for (int i = 0; i < KMAX; ++i) tk[i] = -INFINITY;
@@ -666,7 +666,7 @@ struct PairEngine {
   // ------------------------------------------------------------ top-K
   // Block merge of per-lane sorted lists: K rounds of block max; the lowest
   // thread holding the maximum pops it.  sTop[0..K) = s_[1] >= ... >= s_[K].
-  __device__ void topk(double (&tk)[KMAX]) {
+  __device__ __forceinline__ void topk(double (&tk)[KMAX]) {
     for (int r = 0; r < K; ++r) {
       const double h = tk[0];
       const double wm = wave_max(h);
@@ -701,7 +701,7 @@ struct PairEngine {
   // candidate record per thread in sRec, and body(n) runs with all threads
   // after a barrier for each chunk of n records.
   template <typename F>
-  __device__ void for_filtered(F&& body, double taus = kFilterTaus) {
+  __device__ __forceinline__ void for_filtered(F&& body, double taus = kFilterTaus) {
     const float thr = float(sTop[K - 1] - taus * T.tau) - 1e-6f * fabsf(float(sTop[K - 1]));
     const int ncand = ps.ncand;
     const int seg = (ncand + NW - 1) / NW;
@@ -753,7 +753,7 @@ struct PairEngine {
   // two, at most 64, so a row's lanes sit in one wave); lane j of the group
   // takes records j, j + G, ... and the exponential once for all nine fields.
   // The G partial sums of a row meet in a shuffle tree at the end.
-  __device__ void softsort() {
+  __device__ __forceinline__ void softsort() {
     int G = 64;
     while (G * K > BLOCK) G >>= 1;
     const int kk = tid / G, j0 = tid - kk * G;
