@@ -49,6 +49,16 @@ Readings where the paper is silent or garbled (each is listed in the design doc):
       tests use the raw SDF gradient
   R12 broadphase (not in the paper): keep a pair iff its bounding spheres
       overlap within a margin (default 10 tau), defined in float32
+  R18 superquadric unions (Sec. IV-B, SQ primitives and smooth union): a
+      body is the smooth union -LSE_tau(-phi_i) of M superquadrics; each
+      phi_i = |y| (1 - f(y)^(-eps1/2)) at its primitive-frame point y (the
+      radial distance; the printed division by |x| would not be a length);
+      E-E sign / clash tests use grad phi of the union, V-S normals the
+      union's softmax mix of grad f_i (the footnote on SQ normals), normalised
+      as in R11; mesh = per primitive a parametric grid (poles, rings at
+      -60 / -30 / 0 / 30 / 60 deg of 6 longitudes, quads split by one
+      diagonal: 32 vertices, 90 edges), minus
+      the vertices strictly inside another primitive (f_j < 1) and their edges
 """
 from __future__ import annotations
 
@@ -61,7 +71,7 @@ import torch
 from scipy.spatial import ConvexHull
 
 DT = torch.float64
-SPHERE, CAPSULE, BOX, POLYTOPE = 0, 1, 2, 3
+SPHERE, CAPSULE, BOX, POLYTOPE, SQ_UNION = 0, 1, 2, 3, 4
 LAMBDA_DEFAULT = 0.01
 
 
@@ -203,6 +213,141 @@ def hull_topology(points: np.ndarray):
     return vid, tris, edges
 
 
+SQ_LON = 6
+SQ_RINGS_DEG = (-60.0, -30.0, 0.0, 30.0, 60.0)
+
+
+def sq_local_topology():
+    """Reading R18: parametric samples (eta, omega) of one superquadric's mesh
+    and its edges.  Local vertex 0 is the south pole, then the rings (6 each,
+    omega = 2 pi j / 6), then the north pole; edges: pole spokes, ring edges,
+    meridians between rings and one diagonal per quad (32 vertices, 90 edges).
+    Poles are flagged with eta = +-pi/2 and placed exactly at (0, 0, +-c)."""
+    samples = [(-math.pi / 2, 0.0)]
+    for deg in SQ_RINGS_DEG:
+        for j in range(SQ_LON):
+            samples.append((math.radians(deg), 2 * math.pi * j / SQ_LON))
+    samples.append((math.pi / 2, 0.0))
+    nr = len(SQ_RINGS_DEG)
+    ring = lambda r, j: 1 + r * SQ_LON + (j % SQ_LON)
+    north = 1 + nr * SQ_LON
+    E = [(0, ring(0, j)) for j in range(SQ_LON)]
+    for r in range(nr):
+        E += [(ring(r, j), ring(r, j + 1)) for j in range(SQ_LON)]
+    for r in range(nr - 1):
+        E += [(ring(r, j), ring(r + 1, j)) for j in range(SQ_LON)]
+        E += [(ring(r, j), ring(r + 1, j + 1)) for j in range(SQ_LON)]
+    E += [(ring(nr - 1, j), north) for j in range(SQ_LON)]
+    return samples, np.array(E, dtype=np.int64)
+
+
+def _spow(v, e):
+    """sign(v) |v|^e (the superquadric's signed power)."""
+    return torch.sign(v) * torch.abs(v) ** e
+
+
+def sq_unpack(rec):
+    """Superquadric records [M, 12] -> axes [M, 3], eps1 [M], eps2 [M],
+    rotation primitive -> body [M, 3, 3], translation [M, 3].  Record layout:
+    a, b, c, eps1, eps2, tx, ty, tz, qw, qx, qy, qz (unit-normalised here)."""
+    ax, e1, e2, t = rec[:, 0:3], rec[:, 3], rec[:, 4], rec[:, 5:8]
+    q = rec[:, 8:12]
+    q = q / torch.sqrt((q * q).sum(-1, keepdim=True))
+    R = torch.stack([quat_to_R(q[i]) for i in range(q.shape[0])])
+    return ax, e1, e2, R, t
+
+
+def sq_inside_outside(y, ax, e1, e2):
+    """Inside-outside function f and its gradient at primitive-frame points y
+    [..., M, 3] (Sec. IV-B, SQ primitives): with scaled coordinates
+    s = y / (a, b, c), f = ((s_x^2)^(1/eps2) + (s_y^2)^(1/eps2))^(eps2/eps1)
+    + (s_z^2)^(1/eps1).  Where s_x = s_y = 0 the x / y derivatives are 0."""
+    s = y / ax
+    A = (s[..., 0] ** 2) ** (1.0 / e2)
+    B = (s[..., 1] ** 2) ** (1.0 / e2)
+    C = (s[..., 2] ** 2) ** (1.0 / e1)
+    u = A + B
+    f = u ** (e2 / e1) + C
+    # d/ds (s^2)^p = 2 p sign(s) |s|^(2p - 1)
+    dA = 2.0 / e2 * _spow(s[..., 0], 2.0 / e2 - 1.0)
+    dB = 2.0 / e2 * _spow(s[..., 1], 2.0 / e2 - 1.0)
+    dC = 2.0 / e1 * _spow(s[..., 2], 2.0 / e1 - 1.0)
+    upos = u > 0
+    du = torch.where(upos, (e2 / e1) * torch.where(upos, u, torch.ones_like(u)) ** (e2 / e1 - 1.0),
+                     torch.zeros_like(u))
+    g = torch.stack([du * dA / ax[..., 0], du * dB / ax[..., 1], dC / ax[..., 2]], dim=-1)
+    return f, g
+
+
+def sq_union_sdf(rec, x, tau):
+    """Smooth union of superquadrics at body-frame points x [..., 3]
+    (Sec. IV-B; reading R18).  Returns phi, grad phi and the V-S normal
+    direction sum_i pi_i grad f_i, pi = softmax(-phi_i / tau)."""
+    ax, e1, e2, R, t = sq_unpack(rec)
+    y = ((x[..., None, :] - t)[..., None, :] @ R).squeeze(-2)        # y_i = R_i^T (x - t_i)
+    f, gf = sq_inside_outside(y, ax, e1, e2)
+    r = torch.sqrt((y * y).sum(-1))
+    q = f ** (-e1 / 2.0)
+    phi_i = r * (1.0 - q)
+    gphi = (1.0 - q)[..., None] * y / r[..., None] + (r * (e1 / 2.0) * q / f)[..., None] * gf
+    phi = -lse_t(-phi_i, tau, dim=-1)
+    pi = torch.softmax(-phi_i / tau, dim=-1)
+    to_body = lambda v: (R @ v[..., None]).squeeze(-1)                   # R_i v_i
+    grad = (pi[..., None] * to_body(gphi)).sum(-2)
+    ndir = (pi[..., None] * to_body(gf)).sum(-2)
+    return phi, grad, ndir
+
+
+def sq_union_mesh(rec_np):
+    """Mesh of a superquadric union (reading R18): per primitive the
+    parametric grid of sq_local_topology, minus vertices strictly inside
+    another primitive and the edges touching them.  Returns the kept
+    (primitive, local sample) list and edges [E, 2] over the kept vertices."""
+    rec = torch.as_tensor(np.asarray(rec_np, dtype=np.float64))
+    M = rec.shape[0]
+    samples, le = sq_local_topology()
+    pts = sq_points(rec, [(i, k) for i in range(M) for k in range(len(samples))]).numpy()
+    ax, e1, e2, R, t = sq_unpack(rec)
+    n = len(samples)
+    keep = []
+    for i in range(M):
+        for k in range(n):
+            x = torch.as_tensor(pts[i * n + k])
+            y = ((x - t)[:, None, :] @ R).squeeze(-2)
+            f, _ = sq_inside_outside(y, ax, e1, e2)
+            inside = [(j != i) and bool(f[j] < 1.0) for j in range(M)]
+            if not any(inside):
+                keep.append((i, k))
+    index = {v: j for j, v in enumerate(keep)}
+    E = []
+    for i in range(M):
+        for a, b in le:
+            if (i, a) in index and (i, b) in index:
+                E.append((index[(i, a)], index[(i, b)]))
+    return keep, np.array(E, dtype=np.int64).reshape(-1, 2)
+
+
+def sq_points(rec, which):
+    """Body-frame positions of parametric samples (primitive, local index):
+    (a C(eta)^eps1 C(omega)^eps2, b C(eta)^eps1 S(omega)^eps2, c S(eta)^eps1)
+    with signed powers, rotated and translated by the primitive's pose."""
+    samples, _ = sq_local_topology()
+    ax, e1, e2, R, t = sq_unpack(rec)
+    out = []
+    for i, k in which:
+        eta, om = samples[k]
+        if abs(eta) == math.pi / 2:
+            c = torch.stack([ax[i, 0] * 0.0, ax[i, 1] * 0.0, ax[i, 2] * (1.0 if eta > 0 else -1.0)])
+        else:
+            ce, se = torch.tensor(math.cos(eta), dtype=DT), torch.tensor(math.sin(eta), dtype=DT)
+            co, so = torch.tensor(math.cos(om), dtype=DT), torch.tensor(math.sin(om), dtype=DT)
+            c = torch.stack([ax[i, 0] * _spow(ce, e1[i]) * _spow(co, e2[i]),
+                             ax[i, 1] * _spow(ce, e1[i]) * _spow(so, e2[i]),
+                             ax[i, 2] * _spow(se, e1[i])])
+        out.append(R[i] @ c + t[i])
+    return torch.stack(out)
+
+
 @dataclass
 class OGeom:
     """Oracle geometry: type, differentiable parameters and mesh topology.
@@ -218,11 +363,14 @@ class OGeom:
     edges: Optional[np.ndarray] = None      # [E, 2]
     tris: Optional[np.ndarray] = None       # [F, 3]
     _aux: Optional[np.ndarray] = None
+    sq: Optional[torch.Tensor] = None       # [M, 12] superquadric records (SQ_UNION)
 
     def vertices(self) -> torch.Tensor:
         """Mesh vertices in the body frame (Sec. IV-A: every surface has a mesh)."""
         if self.kind == POLYTOPE:
             return self.points
+        if self.kind == SQ_UNION:
+            return sq_points(self.sq, self._aux)
         p = self.params
         if self.kind == SPHERE:
             return p[0] * _t(self._aux)
@@ -245,6 +393,10 @@ class OGeom:
 
 
 def make_geom(kind: int, params=None, points=None, requires_grad=False) -> OGeom:
+    if kind == SQ_UNION:
+        rec = np.asarray(points, dtype=np.float64).reshape(-1, 12)
+        keep, edges = sq_union_mesh(rec)
+        return OGeom(kind, params=_t(np.zeros(4)), edges=edges, _aux=keep, sq=_t(rec, requires_grad))
     if kind == POLYTOPE:
         vid, tris, edges = hull_topology(points)
         pts = _t(np.asarray(points, dtype=np.float64)[vid], requires_grad)
@@ -270,8 +422,10 @@ def _sgn(x):
     return torch.where(x >= 0, torch.ones_like(x), -torch.ones_like(x))
 
 
-def sdf_local(G: OGeom, x: torch.Tensor, tau, planes=None, chunk: int = 1 << 22):
-    """Smooth SDF phi and its gradient at body-frame points x [..., 3].
+def sdf_local(G: OGeom, x: torch.Tensor, tau, planes=None, chunk: int = 1 << 22, with_ndir=False):
+    """Smooth SDF phi and its gradient at body-frame points x [..., 3]
+    (and with_ndir: the V-S normal direction, the gradient itself except for
+    superquadric unions, reading R18).
 
     sphere  |x| - r
     capsule |x - clamp(x_z, -h, h) z| - r
@@ -279,6 +433,12 @@ def sdf_local(G: OGeom, x: torch.Tensor, tau, planes=None, chunk: int = 1 << 22)
     polytope LSE_tau over face planes n_f . x - o_f (Sec. IV-B, CP primitive);
              gradient = softmax-weighted sum of face normals.
     """
+    if G.kind == SQ_UNION:
+        phi, g, nd = sq_union_sdf(G.sq, x, tau)
+        return (phi, g, nd) if with_ndir else (phi, g)
+    if with_ndir:
+        phi, g = sdf_local(G, x, tau, planes, chunk)
+        return phi, g, g
     if G.kind == SPHERE:
         nrm = torch.sqrt((x * x).sum(-1))
         return nrm - G.params[0], x / nrm[..., None]
@@ -380,9 +540,13 @@ def pose_Rt(pose7, xi=None, exact=False):
 
 # ============================================================== one body pair
 
-def sdf_world(G: OGeom, R, t, X, tau, planes=None):
-    """phi_G and grad phi_G (world frame) at world points X [..., 3]."""
+def sdf_world(G: OGeom, R, t, X, tau, planes=None, with_ndir=False):
+    """phi_G and grad phi_G (world frame) at world points X [..., 3] (and
+    with_ndir: the V-S normal direction, reading R18)."""
     xl = (X - t) @ R
+    if with_ndir:
+        phi, gl, nl = sdf_local(G, xl, tau, planes, with_ndir=True)
+        return phi, gl @ R.T, nl @ R.T
     phi, gl = sdf_local(G, xl, tau, planes)
     return phi, gl @ R.T
 
@@ -587,8 +751,8 @@ def pair_candidates(GA: OGeom, RA, tA, GB: OGeom, RB, tB, tau, lam=LAMBDA_DEFAUL
         a0, a1, b0, b1 = sa0[:, None, :], sa1[:, None, :], sb0[None, :, :], sb1[None, :, :]
 
     # ---- vertex-SDF contacts (Sec. IV-C; normals R11; weights R6)
-    phiB_v, gB_v = sdf_world(GB, RB, tB, vA, tau, planesB)
-    phiA_v, gA_v = sdf_world(GA, RA, tA, vB, tau, planesA)
+    phiB_v, _, gB_v = sdf_world(GB, RB, tB, vA, tau, planesB, with_ndir=True)
+    phiA_v, _, gA_v = sdf_world(GA, RA, tA, vB, tau, planesA, with_ndir=True)
     vs_p = torch.cat([vA, vB])
     vs_nu = torch.cat([-vs_normal(gB_v, tau), vs_normal(gA_v, tau)])   # pair convention (R8)
     vs_d = torch.cat([phiB_v, phiA_v])
@@ -682,10 +846,17 @@ def bound_radius_f32(kind: int, params, points) -> np.float32:
     """Bounding radius about the body origin, in float32 arithmetic.
 
     sphere r; capsule h + r; box sqrt((hx^2 + hy^2) + hz^2);
-    polytope sqrt(max_v ((x^2 + y^2) + z^2)).
+    polytope sqrt(max_v ((x^2 + y^2) + z^2)); superquadric union
+    max_i sqrt((tx^2 + ty^2) + tz^2) + sqrt((a^2 + b^2) + c^2) (each
+    superquadric lies in its (a, b, c) box).
     """
     f = np.float32
     p = np.asarray(params, dtype=np.float32)
+    if kind == SQ_UNION:
+        r = np.asarray(points, dtype=np.float32).reshape(-1, 12)
+        tn = np.sqrt((r[:, 5] * r[:, 5] + r[:, 6] * r[:, 6]) + r[:, 7] * r[:, 7], dtype=np.float32)
+        an = np.sqrt((r[:, 0] * r[:, 0] + r[:, 1] * r[:, 1]) + r[:, 2] * r[:, 2], dtype=np.float32)
+        return np.float32((tn + an).max())
     if kind == SPHERE:
         return f(p[0])
     if kind == CAPSULE:

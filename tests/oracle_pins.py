@@ -783,4 +783,129 @@ def pin_broadphase_f32():
     assert np.array_equal(off, np.concatenate([[0], np.cumsum(cnt)]))
 
 
+# ----------------------------------------------------------------------------- superquadric unions
+
+def _sq_rec(ax, e1, e2, t=(0.0, 0.0, 0.0), q=(1.0, 0.0, 0.0, 0.0)):
+    return T([[ax[0], ax[1], ax[2], e1, e2, t[0], t[1], t[2], q[0], q[1], q[2], q[3]]])
+
+
+def pin_sq_sphere_limit():
+    """eps1 = eps2 = 1 with equal semi-axes is a sphere: phi = |x - t| - r
+    exactly, grad phi = (x - t) / |x - t|, and the V-S normal direction
+    (grad f) is parallel to it."""
+    rng = np.random.default_rng(11)
+    for _ in range(3):
+        r = rng.uniform(0.1, 0.5)
+        t = rng.uniform(-0.5, 0.5, 3)
+        q = Rotation.random(random_state=rng).as_quat()[[3, 0, 1, 2]]
+        rec = _sq_rec((r, r, r), 1.0, 1.0, t, q)
+        x = T(rng.uniform(-1, 1, (40, 3)))
+        phi, g, nd = O.sq_union_sdf(rec, x, 0.01)
+        d = x - T(t)
+        nrm = torch.sqrt((d * d).sum(-1))
+        assert torch.allclose(phi, nrm - r, atol=1e-12)
+        assert torch.allclose(g, d / nrm[:, None], atol=1e-10)
+        ndn = nd / torch.sqrt((nd * nd).sum(-1, keepdim=True))
+        assert torch.allclose(ndn, d / nrm[:, None], atol=1e-10)
+
+
+def pin_sq_axis_distance():
+    """Along a primitive's own axes the radial SDF is the exact distance to
+    the surface: at s a e_x it is a (s - 1), at s c e_z it is c (s - 1), for
+    any exponents (the surface crosses the axes at the semi-axes)."""
+    for ax, e1, e2 in [((0.3, 0.2, 0.5), 0.4, 1.3), ((0.15, 0.4, 0.25), 1.7, 0.6)]:
+        rec = _sq_rec(ax, e1, e2)
+        for s in (0.5, 1.3, 2.0):
+            x = T([[s * ax[0], 0, 0], [0, s * ax[1], 0], [0, 0, s * ax[2]]])
+            phi, _, _ = O.sq_union_sdf(rec, x, 0.01)
+            ref = T([ax[0] * (s - 1), ax[1] * (s - 1), ax[2] * (s - 1)])
+            assert torch.allclose(phi, ref, atol=1e-12), (phi, ref)
+
+
+def pin_sq_surface_and_mesh():
+    """Parametric samples lie on their primitive's surface (f = 1, and the
+    union of one primitive is that primitive exactly); kept mesh vertices lie
+    outside every other primitive; a primitive inside another keeps none."""
+    rng = W._rng(6, 5)
+    rec = T(W.sq_union_records(rng, 4).reshape(-1, 12).astype(np.float64))
+    samples, _ = O.sq_local_topology()
+    for i in range(rec.shape[0]):
+        pts = O.sq_points(rec[i:i + 1], [(0, k) for k in range(len(samples))])
+        ax, e1, e2, R, t = O.sq_unpack(rec[i:i + 1])
+        y = ((pts[:, None, :] - t)[:, :, None, :] @ R).squeeze(-2)
+        f, _ = O.sq_inside_outside(y, ax, e1, e2)
+        assert torch.allclose(f, torch.ones_like(f), atol=1e-12)
+        phi, _, _ = O.sq_union_sdf(rec[i:i + 1], pts, 0.01)
+        assert phi.abs().max() < 1e-12
+    keep, E = O.sq_union_mesh(rec.numpy())
+    V = O.sq_points(rec, keep)
+    ax, e1, e2, R, t = O.sq_unpack(rec)
+    y = ((V[:, None, :] - t)[:, :, None, :] @ R).squeeze(-2)
+    f, _ = O.sq_inside_outside(y, ax, e1, e2)
+    for j, (i, _) in enumerate(keep):
+        others = [m for m in range(rec.shape[0]) if m != i]
+        assert bool((f[j, others] >= 1.0).all())
+    assert E.max() < len(keep)
+    nested = torch.cat([_sq_rec((0.5, 0.5, 0.5), 1.0, 1.0), _sq_rec((0.1, 0.1, 0.1), 0.8, 0.8, (0.05, 0, 0))])
+    keep2, _ = O.sq_union_mesh(nested.numpy())
+    assert all(i == 0 for i, _ in keep2) and len(keep2) == 32
+
+
+def pin_sq_gradients_fd():
+    """grad phi of a union of 3 superquadrics and grad f of each primitive
+    match central finite differences."""
+    rng = W._rng(6, 7)
+    rec = T(W.sq_union_records(rng, 3).reshape(-1, 12).astype(np.float64))
+    x = T(np.random.default_rng(8).uniform(-0.6, 0.6, (25, 3)))
+    tau, h = 0.05, 1e-6
+    phi, g, _ = O.sq_union_sdf(rec, x, tau)
+    ax, e1, e2, R, t = O.sq_unpack(rec)
+    ys = ((x[:, None, :] - t)[:, :, None, :] @ R).squeeze(-2)
+    f, gf = O.sq_inside_outside(ys, ax, e1, e2)
+    for k in range(3):
+        dx = torch.zeros(3, dtype=DT); dx[k] = h
+        fd = (O.sq_union_sdf(rec, x + dx, tau)[0] - O.sq_union_sdf(rec, x - dx, tau)[0]) / (2 * h)
+        assert torch.allclose(fd, g[:, k], rtol=1e-5, atol=1e-6), (fd - g[:, k]).abs().max()
+        dy = torch.zeros(3, dtype=DT); dy[k] = h
+        fp, _ = O.sq_inside_outside(ys + dy, ax, e1, e2)
+        fm, _ = O.sq_inside_outside(ys - dy, ax, e1, e2)
+        fdf = (fp - fm) / (2 * h)
+        assert torch.allclose(fdf, gf[..., k], rtol=1e-5, atol=1e-5 * float(gf.abs().max())), \
+            (fdf - gf[..., k]).abs().max()
+
+
+def pin_sq_union_bounds():
+    """The smooth union lies between min_i phi_i - tau ln M and min_i phi_i,
+    and tends to the hard union as tau -> 0."""
+    rng = W._rng(6, 9)
+    rec = T(W.sq_union_records(rng, 6).reshape(-1, 12).astype(np.float64))
+    x = T(np.random.default_rng(10).uniform(-0.8, 0.8, (60, 3)))
+    mins = torch.stack([O.sq_union_sdf(rec[i:i + 1], x, 0.01)[0] for i in range(6)]).min(0).values
+    for tau in (0.05, 0.01):
+        phi, _, _ = O.sq_union_sdf(rec, x, tau)
+        assert bool((phi <= mins + 1e-12).all()) and bool((phi >= mins - tau * math.log(6) - 1e-12).all())
+    phi0, _, _ = O.sq_union_sdf(rec, x, 1e-7)
+    assert torch.allclose(phi0, mins, atol=1e-6)
+
+
+def pin_sq_rigid_invariance():
+    """Moving every primitive and the query points by one rigid motion leaves
+    phi unchanged and rotates grad phi and the normal direction."""
+    rng = W._rng(6, 12)
+    rec = W.sq_union_records(rng, 4).reshape(-1, 12).astype(np.float64)
+    Rm = Rotation.random(random_state=np.random.default_rng(13))
+    d = np.array([0.3, -0.2, 0.1])
+    moved = rec.copy()
+    moved[:, 5:8] = Rm.apply(rec[:, 5:8]) + d
+    qs = (Rm * Rotation.from_quat(rec[:, [9, 10, 11, 8]])).as_quat()
+    moved[:, 8:12] = qs[:, [3, 0, 1, 2]]
+    x = np.random.default_rng(14).uniform(-0.6, 0.6, (30, 3))
+    p0, g0, n0 = O.sq_union_sdf(T(rec), T(x), 0.01)
+    p1, g1, n1 = O.sq_union_sdf(T(moved), T(Rm.apply(x) + d), 0.01)
+    Q = T(Rm.as_matrix())
+    assert torch.allclose(p0, p1, atol=1e-10)
+    assert torch.allclose(g0 @ Q.T, g1, atol=1e-8)
+    assert torch.allclose(n0 @ Q.T, n1, rtol=1e-8, atol=1e-8 * float(n0.abs().max()))
+
+
 ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_")]

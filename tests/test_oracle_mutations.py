@@ -85,6 +85,22 @@ MUTATIONS = [
      [P.pin_hull_counts, P.pin_polytope_inside_delaunay]),                             # inward normals
     ("broadphase", "keep = d2 <= r * r", "keep = d2 <= r",
      [P.pin_broadphase_f32]),                                                          # missing square
+    ("sq_union_sdf", "phi_i = r * (1.0 - q)", "phi_i = (1.0 - q) / r",
+     [P.pin_sq_axis_distance]),                                                        # printed division by |x|
+    ("sq_union_sdf", "q = f ** (-e1 / 2.0)", "q = f ** (-e2 / 2.0)",
+     [P.pin_sq_axis_distance]),                                                        # wrong exponent
+    ("sq_inside_outside", "f = u ** (e2 / e1) + C", "f = u ** (e1 / e2) + C",
+     [P.pin_sq_axis_distance, P.pin_sq_surface_and_mesh]),                             # inverted ratio
+    ("sq_union_sdf", "phi = -lse_t(-phi_i, tau, dim=-1)", "phi = lse_t(phi_i, tau, dim=-1)",
+     [P.pin_sq_union_bounds]),                                                         # smooth max
+    ("sq_inside_outside", "dC = 2.0 / e1 * _spow(s[..., 2], 2.0 / e1 - 1.0)",
+     "dC = 2.0 / e1 * _spow(s[..., 2], 2.0 / e2 - 1.0)",
+     [P.pin_sq_gradients_fd]),                                                         # gradient exponent
+    ("sq_points", "ax[i, 0] * _spow(ce, e1[i]) * _spow(co, e2[i])", "ax[i, 0] * _spow(ce, e2[i]) * _spow(co, e1[i])",
+     [P.pin_sq_surface_and_mesh]),                                                     # swapped exponents
+    ("sq_union_mesh", "inside = [(j != i) and bool(f[j] < 1.0) for j in range(M)]",
+     "inside = [(j != i) and bool(f[j] > 1.0) for j in range(M)]",
+     [P.pin_sq_surface_and_mesh]),                                                     # pruned the outside
 ]
 
 

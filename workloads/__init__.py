@@ -10,6 +10,10 @@ Geometry type ids and parameter slots (shared vocabulary of the boundary):
   CAPSULE  = 1 : params = (r, half_length, 0, 0), core segment along local z
   BOX      = 2 : params = (hx, hy, hz, rounding)   outer half-extents
   POLYTOPE = 3 : params unused; ``points`` holds the hull input points (local)
+  SQ_UNION = 4 : params unused; ``points`` holds 4 xyz rows per superquadric
+                 primitive: (a, b, c), (eps1, eps2, tx), (ty, tz, qw),
+                 (qx, qy, qz) -- semi-axes, shape exponents and the
+                 primitive's pose in the body frame
 
 Poses are quaternion + translation, stored structure-of-arrays as a float32
 array ``pose[7, n_bodies]`` with rows (qw, qx, qy, qz, tx, ty, tz).
@@ -27,7 +31,7 @@ from typing import Optional
 
 import numpy as np
 
-SPHERE, CAPSULE, BOX, POLYTOPE = 0, 1, 2, 3
+SPHERE, CAPSULE, BOX, POLYTOPE, SQ_UNION = 0, 1, 2, 3, 4
 BOX_ROUNDING = 0.02
 
 
@@ -422,3 +426,44 @@ def subset_scenes(batch: Batch, scenes) -> Batch:
         out.cand_offsets = new_co.astype(np.int32)
         out.cand_pairs = remap[batch.cand_pairs[:, sel]].astype(np.int32)
     return out
+
+
+# ----------------------------------------------------------------------------- superquadric unions
+
+def sq_union_records(rng: np.random.Generator, n_prims: int = 18, spread=(0.4, 0.3, 0.55),
+                     axes=(0.07, 0.16), eps=(0.3, 1.5)) -> np.ndarray:
+    """One body as a union of superquadrics, packed 4 xyz rows per primitive.
+
+    A stand-in for a decomposed articulated mesh: a torso primitive at the
+    origin (semi-axes about 2x the others) and n_prims - 1 primitives whose
+    centres are uniform in an ellipsoid of semi-axes ``spread``, semi-axes
+    U[axes], exponents U[eps], uniform orientations.
+    """
+    M = int(n_prims)
+    ax = rng.uniform(axes[0], axes[1], size=(M, 3))
+    ax[0] *= 2.0
+    e = rng.uniform(eps[0], eps[1], size=(M, 2))
+    d = rng.standard_normal((M, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    t = d * rng.uniform(0.0, 1.0, size=(M, 1)) ** (1.0 / 3.0) * np.asarray(spread)[None, :]
+    t[0] = 0.0
+    q = uniform_quats(rng, M)
+    rec = np.concatenate([ax, e, t, q], axis=1)           # a b c e1 e2 tx ty tz qw qx qy qz
+    return rec.reshape(M * 4, 3).astype(np.float32)
+
+
+def sq_scenes(n_scenes: int = 4096, seed: int = 0, tau: float = 0.01, K: int = 8, n_prims: int = 18,
+              n_geoms: int = 8, bodies: int = 2) -> Batch:
+    """Superquadric-union bodies (the paper's default primitive family):
+    ``bodies`` per scene drawn from a pool of ``n_geoms`` unions of
+    ``n_prims`` primitives, centres uniform in a 1.2-wide cube so that most
+    pairs touch or overlap, uniform rotations."""
+    rng = _rng(6, seed)
+    recs = [sq_union_records(rng, n_prims) for _ in range(n_geoms)]
+    gs = _geomset([SQ_UNION] * n_geoms, np.zeros((n_geoms, 4)), recs)
+    nb = n_scenes * bodies
+    body_geom = rng.integers(0, n_geoms, size=nb).astype(np.int32)
+    t = rng.uniform(-0.6, 0.6, size=(nb, 3))
+    q = uniform_quats(rng, nb)
+    offs = (np.arange(n_scenes + 1) * bodies).astype(np.int32)
+    return Batch(gs, offs, body_geom, _pose_array(q, t), tau, K, name="sq_scenes")
