@@ -38,6 +38,20 @@
  *       CM_BOX      (hx, hy, hz, rounding)  outer half-extents; mesh 8 V / 12 E
  *       CM_POLYTOPE convex hull of the given points; SDF = tau-LSE over the
  *                   face planes (convex-polyhedron primitive, Sec. IV-B)
+ *       CM_SQ_UNION smooth union -LSE_tau(-phi_i) of 1..CM_MAX_SQ superquadric
+ *                   primitives (Sec. IV-B, SQ primitives and smooth union),
+ *                   phi_i = |y| (1 - f_i(y)^(-eps1/2)) at the primitive-frame
+ *                   point y; V-S normals from the union's softmax mix of
+ *                   grad f_i.  Given as 4 xyz rows per primitive in the point
+ *                   array: (a, b, c), (eps1, eps2, tx), (ty, tz, qw),
+ *                   (qx, qy, qz) -- semi-axes > 0, exponents in [0.1, 1.9],
+ *                   the primitive's pose in the body frame.  Mesh: per
+ *                   primitive a parametric grid of 32 V / 90 E (poles, rings
+ *                   at -60..60 degrees of 6 longitudes, one diagonal per
+ *                   quad) minus the vertices strictly inside another
+ *                   primitive.  Forward only: the adjoint records
+ *                   CM_ERR_INVALID_ARG (cm_check_errors) for pairs with such
+ *                   a body and skips them.
  */
 #ifndef CM_H
 #define CM_H
@@ -60,7 +74,8 @@ typedef enum {
   CM_ERR_GEOMETRY = -8
 } cm_status;
 
-enum { CM_SPHERE = 0, CM_CAPSULE = 1, CM_BOX = 2, CM_POLYTOPE = 3 };
+enum { CM_SPHERE = 0, CM_CAPSULE = 1, CM_BOX = 2, CM_POLYTOPE = 3, CM_SQ_UNION = 4 };
+#define CM_MAX_SQ 32
 
 /* Largest K the kernels support. */
 #define CM_MAX_K 32

@@ -134,6 +134,8 @@ cm_status cm_check_errors(cm_context* ctx, void* stream) {
   if (bits) hipMemset(ctx->d_err, 0, sizeof(unsigned));
   if (bits & ERR_BAD_GEOM) return cm_fail(ctx, CM_ERR_NOT_FOUND, "batch references an invalid body or geometry id");
   if (bits & ERR_CAPACITY) return cm_fail(ctx, CM_ERR_CAPACITY, "more kept pairs than the output capacity");
+  if (bits & ERR_NO_ADJOINT)
+    return cm_fail(ctx, CM_ERR_INVALID_ARG, "the adjoint of superquadric unions is not built (those pairs were skipped)");
   if (bits) return cm_fail(ctx, CM_ERR_DEVICE, "device error bits set");
   return CM_OK;
 }
@@ -144,10 +146,10 @@ cm_status cm_geometry_create(cm_context* ctx, int32_t n, const int32_t* types, c
   if (n == 0) return CM_OK;
   if (ctx->servers > 0) return cm_fail(ctx, CM_ERR_INVALID_ARG, "geometry is frozen while a server is running");
   for (int i = 0; i < n; ++i) {
-    if (types[i] < CM_SPHERE || types[i] > CM_POLYTOPE)
+    if (types[i] < CM_SPHERE || types[i] > CM_SQ_UNION)
       return cm_fail(ctx, CM_ERR_INVALID_ARG, "unknown geometry type");
-    if (types[i] == CM_POLYTOPE && (!pt_offsets || !points))
-      return cm_fail(ctx, CM_ERR_INVALID_ARG, "polytope needs points");
+    if ((types[i] == CM_POLYTOPE || types[i] == CM_SQ_UNION) && (!pt_offsets || !points))
+      return cm_fail(ctx, CM_ERR_INVALID_ARG, "polytopes and superquadric unions need points");
   }
   std::vector<HostMesh> meshes(n);
   std::vector<std::string> errs(n);
@@ -157,7 +159,7 @@ cm_status cm_geometry_create(cm_context* ctx, int32_t n, const int32_t* types, c
     for (int i = t; i < n; i += nt) {
       const float* pts = nullptr;
       int64_t np = 0;
-      if (types[i] == CM_POLYTOPE) {
+      if (types[i] == CM_POLYTOPE || types[i] == CM_SQ_UNION) {
         np = pt_offsets[i + 1] - pt_offsets[i];
         pts = points + 3 * pt_offsets[i];
       }
@@ -175,7 +177,7 @@ cm_status cm_geometry_create(cm_context* ctx, int32_t n, const int32_t* types, c
     for (int i = 0; i < n; ++i) {
       const float* pts = nullptr;
       int64_t np = 0;
-      if (types[i] == CM_POLYTOPE) { np = pt_offsets[i + 1] - pt_offsets[i]; pts = points + 3 * pt_offsets[i]; }
+      if (types[i] == CM_POLYTOPE || types[i] == CM_SQ_UNION) { np = pt_offsets[i + 1] - pt_offsets[i]; pts = points + 3 * pt_offsets[i]; }
       if (!build_mesh(types[i], params + 4 * i, pts, np, &meshes[i], &errs[i])) { bad = i; break; }
     }
   }
@@ -205,6 +207,7 @@ cm_status cm_geometry_create(cm_context* ctx, int32_t n, const int32_t* types, c
     ctx->maxV = std::max(ctx->maxV, r.nv);
     ctx->maxE = std::max(ctx->maxE, r.ne);
     ctx->maxF = std::max(ctx->maxF, r.nf);
+    if (r.type == CM_SQ_UNION) ctx->has_sq = true;
     out_ids[i] = int32_t(h.recs.size());
     h.recs.push_back(r);
   }
@@ -217,7 +220,8 @@ cm_status cm_geometry_info(cm_context* ctx, int32_t id, cm_geometry_info_t* out)
   if (!ctx || !out) return CM_ERR_INVALID_ARG;
   if (id < 0 || id >= int32_t(ctx->h.recs.size())) return cm_fail(ctx, CM_ERR_NOT_FOUND, "no such geometry");
   const GeomRec& r = ctx->h.recs[id];
-  out->type = r.type; out->n_vertices = r.nv; out->n_edges = r.ne; out->n_faces = r.nf;
+  // a superquadric union keeps its primitives in the plane pool: no faces
+  out->type = r.type; out->n_vertices = r.nv; out->n_edges = r.ne; out->n_faces = r.type == CM_SQ_UNION ? 0 : r.nf;
   out->vertex_offset = r.v_off; out->bound_radius = r.bound_r;
   return CM_OK;
 }
@@ -233,7 +237,7 @@ cm_status cm_geometry_mesh(cm_context* ctx, int32_t id, float* vertices, int32_t
     vertices[3 * v + 2] = float(h.vz[r.v_off + v]);
   }
   if (edges) for (int e = 0; e < r.ne; ++e) { edges[2 * e] = h.e0[r.e_off + e]; edges[2 * e + 1] = h.e1[r.e_off + e]; }
-  if (faces) for (int f = 0; f < r.nf; ++f) {
+  if (faces && r.type != CM_SQ_UNION) for (int f = 0; f < r.nf; ++f) {
     faces[3 * f] = h.f0[r.f_off + f]; faces[3 * f + 1] = h.f1[r.f_off + f]; faces[3 * f + 2] = h.f2[r.f_off + f];
   }
   return CM_OK;
@@ -272,6 +276,7 @@ cm_status resolve_params(cm_context* ctx, const cm_params* prm, ParamsDev* pd) {
   pd->flags = prm->flags;
   pd->presel_v = presel ? prm->presel_vertices : 0;
   pd->presel_e = presel ? prm->presel_edges : 0;
+  pd->sq = ctx->has_sq ? 1 : 0;
   return CM_OK;
 }
 

@@ -125,6 +125,11 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
     }
     const BodyView& A = P.A;
     const BodyView& B = P.B;
+    if (A.type == CM_SQ_UNION || B.type == CM_SQ_UNION) {   // no adjoint for these: flagged, pair skipped
+      if (tid == 0) atomicOr(err, ERR_NO_ADJOINT);
+      __syncthreads();
+      continue;
+    }
     // mesh counts (pre-selection shrinks A.nv ... to the selection sizes)
     const int nvA_m = A.nv, nvB_m = B.nv, nfA = A.nf, nfB = B.nf;
     for (int i = tid; i < 3 * maxV; i += BLOCK) { vA3[i] = 0.f; vB3[i] = 0.f; }

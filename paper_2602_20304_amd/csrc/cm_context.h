@@ -38,6 +38,7 @@ struct cm_context {
   CmDevPools d;
   CmDevCaps dcap;
   int maxV = 0, maxE = 0, maxF = 0;
+  bool has_sq = false;   // some geometry is a superquadric union
   unsigned* d_err = nullptr;
   int* d_tile_sums = nullptr;
   size_t tile_cap = 0;

@@ -397,17 +397,92 @@ __device__ __forceinline__ double log2_64(double s) {
   return double(e) + 2.0 * kLog2e * y * p;
 }
 
+// Smooth union of superquadrics (Sec. IV-B, SQ primitives and smooth
+// union) at body-frame point l.  Each primitive is 5 staged double4: the
+// rows of its rotation transposed with its translation in .w (so the
+// primitive-frame point is y = R^T (l - t)), then (1/a, 1/b, 1/c, eps1) and
+// (1/eps2, eps2/eps1, 1/eps1, eps2).  With s = y / (a, b, c) the
+// inside-outside function is f = ((s_x^2)^(1/eps2) + (s_y^2)^(1/eps2))^(eps2/eps1)
+// + (s_z^2)^(1/eps1) and phi_i = |y| (1 - f^(-eps1/2)); the union is
+// -LSE_tau(-phi_i), accumulated online (running minimum, rescaled sums).
+// Powers are float64 exp2 / log2 (the values feed weights divided by tau).
+// GRAD: also the union gradient, sum_i pi_i grad phi_i, or with NDIR the V-S
+// normal direction sum_i pi_i grad f_i (normals of superquadrics come from
+// grad f), pi = softmax(-phi_i / tau).
+template <bool GRAD, bool NDIR>
+__device__ __forceinline__ void sdf_squnion(const double4* __restrict__ sq, int nslots, const D3& l, const Temp& T,
+                                            double& phi, D3& g) {
+  const int M = nslots / 5;
+  double mn = 0.0, S = 0.0, ax = 0.0, ay = 0.0, az = 0.0;
+  for (int i = 0; i < M; ++i) {
+    const double4 r0 = sq[5 * i], r1 = sq[5 * i + 1], r2 = sq[5 * i + 2], s3 = sq[5 * i + 3], s4 = sq[5 * i + 4];
+    const double dx = l.x - r0.w, dy = l.y - r1.w, dz = l.z - r2.w;
+    const double yx = fma(r0.x, dx, fma(r0.y, dy, r0.z * dz));
+    const double yy = fma(r1.x, dx, fma(r1.y, dy, r1.z * dz));
+    const double yz = fma(r2.x, dx, fma(r2.y, dy, r2.z * dz));
+    const double sx = yx * s3.x, sy = yy * s3.y, sz = yz * s3.z;
+    const double e1 = s3.w, ie2 = s4.x, r21 = s4.y, ie1 = s4.z;
+    // (s^2)^p = 2^(p log2 s^2): 0 at s = 0 (log2 0 = -inf)
+    const double Ax = exp2(ie2 * log2(sx * sx)), Ay = exp2(ie2 * log2(sy * sy)), Cz = exp2(ie1 * log2(sz * sz));
+    const double u = Ax + Ay;
+    const double U = exp2(r21 * log2(u));
+    const double f = U + Cz;
+    const double r = sqrt(fma(yx, yx, fma(yy, yy, yz * yz)));
+    const double q = exp2(-0.5 * e1 * log2(f));
+    const double ph = r * (1.0 - q);
+    double vx = 0.0, vy = 0.0, vz = 0.0;
+    if (GRAD) {
+      // d/ds (s^2)^p = 2 p (s^2)^p / s (0 at s = 0: 2p > 1 for exponents <= 1.9)
+      const double du = u > 0.0 ? r21 * U / u : 0.0;
+      const double gx = sx != 0.0 ? du * 2.0 * ie2 * Ax / sx * s3.x : 0.0;
+      const double gy = sy != 0.0 ? du * 2.0 * ie2 * Ay / sy * s3.y : 0.0;
+      const double gz = sz != 0.0 ? 2.0 * ie1 * Cz / sz * s3.z : 0.0;
+      double hx = gx, hy = gy, hz = gz;
+      if (!NDIR) {
+        // grad phi_i = (1 - q) y / |y| + |y| (eps1 / 2) (q / f) grad f
+        const double a = r > 0.0 ? (1.0 - q) / r : 0.0, b = r * 0.5 * e1 * q / f;
+        hx = fma(a, yx, b * gx); hy = fma(a, yy, b * gy); hz = fma(a, yz, b * gz);
+      }
+      // back to the body frame: R (h) = sum_k h_k (row k of R^T)
+      vx = fma(hx, r0.x, fma(hy, r1.x, hz * r2.x));
+      vy = fma(hx, r0.y, fma(hy, r1.y, hz * r2.y));
+      vz = fma(hx, r0.z, fma(hy, r1.z, hz * r2.z));
+    }
+    if (i == 0) {
+      mn = ph; S = 1.0; ax = vx; ay = vy; az = vz;
+    } else if (ph < mn) {
+      const double sc = exp64n(-(mn - ph) * T.inv_tau);
+      S = fma(S, sc, 1.0); ax = fma(ax, sc, vx); ay = fma(ay, sc, vy); az = fma(az, sc, vz);
+      mn = ph;
+    } else {
+      const double w = exp64n(-(ph - mn) * T.inv_tau);
+      S += w; ax = fma(w, vx, ax); ay = fma(w, vy, ay); az = fma(w, vz, az);
+    }
+  }
+  phi = mn - T.tau * kLn2 * log2(S);
+  if (GRAD) {
+    const double iS = 1.0 / S;
+    g = d3(ax * iS, ay * iS, az * iS);
+  }
+}
+
 // SDF value of a body at a pair-frame point with a float64 LSE for
 // polytopes (float64 weights and logarithm): the pre-selection metrics, whose
 // differences are divided by tau in the selection weights.  IDENT: the body
 // is A.
-template <bool IDENT>
+template <bool IDENT, bool SQ = false>
 __device__ __forceinline__ double sdf_value64(const BodyView& B, const D3& x, const Temp& T) {
   D3 l = x;
   if (!IDENT) {
     const double dx = x.x - B.t[0], dy = x.y - B.t[1], dz = x.z - B.t[2];
     l = d3(B.R[0] * dx + B.R[3] * dy + B.R[6] * dz, B.R[1] * dx + B.R[4] * dy + B.R[7] * dz,
            B.R[2] * dx + B.R[5] * dy + B.R[8] * dz);
+  }
+  if (SQ && B.type == CM_SQ_UNION) {
+    double phi;
+    D3 g;
+    sdf_squnion<false, false>(B.planes, B.nf, l, T, phi, g);
+    return phi;
   }
   if (B.type != CM_POLYTOPE) {
     double phi;
@@ -432,8 +507,11 @@ __device__ __forceinline__ double sdf_value64(const BodyView& B, const D3& x, co
 // MODE: SdfMode (kValue leaves g untouched, kSurfGrad leaves phi untouched
 // for polytopes).  IDENT: the body is A, whose frame is the pair frame.
 // mk: face subset for polytopes, shared by every active lane of the wave
-// (null or mk->n == 0: all faces).
-template <int MODE, bool IDENT>
+// (null or mk->n == 0: all faces).  NDIR: for superquadric unions return the
+// V-S normal direction (from grad f) instead of grad phi.  SQ: superquadric
+// unions are handled (only the kernels built for contexts that hold them:
+// the union loop would raise every call site's register pressure).
+template <int MODE, bool IDENT, bool NDIR = false, bool SQ = false>
 __device__ __forceinline__ void sdf_body(const BodyView& B, const D3& x, const Temp& T, double& phi, D3& g,
                                          const FaceMask* mk = nullptr) {
   D3 l = x;
@@ -446,6 +524,8 @@ __device__ __forceinline__ void sdf_body(const BodyView& B, const D3& x, const T
   if (B.type == CM_POLYTOPE) {
     if (mk && mk->n > 0) sdf_poly_masked<MODE>(B.planes, B.nf, *mk, l, T, phi, lg);
     else sdf_poly<MODE>(B.planes, B.nf, l, T, phi, lg);
+  } else if (SQ && B.type == CM_SQ_UNION) {
+    sdf_squnion<MODE != kValue, NDIR>(B.planes, B.nf, l, T, phi, lg);
   } else {
     sdf_analytic(B.type, B.p, l, phi, lg);
   }
@@ -563,7 +643,7 @@ struct Cand {
 // averages, which need not lie on their own bodies' surfaces, so the
 // own-body queries are full ones; safeguard then multiplies both activities
 // by sigma(-phi_A(e1)/tau) sigma(-phi_B(e2)/tau).
-template <bool OWN_FULL = false>
+template <bool OWN_FULL = false, bool SQ = false>
 __device__ __forceinline__ void ee_candidates(const D3& a0, const D3& t1, const D3& b0, const D3& t2, const EEQP& q,
                                               double row_lse, double col_lse, const BodyView& A, const BodyView& B,
                                               double eps_n, const Temp& T, const FaceMask* m1, const FaceMask* m2,
@@ -577,12 +657,12 @@ __device__ __forceinline__ void ee_candidates(const D3& a0, const D3& t1, const 
   double phiB1, phiA2, dum;
   D3 gA, gB, dg;
   double phiA1 = 0.0, phiB2 = 0.0;
-  sdf_body<kValue, false>(B, e1, T, phiB1, dg, m1 ? m1 + 1 : nullptr);
-  if (OWN_FULL) sdf_body<kFull, true>(A, e1, T, phiA1, gA, m1);
-  else sdf_body<kSurfGrad, true>(A, e1, T, dum, gA, m1);                   // e1 lies on an edge of A
-  sdf_body<kValue, true>(A, e2, T, phiA2, dg, m2);
-  if (OWN_FULL) sdf_body<kFull, false>(B, e2, T, phiB2, gB, m2 ? m2 + 1 : nullptr);
-  else sdf_body<kSurfGrad, false>(B, e2, T, dum, gB, m2 ? m2 + 1 : nullptr);   // e2 lies on an edge of B
+  sdf_body<kValue, false, false, SQ>(B, e1, T, phiB1, dg, m1 ? m1 + 1 : nullptr);
+  if (OWN_FULL) sdf_body<kFull, true, false, SQ>(A, e1, T, phiA1, gA, m1);
+  else sdf_body<kSurfGrad, true, false, SQ>(A, e1, T, dum, gA, m1);                   // e1 lies on an edge of A
+  sdf_body<kValue, true, false, SQ>(A, e2, T, phiA2, dg, m2);
+  if (OWN_FULL) sdf_body<kFull, false, false, SQ>(B, e2, T, phiB2, gB, m2 ? m2 + 1 : nullptr);
+  else sdf_body<kSurfGrad, false, false, SQ>(B, e2, T, dum, gB, m2 ? m2 + 1 : nullptr);   // e2 lies on an edge of B
   const double gam1 = tanh64(dot(gB, nb), T);
   const double gam2 = tanh64(-dot(gA, nb), T);
   double base = q.log_con + lsig(-dot(gA, gB), T);
@@ -605,12 +685,12 @@ __device__ __forceinline__ void ee_candidates(const D3& a0, const D3& t1, const 
 // V-S candidate (Sec. IV-C): vertex v (pair frame) of one body against the
 // SDF of the other; sgn = -1 for A's vertices (the normal of B pushes A),
 // +1 for B's vertices.  OTHER_IS_A: the SDF is A's (identity frame).
-template <bool OTHER_IS_A>
+template <bool OTHER_IS_A, bool SQ = false>
 __device__ __forceinline__ void vs_candidate(const D3& v, const BodyView& other, double sgn, const Temp& T,
                                              Cand& c) {
   double phi;
   D3 g;
-  sdf_body<kFull, OTHER_IS_A>(other, v, T, phi, g);
+  sdf_body<kFull, OTHER_IS_A, true, SQ>(other, v, T, phi, g);
   const double in = sgn * rcp64(sqrt(T.tau + dot(g, g)));
   c.p = v;
   c.n = d3(g.x * in, g.y * in, g.z * in);

@@ -72,6 +72,7 @@ extern "C" cm_status cm_collide_fused(cm_context* ctx, const cm_batch* batch, co
   cm_status s;
   if ((s = resolve_params(ctx, prm, &pd)) != CM_OK) return s;
   if (pd.presel_v > 0) return cm_fail(ctx, CM_ERR_INVALID_ARG, "the fused path does not support pre-selection");
+  if (pd.sq) return cm_fail(ctx, CM_ERR_INVALID_ARG, "the fused path does not support superquadric unions");
   if ((s = resolve_batch(ctx, batch, &bd)) != CM_OK) return s;
   if ((s = resolve_out(ctx, out, &od)) != CM_OK) return s;
   hipSetDevice(ctx->device);

@@ -51,6 +51,7 @@ struct ParamsDev {
   int32_t eps_tied;         // eps_n = tau^2 (its tau dependence enters the adjoint)
   uint32_t flags;           // CM_FLAG_*
   int32_t presel_v, presel_e;   // soft top-K pre-selection sizes (0: off)
+  int32_t sq;                   // the context holds superquadric unions (selects the kernels built for them)
 };
 
 struct OutDev {
@@ -62,7 +63,7 @@ struct OutDev {
 };
 
 // Device error bits (sticky until cm_check_errors).
-enum : uint32_t { ERR_BAD_GEOM = 1u, ERR_CAPACITY = 2u, ERR_K = 4u };
+enum : uint32_t { ERR_BAD_GEOM = 1u, ERR_CAPACITY = 2u, ERR_K = 4u, ERR_NO_ADJOINT = 8u };
 
 // Host-side mesh of one geometry, built by geometry.cpp.
 struct HostMesh {

@@ -119,7 +119,7 @@ __host__ __device__ inline int presel_lds_bytes(int maxV, int maxE) {
 // edge pairs go row-major and every face is visited.  PRESEL: soft top-K
 // pre-selection (select()) replaces the bodies' vertices and edges by the
 // selected soft ones before the candidate passes.
-template <int BLOCK, int KMAX, bool CULL, bool PRESEL = false>
+template <int BLOCK, int KMAX, bool CULL, bool PRESEL = false, bool SQ = false>
 struct PairEngine {
   static constexpr int NW = BLOCK / 64;
 
@@ -298,7 +298,8 @@ struct PairEngine {
       const int j = isA ? i : i - nfA;
       // planes pre-scaled by c = log2(e) / tau (the polytope SDF works in
       // binary-exponent units)
-      const double c = T.c;
+      // (superquadric-union records are staged as they are)
+      const double c = (isA ? A.type : B.type) == CM_SQ_UNION ? 1.0 : T.c;
       (isA ? sPA : sPB)[j] = make_double4(c * tb.fnx[f], c * tb.fny[f], c * tb.fnz[f], c * tb.fo[f]);
     }
     __syncthreads();
@@ -323,8 +324,8 @@ struct PairEngine {
     double* mEA = sMet + 2 * maxV;
     double* mEB = mEA + maxE;
     for (int i = tid; i < nvA + nvB; i += BLOCK) {
-      if (i < nvA) mVA[i] = sdf_value64<false>(B, vertex<true>(*GA, i, A), T);
-      else mVB[i - nvA] = sdf_value64<true>(A, vertex<false>(*GB, i - nvA, B), T);
+      if (i < nvA) mVA[i] = sdf_value64<false, SQ>(B, vertex<true>(*GA, i, A), T);
+      else mVB[i - nvA] = sdf_value64<true, SQ>(A, vertex<false>(*GB, i - nvA, B), T);
     }
     __syncthreads();
     for (int i = tid; i < neA + neB; i += BLOCK) {
@@ -514,12 +515,12 @@ struct PairEngine {
   }
   __device__ __forceinline__ void vs(int i, Cand& c) const {
     if (PRESEL) {
-      if (i < A.nv) vs_candidate<false>(soft_vertex(i), B, -1.0, T, c);
-      else vs_candidate<true>(soft_vertex(i), A, 1.0, T, c);
+      if (i < A.nv) vs_candidate<false, SQ>(soft_vertex(i), B, -1.0, T, c);
+      else vs_candidate<true, SQ>(soft_vertex(i), A, 1.0, T, c);
       return;
     }
-    if (i < A.nv) vs_candidate<false>(vertex<true>(*GA, i, A), B, -1.0, T, c);
-    else vs_candidate<true>(vertex<false>(*GB, i - A.nv, B), A, 1.0, T, c);
+    if (i < A.nv) vs_candidate<false, SQ>(vertex<true>(*GA, i, A), B, -1.0, T, c);
+    else vs_candidate<true, SQ>(vertex<false>(*GB, i - A.nv, B), A, 1.0, T, c);
   }
   // both candidates of edge pair (k, l) from the QP solution stored by the
   // distance pass.  m1 / m2: the face masks of the groups holding edge k of
@@ -534,7 +535,7 @@ struct PairEngine {
     EB.get(l, b0, t2);
     const int i = k * B.ne + l;
     const EEQP q = ee_from_alpha(a0, t1, b0, t2, Al1[i], Al2[i], Lcon[i]);
-    ee_candidates<PRESEL>(a0, t1, b0, t2, q, sRow[k], sCol[l], A, B, eps_n, T, m1, m2, c1, c2,
+    ee_candidates<PRESEL, SQ>(a0, t1, b0, t2, q, sRow[k], sCol[l], A, B, eps_n, T, m1, m2, c1, c2,
                           PRESEL && (flags & CM_FLAG_SAFEGUARD));
   }
   // candidate idx in the fixed order: A's vertices, B's vertices, E-E (k, l)

@@ -300,6 +300,7 @@ cm_status cm_server_submit(cm_server* srv, const cm_request* q, uint64_t* ticket
   f.block = 256; f.kmax = kmax_for(K); f.queue = nullptr;
   f.prm.presel_v = presel ? q->params.presel_vertices : 0;   // selects the kernel whose occupancy applies
   f.prm.presel_e = presel ? q->params.presel_edges : 0;
+  f.prm.sq = srv->ctx->has_sq ? 1 : 0;
   const long long grid = request_grid(srv->ctx, fwd_occupancy(f), cap);
   r->footprint = footprint(srv->ctx, *r, grid, fwd_scratch_floats(f.maxV, f.maxE));
   if (r->footprint > srv->budget) return cm_fail(srv->ctx, CM_ERR_REJECTED, "request exceeds the HBM budget");

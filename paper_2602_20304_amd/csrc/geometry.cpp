@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <string>
 #include <unordered_set>
 
 #include "cm_internal.h"
@@ -55,6 +56,59 @@ void ring(double lat_deg, double out[8][3]) {
     out[j][1] = std::cos(la) * std::sin(th);
     out[j][2] = std::sin(la);
   }
+}
+
+// ---- superquadric unions (Sec. IV-B, SQ primitives and smooth union)
+// Record of one primitive: a, b, c, eps1, eps2, tx, ty, tz, qw, qx, qy, qz.
+struct SqPrim {
+  double ax[3], e1, e2, t[3], R[9];   // R: primitive frame -> body frame (row-major)
+};
+
+inline double spow(double v, double e) { return std::copysign(std::pow(std::fabs(v), e), v); }
+
+// inside-outside function of primitive P at body-frame point x
+double sq_f(const SqPrim& P, const double* x) {
+  const double d[3] = {x[0] - P.t[0], x[1] - P.t[1], x[2] - P.t[2]};
+  double y[3];
+  for (int k = 0; k < 3; ++k) y[k] = P.R[k] * d[0] + P.R[3 + k] * d[1] + P.R[6 + k] * d[2];   // R^T d
+  const double sx = y[0] / P.ax[0], sy = y[1] / P.ax[1], sz = y[2] / P.ax[2];
+  const double u = std::pow(sx * sx, 1.0 / P.e2) + std::pow(sy * sy, 1.0 / P.e2);
+  return std::pow(u, P.e2 / P.e1) + std::pow(sz * sz, 1.0 / P.e1);
+}
+
+// Per-primitive parametric grid: south pole, rings at -60 / -30 / 0 / 30 /
+// 60 degrees of 6 longitudes, north pole (32 vertices); edges: pole spokes,
+// ring edges, meridians and one diagonal per quad between rings (90 edges).
+constexpr int kSqLon = 6, kSqRings = 5, kSqLocalV = 2 + kSqLon * kSqRings;
+const double kSqRingDeg[kSqRings] = {-60.0, -30.0, 0.0, 30.0, 60.0};
+
+void sq_local_edges(std::vector<int>* E) {
+  auto ring = [](int r, int j) { return 1 + r * kSqLon + (j % kSqLon); };
+  const int north = 1 + kSqRings * kSqLon;
+  for (int j = 0; j < kSqLon; ++j) { E->push_back(0); E->push_back(ring(0, j)); }
+  for (int r = 0; r < kSqRings; ++r)
+    for (int j = 0; j < kSqLon; ++j) { E->push_back(ring(r, j)); E->push_back(ring(r, j + 1)); }
+  for (int r = 0; r + 1 < kSqRings; ++r) {
+    for (int j = 0; j < kSqLon; ++j) { E->push_back(ring(r, j)); E->push_back(ring(r + 1, j)); }
+    for (int j = 0; j < kSqLon; ++j) { E->push_back(ring(r, j)); E->push_back(ring(r + 1, j + 1)); }
+  }
+  for (int j = 0; j < kSqLon; ++j) { E->push_back(ring(kSqRings - 1, j)); E->push_back(north); }
+}
+
+// body-frame position of local sample k of primitive P
+void sq_sample(const SqPrim& P, int k, double* out) {
+  double c[3];
+  if (k == 0 || k == kSqLocalV - 1) {
+    c[0] = 0.0; c[1] = 0.0; c[2] = (k == 0 ? -1.0 : 1.0) * P.ax[2];
+  } else {
+    const int r = (k - 1) / kSqLon, j = (k - 1) % kSqLon;
+    const double eta = kSqRingDeg[r] * (M_PI / 180.0), om = 2.0 * M_PI * j / kSqLon;
+    const double ce = spow(std::cos(eta), P.e1), se = spow(std::sin(eta), P.e1);
+    c[0] = P.ax[0] * ce * spow(std::cos(om), P.e2);
+    c[1] = P.ax[1] * ce * spow(std::sin(om), P.e2);
+    c[2] = P.ax[2] * se;
+  }
+  for (int i = 0; i < 3; ++i) out[i] = P.R[3 * i] * c[0] + P.R[3 * i + 1] * c[1] + P.R[3 * i + 2] * c[2] + P.t[i];
 }
 
 }  // namespace
@@ -305,6 +359,74 @@ bool build_mesh(int32_t type, const float* params, const float* pts, int64_t n_p
       mx = std::max(mx, q);
     }
     m.bound_r = std::sqrt(mx);
+    return true;
+  }
+  if (type == CM_SQ_UNION) {
+    if (n_pts % 4 != 0 || n_pts < 4 || n_pts / 4 > CM_MAX_SQ) {
+      *err = "superquadric union needs 1.." + std::to_string(CM_MAX_SQ) + " primitives of 4 xyz rows";
+      return false;
+    }
+    const int M = int(n_pts / 4);
+    std::vector<SqPrim> P(M);
+    float bound = 0.f;
+    for (int i = 0; i < M; ++i) {
+      const float* r = pts + 12 * i;
+      for (int k = 0; k < 12; ++k)
+        if (!std::isfinite(r[k])) { *err = "non-finite superquadric record"; return false; }
+      SqPrim& q = P[i];
+      for (int k = 0; k < 3; ++k) { q.ax[k] = r[k]; q.t[k] = r[5 + k]; }
+      q.e1 = r[3]; q.e2 = r[4];
+      if (!(q.ax[0] > 0 && q.ax[1] > 0 && q.ax[2] > 0) || !(q.e1 >= 0.1 && q.e1 <= 1.9) ||
+          !(q.e2 >= 0.1 && q.e2 <= 1.9)) {
+        *err = "superquadric needs semi-axes > 0 and exponents in [0.1, 1.9]";
+        return false;
+      }
+      double w = r[8], x = r[9], y = r[10], z = r[11];
+      const double n = std::sqrt(w * w + x * x + y * y + z * z);
+      if (!(n > 0)) { *err = "superquadric quaternion is zero"; return false; }
+      w /= n; x /= n; y /= n; z /= n;
+      const double R[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+                           2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                           2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)};
+      std::memcpy(q.R, R, sizeof(R));
+      // float32 bound: |t| + |(a, b, c)| (the primitive lies in its box)
+      const float tn = std::sqrt((r[5] * r[5] + r[6] * r[6]) + r[7] * r[7]);
+      const float an = std::sqrt((r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]);
+      bound = std::max(bound, tn + an);
+    }
+    // mesh: every primitive's grid minus vertices strictly inside another
+    // primitive (f_j < 1) and the edges that touch them
+    std::vector<int> le;
+    sq_local_edges(&le);
+    std::vector<int> index(size_t(M) * kSqLocalV, -1);
+    for (int i = 0; i < M; ++i)
+      for (int k = 0; k < kSqLocalV; ++k) {
+        double x[3];
+        sq_sample(P[i], k, x);
+        bool inside = false;
+        for (int j = 0; j < M && !inside; ++j) inside = (j != i) && sq_f(P[j], x) < 1.0;
+        if (inside) continue;
+        index[size_t(i) * kSqLocalV + k] = int(m.vd.size() / 3);
+        push_v(x[0], x[1], x[2]);
+      }
+    if (m.vd.empty()) { *err = "superquadric union mesh is empty"; return false; }
+    for (int i = 0; i < M; ++i)
+      for (size_t e = 0; e < le.size(); e += 2) {
+        const int a = index[size_t(i) * kSqLocalV + le[e]], b = index[size_t(i) * kSqLocalV + le[e + 1]];
+        if (a >= 0 && b >= 0) push_e(a, b);
+      }
+    // device records: 5 float64 quadruples per primitive in the plane pool:
+    // the rows of R^T with t in .w, then (1/a, 1/b, 1/c, eps1) and
+    // (1/eps2, eps2/eps1, 1/eps1, eps2); face ids are unused zeros
+    for (int i = 0; i < M; ++i) {
+      const SqPrim& q = P[i];
+      const double slot[20] = {q.R[0], q.R[3], q.R[6], q.t[0], q.R[1], q.R[4], q.R[7], q.t[1],
+                               q.R[2], q.R[5], q.R[8], q.t[2], 1.0 / q.ax[0], 1.0 / q.ax[1], 1.0 / q.ax[2], q.e1,
+                               1.0 / q.e2, q.e2 / q.e1, 1.0 / q.e1, q.e2};
+      for (int k = 0; k < 20; ++k) { m.pd.push_back(slot[k]); m.planes.push_back(float(slot[k])); }
+      for (int k = 0; k < 15; ++k) m.f.push_back(0);
+    }
+    m.bound_r = bound;
     return true;
   }
   *err = "unknown geometry type";

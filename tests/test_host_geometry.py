@@ -108,3 +108,50 @@ def test_invalid_analytic_rejected(shim):
     assert build(shim, W.SPHERE, [-1, 0, 0, 0])[0] is None
     assert build(shim, W.BOX, [0.1, 0.1, 0.1, 0.5])[0] is None
     assert build(shim, 7, [0.1, 0.1, 0.1, 0.0])[0] is None
+
+
+def build_sq(lib, rec):
+    """Library mesh of one superquadric union (records: 4 xyz rows per primitive)."""
+    P = np.ascontiguousarray(rec, np.float32).reshape(-1, 3)
+    M = max(len(P) // 4, 1)
+    capv, cape, capf = 32 * M + 8, 90 * M + 8, 5 * M + 8
+    v = np.zeros(3 * capv, np.float32); e = np.zeros(2 * cape, np.int32); f = np.zeros(3 * capf, np.int32)
+    pl = np.zeros(4 * capf, np.float32); nv = C.c_int(); ne = C.c_int(); nf = C.c_int(); br = C.c_float()
+    err = C.create_string_buffer(256)
+    ptr = lambda a: a.ctypes.data_as(C.c_void_p)
+    params = np.zeros(4, np.float32)
+    ok = lib.shim_build_mesh(W.SQ_UNION, ptr(params), ptr(P), C.c_long(len(P)), ptr(v), C.byref(nv), ptr(e),
+                             C.byref(ne), ptr(f), C.byref(nf), ptr(pl), C.byref(br), err)
+    if not ok:
+        return None, err.value.decode()
+    return dict(v=v[:3 * nv.value].reshape(-1, 3), e=e[:2 * ne.value].reshape(-1, 2), nf=nf.value,
+                slots=pl[:4 * nf.value].reshape(-1, 4), bound=br.value), ""
+
+
+@pytest.mark.parametrize("n_prims,seed", [(1, 0), (3, 1), (18, 2), (18, 3)])
+def test_sq_union_meshes_match_oracle(shim, n_prims, seed):
+    """Library and oracle build the same superquadric-union mesh: vertex set
+    and order, edge list, float32 bounding radius bit for bit."""
+    rec = W.sq_union_records(W._rng(6, seed), n_prims)
+    m, err = build_sq(shim, rec)
+    assert m is not None, err
+    G = O.make_geom(O.SQ_UNION, points=rec)
+    with torch.no_grad():
+        V = G.vertices().numpy()
+    assert m["v"].shape == V.shape
+    assert np.allclose(m["v"], V, atol=1e-6)
+    assert np.array_equal(m["e"], G.edges.astype(np.int32))
+    assert m["nf"] == 5 * n_prims
+    assert np.float32(m["bound"]) == O.bound_radius_f32(O.SQ_UNION, None, rec)
+    if n_prims == 1:
+        assert len(V) == 32 and len(G.edges) == 90
+
+
+def test_invalid_sq_union_rejected(shim):
+    rec = W.sq_union_records(W._rng(6, 0), 2).reshape(-1, 12).copy()
+    bad_eps = rec.copy(); bad_eps[0, 3] = 2.5
+    bad_axis = rec.copy(); bad_axis[1, 1] = 0.0
+    bad_q = rec.copy(); bad_q[0, 8:12] = 0.0
+    for r in (bad_eps, bad_axis, bad_q):
+        assert build_sq(shim, r.reshape(-1, 3))[0] is None
+    assert build_sq(shim, rec.reshape(-1, 3)[:7])[0] is None         # not 4 rows per primitive
