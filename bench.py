@@ -264,6 +264,47 @@ def ee_witness_leg(ctx, trials: int = 100, max_n: int = 10_000_000, tau: float =
     return res
 
 
+def sq_leg(ctx_cls, steps: int = 5, scenes_presel: int = 4096, scenes_all: int = 256):
+    """Superquadric-union bodies (the paper's default primitive family): two
+    bodies per scene, each a smooth union of 18 superquadrics with a
+    ~350-vertex / ~800-edge mesh.  Forward with the paper's benchmark
+    pre-selection (K_V 64, K_E 18) and, on fewer scenes, over all edge pairs.
+    Its own context: contexts holding superquadric unions run the kernels
+    built for them."""
+    import torch
+    import workloads as W
+    ctx = ctx_cls(0)
+    stream = torch.cuda.current_stream()
+    res = {}
+    for name, n, presel in (("presel_64_18", scenes_presel, (64, 18)), ("all_edge_pairs", scenes_all, None)):
+        b = W.sq_scenes(n, seed=3)
+        ids = ctx.create_geometry(b.geoms)
+        db = ctx.upload_batch(b, ids)
+        out = ctx.collide(db, b.tau, b.K, stream=stream, presel=presel)
+        torch.cuda.synchronize()
+        ctx.check_errors()
+        ctx.set_kernel_timing(True)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(steps):
+            ctx.collide(db, b.tau, b.K, out=out, stream=stream, presel=presel)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        k_ms, k_n = ctx.kernel_time("forward")
+        ctx.set_kernel_timing(False)
+        ctx.check_errors()
+        ms = ev0.elapsed_time(ev1) / steps
+        kept = int(out.n_pairs.item())
+        info = [ctx.geometry_info(int(g)) for g in ids]
+        res[name] = {"scenes": n, "kept_pairs": kept, "ms_per_step": ms, "forward_kernel_ms": k_ms / max(k_n, 1),
+                     "pairs_per_s": kept / (ms * 1e-3), "presel": list(presel) if presel else None,
+                     "mesh_vertices": [i["n_vertices"] for i in info], "mesh_edges": [i["n_edges"] for i in info]}
+        log(f"sq {name}: {ms:.3f} ms/step, {kept} kept pairs, {kept / (ms * 1e-3):.4g} pairs/s")
+    res["config"] = ("2 bodies per scene from a pool of 8 smooth unions of 18 superquadrics (semi-axes U[0.07, 0.16], "
+                     "torso x2, exponents U[0.3, 1.5]), centres uniform in [-0.6, 0.6]^3, tau 0.01, K 8")
+    return res
+
+
 def copy_calibration(n_bytes: int, reps: int):
     """Plain device copy of a known size (for scaling PMC byte counters)."""
     import torch
@@ -291,6 +332,8 @@ def main():
     ap.add_argument("--no-ee", action="store_true", help="skip the E-E witness microbenchmark")
     ap.add_argument("--ee-only", action="store_true", help="run only the E-E witness microbenchmark")
     ap.add_argument("--serve-only", action="store_true", help="run only the serving leg")
+    ap.add_argument("--no-sq", action="store_true", help="skip the superquadric-union leg")
+    ap.add_argument("--sq-only", action="store_true", help="run only the superquadric-union leg")
     ap.add_argument("--ee-trials", type=int, default=100, help="timed launches per size in the E-E sweep")
     ap.add_argument("--no-simplifications", action="store_true",
                     help="skip the forward legs without E-E (ne), with one-sided vertex contacts (ne_s) and "
@@ -316,6 +359,9 @@ def main():
 
     if args.serve_only:
         print(json.dumps({"serving": serving_leg(Context, args.serve or 16)}), flush=True)
+        return
+    if args.sq_only:
+        print(json.dumps({"superquadrics": sq_leg(Context, steps=args.steps)}), flush=True)
         return
     if args.ee_only:
         ctx = Context(0)
@@ -455,6 +501,9 @@ def main():
         log("ee_witness: " + ", ".join(f"n={n}: {a:.4f}/{b:.4f} ms" for n, a, b in
                                        zip(ee["sizes"], ee["smooth_ms"], ee["hard_ms"])) +
             f"; 1e7 smooth {ee['smooth_roofline']['achieved']:.0f} GB/s, hard {ee['hard_roofline']['achieved']:.0f} GB/s")
+    if not args.no_sq and not args.only:
+        log("superquadric-union leg ...")
+        line["superquadrics"] = sq_leg(Context, steps=min(args.steps, 5))
     if not args.no_cpu_baseline and not args.only:
         log("timing the FP64 oracle on the host ...")
         line["cpu_baseline"] = cpu_baseline(batch, args.cpu_budget)
