@@ -58,7 +58,9 @@ Readings where the paper is silent or garbled (each is listed in the design doc):
       as in R11; mesh = per primitive a parametric grid (poles, rings at
       -60 / -30 / 0 / 30 / 60 deg of 6 longitudes, quads split by one
       diagonal: 32 vertices, 90 edges), minus
-      the vertices strictly inside another primitive (f_j < 1) and their edges
+      the vertices strictly inside another primitive (f_j < 1) and their edges;
+      a power of a coordinate that is exactly 0 has derivative 0 (its true
+      derivative is infinite for exponents above 1, a kink like R13's)
 """
 from __future__ import annotations
 
@@ -242,8 +244,18 @@ def sq_local_topology():
 
 
 def _spow(v, e):
-    """sign(v) |v|^e (the superquadric's signed power)."""
-    return torch.sign(v) * torch.abs(v) ** e
+    """sign(v) |v|^e (the superquadric's signed power), 0 at v = 0 with
+    derivative 0 there (reading R18's convention for zero coordinates)."""
+    nz = v != 0
+    vs = torch.where(nz, v, torch.ones_like(v))
+    return torch.where(nz, torch.sign(vs) * torch.abs(vs) ** e, torch.zeros_like(v))
+
+
+def _ppow(v, p):
+    """(v^2)^p, 0 at v = 0 with derivative 0 there (R18)."""
+    nz = v != 0
+    vs = torch.where(nz, v, torch.ones_like(v))
+    return torch.where(nz, (vs * vs) ** p, torch.zeros_like(v))
 
 
 def sq_unpack(rec):
@@ -261,20 +273,21 @@ def sq_inside_outside(y, ax, e1, e2):
     """Inside-outside function f and its gradient at primitive-frame points y
     [..., M, 3] (Sec. IV-B, SQ primitives): with scaled coordinates
     s = y / (a, b, c), f = ((s_x^2)^(1/eps2) + (s_y^2)^(1/eps2))^(eps2/eps1)
-    + (s_z^2)^(1/eps1).  Where s_x = s_y = 0 the x / y derivatives are 0."""
+    + (s_z^2)^(1/eps1).  Powers of a zero coordinate are 0 and so are their
+    derivatives there (R18), so autograd stays finite on the axis planes."""
     s = y / ax
-    A = (s[..., 0] ** 2) ** (1.0 / e2)
-    B = (s[..., 1] ** 2) ** (1.0 / e2)
-    C = (s[..., 2] ** 2) ** (1.0 / e1)
+    A = _ppow(s[..., 0], 1.0 / e2)
+    B = _ppow(s[..., 1], 1.0 / e2)
+    C = _ppow(s[..., 2], 1.0 / e1)
     u = A + B
-    f = u ** (e2 / e1) + C
+    upos = u > 0
+    us = torch.where(upos, u, torch.ones_like(u))
+    f = torch.where(upos, us ** (e2 / e1), torch.zeros_like(u)) + C
     # d/ds (s^2)^p = 2 p sign(s) |s|^(2p - 1)
     dA = 2.0 / e2 * _spow(s[..., 0], 2.0 / e2 - 1.0)
     dB = 2.0 / e2 * _spow(s[..., 1], 2.0 / e2 - 1.0)
     dC = 2.0 / e1 * _spow(s[..., 2], 2.0 / e1 - 1.0)
-    upos = u > 0
-    du = torch.where(upos, (e2 / e1) * torch.where(upos, u, torch.ones_like(u)) ** (e2 / e1 - 1.0),
-                     torch.zeros_like(u))
+    du = torch.where(upos, (e2 / e1) * us ** (e2 / e1 - 1.0), torch.zeros_like(u))
     g = torch.stack([du * dA / ax[..., 0], du * dB / ax[..., 1], dC / ax[..., 2]], dim=-1)
     return f, g
 

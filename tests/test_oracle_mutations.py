@@ -89,7 +89,8 @@ MUTATIONS = [
      [P.pin_sq_axis_distance]),                                                        # printed division by |x|
     ("sq_union_sdf", "q = f ** (-e1 / 2.0)", "q = f ** (-e2 / 2.0)",
      [P.pin_sq_axis_distance]),                                                        # wrong exponent
-    ("sq_inside_outside", "f = u ** (e2 / e1) + C", "f = u ** (e1 / e2) + C",
+    ("sq_inside_outside", "torch.where(upos, us ** (e2 / e1), torch.zeros_like(u)) + C",
+     "torch.where(upos, us ** (e1 / e2), torch.zeros_like(u)) + C",
      [P.pin_sq_axis_distance, P.pin_sq_surface_and_mesh]),                             # inverted ratio
     ("sq_union_sdf", "phi = -lse_t(-phi_i, tau, dim=-1)", "phi = lse_t(phi_i, tau, dim=-1)",
      [P.pin_sq_union_bounds]),                                                         # smooth max
