@@ -49,9 +49,14 @@
  *                   primitive a parametric grid of 32 V / 90 E (poles, rings
  *                   at -60..60 degrees of 6 longitudes, one diagonal per
  *                   quad) minus the vertices strictly inside another
- *                   primitive.  Forward only: the adjoint records
- *                   CM_ERR_INVALID_ARG (cm_check_errors) for pairs with such
- *                   a body and skips them.
+ *                   primitive.  cm_collide_backward differentiates through
+ *                   them (pose twists and tau; their records take no
+ *                   gradient and their g_params entries stay 0); for
+ *                   exponents above 1 the normal field's derivative is
+ *                   unbounded on a primitive's axis planes, where mesh edges
+ *                   lie, so gradients there are ill-conditioned.
+ *                   cm_collide_fused returns CM_ERR_INVALID_ARG for contexts
+ *                   that hold them.
  */
 #ifndef CM_H
 #define CM_H

@@ -42,6 +42,120 @@ __device__ __forceinline__ float wave_sumf(float v) {
   return v;
 }
 
+// ---- forward-mode derivatives for superquadric unions
+// A float64 value with its derivatives along four inputs (the query point's
+// x, y, z and tau).  Evaluating the union with it yields the Jacobian of
+// (phi, gradient) in one pass, Hessian terms included.
+struct Dual4 {
+  double v, d[4];
+};
+__device__ __forceinline__ Dual4 dconst(double v) { return Dual4{v, {0.0, 0.0, 0.0, 0.0}}; }
+__device__ __forceinline__ Dual4 dvar(double v, int k) {
+  Dual4 r = dconst(v);
+  r.d[k] = 1.0;
+  return r;
+}
+__device__ __forceinline__ Dual4 operator+(const Dual4& a, const Dual4& b) {
+  return Dual4{a.v + b.v, {a.d[0] + b.d[0], a.d[1] + b.d[1], a.d[2] + b.d[2], a.d[3] + b.d[3]}};
+}
+__device__ __forceinline__ Dual4 operator-(const Dual4& a, const Dual4& b) {
+  return Dual4{a.v - b.v, {a.d[0] - b.d[0], a.d[1] - b.d[1], a.d[2] - b.d[2], a.d[3] - b.d[3]}};
+}
+__device__ __forceinline__ Dual4 operator*(const Dual4& a, const Dual4& b) {
+  Dual4 r;
+  r.v = a.v * b.v;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k];
+  return r;
+}
+__device__ __forceinline__ Dual4 operator*(double s, const Dual4& a) {
+  return Dual4{s * a.v, {s * a.d[0], s * a.d[1], s * a.d[2], s * a.d[3]}};
+}
+__device__ __forceinline__ Dual4 operator/(const Dual4& a, const Dual4& b) {
+  const double ib = 1.0 / b.v, q = a.v * ib;
+  Dual4 r;
+  r.v = q;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) r.d[k] = (a.d[k] - q * b.d[k]) * ib;
+  return r;
+}
+// f(a) with f(a.v) = fv and f'(a.v) = fd
+__device__ __forceinline__ Dual4 dchain(const Dual4& a, double fv, double fd) {
+  return Dual4{fv, {fd * a.d[0], fd * a.d[1], fd * a.d[2], fd * a.d[3]}};
+}
+__device__ __forceinline__ Dual4 dsqrt(const Dual4& a) {
+  const double s = sqrt(a.v);
+  return dchain(a, s, s > 0.0 ? 0.5 / s : 0.0);
+}
+__device__ __forceinline__ Dual4 dexp2(const Dual4& a) {
+  const double e = exp2(a.v);
+  return dchain(a, e, e * kLn2);
+}
+__device__ __forceinline__ Dual4 dlog2(const Dual4& a) { return dchain(a, log2(a.v), 1.0 / (a.v * kLn2)); }
+__device__ __forceinline__ Dual4 dexp(const Dual4& a) {
+  const double e = exp(a.v);
+  return dchain(a, e, e);
+}
+
+// The superquadric union of sdf_squnion (same records, same definitions)
+// over Dual4 inputs: phi and either grad phi or (ndir) the V-S normal
+// direction sum_i pi_i grad f_i, each with its derivatives.  Powers (s^2)^p
+// are taken as 2^(p log2 s^2) where s != 0 and as 0 at s = 0, where their
+// derivatives (2p > 1) vanish too.
+__device__ __forceinline__ void sq_union_dual(const double4* __restrict__ sq, int nslots, const Dual4& lx,
+                                              const Dual4& ly, const Dual4& lz, const Dual4& tau, bool ndir,
+                                              Dual4& phi, Dual4& gx, Dual4& gy, Dual4& gz) {
+  const int M = nslots / 5;
+  const Dual4 itau = dconst(1.0) / tau;
+  Dual4 mn = dconst(0.0), S = dconst(0.0), ax = dconst(0.0), ay = dconst(0.0), az = dconst(0.0);
+  auto ppow = [](const Dual4& s, double p) {   // (s^2)^p
+    if (s.v == 0.0) return dconst(0.0);
+    return dexp2(p * dlog2(s * s));
+  };
+  for (int i = 0; i < M; ++i) {
+    const double4 r0 = sq[5 * i], r1 = sq[5 * i + 1], r2 = sq[5 * i + 2], s3 = sq[5 * i + 3], s4 = sq[5 * i + 4];
+    const Dual4 dx = lx - dconst(r0.w), dy = ly - dconst(r1.w), dz = lz - dconst(r2.w);
+    const Dual4 yx = r0.x * dx + r0.y * dy + r0.z * dz;
+    const Dual4 yy = r1.x * dx + r1.y * dy + r1.z * dz;
+    const Dual4 yz = r2.x * dx + r2.y * dy + r2.z * dz;
+    const Dual4 sx = s3.x * yx, sy = s3.y * yy, sz = s3.z * yz;
+    const double e1 = s3.w, ie2 = s4.x, r21 = s4.y, ie1 = s4.z;
+    const Dual4 Ax = ppow(sx, ie2), Ay = ppow(sy, ie2), Cz = ppow(sz, ie1);
+    const Dual4 u = Ax + Ay;
+    const Dual4 U = u.v > 0.0 ? dexp2(r21 * dlog2(u)) : dconst(0.0);
+    const Dual4 f = U + Cz;
+    const Dual4 r = dsqrt(yx * yx + yy * yy + yz * yz);
+    const Dual4 q = dexp2((-0.5 * e1) * dlog2(f));
+    const Dual4 ph = r * (dconst(1.0) - q);
+    // grad f in the primitive frame: d/ds (s^2)^p = 2 p (s^2)^p / s
+    const Dual4 du = u.v > 0.0 ? r21 * (U / u) : dconst(0.0);
+    const Dual4 gfx = sx.v != 0.0 ? (2.0 * ie2 * s3.x) * (du * (Ax / sx)) : dconst(0.0);
+    const Dual4 gfy = sy.v != 0.0 ? (2.0 * ie2 * s3.y) * (du * (Ay / sy)) : dconst(0.0);
+    const Dual4 gfz = sz.v != 0.0 ? (2.0 * ie1 * s3.z) * (Cz / sz) : dconst(0.0);
+    Dual4 hx = gfx, hy = gfy, hz = gfz;
+    if (!ndir) {
+      const Dual4 a = r.v > 0.0 ? (dconst(1.0) - q) / r : dconst(0.0);
+      const Dual4 b = (0.5 * e1) * (r * q / f);
+      hx = a * yx + b * gfx; hy = a * yy + b * gfy; hz = a * yz + b * gfz;
+    }
+    const Dual4 vx = r0.x * hx + r1.x * hy + r2.x * hz;
+    const Dual4 vy = r0.y * hx + r1.y * hy + r2.y * hz;
+    const Dual4 vz = r0.z * hx + r1.z * hy + r2.z * hz;
+    if (i == 0) {
+      mn = ph; S = dconst(1.0); ax = vx; ay = vy; az = vz;
+    } else if (ph.v < mn.v) {
+      const Dual4 sc = dexp((ph - mn) * itau);
+      S = S * sc + dconst(1.0); ax = ax * sc + vx; ay = ay * sc + vy; az = az * sc + vz;
+      mn = ph;
+    } else {
+      const Dual4 w = dexp((mn - ph) * itau);
+      S = S + w; ax = ax + w * vx; ay = ay + w * vy; az = az + w * vz;
+    }
+  }
+  phi = mn - kLn2 * (tau * dlog2(S));
+  gx = ax / S; gy = ay / S; gz = az / S;
+}
+
 // Gradient sinks of one body during the adjoint of a pair (LDS, float atomics).
 struct BodySink {
   float* plane;    // [4][maxF] adjoints of (n.xyz, o) in the body frame, or null
@@ -53,10 +167,24 @@ struct BodySink {
 // Returns l_bar; accumulates parameter / plane adjoints and tau_bar.
 // WAVE: all 64 lanes execute this call together (plane adjoints are summed
 // across the wave before one atomic per plane).
-template <bool WAVE>
+// SQ: superquadric unions are handled (kernels built for contexts holding
+// them); ndir: the gradient output g_bar refers to is their V-S normal
+// direction.  Their record adjoints are not accumulated (no geometry
+// gradient for them); point and tau adjoints are.
+template <bool WAVE, bool SQ = false>
 __device__ __forceinline__ D3 sdf_local_bwd(int type, const float* p, const double4* __restrict__ pl, int nf, const D3& l,
                                             double phib, const D3& gb, const Temp& T, const BodySink& sink,
-                                            double& taub, D3& g_out) {
+                                            double& taub, D3& g_out, bool ndir = false) {
+  if (SQ && type == CM_SQ_UNION) {
+    Dual4 ph, gx, gy, gz;
+    sq_union_dual(pl, nf, dvar(l.x, 0), dvar(l.y, 1), dvar(l.z, 2), dvar(T.tau, 3), ndir, ph, gx, gy, gz);
+    g_out = d3(gx.v, gy.v, gz.v);
+    double o[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) o[k] = phib * ph.d[k] + gb.x * gx.d[k] + gb.y * gy.d[k] + gb.z * gz.d[k];
+    taub += o[3];
+    return d3(o[0], o[1], o[2]);
+  }
   if (type == CM_SPHERE) {
     const double s = dot(l, l), n = sqrt(s), inv = s > 0.0 ? 1.0 / n : 0.0;
     const D3 g = scl(l, inv);
@@ -167,17 +295,17 @@ struct Twist {
 // Adjoint of an SDF query of body V at pair-frame point x.  IDENT: the body
 // is A (pair frame).  For body B the query moves with B: its placement twist
 // receives rho -= x_bar, omega += g x g_bar - x x x_bar.
-template <bool WAVE, bool IDENT>
+template <bool WAVE, bool IDENT, bool SQ = false>
 __device__ __forceinline__ D3 sdf_body_bwd(const BodyView& V, const D3& x, double phib, const D3& gb, const Temp& T,
-                                           const BodySink& sink, double& taub, Twist& tw) {
+                                           const BodySink& sink, double& taub, Twist& tw, bool ndir = false) {
   if (IDENT) {
     D3 g;
-    return sdf_local_bwd<WAVE>(V.type, V.p, V.planes, V.nf, x, phib, gb, T, sink, taub, g);
+    return sdf_local_bwd<WAVE, SQ>(V.type, V.p, V.planes, V.nf, x, phib, gb, T, sink, taub, g, ndir);
   }
   const D3 l = rotT(V.R, sub(x, d3(V.t[0], V.t[1], V.t[2])));
   const D3 gbl = rotT(V.R, gb);
   D3 gl;
-  const D3 lb = sdf_local_bwd<WAVE>(V.type, V.p, V.planes, V.nf, l, phib, gbl, T, sink, taub, gl);
+  const D3 lb = sdf_local_bwd<WAVE, SQ>(V.type, V.p, V.planes, V.nf, l, phib, gbl, T, sink, taub, gl, ndir);
   const D3 xb = rot(V.R, lb);
   const D3 g = rot(V.R, gl);
   const D3 c1 = cross(g, gb), c2 = cross(x, xb);

@@ -78,7 +78,7 @@ struct BwdArgs {
   GradDev gr;
 };
 
-template <int BLOCK, int KMAX, bool PRESEL>
+template <int BLOCK, int KMAX, bool PRESEL, bool SQ>
 __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, ParamsDev prm, OutDev fwd, BwdArgs ga,
                                                      float* __restrict__ scratch, long long scratch_stride, int maxV,
                                                      int maxE, int maxF, unsigned* err) {
@@ -86,7 +86,7 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
   char* smem = reinterpret_cast<char*>(smem4);
   __shared__ PairShared ps;
   const int extra = bwd_extra_bytes(maxV, maxE, maxF, BLOCK, PRESEL);
-  PairEngine<BLOCK, KMAX, true, PRESEL> P(ps, smem, tb, bt, prm, scratch + (long long)blockIdx.x * scratch_stride, maxV,
+  PairEngine<BLOCK, KMAX, true, PRESEL, SQ> P(ps, smem, tb, bt, prm, scratch + (long long)blockIdx.x * scratch_stride, maxV,
                                           maxE, maxF, extra);
   // the engine's pre-selection arrays sit right after its own layout
   const BwdLds L = bwd_layout(lds_layout(maxE, maxF, BLOCK, extra).bytes + (PRESEL ? presel_lds_bytes(maxV, maxE) : 0),
@@ -125,7 +125,7 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
     }
     const BodyView& A = P.A;
     const BodyView& B = P.B;
-    if (A.type == CM_SQ_UNION || B.type == CM_SQ_UNION) {   // no adjoint for these: flagged, pair skipped
+    if (!SQ && (A.type == CM_SQ_UNION || B.type == CM_SQ_UNION)) {   // not built for these: flagged, skipped
       if (tid == 0) atomicOr(err, ERR_NO_ADJOINT);
       __syncthreads();
       continue;
@@ -305,8 +305,8 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
         const double sgn = ofA ? -1.0 : 1.0;
         double phi;
         D3 g;
-        if (ofA) sdf_body<kFull, false>(B, x, T, phi, g);
-        else sdf_body<kFull, true>(A, x, T, phi, g);
+        if (ofA) sdf_body<kFull, false, true, SQ>(B, x, T, phi, g);
+        else sdf_body<kFull, true, true, SQ>(A, x, T, phi, g);
         const double q = T.tau + dot(g, g), in = 1.0 / sqrt(q);
         const double lw = lsig(-phi, T), w = exp(lw);
         const double dtot = fb[6] - sb, lwb = T.tau * sb + w * fb[7];
@@ -339,14 +339,14 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
         const D3 nb = scl(de, rho);
         double phiB1, phiA2, dum, phiA1 = 0.0, phiB2 = 0.0;
         D3 gA, gB, dg;
-        sdf_body<kValue, false>(B, e1, T, phiB1, dg);
-        sdf_body<kValue, true>(A, e2, T, phiA2, dg);
+        sdf_body<kValue, false, false, SQ>(B, e1, T, phiB1, dg);
+        sdf_body<kValue, true, false, SQ>(A, e2, T, phiA2, dg);
         if (PRESEL) {   // soft edges need not lie on their own bodies: full queries
-          sdf_body<kFull, true>(A, e1, T, phiA1, gA);
-          sdf_body<kFull, false>(B, e2, T, phiB2, gB);
+          sdf_body<kFull, true, false, SQ>(A, e1, T, phiA1, gA);
+          sdf_body<kFull, false, false, SQ>(B, e2, T, phiB2, gB);
         } else {
-          sdf_body<kSurfGrad, true>(A, e1, T, dum, gA);
-          sdf_body<kSurfGrad, false>(B, e2, T, dum, gB);
+          sdf_body<kSurfGrad, true, false, SQ>(A, e1, T, dum, gA);
+          sdf_body<kSurfGrad, false, false, SQ>(B, e2, T, dum, gB);
         }
         const double u1 = dot(gB, nb), u2 = -dot(gA, nb), ucl = -dot(gA, gB);
         const double gam1 = tanh64(u1, T), gam2 = tanh64(u2, T);
@@ -400,10 +400,11 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
         gbar[3] = gBb;
       }
       // ---- stage 2: SDF adjoints, every lane of the wave together
-      const D3 xb0 = sdf_body_bwd<true, true>(A, X[0], phib[0], gbar[0], T, sinkA, taub, tw);
-      const D3 xb1 = sdf_body_bwd<true, false>(B, X[1], phib[1], gbar[1], T, sinkB, taub, tw);
-      const D3 xb2 = sdf_body_bwd<true, true>(A, X[2], phib[2], gbar[2], T, sinkA, taub, tw);
-      const D3 xb3 = sdf_body_bwd<true, false>(B, X[3], phib[3], gbar[3], T, sinkB, taub, tw);
+      // (a V-S slot's gradient adjoint refers to the V-S normal direction)
+      const D3 xb0 = sdf_body_bwd<true, true, SQ>(A, X[0], phib[0], gbar[0], T, sinkA, taub, tw, is_vs);
+      const D3 xb1 = sdf_body_bwd<true, false, SQ>(B, X[1], phib[1], gbar[1], T, sinkB, taub, tw, is_vs);
+      const D3 xb2 = sdf_body_bwd<true, true, SQ>(A, X[2], phib[2], gbar[2], T, sinkA, taub, tw);
+      const D3 xb3 = sdf_body_bwd<true, false, SQ>(B, X[3], phib[3], gbar[3], T, sinkB, taub, tw);
       if (!live) return;
       // ---- stage 3: back to vertices / edges
       if (is_vs) {
@@ -598,14 +599,14 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
         const int v = base + lane;
         const bool live = v < nvA_m;
         const D3 x = P.template vertex<true>(*P.GA, live ? v : 0, A);
-        const D3 xb = sdf_body_bwd<true, false>(B, x, live ? double(mbar[v]) : 0.0, d3(0, 0, 0), T, sinkB, taub, tw);
+        const D3 xb = sdf_body_bwd<true, false, SQ>(B, x, live ? double(mbar[v]) : 0.0, d3(0, 0, 0), T, sinkB, taub, tw);
         if (live) { atomicAdd(&vA3[v], float(xb.x)); atomicAdd(&vA3[maxV + v], float(xb.y)); atomicAdd(&vA3[2 * maxV + v], float(xb.z)); }
       }
       for (int base = wave * 64; base < nvB_m; base += BLOCK) {
         const int v = base + lane;
         const bool live = v < nvB_m;
         const D3 x = P.template vertex<false>(*P.GB, live ? v : 0, B);
-        const D3 xb = sdf_body_bwd<true, true>(A, x, live ? double(mbar[maxV + v]) : 0.0, d3(0, 0, 0), T, sinkA, taub, tw);
+        const D3 xb = sdf_body_bwd<true, true, SQ>(A, x, live ? double(mbar[maxV + v]) : 0.0, d3(0, 0, 0), T, sinkA, taub, tw);
         if (live) { atomicAdd(&vB3[v], float(xb.x)); atomicAdd(&vB3[maxV + v], float(xb.y)); atomicAdd(&vB3[2 * maxV + v], float(xb.z)); }
       }
       __syncthreads();
@@ -617,6 +618,7 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
       const bool isA = i < nfA;
       const int f = isA ? i : i - nfA;
       const GeomRec& G = isA ? *P.GA : *P.GB;
+      if (G.type != CM_POLYTOPE) continue;   // superquadric records are not face planes
       const float* pl = isA ? plA : plB;
       const int iv[3] = {tb.f0[G.f_off + f], tb.f1[G.f_off + f], tb.f2[G.f_off + f]};
       D3 v[3];
@@ -662,7 +664,7 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
           atomicAdd(&ga.gr.g_vertices[ga.gr.pool + o], float(gb.y));
           atomicAdd(&ga.gr.g_vertices[2LL * ga.gr.pool + o], float(gb.z));
         }
-      } else {
+      } else if (G.type != CM_SQ_UNION) {   // no geometry gradient for superquadric unions
         float* pr = isA ? prA : prB;
         if (G.type == CM_SPHERE) {
           atomicAdd(&pr[0], float(dot(lv, gb) / double(G.p[0])));
@@ -717,7 +719,8 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
       const bool isA = tid < 4;
       const GeomRec& G = isA ? *P.GA : *P.GB;
       const int gid = isA ? ps.ga : ps.gb;
-      if (G.type != CM_POLYTOPE) atomicAdd(&ga.gr.g_params[(tid & 3) * (long long)tb.n_geoms + gid], prA[tid]);
+      if (G.type != CM_POLYTOPE && G.type != CM_SQ_UNION)
+        atomicAdd(&ga.gr.g_params[(tid & 3) * (long long)tb.n_geoms + gid], prA[tid]);
     }
     __syncthreads();
   }
@@ -729,47 +732,52 @@ int bwd_lds_bytes(int maxV, int maxE, int maxF, int block, bool presel) {
   return bwd_layout(lds_layout(maxE, maxF, block, extra).bytes + pre, maxV, maxE, maxF, block, presel).bytes;
 }
 
-template <int BLOCK, int KMAX, bool PRESEL>
+template <int BLOCK, int KMAX, bool PRESEL, bool SQ>
 static hipError_t launch_bwd_t(const BwdLaunch& b, hipStream_t st) {
   const int lds = bwd_lds_bytes(b.f.maxV, b.f.maxE, b.f.maxF, BLOCK, PRESEL);
   BwdArgs ga{b.cot, b.gr};
-  hipLaunchKernelGGL((collide_bwd<BLOCK, KMAX, PRESEL>), dim3(b.f.grid), dim3(BLOCK), lds, st, b.f.tb, b.f.bt, b.f.prm,
-                     b.f.out, ga, b.f.scratch, b.f.scratch_stride, b.f.maxV, b.f.maxE, b.f.maxF, b.f.err);
+  hipLaunchKernelGGL((collide_bwd<BLOCK, KMAX, PRESEL, SQ>), dim3(b.f.grid), dim3(BLOCK), lds, st, b.f.tb, b.f.bt,
+                     b.f.prm, b.f.out, ga, b.f.scratch, b.f.scratch_stride, b.f.maxV, b.f.maxE, b.f.maxF, b.f.err);
   return hipGetLastError();
 }
 
-template <int BLOCK, int KMAX, bool PRESEL>
+template <int BLOCK, int KMAX, bool PRESEL, bool SQ>
 static int bwd_occ_t(const BwdLaunch& b) {
   int nb = 0;
   const int lds = bwd_lds_bytes(b.f.maxV, b.f.maxE, b.f.maxF, BLOCK, PRESEL);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, collide_bwd<BLOCK, KMAX, PRESEL>, BLOCK, lds) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, collide_bwd<BLOCK, KMAX, PRESEL, SQ>, BLOCK, lds) != hipSuccess)
     return 1;
   return nb > 0 ? nb : 1;
 }
 
-// Pre-selection runs in its own instantiations (the selection tracks taken
-// items in a 64-bit mask per lane: <= 4096 per set).
+template <bool PRESEL, bool SQ>
+static hipError_t launch_bwd_k(const BwdLaunch& b, hipStream_t st) {
+  if (b.f.kmax == 8) return launch_bwd_t<256, 8, PRESEL, SQ>(b, st);
+  if (b.f.kmax == 16) return launch_bwd_t<256, 16, PRESEL, SQ>(b, st);
+  return launch_bwd_t<256, 32, PRESEL, SQ>(b, st);
+}
+
+template <bool PRESEL, bool SQ>
+static int bwd_occ_k(const BwdLaunch& b) {
+  if (b.f.kmax == 8) return bwd_occ_t<256, 8, PRESEL, SQ>(b);
+  if (b.f.kmax == 16) return bwd_occ_t<256, 16, PRESEL, SQ>(b);
+  return bwd_occ_t<256, 32, PRESEL, SQ>(b);
+}
+
+// Pre-selection and contexts that hold superquadric unions run in their own
+// instantiations (the selection tracks taken items in a 64-bit mask per
+// lane: <= 4096 per set).
 hipError_t launch_collide_bwd(const BwdLaunch& b, hipStream_t st) {
-  if (b.f.prm.presel_v > 0) {
-    if (b.f.maxV > 4096 || b.f.maxE > 4096) return hipErrorInvalidValue;
-    if (b.f.kmax == 8) return launch_bwd_t<256, 8, true>(b, st);
-    if (b.f.kmax == 16) return launch_bwd_t<256, 16, true>(b, st);
-    return launch_bwd_t<256, 32, true>(b, st);
-  }
-  if (b.f.kmax == 8) return launch_bwd_t<256, 8, false>(b, st);
-  if (b.f.kmax == 16) return launch_bwd_t<256, 16, false>(b, st);
-  return launch_bwd_t<256, 32, false>(b, st);
+  const bool ps = b.f.prm.presel_v > 0, sq = b.f.prm.sq != 0;
+  if ((ps || sq) && (b.f.maxV > 4096 || b.f.maxE > 4096)) return hipErrorInvalidValue;
+  if (sq) return ps ? launch_bwd_k<true, true>(b, st) : launch_bwd_k<false, true>(b, st);
+  return ps ? launch_bwd_k<true, false>(b, st) : launch_bwd_k<false, false>(b, st);
 }
 
 int bwd_occupancy(const BwdLaunch& b) {
-  if (b.f.prm.presel_v > 0) {
-    if (b.f.kmax == 8) return bwd_occ_t<256, 8, true>(b);
-    if (b.f.kmax == 16) return bwd_occ_t<256, 16, true>(b);
-    return bwd_occ_t<256, 32, true>(b);
-  }
-  if (b.f.kmax == 8) return bwd_occ_t<256, 8, false>(b);
-  if (b.f.kmax == 16) return bwd_occ_t<256, 16, false>(b);
-  return bwd_occ_t<256, 32, false>(b);
+  const bool ps = b.f.prm.presel_v > 0, sq = b.f.prm.sq != 0;
+  if (sq) return ps ? bwd_occ_k<true, true>(b) : bwd_occ_k<false, true>(b);
+  return ps ? bwd_occ_k<true, false>(b) : bwd_occ_k<false, false>(b);
 }
 
 }  // namespace cm

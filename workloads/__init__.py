@@ -453,13 +453,13 @@ def sq_union_records(rng: np.random.Generator, n_prims: int = 18, spread=(0.4, 0
 
 
 def sq_scenes(n_scenes: int = 4096, seed: int = 0, tau: float = 0.01, K: int = 8, n_prims: int = 18,
-              n_geoms: int = 8, bodies: int = 2) -> Batch:
+              n_geoms: int = 8, bodies: int = 2, eps=(0.3, 1.5)) -> Batch:
     """Superquadric-union bodies (the paper's default primitive family):
     ``bodies`` per scene drawn from a pool of ``n_geoms`` unions of
-    ``n_prims`` primitives, centres uniform in a 1.2-wide cube so that most
-    pairs touch or overlap, uniform rotations."""
+    ``n_prims`` primitives (exponents U[eps]), centres uniform in a
+    1.2-wide cube so that most pairs touch or overlap, uniform rotations."""
     rng = _rng(6, seed)
-    recs = [sq_union_records(rng, n_prims) for _ in range(n_geoms)]
+    recs = [sq_union_records(rng, n_prims, eps=eps) for _ in range(n_geoms)]
     gs = _geomset([SQ_UNION] * n_geoms, np.zeros((n_geoms, 4)), recs)
     nb = n_scenes * bodies
     body_geom = rng.integers(0, n_geoms, size=nb).astype(np.int32)
