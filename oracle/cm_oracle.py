@@ -61,6 +61,12 @@ Readings where the paper is silent or garbled (each is listed in the design doc):
       the vertices strictly inside another primitive (f_j < 1) and their edges;
       a power of a coordinate that is exactly 0 has derivative 0 (its true
       derivative is infinite for exponents above 1, a kink like R13's)
+  R19 witness sphere tracing (Supp., refinement of the witness points): each
+      witness is moved along the fixed unit direction n = grad phi / |grad phi|
+      of its own body's SDF at the QP witness (e1 on A, e2 on B) by
+      x <- x - phi(x) n, a fixed number of steps; points, distances,
+      normals and the sign, penetration and clashing tests then use the moved
+      points, while the nearest-neighbour ranking keeps the QP distances
 """
 from __future__ import annotations
 
@@ -738,8 +744,21 @@ def preselect(GA, RA, tA, GB, RB, tB, tau, KV: int, KE: int, planesA=None, plane
     return (GvA @ vA, GvB @ vB, GeA @ vA[eA[:, 0]], GeA @ vA[eA[:, 1]], GeB @ vB[eB[:, 0]], GeB @ vB[eB[:, 1]])
 
 
+def sphere_trace(G, R, t, x, tau, planes, steps: int):
+    """Refinement of witness points onto the smoothed surface of the body
+    they belong to (Supp., sphere tracing; reading R19): along the fixed unit
+    direction n of grad phi at the start, x <- x - phi(x) n, `steps` times.
+    For a metric SDF one step lands on the surface."""
+    _, g = sdf_world(G, R, t, x, tau, planes)
+    n = g / torch.sqrt(_dot(g, g))[..., None]
+    for _ in range(steps):
+        phi, _ = sdf_world(G, R, t, x, tau, planes)
+        x = x - phi[..., None] * n
+    return x
+
+
 def pair_candidates(GA: OGeom, RA, tA, GB: OGeom, RB, tB, tau, lam=LAMBDA_DEFAULT, eps_n=None, no_ee=False,
-                    one_sided_vs=False, presel=None, safeguard=False):
+                    one_sided_vs=False, presel=None, safeguard=False, refine=0):
     """All contact candidates of one body pair (A, B) in world coordinates.
 
     Returns dict of p [C,3], nu [C,3] (pair convention, A -> B), d [C],
@@ -774,6 +793,15 @@ def pair_candidates(GA: OGeom, RA, tA, GB: OGeom, RB, tB, tau, lam=LAMBDA_DEFAUL
     # ---- edge-edge contacts over all |E_A| x |E_B| edge pairs (Sec. IV-D)
     qp = ee_qp(a0, a1, b0, b1, tau, lam)
     e1, e2, dbar, nbar = ee_witness(a0, a1, b0, b1, qp["al1"], qp["al2"], eps_n)
+    dbar_nn = dbar
+    if refine:
+        # witnesses traced onto their own bodies' smoothed surfaces (R19)
+        e1 = sphere_trace(GA, RA, tA, e1, tau, planesA, refine)
+        e2 = sphere_trace(GB, RB, tB, e2, tau, planesB, refine)
+        de = e1 - e2
+        dsq = _dot(de, de)
+        dbar = torch.sqrt(dsq)
+        nbar = de / torch.sqrt(dsq + eps_n)[..., None]
 
     # SDF queries at the witness points
     phiB_e1, _ = sdf_world(GB, RB, tB, e1, tau, planesB)
@@ -789,7 +817,7 @@ def pair_candidates(GA: OGeom, RA, tA, GB: OGeom, RB, tB, tau, lam=LAMBDA_DEFAUL
     log_pen1 = log_sigmoid(-phiB_e1 / tau)
     log_pen2 = log_sigmoid(-phiA_e2 / tau)
     log_cl = log_sigmoid(-_dot(gA_e1, gB_e2) / tau)
-    log_nn1, log_nn2 = nn_log_indicators(dbar, tau)
+    log_nn1, log_nn2 = nn_log_indicators(dbar_nn, tau)
     # activity indicator Gamma_b = con * pen_b * nn_b * cl, in the log domain
     logG1 = qp["log_con"] + log_pen1 + log_nn1 + log_cl
     logG2 = qp["log_con"] + log_pen2 + log_nn2 + log_cl
@@ -844,12 +872,12 @@ def manifold(c, tau, K: int):
 
 
 def collide_pair(GA, poseA, GB, poseB, tau, K, lam=LAMBDA_DEFAULT, eps_n=None, xiA=None, xiB=None,
-                 exact_exp=False, no_ee=False, one_sided_vs=False, presel=None, safeguard=False):
+                 exact_exp=False, no_ee=False, one_sided_vs=False, presel=None, safeguard=False, refine=0):
     """Contact manifold g_{A,B} of one pair (Sec. IV-A): K x (p, nu, d, w)."""
     RA, tA = pose_Rt(poseA, xiA, exact_exp)
     RB, tB = pose_Rt(poseB, xiB, exact_exp)
     c = pair_candidates(GA, RA, tA, GB, RB, tB, tau, lam, eps_n, no_ee=no_ee, one_sided_vs=one_sided_vs,
-                        presel=presel, safeguard=safeguard)
+                        presel=presel, safeguard=safeguard, refine=refine)
     return manifold(c, tau, K)
 
 
@@ -931,7 +959,7 @@ class GeomCache:
 
 
 def collide_batch(batch, pair_list=None, lam=LAMBDA_DEFAULT, eps_n=None, margin=None, cache=None, no_ee=False,
-                  one_sided_vs=False, presel=None, safeguard=False):
+                  one_sided_vs=False, presel=None, safeguard=False, refine=0):
     """Forward manifold for the kept pairs of a batch (or a given pair subset).
 
     Returns (pairs [2,n], offsets [S+1], outputs dict of numpy float64 arrays
@@ -949,14 +977,15 @@ def collide_batch(batch, pair_list=None, lam=LAMBDA_DEFAULT, eps_n=None, margin=
             a, b = int(pairs[0, i]), int(pairs[1, i])
             GA, GB = cache[batch.body_geom[a]], cache[batch.body_geom[b]]
             m = collide_pair(GA, batch.pose[:, a], GB, batch.pose[:, b], batch.tau, K, lam, eps_n,
-                             no_ee=no_ee, one_sided_vs=one_sided_vs, presel=presel, safeguard=safeguard)
+                             no_ee=no_ee, one_sided_vs=one_sided_vs, presel=presel, safeguard=safeguard,
+                             refine=refine)
             for k in ("p", "nu", "d", "w"):
                 out[k][i] = m[k].numpy()
     return pairs, offsets, out
 
 
 def pair_grad(GA, poseA, GB, poseB, tau, K, cot, lam=LAMBDA_DEFAULT, eps_n=None, no_ee=False, one_sided_vs=False,
-              presel=None, safeguard=False):
+              presel=None, safeguard=False, refine=0):
     """Gradient of L = <cot, outputs> for one pair by autograd of the forward
     (with presel, also through the SoftSort selection weights and metrics).
 
@@ -970,7 +999,7 @@ def pair_grad(GA, poseA, GB, poseB, tau, K, cot, lam=LAMBDA_DEFAULT, eps_n=None,
     xiB = torch.zeros(6, dtype=DT, requires_grad=True)
     tau_t = torch.tensor(float(tau), dtype=DT, requires_grad=True)
     m = collide_pair(GA, poseA, GB, poseB, tau_t, K, lam, eps_n, xiA, xiB, no_ee=no_ee, one_sided_vs=one_sided_vs,
-                     presel=presel, safeguard=safeguard)
+                     presel=presel, safeguard=safeguard, refine=refine)
     L = torch.zeros((), dtype=DT)
     for k, v in cot.items():
         L = L + (m[k] * torch.as_tensor(np.asarray(v, dtype=np.float64))).sum()

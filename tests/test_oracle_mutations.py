@@ -102,6 +102,11 @@ MUTATIONS = [
     ("sq_union_mesh", "inside = [(j != i) and bool(f[j] < 1.0) for j in range(M)]",
      "inside = [(j != i) and bool(f[j] > 1.0) for j in range(M)]",
      [P.pin_sq_surface_and_mesh]),                                                     # pruned the outside
+    ("sphere_trace", "x = x - phi[..., None] * n", "x = x + phi[..., None] * n",
+     [P.pin_sphere_trace_metric_one_step, P.pin_sphere_trace_polytope_converges]),      # steps away
+    ("pair_candidates", "e1 = sphere_trace(GA, RA, tA, e1, tau, planesA, refine)",
+     "e1 = sphere_trace(GB, RB, tB, e1, tau, planesB, refine)",
+     [P.pin_refined_witnesses_on_own_surfaces]),                                       # traced on the wrong body
 ]
 
 
