@@ -103,7 +103,19 @@ typedef struct {
   uint32_t flags;     /* CM_FLAG_* below, 0 = the full method */
   int32_t presel_vertices;  /* soft top-K pre-selection: K_V, K_E per body, */
   int32_t presel_edges;     /* 1..CM_MAX_PRESEL each; both 0 = off (below)  */
+  int32_t refine_steps;     /* witness sphere tracing: 0 = off, 1..CM_MAX_REFINE (below) */
 } cm_params;
+
+/* Witness sphere tracing (supplementary material, refinement of the witness
+ * points by sphere tracing).  With refine_steps > 0 each E-E witness is moved
+ * onto its own body's smoothed surface: along the fixed unit direction of
+ * grad phi at the QP witness, x <- x - phi(x) n, refine_steps times; the
+ * contact point, distance, normal and the sign / penetration / clashing tests
+ * use the moved points, the nearest-neighbour ranking keeps the QP
+ * distances.  cm_collide and served forward requests take it with K <= 16;
+ * cm_collide_fused, cm_collide_backward and served backward requests return
+ * CM_ERR_INVALID_ARG for it. */
+#define CM_MAX_REFINE 8
 
 /* Simplifications the paper evaluates for speed (supplementary material,
  * possible simplifications): CM_FLAG_NO_EE drops the edge-edge candidates

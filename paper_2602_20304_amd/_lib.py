@@ -22,7 +22,8 @@ f32p = C.POINTER(C.c_float)
 
 class cm_params(C.Structure):
     _fields_ = [("tau", C.c_float), ("lambda_reg", C.c_float), ("eps_n", C.c_float), ("cull_margin", C.c_float),
-                ("K", i32), ("flags", C.c_uint32), ("presel_vertices", i32), ("presel_edges", i32)]
+                ("K", i32), ("flags", C.c_uint32), ("presel_vertices", i32), ("presel_edges", i32),
+                ("refine_steps", i32)]
 
 
 class cm_batch(C.Structure):

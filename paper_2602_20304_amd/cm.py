@@ -132,12 +132,14 @@ FLAG_SAFEGUARD = 4      # with pre-selection: scale E-E activities by the inside
 
 
 def make_params(tau: float, K: int, lambda_reg: float = -1.0, eps_n: float = -1.0, cull_margin: float = -1.0,
-                flags: int = 0, presel=None):
-    """presel: None, or (K_V, K_E) for soft top-K pre-selection."""
+                flags: int = 0, presel=None, refine: int = 0):
+    """presel: None, or (K_V, K_E) for soft top-K pre-selection; refine:
+    sphere-tracing steps of the E-E witnesses (0 = off)."""
     p = L.cm_params()
     p.tau, p.K, p.lambda_reg, p.eps_n, p.cull_margin = float(tau), int(K), lambda_reg, eps_n, cull_margin
     p.flags = int(flags)
     p.presel_vertices, p.presel_edges = (0, 0) if presel is None else (int(presel[0]), int(presel[1]))
+    p.refine_steps = int(refine)
     return p
 
 
@@ -238,11 +240,11 @@ class Context:
     # ------------------------------------------------------------- forward
     def collide(self, db: DeviceBatch, tau: float, K: int, capacity: Optional[int] = None, out: Manifold = None,
                 fused: bool = False, stream=None, lambda_reg=-1.0, eps_n=-1.0, cull_margin=-1.0,
-                flags: int = 0, presel=None) -> Manifold:
+                flags: int = 0, presel=None, refine: int = 0) -> Manifold:
         if out is None:
             cap = db.n_cand_total if capacity is None else capacity
             out = Manifold.empty(db.n_scenes, cap, K, self.device)
-        prm = make_params(tau, K, lambda_reg, eps_n, cull_margin, flags, presel)
+        prm = make_params(tau, K, lambda_reg, eps_n, cull_margin, flags, presel, refine)
         b = db.as_c()
         m = out.as_c()
         fn = self.lib.cm_collide_fused if fused else self.lib.cm_collide
@@ -273,7 +275,8 @@ class Context:
     # ------------------------------------------------------------- backward
     def collide_backward(self, db: DeviceBatch, fwd: Manifold, tau: float, K: int, g_point=None, g_normal=None,
                          g_dist=None, g_weight=None, stream=None, want_vertices=True, want_params=True,
-                         lambda_reg=-1.0, eps_n=-1.0, cull_margin=-1.0, flags: int = 0, presel=None) -> dict:
+                         lambda_reg=-1.0, eps_n=-1.0, cull_margin=-1.0, flags: int = 0, presel=None,
+                         refine: int = 0) -> dict:
         """Vector-Jacobian product of the manifold for the given cotangents.
 
         Returns device tensors: pose [6, n_bodies] (left twists rho, omega),
@@ -291,7 +294,7 @@ class Context:
         cot.g_point, cot.g_normal, cot.g_dist, cot.g_weight = (_ptr(t) for t in (g_point, g_normal, g_dist, g_weight))
         gr = L.cm_grads()
         gr.g_pose, gr.g_vertices, gr.g_params, gr.g_tau = (_ptr(out[k]) for k in ("pose", "vertices", "params", "tau"))
-        prm = make_params(tau, K, lambda_reg, eps_n, cull_margin, flags, presel)
+        prm = make_params(tau, K, lambda_reg, eps_n, cull_margin, flags, presel, refine)
         b = db.as_c()
         m = fwd.as_c()
         self._check(self.lib.cm_collide_backward(self.h, C.byref(b), C.byref(prm), C.byref(m), C.byref(cot),
@@ -352,7 +355,7 @@ class Server:
         self._keep = {}
 
     def submit(self, body_offsets, body_geom, pose, tau: float, K: int, want_backward=False, cot_dist=None,
-               cot_normal=None, capacity: int = 0, flags: int = 0, presel=None) -> int:
+               cot_normal=None, capacity: int = 0, flags: int = 0, presel=None, refine: int = 0) -> int:
         """body_geom are context geometry ids; pose float32 [7, n_bodies]."""
         bo = np.ascontiguousarray(body_offsets, np.int32)
         bg = np.ascontiguousarray(body_geom, np.int32)
@@ -360,7 +363,7 @@ class Server:
         q = L.cm_request()
         q.n_scenes, q.n_bodies = len(bo) - 1, len(bg)
         q.body_offsets, q.body_geom, q.pose = _np_ptr(bo), _np_ptr(bg), _np_ptr(ps)
-        q.params = make_params(tau, K, flags=flags, presel=presel)
+        q.params = make_params(tau, K, flags=flags, presel=presel, refine=refine)
         q.want_backward = int(bool(want_backward))
         cd = None if cot_dist is None else np.ascontiguousarray(cot_dist, np.float32)
         cn = None if cot_normal is None else np.ascontiguousarray(cot_normal, np.float32)

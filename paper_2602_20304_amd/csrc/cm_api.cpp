@@ -256,6 +256,10 @@ cm_status resolve_params(cm_context* ctx, const cm_params* prm, ParamsDev* pd) {
   if (prm->K < 1 || prm->K > CM_MAX_K) return cm_fail(ctx, CM_ERR_INVALID_ARG, "K must be in 1..32");
   if (prm->flags & ~(CM_FLAG_NO_EE | CM_FLAG_ONE_SIDED_VS | CM_FLAG_SAFEGUARD))
     return cm_fail(ctx, CM_ERR_INVALID_ARG, "unknown flags");
+  if (prm->refine_steps < 0 || prm->refine_steps > CM_MAX_REFINE)
+    return cm_fail(ctx, CM_ERR_INVALID_ARG, "refine_steps must be in 0..8");
+  if (prm->refine_steps > 0 && prm->K > 16)
+    return cm_fail(ctx, CM_ERR_INVALID_ARG, "witness sphere tracing needs K <= 16");
   const bool presel = prm->presel_vertices != 0 || prm->presel_edges != 0;
   if (presel && (prm->presel_vertices < 1 || prm->presel_vertices > CM_MAX_PRESEL || prm->presel_edges < 1 ||
                  prm->presel_edges > CM_MAX_PRESEL))
@@ -277,6 +281,7 @@ cm_status resolve_params(cm_context* ctx, const cm_params* prm, ParamsDev* pd) {
   pd->presel_v = presel ? prm->presel_vertices : 0;
   pd->presel_e = presel ? prm->presel_edges : 0;
   pd->sq = ctx->has_sq ? 1 : 0;
+  pd->refine = prm->refine_steps;
   return CM_OK;
 }
 
@@ -323,6 +328,10 @@ cm_status ctx_prepare_fwd(cm_context* ctx, const BatchDev& bd, const ParamsDev& 
   f->block = block;
   f->kmax = kmax_for(pd.K);
   f->order = nullptr; f->range = nullptr; f->queue = dynamic ? reinterpret_cast<int*>(1) : nullptr;   // dispatch hint
+  const int lds = fwd_lds_bytes(f->maxV, f->maxE, f->maxF, block, f->kmax, pd.presel_v > 0);
+  if (lds > 160 * 1024)
+    return cm_fail(ctx, CM_ERR_INVALID_ARG, "the context's largest geometry needs " + std::to_string(lds) +
+                                                " B of LDS for this forward (160 KiB per workgroup)");
   f->err = ctx->d_err;
   const int occ = fwd_occupancy(*f);
   f->queue = nullptr;
@@ -462,6 +471,7 @@ extern "C" cm_status cm_collide_backward(cm_context* ctx, const cm_batch* batch,
   if (!cot || !out) return cm_fail(ctx, CM_ERR_INVALID_ARG, "null cotangent or gradient struct");
   if (pd.presel_v > 0 && (ctx->maxV > 4096 || ctx->maxE > 4096))
     return cm_fail(ctx, CM_ERR_INVALID_ARG, "pre-selection needs at most 4096 vertices and edges per body");
+  if (pd.refine > 0) return cm_fail(ctx, CM_ERR_INVALID_ARG, "the adjoint does not support witness sphere tracing");
   hipSetDevice(ctx->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
   const long long pool = (long long)ctx->h.vx.size();
@@ -485,6 +495,10 @@ extern "C" cm_status cm_collide_backward(cm_context* ctx, const cm_batch* batch,
   b.f.order = nullptr; b.f.range = nullptr; b.f.queue = nullptr; b.f.err = ctx->d_err;
   b.cot = CotDev{cot->g_point, cot->g_normal, cot->g_dist, cot->g_weight};
   b.gr = GradDev{out->g_pose, out->g_vertices, out->g_params, out->g_tau, pool};
+  const int lds = bwd_lds_bytes(b.f.maxV, b.f.maxE, b.f.maxF, 256, pd.presel_v > 0);
+  if (lds > 160 * 1024)
+    return cm_fail(ctx, CM_ERR_INVALID_ARG, "the context's largest geometry needs " + std::to_string(lds) +
+                                                " B of LDS for this adjoint (160 KiB per workgroup)");
   b.f.grid = std::max(1, bwd_occupancy(b) * ctx->num_cus);
   if (b.f.grid > od.capacity) b.f.grid = std::max(1, od.capacity);
   b.f.scratch_stride = fwd_scratch_floats(b.f.maxV, b.f.maxE);

@@ -642,26 +642,55 @@ struct Cand {
 // every active lane of the wave.  OWN_FULL: the edges are soft pre-selected
 // averages, which need not lie on their own bodies' surfaces, so the
 // own-body queries are full ones; safeguard then multiplies both activities
-// by sigma(-phi_A(e1)/tau) sigma(-phi_B(e2)/tau).
-template <bool OWN_FULL = false, bool SQ = false>
+// by sigma(-phi_A(e1)/tau) sigma(-phi_B(e2)/tau).  REFINE: each witness is
+// first traced onto its own body's smoothed surface (Supp., sphere tracing):
+// along the fixed unit direction of grad phi at the QP witness, x <- x -
+// phi(x) n, `steps` times; points, distances, normals and the sign /
+// penetration / clashing tests use the traced points, the nearest-neighbour
+// term keeps the QP distance, and every query visits all faces (a moved
+// point is outside what the segment's face masks bound).
+template <bool OWN_FULL = false, bool SQ = false, bool REFINE = false>
 __device__ __forceinline__ void ee_candidates(const D3& a0, const D3& t1, const D3& b0, const D3& t2, const EEQP& q,
                                               double row_lse, double col_lse, const BodyView& A, const BodyView& B,
                                               double eps_n, const Temp& T, const FaceMask* m1, const FaceMask* m2,
-                                              Cand& c1, Cand& c2, bool safeguard = false) {
-  const D3 e1 = d3(a0.x + q.al1 * t1.x, a0.y + q.al1 * t1.y, a0.z + q.al1 * t1.z);
-  const D3 e2 = d3(b0.x + q.al2 * t2.x, b0.y + q.al2 * t2.y, b0.z + q.al2 * t2.z);
-  const double dsq = dot(q.de, q.de);
-  const double dbar = sqrt(dsq);
+                                              Cand& c1, Cand& c2, bool safeguard = false, int steps = 0) {
+  D3 e1 = d3(a0.x + q.al1 * t1.x, a0.y + q.al1 * t1.y, a0.z + q.al1 * t1.z);
+  D3 e2 = d3(b0.x + q.al2 * t2.x, b0.y + q.al2 * t2.y, b0.z + q.al2 * t2.z);
+  const double dqp = sqrt(dot(q.de, q.de));   // the nearest-neighbour term's distance
+  D3 de = q.de;
+  if (REFINE) {
+    m1 = nullptr;
+    m2 = nullptr;
+    double ph;
+    D3 g, dg;
+    sdf_body<kFull, true, false, SQ>(A, e1, T, ph, g);
+    double in = rcp64(sqrt(dot(g, g)));
+    const D3 n1 = d3(g.x * in, g.y * in, g.z * in);
+    for (int s = 0; s < steps; ++s) {
+      if (s > 0) sdf_body<kValue, true, false, SQ>(A, e1, T, ph, dg);
+      e1 = d3(e1.x - ph * n1.x, e1.y - ph * n1.y, e1.z - ph * n1.z);
+    }
+    sdf_body<kFull, false, false, SQ>(B, e2, T, ph, g);
+    in = rcp64(sqrt(dot(g, g)));
+    const D3 n2 = d3(g.x * in, g.y * in, g.z * in);
+    for (int s = 0; s < steps; ++s) {
+      if (s > 0) sdf_body<kValue, false, false, SQ>(B, e2, T, ph, dg);
+      e2 = d3(e2.x - ph * n2.x, e2.y - ph * n2.y, e2.z - ph * n2.z);
+    }
+    de = d3(e1.x - e2.x, e1.y - e2.y, e1.z - e2.z);
+  }
+  const double dsq = dot(de, de);
+  const double dbar = REFINE ? sqrt(dsq) : dqp;
   const double in = rcp64(sqrt(dsq + eps_n));
-  const D3 nb = d3(q.de.x * in, q.de.y * in, q.de.z * in);
+  const D3 nb = d3(de.x * in, de.y * in, de.z * in);
   double phiB1, phiA2, dum;
   D3 gA, gB, dg;
   double phiA1 = 0.0, phiB2 = 0.0;
   sdf_body<kValue, false, false, SQ>(B, e1, T, phiB1, dg, m1 ? m1 + 1 : nullptr);
-  if (OWN_FULL) sdf_body<kFull, true, false, SQ>(A, e1, T, phiA1, gA, m1);
+  if (OWN_FULL || REFINE) sdf_body<kFull, true, false, SQ>(A, e1, T, phiA1, gA, m1);
   else sdf_body<kSurfGrad, true, false, SQ>(A, e1, T, dum, gA, m1);                   // e1 lies on an edge of A
   sdf_body<kValue, true, false, SQ>(A, e2, T, phiA2, dg, m2);
-  if (OWN_FULL) sdf_body<kFull, false, false, SQ>(B, e2, T, phiB2, gB, m2 ? m2 + 1 : nullptr);
+  if (OWN_FULL || REFINE) sdf_body<kFull, false, false, SQ>(B, e2, T, phiB2, gB, m2 ? m2 + 1 : nullptr);
   else sdf_body<kSurfGrad, false, false, SQ>(B, e2, T, dum, gB, m2 ? m2 + 1 : nullptr);   // e2 lies on an edge of B
   const double gam1 = tanh64(dot(gB, nb), T);
   const double gam2 = tanh64(-dot(gA, nb), T);
@@ -671,10 +700,10 @@ __device__ __forceinline__ void ee_candidates(const D3& a0, const D3& t1, const 
   const double lp2 = base + lsig(-phiA2, T);
   c1.d = gam1 * dbar;
   c2.d = gam2 * dbar;
-  c1.lw = lp1 + (row_lse - dbar) * T.inv_tau;
-  c2.lw = lp2 + (col_lse - dbar) * T.inv_tau;
-  c1.s = -c1.d + T.tau * lp1 + (row_lse - dbar);
-  c2.s = -c2.d + T.tau * lp2 + (col_lse - dbar);
+  c1.lw = lp1 + (row_lse - dqp) * T.inv_tau;
+  c2.lw = lp2 + (col_lse - dqp) * T.inv_tau;
+  c1.s = -c1.d + T.tau * lp1 + (row_lse - dqp);
+  c2.s = -c2.d + T.tau * lp2 + (col_lse - dqp);
   c1.p = e1;
   c2.p = e2;
   // witness 1: nu = -gam1 n_bar; witness 2: nu = gam2 (-n_bar)

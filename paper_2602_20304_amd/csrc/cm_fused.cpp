@@ -73,6 +73,7 @@ extern "C" cm_status cm_collide_fused(cm_context* ctx, const cm_batch* batch, co
   if ((s = resolve_params(ctx, prm, &pd)) != CM_OK) return s;
   if (pd.presel_v > 0) return cm_fail(ctx, CM_ERR_INVALID_ARG, "the fused path does not support pre-selection");
   if (pd.sq) return cm_fail(ctx, CM_ERR_INVALID_ARG, "the fused path does not support superquadric unions");
+  if (pd.refine > 0) return cm_fail(ctx, CM_ERR_INVALID_ARG, "the fused path does not support witness sphere tracing");
   if ((s = resolve_batch(ctx, batch, &bd)) != CM_OK) return s;
   if ((s = resolve_out(ctx, out, &od)) != CM_OK) return s;
   hipSetDevice(ctx->device);

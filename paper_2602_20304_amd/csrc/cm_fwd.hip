@@ -146,8 +146,8 @@ __global__ __launch_bounds__(256) void bp_emit(Tables tb, BatchDev bt, float mar
 // Occupancy target: 3 waves per SIMD (<= 168 VGPRs) for K <= 8, where the
 // per-lane top-K list is short enough to fit with a handful of spills; 2
 // otherwise.
-template <int BLOCK, int KMAX, bool DYN, bool PRESEL = false, bool SQ = false>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu((KMAX <= 8 && !SQ) ? 3 : 2)))
+template <int BLOCK, int KMAX, bool DYN, bool PRESEL = false, bool SQ = false, bool REFINE = false>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu((KMAX <= 8 && !SQ && !REFINE) ? 3 : 2)))
 void collide_fwd(Tables tb, BatchDev bt, ParamsDev prm, OutDev out,
                                                      float* __restrict__ scratch, long long scratch_stride, int maxV,
                                                      int maxE, int maxF, const int* __restrict__ order,
@@ -155,7 +155,7 @@ void collide_fwd(Tables tb, BatchDev bt, ParamsDev prm, OutDev out,
                                                      unsigned* err) {
   extern __shared__ float4 smem4[];
   __shared__ PairShared ps;
-  PairEngine<BLOCK, KMAX, true, PRESEL, SQ> P(ps, reinterpret_cast<char*>(smem4), tb, bt, prm,
+  PairEngine<BLOCK, KMAX, true, PRESEL, SQ, REFINE> P(ps, reinterpret_cast<char*>(smem4), tb, bt, prm,
                                           scratch + (long long)blockIdx.x * scratch_stride, maxV, maxE, maxF,
                                           PRESEL ? presel_lds_bytes(maxV, maxE) : 0);
   const int tid = threadIdx.x;
@@ -234,20 +234,20 @@ hipError_t launch_broadphase(const Tables& tb, const BatchDev& bt, float margin,
   return hipGetLastError();
 }
 
-template <int BLOCK, int KMAX, bool DYN, bool PRESEL = false, bool SQ = false>
+template <int BLOCK, int KMAX, bool DYN, bool PRESEL = false, bool SQ = false, bool REFINE = false>
 static hipError_t launch_fwd_t(const FwdLaunch& f, hipStream_t st) {
-  auto kern = collide_fwd<BLOCK, KMAX, DYN, PRESEL, SQ>;
+  auto kern = collide_fwd<BLOCK, KMAX, DYN, PRESEL, SQ, REFINE>;
   const int lds = fwd_lds_bytes(f.maxV, f.maxE, f.maxF, BLOCK, KMAX, PRESEL);
   hipLaunchKernelGGL(kern, dim3(f.grid), dim3(BLOCK), lds, st, f.tb, f.bt, f.prm, f.out, f.scratch,
                      f.scratch_stride, f.maxV, f.maxE, f.maxF, f.order, f.range, f.queue, f.err);
   return hipGetLastError();
 }
 
-template <int BLOCK, int KMAX, bool DYN, bool PRESEL = false, bool SQ = false>
+template <int BLOCK, int KMAX, bool DYN, bool PRESEL = false, bool SQ = false, bool REFINE = false>
 static int occ_t(int maxV, int maxE, int maxF) {
   int nb = 0;
   const int lds = fwd_lds_bytes(maxV, maxE, maxF, BLOCK, KMAX, PRESEL);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, collide_fwd<BLOCK, KMAX, DYN, PRESEL, SQ>, BLOCK, lds) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, collide_fwd<BLOCK, KMAX, DYN, PRESEL, SQ, REFINE>, BLOCK, lds) != hipSuccess)
     return 1;
   return nb > 0 ? nb : 1;
 }
@@ -266,7 +266,26 @@ static int occ_t(int maxV, int maxE, int maxF) {
 
 // Pre-selection and contexts that hold superquadric unions run in their own
 // instantiations (block 256, static order).
+// Sphere-traced witnesses: block 256, static order, K <= 16 (the paper's
+// manifolds are small; each refined candidate costs several SDF queries).
+template <bool PRESEL, bool SQ>
+static hipError_t launch_refine(const FwdLaunch& f, hipStream_t st) {
+  if (f.kmax == 8) return launch_fwd_t<256, 8, false, PRESEL, SQ, true>(f, st);
+  return launch_fwd_t<256, 16, false, PRESEL, SQ, true>(f, st);
+}
+template <bool PRESEL, bool SQ>
+static int occ_refine(const FwdLaunch& f) {
+  if (f.kmax == 8) return occ_t<256, 8, false, PRESEL, SQ, true>(f.maxV, f.maxE, f.maxF);
+  return occ_t<256, 16, false, PRESEL, SQ, true>(f.maxV, f.maxE, f.maxF);
+}
+
 hipError_t launch_collide_fwd(const FwdLaunch& f, hipStream_t st) {
+  if (f.prm.refine > 0) {
+    if (f.queue || f.block != 256 || f.kmax > 16 || f.maxV > 4096 || f.maxE > 4096) return hipErrorInvalidValue;
+    const bool ps = f.prm.presel_v > 0;
+    if (f.prm.sq) return ps ? launch_refine<true, true>(f, st) : launch_refine<false, true>(f, st);
+    return ps ? launch_refine<true, false>(f, st) : launch_refine<false, false>(f, st);
+  }
   if (f.prm.sq) {
     if (f.queue || f.block != 256 || f.maxV > 4096 || f.maxE > 4096) return hipErrorInvalidValue;
     const bool ps = f.prm.presel_v > 0;
@@ -291,6 +310,11 @@ hipError_t launch_collide_fwd(const FwdLaunch& f, hipStream_t st) {
 }
 
 int fwd_occupancy(const FwdLaunch& f) {
+  if (f.prm.refine > 0) {
+    const bool ps = f.prm.presel_v > 0;
+    if (f.prm.sq) return ps ? occ_refine<true, true>(f) : occ_refine<false, true>(f);
+    return ps ? occ_refine<true, false>(f) : occ_refine<false, false>(f);
+  }
   if (f.prm.sq) {
     const bool ps = f.prm.presel_v > 0;
     if (f.kmax == 8) return ps ? occ_t<256, 8, false, true, true>(f.maxV, f.maxE, f.maxF) : occ_t<256, 8, false, false, true>(f.maxV, f.maxE, f.maxF);

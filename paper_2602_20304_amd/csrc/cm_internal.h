@@ -52,6 +52,7 @@ struct ParamsDev {
   uint32_t flags;           // CM_FLAG_*
   int32_t presel_v, presel_e;   // soft top-K pre-selection sizes (0: off)
   int32_t sq;                   // the context holds superquadric unions (selects the kernels built for them)
+  int32_t refine;               // sphere-tracing steps of the E-E witnesses (0: off)
 };
 
 struct OutDev {

@@ -119,7 +119,7 @@ __host__ __device__ inline int presel_lds_bytes(int maxV, int maxE) {
 // edge pairs go row-major and every face is visited.  PRESEL: soft top-K
 // pre-selection (select()) replaces the bodies' vertices and edges by the
 // selected soft ones before the candidate passes.
-template <int BLOCK, int KMAX, bool CULL, bool PRESEL = false, bool SQ = false>
+template <int BLOCK, int KMAX, bool CULL, bool PRESEL = false, bool SQ = false, bool REFINE = false>
 struct PairEngine {
   static constexpr int NW = BLOCK / 64;
 
@@ -153,6 +153,7 @@ struct PairEngine {
   double* sSel;     // PRESEL: [4][CM_MAX_PRESEL] selected values of the four sets
   double* sSoft;    // PRESEL: soft vertices [2][CM_MAX_PRESEL][3], then soft edges [2][CM_MAX_PRESEL][6]
   int kv, ke;       // PRESEL: requested K_V, K_E
+  int refine;       // REFINE: sphere-tracing steps of the E-E witnesses
   Temp T;
   double lam, eps_n;
   unsigned flags;   // CM_FLAG_*
@@ -191,6 +192,7 @@ struct PairEngine {
     sSoft = sSel + 4 * CM_MAX_PRESEL;
     kv = prm.presel_v;
     ke = prm.presel_e;
+    refine = prm.refine;
     MW = CULL ? mask_words(maxF_) : 0;
     const long long mm = (long long)maxE_ * maxE_;
     Dbuf = reinterpret_cast<double*>(slot);
@@ -535,8 +537,8 @@ struct PairEngine {
     EB.get(l, b0, t2);
     const int i = k * B.ne + l;
     const EEQP q = ee_from_alpha(a0, t1, b0, t2, Al1[i], Al2[i], Lcon[i]);
-    ee_candidates<PRESEL, SQ>(a0, t1, b0, t2, q, sRow[k], sCol[l], A, B, eps_n, T, m1, m2, c1, c2,
-                          PRESEL && (flags & CM_FLAG_SAFEGUARD));
+    ee_candidates<PRESEL, SQ, REFINE>(a0, t1, b0, t2, q, sRow[k], sCol[l], A, B, eps_n, T, m1, m2, c1, c2,
+                                      PRESEL && (flags & CM_FLAG_SAFEGUARD), refine);
   }
   // candidate idx in the fixed order: A's vertices, B's vertices, E-E (k, l)
   // row-major with witness 1 before witness 2

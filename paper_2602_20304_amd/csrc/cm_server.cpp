@@ -271,6 +271,9 @@ cm_status cm_server_submit(cm_server* srv, const cm_request* q, uint64_t* ticket
                  q->params.presel_edges < 1 || q->params.presel_edges > CM_MAX_PRESEL))
     return CM_ERR_INVALID_ARG;
   if ((q->params.flags & CM_FLAG_SAFEGUARD) && !presel) return CM_ERR_INVALID_ARG;
+  if (q->params.refine_steps < 0 || q->params.refine_steps > CM_MAX_REFINE ||
+      (q->params.refine_steps > 0 && (q->want_backward || q->params.K > 16)))
+    return CM_ERR_INVALID_ARG;
   auto r = std::make_unique<Request>();
   r->n_scenes = q->n_scenes;
   r->n_bodies = q->n_bodies;
@@ -301,6 +304,7 @@ cm_status cm_server_submit(cm_server* srv, const cm_request* q, uint64_t* ticket
   f.prm.presel_v = presel ? q->params.presel_vertices : 0;   // selects the kernel whose occupancy applies
   f.prm.presel_e = presel ? q->params.presel_edges : 0;
   f.prm.sq = srv->ctx->has_sq ? 1 : 0;
+  f.prm.refine = q->params.refine_steps;
   const long long grid = request_grid(srv->ctx, fwd_occupancy(f), cap);
   r->footprint = footprint(srv->ctx, *r, grid, fwd_scratch_floats(f.maxV, f.maxE));
   if (r->footprint > srv->budget) return cm_fail(srv->ctx, CM_ERR_REJECTED, "request exceeds the HBM budget");

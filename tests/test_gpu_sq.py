@@ -122,16 +122,38 @@ def test_sq_fused_refused(ctx):
 # above 1 the derivative of the normal field is unbounded on a primitive's
 # axis planes, where mesh edges lie.
 
-def test_sq_backward_small_unions(ctx):
+# (each in a fresh context: the adjoint's LDS is sized by the context's
+# largest geometry, and the 18-primitive bodies above leave no room for the
+# pre-selection adjoint's arrays)
+
+@pytest.fixture
+def fresh():
+    from paper_2602_20304_amd.cm import Context
+    return Context(0)
+
+
+def test_sq_backward_small_unions(fresh):
     from tests.test_gpu_backward import check as grad_check
-    grad_check(ctx, W.sq_scenes(8, seed=11, n_prims=3, n_geoms=3, eps=(0.3, 1.0)))
+    grad_check(fresh, W.sq_scenes(8, seed=11, n_prims=3, n_geoms=3, eps=(0.3, 1.0)))
 
 
-def test_sq_backward_with_other_types(ctx):
+def test_sq_backward_with_other_types(fresh):
     from tests.test_gpu_backward import check as grad_check
-    grad_check(ctx, mixed_with_sq(6, seed=13, eps=(0.3, 1.0)))
+    grad_check(fresh, mixed_with_sq(6, seed=13, eps=(0.3, 1.0)))
 
 
-def test_sq_backward_preselected_safeguard(ctx):
+def test_sq_backward_preselected_safeguard(fresh):
     from tests.test_gpu_backward import check as grad_check
-    grad_check(ctx, W.sq_scenes(8, seed=12, n_prims=5, n_geoms=2, eps=(0.3, 1.0)), flags=4, presel=(16, 10))
+    grad_check(fresh, W.sq_scenes(8, seed=12, n_prims=5, n_geoms=2, eps=(0.3, 1.0)), flags=4, presel=(16, 10))
+
+
+def test_sq_adjoint_lds_overflow_reported(ctx):
+    """After the 18-primitive bodies, the pre-selection adjoint's LDS would
+    exceed 160 KiB: a clear CM_ERR_INVALID_ARG, not a failed launch."""
+    import torch
+    from paper_2602_20304_amd._lib import CMError
+    b = W.sq_scenes(4, seed=14)
+    ids, db, m = run(ctx, b, presel=(16, 10))
+    g = torch.zeros(m.dist.shape, device=ctx.device)
+    with pytest.raises(CMError, match="LDS"):
+        ctx.collide_backward(db, m, b.tau, b.K, None, None, g, None, presel=(16, 10))
