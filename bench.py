@@ -15,6 +15,7 @@ Legs, all in one process on the same inputs:
   fwd_bwd   cm_collide + cm_collide_backward with random cotangents
   plain_ne, plain_ne_s     the no-E-E / one-sided simplification flags
   plain_presel, fwd_bwd_presel   soft top-K pre-selection (K_V 64, K_E 18)
+  plain_refine  E-E witnesses sphere-traced onto the smoothed surfaces (3 steps)
   serving   a short Poisson request stream through cm_server_* (p50 / p99)
 The headline value is the forward throughput of --path (fused by default).
 
@@ -340,7 +341,7 @@ def main():
                          "with soft top-K pre-selection (presel)")
     ap.add_argument("--only", default=None,
                     choices=[None, "plain", "fused", "fwd_bwd", "plain_ne", "plain_ne_s", "plain_presel",
-                             "fwd_bwd_presel"],
+                             "fwd_bwd_presel", "plain_refine"],
                     help="run one leg only (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (PMC byte calibration)")
@@ -390,15 +391,17 @@ def main():
     # meshes here) and the K_E = 18 deepest edges per body
     leg_presel = {"plain_presel": (64, 18), "fwd_bwd_presel": (64, 18)}
 
+    leg_refine = {"plain_refine": 3}
+
     def step(leg):
         ctx.collide(db, batch.tau, batch.K, out=out, fused=(leg == "fused"), stream=stream,
-                    flags=leg_flags.get(leg, 0), presel=leg_presel.get(leg))
+                    flags=leg_flags.get(leg, 0), presel=leg_presel.get(leg), refine=leg_refine.get(leg, 0))
         if leg in ("fwd_bwd", "fwd_bwd_presel"):
             ctx.collide_backward(db, out, batch.tau, batch.K, None, cot_n, cot_d, None, stream=stream,
                                  presel=leg_presel.get(leg))
 
     legs = ["plain", "fused"] + ([] if args.no_bwd else ["fwd_bwd"])
-    legs += [] if args.no_simplifications else ["plain_ne", "plain_ne_s", "plain_presel"]
+    legs += [] if args.no_simplifications else ["plain_ne", "plain_ne_s", "plain_presel", "plain_refine"]
     legs += [] if (args.no_simplifications or args.no_bwd) else ["fwd_bwd_presel"]
     if args.only:
         legs = [args.only]
@@ -489,6 +492,9 @@ def main():
         if "fwd_bwd" in results and "fwd_bwd_presel" in results:
             line["preselection"]["fwd_bwd_speedup_vs_all_pairs"] = (results["fwd_bwd"]["ms"]
                                                                     / results["fwd_bwd_presel"]["ms"])
+    if "plain" in results and "plain_refine" in results:
+        line["witness_refinement"] = {"steps": leg_refine["plain_refine"],
+                                      "cost_vs_plain": results["plain_refine"]["ms"] / results["plain"]["ms"]}
     if args.serve and not args.only:
         log(f"serving leg: {args.serve} requests ...")
         line["serving"] = serving_leg(Context, args.serve)
