@@ -67,6 +67,11 @@ Readings where the paper is silent or garbled (each is listed in the design doc):
       x <- x - phi(x) n, a fixed number of steps; points, distances,
       normals and the sign, penetration and clashing tests then use the moved
       points, while the nearest-neighbour ranking keeps the QP distances
+  R20 oriented point clouds (Sec. IV-B, OPC primitives): the radial basis is
+      B_j(x - p_j; sigma_j) = exp(-|x - p_j|^2 / (2 sigma_j^2)) (the paper
+      names the interpolant, not its kernel); normals are unit-normalised;
+      the body's mesh is the point set with the edges of its 4-nearest-
+      neighbour graph (ties by index); bound = max |p_j| + max sigma_j
 """
 from __future__ import annotations
 
@@ -79,7 +84,8 @@ import torch
 from scipy.spatial import ConvexHull
 
 DT = torch.float64
-SPHERE, CAPSULE, BOX, POLYTOPE, SQ_UNION = 0, 1, 2, 3, 4
+SPHERE, CAPSULE, BOX, POLYTOPE, SQ_UNION, OPC = 0, 1, 2, 3, 4, 5
+OPC_KNN = 4
 LAMBDA_DEFAULT = 0.01
 
 
@@ -367,6 +373,44 @@ def sq_points(rec, which):
     return torch.stack(out)
 
 
+def opc_unpack(rec):
+    """Oriented point records [N, 9] (p, n, sigma, 0, 0) -> p [N, 3], unit
+    n [N, 3], sigma [N]."""
+    p, n, sg = rec[:, 0:3], rec[:, 3:6], rec[:, 6]
+    return p, n / torch.sqrt((n * n).sum(-1, keepdim=True)), sg
+
+
+def opc_sdf(rec, x):
+    """Radial-basis SDF of an oriented point cloud at body-frame points x
+    [..., 3] (Sec. IV-B, OPC primitives; reading R20):
+    phi = sum_j B_j n_j . (x - p_j) / sum_j B_j with Gaussian B_j, and its
+    gradient by the quotient rule."""
+    p, n, sg = opc_unpack(rec)
+    d = x[..., None, :] - p                                   # [..., N, 3]
+    h = (d * n).sum(-1)                                       # n_j . (x - p_j)
+    lb = -(d * d).sum(-1) / (2.0 * sg * sg)                   # log B_j
+    w = torch.softmax(lb, dim=-1)                             # B_j / sum B
+    phi = (w * h).sum(-1)
+    dlb = -d / (sg * sg)[:, None]                             # grad log B_j
+    grad = (w[..., None] * (n + dlb * (h - phi[..., None])[..., None])).sum(-2)
+    return phi, grad
+
+
+def opc_knn_edges(p_np, k=OPC_KNN):
+    """Edges of the k-nearest-neighbour graph of the points (R20): i -- j
+    when j is among the k nearest of i (squared distances, ties by the lower
+    index), undirected, unique, sorted."""
+    P = np.asarray(p_np, dtype=np.float64)
+    es = set()
+    for i in range(len(P)):
+        d2 = ((P - P[i]) ** 2).sum(-1)
+        d2[i] = np.inf
+        order = sorted(range(len(P)), key=lambda j: (d2[j], j))[:min(k, len(P) - 1)]
+        for j in order:
+            es.add((min(i, j), max(i, j)))
+    return np.array(sorted(es), dtype=np.int64).reshape(-1, 2)
+
+
 @dataclass
 class OGeom:
     """Oracle geometry: type, differentiable parameters and mesh topology.
@@ -383,6 +427,7 @@ class OGeom:
     tris: Optional[np.ndarray] = None       # [F, 3]
     _aux: Optional[np.ndarray] = None
     sq: Optional[torch.Tensor] = None       # [M, 12] superquadric records (SQ_UNION)
+    opc: Optional[torch.Tensor] = None      # [N, 9] oriented point records (OPC)
 
     def vertices(self) -> torch.Tensor:
         """Mesh vertices in the body frame (Sec. IV-A: every surface has a mesh)."""
@@ -390,6 +435,8 @@ class OGeom:
             return self.points
         if self.kind == SQ_UNION:
             return sq_points(self.sq, self._aux)
+        if self.kind == OPC:
+            return self.opc[:, 0:3]
         p = self.params
         if self.kind == SPHERE:
             return p[0] * _t(self._aux)
@@ -412,6 +459,9 @@ class OGeom:
 
 
 def make_geom(kind: int, params=None, points=None, requires_grad=False) -> OGeom:
+    if kind == OPC:
+        rec = np.asarray(points, dtype=np.float64).reshape(-1, 9)
+        return OGeom(kind, params=_t(np.zeros(4)), edges=opc_knn_edges(rec[:, 0:3]), opc=_t(rec, requires_grad))
     if kind == SQ_UNION:
         rec = np.asarray(points, dtype=np.float64).reshape(-1, 12)
         keep, edges = sq_union_mesh(rec)
@@ -455,6 +505,9 @@ def sdf_local(G: OGeom, x: torch.Tensor, tau, planes=None, chunk: int = 1 << 22,
     if G.kind == SQ_UNION:
         phi, g, nd = sq_union_sdf(G.sq, x, tau)
         return (phi, g, nd) if with_ndir else (phi, g)
+    if G.kind == OPC:
+        phi, g = opc_sdf(G.opc, x)
+        return (phi, g, g) if with_ndir else (phi, g)
     if with_ndir:
         phi, g = sdf_local(G, x, tau, planes, chunk)
         return phi, g, g
@@ -893,6 +946,10 @@ def bound_radius_f32(kind: int, params, points) -> np.float32:
     """
     f = np.float32
     p = np.asarray(params, dtype=np.float32)
+    if kind == OPC:
+        r = np.asarray(points, dtype=np.float32).reshape(-1, 9)
+        n2 = (r[:, 0] * r[:, 0] + r[:, 1] * r[:, 1]) + r[:, 2] * r[:, 2]
+        return np.float32(np.sqrt(n2.max(), dtype=np.float32) + r[:, 6].max())
     if kind == SQ_UNION:
         r = np.asarray(points, dtype=np.float32).reshape(-1, 12)
         tn = np.sqrt((r[:, 5] * r[:, 5] + r[:, 6] * r[:, 6]) + r[:, 7] * r[:, 7], dtype=np.float32)

@@ -107,6 +107,16 @@ MUTATIONS = [
     ("pair_candidates", "e1 = sphere_trace(GA, RA, tA, e1, tau, planesA, refine)",
      "e1 = sphere_trace(GB, RB, tB, e1, tau, planesB, refine)",
      [P.pin_refined_witnesses_on_own_surfaces]),                                       # traced on the wrong body
+    ("opc_sdf", "grad = (w[..., None] * (n + dlb * (h - phi[..., None])[..., None])).sum(-2)",
+     "grad = (w[..., None] * n).sum(-2)",
+     [P.pin_opc_gradient_fd]),                                                         # dropped weight derivative
+    ("opc_sdf", "lb = -(d * d).sum(-1) / (2.0 * sg * sg)", "lb = -(d * d).sum(-1) / (sg * sg)",
+     [P.pin_opc_gradient_fd]),                                                         # kernel width
+    ("opc_sdf", "h = (d * n).sum(-1)", "h = -(d * n).sum(-1)",
+     [P.pin_opc_single_point_and_plane]),                                              # inward normals
+    ("opc_knn_edges", "order = sorted(range(len(P)), key=lambda j: (d2[j], j))[:min(k, len(P) - 1)]",
+     "order = sorted(range(len(P)), key=lambda j: (d2[j], j))[:min(k + 1, len(P) - 1)]",
+     [P.pin_opc_knn_edges]),                                                           # k + 1 neighbours
 ]
 
 

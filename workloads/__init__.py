@@ -31,7 +31,7 @@ from typing import Optional
 
 import numpy as np
 
-SPHERE, CAPSULE, BOX, POLYTOPE, SQ_UNION = 0, 1, 2, 3, 4
+SPHERE, CAPSULE, BOX, POLYTOPE, SQ_UNION, OPC = 0, 1, 2, 3, 4, 5
 BOX_ROUNDING = 0.02
 
 
@@ -467,3 +467,44 @@ def sq_scenes(n_scenes: int = 4096, seed: int = 0, tau: float = 0.01, K: int = 8
     q = uniform_quats(rng, nb)
     offs = (np.arange(n_scenes + 1) * bodies).astype(np.int32)
     return Batch(gs, offs, body_geom, _pose_array(q, t), tau, K, name="sq_scenes")
+
+
+# ----------------------------------------------------------------------------- oriented point clouds
+
+def opc_torus_records(rng: np.random.Generator, nu: int = 16, nv: int = 8) -> np.ndarray:
+    """A torus (a non-convex surface) as an oriented point cloud: major radius
+    U[0.25, 0.35], minor U[0.08, 0.14], nu x nv grid samples with their exact
+    normals and bandwidth sigma = 0.5 x the minor-circle spacing; 3 xyz rows
+    per point (position, normal, (sigma, 0, 0))."""
+    R, r = rng.uniform(0.25, 0.35), rng.uniform(0.08, 0.14)
+    u = 2 * np.pi * (np.arange(nu) + rng.uniform()) / nu
+    v = 2 * np.pi * (np.arange(nv) + rng.uniform()) / nv
+    U, V = np.meshgrid(u, v, indexing="ij")
+    U, V = U.reshape(-1), V.reshape(-1)
+    p = np.stack([(R + r * np.cos(V)) * np.cos(U), (R + r * np.cos(V)) * np.sin(U), r * np.sin(V)], axis=1)
+    n = np.stack([np.cos(V) * np.cos(U), np.cos(V) * np.sin(U), np.sin(V)], axis=1)
+    sg = np.full((len(p), 1), 0.5 * 2 * np.pi * r / nv)
+    rec = np.concatenate([p, n, sg, np.zeros((len(p), 2))], axis=1)
+    return rec.reshape(-1, 3).astype(np.float32)
+
+
+def opc_scenes(n_scenes: int = 1024, seed: int = 0, tau: float = 0.01, K: int = 8, n_geoms: int = 4,
+               nu: int = 16, nv: int = 8, with_analytic: bool = True) -> Batch:
+    """Pairs of oriented-point-cloud tori (and, with_analytic, a sphere or
+    rounded box as a third body) with centres U[-0.35, 0.35]^3 so that the
+    tori interlock or touch, uniform rotations."""
+    rng = _rng(8, seed)
+    recs = [opc_torus_records(rng, nu, nv) for _ in range(n_geoms)]
+    types = [OPC] * n_geoms + ([SPHERE, BOX] if with_analytic else [])
+    params = [[0] * 4] * n_geoms + ([[0.12, 0, 0, 0], [0.1, 0.08, 0.12, BOX_ROUNDING]] if with_analytic else [])
+    gs = _geomset(types, params, recs + ([None, None] if with_analytic else []))
+    per = 3 if with_analytic else 2
+    nb = n_scenes * per
+    cols = [rng.integers(0, n_geoms, n_scenes), rng.integers(0, n_geoms, n_scenes)]
+    if with_analytic:
+        cols.append(rng.integers(n_geoms, n_geoms + 2, n_scenes))
+    body_geom = np.stack(cols, axis=1).reshape(-1).astype(np.int32)
+    t = rng.uniform(-0.35, 0.35, size=(nb, 3))
+    q = uniform_quats(rng, nb)
+    return Batch(gs, (np.arange(n_scenes + 1) * per).astype(np.int32), body_geom, _pose_array(q, t), tau, K,
+                 name="opc_scenes")
