@@ -277,8 +277,10 @@ def sq_leg(ctx_cls, steps: int = 5, scenes_presel: int = 4096, scenes_all: int =
     ctx = ctx_cls(0)
     stream = torch.cuda.current_stream()
     res = {}
-    for name, n, presel in (("presel_64_18", scenes_presel, (64, 18)), ("all_edge_pairs", scenes_all, None)):
-        b = W.sq_scenes(n, seed=3)
+    configs = (("presel_64_18", scenes_presel, (64, 18), "sq"), ("all_edge_pairs", scenes_all, None, "sq"),
+               ("opc_tori_all_edge_pairs", scenes_presel // 4, None, "opc"))
+    for name, n, presel, kind in configs:
+        b = W.sq_scenes(n, seed=3) if kind == "sq" else W.opc_scenes(n, seed=3)
         ids = ctx.create_geometry(b.geoms)
         db = ctx.upload_batch(b, ids)
         out = ctx.collide(db, b.tau, b.K, stream=stream, presel=presel)
@@ -302,7 +304,9 @@ def sq_leg(ctx_cls, steps: int = 5, scenes_presel: int = 4096, scenes_all: int =
                      "mesh_vertices": [i["n_vertices"] for i in info], "mesh_edges": [i["n_edges"] for i in info]}
         log(f"sq {name}: {ms:.3f} ms/step, {kept} kept pairs, {kept / (ms * 1e-3):.4g} pairs/s")
     res["config"] = ("2 bodies per scene from a pool of 8 smooth unions of 18 superquadrics (semi-axes U[0.07, 0.16], "
-                     "torso x2, exponents U[0.3, 1.5]), centres uniform in [-0.6, 0.6]^3, tau 0.01, K 8")
+                     "torso x2, exponents U[0.3, 1.5]), centres uniform in [-0.6, 0.6]^3, tau 0.01, K 8; "
+                     "opc_tori: 2 oriented-point-cloud tori (128 points, 4-NN mesh edges) and a sphere or rounded box "
+                     "per scene, centres uniform in [-0.35, 0.35]^3")
     return res
 
 

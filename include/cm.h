@@ -57,6 +57,16 @@
  *                   lie, so gradients there are ill-conditioned.
  *                   cm_collide_fused returns CM_ERR_INVALID_ARG for contexts
  *                   that hold them.
+ *       CM_OPC      oriented point cloud (Sec. IV-B, OPC primitives):
+ *                   phi = sum_j B_j n_j . (x - p_j) / sum_j B_j with the
+ *                   Gaussian basis B_j = exp(-|x - p_j|^2 / (2 sigma_j^2));
+ *                   1..CM_MAX_OPC points given as 3 xyz rows each in the
+ *                   point array: position, normal (normalised here),
+ *                   (sigma > 0, 0, 0).  Mesh: the points as vertices and the
+ *                   edges of their 4-nearest-neighbour graph.  Like
+ *                   superquadric unions: run by the kernels built for
+ *                   contexts holding either, no record gradient, no fused
+ *                   path.
  */
 #ifndef CM_H
 #define CM_H
@@ -79,8 +89,9 @@ typedef enum {
   CM_ERR_GEOMETRY = -8
 } cm_status;
 
-enum { CM_SPHERE = 0, CM_CAPSULE = 1, CM_BOX = 2, CM_POLYTOPE = 3, CM_SQ_UNION = 4 };
+enum { CM_SPHERE = 0, CM_CAPSULE = 1, CM_BOX = 2, CM_POLYTOPE = 3, CM_SQ_UNION = 4, CM_OPC = 5 };
 #define CM_MAX_SQ 32
+#define CM_MAX_OPC 512
 
 /* Largest K the kernels support. */
 #define CM_MAX_K 32

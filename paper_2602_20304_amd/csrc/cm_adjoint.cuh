@@ -156,6 +156,37 @@ __device__ __forceinline__ void sq_union_dual(const double4* __restrict__ sq, in
   gx = ax / S; gy = ay / S; gz = az / S;
 }
 
+// The oriented point cloud of sdf_opc over Dual4 inputs: phi and grad phi
+// with their derivatives (no tau dependence).
+__device__ __forceinline__ void opc_dual(const double4* __restrict__ pc, int nslots, const Dual4& lx, const Dual4& ly,
+                                         const Dual4& lz, Dual4& phi, Dual4& gx, Dual4& gy, Dual4& gz) {
+  const int N = nslots / 2;
+  double m = -INFINITY;
+  for (int j = 0; j < N; ++j) {
+    const double4 a = pc[2 * j];
+    const double dx = lx.v - a.x, dy = ly.v - a.y, dz = lz.v - a.z;
+    m = fmax(m, -(dx * dx + dy * dy + dz * dz) * a.w);
+  }
+  Dual4 S = dconst(0.0), A = dconst(0.0), nx = dconst(0.0), ny = dconst(0.0), nz = dconst(0.0);
+  Dual4 hx = dconst(0.0), hy = dconst(0.0), hz = dconst(0.0), qx = dconst(0.0), qy = dconst(0.0), qz = dconst(0.0);
+  for (int j = 0; j < N; ++j) {
+    const double4 a = pc[2 * j], b = pc[2 * j + 1];
+    const Dual4 dx = lx - dconst(a.x), dy = ly - dconst(a.y), dz = lz - dconst(a.z);
+    const Dual4 w = dexp((-a.w) * (dx * dx + dy * dy + dz * dz) - dconst(m));
+    const Dual4 h = b.x * dx + b.y * dy + b.z * dz;
+    S = S + w;
+    A = A + w * h;
+    nx = nx + b.x * w; ny = ny + b.y * w; nz = nz + b.z * w;
+    const Dual4 wq = (-b.w) * w;
+    qx = qx + wq * dx; qy = qy + wq * dy; qz = qz + wq * dz;
+    hx = hx + (wq * h) * dx; hy = hy + (wq * h) * dy; hz = hz + (wq * h) * dz;
+  }
+  phi = A / S;
+  gx = (nx + hx - phi * qx) / S;
+  gy = (ny + hy - phi * qy) / S;
+  gz = (nz + hz - phi * qz) / S;
+}
+
 // Gradient sinks of one body during the adjoint of a pair (LDS, float atomics).
 struct BodySink {
   float* plane;    // [4][maxF] adjoints of (n.xyz, o) in the body frame, or null
@@ -175,9 +206,12 @@ template <bool WAVE, bool SQ = false>
 __device__ __forceinline__ D3 sdf_local_bwd(int type, const float* p, const double4* __restrict__ pl, int nf, const D3& l,
                                             double phib, const D3& gb, const Temp& T, const BodySink& sink,
                                             double& taub, D3& g_out, bool ndir = false) {
-  if (SQ && type == CM_SQ_UNION) {
+  if (SQ && (type == CM_SQ_UNION || type == CM_OPC)) {
     Dual4 ph, gx, gy, gz;
-    sq_union_dual(pl, nf, dvar(l.x, 0), dvar(l.y, 1), dvar(l.z, 2), dvar(T.tau, 3), ndir, ph, gx, gy, gz);
+    if (type == CM_SQ_UNION)
+      sq_union_dual(pl, nf, dvar(l.x, 0), dvar(l.y, 1), dvar(l.z, 2), dvar(T.tau, 3), ndir, ph, gx, gy, gz);
+    else
+      opc_dual(pl, nf, dvar(l.x, 0), dvar(l.y, 1), dvar(l.z, 2), ph, gx, gy, gz);
     g_out = d3(gx.v, gy.v, gz.v);
     double o[4];
 #pragma unroll

@@ -146,10 +146,10 @@ cm_status cm_geometry_create(cm_context* ctx, int32_t n, const int32_t* types, c
   if (n == 0) return CM_OK;
   if (ctx->servers > 0) return cm_fail(ctx, CM_ERR_INVALID_ARG, "geometry is frozen while a server is running");
   for (int i = 0; i < n; ++i) {
-    if (types[i] < CM_SPHERE || types[i] > CM_SQ_UNION)
+    if (types[i] < CM_SPHERE || types[i] > CM_OPC)
       return cm_fail(ctx, CM_ERR_INVALID_ARG, "unknown geometry type");
-    if ((types[i] == CM_POLYTOPE || types[i] == CM_SQ_UNION) && (!pt_offsets || !points))
-      return cm_fail(ctx, CM_ERR_INVALID_ARG, "polytopes and superquadric unions need points");
+    if ((types[i] == CM_POLYTOPE || types[i] == CM_SQ_UNION || types[i] == CM_OPC) && (!pt_offsets || !points))
+      return cm_fail(ctx, CM_ERR_INVALID_ARG, "polytopes, superquadric unions and point clouds need points");
   }
   std::vector<HostMesh> meshes(n);
   std::vector<std::string> errs(n);
@@ -159,7 +159,7 @@ cm_status cm_geometry_create(cm_context* ctx, int32_t n, const int32_t* types, c
     for (int i = t; i < n; i += nt) {
       const float* pts = nullptr;
       int64_t np = 0;
-      if (types[i] == CM_POLYTOPE || types[i] == CM_SQ_UNION) {
+      if (types[i] == CM_POLYTOPE || types[i] == CM_SQ_UNION || types[i] == CM_OPC) {
         np = pt_offsets[i + 1] - pt_offsets[i];
         pts = points + 3 * pt_offsets[i];
       }
@@ -177,7 +177,7 @@ cm_status cm_geometry_create(cm_context* ctx, int32_t n, const int32_t* types, c
     for (int i = 0; i < n; ++i) {
       const float* pts = nullptr;
       int64_t np = 0;
-      if (types[i] == CM_POLYTOPE || types[i] == CM_SQ_UNION) { np = pt_offsets[i + 1] - pt_offsets[i]; pts = points + 3 * pt_offsets[i]; }
+      if (types[i] == CM_POLYTOPE || types[i] == CM_SQ_UNION || types[i] == CM_OPC) { np = pt_offsets[i + 1] - pt_offsets[i]; pts = points + 3 * pt_offsets[i]; }
       if (!build_mesh(types[i], params + 4 * i, pts, np, &meshes[i], &errs[i])) { bad = i; break; }
     }
   }
@@ -207,7 +207,7 @@ cm_status cm_geometry_create(cm_context* ctx, int32_t n, const int32_t* types, c
     ctx->maxV = std::max(ctx->maxV, r.nv);
     ctx->maxE = std::max(ctx->maxE, r.ne);
     ctx->maxF = std::max(ctx->maxF, r.nf);
-    if (r.type == CM_SQ_UNION) ctx->has_sq = true;
+    if (r.type == CM_SQ_UNION || r.type == CM_OPC) ctx->has_sq = true;   // extended primitives
     out_ids[i] = int32_t(h.recs.size());
     h.recs.push_back(r);
   }
@@ -221,7 +221,8 @@ cm_status cm_geometry_info(cm_context* ctx, int32_t id, cm_geometry_info_t* out)
   if (id < 0 || id >= int32_t(ctx->h.recs.size())) return cm_fail(ctx, CM_ERR_NOT_FOUND, "no such geometry");
   const GeomRec& r = ctx->h.recs[id];
   // a superquadric union keeps its primitives in the plane pool: no faces
-  out->type = r.type; out->n_vertices = r.nv; out->n_edges = r.ne; out->n_faces = r.type == CM_SQ_UNION ? 0 : r.nf;
+  out->type = r.type; out->n_vertices = r.nv; out->n_edges = r.ne;
+  out->n_faces = (r.type == CM_SQ_UNION || r.type == CM_OPC) ? 0 : r.nf;
   out->vertex_offset = r.v_off; out->bound_radius = r.bound_r;
   return CM_OK;
 }
@@ -237,7 +238,7 @@ cm_status cm_geometry_mesh(cm_context* ctx, int32_t id, float* vertices, int32_t
     vertices[3 * v + 2] = float(h.vz[r.v_off + v]);
   }
   if (edges) for (int e = 0; e < r.ne; ++e) { edges[2 * e] = h.e0[r.e_off + e]; edges[2 * e + 1] = h.e1[r.e_off + e]; }
-  if (faces && r.type != CM_SQ_UNION) for (int f = 0; f < r.nf; ++f) {
+  if (faces && r.type != CM_SQ_UNION && r.type != CM_OPC) for (int f = 0; f < r.nf; ++f) {
     faces[3 * f] = h.f0[r.f_off + f]; faces[3 * f + 1] = h.f1[r.f_off + f]; faces[3 * f + 2] = h.f2[r.f_off + f];
   }
   return CM_OK;

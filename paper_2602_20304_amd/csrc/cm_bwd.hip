@@ -125,7 +125,7 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
     }
     const BodyView& A = P.A;
     const BodyView& B = P.B;
-    if (!SQ && (A.type == CM_SQ_UNION || B.type == CM_SQ_UNION)) {   // not built for these: flagged, skipped
+    if (!SQ && (A.type >= CM_SQ_UNION || B.type >= CM_SQ_UNION)) {   // not built for these: flagged, skipped
       if (tid == 0) atomicOr(err, ERR_NO_ADJOINT);
       __syncthreads();
       continue;
@@ -664,7 +664,7 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
           atomicAdd(&ga.gr.g_vertices[ga.gr.pool + o], float(gb.y));
           atomicAdd(&ga.gr.g_vertices[2LL * ga.gr.pool + o], float(gb.z));
         }
-      } else if (G.type != CM_SQ_UNION) {   // no geometry gradient for superquadric unions
+      } else if (G.type < CM_SQ_UNION) {   // no record gradient for superquadric unions / point clouds
         float* pr = isA ? prA : prB;
         if (G.type == CM_SPHERE) {
           atomicAdd(&pr[0], float(dot(lv, gb) / double(G.p[0])));
@@ -719,7 +719,7 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
       const bool isA = tid < 4;
       const GeomRec& G = isA ? *P.GA : *P.GB;
       const int gid = isA ? ps.ga : ps.gb;
-      if (G.type != CM_POLYTOPE && G.type != CM_SQ_UNION)
+      if (G.type < CM_POLYTOPE)
         atomicAdd(&ga.gr.g_params[(tid & 3) * (long long)tb.n_geoms + gid], prA[tid]);
     }
     __syncthreads();

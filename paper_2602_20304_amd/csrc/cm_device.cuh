@@ -466,6 +466,41 @@ __device__ __forceinline__ void sdf_squnion(const double4* __restrict__ sq, int 
   }
 }
 
+// Oriented point cloud (Sec. IV-B, OPC primitives) at body-frame point l:
+// phi = sum_j B_j h_j / sum_j B_j with h_j = n_j . (l - p_j) and the Gaussian
+// basis B_j = exp(-|l - p_j|^2 / (2 sigma_j^2)), weights taken relative to
+// their maximum (two passes).  Each point is 2 staged double4: (p, 1 / (2
+// sigma^2)) and (unit n, 1 / sigma^2).  GRAD: grad phi by the quotient rule,
+// (sum_j B_j (n_j + g_j (h_j - phi))) / sum_j B_j with g_j = -(l - p_j) / sigma^2.
+template <bool GRAD>
+__device__ __forceinline__ void sdf_opc(const double4* __restrict__ pc, int nslots, const D3& l, double& phi, D3& g) {
+  const int N = nslots / 2;
+  double m = -INFINITY;
+  for (int j = 0; j < N; ++j) {
+    const double4 a = pc[2 * j];
+    const double dx = l.x - a.x, dy = l.y - a.y, dz = l.z - a.z;
+    m = fmax(m, -fma(dx, dx, fma(dy, dy, dz * dz)) * a.w);
+  }
+  double S = 0.0, A = 0.0, nx = 0.0, ny = 0.0, nz = 0.0, hx = 0.0, hy = 0.0, hz = 0.0, qx = 0.0, qy = 0.0, qz = 0.0;
+  for (int j = 0; j < N; ++j) {
+    const double4 a = pc[2 * j], b = pc[2 * j + 1];
+    const double dx = l.x - a.x, dy = l.y - a.y, dz = l.z - a.z;
+    const double w = exp64n(-fma(dx, dx, fma(dy, dy, dz * dz)) * a.w - m);
+    const double h = fma(b.x, dx, fma(b.y, dy, b.z * dz));
+    S += w;
+    A = fma(w, h, A);
+    if (GRAD) {
+      nx = fma(w, b.x, nx); ny = fma(w, b.y, ny); nz = fma(w, b.z, nz);
+      const double wq = -w * b.w;   // w * g_j / (l - p_j)
+      qx = fma(wq, dx, qx); qy = fma(wq, dy, qy); qz = fma(wq, dz, qz);
+      hx = fma(wq * h, dx, hx); hy = fma(wq * h, dy, hy); hz = fma(wq * h, dz, hz);
+    }
+  }
+  const double iS = 1.0 / S;
+  phi = A * iS;
+  if (GRAD) g = d3((nx + hx - phi * qx) * iS, (ny + hy - phi * qy) * iS, (nz + hz - phi * qz) * iS);
+}
+
 // SDF value of a body at a pair-frame point with a float64 LSE for
 // polytopes (float64 weights and logarithm): the pre-selection metrics, whose
 // differences are divided by tau in the selection weights.  IDENT: the body
@@ -482,6 +517,12 @@ __device__ __forceinline__ double sdf_value64(const BodyView& B, const D3& x, co
     double phi;
     D3 g;
     sdf_squnion<false, false>(B.planes, B.nf, l, T, phi, g);
+    return phi;
+  }
+  if (SQ && B.type == CM_OPC) {
+    double phi;
+    D3 g;
+    sdf_opc<false>(B.planes, B.nf, l, phi, g);
     return phi;
   }
   if (B.type != CM_POLYTOPE) {
@@ -508,9 +549,10 @@ __device__ __forceinline__ double sdf_value64(const BodyView& B, const D3& x, co
 // for polytopes).  IDENT: the body is A, whose frame is the pair frame.
 // mk: face subset for polytopes, shared by every active lane of the wave
 // (null or mk->n == 0: all faces).  NDIR: for superquadric unions return the
-// V-S normal direction (from grad f) instead of grad phi.  SQ: superquadric
-// unions are handled (only the kernels built for contexts that hold them:
-// the union loop would raise every call site's register pressure).
+// V-S normal direction (from grad f) instead of grad phi.  SQ: the extended
+// primitives (superquadric unions, oriented point clouds) are handled, in
+// the kernels built for contexts that hold them only (their loops would
+// raise every call site's register pressure).
 template <int MODE, bool IDENT, bool NDIR = false, bool SQ = false>
 __device__ __forceinline__ void sdf_body(const BodyView& B, const D3& x, const Temp& T, double& phi, D3& g,
                                          const FaceMask* mk = nullptr) {
@@ -526,6 +568,8 @@ __device__ __forceinline__ void sdf_body(const BodyView& B, const D3& x, const T
     else sdf_poly<MODE>(B.planes, B.nf, l, T, phi, lg);
   } else if (SQ && B.type == CM_SQ_UNION) {
     sdf_squnion<MODE != kValue, NDIR>(B.planes, B.nf, l, T, phi, lg);
+  } else if (SQ && B.type == CM_OPC) {
+    sdf_opc<MODE != kValue>(B.planes, B.nf, l, phi, lg);
   } else {
     sdf_analytic(B.type, B.p, l, phi, lg);
   }

@@ -300,8 +300,9 @@ struct PairEngine {
       const int j = isA ? i : i - nfA;
       // planes pre-scaled by c = log2(e) / tau (the polytope SDF works in
       // binary-exponent units)
-      // (superquadric-union records are staged as they are)
-      const double c = (isA ? A.type : B.type) == CM_SQ_UNION ? 1.0 : T.c;
+      // (superquadric-union and point-cloud records are staged as they are)
+      const int ty = isA ? A.type : B.type;
+      const double c = (ty == CM_SQ_UNION || ty == CM_OPC) ? 1.0 : T.c;
       (isA ? sPA : sPB)[j] = make_double4(c * tb.fnx[f], c * tb.fny[f], c * tb.fnz[f], c * tb.fo[f]);
     }
     __syncthreads();

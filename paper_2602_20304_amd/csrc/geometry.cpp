@@ -10,6 +10,7 @@
 #include <cstring>
 #include <string>
 #include <unordered_set>
+#include <utility>
 
 #include "cm_internal.h"
 
@@ -110,6 +111,8 @@ void sq_sample(const SqPrim& P, int k, double* out) {
   }
   for (int i = 0; i < 3; ++i) out[i] = P.R[3 * i] * c[0] + P.R[3 * i + 1] * c[1] + P.R[3 * i + 2] * c[2] + P.t[i];
 }
+
+constexpr int kOpcKnn = 4;   // mesh edges of an oriented point cloud: k-nearest-neighbour graph
 
 }  // namespace
 
@@ -427,6 +430,51 @@ bool build_mesh(int32_t type, const float* params, const float* pts, int64_t n_p
       for (int k = 0; k < 15; ++k) m.f.push_back(0);
     }
     m.bound_r = bound;
+    return true;
+  }
+  if (type == CM_OPC) {
+    if (n_pts % 3 != 0 || n_pts < 3 || n_pts / 3 > CM_MAX_OPC) {
+      *err = "oriented point cloud needs 1.." + std::to_string(CM_MAX_OPC) + " points of 3 xyz rows";
+      return false;
+    }
+    const int N = int(n_pts / 3);
+    float mx = 0.f, smax = 0.f;
+    for (int j = 0; j < N; ++j) {
+      const float* r = pts + 9 * j;
+      for (int k = 0; k < 7; ++k)
+        if (!std::isfinite(r[k])) { *err = "non-finite oriented point"; return false; }
+      const double nn = std::sqrt(double(r[3]) * r[3] + double(r[4]) * r[4] + double(r[5]) * r[5]);
+      if (!(r[6] > 0.f) || !(nn > 0)) { *err = "oriented point needs sigma > 0 and a nonzero normal"; return false; }
+      push_v(r[0], r[1], r[2]);
+      mx = std::max(mx, (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]);
+      smax = std::max(smax, r[6]);
+      const double sg = r[6];
+      // device records: (p, 1 / (2 sigma^2)) and (unit n, 1 / sigma^2); face ids unused
+      const double slot[8] = {double(r[0]), double(r[1]), double(r[2]), 1.0 / (2.0 * sg * sg),
+                              r[3] / nn, r[4] / nn, r[5] / nn, 1.0 / (sg * sg)};
+      for (int k = 0; k < 8; ++k) { m.pd.push_back(slot[k]); m.planes.push_back(float(slot[k])); }
+      for (int k = 0; k < 6; ++k) m.f.push_back(0);
+    }
+    // mesh edges: the undirected k-nearest-neighbour graph (ties by index)
+    const std::vector<double>& P = m.vd;
+    std::vector<std::pair<int, int>> es;
+    std::vector<std::pair<double, int>> d2(N);
+    const int k = std::min(kOpcKnn, N - 1);
+    for (int i = 0; i < N; ++i) {
+      for (int j = 0; j < N; ++j) {
+        const double dx = P[3 * j] - P[3 * i], dy = P[3 * j + 1] - P[3 * i + 1], dz = P[3 * j + 2] - P[3 * i + 2];
+        d2[j] = {j == i ? HUGE_VAL : (dx * dx + dy * dy) + dz * dz, j};
+      }
+      std::partial_sort(d2.begin(), d2.begin() + k, d2.end());
+      for (int q = 0; q < k; ++q) {
+        const int j = d2[q].second;
+        es.push_back({std::min(i, j), std::max(i, j)});
+      }
+    }
+    std::sort(es.begin(), es.end());
+    es.erase(std::unique(es.begin(), es.end()), es.end());
+    for (auto& e : es) push_e(e.first, e.second);
+    m.bound_r = std::sqrt(mx) + smax;
     return true;
   }
   *err = "unknown geometry type";

@@ -155,3 +155,24 @@ def test_invalid_sq_union_rejected(shim):
     for r in (bad_eps, bad_axis, bad_q):
         assert build_sq(shim, r.reshape(-1, 3))[0] is None
     assert build_sq(shim, rec.reshape(-1, 3)[:7])[0] is None         # not 4 rows per primitive
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_opc_meshes_match_oracle(shim, seed):
+    """Oriented point clouds: the points are the vertices, the edges the
+    undirected 4-nearest-neighbour graph, the float32 bound bit for bit."""
+    rec = W.opc_torus_records(W._rng(8, seed))
+    P = np.ascontiguousarray(rec, np.float32)
+    N = len(P) // 3
+    v = np.zeros(3 * N, np.float32); e = np.zeros(2 * 4 * N, np.int32); f = np.zeros(3 * 2 * N, np.int32)
+    pl = np.zeros(4 * 2 * N, np.float32); nv = C.c_int(); ne = C.c_int(); nf = C.c_int(); br = C.c_float()
+    err = C.create_string_buffer(256)
+    ptr = lambda a: a.ctypes.data_as(C.c_void_p)
+    ok = shim.shim_build_mesh(W.OPC, ptr(np.zeros(4, np.float32)), ptr(P), C.c_long(len(P)), ptr(v), C.byref(nv),
+                              ptr(e), C.byref(ne), ptr(f), C.byref(nf), ptr(pl), C.byref(br), err)
+    assert ok, err.value
+    G = O.make_geom(O.OPC, points=rec)
+    assert nv.value == N and nf.value == 2 * N
+    assert np.array_equal(v[:3 * N].reshape(-1, 3), rec.reshape(-1, 9)[:, 0:3])
+    assert np.array_equal(e[:2 * ne.value].reshape(-1, 2), G.edges.astype(np.int32))
+    assert np.float32(br.value) == O.bound_radius_f32(O.OPC, None, rec)
