@@ -345,7 +345,7 @@ def main():
                          "with soft top-K pre-selection (presel)")
     ap.add_argument("--only", default=None,
                     choices=[None, "plain", "fused", "fwd_bwd", "plain_ne", "plain_ne_s", "plain_presel",
-                             "fwd_bwd_presel", "plain_refine"],
+                             "fwd_bwd_presel", "plain_refine", "fused_presel"],
                     help="run one leg only (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (PMC byte calibration)")
@@ -393,19 +393,20 @@ def main():
     leg_flags = {"plain_ne": FLAG_NO_EE, "plain_ne_s": FLAG_NO_EE | FLAG_ONE_SIDED_VS}
     # the paper's benchmark shape: every vertex (K_V at its cap of 64 covers the
     # meshes here) and the K_E = 18 deepest edges per body
-    leg_presel = {"plain_presel": (64, 18), "fwd_bwd_presel": (64, 18)}
+    leg_presel = {"plain_presel": (64, 18), "fwd_bwd_presel": (64, 18), "fused_presel": (64, 18)}
 
     leg_refine = {"plain_refine": 3}
 
     def step(leg):
-        ctx.collide(db, batch.tau, batch.K, out=out, fused=(leg == "fused"), stream=stream,
+        ctx.collide(db, batch.tau, batch.K, out=out, fused=(leg in ("fused", "fused_presel")), stream=stream,
                     flags=leg_flags.get(leg, 0), presel=leg_presel.get(leg), refine=leg_refine.get(leg, 0))
         if leg in ("fwd_bwd", "fwd_bwd_presel"):
             ctx.collide_backward(db, out, batch.tau, batch.K, None, cot_n, cot_d, None, stream=stream,
                                  presel=leg_presel.get(leg))
 
     legs = ["plain", "fused"] + ([] if args.no_bwd else ["fwd_bwd"])
-    legs += [] if args.no_simplifications else ["plain_ne", "plain_ne_s", "plain_presel", "plain_refine"]
+    legs += [] if args.no_simplifications else ["plain_ne", "plain_ne_s", "plain_presel", "fused_presel",
+                                                "plain_refine"]
     legs += [] if (args.no_simplifications or args.no_bwd) else ["fwd_bwd_presel"]
     if args.only:
         legs = [args.only]
@@ -493,6 +494,9 @@ def main():
     if "plain" in results and "plain_presel" in results:
         line["preselection"] = {"presel": list(leg_presel["plain_presel"]),
                                 "speedup_vs_all_pairs": results["plain"]["ms"] / results["plain_presel"]["ms"]}
+        if "fused_presel" in results:
+            line["preselection"]["fused_speedup_vs_plain_presel"] = (results["plain_presel"]["ms"]
+                                                                     / results["fused_presel"]["ms"])
         if "fwd_bwd" in results and "fwd_bwd_presel" in results:
             line["preselection"]["fwd_bwd_speedup_vs_all_pairs"] = (results["fwd_bwd"]["ms"]
                                                                     / results["fwd_bwd_presel"]["ms"])

@@ -144,9 +144,9 @@ typedef struct {
  * (V-S over the selected vertices, E-E over the selected edge pairs).
  * CM_FLAG_SAFEGUARD additionally scales every E-E activity by the soft
  * indicators that both witness points lie inside their own bodies.
- * cm_collide, cm_collide_backward (whose gradient also runs through the
- * selection weights into every vertex's metric) and served requests take
- * it; cm_collide_fused returns CM_ERR_INVALID_ARG for it.  Bodies of at
+ * cm_collide, cm_collide_fused, cm_collide_backward (whose gradient also
+ * runs through the selection weights into every vertex's metric) and served
+ * requests take it.  Bodies of at
  * most 4096 vertices and edges (else CM_ERR_INVALID_ARG or CM_ERR_DEVICE). */
 #define CM_MAX_PRESEL 64
 #define CM_FLAG_SAFEGUARD 4u

@@ -294,8 +294,14 @@ hipError_t launch_collide_fwd(const FwdLaunch& f, hipStream_t st) {
     return ps ? launch_fwd_t<256, 32, false, true, true>(f, st) : launch_fwd_t<256, 32, false, false, true>(f, st);
   }
   if (f.prm.presel_v > 0) {
-    // the selection tracks taken items in a 64-bit mask per lane: <= 4096 per set
-    if (f.queue || f.block != 256 || f.maxV > 4096 || f.maxE > 4096) return hipErrorInvalidValue;
+    // the selection tracks taken items in a 64-bit mask per lane: <= 4096 per
+    // set; static order (cm_collide) or the fused path's work queue
+    if (f.block != 256 || f.maxV > 4096 || f.maxE > 4096) return hipErrorInvalidValue;
+    if (f.queue) {
+      if (f.kmax == 8) return launch_fwd_t<256, 8, true, true>(f, st);
+      if (f.kmax == 16) return launch_fwd_t<256, 16, true, true>(f, st);
+      return launch_fwd_t<256, 32, true, true>(f, st);
+    }
     if (f.kmax == 8) return launch_fwd_t<256, 8, false, true>(f, st);
     if (f.kmax == 16) return launch_fwd_t<256, 16, false, true>(f, st);
     return launch_fwd_t<256, 32, false, true>(f, st);
@@ -322,6 +328,11 @@ int fwd_occupancy(const FwdLaunch& f) {
     return ps ? occ_t<256, 32, false, true, true>(f.maxV, f.maxE, f.maxF) : occ_t<256, 32, false, false, true>(f.maxV, f.maxE, f.maxF);
   }
   if (f.prm.presel_v > 0) {
+    if (f.queue) {
+      if (f.kmax == 8) return occ_t<256, 8, true, true>(f.maxV, f.maxE, f.maxF);
+      if (f.kmax == 16) return occ_t<256, 16, true, true>(f.maxV, f.maxE, f.maxF);
+      return occ_t<256, 32, true, true>(f.maxV, f.maxE, f.maxF);
+    }
     if (f.kmax == 8) return occ_t<256, 8, false, true>(f.maxV, f.maxE, f.maxF);
     if (f.kmax == 16) return occ_t<256, 16, false, true>(f.maxV, f.maxE, f.maxF);
     return occ_t<256, 32, false, true>(f.maxV, f.maxE, f.maxF);

@@ -103,8 +103,6 @@ def test_presel_rejected_where_unsupported(ctx):
     ids = ctx.create_geometry(b.geoms)
     db = ctx.upload_batch(b, ids)
     with pytest.raises(CMError):
-        ctx.collide(db, b.tau, b.K, fused=True, presel=(4, 4))
-    with pytest.raises(CMError):
         ctx.collide(db, b.tau, b.K, presel=(0, 4))
     with pytest.raises(CMError):
         ctx.collide(db, b.tau, b.K, presel=(4, 65))
@@ -151,3 +149,18 @@ def test_presel_served_backward_matches_direct(ctx):
     assert np.abs(r["g_pose"] - ga).max() <= 1e-4 * (np.abs(ga).max() + 1e-6)
     srv.release(t)
     srv.close()
+
+
+def test_presel_fused_matches_plain_bitwise(ctx):
+    """The fused path (cost classes, work queues, replayed graph) with
+    pre-selection equals the plain kernel bit for bit, on two replays."""
+    b = W.mixed_scenes(64, seed=68)
+    ids = ctx.create_geometry(b.geoms)
+    db = ctx.upload_batch(b, ids)
+    _say(f"[gpu-presel] fused vs plain, presel=(16, 10), scenes={b.n_scenes}")
+    g1 = ctx.collide(db, b.tau, b.K, presel=(16, 10)).to_numpy()
+    for _ in range(2):
+        g2 = ctx.collide(db, b.tau, b.K, fused=True, presel=(16, 10)).to_numpy()
+        ctx.check_errors()
+        for k in ("pairs", "offsets", "p", "nu", "d", "w"):
+            assert np.array_equal(g1[k], g2[k]), k
