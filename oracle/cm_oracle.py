@@ -22,7 +22,7 @@ Sections of the paper followed (cited per function below):
   * Supp. C            smooth operator and E-E routine pseudo-code (used as a
                        description of what is computed, not transcribed)
 
-Readings where the paper is silent or garbled (each is listed in the design doc):
+Readings where the paper is silent or garbled:
   R1  unconstrained minimiser is -Q^{-1} c (the text drops the sign)
   R2  edge minimiser on alpha1 = 1 is -(Q12 + c2)/Q22 (text has a sign slip)
   R3  the cost of the (alpha1, 0) edge point is J evaluated there (the
