@@ -405,10 +405,17 @@ __device__ __forceinline__ double log2_64(double s) {
 // inside-outside function is f = ((s_x^2)^(1/eps2) + (s_y^2)^(1/eps2))^(eps2/eps1)
 // + (s_z^2)^(1/eps1) and phi_i = |y| (1 - f^(-eps1/2)); the union is
 // -LSE_tau(-phi_i), accumulated online (running minimum, rescaled sums).
-// Powers are float64 exp2 / log2 (the values feed weights divided by tau).
+// Powers use the float64 exp2_64 / log2_64 above (the values feed weights
+// divided by tau).
 // GRAD: also the union gradient, sum_i pi_i grad phi_i, or with NDIR the V-S
 // normal direction sum_i pi_i grad f_i (normals of superquadrics come from
 // grad f), pi = softmax(-phi_i / tau).
+// (s^2)^p for the superquadric powers, 0 at s = 0
+__device__ __forceinline__ double sqpow(double s, double p) {
+  const double s2 = s * s;
+  return s2 > 0.0 ? exp2_64(p * log2_64(s2)) : 0.0;
+}
+
 template <bool GRAD, bool NDIR>
 __device__ __forceinline__ void sdf_squnion(const double4* __restrict__ sq, int nslots, const D3& l, const Temp& T,
                                             double& phi, D3& g) {
@@ -422,13 +429,15 @@ __device__ __forceinline__ void sdf_squnion(const double4* __restrict__ sq, int 
     const double yz = fma(r2.x, dx, fma(r2.y, dy, r2.z * dz));
     const double sx = yx * s3.x, sy = yy * s3.y, sz = yz * s3.z;
     const double e1 = s3.w, ie2 = s4.x, r21 = s4.y, ie1 = s4.z;
-    // (s^2)^p = 2^(p log2 s^2): 0 at s = 0 (log2 0 = -inf)
-    const double Ax = exp2(ie2 * log2(sx * sx)), Ay = exp2(ie2 * log2(sy * sy)), Cz = exp2(ie1 * log2(sz * sz));
+    // (s^2)^p = 2^(p log2 s^2), 0 at s = 0 (the branch-free exp2_64 /
+    // log2_64 of this file: relative error ~1e-9, far inside what the
+    // weights' division by tau can amplify to a visible difference)
+    const double Ax = sqpow(sx, ie2), Ay = sqpow(sy, ie2), Cz = sqpow(sz, ie1);
     const double u = Ax + Ay;
-    const double U = exp2(r21 * log2(u));
+    const double U = u > 0.0 ? exp2_64(r21 * log2_64(u)) : 0.0;
     const double f = U + Cz;
     const double r = sqrt(fma(yx, yx, fma(yy, yy, yz * yz)));
-    const double q = exp2(-0.5 * e1 * log2(f));
+    const double q = exp2_64(-0.5 * e1 * log2_64(f));
     const double ph = r * (1.0 - q);
     double vx = 0.0, vy = 0.0, vz = 0.0;
     if (GRAD) {
@@ -459,7 +468,7 @@ __device__ __forceinline__ void sdf_squnion(const double4* __restrict__ sq, int 
       S += w; ax = fma(w, vx, ax); ay = fma(w, vy, ay); az = fma(w, vz, az);
     }
   }
-  phi = mn - T.tau * kLn2 * log2(S);
+  phi = mn - T.tau * kLn2 * log2_64(S);
   if (GRAD) {
     const double iS = 1.0 / S;
     g = d3(ax * iS, ay * iS, az * iS);
