@@ -55,8 +55,8 @@
  *                   exponents above 1 the normal field's derivative is
  *                   unbounded on a primitive's axis planes, where mesh edges
  *                   lie, so gradients there are ill-conditioned.
- *                   cm_collide_fused returns CM_ERR_INVALID_ARG for contexts
- *                   that hold them.
+ *                   Contexts that hold them run every forward (plain and
+ *                   fused) in 256-thread blocks.
  *       CM_OPC      oriented point cloud (Sec. IV-B, OPC primitives):
  *                   phi = sum_j B_j n_j . (x - p_j) / sum_j B_j with the
  *                   Gaussian basis B_j = exp(-|x - p_j|^2 / (2 sigma_j^2));
@@ -65,8 +65,7 @@
  *                   (sigma > 0, 0, 0).  Mesh: the points as vertices and the
  *                   edges of their 4-nearest-neighbour graph.  Like
  *                   superquadric unions: run by the kernels built for
- *                   contexts holding either, no record gradient, no fused
- *                   path.
+ *                   contexts holding either, no record gradient.
  */
 #ifndef CM_H
 #define CM_H

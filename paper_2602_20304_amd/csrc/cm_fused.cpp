@@ -47,7 +47,7 @@ FwdLaunch class_launch(cm_context* ctx, const BatchDev& bd, const ParamsDev& pd,
   f.tb = ctx_tables(ctx);
   f.bt = bd; f.prm = pd; f.out = od;
   f.maxV = ctx->cls_maxV[c]; f.maxE = ctx->cls_maxE[c]; f.maxF = ctx->cls_maxF[c];
-  f.block = pd.presel_v > 0 ? 256 : block;   // pre-selection kernels are built for 256-thread blocks
+  f.block = (pd.presel_v > 0 || pd.sq) ? 256 : block;   // those kernels are built for 256-thread blocks
   f.kmax = kmax_for(pd.K);
   f.order = w.order;
   f.range = w.ranges + 2 * c;
@@ -71,7 +71,6 @@ extern "C" cm_status cm_collide_fused(cm_context* ctx, const cm_batch* batch, co
   ParamsDev pd; BatchDev bd; OutDev od;
   cm_status s;
   if ((s = resolve_params(ctx, prm, &pd)) != CM_OK) return s;
-  if (pd.sq) return cm_fail(ctx, CM_ERR_INVALID_ARG, "the fused path does not support superquadric unions");
   if (pd.refine > 0) return cm_fail(ctx, CM_ERR_INVALID_ARG, "the fused path does not support witness sphere tracing");
   if ((s = resolve_batch(ctx, batch, &bd)) != CM_OK) return s;
   if ((s = resolve_out(ctx, out, &od)) != CM_OK) return s;
@@ -119,8 +118,9 @@ extern "C" cm_status cm_collide_fused(cm_context* ctx, const cm_batch* batch, co
   if (e != hipSuccess) return cm_hip(ctx, e, "tile sums");
 
   // autotune the block size of each class once per plan, on this batch
-  // (full-method calls only: pre-selection always runs 256-thread blocks)
-  if (!ctx->plan_tuned && od.capacity > 0 && pd.presel_v == 0) {
+  // (full-method calls on the basic primitives only: pre-selection and the
+  // extended primitives always run 256-thread blocks)
+  if (!ctx->plan_tuned && od.capacity > 0 && pd.presel_v == 0 && !pd.sq) {
     ctx->cls_block[0] = ctx->cls_block[1] = ctx->cls_block[2] = 256;
     if ((s = plan_scratch()) != CM_OK) return s;
     if ((e = record(st)) != hipSuccess) return cm_hip(ctx, e, "fused warm-up");

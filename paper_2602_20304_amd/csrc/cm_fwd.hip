@@ -279,6 +279,20 @@ static int occ_refine(const FwdLaunch& f) {
   return occ_t<256, 16, false, PRESEL, SQ, true>(f.maxV, f.maxE, f.maxF);
 }
 
+// The extended primitives (superquadric unions, point clouds): block 256.
+template <bool DYN, bool PRESEL>
+static hipError_t launch_sq_k(const FwdLaunch& f, hipStream_t st) {
+  if (f.kmax == 8) return launch_fwd_t<256, 8, DYN, PRESEL, true>(f, st);
+  if (f.kmax == 16) return launch_fwd_t<256, 16, DYN, PRESEL, true>(f, st);
+  return launch_fwd_t<256, 32, DYN, PRESEL, true>(f, st);
+}
+template <bool DYN, bool PRESEL>
+static int occ_sq_k(const FwdLaunch& f) {
+  if (f.kmax == 8) return occ_t<256, 8, DYN, PRESEL, true>(f.maxV, f.maxE, f.maxF);
+  if (f.kmax == 16) return occ_t<256, 16, DYN, PRESEL, true>(f.maxV, f.maxE, f.maxF);
+  return occ_t<256, 32, DYN, PRESEL, true>(f.maxV, f.maxE, f.maxF);
+}
+
 hipError_t launch_collide_fwd(const FwdLaunch& f, hipStream_t st) {
   if (f.prm.refine > 0) {
     if (f.queue || f.block != 256 || f.kmax > 16 || f.maxV > 4096 || f.maxE > 4096) return hipErrorInvalidValue;
@@ -286,12 +300,11 @@ hipError_t launch_collide_fwd(const FwdLaunch& f, hipStream_t st) {
     if (f.prm.sq) return ps ? launch_refine<true, true>(f, st) : launch_refine<false, true>(f, st);
     return ps ? launch_refine<true, false>(f, st) : launch_refine<false, false>(f, st);
   }
-  if (f.prm.sq) {
-    if (f.queue || f.block != 256 || f.maxV > 4096 || f.maxE > 4096) return hipErrorInvalidValue;
+  if (f.prm.sq) {   // static order (cm_collide) or the fused path's work queue
+    if (f.block != 256 || f.maxV > 4096 || f.maxE > 4096) return hipErrorInvalidValue;
     const bool ps = f.prm.presel_v > 0;
-    if (f.kmax == 8) return ps ? launch_fwd_t<256, 8, false, true, true>(f, st) : launch_fwd_t<256, 8, false, false, true>(f, st);
-    if (f.kmax == 16) return ps ? launch_fwd_t<256, 16, false, true, true>(f, st) : launch_fwd_t<256, 16, false, false, true>(f, st);
-    return ps ? launch_fwd_t<256, 32, false, true, true>(f, st) : launch_fwd_t<256, 32, false, false, true>(f, st);
+    if (f.queue) return ps ? launch_sq_k<true, true>(f, st) : launch_sq_k<true, false>(f, st);
+    return ps ? launch_sq_k<false, true>(f, st) : launch_sq_k<false, false>(f, st);
   }
   if (f.prm.presel_v > 0) {
     // the selection tracks taken items in a 64-bit mask per lane: <= 4096 per
@@ -323,9 +336,8 @@ int fwd_occupancy(const FwdLaunch& f) {
   }
   if (f.prm.sq) {
     const bool ps = f.prm.presel_v > 0;
-    if (f.kmax == 8) return ps ? occ_t<256, 8, false, true, true>(f.maxV, f.maxE, f.maxF) : occ_t<256, 8, false, false, true>(f.maxV, f.maxE, f.maxF);
-    if (f.kmax == 16) return ps ? occ_t<256, 16, false, true, true>(f.maxV, f.maxE, f.maxF) : occ_t<256, 16, false, false, true>(f.maxV, f.maxE, f.maxF);
-    return ps ? occ_t<256, 32, false, true, true>(f.maxV, f.maxE, f.maxF) : occ_t<256, 32, false, false, true>(f.maxV, f.maxE, f.maxF);
+    if (f.queue) return ps ? occ_sq_k<true, true>(f) : occ_sq_k<true, false>(f);
+    return ps ? occ_sq_k<false, true>(f) : occ_sq_k<false, false>(f);
   }
   if (f.prm.presel_v > 0) {
     if (f.queue) {

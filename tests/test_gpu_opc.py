@@ -54,3 +54,16 @@ def test_opc_preselected_and_traced(ctx):
 def test_opc_backward(ctx):
     from tests.test_gpu_backward import check as grad_check
     grad_check(ctx, W.opc_scenes(4, seed=3, nu=12, nv=6))
+
+
+def test_opc_fused_matches_plain_bitwise(ctx):
+    b = W.opc_scenes(24, seed=4)
+    ids = ctx.create_geometry(b.geoms)
+    db = ctx.upload_batch(b, ids)
+    _say(f"[gpu-opc] fused vs plain, scenes={b.n_scenes}")
+    g1 = ctx.collide(db, b.tau, b.K).to_numpy()
+    for _ in range(2):
+        g2 = ctx.collide(db, b.tau, b.K, fused=True).to_numpy()
+        ctx.check_errors()
+        for k in ("pairs", "offsets", "p", "nu", "d", "w"):
+            assert np.array_equal(g1[k], g2[k]), k
