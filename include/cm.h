@@ -243,9 +243,12 @@ int32_t cm_vertex_pool_size(cm_context* ctx);
 cm_status cm_collide(cm_context* ctx, const cm_batch* batch, const cm_params* prm, cm_manifold* out,
                      void* stream);
 
-/* Same results through the fused batched path: pairs are ordered by cost and
- * pulled from a device work queue by a persistent grid; the whole sequence is
- * captured once per (batch shape, stream) in a hipGraph and replayed. */
+/* Same results (bit for bit) through the fused batched path: pairs are
+ * ordered by cost into size classes and pulled from device work queues by
+ * persistent grids whose block sizes are autotuned once per plan; the whole
+ * sequence is captured once per (batch shape, parameters) in a hipGraph and
+ * replayed.  Takes pre-selection and the extended primitives; returns
+ * CM_ERR_INVALID_ARG for refine_steps > 0. */
 cm_status cm_collide_fused(cm_context* ctx, const cm_batch* batch, const cm_params* prm, cm_manifold* out,
                            void* stream);
 
