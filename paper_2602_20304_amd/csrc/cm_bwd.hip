@@ -400,11 +400,17 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
         gbar[3] = gBb;
       }
       // ---- stage 2: SDF adjoints, every lane of the wave together
-      // (a V-S slot's gradient adjoint refers to the V-S normal direction)
-      const D3 xb0 = sdf_body_bwd<true, true, SQ>(A, X[0], phib[0], gbar[0], T, sinkA, taub, tw, is_vs);
-      const D3 xb1 = sdf_body_bwd<true, false, SQ>(B, X[1], phib[1], gbar[1], T, sinkB, taub, tw, is_vs);
-      const D3 xb2 = sdf_body_bwd<true, true, SQ>(A, X[2], phib[2], gbar[2], T, sinkA, taub, tw);
-      const D3 xb3 = sdf_body_bwd<true, false, SQ>(B, X[3], phib[3], gbar[3], T, sinkB, taub, tw);
+      // (a V-S slot's gradient adjoint refers to the V-S normal direction);
+      // a slot whose adjoints are zero on every lane of the wave contributes
+      // nothing and is skipped (a wave-uniform test)
+      auto used = [](double ph, const D3& g) {
+        return __ballot(ph != 0.0 || g.x != 0.0 || g.y != 0.0 || g.z != 0.0) != 0ull;
+      };
+      const D3 zero = d3(0, 0, 0);
+      const D3 xb0 = used(phib[0], gbar[0]) ? sdf_body_bwd<true, true, SQ>(A, X[0], phib[0], gbar[0], T, sinkA, taub, tw, is_vs) : zero;
+      const D3 xb1 = used(phib[1], gbar[1]) ? sdf_body_bwd<true, false, SQ>(B, X[1], phib[1], gbar[1], T, sinkB, taub, tw, is_vs) : zero;
+      const D3 xb2 = used(phib[2], gbar[2]) ? sdf_body_bwd<true, true, SQ>(A, X[2], phib[2], gbar[2], T, sinkA, taub, tw) : zero;
+      const D3 xb3 = used(phib[3], gbar[3]) ? sdf_body_bwd<true, false, SQ>(B, X[3], phib[3], gbar[3], T, sinkB, taub, tw) : zero;
       if (!live) return;
       // ---- stage 3: back to vertices / edges
       if (is_vs) {
