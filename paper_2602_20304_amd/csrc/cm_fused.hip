@@ -25,6 +25,28 @@ __device__ __forceinline__ float pair_cost(const GeomRec& A, const GeomRec& B) {
   return float(A.ne) * float(B.ne) * (400.f + 2.f * (fa + fb)) + float(A.nv) * fb + float(B.nv) * fa;
 }
 
+// Wave-aggregated claim of one slot per lane at counter[key]: one atomic per
+// distinct key held by the wave's active lanes (leader = lowest pending
+// lane); each lane gets the counter's old value plus its rank among the
+// lanes holding the same key.  The loop runs once per distinct key and its
+// condition is wave-uniform (a ballot).
+__device__ __forceinline__ int wave_claim(int* __restrict__ counter, int key) {
+  const int lane = __lane_id();
+  unsigned long long pending = __ballot(1);
+  int slot = 0;
+  while (pending) {
+    const int leader = __builtin_ctzll(pending);
+    const int lk = __shfl(key, leader);
+    const unsigned long long same = __ballot(key == lk);
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&counter[lk], __popcll(same));
+    base = __shfl(base, leader);
+    if (key == lk) slot = base + __popcll(same & ((1ull << lane) - 1ull));
+    pending &= ~same;
+  }
+  return slot;
+}
+
 __global__ void fused_classify(Tables tb, BatchDev bt, OutDev out, int cmax0, int cmax1, int* __restrict__ counts,
                                int* __restrict__ keys) {
   const int n = min(*out.n_pairs, out.capacity);
@@ -40,11 +62,10 @@ __global__ void fused_classify(Tables tb, BatchDev bt, OutDev out, int cmax0, in
       int bucket = int(log2f(fmaxf(cost, 1.f)));
       bucket = min(max(bucket, 0), kNumBuckets - 1);
       key = c * kNumBuckets + (kNumBuckets - 1 - bucket);   // costly first
-      atomicAdd(&counts[key], 1);
     } else {
       key = kNumBuckets - 1;                                 // invalid: class 0, cheapest; flagged by the kernel
-      atomicAdd(&counts[key], 1);
     }
+    (void)wave_claim(counts, key);
     keys[i] = key;
   }
 }
@@ -71,7 +92,7 @@ __global__ void fused_scatter(OutDev out, const int* __restrict__ keys, int* __r
                               int* __restrict__ order) {
   const int n = min(*out.n_pairs, out.capacity);
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const int pos = atomicAdd(&cursors[keys[i]], 1);
+    const int pos = wave_claim(cursors, keys[i]);
     order[pos] = i;
   }
 }
