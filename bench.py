@@ -16,6 +16,7 @@ Legs, all in one process on the same inputs:
   plain_ne, plain_ne_s     the no-E-E / one-sided simplification flags
   plain_presel, fwd_bwd_presel   soft top-K pre-selection (K_V 64, K_E 18)
   plain_refine  E-E witnesses sphere-traced onto the smoothed surfaces (3 steps)
+  plain_presel_refine   the two together (tracing after pre-selection)
   serving   a short Poisson request stream through cm_server_* (p50 / p99)
 The headline value is the forward throughput of --path (fused by default).
 
@@ -345,7 +346,7 @@ def main():
                          "with soft top-K pre-selection (presel)")
     ap.add_argument("--only", default=None,
                     choices=[None, "plain", "fused", "fwd_bwd", "plain_ne", "plain_ne_s", "plain_presel",
-                             "fwd_bwd_presel", "plain_refine", "fused_presel"],
+                             "fwd_bwd_presel", "plain_refine", "fused_presel", "plain_presel_refine"],
                     help="run one leg only (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (PMC byte calibration)")
@@ -393,9 +394,10 @@ def main():
     leg_flags = {"plain_ne": FLAG_NO_EE, "plain_ne_s": FLAG_NO_EE | FLAG_ONE_SIDED_VS}
     # the paper's benchmark shape: every vertex (K_V at its cap of 64 covers the
     # meshes here) and the K_E = 18 deepest edges per body
-    leg_presel = {"plain_presel": (64, 18), "fwd_bwd_presel": (64, 18), "fused_presel": (64, 18)}
+    leg_presel = {"plain_presel": (64, 18), "fwd_bwd_presel": (64, 18), "fused_presel": (64, 18),
+                  "plain_presel_refine": (64, 18)}
 
-    leg_refine = {"plain_refine": 3}
+    leg_refine = {"plain_refine": 3, "plain_presel_refine": 3}
 
     def step(leg):
         ctx.collide(db, batch.tau, batch.K, out=out, fused=(leg in ("fused", "fused_presel")), stream=stream,
@@ -406,7 +408,7 @@ def main():
 
     legs = ["plain", "fused"] + ([] if args.no_bwd else ["fwd_bwd"])
     legs += [] if args.no_simplifications else ["plain_ne", "plain_ne_s", "plain_presel", "fused_presel",
-                                                "plain_refine"]
+                                                "plain_refine", "plain_presel_refine"]
     legs += [] if (args.no_simplifications or args.no_bwd) else ["fwd_bwd_presel"]
     if args.only:
         legs = [args.only]
@@ -503,6 +505,9 @@ def main():
     if "plain" in results and "plain_refine" in results:
         line["witness_refinement"] = {"steps": leg_refine["plain_refine"],
                                       "cost_vs_plain": results["plain_refine"]["ms"] / results["plain"]["ms"]}
+        if "plain_presel" in results and "plain_presel_refine" in results:
+            line["witness_refinement"]["presel_cost_vs_plain_presel"] = (results["plain_presel_refine"]["ms"]
+                                                                         / results["plain_presel"]["ms"])
     if args.serve and not args.only:
         log(f"serving leg: {args.serve} requests ...")
         line["serving"] = serving_leg(Context, args.serve)
