@@ -460,6 +460,15 @@ def main():
                     "peak": roof["peak_flops"] / 1e12, "unit": "TFLOP/s", "frac": roof["frac"],
                     "traffic": traffic, "kernel_ms": kms, "launches": k_n,
                     "ops_per_launch": {"fma": int(ops[0]), "alu": int(ops[1]), "trans": int(ops[2])}}
+        # the fused path does the same algorithmic work; its time is the whole
+        # replayed graph (broadphase, classification, class launches) timed
+        # with HIP events around the graph launch, so this rate is a lower
+        # bound for its pair kernel
+        f_ms, f_n = kernel["fused"]["fused"] if "fused" in kernel else (0.0, 0)
+        if f_n:
+            froof = opmodel.roofline(ops, f_ms / f_n * 1e-3)
+            roofline["fused_path"] = {"achieved": froof["achieved_flops"] / 1e12, "frac": froof["frac"],
+                                      "graph_ms": f_ms / f_n, "launches": f_n}
 
     legs_out = {}
     for k, v in results.items():
