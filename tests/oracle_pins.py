@@ -469,6 +469,145 @@ def pin_nn_rows_columns():
     assert torch.equal(torch.exp(l2).argmax(0), D.argmin(0))
 
 
+def _hard_face_gradient(eq, x, tie=1e-9, margin=1e-4):
+    """tau -> 0 gradient of a polytope's smoothed SDF at x from scipy's hull
+    facets: the mean outward normal of the facets whose planes attain the
+    largest value at x (a point on an edge or vertex ties its facets).  Also
+    returns that largest plane value and whether another facet lies within
+    `margin` of it without tying (a kink the limit cannot resolve)."""
+    v = eq[:, :3] @ x + eq[:, 3]
+    m = v.max()
+    tied = v >= m - tie
+    kink = bool(((v < m - tie) & (v > m - margin)).any())
+    return eq[tied, :3].mean(0), m, kink
+
+
+def _activity_hard_limit(seed, lam, tau=1e-7, margin=1e-4):
+    """One polytope pair: the oracle's E-E activities exp(log Gamma_b) beside
+    the product of independent hard indicators, and per-sample validity (every
+    factor at least `margin` from its kink)."""
+    from scipy.optimize import lsq_linear
+    from scipy.spatial import ConvexHull
+    rng = np.random.default_rng(700 + seed)
+    GA = O.make_geom(O.POLYTOPE, points=W.ellipsoid_points(rng, 14, rng.uniform(0.25, 0.45, 3)))
+    GB = O.make_geom(O.POLYTOPE, points=W.ellipsoid_points(rng, 13, rng.uniform(0.25, 0.45, 3)))
+    qA, qB = W.uniform_quats(rng, 2)
+    u = rng.normal(size=3)
+    u /= np.linalg.norm(u)
+    pA, pB = _pose(qA, [0, 0, 0]), _pose(qB, (0.2 + 0.1 * (seed % 5)) * u)
+    RA, tA = O.pose_Rt(pA)
+    RB, tB = O.pose_Rt(pB)
+    with torch.no_grad():
+        c = O.pair_candidates(GA, RA, tA, GB, RB, tB, tau, lam)
+        PA = (GA.vertices() @ RA.T + tA).numpy()
+        PB = (GB.vertices() @ RB.T + tB).numpy()
+    EA, EB = np.asarray(GA.edges), np.asarray(GB.edges)
+    nA, nB = len(EA), len(EB)
+    ex = c["extra"]
+    act = np.exp(c["logw"].numpy()[ex["n_vs"]:].reshape(nA, nB, 2))
+    eqA, eqB = ConvexHull(PA).equations, ConvexHull(PB).equations
+    dlA, dlB = Delaunay(PA), Delaunay(PB)
+    # hard witnesses: the regularised box QP solved by bounded-variable least
+    # squares (|M a - y|^2 = |e1 - e2|^2 + lam |a - 1/2|^2); the unconstrained
+    # minimiser by ordinary least squares
+    sl = math.sqrt(lam)
+    con = np.zeros((nA, nB))
+    side = np.zeros((nA, nB), int)
+    ok = np.ones((nA, nB), bool)
+    e1 = np.zeros((nA, nB, 3))
+    e2 = np.zeros((nA, nB, 3))
+    for k in range(nA):
+        a0, a1 = PA[EA[k, 0]], PA[EA[k, 1]]
+        for l in range(nB):
+            b0, b1 = PB[EB[l, 0]], PB[EB[l, 1]]
+            M = np.zeros((5, 2))
+            M[:3, 0], M[:3, 1], M[3, 0], M[4, 1] = a1 - a0, b0 - b1, sl, sl
+            y = np.concatenate([b0 - a0, [0.5 * sl, 0.5 * sl]])
+            au = np.linalg.lstsq(M, y, rcond=None)[0]
+            al = np.clip(lsq_linear(M, y, bounds=(0.0, 1.0), method="bvls", tol=1e-14).x, 0.0, 1.0)
+            e1[k, l], e2[k, l] = a0 + al[0] * (a1 - a0), b0 + al[1] * (b1 - b0)
+            con[k, l] = float(np.all((au > 0) & (au < 1)))
+            side[k, l] = -1 if (au < 0).any() else (1 if (au > 1).any() else 0)
+            ok[k, l] = np.minimum(np.abs(au), np.abs(au - 1)).min() >= margin
+    # a near tie of box-edge costs leaves the smoothed witness between two
+    # points even at tau = 1e-7; those samples (rare) are not limits
+    moved = (np.linalg.norm(ex["e1"].numpy() - e1, axis=-1) + np.linalg.norm(ex["e2"].numpy() - e2, axis=-1)) > 1e-6
+    assert moved.mean() < 0.03, moved.mean()
+    ok &= ~moved
+    # nearest neighbours: hard arg-min of each row (witness 1) / column (witness 2)
+    D = np.linalg.norm(e1 - e2, axis=-1)
+
+    def nn_hard(Dm):
+        idx = Dm.argmin(1)
+        gap = Dm - Dm.min(1, keepdims=True)
+        second = np.sort(Dm, axis=1)[:, 1] - Dm.min(1)
+        hard = np.zeros_like(Dm)
+        hard[np.arange(len(Dm)), idx] = 1.0
+        valid = (gap >= margin) | ((hard == 1.0) & (second[:, None] >= margin))
+        return hard, valid
+    nn1, okn1 = nn_hard(D)
+    nn2, okn2 = (m.T for m in nn_hard(D.T))
+    pen1, pen2, cl = (np.zeros((nA, nB)) for _ in range(3))
+    okp1, okp2, okc = (np.ones((nA, nB), bool) for _ in range(3))
+    for k in range(nA):
+        for l in range(nB):
+            x1, x2 = e1[k, l], e2[k, l]
+            gA, _, kinkA = _hard_face_gradient(eqA, x1)
+            gB, _, kinkB = _hard_face_gradient(eqB, x2)
+            mB1 = _hard_face_gradient(eqB, x1)[1]
+            mA2 = _hard_face_gradient(eqA, x2)[1]
+            pen1[k, l], okp1[k, l] = float(dlB.find_simplex(x1) >= 0), abs(mB1) > margin
+            pen2[k, l], okp2[k, l] = float(dlA.find_simplex(x2) >= 0), abs(mA2) > margin
+            dot = gA @ gB
+            cl[k, l], okc[k, l] = float(dot < 0), abs(dot) > margin and not (kinkA or kinkB)
+    return dict(act=act, con=con, side=side, pen1=pen1, pen2=pen2, nn1=nn1, nn2=nn2, cl=cl,
+                v1=ok & okn1 & okp1 & okc, v2=ok & okn2 & okp2 & okc, qp=ex["qp"])
+
+
+def pin_ee_activity_hard_limit():
+    """E-E activity Gamma_b = con * pen_b * nn_b * cl (Sec. IV-D-3) as tau -> 0
+    (1e-7, samples at least 1e-4 from every kink), factor by factor against
+    independent hard tests on pairs of 14- and 13-point hulls: con against
+    the unconstrained least-squares minimiser of the regularised QP lying
+    inside the box, pen_b against scipy's Delaunay location of the witness
+    (found by bounded-variable least squares) in the other hull, nn_b against
+    the arg-min along each row (witness 1) / column (witness 2) of the
+    witness distances, cl against the sign of the dot product of the two
+    hulls' facet normals at the witnesses.  The seeded pairs must include, for
+    every factor, samples where it alone is zero, and samples where the
+    row and column indicators differ, so that dropping or exchanging a
+    factor changes some activity from 1 to 0 or back.  A weak regulariser
+    (lam = 1e-3) makes box-edge minimisers common.  Also exp(log con) = con
+    at finite tau."""
+    cover = dict(con=0, pen=0, nn=0, cl=0, all=0, swap=0, below=0, above=0)
+    for seed in range(20):
+        r = _activity_hard_limit(seed, 1e-3)
+        G1 = r["con"] * r["pen1"] * r["nn1"] * r["cl"]
+        G2 = r["con"] * r["pen2"] * r["nn2"] * r["cl"]
+        assert r["v1"].mean() > 0.8 and r["v2"].mean() > 0.8
+        assert np.abs(r["act"][..., 0] - G1)[r["v1"]].max() < 1e-6, seed
+        assert np.abs(r["act"][..., 1] - G2)[r["v2"]].max() < 1e-6, seed
+        f = dict(con=r["con"], pen=r["pen1"], nn=r["nn1"], cl=r["cl"])
+        for name in f:
+            rest = np.prod([f[o] for o in f if o != name], axis=0)
+            cover[name] += int(((f[name] == 0) & (rest == 1) & r["v1"]).sum())
+        cover["all"] += int(((G1 == 1) & r["v1"]).sum())
+        both = r["v1"] & r["v2"] & (r["con"] * r["cl"] == 1) & (r["nn1"] != r["nn2"])
+        cover["swap"] += int((both & ((r["pen1"] == 1) | (r["pen2"] == 1))).sum())
+        rest = r["pen1"] * r["nn1"] * r["cl"]
+        cover["below"] += int(((r["side"] == -1) & (rest == 1) & r["v1"]).sum())
+        cover["above"] += int(((r["side"] == 1) & (rest == 1) & r["v1"]).sum())
+    assert min(cover.values()) >= 2, cover
+    # log con is the log of con (at finite tau, both sides of the box)
+    rng = np.random.default_rng(31)
+    E = np.array(_rand_edges(rng, 300)) * 2.0 - 0.5
+    with torch.no_grad():
+        for tau in (0.3, 0.05):
+            q = O.ee_qp(*(T(E[:, i]) for i in range(4)), tau, 0.01)
+            assert torch.allclose(torch.exp(q["log_con"]), q["con"], rtol=1e-12, atol=1e-300)
+            assert bool((q["au1"] < -0.5).any() and (q["au1"] > 1.5).any())
+
+
 def _rand_cands(rng, C=60):
     return dict(p=T(rng.normal(size=(C, 3))), nu=T(rng.normal(size=(C, 3))), d=T(rng.normal(0, 0.1, C)),
                 logw=T(-np.abs(rng.normal(0, 3, C))))

@@ -14,6 +14,10 @@ import pytest
 from oracle import cm_oracle as O
 from tests import oracle_pins as P
 
+# the activity products of the two E-E witnesses, as the oracle writes them
+_ACT = ('logG1 = qp["log_con"] + log_pen1 + log_nn1 + log_cl\n'
+        '    logG2 = qp["log_con"] + log_pen2 + log_nn2 + log_cl')
+
 # (oracle function, original text, mutated text, pins expected to catch it)
 MUTATIONS = [
     ("ee_qp", "au1 = (-c1 * Q22 + Q12 * c2) / det", "au1 = (c1 * Q22 - Q12 * c2) / det",
@@ -46,6 +50,21 @@ MUTATIONS = [
      [P.pin_vs_weights_point_in_polytope]),                                            # inverted pen test
     ("pair_candidates", "log_pen1 = log_sigmoid(-phiB_e1 / tau)", "log_pen1 = log_sigmoid(-phiA_e2 / tau)",
      [P.pin_pair_swap_antisymmetry]),                                                  # wrong SDF for pen
+    # symmetric mistakes in the activity product (both witnesses alike)
+    ("pair_candidates", _ACT, _ACT.replace('qp["log_con"] + ', ""),
+     [P.pin_ee_activity_hard_limit]),                                                  # dropped con
+    ("pair_candidates", _ACT, _ACT.replace("log_pen1 + ", "").replace("log_pen2 + ", ""),
+     [P.pin_ee_activity_hard_limit]),                                                  # dropped pen
+    ("pair_candidates", _ACT, _ACT.replace(" + log_cl", ""),
+     [P.pin_ee_activity_hard_limit]),                                                  # dropped cl
+    ("pair_candidates", _ACT, _ACT.replace("log_nn1 + ", "").replace("log_nn2 + ", ""),
+     [P.pin_ee_activity_hard_limit]),                                                  # dropped nn
+    ("pair_candidates", _ACT, _ACT.replace("log_nn1", "@").replace("log_nn2", "log_nn1").replace("@", "log_nn2"),
+     [P.pin_ee_activity_hard_limit]),                                                  # nn rows <-> columns
+    ("log_within_s", "return log_sigmoid((x - lo) / tau) + log_sigmoid((hi - x) / tau)",
+     "return log_sigmoid((x - lo) / tau)", [P.pin_ee_activity_hard_limit]),           # upper side dropped
+    ("log_within_s", "return log_sigmoid((x - lo) / tau) + log_sigmoid((hi - x) / tau)",
+     "return log_sigmoid((hi - x) / tau)", [P.pin_ee_activity_hard_limit]),           # lower side dropped
     ("manifold", "torch.softmax(-torch.abs(top[:, None] - s[None, :]) / tau, dim=1)",
      "torch.softmax(-(top[:, None] - s[None, :]) / tau, dim=1)",
      [P.pin_manifold_properties]),                                                     # SoftSort without |.|
