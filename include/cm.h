@@ -252,6 +252,27 @@ cm_status cm_collide(cm_context* ctx, const cm_batch* batch, const cm_params* pr
 cm_status cm_collide_fused(cm_context* ctx, const cm_batch* batch, const cm_params* prm, cm_manifold* out,
                            void* stream);
 
+/* For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, hosts that forbid hipMalloc): the same
+ * forward as cm_collide (same kernels, same arguments, bit-identical
+ * results), with every workspace -- the broadphase scan's tile sums and the
+ * per-workgroup scratch slots of the pair kernel -- taken from one static
+ * device array of CM_NOALLOC_SCRATCH_BYTES compiled into the library instead
+ * of the context's growable workspace.  It calls no hipMalloc / hipFree and
+ * records no timing events.  The array's device address is looked up once
+ * per device in cm_context_create; if that lookup failed, this call returns
+ * CM_ERR_DEVICE.  The pair kernel's grid shrinks to the number of
+ * workgroup slots that fit (fewer than cm_collide launches for large meshes,
+ * hence slower); a batch whose tile sums plus one slot exceed the array
+ * returns CM_ERR_CAPACITY with the sizes in cm_last_error.  Nothing in the
+ * array needs to start at zero.  Every call on one device shares that
+ * device's single array: calls that overlap in time on one device (several
+ * streams, contexts or threads) race and corrupt each other's results, so
+ * order them on one stream. */
+#define CM_NOALLOC_SCRATCH_BYTES (64u << 20)
+cm_status cm_collide_noalloc(cm_context* ctx, const cm_batch* batch, const cm_params* prm, cm_manifold* out,
+                             void* stream);
+
 /* ---------------------------------------------------------------- backward
  * Vector-Jacobian product of the manifold (the gradient the paper obtains by
  * automatic differentiation and times in Sec. V): recomputes every per-pair

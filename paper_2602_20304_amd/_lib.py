@@ -11,6 +11,7 @@ CM_OK = 0
 STATUS = {0: "CM_OK", -1: "CM_ERR_INVALID_ARG", -2: "CM_ERR_OOM", -3: "CM_ERR_DEVICE", -4: "CM_ERR_NOT_READY",
           -5: "CM_ERR_REJECTED", -6: "CM_ERR_NOT_FOUND", -7: "CM_ERR_CAPACITY", -8: "CM_ERR_GEOMETRY"}
 CM_MAX_K = 32
+CM_NOALLOC_SCRATCH_BYTES = 64 << 20
 TIMERS = {"broadphase": 0, "forward": 1, "backward": 2, "fused": 3, "ee_witness": 4}
 
 vp = C.c_void_p
@@ -75,6 +76,7 @@ SIGNATURES = {
     "cm_vertex_pool_size": (i32, [vp]),
     "cm_collide": (i32, [vp, C.POINTER(cm_batch), C.POINTER(cm_params), C.POINTER(cm_manifold), vp]),
     "cm_collide_fused": (i32, [vp, C.POINTER(cm_batch), C.POINTER(cm_params), C.POINTER(cm_manifold), vp]),
+    "cm_collide_noalloc": (i32, [vp, C.POINTER(cm_batch), C.POINTER(cm_params), C.POINTER(cm_manifold), vp]),
     "cm_collide_backward": (i32, [vp, C.POINTER(cm_batch), C.POINTER(cm_params), C.POINTER(cm_manifold),
                                   C.POINTER(cm_cotangent), C.POINTER(cm_grads), vp]),
     "cm_ee_witness": (i32, [vp, vp, C.c_int64, C.c_float, C.c_float, i32, vp, vp]),

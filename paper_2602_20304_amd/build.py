@@ -21,7 +21,19 @@ def sources():
     return hip, cpp
 
 
-def build(verbose: bool = False, jobs: int = 8) -> str:
+def _stale(src: str, obj: str) -> bool:
+    """An object is stale when it is older than its source or any header."""
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    heads = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".h", ".cuh"))]
+    heads.append(os.path.join(HERE, "..", "include", "cm.h"))
+    return any(os.path.getmtime(x) > t for x in [src] + heads)
+
+
+def build(verbose: bool = False, jobs: int = 8, incremental: bool = False) -> str:
+    """Compile every source (incremental=True: only objects older than their
+    source or any header) and link libcm.so."""
     hip, cpp = sources()
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
@@ -31,6 +43,8 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     for src in hip + cpp:
         obj = os.path.join(objdir, os.path.basename(src) + ".o")
         objs.append(obj)
+        if incremental and not _stale(src, obj):
+            continue
         if src.endswith(".hip"):
             cmd = ["hipcc", "-c", "-x", "hip", src, "-o", obj, "-I", CSRC] + HIP_FLAGS
         else:
@@ -59,4 +73,4 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, incremental="--incremental" in sys.argv)

@@ -240,14 +240,18 @@ class Context:
     # ------------------------------------------------------------- forward
     def collide(self, db: DeviceBatch, tau: float, K: int, capacity: Optional[int] = None, out: Manifold = None,
                 fused: bool = False, stream=None, lambda_reg=-1.0, eps_n=-1.0, cull_margin=-1.0,
-                flags: int = 0, presel=None, refine: int = 0) -> Manifold:
+                flags: int = 0, presel=None, refine: int = 0, noalloc: bool = False) -> Manifold:
+        """fused: cm_collide_fused; noalloc: cm_collide_noalloc (workspace in
+        the library's static device array; the caller allocates `out`)."""
+        if fused and noalloc:
+            raise ValueError("fused and noalloc are different entry points")
         if out is None:
             cap = db.n_cand_total if capacity is None else capacity
             out = Manifold.empty(db.n_scenes, cap, K, self.device)
         prm = make_params(tau, K, lambda_reg, eps_n, cull_margin, flags, presel, refine)
         b = db.as_c()
         m = out.as_c()
-        fn = self.lib.cm_collide_fused if fused else self.lib.cm_collide
+        fn = self.lib.cm_collide_fused if fused else (self.lib.cm_collide_noalloc if noalloc else self.lib.cm_collide)
         self._check(fn(self.h, C.byref(b), C.byref(prm), C.byref(m), _stream_handle(stream)))
         return out
 

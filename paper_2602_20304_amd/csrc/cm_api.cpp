@@ -110,6 +110,14 @@ cm_status cm_context_create(int device, cm_context** out) {
     delete ctx;
     return CM_ERR_OOM;
   }
+  // device address of the allocation-free forward's static workspace (a
+  // failure only disables cm_collide_noalloc, which then reports it)
+  const hipError_t se = noalloc_scratch(device, &ctx->noalloc_scratch);
+  if (se != hipSuccess || !ctx->noalloc_scratch) {
+    ctx->noalloc_scratch = nullptr;
+    ctx->noalloc_error = std::string("hipGetSymbolAddress of the static workspace: ") + hipGetErrorString(se);
+    (void)hipGetLastError();
+  }
   *out = ctx;
   return CM_OK;
 }
@@ -366,6 +374,62 @@ extern "C" cm_status cm_collide(cm_context* ctx, const cm_batch* batch, const cm
   if ((s = cm_hip(ctx, launch_collide_fwd(f, st), "collide launch")) != CM_OK) return s;
   timer_end(ctx, CM_TIMER_FORWARD, t0, st);
   return CM_OK;
+}
+
+// The forward of cm_collide with every workspace in the static device array
+// (no allocation): tile sums at the array's start, then one scratch slot per
+// workgroup of the pair kernel, whose grid is cut to the slots that fit.  All
+// checks run before the first launch.
+extern "C" cm_status cm_collide_noalloc(cm_context* ctx, const cm_batch* batch, const cm_params* prm,
+                                        cm_manifold* out, void* stream) {
+  if (!ctx) return CM_ERR_INVALID_ARG;
+  ParamsDev pd; BatchDev bd; OutDev od;
+  cm_status s;
+  if ((s = resolve_params(ctx, prm, &pd)) != CM_OK) return s;
+  if ((s = resolve_batch(ctx, batch, &bd)) != CM_OK) return s;
+  if ((s = resolve_out(ctx, out, &od)) != CM_OK) return s;
+  if (!ctx->noalloc_scratch) return cm_fail(ctx, CM_ERR_DEVICE, ctx->noalloc_error);
+  const size_t cap = CM_NOALLOC_SCRATCH_BYTES;
+  const size_t tiles = size_t(bd.n_scenes) / 1024 + 2;
+  const size_t tile_bytes = (tiles * sizeof(int) + 255) & ~size_t(255);
+  if (tile_bytes > cap)
+    return cm_fail(ctx, CM_ERR_CAPACITY, "the broadphase tile sums of " + std::to_string(bd.n_scenes) +
+                                             " scenes need " + std::to_string(tile_bytes) + " B, beyond the " +
+                                             std::to_string(cap) + " B static workspace");
+  char* base = static_cast<char*>(ctx->noalloc_scratch);
+  hipSetDevice(ctx->device);
+  FwdLaunch f;
+  f.tb = ctx_tables(ctx);
+  f.bt = bd; f.prm = pd; f.out = od;
+  f.maxV = std::max(ctx->maxV, 1); f.maxE = std::max(ctx->maxE, 1); f.maxF = std::max(ctx->maxF, 1);
+  f.block = 256;
+  f.kmax = kmax_for(pd.K);
+  f.order = nullptr; f.range = nullptr; f.queue = nullptr; f.err = ctx->d_err;
+  f.scratch_stride = fwd_scratch_floats(f.maxV, f.maxE);
+  f.scratch = reinterpret_cast<float*>(base + tile_bytes);
+  f.grid = 1;
+  if (od.capacity > 0) {
+    const int lds = fwd_lds_bytes(f.maxV, f.maxE, f.maxF, f.block, f.kmax, pd.presel_v > 0);
+    if (lds > 160 * 1024)
+      return cm_fail(ctx, CM_ERR_INVALID_ARG, "the context's largest geometry needs " + std::to_string(lds) +
+                                                  " B of LDS for this forward (160 KiB per workgroup)");
+    const size_t slot = size_t(f.scratch_stride) * sizeof(float);
+    const size_t slots = (cap - tile_bytes) / slot;
+    if (slots < 1)
+      return cm_fail(ctx, CM_ERR_CAPACITY, "one workgroup of this forward needs " + std::to_string(slot) +
+                                               " B of scratch (largest geometry: " + std::to_string(ctx->maxE) +
+                                               " edges), beyond the " + std::to_string(cap - tile_bytes) +
+                                               " B left in the static workspace");
+    const int occ = fwd_occupancy(f);
+    f.grid = int(std::min<size_t>(size_t(std::max(1, occ * ctx->num_cus)), slots));
+    f.grid = std::max(1, std::min(f.grid, od.capacity));
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((s = cm_hip(ctx, launch_broadphase(f.tb, bd, pd.margin, od, reinterpret_cast<int*>(base), ctx->d_err, st),
+                  "broadphase launch")) != CM_OK)
+    return s;
+  if (od.capacity == 0) return CM_OK;
+  return cm_hip(ctx, launch_collide_fwd(f, st), "collide launch");
 }
 
 extern "C" cm_status cm_ee_witness(cm_context* ctx, const float* edges, int64_t n, float tau, float lambda_reg,

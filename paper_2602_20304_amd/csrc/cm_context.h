@@ -44,6 +44,9 @@ struct cm_context {
   size_t tile_cap = 0;
   float* d_scratch = nullptr;
   size_t scratch_cap = 0;
+  // the allocation-free forward's workspace on this device (static array)
+  void* noalloc_scratch = nullptr;
+  std::string noalloc_error;
   void* d_work = nullptr;      // fused path: queue counter, order, keys
   size_t work_cap = 0;
   void* d_bwd = nullptr;       // backward workspace

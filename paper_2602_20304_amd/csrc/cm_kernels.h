@@ -63,6 +63,11 @@ hipError_t launch_broadphase(const Tables& tb, const BatchDev& bt, float margin,
                              unsigned* err, hipStream_t st);
 hipError_t launch_collide_fwd(const FwdLaunch& f, hipStream_t st);
 
+// Device address of the allocation-free entry point's static workspace
+// (CM_NOALLOC_SCRATCH_BYTES) on `device`, looked up on the first call for that
+// device and cached; later calls return the cached address and status.
+hipError_t noalloc_scratch(int device, void** out);
+
 // batched E-E witness points of independent edge pairs: edges [12][n],
 // out [9][n] (float32 rows of stride n); hard = no smoothing
 hipError_t launch_ee_witness(const float* edges, long long n, const ParamsDev& prm, bool hard, float* out,
