@@ -5,20 +5,38 @@ per-scene compaction, vertex-SDF both ways, all-pairs edge-edge witness
 contacts with their indicators, and the SoftSort K-contact manifold -- over
 one batch of synthetic scenes already resident in HBM.
 
-Default workload: 65,536 scenes x 8 bodies (2 spheres, 2 capsules, 2 rounded
-boxes, 2 convex polytopes of 32 points), all 28 pairs per scene are
-candidates, tau = 0.005, K = 8.
+Headline (--steps / --warmup apply to it): the differentiation workload,
+16,384 scenes x 4 convex polytopes (hulls of 64 unit-sphere points scaled
+per axis by U[0.3, 0.6]: 64 V / 186 E / 124 F), all 6 pairs per scene
+candidates, tau = 0.01, K = 8, through the fused batched path
+(cm_collide_fused).  The same process then times, with the replay counts
+given in parentheses (warm-up + timed):
 
-Legs, all in one process on the same inputs:
-  plain     cm_collide (broadphase + one forward pair kernel)
-  fused     cm_collide_fused (cost-ordered work queue, replayed hipGraph)
-  fwd_bwd   cm_collide + cm_collide_backward with random cotangents
-  plain_ne, plain_ne_s     the no-E-E / one-sided simplification flags
-  plain_presel, fwd_bwd_presel   soft top-K pre-selection (K_V 64, K_E 18)
-  plain_refine  E-E witnesses sphere-traced onto the smoothed surfaces (3 steps)
-  plain_presel_refine   the two together (tracing after pre-selection)
-  serving   a short Poisson request stream through cm_server_* (p50 / p99)
-The headline value is the forward throughput of --path (fused by default).
+  cfg3_plain_fwd            cm_collide on the headline batch (1 + 3)
+  cfg3_fwd_bwd_tau*         cm_collide + cm_collide_backward at tau 0.1, 0.01,
+                            0.001 with L = sum_k a_k w_k d_k + b_k . nu_k
+                            (cotangents g_dist = a w, g_weight = a d,
+                            g_normal = b, seeded standard normals) (1 + 2)
+  cfg3_fused_fwd_bwd        the fused forward + the adjoint at tau 0.01 (1 + 2)
+  cfg4_fused_fwd, cfg4_plain_fwd, cfg4_fused_fwd_bwd
+                            100,000 uneven scenes (geometric pairs per scene,
+                            8-256-point hulls, 20 % analytic bodies, 30 %
+                            forced penetration, tau 0.01, K 16) (1 + 1, 0 + 1,
+                            0 + 1 after the fused forward's warm-up)
+  cfg2_*                    65,536 mixed scenes x 8 bodies (tau 0.005, K 8):
+                            plain, fused, fwd+bwd, pre-selected (K_V 64, K_E
+                            18) plain and fused, no-E-E and one-sided
+                            simplifications (1 + 3)
+  cfg1_*                    4,096 cube pairs (tau 0.01, K 8), plain and fused
+                            (5 + 20; launch-latency bound)
+  serving                   a Poisson request stream through cm_server_*
+                            (p50 / p99), a sample of served pairs checked
+                            against the FP64 oracle
+  ee_witness                the E-E witness routine alone, 1 .. 10^7 queries
+  superquadrics             superquadric-union and point-cloud bodies
+Legs that would push the run past --budget seconds of wall clock are skipped
+and listed under "skipped".  The FP64 oracle is timed on the host cores
+first, before the GPU is touched (cpu_baseline).
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -42,32 +60,11 @@ METRIC = "geom-pair contact evals/s (fwd, fwd+bwd) vs plain kernel; p50/p99 quer
 FWD_KERNEL = "collide_fwd"
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "collide_fwd_mixed65536_traffic.md")
+TRAFFIC_FILE_CFG3 = os.path.join(ROOT, "profiles", "collide_fwd_polytopes16384_traffic.md")
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
-
-
-def build_workload(name: str, scenes: int | None):
-    import workloads as W
-    if name == "mixed":
-        b = W.mixed_scenes(scenes or 65536, seed=0)
-        desc = (f"mixed_scenes: {b.n_scenes} scenes x 8 bodies (2 sphere, 2 capsule, 2 rounded box, "
-                f"2 polytope hull-of-32), all 28 pairs/scene candidates, tau={b.tau:g}, K={b.K}")
-    elif name == "cubes":
-        b = W.cube_pairs(scenes or 4096, seed=0)
-        desc = f"cube_pairs: {b.n_scenes} scenes x 1 cube pair (8 V / 12 E), tau={b.tau:g}, K={b.K}"
-    elif name == "polytopes":
-        b = W.polytope_scenes(scenes or 16384, seed=0)
-        desc = (f"polytope_scenes: {b.n_scenes} scenes x 4 polytopes (hull of 64: 64 V / 186 E / 124 F), "
-                f"6 pairs/scene, tau={b.tau:g}, K={b.K}")
-    elif name == "uneven":
-        b = W.uneven_scenes(scenes or 100_000, seed=0)
-        desc = (f"uneven_scenes: {b.n_scenes} scenes, geometric pairs/scene (mean 12), polytopes 8-256 V, "
-                f"20% analytic, 30% forced penetration, tau={b.tau:g}, K={b.K}")
-    else:
-        raise SystemExit(f"unknown workload {name}")
-    return b, desc
 
 
 FWD_SOURCES = ("cm_fwd.hip", "cm_pair.cuh", "cm_device.cuh", "cm_kernels.h", "cm_internal.h")
@@ -98,34 +95,78 @@ def stored_traffic(path: str, files, key: str = "traffic_bytes_per_launch"):
     return float(m_bytes.group(1))
 
 
-def cpu_baseline(batch, budget_s: float):
-    """Time the FP64 oracle on the host over whole scenes in scene order until
-    the time budget is spent.  Only the per-pair evaluations are timed (the
-    oracle's mesh and hull construction for a geometry happens before)."""
+def excess_max(gpu, ref, atol=1e-6, rtol=2e-5) -> float:
+    """Largest amount by which |gpu - ref| exceeds atol + rtol |ref| (<= 0: within the bar)."""
+    g = np.asarray(gpu, np.float64)
+    r = np.asarray(ref, np.float64)
+    return float((np.abs(g - r) - (atol + rtol * np.abs(r))).max()) if g.size else 0.0
+
+
+_CPU_JOB = {}
+
+
+def _oracle_worker(w: int):
+    """Forked worker of the CPU baseline: one intra-op thread, pairs w, w + n,
+    w + 2n, ... of the sample until its time budget is spent.  Geometry
+    (hull) construction is done before timing each pair."""
     import torch
     from oracle import cm_oracle as O
-    pairs, offsets = O.broadphase(batch)
-    cache = O.GeomCache(batch.geoms)
-    threads = int(torch.get_num_threads())
-    spent = 0.0
-    done = 0
-    scenes = 0
+    torch.set_num_threads(1)
+    job = _CPU_JOB
+    b, pairs, n, budget = job["batch"], job["pairs"], job["n"], job["budget"]
+    cache = O.GeomCache(b.geoms)
+    spent, done = 0.0, 0
+    t_start = time.perf_counter()
     with torch.no_grad():
-        for s in range(batch.n_scenes):
-            for i in range(int(offsets[s]), int(offsets[s + 1])):
-                a, b = int(pairs[0, i]), int(pairs[1, i])
-                GA, GB = cache[batch.body_geom[a]], cache[batch.body_geom[b]]
-                t0 = time.perf_counter()
-                O.collide_pair(GA, batch.pose[:, a], GB, batch.pose[:, b], batch.tau, batch.K)
-                spent += time.perf_counter() - t0
-                done += 1
-            scenes += 1
-            if spent > budget_s:
+        for i in range(w, pairs.shape[1], n):
+            a, c = int(pairs[0, i]), int(pairs[1, i])
+            GA, GB = cache[b.body_geom[a]], cache[b.body_geom[c]]
+            t0 = time.perf_counter()
+            O.collide_pair(GA, b.pose[:, a], GB, b.pose[:, c], b.tau, b.K)
+            spent += time.perf_counter() - t0
+            done += 1
+            if time.perf_counter() - t_start > budget:
                 break
-    return dict(value=done / spent, unit="pairs/s", cores=threads, kind="oracle",
-                sample=f"first {scenes} scenes ({done} kept pairs) of the same workload, FP64 oracle, "
-                       f"{spent:.1f} s of pair evaluation, torch intra-op threads={threads}, "
-                       f"mesh builds excluded")
+    return done, spent
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(batch, budget_s: float, max_workers: int = 16):
+    """The FP64 oracle on the host, before any GPU call (so the pool's forked
+    workers start from a process that has not touched the GPU).  Kept pairs of
+    the batch in scene order; one process per core of this process's CPU
+    affinity (at most max_workers, the host share of one GPU), each with one
+    intra-op thread, for about 2/3 of the budget; then one process with one
+    thread for the rest (the 1-thread figure)."""
+    import multiprocessing as mp
+    from oracle import cm_oracle as O
+    pairs, _ = O.broadphase(batch)
+    affinity = len(os.sched_getaffinity(0))
+    workers = max(1, min(affinity, max_workers))
+    _CPU_JOB.update(batch=batch, pairs=pairs, n=workers, budget=budget_s * 2 / 3)
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(workers) as pool:
+        res = pool.map(_oracle_worker, range(workers))
+    wall = time.perf_counter() - t0
+    done = sum(r[0] for r in res)
+    busy = max(r[1] for r in res)
+    _CPU_JOB.update(n=1, budget=budget_s / 3)
+    d1, s1 = _oracle_worker(0)
+    return dict(value=done / busy, unit="pairs/s", cores=workers, kind="oracle",
+                sample=f"{done} kept pairs of the headline workload (scene order, strided over {workers} "
+                       f"processes x 1 thread), FP64 oracle, {busy:.1f} s of pair evaluation per process "
+                       f"({wall:.1f} s wall incl. hull builds); value = pairs / busiest process's evaluation time",
+                cpu_model=cpu_model(), affinity_cores=affinity, one_thread_pairs_per_s=d1 / s1,
+                one_thread_sample=f"{d1} pairs, {s1:.1f} s")
 
 
 def serving_leg(ctx_cls, n_requests: int, seed: int = 11):
@@ -154,8 +195,9 @@ def serving_leg(ctx_cls, n_requests: int, seed: int = 11):
             cn = rng.standard_normal(3 * cap * K).astype(np.float32)
         payload.append((q, cd, cn))
     srv = Server(ctx, 64 << 30, n_streams=4)
+    kept_results = {}
 
-    def run(items, arrivals):
+    def run(items, arrivals, keep=0):
         tickets = []
         t0 = time.perf_counter()
         for (q, cd, cn), at in zip(items, arrivals):
@@ -172,6 +214,9 @@ def serving_leg(ctx_cls, n_requests: int, seed: int = 11):
                         if r["status"] != 0:
                             raise RuntimeError(f"request {t} failed with status {r['status']}")
                         done[t] = (r["t_submit"], r["t_start"], r["t_done"], r["n_pairs"])
+                        i = tickets.index(t)
+                        if i < keep:
+                            kept_results[i] = r
                         srv.release(t)
             time.sleep(0.001)
         return done, time.perf_counter() - t0
@@ -203,8 +248,23 @@ def serving_leg(ctx_cls, n_requests: int, seed: int = 11):
     rate = 0.7 * sat
     gaps = np.random.default_rng(seed + 1).exponential(1.0 / rate, size=n_requests)
     arrivals = np.cumsum(gaps) - gaps[0]
-    done, wall = run(payload[n_cal:], arrivals)
+    done, wall = run(payload[n_cal:], arrivals, keep=4)
     srv.close()
+    # FP64 oracle on a seeded sample of served pairs (4 per request, first 4 requests of the stream)
+    from oracle import cm_oracle as O
+    cache = O.GeomCache(pool)
+    worst, checked = 0.0, 0
+    srng = np.random.default_rng(seed + 2)
+    for i, r in sorted(kept_results.items()):
+        q = payload[n_cal + i][0]
+        m = min(r["n_pairs"], r["capacity"])
+        for j in srng.choice(m, size=min(4, m), replace=False):
+            a_, b_ = int(r["pairs"][0, j]), int(r["pairs"][1, j])
+            with __import__("torch").no_grad():
+                ref = O.collide_pair(cache[q.body_geom[a_]], q.pose[:, a_], cache[q.body_geom[b_]], q.pose[:, b_], tau, K)
+            for k in ("p", "nu", "d", "w"):
+                worst = max(worst, excess_max(r[k][j], ref[k].numpy()))
+            checked += 1
     burst_pairs = sum(d[3] for d in cal.values()) / cal_wall
     plain_pairs = run_plain(payload[:n_cal])
     lat = np.array([d[2] - d[0] for d in done.values()])
@@ -212,6 +272,8 @@ def serving_leg(ctx_cls, n_requests: int, seed: int = 11):
     return dict(requests=len(done), rate_per_s=rate, saturated_per_s=sat, burst_pairs_per_s=burst_pairs,
                 plain_sequential_pairs_per_s=plain_pairs, p50_ms=float(np.percentile(lat, 50) * 1e3),
                 p99_ms=float(np.percentile(lat, 99) * 1e3), pairs_per_s=pairs / wall, wall_s=wall,
+                oracle_check={"pairs": checked, "max_excess": worst,
+                              "bar": "|gpu - fp64| <= 1e-6 + 2e-5 |fp64| (max_excess <= 0 passes)"},
                 config=f"{n_requests} Poisson requests at 0.7 x the saturated rate measured on a burst of {n_cal}; "
                        f"256-4096 envs (log-uniform), 2-6 bodies/env from a resident pool of 64 hull-of-64 polytopes, "
                        f"fwd or fwd+bwd 50/50, tau={tau}, K={K}, 4 streams, 64 GiB budget")
@@ -323,31 +385,81 @@ def copy_calibration(n_bytes: int, reps: int):
     print(json.dumps({"copy_calibration_bytes_read": 4 * n, "bytes_written": 4 * n, "reps": reps}), flush=True)
 
 
+class Timer:
+    """HIP-event timing of `steps` calls of fn on the current stream, with
+    the library's per-kernel event timers enabled over the timed region."""
+
+    def __init__(self, ctx, stream):
+        self.ctx, self.stream = ctx, stream
+
+    def run(self, fn, warmup: int, steps: int) -> dict:
+        import torch
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        self.ctx.check_errors()
+        self.ctx.set_kernel_timing(True)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(self.stream)
+        for _ in range(steps):
+            fn()
+        ev1.record(self.stream)
+        torch.cuda.synchronize()
+        out = {"ms": ev0.elapsed_time(ev1) / steps, "steps": steps, "warmup": warmup}
+        for t in ("broadphase", "forward", "backward", "fused"):
+            ms, n = self.ctx.kernel_time(t)
+            if n:
+                out[f"{t}_kernel_ms"] = ms / n
+                out[f"{t}_launches"] = n
+        self.ctx.set_kernel_timing(False)
+        self.ctx.check_errors()
+        return out
+
+
+def config_ops(ctx, ids, batch, out):
+    """Algorithmic (fma, alu, trans) of the kept pairs of `out` (op model)."""
+    from paper_2602_20304_amd import opmodel
+    kept = min(int(out.n_pairs.item()), out.capacity)
+    pairs = out.pairs[:, :kept].cpu().numpy()
+    gids = np.unique(ids)
+    info = {int(g): ctx.geometry_info(int(g)) for g in gids}
+    lut = np.zeros((int(gids.max()) + 1, 4), np.int64)
+    for g, i in info.items():
+        lut[g] = (i["type"], i["n_vertices"], i["n_edges"], i["n_faces"])
+    body_geom = ids[batch.body_geom]
+    return opmodel.batch_ops(lut[:, 0], lut[:, 1], lut[:, 2], lut[:, 3], pairs[0], pairs[1], body_geom)
+
+
+def roofline_entry(ops, kernel_ms, kernel, launches, traffic=None, note=None):
+    from paper_2602_20304_amd import opmodel
+    r = opmodel.roofline(ops, kernel_ms * 1e-3)
+    e = {"bound": "alu", "kernel": kernel, "achieved": r["achieved_flops"] / 1e12, "peak": r["peak_flops"] / 1e12,
+         "unit": "TFLOP/s", "frac": r["frac"], "traffic": traffic, "kernel_ms": kernel_ms, "launches": launches,
+         "ops_per_launch": {"fma": int(ops[0]), "alu": int(ops[1]), "trans": int(ops[2])}}
+    if note:
+        e["note"] = note
+    return e
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="mixed")
-    ap.add_argument("--scenes", type=int, default=None)
-    ap.add_argument("--path", default="fused", choices=["plain", "fused"])
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--budget", type=float, default=480.0,
+                    help="wall-clock seconds after which remaining legs are skipped")
+    ap.add_argument("--cpu-budget", type=float, default=18.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-bwd", action="store_true")
-    ap.add_argument("--serve", type=int, default=16, help="requests in the serving leg (0 = skip)")
-    ap.add_argument("--no-ee", action="store_true", help="skip the E-E witness microbenchmark")
-    ap.add_argument("--ee-only", action="store_true", help="run only the E-E witness microbenchmark")
-    ap.add_argument("--serve-only", action="store_true", help="run only the serving leg")
-    ap.add_argument("--no-sq", action="store_true", help="skip the superquadric-union leg")
-    ap.add_argument("--sq-only", action="store_true", help="run only the superquadric-union leg")
-    ap.add_argument("--ee-trials", type=int, default=100, help="timed launches per size in the E-E sweep")
-    ap.add_argument("--no-simplifications", action="store_true",
-                    help="skip the forward legs without E-E (ne), with one-sided vertex contacts (ne_s) and "
-                         "with soft top-K pre-selection (presel)")
+    ap.add_argument("--configs", default="3,4,2,1,5,ee,sq",
+                    help="comma list of legs to run after the headline: 3 4 2 1 5(serving) ee sq")
+    ap.add_argument("--scenes", type=int, default=None, help="override the headline's scene count (testing)")
+    ap.add_argument("--cfg4-scenes", type=int, default=100_000)
+    ap.add_argument("--serve", type=int, default=24, help="requests in the serving leg")
+    ap.add_argument("--ee-trials", type=int, default=20, help="timed launches per size in the E-E sweep")
     ap.add_argument("--only", default=None,
-                    choices=[None, "plain", "fused", "fwd_bwd", "plain_ne", "plain_ne_s", "plain_presel",
-                             "fwd_bwd_presel", "plain_refine", "fused_presel", "plain_presel_refine"],
-                    help="run one leg only (for profiling)")
+                    choices=[None, "cfg3_fused", "cfg3_plain", "cfg3_bwd", "cfg4_fused", "cfg4_plain", "cfg2_plain",
+                             "cfg2_fused", "cfg2_bwd", "cfg2_refine"],
+                    help="run one leg only, without the headline and the other legs (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (PMC byte calibration)")
     args = ap.parse_args()
@@ -357,184 +469,260 @@ def main():
     if args.copy_calibration:
         copy_calibration(args.copy_calibration << 20, 5)
         return
+    t_start = time.perf_counter()
+    elapsed = lambda: time.perf_counter() - t_start
+    wanted = set(args.configs.split(",")) if args.configs else set()
+
+    import workloads as W
+    b3 = W.polytope_scenes(args.scenes or 16384, seed=0, tau=0.01)
+    desc3 = (f"polytope_scenes (differentiation workload): {b3.n_scenes} scenes x 4 convex polytopes (hull of 64 "
+             f"unit-sphere points scaled per axis U[0.3,0.6]: 64 V / 186 E / 124 F), all 6 pairs/scene candidates, "
+             f"centres U[-0.5,0.5]^3, tau={b3.tau:g}, K={b3.K}")
+    cpu = None
+    if not args.no_cpu_baseline and not args.only:
+        log("timing the FP64 oracle on the host cores (before any GPU call) ...")
+        cpu = cpu_baseline(b3, args.cpu_budget)
+        log(f"cpu baseline: {cpu['value']:.3g} pairs/s on {cpu['cores']} processes ({cpu['cpu_model']}), "
+            f"1 thread {cpu['one_thread_pairs_per_s']:.3g} pairs/s")
 
     import torch
-    import workloads as W
     from paper_2602_20304_amd.cm import FLAG_NO_EE, FLAG_ONE_SIDED_VS, Context, Manifold
     from paper_2602_20304_amd import opmodel
 
-    if args.serve_only:
-        print(json.dumps({"serving": serving_leg(Context, args.serve or 16)}), flush=True)
-        return
-    if args.sq_only:
-        print(json.dumps({"superquadrics": sq_leg(Context, steps=args.steps)}), flush=True)
-        return
-    if args.ee_only:
-        ctx = Context(0)
-        print(json.dumps({"ee_witness": ee_witness_leg(ctx, trials=args.ee_trials)}), flush=True)
-        return
-
-    batch, desc = build_workload(args.workload, args.scenes)
-    log(f"workload: {desc}")
+    # one context per workload: a plain launch sizes its LDS and face masks by
+    # the largest geometry its context holds
     ctx = Context(0)
-    t0 = time.perf_counter()
-    ids = ctx.create_geometry(batch.geoms)
-    t_geom = time.perf_counter() - t0
-    db = ctx.upload_batch(batch, ids)
-    cap = db.n_cand_total
-    out = Manifold.empty(db.n_scenes, cap, batch.K, ctx.device)
-    log(f"geometry build {t_geom:.1f}s; {batch.n_bodies} bodies, {cap} candidate pairs")
     stream = torch.cuda.current_stream()
-    cot_d = cot_n = None
-    if not args.no_bwd:
-        a, b = W.cotangents(cap, batch.K, seed=1)
-        cot_d = torch.as_tensor(a).to(ctx.device)
-        cot_n = torch.as_tensor(b).to(ctx.device)
+    timer = Timer(ctx, stream)
+    legs, skipped, rooflines = {}, {}, {}
 
-    leg_flags = {"plain_ne": FLAG_NO_EE, "plain_ne_s": FLAG_NO_EE | FLAG_ONE_SIDED_VS}
-    # the paper's benchmark shape: every vertex (K_V at its cap of 64 covers the
-    # meshes here) and the K_E = 18 deepest edges per body
-    leg_presel = {"plain_presel": (64, 18), "fwd_bwd_presel": (64, 18), "fused_presel": (64, 18),
-                  "plain_presel_refine": (64, 18)}
+    def new_context():
+        nonlocal ctx
+        ctx.close()
+        torch.cuda.empty_cache()
+        ctx = Context(0)
+        timer.ctx = ctx
 
-    leg_refine = {"plain_refine": 3, "plain_presel_refine": 3}
+    def fits(name, est_s):
+        if elapsed() + est_s > args.budget:
+            skipped[name] = f"estimated {est_s:.0f} s would pass the {args.budget:.0f} s budget at {elapsed():.0f} s"
+            log(f"skip {name}: {skipped[name]}")
+            return False
+        return True
 
-    def step(leg):
-        ctx.collide(db, batch.tau, batch.K, out=out, fused=(leg in ("fused", "fused_presel")), stream=stream,
-                    flags=leg_flags.get(leg, 0), presel=leg_presel.get(leg), refine=leg_refine.get(leg, 0))
-        if leg in ("fwd_bwd", "fwd_bwd_presel"):
-            ctx.collide_backward(db, out, batch.tau, batch.K, None, cot_n, cot_d, None, stream=stream,
-                                 presel=leg_presel.get(leg))
+    def record(name, res, kept, cand):
+        res = dict(res)
+        res["kept_pairs"] = kept
+        res["candidate_pairs"] = cand
+        res["pairs_per_s"] = kept / (res["ms"] * 1e-3)
+        res["ms_per_step"] = res.pop("ms")
+        legs[name] = res
+        log(f"{name}: {res['ms_per_step']:.3f} ms/step, {kept} kept pairs, {res['pairs_per_s']:.4g} pairs/s"
+            + "".join(f", {k} {v:.3f}" for k, v in res.items() if k.endswith("_kernel_ms")))
+        return res
 
-    legs = ["plain", "fused"] + ([] if args.no_bwd else ["fwd_bwd"])
-    legs += [] if args.no_simplifications else ["plain_ne", "plain_ne_s", "plain_presel", "fused_presel",
-                                                "plain_refine", "plain_presel_refine"]
-    legs += [] if (args.no_simplifications or args.no_bwd) else ["fwd_bwd_presel"]
-    if args.only:
-        legs = [args.only]
-    results = {}
-    kernel = {}
-    for leg in legs:
-        for _ in range(args.warmup):
-            step(leg)
-        torch.cuda.synchronize()
-        ctx.check_errors()
-        ctx.set_kernel_timing(True)
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        ev0.record(stream)
-        for _ in range(args.steps):
-            step(leg)
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        ms = ev0.elapsed_time(ev1) / args.steps
-        kernel[leg] = {t: ctx.kernel_time(t) for t in ("broadphase", "forward", "backward", "fused")}
-        ctx.set_kernel_timing(False)
-        ctx.check_errors()
-        n_pairs = int(out.n_pairs.item())
-        results[leg] = dict(ms=ms, n_pairs=n_pairs)
-        log(f"{leg}: {ms:.3f} ms/step, {n_pairs} kept pairs, {n_pairs / (ms * 1e-3):.4g} pairs/s; "
-            + ", ".join(f"{k} {v[0] / max(v[1], 1):.3f} ms x{v[1]}" for k, v in kernel[leg].items() if v[1]))
+    def upload(batch):
+        t0 = time.perf_counter()
+        ids = ctx.create_geometry(batch.geoms)
+        db = ctx.upload_batch(batch, ids)
+        cap = db.n_cand_total
+        out = Manifold.empty(db.n_scenes, cap, batch.K, ctx.device)
+        log(f"{batch.name}: {batch.n_scenes} scenes, {batch.n_bodies} bodies, {cap} candidate pairs, "
+            f"geometry build + upload {time.perf_counter() - t0:.1f} s")
+        return ids, db, cap, out
 
-    main_leg = args.path if args.path in results else legs[0]
-    ms = results[main_leg]["ms"]
-    n_pairs = results[main_leg]["n_pairs"]
-    kept = min(n_pairs, cap)
-    pairs = out.pairs[:, :kept].cpu().numpy()
-    G = ctx.geometry_count
-    sizes = np.array([[ctx.geometry_info(int(g))[k] for k in ("type", "n_vertices", "n_edges", "n_faces")]
-                      for g in range(G)], dtype=np.int64)
-    body_geom = ids[batch.body_geom]
-    ops = opmodel.batch_ops(sizes[:, 0], sizes[:, 1], sizes[:, 2], sizes[:, 3], pairs[0], pairs[1], body_geom)
+    def loss_cotangents(cap, K, seed):
+        """a [cap K], b [3, cap K] seeded standard normals (float32)."""
+        a, b = W.cotangents(cap, K, seed=seed)
+        return torch.as_tensor(a).to(ctx.device), torch.as_tensor(b).to(ctx.device)
 
-    # roofline of the dominant kernel: the forward pair kernel, timed with HIP
-    # events on its own stream during the plain leg (one launch = all kept pairs)
-    roof_leg = "plain" if "plain" in kernel else main_leg
-    k_ms, k_n = kernel[roof_leg]["forward"]
-    roofline = None
-    if k_n:
-        kms = k_ms / k_n
-        roof = opmodel.roofline(ops, kms * 1e-3)
-        traffic = stored_traffic(TRAFFIC_FILE, FWD_SOURCES) if args.workload == "mixed" else None
-        roofline = {"bound": "alu", "kernel": FWD_KERNEL, "achieved": roof["achieved_flops"] / 1e12,
-                    "peak": roof["peak_flops"] / 1e12, "unit": "TFLOP/s", "frac": roof["frac"],
-                    "traffic": traffic, "kernel_ms": kms, "launches": k_n,
-                    "ops_per_launch": {"fma": int(ops[0]), "alu": int(ops[1]), "trans": int(ops[2])}}
-        # the fused path does the same algorithmic work; its time is the whole
-        # replayed graph (broadphase, classification, class launches) timed
-        # with HIP events around the graph launch, so this rate is a lower
-        # bound for its pair kernel
-        f_ms, f_n = kernel["fused"]["fused"] if "fused" in kernel else (0.0, 0)
-        if f_n:
-            froof = opmodel.roofline(ops, f_ms / f_n * 1e-3)
-            roofline["fused_path"] = {"achieved": froof["achieved_flops"] / 1e12, "frac": froof["frac"],
-                                      "graph_ms": f_ms / f_n, "launches": f_n}
+    def fwd_bwd(db, out, tau, K, a, b, fused=False, presel=None):
+        ctx.collide(db, tau, K, out=out, fused=fused, stream=stream, presel=presel)
+        # L = sum_k a_k w_k d_k + b_k . nu_k
+        gd = a * out.weight
+        gw = a * out.dist
+        ctx.collide_backward(db, out, tau, K, None, b, gd, gw, stream=stream, presel=presel,
+                             want_vertices=True, want_params=True)
 
-    legs_out = {}
-    for k, v in results.items():
-        legs_out[k] = {"ms_per_step": v["ms"], "pairs_per_s": v["n_pairs"] / (v["ms"] * 1e-3)}
-        for t, (tms, tn) in kernel[k].items():
-            if tn:
-                legs_out[k][f"{t}_kernel_ms"] = tms / tn
+    only = args.only
+    # ------------------------------------------------------------ headline: cfg 3 fused forward
+    ids3, db3, cap3, out3 = upload(b3)
+    ops3 = None
+    if only in (None, "cfg3_fused"):
+        res = timer.run(lambda: ctx.collide(db3, b3.tau, b3.K, out=out3, fused=True, stream=stream),
+                        args.warmup, args.steps)
+        head = record("cfg3_fused_fwd", res, int(out3.n_pairs.item()), cap3)
+        ops3 = config_ops(ctx, ids3, b3, out3)
+        rooflines["cfg3_fused_fwd"] = roofline_entry(
+            ops3, res["fused_kernel_ms"], "collide_fwd (fused class kernel)", res["fused_launches"],
+            stored_traffic(TRAFFIC_FILE_CFG3, FWD_SOURCES),
+            "duration = the whole replayed graph (broadphase, pricing, sort, class launches) between HIP events "
+            "on the launch stream: an upper bound of the class kernel's, so a lower bound of its rate")
+    if only in (None, "cfg3_plain") and ("3" in wanted or only):
+        res = timer.run(lambda: ctx.collide(db3, b3.tau, b3.K, out=out3, stream=stream), 1, 3)
+        record("cfg3_plain_fwd", res, int(out3.n_pairs.item()), cap3)
+        ops3 = ops3 if ops3 is not None else config_ops(ctx, ids3, b3, out3)
+        rooflines["cfg3_plain_fwd"] = roofline_entry(ops3, res["forward_kernel_ms"], "collide_fwd (plain)",
+                                                     res["forward_launches"])
+    if only in (None, "cfg3_bwd") and ("3" in wanted or only):
+        a3, bb3 = loss_cotangents(cap3, b3.K, seed=1)
+        for tau in (0.01, 0.001, 0.1):
+            name = f"cfg3_fwd_bwd_tau{tau:g}"
+            # at tau 0.1 nearly every candidate lies inside the adjoint's
+            # window: one timed pass, no warm-up (the kernels are loaded)
+            wu, st = (0, 1) if tau > 0.05 else (1, 2)
+            if not fits(name, 40.0 if tau > 0.05 else 15.0):
+                continue
+            res = timer.run(lambda: fwd_bwd(db3, out3, tau, b3.K, a3, bb3), wu, st)
+            r = record(name, res, int(out3.n_pairs.item()), cap3)
+            if tau == 0.01:
+                ops = config_ops(ctx, ids3, b3, out3)
+                rooflines["cfg3_adjoint"] = roofline_entry(
+                    opmodel.reverse_ops(ops), r["backward_kernel_ms"], "collide_bwd", r["backward_launches"],
+                    note="algorithmic ops = the reverse sweep of the op model (2x the forward's multiply-adds; "
+                         "the kernel's own forward recompute is not counted)")
+        if not only and fits("cfg3_fused_fwd_bwd", 15.0):
+            res = timer.run(lambda: fwd_bwd(db3, out3, b3.tau, b3.K, a3, bb3, fused=True), 1, 2)
+            record("cfg3_fused_fwd_bwd", res, int(out3.n_pairs.item()), cap3)
+        del a3, bb3
+    # restore the headline manifold (tau 0.01) for anything that reads it
+    # ------------------------------------------------------------ cfg 4 uneven batching
+    if (only in ("cfg4_fused", "cfg4_plain")) or (only is None and "4" in wanted and fits("cfg4", 150.0)):
+        del db3, out3
+        new_context()
+        t0 = time.perf_counter()
+        b4 = W.uneven_scenes(args.cfg4_scenes, seed=0)
+        log(f"cfg4 generated in {time.perf_counter() - t0:.1f} s")
+        ids4, db4, cap4, out4 = upload(b4)
+        est = max(30.0, 1e-4 * cap4)
+        if only in (None, "cfg4_fused"):
+            res = timer.run(lambda: ctx.collide(db4, b4.tau, b4.K, out=out4, fused=True, stream=stream), 1, 1)
+            r = record("cfg4_fused_fwd", res, int(out4.n_pairs.item()), cap4)
+            est = r["ms_per_step"] * 1e-3
+            ops4 = config_ops(ctx, ids4, b4, out4)
+            rooflines["cfg4_fused_fwd"] = roofline_entry(ops4, r["fused_kernel_ms"], "collide_fwd (fused graph)",
+                                                         r["fused_launches"])
+        if only in (None, "cfg4_plain") and (only or fits("cfg4_plain_fwd", 1.5 * est)):
+            res = timer.run(lambda: ctx.collide(db4, b4.tau, b4.K, out=out4, stream=stream), 0, 1)
+            r = record("cfg4_plain_fwd", res, int(out4.n_pairs.item()), cap4)
+            ops4 = config_ops(ctx, ids4, b4, out4)
+            rooflines["cfg4_plain_fwd"] = roofline_entry(ops4, r["forward_kernel_ms"], "collide_fwd (plain)",
+                                                         r["forward_launches"])
+        if only is None and fits("cfg4_fused_fwd_bwd", 4.0 * est):
+            a4, bb4 = loss_cotangents(cap4, b4.K, seed=4)
+            res = timer.run(lambda: fwd_bwd(db4, out4, b4.tau, b4.K, a4, bb4, fused=True), 0, 1)
+            r = record("cfg4_fused_fwd_bwd", res, int(out4.n_pairs.item()), cap4)
+            ops4 = config_ops(ctx, ids4, b4, out4)
+            rooflines["cfg4_adjoint"] = roofline_entry(opmodel.reverse_ops(ops4), r["backward_kernel_ms"],
+                                                       "collide_bwd", r["backward_launches"])
+            del a4, bb4
+        legs_cfg4 = dict(workload=f"uneven_scenes: {b4.n_scenes} scenes, geometric pairs/scene (mean 12, clip "
+                                  f"[1,64]), polytopes of 8-256 points on random ellipsoids, 20% analytic, 30% forced "
+                                  f"penetration U[0,0.05], tau={b4.tau:g}, K={b4.K}", bodies=b4.n_bodies)
+        legs["cfg4_config"] = legs_cfg4
+        del db4, out4, b4
+        torch.cuda.empty_cache()
+    # ------------------------------------------------------------ cfg 5 serving
+    serving = ee = sq = None
+    if only is None and "5" in wanted and fits("serving", 40.0):
+        log(f"serving leg: {args.serve} requests ...")
+        serving = serving_leg(Context, args.serve)
+        log(f"serving: {serving['rate_per_s']:.2f} req/s (saturated {serving['saturated_per_s']:.2f}), "
+            f"p50 {serving['p50_ms']:.1f} ms, p99 {serving['p99_ms']:.1f} ms, oracle sample max excess "
+            f"{serving['oracle_check']['max_excess']:.3g}")
+    # ------------------------------------------------------------ cfg 2 mixed scenes
+    if (only and only.startswith("cfg2")) or (only is None and "2" in wanted and fits("cfg2", 40.0)):
+        new_context()
+        b2 = W.mixed_scenes(65536, seed=0)
+        ids2, db2, cap2, out2 = upload(b2)
+        a2, bb2 = loss_cotangents(cap2, b2.K, seed=1)
+        cfg2 = {"cfg2_plain_fwd": dict(), "cfg2_fused_fwd": dict(fused=True),
+                "cfg2_plain_presel_fwd": dict(presel=(64, 18)), "cfg2_fused_presel_fwd": dict(fused=True, presel=(64, 18)),
+                "cfg2_plain_ne_fwd": dict(flags=FLAG_NO_EE),
+                "cfg2_plain_ne_s_fwd": dict(flags=FLAG_NO_EE | FLAG_ONE_SIDED_VS),
+                "cfg2_plain_refine_fwd": dict(refine=3)}
+        pick = {"cfg2_plain": ["cfg2_plain_fwd"], "cfg2_fused": ["cfg2_fused_fwd"], "cfg2_bwd": [],
+                "cfg2_refine": ["cfg2_plain_refine_fwd"]}
+        names = pick[only] if only else [n for n in cfg2 if n != "cfg2_plain_refine_fwd"]
+        for name in names:
+            kw = cfg2[name]
+            if not only and not fits(name, 3.0):
+                continue
+            res = timer.run(lambda: ctx.collide(db2, b2.tau, b2.K, out=out2, stream=stream, **kw), 1, 3)
+            r = record(name, res, int(out2.n_pairs.item()), cap2)
+            if name == "cfg2_plain_fwd":
+                ops2 = config_ops(ctx, ids2, b2, out2)
+                rooflines["cfg2_plain_fwd"] = roofline_entry(ops2, r["forward_kernel_ms"], "collide_fwd (plain)",
+                                                             r["forward_launches"], stored_traffic(TRAFFIC_FILE, FWD_SOURCES))
+            if name == "cfg2_fused_fwd":
+                ops2 = config_ops(ctx, ids2, b2, out2)
+                rooflines["cfg2_fused_fwd"] = roofline_entry(ops2, r["fused_kernel_ms"], "collide_fwd (fused graph)",
+                                                             r["fused_launches"])
+        if only in (None, "cfg2_bwd") and (only or fits("cfg2_fwd_bwd", 8.0)):
+            for name, presel in (("cfg2_fwd_bwd", None), ("cfg2_fwd_bwd_presel", (64, 18))):
+                res = timer.run(lambda: fwd_bwd(db2, out2, b2.tau, b2.K, a2, bb2, presel=presel), 1, 2)
+                r = record(name, res, int(out2.n_pairs.item()), cap2)
+                if presel is None:
+                    ops2 = config_ops(ctx, ids2, b2, out2)
+                    rooflines["cfg2_adjoint"] = roofline_entry(opmodel.reverse_ops(ops2), r["backward_kernel_ms"],
+                                                               "collide_bwd", r["backward_launches"])
+        del db2, out2, a2, bb2
+        torch.cuda.empty_cache()
+    # ------------------------------------------------------------ cfg 1 cube pairs
+    if only is None and "1" in wanted and fits("cfg1", 5.0):
+        new_context()
+        b1 = W.cube_pairs(4096, seed=0)
+        ids1, db1, cap1, out1 = upload(b1)
+        for name, fused in (("cfg1_plain_fwd", False), ("cfg1_fused_fwd", True)):
+            res = timer.run(lambda: ctx.collide(db1, b1.tau, b1.K, out=out1, fused=fused, stream=stream), 5, 20)
+            record(name, res, int(out1.n_pairs.item()), cap1)
+    # ------------------------------------------------------------ serving, E-E, extended primitives
+    if only is None and "ee" in wanted and fits("ee_witness", 15.0):
+        log("E-E witness microbenchmark ...")
+        ee = ee_witness_leg(ctx, trials=args.ee_trials)
+    if only is None and "sq" in wanted and fits("superquadrics", 10.0):
+        log("superquadric-union leg ...")
+        sq = sq_leg(Context, steps=3)
+
+    if only:
+        print(json.dumps({"only": only, "legs": legs, "rooflines": rooflines}), flush=True)
+        return
     line = {
         "metric": METRIC,
-        "value": n_pairs / (ms * 1e-3),
+        "value": head["pairs_per_s"],
         "unit": "pairs/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64+f32",
         "data": "synthetic",
-        "config": {"workload": desc, "scenes": batch.n_scenes, "candidate_pairs": cap, "kept_pairs": n_pairs,
-                   "tau": batch.tau, "K": batch.K, "path": main_leg, "parallelism": "single-gpu"},
-        "legs": legs_out,
-        "roofline": roofline,
+        "config": {"workload": desc3, "scenes": b3.n_scenes, "candidate_pairs": cap3,
+                   "kept_pairs": head["kept_pairs"], "tau": b3.tau, "K": b3.K, "path": "fused",
+                   "parallelism": "single-gpu"},
+        "roofline": rooflines.get("cfg3_fused_fwd"),
+        "rooflines": rooflines,
+        "legs": legs,
     }
-    if "fwd_bwd" in results:
-        v = results["fwd_bwd"]
-        line["fwd_bwd_pairs_per_s"] = v["n_pairs"] / (v["ms"] * 1e-3)
-    if "plain" in results and main_leg != "plain":
-        line["speedup_vs_plain"] = results["plain"]["ms"] / ms
-    if "plain" in results and "plain_ne" in results and "plain_ne_s" in results:
-        line["simplifications"] = {"ne_speedup": results["plain"]["ms"] / results["plain_ne"]["ms"],
-                                   "ne_s_speedup_over_ne": results["plain_ne"]["ms"] / results["plain_ne_s"]["ms"]}
-    if "plain" in results and "plain_presel" in results:
-        line["preselection"] = {"presel": list(leg_presel["plain_presel"]),
-                                "speedup_vs_all_pairs": results["plain"]["ms"] / results["plain_presel"]["ms"]}
-        if "fused_presel" in results:
-            line["preselection"]["fused_speedup_vs_plain_presel"] = (results["plain_presel"]["ms"]
-                                                                     / results["fused_presel"]["ms"])
-        if "fwd_bwd" in results and "fwd_bwd_presel" in results:
-            line["preselection"]["fwd_bwd_speedup_vs_all_pairs"] = (results["fwd_bwd"]["ms"]
-                                                                    / results["fwd_bwd_presel"]["ms"])
-    if "plain" in results and "plain_refine" in results:
-        line["witness_refinement"] = {"steps": leg_refine["plain_refine"],
-                                      "cost_vs_plain": results["plain_refine"]["ms"] / results["plain"]["ms"]}
-        if "plain_presel" in results and "plain_presel_refine" in results:
-            line["witness_refinement"]["presel_cost_vs_plain_presel"] = (results["plain_presel_refine"]["ms"]
-                                                                         / results["plain_presel"]["ms"])
-    if args.serve and not args.only:
-        log(f"serving leg: {args.serve} requests ...")
-        line["serving"] = serving_leg(Context, args.serve)
-        log(f"serving: {line['serving']['rate_per_s']:.2f} req/s (saturated {line['serving']['saturated_per_s']:.2f}), "
-            f"p50 {line['serving']['p50_ms']:.1f} ms, p99 {line['serving']['p99_ms']:.1f} ms")
-    if not args.no_ee:
-        log("E-E witness microbenchmark ...")
-        ee = ee_witness_leg(ctx)
+    if "cfg3_plain_fwd" in legs:
+        line["speedup_vs_plain"] = legs["cfg3_plain_fwd"]["ms_per_step"] / head["ms_per_step"]
+    if "cfg3_fwd_bwd_tau0.01" in legs:
+        line["fwd_bwd_pairs_per_s"] = legs["cfg3_fwd_bwd_tau0.01"]["pairs_per_s"]
+    if "cfg4_fused_fwd" in legs and "cfg4_plain_fwd" in legs:
+        line["cfg4_fused_speedup_vs_plain"] = legs["cfg4_plain_fwd"]["ms_per_step"] / legs["cfg4_fused_fwd"]["ms_per_step"]
+    if serving:
+        line["serving"] = serving
+    if ee:
         line["ee_witness"] = ee
-        log("ee_witness: " + ", ".join(f"n={n}: {a:.4f}/{b:.4f} ms" for n, a, b in
-                                       zip(ee["sizes"], ee["smooth_ms"], ee["hard_ms"])) +
-            f"; 1e7 smooth {ee['smooth_roofline']['achieved']:.0f} GB/s, hard {ee['hard_roofline']['achieved']:.0f} GB/s")
-    if not args.no_sq and not args.only:
-        log("superquadric-union leg ...")
-        line["superquadrics"] = sq_leg(Context, steps=min(args.steps, 5))
-    if not args.no_cpu_baseline and not args.only:
-        log("timing the FP64 oracle on the host ...")
-        line["cpu_baseline"] = cpu_baseline(batch, args.cpu_budget)
+    if sq:
+        line["superquadrics"] = sq
+    if cpu:
+        line["cpu_baseline"] = cpu
+    line["skipped"] = skipped
+    line["wall_s"] = elapsed()
     print(json.dumps(line), flush=True)
 
 

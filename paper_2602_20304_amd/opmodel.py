@@ -75,6 +75,23 @@ def batch_ops(types, nv, ne, nf, pairs_a, pairs_b, body_geom) -> np.ndarray:
     return tot
 
 
+def reverse_ops(forward: np.ndarray) -> np.ndarray:
+    """(fma, alu, trans) of the reverse sweep of the vector-Jacobian product
+    (cm_collide_backward), given the forward's count.
+
+    Reverse-mode differentiation visits every forward operation once more:
+    the adjoint of y = a b + c is a_bar += y_bar b, b_bar += y_bar a, c_bar +=
+    y_bar (2 fma + 1 alu), of y = a op b for add / mul / compare-select at most
+    2 alu, and of a transcendental y = f(x) one alu (x_bar += y_bar f'(x), with
+    f' a multiple of y or of 1/x, both already computed).  So the sweep costs
+    (2 fma, fma + 2 alu + trans, 0).  The forward recompute the adjoint kernel
+    performs (it stores no E x E state) is implementation work and is not
+    counted; the candidates whose SoftSort weights it drops as negligible are
+    counted (the model counts every step of the definition once)."""
+    fma, alu, trans = (int(x) for x in forward)
+    return np.array([2 * fma, fma + 2 * alu + trans, 0], dtype=np.int64)
+
+
 # MI355X (gfx950): 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz
 VALU_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9      # full-rate lane operations per second
 TRANS_SLOT_COST = 4                            # transcendental ops issue at a quarter rate
