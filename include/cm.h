@@ -29,7 +29,14 @@
  *     synchronously, device-side data errors (an out-of-range geometry id,
  *     more kept pairs than the output capacity) are recorded in a device
  *     error word that cm_check_errors() reads (it synchronises the stream).
- *   - A context is not thread-safe; the server functions are.
+ *   - A context is not thread-safe; the server functions are.  Calls on one
+ *     context that use its workspace (cm_collide, cm_collide_fused,
+ *     cm_collide_backward) may go to different streams: a call on another
+ *     stream than the previous such call first makes its stream wait for that
+ *     call's work (an event), so they serialise rather than corrupt each
+ *     other's scratch.  Under stream capture no such wait is inserted: keep
+ *     a captured sequence on one stream.  cm_collide_noalloc uses the
+ *     device-wide static workspace instead (see there).
  *   - Layouts are structure-of-arrays.  Poses: float [7][n_bodies] with rows
  *     (qw, qx, qy, qz, tx, ty, tz); the quaternion need not be normalised.
  *   - Geometry type ids / params:
@@ -234,6 +241,17 @@ cm_status cm_geometry_info(cm_context* ctx, int32_t id, cm_geometry_info_t* out)
 cm_status cm_geometry_mesh(cm_context* ctx, int32_t id, float* vertices, int32_t* edges, int32_t* faces);
 int32_t cm_geometry_count(cm_context* ctx);
 int32_t cm_vertex_pool_size(cm_context* ctx);
+/* Destroy n geometries (host ids[n]).  Every id must name a live geometry of
+ * this context (else CM_ERR_NOT_FOUND and nothing changes); geometry is
+ * frozen while a server runs (CM_ERR_INVALID_ARG).  The call waits for the
+ * device to finish queued work, then repacks the vertex / edge / plane
+ * tables without the destroyed geometries: the other geometries keep their
+ * ids but their vertex_offset (cm_geometry_info) may change, and
+ * cm_vertex_pool_size shrinks.  Destroyed ids are not reused; a batch that
+ * still references one is flagged like an out-of-range id (CM_ERR_NOT_FOUND
+ * from cm_check_errors), and cm_geometry_info / cm_geometry_mesh return
+ * CM_ERR_NOT_FOUND for it.  cm_geometry_count keeps counting ids. */
+cm_status cm_geometry_destroy(cm_context* ctx, const int32_t* ids, int32_t n);
 
 /* ---------------------------------------------------------------- forward
  * Broadphase (keep a candidate pair iff its float32 bounding spheres overlap
@@ -308,39 +326,62 @@ cm_status cm_ee_witness(cm_context* ctx, const float* edges, int64_t n, float ta
                         float* out, void* stream);
 
 /* ---------------------------------------------------------------- serving
- * A continuous-batching request loop over resident geometry.  Requests are
- * admitted while their device footprint fits in hbm_budget_bytes; admitted
- * requests run concurrently on n_streams streams.  submit copies the request
- * (host arrays) and returns a ticket; poll returns CM_ERR_NOT_READY until the
- * request completed, then fills the result (host arrays it owns until
- * cm_server_release).  A request whose footprint exceeds the whole budget is
- * rejected with CM_ERR_REJECTED. */
+ * A continuous-batching request loop over resident geometry (the serving
+ * form; no passage of the paper: it serves the method of Sec. IV to many
+ * callers).  A scheduler thread admits requests in arrival order while (a)
+ * their device footprint (inputs, outputs, per-workgroup scratch, gradients)
+ * fits in hbm_budget_bytes beside the running ones, (b) their pinned host
+ * result block fits in the host budget (8 GiB unless set with
+ * cm_server_set_host_budget) beside the results not yet released, and (c)
+ * one of n_streams stream slots is free;
+ * admitted requests run concurrently, one stream each, with their own
+ * device workspace and device error word.  submit copies the request (host
+ * arrays) and returns a ticket; a request that could never fit either budget
+ * is rejected at submit with CM_ERR_REJECTED.  poll returns CM_ERR_NOT_READY
+ * until the request completed, then fills the result, whose host arrays the
+ * server owns until cm_server_release (released blocks are reused, so
+ * release results promptly: unreleased results hold host budget and can keep
+ * later requests waiting).  A completed request's status: CM_OK,
+ * CM_ERR_CAPACITY (more kept pairs than capacity; the first capacity pairs
+ * are valid), CM_ERR_NOT_FOUND (a destroyed geometry), CM_ERR_OOM or
+ * CM_ERR_DEVICE.  The geometry of the context is frozen while a server
+ * exists.  submit / poll / release / stats are thread-safe; a failing
+ * server call leaves its message in cm_server_last_error() of the calling
+ * thread (the context's cm_last_error is not used by the server). */
 typedef struct {
   int32_t n_scenes;
   int32_t n_bodies;
-  const int32_t* body_offsets;   /* host [n_scenes + 1] */
-  const int32_t* body_geom;      /* host [n_bodies] */
+  const int32_t* body_offsets;   /* host [n_scenes + 1], body_offsets[0] = 0, non-decreasing */
+  const int32_t* body_geom;      /* host [n_bodies] live geometry ids */
   const float* pose;             /* host [7][n_bodies] */
   cm_params params;
-  int32_t want_backward;         /* also compute gradients of L = <cot, out> */
-  const float* cot_dist;         /* host [capacity*K] or NULL (backward only) */
+  int32_t want_backward;         /* also the vector-Jacobian product of L = <cot, outputs> */
+  const float* cot_point;        /* host [3][capacity*K] or NULL = 0 (backward only) */
   const float* cot_normal;       /* host [3][capacity*K] or NULL */
-  int32_t capacity;              /* output pair capacity (<= 0: all candidates) */
+  const float* cot_dist;         /* host [capacity*K] or NULL */
+  const float* cot_weight;       /* host [capacity*K] or NULL */
+  int32_t want_geometry_grads;   /* backward: also g_vertices and g_params */
+  int32_t capacity;              /* output pair capacity (<= 0: all candidate pairs) */
 } cm_request;
 
 typedef struct {
   cm_status status;
   int32_t n_pairs;
-  int32_t capacity;              /* row stride of the arrays below */
+  int32_t capacity;              /* row stride of the manifold arrays below */
   const int32_t* pair_offsets;   /* host [n_scenes + 1] */
   const int32_t* pairs;          /* host [2][capacity] */
   const float* point;            /* host [3][capacity*K] */
   const float* normal;
   const float* dist;
   const float* weight;
-  const float* g_pose;           /* host [6][n_bodies] (backward only) */
+  const float* g_pose;           /* host [6][n_bodies] (backward) */
+  const float* g_tau;            /* host [1] (backward) */
+  const float* g_vertices;       /* host [3][vertex_pool] (backward with want_geometry_grads) */
+  const float* g_params;         /* host [4][n_geometries] (same) */
+  int32_t vertex_pool;           /* row stride of g_vertices (the pool size at submit) */
+  int32_t n_geometries;          /* row stride of g_params */
   double t_submit, t_start, t_done;   /* seconds, server clock */
-  uint64_t footprint_bytes;
+  uint64_t footprint_bytes;      /* device bytes the request was admitted with */
 } cm_result;
 
 /* ---------------------------------------------------------------- timing
@@ -364,11 +405,13 @@ cm_status cm_set_kernel_timing(cm_context* ctx, int32_t enable);
 cm_status cm_kernel_time(cm_context* ctx, int32_t timer, double* total_ms, int64_t* launches);
 
 cm_status cm_server_create(cm_context* ctx, uint64_t hbm_budget_bytes, int32_t n_streams, cm_server** out);
+cm_status cm_server_set_host_budget(cm_server* srv, uint64_t host_budget_bytes);
 cm_status cm_server_submit(cm_server* srv, const cm_request* req, uint64_t* ticket);
 cm_status cm_server_poll(cm_server* srv, uint64_t ticket, cm_result* out);
 cm_status cm_server_release(cm_server* srv, uint64_t ticket);
 cm_status cm_server_stats(cm_server* srv, uint64_t* in_flight_bytes, int32_t* n_pending, int32_t* n_running);
 cm_status cm_server_destroy(cm_server* srv);
+const char* cm_server_last_error(void);
 
 #ifdef __cplusplus
 }

@@ -52,14 +52,16 @@ class cm_geometry_info_t(C.Structure):
 
 class cm_request(C.Structure):
     _fields_ = [("n_scenes", i32), ("n_bodies", i32), ("body_offsets", vp), ("body_geom", vp), ("pose", vp),
-                ("params", cm_params), ("want_backward", i32), ("cot_dist", vp), ("cot_normal", vp),
-                ("capacity", i32)]
+                ("params", cm_params), ("want_backward", i32), ("cot_point", vp), ("cot_normal", vp),
+                ("cot_dist", vp), ("cot_weight", vp), ("want_geometry_grads", i32), ("capacity", i32)]
 
 
 class cm_result(C.Structure):
-    _fields_ = [("status", i32), ("n_pairs", i32), ("capacity", i32), ("pair_offsets", i32p), ("pairs", i32p), ("point", f32p),
-                ("normal", f32p), ("dist", f32p), ("weight", f32p), ("g_pose", f32p), ("t_submit", C.c_double),
-                ("t_start", C.c_double), ("t_done", C.c_double), ("footprint_bytes", C.c_uint64)]
+    _fields_ = [("status", i32), ("n_pairs", i32), ("capacity", i32), ("pair_offsets", i32p), ("pairs", i32p),
+                ("point", f32p), ("normal", f32p), ("dist", f32p), ("weight", f32p), ("g_pose", f32p),
+                ("g_tau", f32p), ("g_vertices", f32p), ("g_params", f32p), ("vertex_pool", i32),
+                ("n_geometries", i32), ("t_submit", C.c_double), ("t_start", C.c_double), ("t_done", C.c_double),
+                ("footprint_bytes", C.c_uint64)]
 
 
 # name -> (restype, argtypes)
@@ -74,6 +76,7 @@ SIGNATURES = {
     "cm_geometry_mesh": (i32, [vp, i32, vp, vp, vp]),
     "cm_geometry_count": (i32, [vp]),
     "cm_vertex_pool_size": (i32, [vp]),
+    "cm_geometry_destroy": (i32, [vp, vp, i32]),
     "cm_collide": (i32, [vp, C.POINTER(cm_batch), C.POINTER(cm_params), C.POINTER(cm_manifold), vp]),
     "cm_collide_fused": (i32, [vp, C.POINTER(cm_batch), C.POINTER(cm_params), C.POINTER(cm_manifold), vp]),
     "cm_collide_noalloc": (i32, [vp, C.POINTER(cm_batch), C.POINTER(cm_params), C.POINTER(cm_manifold), vp]),
@@ -83,11 +86,13 @@ SIGNATURES = {
     "cm_set_kernel_timing": (i32, [vp, i32]),
     "cm_kernel_time": (i32, [vp, i32, C.POINTER(C.c_double), i64p]),
     "cm_server_create": (i32, [vp, C.c_uint64, i32, C.POINTER(vp)]),
+    "cm_server_set_host_budget": (i32, [vp, C.c_uint64]),
     "cm_server_submit": (i32, [vp, C.POINTER(cm_request), C.POINTER(C.c_uint64)]),
     "cm_server_poll": (i32, [vp, C.c_uint64, C.POINTER(cm_result)]),
     "cm_server_release": (i32, [vp, C.c_uint64]),
     "cm_server_stats": (i32, [vp, C.POINTER(C.c_uint64), i32p, i32p]),
     "cm_server_destroy": (i32, [vp]),
+    "cm_server_last_error": (C.c_char_p, []),
 }
 
 _lib = None

@@ -202,6 +202,11 @@ class Context:
         self._check(self.lib.cm_geometry_mesh(self.h, int(gid), _np_ptr(v), _np_ptr(e), _np_ptr(f)))
         return v.reshape(-1, 3), e.reshape(-1, 2), f[:3 * info["n_faces"]].reshape(-1, 3)
 
+    def destroy_geometry(self, gids) -> None:
+        """Destroy geometries (cm_geometry_destroy); ids stay reserved."""
+        g = np.ascontiguousarray(np.atleast_1d(gids), dtype=np.int32)
+        self._check(self.lib.cm_geometry_destroy(self.h, _np_ptr(g), int(g.size)))
+
     @property
     def vertex_pool_size(self) -> int:
         return int(self.lib.cm_vertex_pool_size(self.h))
@@ -355,13 +360,24 @@ class Server:
         self.ctx = cmctx
         self.lib = cmctx.lib
         h = C.c_void_p()
-        cmctx._check(self.lib.cm_server_create(cmctx.h, C.c_uint64(int(budget_bytes)), int(n_streams), C.byref(h)))
+        self._check(self.lib.cm_server_create(cmctx.h, C.c_uint64(int(budget_bytes)), int(n_streams), C.byref(h)))
         self.h = h
         self._keep = {}
 
+    def _check(self, status):
+        if status != L.CM_OK:
+            raise L.CMError(status, (self.lib.cm_server_last_error() or b"").decode())
+
+    def set_host_budget(self, budget_bytes: int):
+        """Pinned host bytes the unreleased results may hold (default 8 GiB)."""
+        self._check(self.lib.cm_server_set_host_budget(self.h, C.c_uint64(int(budget_bytes))))
+
     def submit(self, body_offsets, body_geom, pose, tau: float, K: int, want_backward=False, cot_dist=None,
-               cot_normal=None, capacity: int = 0, flags: int = 0, presel=None, refine: int = 0) -> int:
-        """body_geom are context geometry ids; pose float32 [7, n_bodies]."""
+               cot_normal=None, capacity: int = 0, flags: int = 0, presel=None, refine: int = 0, cot_point=None,
+               cot_weight=None, want_geometry=False) -> int:
+        """body_geom are context geometry ids; pose float32 [7, n_bodies];
+        cotangents host float32 arrays laid out like the outputs ([3, cap*K] /
+        [cap*K]) or None (zero)."""
         bo = np.ascontiguousarray(body_offsets, np.int32)
         bg = np.ascontiguousarray(body_geom, np.int32)
         ps = np.ascontiguousarray(pose, np.float32)
@@ -370,15 +386,14 @@ class Server:
         q.body_offsets, q.body_geom, q.pose = _np_ptr(bo), _np_ptr(bg), _np_ptr(ps)
         q.params = make_params(tau, K, flags=flags, presel=presel, refine=refine)
         q.want_backward = int(bool(want_backward))
-        cd = None if cot_dist is None else np.ascontiguousarray(cot_dist, np.float32)
-        cn = None if cot_normal is None else np.ascontiguousarray(cot_normal, np.float32)
-        q.cot_dist, q.cot_normal = _np_ptr(cd), _np_ptr(cn)
+        cots = [None if c is None else np.ascontiguousarray(c, np.float32)
+                for c in (cot_point, cot_normal, cot_dist, cot_weight)]
+        q.cot_point, q.cot_normal, q.cot_dist, q.cot_weight = (_np_ptr(c) for c in cots)
+        q.want_geometry_grads = int(bool(want_geometry))
         q.capacity = int(capacity)
         t = C.c_uint64()
-        st = self.lib.cm_server_submit(self.h, C.byref(q), C.byref(t))
-        if st != L.CM_OK:
-            raise L.CMError(st, self.lib.cm_last_error(self.ctx.h).decode())
-        self._keep[t.value] = (K, q.n_scenes, q.n_bodies, bool(want_backward))
+        self._check(self.lib.cm_server_submit(self.h, C.byref(q), C.byref(t)))
+        self._keep[t.value] = (K, q.n_scenes, q.n_bodies, bool(want_backward), bool(want_geometry and want_backward))
         return t.value
 
     def poll(self, ticket: int):
@@ -387,12 +402,17 @@ class Server:
         st = self.lib.cm_server_poll(self.h, C.c_uint64(ticket), C.byref(r))
         if st == -4:
             return None
-        K, S, nb, bwd = self._keep[ticket]
+        if st == -6 and ticket not in self._keep:
+            self._check(st)
+        K, S, nb, bwd, geo = self._keep[ticket]
+        out = dict(status=st, n_pairs=r.n_pairs, capacity=r.capacity, t_submit=r.t_submit, t_start=r.t_start,
+                   t_done=r.t_done, footprint=r.footprint_bytes)
+        if not r.point:
+            return out
         n, cap = r.n_pairs, r.capacity
         m = min(n, cap)
         arr = lambda p, cnt: np.ctypeslib.as_array(p, shape=(cnt,)).copy()
-        out = dict(status=st, n_pairs=n, capacity=cap, t_submit=r.t_submit, t_start=r.t_start, t_done=r.t_done,
-                   footprint=r.footprint_bytes, offsets=arr(r.pair_offsets, S + 1))
+        out["offsets"] = arr(r.pair_offsets, S + 1)
         pr = arr(r.pairs, 2 * max(cap, 1))
         out["pairs"] = np.stack([pr[:m], pr[cap:cap + m]])
         pt = arr(r.point, 3 * max(cap, 1) * K).reshape(3, -1)[:, :m * K]
@@ -403,6 +423,10 @@ class Server:
         out["w"] = arr(r.weight, max(cap, 1) * K)[:m * K].reshape(m, K)
         if bwd:
             out["g_pose"] = arr(r.g_pose, 6 * max(nb, 1)).reshape(6, -1)[:, :nb]
+            out["g_tau"] = float(r.g_tau[0])
+            if geo:
+                out["g_vertices"] = arr(r.g_vertices, 3 * max(r.vertex_pool, 1)).reshape(3, -1)[:, :r.vertex_pool]
+                out["g_params"] = arr(r.g_params, 4 * max(r.n_geometries, 1)).reshape(4, -1)[:, :r.n_geometries]
         return out
 
     def release(self, ticket: int):

@@ -224,9 +224,69 @@ cm_status cm_geometry_create(cm_context* ctx, int32_t n, const int32_t* types, c
   return ctx_upload_tables(ctx);
 }
 
+// Destroy geometries: their records keep their ids with a negative type (a
+// batch that references them is flagged CM_ERR_NOT_FOUND), the vertex / edge
+// / plane pools are repacked without them (vertex offsets of the remaining
+// geometries change), the context maxima are recomputed and the device
+// tables re-uploaded.  All ids are checked before anything changes.
+cm_status cm_geometry_destroy(cm_context* ctx, const int32_t* ids, int32_t n) {
+  if (!ctx || n < 0 || (n > 0 && !ids)) return CM_ERR_INVALID_ARG;
+  if (n == 0) return CM_OK;
+  if (ctx->servers > 0) return cm_fail(ctx, CM_ERR_INVALID_ARG, "geometry is frozen while a server is running");
+  auto& h = ctx->h;
+  std::vector<char> kill(h.recs.size(), 0);
+  for (int i = 0; i < n; ++i) {
+    const int32_t id = ids[i];
+    if (id < 0 || id >= int32_t(h.recs.size()) || h.recs[id].type < 0)
+      return cm_fail(ctx, CM_ERR_NOT_FOUND, "no such geometry: " + std::to_string(id));
+    kill[id] = 1;
+  }
+  hipSetDevice(ctx->device);
+  // the tables may still be read by queued work
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return cm_hip(ctx, e, "synchronize before destroy");
+  CmPools np;
+  np.recs = h.recs;
+  ctx->maxV = ctx->maxE = ctx->maxF = 0;
+  ctx->has_sq = false;
+  for (size_t g = 0; g < h.recs.size(); ++g) {
+    GeomRec& r = np.recs[g];
+    if (kill[g] || r.type < 0) {
+      std::memset(&r, 0, sizeof(r));
+      r.type = -1;
+      continue;
+    }
+    const GeomRec& o = h.recs[g];
+    r.v_off = int32_t(np.vx.size());
+    r.e_off = int32_t(np.e0.size());
+    r.f_off = int32_t(np.fnx.size());
+    np.vx.insert(np.vx.end(), h.vx.begin() + o.v_off, h.vx.begin() + o.v_off + o.nv);
+    np.vy.insert(np.vy.end(), h.vy.begin() + o.v_off, h.vy.begin() + o.v_off + o.nv);
+    np.vz.insert(np.vz.end(), h.vz.begin() + o.v_off, h.vz.begin() + o.v_off + o.nv);
+    np.e0.insert(np.e0.end(), h.e0.begin() + o.e_off, h.e0.begin() + o.e_off + o.ne);
+    np.e1.insert(np.e1.end(), h.e1.begin() + o.e_off, h.e1.begin() + o.e_off + o.ne);
+    np.fnx.insert(np.fnx.end(), h.fnx.begin() + o.f_off, h.fnx.begin() + o.f_off + o.nf);
+    np.fny.insert(np.fny.end(), h.fny.begin() + o.f_off, h.fny.begin() + o.f_off + o.nf);
+    np.fnz.insert(np.fnz.end(), h.fnz.begin() + o.f_off, h.fnz.begin() + o.f_off + o.nf);
+    np.fo.insert(np.fo.end(), h.fo.begin() + o.f_off, h.fo.begin() + o.f_off + o.nf);
+    np.f0.insert(np.f0.end(), h.f0.begin() + o.f_off, h.f0.begin() + o.f_off + o.nf);
+    np.f1.insert(np.f1.end(), h.f1.begin() + o.f_off, h.f1.begin() + o.f_off + o.nf);
+    np.f2.insert(np.f2.end(), h.f2.begin() + o.f_off, h.f2.begin() + o.f_off + o.nf);
+    ctx->maxV = std::max(ctx->maxV, r.nv);
+    ctx->maxE = std::max(ctx->maxE, r.ne);
+    ctx->maxF = std::max(ctx->maxF, r.nf);
+    if (r.type == CM_SQ_UNION || r.type == CM_OPC) ctx->has_sq = true;
+  }
+  h = std::move(np);
+  ctx->geom_version++;
+  ctx->drop_graphs();
+  return ctx_upload_tables(ctx);
+}
+
 cm_status cm_geometry_info(cm_context* ctx, int32_t id, cm_geometry_info_t* out) {
   if (!ctx || !out) return CM_ERR_INVALID_ARG;
-  if (id < 0 || id >= int32_t(ctx->h.recs.size())) return cm_fail(ctx, CM_ERR_NOT_FOUND, "no such geometry");
+  if (id < 0 || id >= int32_t(ctx->h.recs.size()) || ctx->h.recs[id].type < 0)
+    return cm_fail(ctx, CM_ERR_NOT_FOUND, "no such geometry");
   const GeomRec& r = ctx->h.recs[id];
   // a superquadric union keeps its primitives in the plane pool: no faces
   out->type = r.type; out->n_vertices = r.nv; out->n_edges = r.ne;
@@ -237,7 +297,8 @@ cm_status cm_geometry_info(cm_context* ctx, int32_t id, cm_geometry_info_t* out)
 
 cm_status cm_geometry_mesh(cm_context* ctx, int32_t id, float* vertices, int32_t* edges, int32_t* faces) {
   if (!ctx) return CM_ERR_INVALID_ARG;
-  if (id < 0 || id >= int32_t(ctx->h.recs.size())) return cm_fail(ctx, CM_ERR_NOT_FOUND, "no such geometry");
+  if (id < 0 || id >= int32_t(ctx->h.recs.size()) || ctx->h.recs[id].type < 0)
+    return cm_fail(ctx, CM_ERR_NOT_FOUND, "no such geometry");
   const GeomRec& r = ctx->h.recs[id];
   const auto& h = ctx->h;
   if (vertices) for (int v = 0; v < r.nv; ++v) {
@@ -321,6 +382,28 @@ cm_status resolve_out(cm_context* ctx, const cm_manifold* o, OutDev* od) {
 
 int kmax_for(int K) { return K <= 8 ? 8 : (K <= 16 ? 16 : 32); }
 
+static bool capturing(hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+}
+
+cm_status ctx_order(cm_context* ctx, hipStream_t st) {
+  if (!ctx->order_pending || st == ctx->last_stream || capturing(st)) return CM_OK;
+  return cm_hip(ctx, hipStreamWaitEvent(st, ctx->order_ev, 0), "cross-stream ordering");
+}
+
+void ctx_mark(cm_context* ctx, hipStream_t st) {
+  if (capturing(st)) return;
+  if (!ctx->order_ev && hipEventCreateWithFlags(&ctx->order_ev, hipEventDisableTiming) != hipSuccess) {
+    ctx->order_ev = nullptr;
+    return;
+  }
+  if (hipEventRecord(ctx->order_ev, st) == hipSuccess) {
+    ctx->last_stream = st;
+    ctx->order_pending = true;
+  }
+}
+
 cm_status ctx_broadphase(cm_context* ctx, const BatchDev& bd, const ParamsDev& pd, const OutDev& od, hipStream_t st) {
   const Tables tb = ctx_tables(ctx);
   const size_t tiles = size_t(bd.n_scenes) / 1024 + 2;
@@ -364,15 +447,18 @@ extern "C" cm_status cm_collide(cm_context* ctx, const cm_batch* batch, const cm
   if ((s = resolve_out(ctx, out, &od)) != CM_OK) return s;
   hipSetDevice(ctx->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((s = ctx_order(ctx, st)) != CM_OK) return s;
+  FwdLaunch f;
+  if (od.capacity > 0 && (s = ctx_prepare_fwd(ctx, bd, pd, od, 256, false, &f)) != CM_OK) return s;
   hipEvent_t t0 = timer_begin(ctx, st);
   if ((s = ctx_broadphase(ctx, bd, pd, od, st)) != CM_OK) return s;
   timer_end(ctx, CM_TIMER_BROADPHASE, t0, st);
-  if (od.capacity == 0) return CM_OK;
-  FwdLaunch f;
-  if ((s = ctx_prepare_fwd(ctx, bd, pd, od, 256, false, &f)) != CM_OK) return s;
-  t0 = timer_begin(ctx, st);
-  if ((s = cm_hip(ctx, launch_collide_fwd(f, st), "collide launch")) != CM_OK) return s;
-  timer_end(ctx, CM_TIMER_FORWARD, t0, st);
+  if (od.capacity > 0) {
+    t0 = timer_begin(ctx, st);
+    if ((s = cm_hip(ctx, launch_collide_fwd(f, st), "collide launch")) != CM_OK) return s;
+    timer_end(ctx, CM_TIMER_FORWARD, t0, st);
+  }
+  ctx_mark(ctx, st);
   return CM_OK;
 }
 
@@ -539,6 +625,7 @@ extern "C" cm_status cm_collide_backward(cm_context* ctx, const cm_batch* batch,
   if (pd.refine > 0) return cm_fail(ctx, CM_ERR_INVALID_ARG, "the adjoint does not support witness sphere tracing");
   hipSetDevice(ctx->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((s = ctx_order(ctx, st)) != CM_OK) return s;
   const long long pool = (long long)ctx->h.vx.size();
   const long long G = (long long)ctx->h.recs.size();
   hipError_t e;
@@ -550,7 +637,10 @@ extern "C" cm_status cm_collide_backward(cm_context* ctx, const cm_batch* batch,
     return cm_hip(ctx, e, "zero g_params");
   if (out->g_tau && (e = hipMemsetAsync(out->g_tau, 0, sizeof(float), st)) != hipSuccess)
     return cm_hip(ctx, e, "zero g_tau");
-  if (od.capacity == 0) return CM_OK;
+  if (od.capacity == 0) {
+    ctx_mark(ctx, st);
+    return CM_OK;
+  }
   BwdLaunch b;
   b.f.tb = ctx_tables(ctx);
   b.f.bt = bd; b.f.prm = pd; b.f.out = od;
@@ -574,5 +664,6 @@ extern "C" cm_status cm_collide_backward(cm_context* ctx, const cm_batch* batch,
   hipEvent_t t0 = timer_begin(ctx, st);
   if ((s = cm_hip(ctx, launch_collide_bwd(b, st), "backward launch")) != CM_OK) return s;
   timer_end(ctx, CM_TIMER_BACKWARD, t0, st);
+  ctx_mark(ctx, st);
   return CM_OK;
 }

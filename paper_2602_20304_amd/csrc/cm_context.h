@@ -71,6 +71,10 @@ struct cm_context {
     graphs.clear();
   }
   std::string last_error;
+  // cross-stream ordering of calls that use the workspace above
+  hipStream_t last_stream = nullptr;
+  hipEvent_t order_ev = nullptr;
+  bool order_pending = false;
   // opt-in event timing (cm_set_kernel_timing)
   struct Timer {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
@@ -92,6 +96,8 @@ struct cm_context {
       t.pending.clear();
     }
     for (auto ev : spare_events) (void)hipEventDestroy(ev);
+    if (order_ev) (void)hipEventDestroy(order_ev);
+    order_ev = nullptr;
     spare_events.clear();
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     cap_stream = nullptr;
@@ -105,6 +111,13 @@ hipError_t ensure_bytes(void** p, size_t* cap, size_t need);
 hipError_t ctx_ensure(cm_context* ctx, void** p, size_t* cap, size_t need);
 cm::Tables ctx_tables(const cm_context* ctx);
 cm_status resolve_params(cm_context* ctx, const cm_params* prm, cm::ParamsDev* pd);
+// Calls that use the context's workspace are ordered across streams: before
+// queuing work on `st`, ctx_order makes st wait for the previous such call
+// when that one went to another stream; ctx_mark records the point after the
+// new call's work.  Neither acts on a stream under capture (a captured
+// sequence stays on one stream).
+cm_status ctx_order(cm_context* ctx, hipStream_t st);
+void ctx_mark(cm_context* ctx, hipStream_t st);
 cm_status resolve_batch(cm_context* ctx, const cm_batch* b, cm::BatchDev* bd);
 cm_status resolve_out(cm_context* ctx, const cm_manifold* o, cm::OutDev* od);
 cm_status ctx_broadphase(cm_context* ctx, const cm::BatchDev& bd, const cm::ParamsDev& pd, const cm::OutDev& od,

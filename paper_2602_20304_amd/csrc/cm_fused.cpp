@@ -76,6 +76,7 @@ extern "C" cm_status cm_collide_fused(cm_context* ctx, const cm_batch* batch, co
   if ((s = resolve_out(ctx, out, &od)) != CM_OK) return s;
   hipSetDevice(ctx->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((s = ctx_order(ctx, st)) != CM_OK) return s;
   build_plan(ctx, pd.K);
 
   // work buffers: counts, ranges, queues, order[cap], keys[cap]
@@ -167,6 +168,7 @@ extern "C" cm_status cm_collide_fused(cm_context* ctx, const cm_batch* batch, co
       hipEvent_t t0 = timer_begin(ctx, st);
       if ((s = cm_hip(ctx, hipGraphLaunch(g.exec, st), "graph replay")) != CM_OK) return s;
       timer_end(ctx, CM_TIMER_FUSED, t0, st);
+      ctx_mark(ctx, st);
       return CM_OK;
     }
 
@@ -191,5 +193,6 @@ extern "C" cm_status cm_collide_fused(cm_context* ctx, const cm_batch* batch, co
   hipEvent_t t0 = timer_begin(ctx, st);
   if ((s = cm_hip(ctx, hipGraphLaunch(exec, st), "graph launch")) != CM_OK) return s;
   timer_end(ctx, CM_TIMER_FUSED, t0, st);
+  ctx_mark(ctx, st);
   return CM_OK;
 }

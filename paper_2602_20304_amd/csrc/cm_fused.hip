@@ -54,7 +54,7 @@ __global__ void fused_classify(Tables tb, BatchDev bt, OutDev out, int cmax0, in
     const int a = out.pairs[i], b = out.pairs[out.capacity + i];
     const int ga = bt.body_geom[a], gb = bt.body_geom[b];
     int key = -1;
-    if (ga >= 0 && ga < tb.n_geoms && gb >= 0 && gb < tb.n_geoms) {
+    if (ga >= 0 && ga < tb.n_geoms && gb >= 0 && gb < tb.n_geoms && tb.geoms[ga].type >= 0 && tb.geoms[gb].type >= 0) {
       const GeomRec A = tb.geoms[ga], B = tb.geoms[gb];
       const int e = max(A.ne, B.ne);
       const int c = e <= cmax0 ? 0 : (e <= cmax1 ? 1 : 2);

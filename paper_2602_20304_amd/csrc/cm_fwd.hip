@@ -26,7 +26,8 @@ __device__ __forceinline__ bool body_radius(const Tables& tb, const BatchDev& bt
                                             unsigned* err) {
   if (body < 0 || body >= bt.n_bodies) { atomicOr(err, ERR_BAD_GEOM); return false; }
   const int g = bt.body_geom[body];
-  if (g < 0 || g >= tb.n_geoms) { atomicOr(err, ERR_BAD_GEOM); return false; }
+  // a destroyed geometry keeps its id with a negative type
+  if (g < 0 || g >= tb.n_geoms || tb.geoms[g].type < 0) { atomicOr(err, ERR_BAD_GEOM); return false; }
   R = tb.geoms[g].bound_r;
   return true;
 }

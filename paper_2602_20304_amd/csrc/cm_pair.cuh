@@ -223,6 +223,10 @@ struct PairEngine {
       } else {
         const GeomRec G1 = tb.geoms[ga], G2 = tb.geoms[gb];
         ps.ga = ga; ps.gb = gb;
+        if (G1.type < 0 || G2.type < 0) {   // destroyed geometry
+          ps.valid = 0;
+          atomicOr(err, ERR_BAD_GEOM);
+        }
         const int nb = bt.n_bodies;
         double RA[9], RB[9];
         quat_to_R(bt.pose[a], bt.pose[nb + a], bt.pose[2 * nb + a], bt.pose[3 * nb + a], RA);
@@ -246,7 +250,7 @@ struct PairEngine {
         ps.nvs = G1.nv + ((flags & CM_FLAG_ONE_SIDED_VS) ? 0 : G2.nv);
         ps.nee = (flags & CM_FLAG_NO_EE) ? 0 : G1.ne * G2.ne;
         ps.ncand = ps.nvs + 2 * ps.nee;
-        if (G1.nv > maxV || G2.nv > maxV || G1.ne > maxE || G2.ne > maxE || G1.nf > maxF || G2.nf > maxF) {
+        if (ps.valid && (G1.nv > maxV || G2.nv > maxV || G1.ne > maxE || G2.ne > maxE || G1.nf > maxF || G2.nf > maxF)) {
           ps.valid = 0;
           atomicOr(err, ERR_BAD_GEOM);
         }

@@ -215,3 +215,26 @@ def test_fewer_candidates_than_K(ctx):
     assert n > 0
     for k in ("p", "nu", "d", "w"):
         assert not np.any(got[k][:n, 8:]), k
+
+
+def test_calls_on_two_streams_are_ordered(ctx):
+    """Forward calls on one context alternating between two streams, with no
+    synchronisation between them, share the context's scratch: the library
+    orders them, so every result equals the single-stream one bit for bit."""
+    import torch
+    b = W.polytope_scenes(32, seed=12)
+    _say(f"[gpu] two streams: {b.n_scenes} scenes")
+    ids = ctx.create_geometry(b.geoms)
+    db = ctx.upload_batch(b, ids)
+    ref = ctx.collide(db, b.tau, b.K)
+    ctx.check_errors()
+    r = ref.to_numpy()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    outs = [ctx.collide(db, b.tau, b.K, stream=(s1 if i % 2 == 0 else s2)) for i in range(4)]
+    torch.cuda.synchronize()
+    ctx.check_errors()
+    for m in outs:
+        g = m.to_numpy()
+        for k in ("pairs", "offsets", "p", "nu", "d", "w"):
+            assert np.array_equal(g[k], r[k]), k

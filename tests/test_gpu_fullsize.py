@@ -1,0 +1,101 @@
+"""Parity at the sizes the workloads name (needs an MI355X).
+
+* the adjoint on the differentiation workload's bodies: hulls of 64 points
+  (64 V / 186 E / 124 F: two-word face masks), tau 0.1, 0.01, 0.001;
+* the adjoint on uneven-workload pairs at K = 16 whose larger body has more
+  than 300 edges (the fused path's largest size class, no face culling above
+  128 faces, edge arrays outside LDS);
+* the forward, plain and fused, on uneven-workload pairs whose bodies both
+  have more than 200 vertices (up to 762 edges), beside a random sample.
+
+The FP64 oracle is the reference throughout (gradients: its autograd).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import cm_oracle as O
+from tests.parity import compare_outputs
+from tests.test_gpu_backward import check as check_grads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2602_20304_amd.cm import Context
+    return Context(0)
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def pairs_batch(b, sel, name):
+    """One scene per selected (a, b) body pair of batch b, listed as the
+    scene's only candidate; the geometry set is kept whole."""
+    bodies = np.array([x for p in sel for x in p], dtype=np.int64)
+    n = len(sel)
+    return W.Batch(geoms=b.geoms, body_offsets=(2 * np.arange(n + 1)).astype(np.int32),
+                   body_geom=b.body_geom[bodies].astype(np.int32), pose=b.pose[:, bodies].copy(),
+                   tau=b.tau, K=b.K, cand_offsets=np.arange(n + 1, dtype=np.int32),
+                   cand_pairs=np.stack([2 * np.arange(n), 2 * np.arange(n) + 1]).astype(np.int32), name=name)
+
+
+def _vertex_counts(b):
+    return np.diff(b.geoms.pt_off)[b.body_geom]
+
+
+@pytest.mark.parametrize("tau", [0.1, 0.01, 0.001])
+def test_backward_differentiation_hulls(ctx, tau):
+    """One scene of the differentiation workload: 4 hulls of 64 points, all 6
+    pairs candidates."""
+    b = W.polytope_scenes(1, seed=60, tau=tau)
+    check_grads(ctx, b, seed=61)
+
+
+def test_backward_uneven_largest_class(ctx):
+    """K = 16 uneven pairs: the first two kept pairs whose larger body has
+    more than 300 edges (hulls of more than 102 points) and whose smaller one
+    more than 200, and two smaller pairs."""
+    b = W.uneven_scenes(300, seed=62)
+    pairs, _ = O.broadphase(b)
+    nv = _vertex_counts(b)
+    eA, eB = 3 * nv[pairs[0]] - 6, 3 * nv[pairs[1]] - 6
+    e_max = np.maximum(eA, eB)
+    big = np.nonzero((e_max > 300) & (np.minimum(eA, eB) > 200))[0][:2]
+    small = np.nonzero((e_max > 0) & (e_max <= 300))[0][:2]
+    assert len(big) == 2
+    sel = [(int(pairs[0, i]), int(pairs[1, i])) for i in np.concatenate([big, small])]
+    _say(f"[gpu-bwd] uneven largest class: edges {[int(e_max[i]) for i in np.concatenate([big, small])]}")
+    check_grads(ctx, pairs_batch(b, sel, "uneven_largest_class"), seed=63)
+
+
+def test_forward_uneven_both_bodies_above_200_vertices(ctx):
+    """Forward parity on uneven scenes with hulls of up to 256 points: every
+    kept pair whose bodies both exceed 200 vertices (at least one exists for
+    this seed) plus 24 random kept pairs, plain and fused."""
+    b = W.uneven_scenes(400, seed=41)
+    pairs, off = O.broadphase(b)
+    nv = _vertex_counts(b)
+    big = np.nonzero((nv[pairs[0]] > 200) & (nv[pairs[1]] > 200))[0][:3]
+    assert len(big) >= 1
+    rng = np.random.default_rng(64)
+    rest = np.setdiff1d(np.arange(pairs.shape[1]), big)
+    sel = np.sort(np.concatenate([big, rng.choice(rest, 24, replace=False)]))
+    _say(f"[gpu] uneven 400 scenes: {pairs.shape[1]} kept pairs, big pairs {list(big)} "
+         f"(vertices {[(int(nv[pairs[0, i]]), int(nv[pairs[1, i]])) for i in big]})")
+    ids = ctx.create_geometry(b.geoms)
+    db = ctx.upload_batch(b, ids)
+    _, _, ref = O.collide_batch(b, pair_list=pairs[:, sel])
+    for fused in (False, True):
+        m = ctx.collide(db, b.tau, b.K, fused=fused)
+        ctx.check_errors()
+        got = m.to_numpy()
+        assert np.array_equal(got["pairs"], pairs) and np.array_equal(got["offsets"], off)
+        ok, rep = compare_outputs(got, ref, idx=sel)
+        _say(f"   parity uneven (fused={fused}): {rep}")
+        assert ok, rep

@@ -134,3 +134,157 @@ def test_server_budget_admission_and_rejection(setup):
     for t in tickets:
         srv.release(t)
     srv.close()
+
+
+def _oracle_env_check(q, r, pool, tau, K, envs, cot=None):
+    """Served outputs of the kept pairs in environments `envs` against the
+    FP64 oracle; with cot (host cotangents laid out like the outputs) also
+    the pose gradients of those environments' bodies."""
+    from oracle import cm_oracle as O
+    from tests.parity import excess
+    from tests.test_gpu_backward import close
+    cache = O.GeomCache(pool, requires_grad=cot is not None)
+    off = r["offsets"]
+    worst, n = -1.0, 0
+    g_ref, bodies = {}, []
+    for e in envs:
+        for i in range(int(off[e]), int(off[e + 1])):
+            a, b = int(r["pairs"][0, i]), int(r["pairs"][1, i])
+            GA, GB = cache[q.body_geom[a]], cache[q.body_geom[b]]
+            import torch
+            with torch.no_grad():
+                ref = O.collide_pair(GA, q.pose[:, a], GB, q.pose[:, b], tau, K)
+            for k in ("p", "nu", "d", "w"):
+                worst = max(worst, float(excess(r[k][i], ref[k].numpy()).max()))
+            n += 1
+            if cot is not None:
+                sl = slice(i * K, (i + 1) * K)
+                c = dict(p=cot["p"][:, sl].T, nu=cot["nu"][:, sl].T, d=cot["d"][sl], w=cot["w"][sl])
+                g = O.pair_grad(GA, q.pose[:, a], GB, q.pose[:, b], tau, K, c)
+                g_ref[a] = g_ref.get(a, 0) + g["xiA"]
+                g_ref[b] = g_ref.get(b, 0) + g["xiB"]
+        bodies += list(range(int(q.body_offsets[e]), int(q.body_offsets[e + 1])))
+    rep = {"pairs": n, "max_excess": worst}
+    if cot is not None:
+        got = np.stack([r["g_pose"][:, b] for b in bodies])
+        ref = np.stack([g_ref.get(b, np.zeros(6)) for b in bodies])
+        rep["g_pose"] = close(got, ref)
+    return rep
+
+
+def test_served_results_against_oracle_sample():
+    """Served requests over a resident pool of 64-point hulls (the
+    differentiation workload's bodies), forward and forward + backward with
+    all four cotangents: on a seeded 1 % of each request's environments (at
+    least 2) every kept pair matches the FP64 oracle, and so do the pose
+    gradients of those environments' bodies."""
+    from paper_2602_20304_amd.cm import Context, Server
+    ctx = Context(0)
+    pool = W.polytope_pool(32, seed=3, n_points=64)
+    ids = ctx.create_geometry(pool)
+    tau, K = 0.01, 8
+    reqs = W.serving_requests(n_requests=4, seed=8, env_min=150, env_max=300, bodies_min=2, bodies_max=5,
+                              pool_size=32)
+    rng = np.random.default_rng(9)
+    srv = Server(ctx, 1 << 34, n_streams=3)
+    tickets = []
+    for q in reqs:
+        nbe = np.diff(q.body_offsets.astype(np.int64))
+        cap = int((nbe * (nbe - 1) // 2).sum())
+        cot = None
+        if q.want_bwd:
+            cot = dict(p=rng.standard_normal((3, cap * K)).astype(np.float32),
+                       nu=rng.standard_normal((3, cap * K)).astype(np.float32),
+                       d=rng.standard_normal(cap * K).astype(np.float32),
+                       w=rng.standard_normal(cap * K).astype(np.float32))
+        _say(f"[gpu-server] oracle sample: submit envs={q.n_env} bwd={q.want_bwd}")
+        t = srv.submit(q.body_offsets, ids[q.body_geom], q.pose, tau, K, q.want_bwd,
+                       None if cot is None else cot["d"], None if cot is None else cot["nu"],
+                       cot_point=None if cot is None else cot["p"], cot_weight=None if cot is None else cot["w"])
+        tickets.append((t, q, cot))
+    done, _ = _wait(srv, [t for t, _, _ in tickets], 1 << 34)
+    assert any(c is not None for _, _, c in tickets) and any(c is None for _, _, c in tickets)
+    for t, q, cot in tickets:
+        r = done[t]
+        assert r["status"] == 0
+        envs = np.sort(rng.choice(q.n_env, size=max(2, q.n_env // 100), replace=False))
+        rep = _oracle_env_check(q, r, pool, tau, K, envs, cot)
+        _say(f"   served vs oracle ({len(envs)} envs of {q.n_env}): {rep}")
+        assert rep["pairs"] > 0 and rep["max_excess"] <= 0, rep
+        if cot is not None:
+            assert rep["g_pose"][0] <= 0, rep
+        srv.release(t)
+    srv.close()
+    ctx.close()
+
+
+def test_served_backward_all_gradients_match_direct(setup):
+    """A served backward request with all four cotangents and geometry
+    gradients equals cm_collide_backward run alone on the same request:
+    pose, tau, hull-vertex and parameter gradients (float atomics may
+    reorder: 1e-4 relative)."""
+    from paper_2602_20304_amd.cm import DeviceBatch, Server
+    ctx, ids = setup
+    tau, K = 0.01, 8
+    q = W.serving_requests(n_requests=1, seed=12, env_min=40, env_max=40, bodies_min=3, bodies_max=5,
+                           pool_size=24)[0]
+    nbe = np.diff(q.body_offsets.astype(np.int64))
+    cap = int((nbe * (nbe - 1) // 2).sum())
+    rng = np.random.default_rng(13)
+    cot = dict(p=rng.standard_normal((3, cap * K)).astype(np.float32),
+               nu=rng.standard_normal((3, cap * K)).astype(np.float32),
+               d=rng.standard_normal(cap * K).astype(np.float32),
+               w=rng.standard_normal(cap * K).astype(np.float32))
+    srv = Server(ctx, 1 << 34, n_streams=2)
+    _say(f"[gpu-server] full backward: envs={q.n_env}")
+    t = srv.submit(q.body_offsets, ids[q.body_geom], q.pose, tau, K, True, cot["d"], cot["nu"],
+                   cot_point=cot["p"], cot_weight=cot["w"], want_geometry=True)
+    done, _ = _wait(srv, [t], 1 << 34)
+    r = done[t]
+    assert r["status"] == 0
+    dev = ctx.device
+    db = DeviceBatch(q.n_env, int(len(q.body_geom)), torch.as_tensor(q.body_offsets, dtype=torch.int32).to(dev),
+                     torch.as_tensor(ids[q.body_geom], dtype=torch.int32).to(dev),
+                     torch.as_tensor(q.pose, dtype=torch.float32).contiguous().to(dev))
+    m = ctx.collide(db, tau, K)
+    tt = {k: torch.as_tensor(v).to(dev) for k, v in cot.items()}
+    g = ctx.collide_backward(db, m, tau, K, tt["p"], tt["nu"], tt["d"], tt["w"])
+    ctx.check_errors()
+    ref = {"g_pose": g["pose"].cpu().numpy(), "g_tau": float(g["tau"].item()),
+           "g_vertices": g["vertices"].cpu().numpy(), "g_params": g["params"].cpu().numpy()}
+    for k in ("g_pose", "g_vertices", "g_params"):
+        a, b = np.asarray(r[k], np.float64), np.asarray(ref[k], np.float64)
+        assert a.shape == b.shape, k
+        assert np.abs(a - b).max() <= 1e-4 * (np.abs(b).max() + 1e-6), k
+    assert abs(r["g_tau"] - ref["g_tau"]) <= 1e-4 * (abs(ref["g_tau"]) + 1e-6)
+    srv.release(t)
+    srv.close()
+
+
+def test_served_errors_per_request(setup):
+    """A request naming a geometry id the context does not hold is refused at
+    submit with CM_ERR_NOT_FOUND and a message on the calling thread; a
+    malformed body_offsets is CM_ERR_INVALID_ARG; other requests are
+    unaffected."""
+    from paper_2602_20304_amd.cm import Server
+    from paper_2602_20304_amd._lib import CMError
+    ctx, ids = setup
+    tau, K = 0.01, 8
+    q = W.serving_requests(n_requests=1, seed=14, env_min=8, env_max=8, bodies_min=2, bodies_max=3,
+                           pool_size=24)[0]
+    srv = Server(ctx, 1 << 34, n_streams=2)
+    bad_geom = ids[q.body_geom].copy()
+    bad_geom[0] = 10 ** 6
+    with pytest.raises(CMError) as e:
+        srv.submit(q.body_offsets, bad_geom, q.pose, tau, K)
+    assert e.value.status == -6 and "geometry" in str(e.value)
+    bad_off = q.body_offsets.copy()
+    bad_off[0] = -1
+    with pytest.raises(CMError) as e:
+        srv.submit(bad_off, ids[q.body_geom], q.pose, tau, K)
+    assert e.value.status == -1 and "body_offsets" in str(e.value)
+    t = srv.submit(q.body_offsets, ids[q.body_geom], q.pose, tau, K)
+    done, _ = _wait(srv, [t], 1 << 34)
+    assert done[t]["status"] == 0
+    srv.release(t)
+    srv.close()
