@@ -552,6 +552,7 @@ def main():
         res = timer.run(lambda: ctx.collide(db3, b3.tau, b3.K, out=out3, fused=True, stream=stream),
                         args.warmup, args.steps)
         head = record("cfg3_fused_fwd", res, int(out3.n_pairs.item()), cap3)
+        head["tuning"] = ctx.fused_tuning()
         ops3 = config_ops(ctx, ids3, b3, out3)
         rooflines["cfg3_fused_fwd"] = roofline_entry(
             ops3, res["fused_kernel_ms"], "collide_fwd (fused class kernel)", res["fused_launches"],
@@ -598,6 +599,7 @@ def main():
         if only in (None, "cfg4_fused"):
             res = timer.run(lambda: ctx.collide(db4, b4.tau, b4.K, out=out4, fused=True, stream=stream), 1, 1)
             r = record("cfg4_fused_fwd", res, int(out4.n_pairs.item()), cap4)
+            r["tuning"] = ctx.fused_tuning()
             est = r["ms_per_step"] * 1e-3
             ops4 = config_ops(ctx, ids4, b4, out4)
             rooflines["cfg4_fused_fwd"] = roofline_entry(ops4, r["fused_kernel_ms"], "collide_fwd (fused graph)",
@@ -655,6 +657,7 @@ def main():
                 rooflines["cfg2_plain_fwd"] = roofline_entry(ops2, r["forward_kernel_ms"], "collide_fwd (plain)",
                                                              r["forward_launches"], stored_traffic(TRAFFIC_FILE, FWD_SOURCES))
             if name == "cfg2_fused_fwd":
+                r["tuning"] = ctx.fused_tuning()
                 ops2 = config_ops(ctx, ids2, b2, out2)
                 rooflines["cfg2_fused_fwd"] = roofline_entry(ops2, r["fused_kernel_ms"], "collide_fwd (fused graph)",
                                                              r["fused_launches"])

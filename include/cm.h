@@ -263,12 +263,27 @@ cm_status cm_collide(cm_context* ctx, const cm_batch* batch, const cm_params* pr
 
 /* Same results (bit for bit) through the fused batched path: pairs are
  * ordered by cost into size classes and pulled from device work queues by
- * persistent grids whose block sizes are autotuned once per plan; the whole
+ * persistent grids whose block sizes are autotuned (below); the whole
  * sequence is captured once per (batch shape, parameters) in a hipGraph and
  * replayed.  Takes pre-selection and the extended primitives; returns
  * CM_ERR_INVALID_ARG for refine_steps > 0. */
 cm_status cm_collide_fused(cm_context* ctx, const cm_batch* batch, const cm_params* prm, cm_manifold* out,
                            void* stream);
+/* The fused path's autotuner: pairs fall in 3 size classes by the larger edge
+ * count of their bodies (<= 96, <= 300, above), each with its own LDS sizing
+ * and persistent grid.  Once per (geometry set, K) the first
+ * cm_collide_fused call classifies its batch, times each class's kernel at
+ * 256- and 128-thread blocks on the same evenly strided sample of the
+ * class's cost order (about 1/16 of its pairs) and keeps the faster; the
+ * choice is stored in the text file named by CM_TUNE_CACHE (default
+ * $HOME/.cache/cm_fused_tune.txt), keyed by device architecture, CU count
+ * and the class's largest vertex / edge / face counts and K, and read back
+ * by later processes instead of timing.  cm_fused_tuning reports the current
+ * plan: per class (arrays of 3, any may be NULL) the largest edge count, the
+ * block size, the sample size, the sample timings in ms at 256 and 128
+ * ([3][2], 0 when not timed) and whether the choice came from the cache. */
+cm_status cm_fused_tuning(cm_context* ctx, int32_t* class_max_edges, int32_t* class_blocks, int32_t* sample_pairs,
+                          float* sample_ms, int32_t* from_cache);
 
 /* For callers that cannot allocate device memory (code under hipGraph
  * capture, tight serving loops, hosts that forbid hipMalloc): the same

@@ -79,6 +79,7 @@ SIGNATURES = {
     "cm_geometry_destroy": (i32, [vp, vp, i32]),
     "cm_collide": (i32, [vp, C.POINTER(cm_batch), C.POINTER(cm_params), C.POINTER(cm_manifold), vp]),
     "cm_collide_fused": (i32, [vp, C.POINTER(cm_batch), C.POINTER(cm_params), C.POINTER(cm_manifold), vp]),
+    "cm_fused_tuning": (i32, [vp, i32p, i32p, i32p, f32p, i32p]),
     "cm_collide_noalloc": (i32, [vp, C.POINTER(cm_batch), C.POINTER(cm_params), C.POINTER(cm_manifold), vp]),
     "cm_collide_backward": (i32, [vp, C.POINTER(cm_batch), C.POINTER(cm_params), C.POINTER(cm_manifold),
                                   C.POINTER(cm_cotangent), C.POINTER(cm_grads), vp]),

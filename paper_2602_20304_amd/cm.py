@@ -260,6 +260,14 @@ class Context:
         self._check(fn(self.h, C.byref(b), C.byref(prm), C.byref(m), _stream_handle(stream)))
         return out
 
+    def fused_tuning(self) -> dict:
+        """The fused path's per-size-class plan (cm_fused_tuning)."""
+        a = [(C.c_int32 * 3)() for _ in range(4)]
+        ms = (C.c_float * 6)()
+        self._check(self.lib.cm_fused_tuning(self.h, a[0], a[1], a[2], ms, a[3]))
+        return dict(class_max_edges=list(a[0]), class_blocks=list(a[1]), sample_pairs=list(a[2]),
+                    sample_ms=[[ms[2 * c], ms[2 * c + 1]] for c in range(3)], from_cache=[bool(x) for x in a[3]])
+
     # ------------------------------------------------------------- E-E witness points
     def ee_witness(self, edges: torch.Tensor, tau: float, lambda_reg: float = -1.0, hard: bool = False,
                    out: torch.Tensor = None, stream=None) -> torch.Tensor:

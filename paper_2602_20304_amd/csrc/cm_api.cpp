@@ -106,6 +106,7 @@ cm_status cm_context_create(int device, cm_context** out) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) != hipSuccess) { delete ctx; return CM_ERR_DEVICE; }
   ctx->num_cus = prop.multiProcessorCount;
+  ctx->arch = prop.gcnArchName;
   if (hipMalloc(&ctx->d_err, sizeof(unsigned)) != hipSuccess || hipMemset(ctx->d_err, 0, sizeof(unsigned)) != hipSuccess) {
     delete ctx;
     return CM_ERR_OOM;

@@ -34,6 +34,7 @@ struct CmDevCaps {
 struct cm_context {
   int device = 0;
   int num_cus = 1;
+  std::string arch;           // device architecture name (autotune cache key)
   CmPools h;
   CmDevPools d;
   CmDevCaps dcap;
@@ -58,6 +59,9 @@ struct cm_context {
   bool plan_tuned = false;
   int cls_maxE[3] = {0, 0, 0}, cls_maxV[3] = {0, 0, 0}, cls_maxF[3] = {0, 0, 0}, cls_block[3] = {256, 256, 256};
   int cls_bound[2] = {96, 300};
+  float cls_tuned_ms[3][2] = {};   // autotune sample timings (block 256, 128), 0 = not timed
+  int cls_tune_n[3] = {0, 0, 0};   // sample sizes
+  int cls_cached[3] = {0, 0, 0};   // choice taken from the cache file
   void* d_fused = nullptr;
   size_t fused_cap = 0;
   hipStream_t cap_stream = nullptr;

@@ -285,10 +285,12 @@ __device__ __forceinline__ BodyView load_uniform(const BodyView& src, bool with_
   return v;
 }
 
-// A subset of a polytope's faces (bit f of word f / 64); n = 0 means all
-// faces.
+// Polytopes of up to 64 * kMaxMaskWords faces are culled.
+constexpr int kMaxMaskWords = 8;
+// A subset of a polytope's faces, in LDS: the first n words (bit f of word
+// f / 64), shared by every active lane of a wave; n = 0 means all faces.
 struct FaceMask {
-  unsigned long long w[2];
+  unsigned long long w[kMaxMaskWords];
   int n;
 };
 
@@ -298,6 +300,14 @@ __device__ __forceinline__ unsigned long long uni64(unsigned long long v) {
   return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
 }
 
+// Word w of a face mask, limited to the polytope's nf faces, made
+// wave-uniform (scalar registers).
+__device__ __forceinline__ unsigned long long mask_word(const FaceMask& mk, int w, int nf) {
+  const int rem = nf - 64 * w;
+  const unsigned long long valid = rem >= 64 ? ~0ull : (rem > 0 ? (1ull << rem) - 1ull : 0ull);
+  return uni64(mk.w[w]) & valid;
+}
+
 // sdf_poly restricted to the faces of a mask that every active lane of the
 // wave shares: a wave-uniform walk over its set bits in increasing face order,
 // two faces per step with both LDS loads issued before either is used (a
@@ -305,18 +315,13 @@ __device__ __forceinline__ unsigned long long uni64(unsigned long long v) {
 template <int MODE>
 __device__ __forceinline__ void sdf_poly_masked(const double4* __restrict__ pd, int nf, const FaceMask& mk,
                                                 const D3& x, const Temp& T, double& phi, D3& g) {
-  const unsigned long long valid[2] = {nf >= 64 ? ~0ull : (1ull << nf) - 1ull,
-                                       nf >= 128 ? ~0ull : (nf > 64 ? (1ull << (nf - 64)) - 1ull : 0ull)};
-  unsigned long long u[2];
-#pragma unroll
-  for (int w = 0; w < 2; ++w) u[w] = w < mk.n ? uni64(mk.w[w]) & valid[w] : 0ull;
+  const int nw = mk.n;
   double m = 0.0;
   if (MODE != kSurfGrad) {
     m = -1e300;
-#pragma unroll
-    for (int w = 0; w < 2; ++w) {
+    for (int w = 0; w < nw; ++w) {
       const double4* pw = pd + 64 * w;
-      unsigned long long bits = u[w];
+      unsigned long long bits = mask_word(mk, w, nf);
       while (bits) {
         const int b0 = __builtin_ctzll(bits);
         bits &= bits - 1ull;
@@ -336,10 +341,9 @@ __device__ __forceinline__ void sdf_poly_masked(const double4* __restrict__ pd, 
   }
   float s = 0.f;
   double S = 0.0, ax = 0.0, ay = 0.0, az = 0.0;
-#pragma unroll
-  for (int w = 0; w < 2; ++w) {
+  for (int w = 0; w < nw; ++w) {
     const double4* pw = pd + 64 * w;
-    unsigned long long bits = u[w];
+    unsigned long long bits = mask_word(mk, w, nf);
     while (bits) {
       const int b0 = __builtin_ctzll(bits);
       bits &= bits - 1ull;

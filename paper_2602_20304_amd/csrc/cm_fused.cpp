@@ -5,7 +5,16 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+
+#include <sys/stat.h>
 
 #include "cm_context.h"
 #include "cm_kernels.h"
@@ -58,6 +67,57 @@ FwdLaunch class_launch(cm_context* ctx, const BatchDev& bd, const ParamsDev& pd,
   return f;
 }
 
+// Persistent autotune cache: one "key block" line per tuned (device, size
+// class) configuration, in the file named by CM_TUNE_CACHE (default
+// $HOME/.cache/cm_fused_tune.txt; none without HOME).  Read on first use and
+// whenever that name changes, appended to after each tuning; an unreadable
+// or unwritable file only disables the cache.
+std::mutex g_tune_mu;
+bool g_tune_loaded = false;
+std::string g_tune_loaded_path;
+std::map<std::string, int> g_tune;
+
+std::string tune_path() {
+  if (const char* p = std::getenv("CM_TUNE_CACHE")) return p;
+  if (const char* h = std::getenv("HOME")) return std::string(h) + "/.cache/cm_fused_tune.txt";
+  return std::string();
+}
+
+std::string tune_key(const cm_context* ctx, int c, int kmax) {
+  std::ostringstream k;
+  k << ctx->arch << ":cu" << ctx->num_cus << ":E" << ctx->cls_maxE[c] << ":V" << ctx->cls_maxV[c] << ":F"
+    << ctx->cls_maxF[c] << ":k" << kmax;
+  return k.str();
+}
+
+int tune_lookup(const std::string& key) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  const std::string p = tune_path();
+  if (!g_tune_loaded || p != g_tune_loaded_path) {   // (re)read when the file name changes
+    g_tune_loaded = true;
+    g_tune_loaded_path = p;
+    g_tune.clear();
+    std::ifstream in(p);
+    std::string k;
+    int b;
+    while (in >> k >> b)
+      if (b == 128 || b == 256) g_tune[k] = b;
+  }
+  auto it = g_tune.find(key);
+  return it == g_tune.end() ? 0 : it->second;
+}
+
+void tune_store(const std::string& key, int block) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[key] = block;
+  const std::string p = tune_path();
+  if (p.empty()) return;
+  const size_t slash = p.find_last_of('/');
+  if (slash != std::string::npos && slash > 0) (void)::mkdir(p.substr(0, slash).c_str(), 0755);
+  std::ofstream out(p, std::ios::app);
+  if (out) out << key << " " << block << "\n";
+}
+
 uint64_t mix(uint64_t h, uint64_t v) {
   h ^= v + 0x9e3779b97f4a7c15ULL + (h << 6) + (h >> 2);
   return h;
@@ -81,7 +141,8 @@ extern "C" cm_status cm_collide_fused(cm_context* ctx, const cm_batch* batch, co
 
   // work buffers: counts, ranges, queues, order[cap], keys[cap]
   const size_t head = 4 * (kNumClasses * kNumBuckets + 2 * kNumClasses + kNumClasses + 16);
-  const size_t need = head + 8 * size_t(std::max(od.capacity, 1));
+  // order[cap], keys[cap], then the autotune sample (cap pairs + range + queue)
+  const size_t need = head + 12 * size_t(std::max(od.capacity, 1)) + 64;
   hipError_t e = ctx_ensure(ctx, &ctx->d_fused, &ctx->fused_cap, need);
   if (e != hipSuccess) return cm_hip(ctx, e, "fused work buffers");
   int* base = static_cast<int*>(ctx->d_fused);
@@ -91,6 +152,7 @@ extern "C" cm_status cm_collide_fused(cm_context* ctx, const cm_batch* batch, co
   w.queues = w.ranges + 2 * kNumClasses;
   w.order = reinterpret_cast<int*>(reinterpret_cast<char*>(ctx->d_fused) + head);
   w.keys = w.order + std::max(od.capacity, 1);
+  w.sample = w.keys + std::max(od.capacity, 1);
 
   FwdLaunch fl[kNumClasses];
   auto plan_scratch = [&]() -> cm_status {
@@ -118,35 +180,75 @@ extern "C" cm_status cm_collide_fused(cm_context* ctx, const cm_batch* batch, co
   e = ctx_ensure(ctx, reinterpret_cast<void**>(&ctx->d_tile_sums), &ctx->tile_cap, tiles * sizeof(int));
   if (e != hipSuccess) return cm_hip(ctx, e, "tile sums");
 
-  // autotune the block size of each class once per plan, on this batch
+  // Autotune the block size of each size class once per plan: cached
+  // choices first; otherwise, after this batch's broadphase and
+  // classification, every candidate block size runs on the same evenly
+  // strided sample of the class's cost order (about 1/16 of the class, at
+  // least 4 pairs per workgroup of the larger grid) and the fastest is kept
   // (full-method calls on the basic primitives only: pre-selection and the
-  // extended primitives always run 256-thread blocks)
+  // extended primitives always run 256-thread blocks).
   if (!ctx->plan_tuned && od.capacity > 0 && pd.presel_v == 0 && !pd.sq) {
-    ctx->cls_block[0] = ctx->cls_block[1] = ctx->cls_block[2] = 256;
-    if ((s = plan_scratch()) != CM_OK) return s;
-    if ((e = record(st)) != hipSuccess) return cm_hip(ctx, e, "fused warm-up");
-    hipEvent_t e0, e1;
-    (void)hipEventCreate(&e0);
-    (void)hipEventCreate(&e1);
+    const int kmax = kmax_for(pd.K);
+    bool all_cached = true;
     for (int c = 0; c < kNumClasses; ++c) {
-      float best = 1e30f;
-      int best_block = 256;
-      for (int blk : {256, 128}) {
-        ctx->cls_block[c] = blk;
-        if ((s = plan_scratch()) != CM_OK) return s;
-        (void)hipMemsetAsync(w.queues + c, 0, sizeof(int), st);
-        (void)hipEventRecord(e0, st);
-        if ((e = launch_collide_fwd(fl[c], st)) != hipSuccess) return cm_hip(ctx, e, "autotune launch");
-        (void)hipEventRecord(e1, st);
-        (void)hipEventSynchronize(e1);
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        if (ms < best) { best = ms; best_block = blk; }
-      }
-      ctx->cls_block[c] = best_block;
+      const int b = tune_lookup(tune_key(ctx, c, kmax));
+      ctx->cls_cached[c] = b;
+      ctx->cls_block[c] = b ? b : 256;
+      all_cached &= b != 0;
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    if (!all_cached) {
+      if ((s = plan_scratch()) != CM_OK) return s;
+      if ((e = launch_broadphase(ctx_tables(ctx), bd, pd.margin, od, ctx->d_tile_sums, ctx->d_err, st)) != hipSuccess ||
+          (e = launch_fused_prepare(ctx_tables(ctx), bd, od, cmax, w, st)) != hipSuccess)
+        return cm_hip(ctx, e, "autotune classification");
+      int ranges[2 * kNumClasses];
+      if ((e = hipMemcpyAsync(ranges, w.ranges, sizeof(ranges), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+          (e = hipStreamSynchronize(st)) != hipSuccess)
+        return cm_hip(ctx, e, "autotune ranges");
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess)
+        return cm_hip(ctx, e, "autotune events");
+      for (int c = 0; c < kNumClasses && s == CM_OK; ++c) {
+        const int count = ranges[2 * c + 1];
+        ctx->cls_tune_n[c] = 0;
+        ctx->cls_tuned_ms[c][0] = ctx->cls_tuned_ms[c][1] = 0.f;
+        if (ctx->cls_cached[c] || count <= 0) continue;
+        float best = 1e30f;
+        int best_block = 256;
+        const int blocks[2] = {256, 128};
+        for (int bi = 0; bi < 2; ++bi) {
+          ctx->cls_block[c] = blocks[bi];
+          if ((s = plan_scratch()) != CM_OK) break;
+          FwdLaunch t = fl[c];
+          if (bi == 0) {
+            const int n = std::min(count, std::max(count / 16, 4 * 2 * t.grid));
+            ctx->cls_tune_n[c] = n;
+            if ((e = launch_fused_sample(w, c, n, w.sample, w.sample + n + 1, st)) != hipSuccess) {
+              s = cm_hip(ctx, e, "autotune sample");
+              break;
+            }
+          }
+          const int n = ctx->cls_tune_n[c];
+          t.order = w.sample;
+          t.range = w.sample + n + 1;
+          t.queue = w.sample + n + 3;
+          (void)hipMemsetAsync(t.queue, 0, sizeof(int), st);
+          (void)hipEventRecord(e0, st);
+          if ((e = launch_collide_fwd(t, st)) != hipSuccess) { s = cm_hip(ctx, e, "autotune launch"); break; }
+          (void)hipEventRecord(e1, st);
+          (void)hipEventSynchronize(e1);
+          float ms = 0.f;
+          (void)hipEventElapsedTime(&ms, e0, e1);
+          ctx->cls_tuned_ms[c][bi] = ms;
+          if (ms < best) { best = ms; best_block = blocks[bi]; }
+        }
+        ctx->cls_block[c] = best_block;
+        if (s == CM_OK) tune_store(tune_key(ctx, c, kmax), best_block);
+      }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      if (s != CM_OK) return s;
+    }
     ctx->plan_tuned = true;
   }
   if ((s = plan_scratch()) != CM_OK) return s;
@@ -194,5 +296,22 @@ extern "C" cm_status cm_collide_fused(cm_context* ctx, const cm_batch* batch, co
   if ((s = cm_hip(ctx, hipGraphLaunch(exec, st), "graph launch")) != CM_OK) return s;
   timer_end(ctx, CM_TIMER_FUSED, t0, st);
   ctx_mark(ctx, st);
+  return CM_OK;
+}
+
+// The fused path's current plan: per size class its largest edge count, the
+// block size in use, the autotune sample size and the sample timings at
+// blocks 256 and 128 (0 when not timed), and whether the choice came from
+// the cache file.
+extern "C" cm_status cm_fused_tuning(cm_context* ctx, int32_t* class_max_edges, int32_t* class_blocks,
+                                     int32_t* sample_pairs, float* sample_ms, int32_t* from_cache) {
+  if (!ctx) return CM_ERR_INVALID_ARG;
+  for (int c = 0; c < kNumClasses; ++c) {
+    if (class_max_edges) class_max_edges[c] = ctx->cls_maxE[c];
+    if (class_blocks) class_blocks[c] = ctx->cls_block[c];
+    if (sample_pairs) sample_pairs[c] = ctx->cls_tune_n[c];
+    if (sample_ms) { sample_ms[2 * c] = ctx->cls_tuned_ms[c][0]; sample_ms[2 * c + 1] = ctx->cls_tuned_ms[c][1]; }
+    if (from_cache) from_cache[c] = ctx->cls_cached[c] != 0;
+  }
   return CM_OK;
 }

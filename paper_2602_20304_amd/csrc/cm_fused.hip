@@ -97,6 +97,27 @@ __global__ void fused_scatter(OutDev out, const int* __restrict__ keys, int* __r
   }
 }
 
+// Evenly strided sample of size class c's cost order (autotuning): sample[i]
+// = order[start + i * count / m] for i < m = min(n, count), and the sample's
+// {0, m} range for the class kernel.
+__global__ void fused_sample(const int* __restrict__ order, const int* __restrict__ ranges, int c, int n,
+                             int* __restrict__ sample, int* __restrict__ sample_range) {
+  const int start = ranges[2 * c], count = ranges[2 * c + 1];
+  const int m = min(n, count);
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x)
+    sample[i] = order[start + int((long long)i * count / m)];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sample_range[0] = 0;
+    sample_range[1] = m;
+  }
+}
+
+hipError_t launch_fused_sample(const FusedWork& w, int c, int n, int* sample, int* sample_range, hipStream_t st) {
+  const int grid = std::max(1, std::min(1024, (n + 255) / 256));
+  hipLaunchKernelGGL(fused_sample, dim3(grid), dim3(256), 0, st, w.order, w.ranges, c, n, sample, sample_range);
+  return hipGetLastError();
+}
+
 hipError_t launch_fused_prepare(const Tables& tb, const BatchDev& bt, const OutDev& out, const int* class_maxE,
                                 const FusedWork& w, hipStream_t st) {
   hipLaunchKernelGGL(fused_zero, dim3(1), dim3(256), 0, st, w.counts, w.queues);

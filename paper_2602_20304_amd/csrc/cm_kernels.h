@@ -82,8 +82,12 @@ struct FusedWork {
   int* queues;    // [kNumClasses] work-queue counters
   int* order;     // [capacity] pair indices, class-major, cost-descending
   int* keys;      // [capacity]
+  int* sample;    // [capacity + 4] autotune sample order, then its range {0, n} and queue counter
 };
 hipError_t launch_fused_prepare(const Tables& tb, const BatchDev& bt, const OutDev& out, const int* class_maxE,
                                 const FusedWork& w, hipStream_t st);
+// autotuning sample: n pairs evenly strided over class c's cost order into
+// sample[], with the device range {0, min(n, count)} in sample_range[2]
+hipError_t launch_fused_sample(const FusedWork& w, int c, int n, int* sample, int* sample_range, hipStream_t st);
 
 }  // namespace cm

@@ -45,7 +45,7 @@ struct Rec {
 };
 
 struct LdsLayout {
-  int eA, eB, row, col, red, top, rec, acc, pA, pB, cnt, mA, mB, mA2, mB2, g1, g2, bytes;
+  int eA, eB, row, col, red, top, rec, acc, pA, pB, cnt, g1, g2, bytes;
   bool edges_lds;   // false: the edge arrays live in the workgroup's scratch slot
 };
 
@@ -53,10 +53,13 @@ struct LdsLayout {
 // the kernels' static shared variables.
 constexpr int kLdsBudget = 160 * 1024 - 1024;
 
-// 64-bit words of a per-edge face mask (0: culling off): one word up to 64
-// faces, two up to 128; larger polytopes are not culled.
+// 64-bit words of a face mask (0: culling off): the fewest powers of two
+// covering maxF faces, up to kMaxMaskWords (512 faces); larger polytopes
+// are not culled.
 __host__ __device__ inline int mask_words(int maxF) {
-  return maxF <= 64 ? 1 : (maxF <= 128 ? 2 : 0);
+  int w = 1;
+  while (64 * w < maxF && w < kMaxMaskWords) w <<= 1;
+  return 64 * w >= maxF ? w : 0;
 }
 
 // extra: LDS bytes the calling kernel needs beyond the engine.  When the
@@ -67,14 +70,12 @@ __host__ __device__ inline LdsLayout lds_layout(int maxE, int maxF, int block, i
   int o = 0;
   const int edge_bytes = 2 * 6 * 8 * maxE;
   // the face masks (cull to pass 2) and the SoftSort records (after pass 2)
-  // are never live together: they share one region
-  const int mask_bytes = 8 * mask_words(maxF) * maxE;
-  // masks of the groups of 8 consecutive edges: per group of A's and of B's
-  // edges, the union over the group (faces of A, faces of B)
-  const int group_bytes = mask_words(maxF) > 0 ? 2 * 2 * ((maxE + 7) / 8) * int(sizeof(FaceMask)) : 0;
+  // are never live together: they share one region.  Masks of the groups of
+  // 8 consecutive edges: per group of A's and of B's edges, the union over
+  // the group's segments (faces of A, faces of B).
+  const int group_bytes = mask_words(maxF) > 0 ? 2 * ((maxE + 7) / 8) * 2 * int(sizeof(FaceMask)) : 0;
   const int rec_bytes = int(sizeof(Rec)) * block;
-  const int mask_total = 4 * mask_bytes + group_bytes;
-  const int shared_bytes = ((rec_bytes > mask_total ? rec_bytes : mask_total) + 7) & ~7;
+  const int shared_bytes = ((rec_bytes > group_bytes ? rec_bytes : group_bytes) + 7) & ~7;
   L.edges_lds = true;
   {
     // size with the edges in LDS (same sequence as below)
@@ -91,12 +92,8 @@ __host__ __device__ inline LdsLayout lds_layout(int maxE, int maxF, int block, i
   L.red = o; o += 2 * 8 * block;
   L.top = o; o += 8 * 64;
   L.rec = o;
-  L.mA = o;                      // A's faces near each edge segment of A
-  L.mB = o + mask_bytes;         // B's faces near each edge segment of A
-  L.mA2 = o + 2 * mask_bytes;    // A's faces near each edge segment of B
-  L.mB2 = o + 3 * mask_bytes;    // B's faces near each edge segment of B
-  L.g1 = o + 4 * mask_bytes;     // [group of A's edges][A's faces, B's faces]
-  L.g2 = L.g1 + group_bytes / 2; // [group of B's edges][A's faces, B's faces]
+  L.g1 = o;                      // [group of A's edges][A's faces, B's faces]
+  L.g2 = o + group_bytes / 2;    // [group of B's edges][A's faces, B's faces]
   o += shared_bytes;
   L.acc = o; o += 8 * 9 * CM_MAX_K;
   L.pA = o; o += 32 * maxF;    // double4 planes (n.xyz, o)
@@ -136,12 +133,8 @@ struct PairEngine {
   Rec* sRec;
   double* sAcc;   // [9K] unnormalised SoftSort sums (1, p, nu, d, w) per row
   int* sCnt;
-  unsigned long long* sMA;   // [maxE][MW] face masks of A's edges, see cull()
-  unsigned long long* sMB;
-  unsigned long long* sMA2;  // [maxE][MW] face masks of B's edges
-  unsigned long long* sMB2;
-  FaceMask* sG1;             // [ceil(maxE / 8)][2] unions over groups of 8 edges of A
-  FaceMask* sG2;             // [ceil(maxE / 8)][2] unions over groups of 8 edges of B
+  FaceMask* sG1;             // [ceil(maxE / 8)][2] face masks of groups of 8 edges of A, see cull()
+  FaceMask* sG2;             // [ceil(maxE / 8)][2] the same for B's edges
   int MW;
   double* Dbuf;   // [maxE^2] unsigned distance of edge pair (k, l) at k * neB + l
   double* Al1;    // [maxE^2] QP solution al1, al2 and ln con of the same edge pair
@@ -181,10 +174,6 @@ struct PairEngine {
     sRec = reinterpret_cast<Rec*>(smem + L.rec);
     sAcc = reinterpret_cast<double*>(smem + L.acc);
     sCnt = reinterpret_cast<int*>(smem + L.cnt);
-    sMA = reinterpret_cast<unsigned long long*>(smem + L.mA);
-    sMB = reinterpret_cast<unsigned long long*>(smem + L.mB);
-    sMA2 = reinterpret_cast<unsigned long long*>(smem + L.mA2);
-    sMB2 = reinterpret_cast<unsigned long long*>(smem + L.mB2);
     sG1 = reinterpret_cast<FaceMask*>(smem + L.g1);
     sG2 = reinterpret_cast<FaceMask*>(smem + L.g2);
     sMet = reinterpret_cast<double*>(smem + L.bytes);
@@ -439,11 +428,22 @@ struct PairEngine {
   // linear along the segment, so face g is dropped when
   // max(y'_g(p0), y'_g(p1)) < max_f min(y'_f(p0), y'_f(p1)) - 38, which
   // bounds its term in the LSE and in the gradient softmax below 2^-38.
-  // Witness 1 lies on an edge of A, witness 2 on an edge of B.
+  // Witness 1 lies on an edge of A, witness 2 on an edge of B.  The
+  // candidate pass needs the union over each group of 8 consecutive edges
+  // (the rows and columns of its tiles): each edge's thread ORs its
+  // segment's words into its group's masks (LDS atomics), so no per-edge
+  // mask is stored.
   __device__ __forceinline__ void cull() {
     if (!CULL || MW == 0 || ps.nee == 0) return;
     const double ext = 0.3 * T.tau;
     const int neA = A.ne;
+    const int ngA = (neA + 7) >> 3, ngB = (B.ne + 7) >> 3;
+    for (int i = tid; i < 2 * (ngA + ngB); i += BLOCK) {
+      FaceMask& m = i < 2 * ngA ? sG1[i] : sG2[i - 2 * ngA];
+      for (int w = 0; w < MW; ++w) m.w[w] = 0ull;
+      m.n = MW;
+    }
+    __syncthreads();
     for (int i = tid; i < neA + B.ne; i += BLOCK) {
       const bool onA = i < neA;
       const int k = onA ? i : i - neA;
@@ -452,37 +452,17 @@ struct PairEngine {
       else EB.get(k, a0, t1);
       const D3 p0 = d3(a0.x - ext * t1.x, a0.y - ext * t1.y, a0.z - ext * t1.z);
       const D3 p1 = d3(a0.x + (1.0 + ext) * t1.x, a0.y + (1.0 + ext) * t1.y, a0.z + (1.0 + ext) * t1.z);
-      unsigned long long* oA = onA ? sMA : sMA2;
-      unsigned long long* oB = onA ? sMB : sMB2;
-      seg_mask(A, false, p0, p1, oA + k * MW);
-      seg_mask(B, true, p0, p1, oB + k * MW);
-    }
-    __syncthreads();
-    // unions over the groups of 8 consecutive edges (the rows and columns of
-    // the candidate pass's tiles)
-    const int ngA = (neA + 7) >> 3, ngB = (B.ne + 7) >> 3;
-    for (int i = tid; i < ngA + ngB; i += BLOCK) {
-      const bool onA = i < ngA;
-      const int g = onA ? i : i - ngA;
-      const int e0 = 8 * g, e1 = min(onA ? neA : B.ne, e0 + 8);
-      const unsigned long long* iA = onA ? sMA : sMA2;
-      const unsigned long long* iB = onA ? sMB : sMB2;
-      unsigned long long a0 = 0ull, a1 = 0ull, b0 = 0ull, b1 = 0ull;
-      for (int e = e0; e < e1; ++e) {
-        a0 |= iA[e * MW]; b0 |= iB[e * MW];
-        if (MW > 1) { a1 |= iA[e * MW + 1]; b1 |= iB[e * MW + 1]; }
-      }
-      FaceMask* o = (onA ? sG1 : sG2) + 2 * g;
-      o[0].w[0] = a0; o[0].w[1] = a1; o[0].n = MW;
-      o[1].w[0] = b0; o[1].w[1] = b1; o[1].n = MW;
+      FaceMask* grp = (onA ? sG1 : sG2) + 2 * (k >> 3);
+      seg_mask_or(A, false, p0, p1, grp[0].w);
+      seg_mask_or(B, true, p0, p1, grp[1].w);
     }
     __syncthreads();
   }
-  __device__ __forceinline__ void seg_mask(const BodyView& V, bool moved, const D3& p0w, const D3& p1w,
-                                           unsigned long long* out) const {
+  // OR the faces of V near segment [p0w, p1w] (pair frame) into out[MW]
+  __device__ __forceinline__ void seg_mask_or(const BodyView& V, bool moved, const D3& p0w, const D3& p1w,
+                                              unsigned long long* out) const {
     if (V.type != CM_POLYTOPE) {
-      out[0] = ~0ull;
-      if (MW > 1) out[1] = ~0ull;
+      for (int w = 0; w < MW; ++w) atomicOr(out + w, ~0ull);
       return;
     }
     D3 p0 = p0w, p1 = p1w;
@@ -501,17 +481,17 @@ struct PairEngine {
       const double y1 = fma(q.x, p1.x, fma(q.y, p1.y, fma(q.z, p1.z, -q.w)));
       L = fmax(L, fmin(y0, y1));
     }
-    unsigned long long m0 = 0ull, m1 = 0ull;
+    unsigned long long m = 0ull;
     for (int f = 0; f < V.nf; ++f) {
       const double4 q = V.planes[f];
       const double y0 = fma(q.x, p0.x, fma(q.y, p0.y, fma(q.z, p0.z, -q.w)));
       const double y1 = fma(q.x, p1.x, fma(q.y, p1.y, fma(q.z, p1.z, -q.w)));
-      const unsigned long long bit = fmax(y0, y1) >= L - 38.0 ? 1ull << (f & 63) : 0ull;
-      if (f < 64) m0 |= bit;
-      else m1 |= bit;
+      if (fmax(y0, y1) >= L - 38.0) m |= 1ull << (f & 63);
+      if ((f & 63) == 63 || f == V.nf - 1) {
+        if (m) atomicOr(out + (f >> 6), m);
+        m = 0ull;
+      }
     }
-    out[0] = m0;
-    if (MW > 1) out[1] = m1;
   }
 
   // ------------------------------------------------------------ candidates
@@ -642,6 +622,7 @@ struct PairEngine {
       const int kk = lane >> 3, ll = lane & 7;
       for (int t = wave; t < ntiles; t += NW) {
         const int k0 = (t / ntl) * 8, l0 = (t - (t / ntl) * ntl) * 8;
+        // the tile's group masks: [A's faces, B's faces] near its rows / columns
         const FaceMask* m1 = MW > 0 ? sG1 + 2 * (k0 >> 3) : nullptr;
         const FaceMask* m2 = MW > 0 ? sG2 + 2 * (l0 >> 3) : nullptr;
         const int k = k0 + kk, l = l0 + ll;

@@ -192,3 +192,30 @@ def test_backward_presel_with_simplifications(ctx):
     b = W.cube_pairs(16, seed=28, K=12)
     b.pose[4:7] += np.array([[0.3], [-0.2], [0.5]], dtype=b.pose.dtype)   # body A off the origin
     check(ctx, b, flags=2, presel=(4, 6))
+
+
+def test_adjoint_lds_overflow_reported():
+    """A context holding a hull of 600 points (1,794 edges, 1,196 faces): the
+    forward fits in 160 KiB of LDS, the adjoint would not, so
+    cm_collide_backward returns a clear CM_ERR_INVALID_ARG naming LDS before
+    any launch (the two bodies are far apart: no pair is kept)."""
+    from paper_2602_20304_amd.cm import Context
+    from paper_2602_20304_amd._lib import CMError
+    c = Context(0)
+    rng = np.random.default_rng(3)
+    gs = W._geomset([W.POLYTOPE], [np.zeros(4)], [W.ellipsoid_points(rng, 600, [0.5, 0.4, 0.45])])
+    pose = np.zeros((7, 2), np.float32)
+    pose[0] = 1.0
+    pose[4, 1] = 5.0
+    b = W.Batch(geoms=gs, body_offsets=np.array([0, 2], np.int32), body_geom=np.array([0, 0], np.int32),
+                pose=pose, tau=0.01, K=8, name="hull600_apart")
+    _say("[gpu-bwd] adjoint LDS overflow: hull of 600 points")
+    ids = c.create_geometry(gs)
+    db = c.upload_batch(b, ids)
+    m = c.collide(db, b.tau, b.K)
+    c.check_errors()
+    assert int(m.n_pairs.item()) == 0
+    g = torch.zeros(m.dist.shape, device=c.device)
+    with pytest.raises(CMError, match="LDS"):
+        c.collide_backward(db, m, b.tau, b.K, None, None, g, None)
+    c.close()

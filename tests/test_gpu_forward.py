@@ -238,3 +238,36 @@ def test_calls_on_two_streams_are_ordered(ctx):
         g = m.to_numpy()
         for k in ("pairs", "offsets", "p", "nu", "d", "w"):
             assert np.array_equal(g[k], r[k]), k
+
+
+def test_fused_autotune_sample_and_cache(tmp_path, monkeypatch):
+    """The fused path's autotuner times its size classes on strided samples
+    and stores the choices; a fresh context with the same geometry reads them
+    back from the cache file instead of timing, with the same results."""
+    from paper_2602_20304_amd.cm import Context
+    monkeypatch.setenv("CM_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    b = W.uneven_scenes(60, seed=33, v_max=160)
+    _say(f"[gpu] autotune cache: {b.n_scenes} scenes")
+    outs = []
+    for run in range(2):
+        c = Context(0)
+        ids = c.create_geometry(b.geoms)
+        db = c.upload_batch(b, ids)
+        m = c.collide(db, b.tau, b.K, fused=True)
+        c.check_errors()
+        t = c.fused_tuning()
+        _say(f"   run {run}: {t}")
+        if run == 0:
+            assert not any(t["from_cache"])
+            timed = [i for i in range(3) if t["sample_pairs"][i] > 0]
+            assert timed and all(min(t["sample_ms"][i]) > 0 for i in timed)
+            lines = (tmp_path / "tune.txt").read_text().split("\n")
+            assert len([x for x in lines if x.strip()]) == len(timed)
+        else:
+            assert all(t["from_cache"][i] for i in timed) and not any(t["sample_pairs"])
+            assert t["class_blocks"] == first["class_blocks"]
+        first = t if run == 0 else first
+        outs.append(m.to_numpy())
+        c.close()
+    for k in ("pairs", "offsets", "p", "nu", "d", "w"):
+        assert np.array_equal(outs[0][k], outs[1][k]), k
