@@ -129,9 +129,12 @@ typedef struct {
  * grad phi at the QP witness, x <- x - phi(x) n, refine_steps times; the
  * contact point, distance, normal and the sign / penetration / clashing tests
  * use the moved points, the nearest-neighbour ranking keeps the QP
- * distances.  cm_collide and served forward requests take it with K <= 16;
- * cm_collide_fused, cm_collide_backward and served backward requests return
- * CM_ERR_INVALID_ARG for it. */
+ * distances.  cm_collide, cm_collide_backward and served requests (forward
+ * and backward) take it with K <= 16 and at most 4096 vertices and edges per
+ * body; cm_collide_fused returns CM_ERR_INVALID_ARG for it.  The adjoint
+ * reverses every step: x_s_bar gains grad phi(x_s) (-n . x_{s+1}_bar), the
+ * direction gains -phi(x_s) x_{s+1}_bar, and the direction's adjoint reaches
+ * the QP witness through the Hessian of phi there. */
 #define CM_MAX_REFINE 8
 
 /* Simplifications the paper evaluates for speed (supplementary material,
@@ -312,8 +315,9 @@ cm_status cm_collide_noalloc(cm_context* ctx, const cm_batch* batch, const cm_pa
  * intermediate from the inputs and the kept-pair list in `fwd` (no E x E
  * state is stored by the forward), then reverses the SoftSort, the
  * activity/score terms, the nearest-neighbour softmaxes, the SDF queries,
- * the witness QP and the rigid transforms.  Broadphase decisions and hull
- * topology are held fixed. */
+ * the witness QP and the rigid transforms (with refine_steps > 0 also the
+ * sphere-tracing steps, above).  Broadphase decisions and hull topology are
+ * held fixed. */
 cm_status cm_collide_backward(cm_context* ctx, const cm_batch* batch, const cm_params* prm,
                               const cm_manifold* fwd, const cm_cotangent* cot, cm_grads* out, void* stream);
 

@@ -325,29 +325,31 @@ class _CollideFn(torch.autograd.Function):
     cm_collide at the batch's poses, the backward cm_collide_backward."""
 
     @staticmethod
-    def forward(fctx, xi, verts, params, tau_t, cmctx, db, K, capacity, fused, flags, presel):
+    def forward(fctx, xi, verts, params, tau_t, cmctx, db, K, capacity, fused, flags, presel, refine):
         tau = float(tau_t.item())
-        m = cmctx.collide(db, tau, K, capacity, fused=fused, flags=flags, presel=presel)
-        fctx.cm = (cmctx, db, m, tau, K, flags, presel)
+        m = cmctx.collide(db, tau, K, capacity, fused=fused, flags=flags, presel=presel, refine=refine)
+        fctx.cm = (cmctx, db, m, tau, K, flags, presel, refine)
         fctx.mark_non_differentiable(m.n_pairs, m.pairs)
         return m.point, m.normal, m.dist, m.weight, m.n_pairs, m.pairs
 
     @staticmethod
     def backward(fctx, gp, gn, gd, gw, _n, _p):
-        cmctx, db, m, tau, K, flags, presel = fctx.cm
+        cmctx, db, m, tau, K, flags, presel, refine = fctx.cm
         c = lambda t: None if t is None else t.contiguous()
-        g = cmctx.collide_backward(db, m, tau, K, c(gp), c(gn), c(gd), c(gw), flags=flags, presel=presel)
-        return g["pose"], g["vertices"], g["params"], g["tau"], None, None, None, None, None, None, None
+        g = cmctx.collide_backward(db, m, tau, K, c(gp), c(gn), c(gd), c(gw), flags=flags, presel=presel,
+                                   refine=refine)
+        return g["pose"], g["vertices"], g["params"], g["tau"], None, None, None, None, None, None, None, None
 
 
 def collide_autograd(cmctx: Context, db: DeviceBatch, tau_t: torch.Tensor, K: int, xi=None, verts=None,
-                     params=None, capacity=None, fused=False, flags: int = 0, presel=None):
+                     params=None, capacity=None, fused=False, flags: int = 0, presel=None, refine: int = 0):
     """Manifold outputs (point, normal, dist, weight, n_pairs, pairs) that
     autograd can differentiate.  ``xi`` [6, n_bodies] must be zeros (the
     twist at which the gradient is taken); ``verts`` [3, vertex_pool] and
     ``params`` [4, n_geometries] are placeholders that receive geometry
-    gradients.  ``flags`` and ``presel`` select the simplifications and soft
-    top-K pre-selection for both passes."""
+    gradients.  ``flags``, ``presel`` and ``refine`` select the
+    simplifications, soft top-K pre-selection and witness sphere tracing for
+    both passes."""
     dev = cmctx.device
     if xi is None:
         xi = torch.zeros(6, db.n_bodies, device=dev, requires_grad=True)
@@ -356,7 +358,7 @@ def collide_autograd(cmctx: Context, db: DeviceBatch, tau_t: torch.Tensor, K: in
     if params is None:
         params = torch.zeros(4, max(cmctx.geometry_count, 1), device=dev, requires_grad=True)
     cap = db.n_cand_total if capacity is None else capacity
-    return _CollideFn.apply(xi, verts, params, tau_t, cmctx, db, K, cap, fused, flags, presel)
+    return _CollideFn.apply(xi, verts, params, tau_t, cmctx, db, K, cap, fused, flags, presel, refine)
 
 
 class Server:

@@ -348,6 +348,67 @@ __device__ __forceinline__ D3 sdf_body_bwd(const BodyView& V, const D3& x, doubl
   return xb;
 }
 
+// ---- witness sphere tracing (Supp., refinement of the witness points)
+// Forward: (phi_0, g) = the full query at the QP witness w, n = g / |g|,
+// x_0 = w, x_{s+1} = x_s - phi(x_s) n for s < steps (phi(x_0) = phi_0).  The
+// step values phi_s are kept for the reverse; x_s is rebuilt from them.
+struct Trace {
+  D3 w, n;                    // start point, unit direction (0 on lanes that do not trace)
+  double ig;                  // 1 / |grad phi(w)|
+  double ph[CM_MAX_REFINE];   // phi(x_s)
+};
+
+__device__ __forceinline__ void trace_none(const D3& x, Trace& tr) {
+  tr.w = x;
+  tr.n = d3(0.0, 0.0, 0.0);
+  tr.ig = 0.0;
+  for (int s = 0; s < CM_MAX_REFINE; ++s) tr.ph[s] = 0.0;
+}
+
+// The same operations, in the same order, as the forward's tracing; returns x_steps.
+template <bool IDENT, bool SQ>
+__device__ __forceinline__ D3 trace_fwd(const BodyView& V, const D3& w, const Temp& T, int steps, Trace& tr) {
+  double ph;
+  D3 g, dg;
+  sdf_body<kFull, IDENT, false, SQ>(V, w, T, ph, g);
+  const double in = rcp64(sqrt(dot(g, g)));
+  tr.w = w;
+  tr.ig = in;
+  tr.n = d3(g.x * in, g.y * in, g.z * in);
+  for (int s = 0; s < CM_MAX_REFINE; ++s) tr.ph[s] = 0.0;
+  D3 x = w;
+  for (int s = 0; s < steps; ++s) {
+    if (s > 0) sdf_body<kValue, IDENT, false, SQ>(V, x, T, ph, dg);
+    tr.ph[s] = ph;
+    x = d3(x.x - ph * tr.n.x, x.y - ph * tr.n.y, x.z - ph * tr.n.z);
+  }
+  return x;
+}
+
+// Reverse of trace_fwd: given the adjoint xb of x_steps returns that of w.
+// x_{s+1} = x_s - phi_s n gives x_s_bar += grad phi(x_s) (-n . x_{s+1}_bar)
+// and n_bar -= phi_s x_{s+1}_bar; at s = 0 the query at w also carries the
+// direction's gradient adjoint (n_bar - n (n . n_bar)) / |g|.  Every lane of
+// the wave calls this together (wave-summed plane adjoints); a lane that does
+// not trace passes xb = 0 and trace_none's record.
+template <bool IDENT, bool SQ>
+__device__ __forceinline__ D3 trace_bwd(const BodyView& V, const Trace& tr, D3 xb, const Temp& T, int steps,
+                                        const BodySink& sink, double& taub, Twist& tw) {
+  const D3 zero = d3(0.0, 0.0, 0.0);
+  double c = 0.0;
+  for (int s = 0; s < steps; ++s) c += tr.ph[s];
+  D3 nb = zero;
+  for (int s = steps - 1; s >= 1; --s) {
+    c -= tr.ph[s];   // x_s = w - (phi_0 + ... + phi_{s-1}) n
+    const D3 x = d3(tr.w.x - c * tr.n.x, tr.w.y - c * tr.n.y, tr.w.z - c * tr.n.z);
+    nb = axpy(-tr.ph[s], xb, nb);
+    xb = add(xb, sdf_body_bwd<true, IDENT, SQ>(V, x, -dot(tr.n, xb), zero, T, sink, taub, tw));
+  }
+  nb = axpy(-tr.ph[0], xb, nb);
+  const D3 gb = scl(sub(nb, scl(tr.n, dot(tr.n, nb))), tr.ig);
+  return add(xb, sdf_body_bwd<true, IDENT, SQ>(V, tr.w, -dot(tr.n, xb), gb, T, sink, taub, tw));
+}
+
 // Adjoint of the smoothed E-E QP (recomputes the forward).  Given adjoints of
 // (al1, al2, log_con) accumulates adjoints of the edge data a0, t1, b0, t2 and tau.
 __device__ __forceinline__ void ee_qp_bwd(const D3& a0, const D3& t1, const D3& b0, const D3& t2, double lam,

@@ -621,9 +621,8 @@ extern "C" cm_status cm_collide_backward(cm_context* ctx, const cm_batch* batch,
   if ((s = resolve_batch(ctx, batch, &bd)) != CM_OK) return s;
   if ((s = resolve_out(ctx, fwd, &od)) != CM_OK) return s;
   if (!cot || !out) return cm_fail(ctx, CM_ERR_INVALID_ARG, "null cotangent or gradient struct");
-  if (pd.presel_v > 0 && (ctx->maxV > 4096 || ctx->maxE > 4096))
-    return cm_fail(ctx, CM_ERR_INVALID_ARG, "pre-selection needs at most 4096 vertices and edges per body");
-  if (pd.refine > 0) return cm_fail(ctx, CM_ERR_INVALID_ARG, "the adjoint does not support witness sphere tracing");
+  if ((pd.presel_v > 0 || pd.refine > 0) && (ctx->maxV > 4096 || ctx->maxE > 4096))
+    return cm_fail(ctx, CM_ERR_INVALID_ARG, "the pre-selection and sphere-tracing adjoints need at most 4096 vertices and edges per body");
   hipSetDevice(ctx->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
   if ((s = ctx_order(ctx, st)) != CM_OK) return s;

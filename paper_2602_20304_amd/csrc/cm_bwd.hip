@@ -78,7 +78,7 @@ struct BwdArgs {
   GradDev gr;
 };
 
-template <int BLOCK, int KMAX, bool PRESEL, bool SQ>
+template <int BLOCK, int KMAX, bool PRESEL, bool SQ, bool REFINE = false>
 __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, ParamsDev prm, OutDev fwd, BwdArgs ga,
                                                      float* __restrict__ scratch, long long scratch_stride, int maxV,
                                                      int maxE, int maxF, unsigned* err) {
@@ -86,8 +86,8 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
   char* smem = reinterpret_cast<char*>(smem4);
   __shared__ PairShared ps;
   const int extra = bwd_extra_bytes(maxV, maxE, maxF, BLOCK, PRESEL);
-  PairEngine<BLOCK, KMAX, true, PRESEL, SQ> P(ps, smem, tb, bt, prm, scratch + (long long)blockIdx.x * scratch_stride, maxV,
-                                          maxE, maxF, extra);
+  PairEngine<BLOCK, KMAX, true, PRESEL, SQ, REFINE> P(ps, smem, tb, bt, prm, scratch + (long long)blockIdx.x * scratch_stride,
+                                                  maxV, maxE, maxF, extra);
   // the engine's pre-selection arrays sit right after its own layout
   const BwdLds L = bwd_layout(lds_layout(maxE, maxF, BLOCK, extra).bytes + (PRESEL ? presel_lds_bytes(maxV, maxE) : 0),
                               maxV, maxE, maxF, BLOCK, PRESEL);
@@ -152,6 +152,7 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
     P.cull();
     // candidate-space counts (the selection sizes under pre-selection)
     const int nvA = A.nv, neB = B.ne;
+    const int steps = REFINE ? min(max(P.refine, 1), CM_MAX_REFINE) : 0;   // sphere-tracing steps
     double tk[KMAX];
     P.scores(tk);
     P.topk(tk);
@@ -298,6 +299,10 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
       D3 a0, t1, b0, t2, de, pb = d3(fb[0], fb[1], fb[2]), nbb = d3(0, 0, 0);
       double al1 = 0, al2 = 0, dbar = 0, rho = 0, dbarb = 0, lcb = 0;
       int k = 0, l = 0, wit = 0;
+      // REFINE: both witnesses' traces, the QP distance vector and its adjoint
+      Trace trA, trB;
+      D3 dqe = d3(0, 0, 0);
+      double dqp = 0, dqpb = 0;
       if (is_vs) {
         const bool ofA = idx < nvA;
         const D3 x = PRESEL ? P.soft_vertex(idx)
@@ -323,6 +328,7 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
         const int s = ofA ? 1 : 0;
         phib[s] = phb;
         gbar[s] = gb;
+        if (REFINE) { trace_none(x, trA); trace_none(x, trB); }
       } else {
         const int e = idx - ps.nvs;
         const int ee_i = e >> 1;
@@ -332,16 +338,24 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
         P.EB.get(l, b0, t2);
         const EEQP q = ee_qp(a0, t1, b0, t2, P.lam, T);
         al1 = q.al1; al2 = q.al2; de = q.de;
-        const D3 e1 = axpy(al1, t1, a0), e2 = axpy(al2, t2, b0);
+        D3 e1 = axpy(al1, t1, a0), e2 = axpy(al2, t2, b0);
+        if (REFINE) {   // each witness traced onto its own body
+          dqe = q.de;
+          dqp = sqrt(dot(q.de, q.de));
+          e1 = trace_fwd<true, SQ>(A, e1, T, steps, trA);
+          e2 = trace_fwd<false, SQ>(B, e2, T, steps, trB);
+          de = sub(e1, e2);
+        }
         const double dsq = dot(de, de);
         dbar = sqrt(dsq);
+        const double dnn = REFINE ? dqp : dbar;   // the nearest-neighbour term's distance
         rho = 1.0 / sqrt(dsq + P.eps_n);
         const D3 nb = scl(de, rho);
         double phiB1, phiA2, dum, phiA1 = 0.0, phiB2 = 0.0;
         D3 gA, gB, dg;
         sdf_body<kValue, false, false, SQ>(B, e1, T, phiB1, dg);
         sdf_body<kValue, true, false, SQ>(A, e2, T, phiA2, dg);
-        if (PRESEL) {   // soft edges need not lie on their own bodies: full queries
+        if (PRESEL || REFINE) {   // soft edges / traced points need not lie on the edges: full queries
           sdf_body<kFull, true, false, SQ>(A, e1, T, phiA1, gA);
           sdf_body<kFull, false, false, SQ>(B, e2, T, phiB2, gB);
         } else {
@@ -355,7 +369,7 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
         const double lp = wit ? lsig(-phiA2, T) : lsig(-phiB1, T);
         const double lse = wit ? P.sCol[l] : P.sRow[k];
         const double lsg = safeguard ? lsig(-phiA1, T) + lsig(-phiB2, T) : 0.0;
-        const double lw = q.log_con + lcl + lp + lsg + (lse - dbar) * T.inv_tau;
+        const double lw = q.log_con + lcl + lp + lsg + (lse - dnn) * T.inv_tau;
         const double w = exp(lw);
         const double dtot = fb[6] - sb, lwb = T.tau * sb + w * fb[7];
         taub += sb * lw;
@@ -381,8 +395,8 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
           taub += lwb * dt;
         }
         if (live) atomicAdd(wit ? &cbar[l] : &rbar[k], float(lwb * T.inv_tau));
-        dbarb -= lwb * T.inv_tau;
-        taub -= lwb * (lse - dbar) * T.inv_tau * T.inv_tau;
+        (REFINE ? dqpb : dbarb) -= lwb * T.inv_tau;
+        taub -= lwb * (lse - dnn) * T.inv_tau * T.inv_tau;
         if (!wit) {
           const double ub = gamb * (1.0 - gam1 * gam1) * T.inv_tau;
           taub -= ub * u1 * T.inv_tau;
@@ -411,6 +425,29 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
       const D3 xb1 = used(phib[1], gbar[1]) ? sdf_body_bwd<true, false, SQ>(B, X[1], phib[1], gbar[1], T, sinkB, taub, tw, is_vs) : zero;
       const D3 xb2 = used(phib[2], gbar[2]) ? sdf_body_bwd<true, true, SQ>(A, X[2], phib[2], gbar[2], T, sinkA, taub, tw) : zero;
       const D3 xb3 = used(phib[3], gbar[3]) ? sdf_body_bwd<true, false, SQ>(B, X[3], phib[3], gbar[3], T, sinkB, taub, tw) : zero;
+      // E-E: adjoints of the two witness points (zero on idle lanes, whose
+      // seeds are all zero)
+      D3 e1b = zero, e2b = zero;
+      if (!is_vs) {
+        const double dn = dot(de, nbb);
+        D3 deb = sub(scl(nbb, rho), scl(de, rho * rho * rho * dn));
+        if (prm.eps_tied && live) taub += -0.5 * rho * rho * rho * dn * 2.0 * T.tau;
+        if (dbar > 0.0) deb = axpy(dbarb / dbar, de, deb);
+        e1b = add(add(xb0, xb1), deb);
+        e2b = sub(add(xb2, xb3), deb);
+        if (!wit) e1b = add(e1b, pb); else e2b = add(e2b, pb);
+      }
+      // ---- stage 2b (REFINE): back through both traces to the QP witnesses,
+      // every lane of the wave together (V-S and idle lanes carry zero)
+      if (REFINE && __ballot(!is_vs) != 0ull) {
+        e1b = trace_bwd<true, SQ>(A, trA, e1b, T, steps, sinkA, taub, tw);
+        e2b = trace_bwd<false, SQ>(B, trB, e2b, T, steps, sinkB, taub, tw);
+        if (dqp > 0.0) {   // the nearest-neighbour term's QP distance
+          const D3 dq = scl(dqe, dqpb / dqp);
+          e1b = add(e1b, dq);
+          e2b = sub(e2b, dq);
+        }
+      }
       if (!live) return;
       // ---- stage 3: back to vertices / edges
       if (is_vs) {
@@ -427,12 +464,7 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
           atomicAdd(&V[2 * maxV + i], float(xb.z));
         }
       } else {
-        const double dn = dot(de, nbb);
-        D3 deb = sub(scl(nbb, rho), scl(de, rho * rho * rho * dn));
-        if (prm.eps_tied) taub += -0.5 * rho * rho * rho * dn * 2.0 * T.tau;
-        if (dbar > 0.0) deb = axpy(dbarb / dbar, de, deb);
-        D3 e1b = add(add(xb0, xb1), deb), e2b = sub(add(xb2, xb3), deb);
-        if (!wit) e1b = add(e1b, pb); else e2b = add(e2b, pb);
+        // e1b / e2b: adjoints of the QP witnesses a0 + al1 t1, b0 + al2 t2
         D3 a0b = e1b, t1b = scl(e1b, al1), b0b = e2b, t2b = scl(e2b, al2);
         ee_qp_bwd(a0, t1, b0, t2, P.lam, T, dot(e1b, t1), dot(e2b, t2), lcb, a0b, t1b, b0b, t2b, taub);
         edge_adj(k, l, sub(a0b, t1b), t1b, sub(b0b, t2b), t2b);
@@ -738,20 +770,20 @@ int bwd_lds_bytes(int maxV, int maxE, int maxF, int block, bool presel) {
   return bwd_layout(lds_layout(maxE, maxF, block, extra).bytes + pre, maxV, maxE, maxF, block, presel).bytes;
 }
 
-template <int BLOCK, int KMAX, bool PRESEL, bool SQ>
+template <int BLOCK, int KMAX, bool PRESEL, bool SQ, bool REFINE = false>
 static hipError_t launch_bwd_t(const BwdLaunch& b, hipStream_t st) {
   const int lds = bwd_lds_bytes(b.f.maxV, b.f.maxE, b.f.maxF, BLOCK, PRESEL);
   BwdArgs ga{b.cot, b.gr};
-  hipLaunchKernelGGL((collide_bwd<BLOCK, KMAX, PRESEL, SQ>), dim3(b.f.grid), dim3(BLOCK), lds, st, b.f.tb, b.f.bt,
+  hipLaunchKernelGGL((collide_bwd<BLOCK, KMAX, PRESEL, SQ, REFINE>), dim3(b.f.grid), dim3(BLOCK), lds, st, b.f.tb, b.f.bt,
                      b.f.prm, b.f.out, ga, b.f.scratch, b.f.scratch_stride, b.f.maxV, b.f.maxE, b.f.maxF, b.f.err);
   return hipGetLastError();
 }
 
-template <int BLOCK, int KMAX, bool PRESEL, bool SQ>
+template <int BLOCK, int KMAX, bool PRESEL, bool SQ, bool REFINE = false>
 static int bwd_occ_t(const BwdLaunch& b) {
   int nb = 0;
   const int lds = bwd_lds_bytes(b.f.maxV, b.f.maxE, b.f.maxF, BLOCK, PRESEL);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, collide_bwd<BLOCK, KMAX, PRESEL, SQ>, BLOCK, lds) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, collide_bwd<BLOCK, KMAX, PRESEL, SQ, REFINE>, BLOCK, lds) != hipSuccess)
     return 1;
   return nb > 0 ? nb : 1;
 }
@@ -770,18 +802,40 @@ static int bwd_occ_k(const BwdLaunch& b) {
   return bwd_occ_t<256, 32, PRESEL, SQ>(b);
 }
 
+// Sphere-traced witnesses (K <= 16, as in the forward).
+template <bool PRESEL, bool SQ>
+static hipError_t launch_bwd_refine(const BwdLaunch& b, hipStream_t st) {
+  if (b.f.kmax == 8) return launch_bwd_t<256, 8, PRESEL, SQ, true>(b, st);
+  return launch_bwd_t<256, 16, PRESEL, SQ, true>(b, st);
+}
+
+template <bool PRESEL, bool SQ>
+static int bwd_occ_refine(const BwdLaunch& b) {
+  if (b.f.kmax == 8) return bwd_occ_t<256, 8, PRESEL, SQ, true>(b);
+  return bwd_occ_t<256, 16, PRESEL, SQ, true>(b);
+}
+
 // Pre-selection and contexts that hold superquadric unions run in their own
 // instantiations (the selection tracks taken items in a 64-bit mask per
 // lane: <= 4096 per set).
 hipError_t launch_collide_bwd(const BwdLaunch& b, hipStream_t st) {
   const bool ps = b.f.prm.presel_v > 0, sq = b.f.prm.sq != 0;
-  if ((ps || sq) && (b.f.maxV > 4096 || b.f.maxE > 4096)) return hipErrorInvalidValue;
+  if ((ps || sq || b.f.prm.refine > 0) && (b.f.maxV > 4096 || b.f.maxE > 4096)) return hipErrorInvalidValue;
+  if (b.f.prm.refine > 0) {
+    if (b.f.kmax > 16) return hipErrorInvalidValue;
+    if (sq) return ps ? launch_bwd_refine<true, true>(b, st) : launch_bwd_refine<false, true>(b, st);
+    return ps ? launch_bwd_refine<true, false>(b, st) : launch_bwd_refine<false, false>(b, st);
+  }
   if (sq) return ps ? launch_bwd_k<true, true>(b, st) : launch_bwd_k<false, true>(b, st);
   return ps ? launch_bwd_k<true, false>(b, st) : launch_bwd_k<false, false>(b, st);
 }
 
 int bwd_occupancy(const BwdLaunch& b) {
   const bool ps = b.f.prm.presel_v > 0, sq = b.f.prm.sq != 0;
+  if (b.f.prm.refine > 0) {
+    if (sq) return ps ? bwd_occ_refine<true, true>(b) : bwd_occ_refine<false, true>(b);
+    return ps ? bwd_occ_refine<true, false>(b) : bwd_occ_refine<false, false>(b);
+  }
   if (sq) return ps ? bwd_occ_k<true, true>(b) : bwd_occ_k<false, true>(b);
   return ps ? bwd_occ_k<true, false>(b) : bwd_occ_k<false, false>(b);
 }

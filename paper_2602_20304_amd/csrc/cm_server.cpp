@@ -414,8 +414,8 @@ cm_status cm_server_submit(cm_server* srv, const cm_request* q, uint64_t* ticket
   if ((q->params.flags & CM_FLAG_SAFEGUARD) && !presel)
     return srv_fail(CM_ERR_INVALID_ARG, "CM_FLAG_SAFEGUARD needs pre-selection");
   if (q->params.refine_steps < 0 || q->params.refine_steps > CM_MAX_REFINE ||
-      (q->params.refine_steps > 0 && (q->want_backward || q->params.K > 16)))
-    return srv_fail(CM_ERR_INVALID_ARG, "refine_steps outside 0..8, or with a backward pass or K > 16");
+      (q->params.refine_steps > 0 && q->params.K > 16))
+    return srv_fail(CM_ERR_INVALID_ARG, "refine_steps outside 0..8, or with K > 16");
   auto r = std::make_unique<Request>();
   r->n_scenes = q->n_scenes;
   r->n_bodies = q->n_bodies;

@@ -27,11 +27,12 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def gpu_grads(ctx, batch, seed=0, flags=0, presel=None):
-    _say(f"[gpu-bwd] {batch.name} scenes={batch.n_scenes} tau={batch.tau} K={batch.K} flags={flags} presel={presel}")
+def gpu_grads(ctx, batch, seed=0, flags=0, presel=None, refine=0):
+    _say(f"[gpu-bwd] {batch.name} scenes={batch.n_scenes} tau={batch.tau} K={batch.K} flags={flags} presel={presel} "
+         f"refine={refine}")
     ids = ctx.create_geometry(batch.geoms)
     db = ctx.upload_batch(batch, ids)
-    m = ctx.collide(db, batch.tau, batch.K, flags=flags, presel=presel)
+    m = ctx.collide(db, batch.tau, batch.K, flags=flags, presel=presel, refine=refine)
     ctx.check_errors()
     n = int(m.n_pairs.item())
     K = batch.K
@@ -40,13 +41,14 @@ def gpu_grads(ctx, batch, seed=0, flags=0, presel=None):
     cot = {k: rng.standard_normal(s).astype(np.float32) for k, s in
            (("p", (3, cap * K)), ("nu", (3, cap * K)), ("d", (cap * K,)), ("w", (cap * K,)))}
     tt = {k: torch.as_tensor(v).to(ctx.device) for k, v in cot.items()}
-    g = ctx.collide_backward(db, m, batch.tau, K, tt["p"], tt["nu"], tt["d"], tt["w"], flags=flags, presel=presel)
+    g = ctx.collide_backward(db, m, batch.tau, K, tt["p"], tt["nu"], tt["d"], tt["w"], flags=flags, presel=presel,
+                             refine=refine)
     ctx.check_errors()
     out = {k: (v.cpu().numpy() if v is not None else None) for k, v in g.items()}
     return ids, m.to_numpy(), cot, out, n
 
 
-def oracle_grads(batch, pairs, cot, K, flags=0, presel=None):
+def oracle_grads(batch, pairs, cot, K, flags=0, presel=None, refine=0):
     cache = O.GeomCache(batch.geoms, requires_grad=True)
     nb = batch.n_bodies
     g_pose = np.zeros((6, nb))
@@ -58,7 +60,7 @@ def oracle_grads(batch, pairs, cot, K, flags=0, presel=None):
         sl = slice(i * K, (i + 1) * K)
         c = dict(p=cot["p"][:, sl].T, nu=cot["nu"][:, sl].T, d=cot["d"][sl], w=cot["w"][sl])
         r = O.pair_grad(GA, batch.pose[:, a], GB, batch.pose[:, b], batch.tau, K, c, no_ee=bool(flags & 1),
-                        one_sided_vs=bool(flags & 2), presel=presel, safeguard=bool(flags & 4))
+                        one_sided_vs=bool(flags & 2), presel=presel, safeguard=bool(flags & 4), refine=refine)
         g_pose[:, a] += r["xiA"]
         g_pose[:, b] += r["xiB"]
         ga, gb = int(batch.body_geom[a]), int(batch.body_geom[b])
@@ -77,10 +79,10 @@ def close(got, ref, rtol=GRAD_RTOL):
     return float(err.max()) if err.size else -1.0, float(np.max(np.abs(got - ref))) if err.size else 0.0, scale
 
 
-def check(ctx, batch, seed=0, flags=0, presel=None):
-    ids, fwd, cot, g, n = gpu_grads(ctx, batch, seed, flags, presel)
+def check(ctx, batch, seed=0, flags=0, presel=None, refine=0):
+    ids, fwd, cot, g, n = gpu_grads(ctx, batch, seed, flags, presel, refine)
     pairs = fwd["pairs"]
-    g_pose, g_geom, g_tau, cache = oracle_grads(batch, pairs, cot, batch.K, flags, presel)
+    g_pose, g_geom, g_tau, cache = oracle_grads(batch, pairs, cot, batch.K, flags, presel, refine)
     rep = {}
     rep["pose"] = close(g["pose"], g_pose)
     vx, vr, pr_g, pr_r = [], [], [], []
