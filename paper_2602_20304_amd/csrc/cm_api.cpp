@@ -426,7 +426,7 @@ cm_status ctx_prepare_fwd(cm_context* ctx, const BatchDev& bd, const ParamsDev& 
     return cm_fail(ctx, CM_ERR_INVALID_ARG, "the context's largest geometry needs " + std::to_string(lds) +
                                                 " B of LDS for this forward (160 KiB per workgroup)");
   f->err = ctx->d_err;
-  const int occ = fwd_occupancy(*f);
+  const int occ = fwd_place_edges(*f);
   f->queue = nullptr;
   f->grid = std::max(1, occ * ctx->num_cus);
   if (od.capacity > 0 && f->grid > od.capacity && !dynamic) f->grid = std::max(1, od.capacity);
@@ -507,7 +507,7 @@ extern "C" cm_status cm_collide_noalloc(cm_context* ctx, const cm_batch* batch, 
                                                " B of scratch (largest geometry: " + std::to_string(ctx->maxE) +
                                                " edges), beyond the " + std::to_string(cap - tile_bytes) +
                                                " B left in the static workspace");
-    const int occ = fwd_occupancy(f);
+    const int occ = fwd_place_edges(f);
     f.grid = int(std::min<size_t>(size_t(std::max(1, occ * ctx->num_cus)), slots));
     f.grid = std::max(1, std::min(f.grid, od.capacity));
   }

@@ -62,7 +62,7 @@ FwdLaunch class_launch(cm_context* ctx, const BatchDev& bd, const ParamsDev& pd,
   f.range = w.ranges + 2 * c;
   f.queue = w.queues + c;
   f.err = ctx->d_err;
-  f.grid = std::max(1, fwd_occupancy(f) * ctx->num_cus);
+  f.grid = std::max(1, fwd_place_edges(f) * ctx->num_cus);
   f.scratch_stride = fwd_scratch_floats(f.maxV, f.maxE);
   return f;
 }

@@ -153,12 +153,12 @@ void collide_fwd(Tables tb, BatchDev bt, ParamsDev prm, OutDev out,
                                                      float* __restrict__ scratch, long long scratch_stride, int maxV,
                                                      int maxE, int maxF, const int* __restrict__ order,
                                                      const int* __restrict__ range, int* __restrict__ queue,
-                                                     unsigned* err) {
+                                                     unsigned* err, int edges_out) {
   extern __shared__ float4 smem4[];
   __shared__ PairShared ps;
   PairEngine<BLOCK, KMAX, true, PRESEL, SQ, REFINE> P(ps, reinterpret_cast<char*>(smem4), tb, bt, prm,
                                           scratch + (long long)blockIdx.x * scratch_stride, maxV, maxE, maxF,
-                                          PRESEL ? presel_lds_bytes(maxV, maxE) : 0);
+                                          PRESEL ? presel_lds_bytes(maxV, maxE) : 0, edges_out != 0);
   const int tid = threadIdx.x;
   const int K = prm.K;
   // items: all kept pairs, or the [start, start + count) slice of `order`
@@ -212,10 +212,10 @@ void collide_fwd(Tables tb, BatchDev bt, ParamsDev prm, OutDev out,
 
 // ============================================================ launchers
 
-int fwd_lds_bytes(int maxV, int maxE, int maxF, int block, int kmax, bool presel) {
+int fwd_lds_bytes(int maxV, int maxE, int maxF, int block, int kmax, bool presel, bool edges_out) {
   (void)kmax;
   const int extra = presel ? presel_lds_bytes(maxV, maxE) : 0;
-  return lds_layout(maxE, maxF, block, extra).bytes + extra;
+  return lds_layout(maxE, maxF, block, extra, edges_out).bytes + extra;
 }
 
 hipError_t launch_broadphase(const Tables& tb, const BatchDev& bt, float margin, const OutDev& out, int* tile_sums,
@@ -238,16 +238,16 @@ hipError_t launch_broadphase(const Tables& tb, const BatchDev& bt, float margin,
 template <int BLOCK, int KMAX, bool DYN, bool PRESEL = false, bool SQ = false, bool REFINE = false>
 static hipError_t launch_fwd_t(const FwdLaunch& f, hipStream_t st) {
   auto kern = collide_fwd<BLOCK, KMAX, DYN, PRESEL, SQ, REFINE>;
-  const int lds = fwd_lds_bytes(f.maxV, f.maxE, f.maxF, BLOCK, KMAX, PRESEL);
+  const int lds = fwd_lds_bytes(f.maxV, f.maxE, f.maxF, BLOCK, KMAX, PRESEL, f.edges_out != 0);
   hipLaunchKernelGGL(kern, dim3(f.grid), dim3(BLOCK), lds, st, f.tb, f.bt, f.prm, f.out, f.scratch,
-                     f.scratch_stride, f.maxV, f.maxE, f.maxF, f.order, f.range, f.queue, f.err);
+                     f.scratch_stride, f.maxV, f.maxE, f.maxF, f.order, f.range, f.queue, f.err, f.edges_out);
   return hipGetLastError();
 }
 
 template <int BLOCK, int KMAX, bool DYN, bool PRESEL = false, bool SQ = false, bool REFINE = false>
-static int occ_t(int maxV, int maxE, int maxF) {
+static int occ_t(int maxV, int maxE, int maxF, bool edges_out) {
   int nb = 0;
-  const int lds = fwd_lds_bytes(maxV, maxE, maxF, BLOCK, KMAX, PRESEL);
+  const int lds = fwd_lds_bytes(maxV, maxE, maxF, BLOCK, KMAX, PRESEL, edges_out);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, collide_fwd<BLOCK, KMAX, DYN, PRESEL, SQ, REFINE>, BLOCK, lds) != hipSuccess)
     return 1;
   return nb > 0 ? nb : 1;
@@ -276,8 +276,8 @@ static hipError_t launch_refine(const FwdLaunch& f, hipStream_t st) {
 }
 template <bool PRESEL, bool SQ>
 static int occ_refine(const FwdLaunch& f) {
-  if (f.kmax == 8) return occ_t<256, 8, false, PRESEL, SQ, true>(f.maxV, f.maxE, f.maxF);
-  return occ_t<256, 16, false, PRESEL, SQ, true>(f.maxV, f.maxE, f.maxF);
+  if (f.kmax == 8) return occ_t<256, 8, false, PRESEL, SQ, true>(f.maxV, f.maxE, f.maxF, f.edges_out != 0);
+  return occ_t<256, 16, false, PRESEL, SQ, true>(f.maxV, f.maxE, f.maxF, f.edges_out != 0);
 }
 
 // The extended primitives (superquadric unions, point clouds): block 256.
@@ -289,9 +289,9 @@ static hipError_t launch_sq_k(const FwdLaunch& f, hipStream_t st) {
 }
 template <bool DYN, bool PRESEL>
 static int occ_sq_k(const FwdLaunch& f) {
-  if (f.kmax == 8) return occ_t<256, 8, DYN, PRESEL, true>(f.maxV, f.maxE, f.maxF);
-  if (f.kmax == 16) return occ_t<256, 16, DYN, PRESEL, true>(f.maxV, f.maxE, f.maxF);
-  return occ_t<256, 32, DYN, PRESEL, true>(f.maxV, f.maxE, f.maxF);
+  if (f.kmax == 8) return occ_t<256, 8, DYN, PRESEL, true>(f.maxV, f.maxE, f.maxF, f.edges_out != 0);
+  if (f.kmax == 16) return occ_t<256, 16, DYN, PRESEL, true>(f.maxV, f.maxE, f.maxF, f.edges_out != 0);
+  return occ_t<256, 32, DYN, PRESEL, true>(f.maxV, f.maxE, f.maxF, f.edges_out != 0);
 }
 
 hipError_t launch_collide_fwd(const FwdLaunch& f, hipStream_t st) {
@@ -342,21 +342,30 @@ int fwd_occupancy(const FwdLaunch& f) {
   }
   if (f.prm.presel_v > 0) {
     if (f.queue) {
-      if (f.kmax == 8) return occ_t<256, 8, true, true>(f.maxV, f.maxE, f.maxF);
-      if (f.kmax == 16) return occ_t<256, 16, true, true>(f.maxV, f.maxE, f.maxF);
-      return occ_t<256, 32, true, true>(f.maxV, f.maxE, f.maxF);
+      if (f.kmax == 8) return occ_t<256, 8, true, true>(f.maxV, f.maxE, f.maxF, f.edges_out != 0);
+      if (f.kmax == 16) return occ_t<256, 16, true, true>(f.maxV, f.maxE, f.maxF, f.edges_out != 0);
+      return occ_t<256, 32, true, true>(f.maxV, f.maxE, f.maxF, f.edges_out != 0);
     }
-    if (f.kmax == 8) return occ_t<256, 8, false, true>(f.maxV, f.maxE, f.maxF);
-    if (f.kmax == 16) return occ_t<256, 16, false, true>(f.maxV, f.maxE, f.maxF);
-    return occ_t<256, 32, false, true>(f.maxV, f.maxE, f.maxF);
+    if (f.kmax == 8) return occ_t<256, 8, false, true>(f.maxV, f.maxE, f.maxF, f.edges_out != 0);
+    if (f.kmax == 16) return occ_t<256, 16, false, true>(f.maxV, f.maxE, f.maxF, f.edges_out != 0);
+    return occ_t<256, 32, false, true>(f.maxV, f.maxE, f.maxF, f.edges_out != 0);
   }
   if (f.queue) {
     constexpr bool DYNV = true;
-    CM_FWD_DISPATCH(occ_t, f.maxV, f.maxE, f.maxF)
+    CM_FWD_DISPATCH(occ_t, f.maxV, f.maxE, f.maxF, f.edges_out != 0)
   } else {
     constexpr bool DYNV = false;
-    CM_FWD_DISPATCH(occ_t, f.maxV, f.maxE, f.maxF)
+    CM_FWD_DISPATCH(occ_t, f.maxV, f.maxE, f.maxF, f.edges_out != 0)
   }
+}
+
+int fwd_place_edges(FwdLaunch& f) {
+  f.edges_out = 0;
+  const int in = fwd_occupancy(f);
+  f.edges_out = 1;
+  const int out = fwd_occupancy(f);
+  f.edges_out = out > in ? 1 : 0;
+  return out > in ? out : in;
 }
 
 }  // namespace cm

@@ -14,6 +14,7 @@ struct FwdLaunch {
   float* scratch;              // per-workgroup slots of scratch_stride floats
   long long scratch_stride;
   int maxV, maxE, maxF;        // LDS sizing (context-wide maxima)
+  int edges_out = 0;           // 1: the edge arrays live in the scratch slot (fwd_place_edges)
   const int* order;            // optional pair order (cost-sorted), or null
   const int* range;            // optional device int2 {start, count} into order, or null
   int* queue;                  // dynamic work-queue counter (zeroed), or null for static round robin
@@ -54,11 +55,15 @@ struct BwdLaunch {
   GradDev gr;
 };
 
-int fwd_lds_bytes(int maxV, int maxE, int maxF, int block, int kmax, bool presel = false);
+int fwd_lds_bytes(int maxV, int maxE, int maxF, int block, int kmax, bool presel = false, bool edges_out = false);
 int bwd_lds_bytes(int maxV, int maxE, int maxF, int block, bool presel = false);
 int bwd_occupancy(const BwdLaunch& b);
 hipError_t launch_collide_bwd(const BwdLaunch& b, hipStream_t st);
 int fwd_occupancy(const FwdLaunch& f);
+// Sets f.edges_out when keeping the edge arrays in the scratch slot lets more
+// workgroups share a CU than keeping them in LDS (LDS-limited launches);
+// returns the workgroups per CU of the chosen placement.
+int fwd_place_edges(FwdLaunch& f);
 hipError_t launch_broadphase(const Tables& tb, const BatchDev& bt, float margin, const OutDev& out, int* tile_sums,
                              unsigned* err, hipStream_t st);
 hipError_t launch_collide_fwd(const FwdLaunch& f, hipStream_t st);

@@ -52,6 +52,8 @@ struct LdsLayout {
 // Dynamic LDS a workgroup may use on gfx950 (160 KB per CU), leaving room for
 // the kernels' static shared variables.
 constexpr int kLdsBudget = 160 * 1024 - 1024;
+// Virtual threads of the column LSE's chunking (the same in every block size).
+constexpr int kColSlots = 256;
 
 // 64-bit words of a face mask (0: culling off): the fewest powers of two
 // covering maxF faces, up to kMaxMaskWords (512 faces); larger polytopes
@@ -63,9 +65,10 @@ __host__ __device__ inline int mask_words(int maxF) {
 }
 
 // extra: LDS bytes the calling kernel needs beyond the engine.  When the
-// whole does not fit kLdsBudget, both bodies' edge arrays (96 B per edge)
-// move to the scratch slot.
-__host__ __device__ inline LdsLayout lds_layout(int maxE, int maxF, int block, int extra = 0) {
+// whole does not fit kLdsBudget, or when edges_out is set (the launch found
+// that it fits more workgroups per CU that way), both bodies' edge arrays
+// (96 B per edge) live in the workgroup's scratch slot instead.
+__host__ __device__ inline LdsLayout lds_layout(int maxE, int maxF, int block, int extra = 0, bool edges_out = false) {
   LdsLayout L;
   int o = 0;
   const int edge_bytes = 2 * 6 * 8 * maxE;
@@ -76,10 +79,11 @@ __host__ __device__ inline LdsLayout lds_layout(int maxE, int maxF, int block, i
   const int group_bytes = mask_words(maxF) > 0 ? 2 * ((maxE + 7) / 8) * 2 * int(sizeof(FaceMask)) : 0;
   const int rec_bytes = int(sizeof(Rec)) * block;
   const int shared_bytes = ((rec_bytes > group_bytes ? rec_bytes : group_bytes) + 7) & ~7;
-  L.edges_lds = true;
-  {
+  const int red_n = block > kColSlots ? block : kColSlots;   // reduction slots: 2 x 8 B each
+  L.edges_lds = !edges_out;
+  if (L.edges_lds) {
     // size with the edges in LDS (same sequence as below)
-    int t = edge_bytes + 16 * maxE + 16 * block + 8 * 64 + shared_bytes + 8 * 9 * CM_MAX_K + 64 * maxF + 64;
+    int t = edge_bytes + 16 * maxE + 16 * red_n + 8 * 64 + shared_bytes + 8 * 9 * CM_MAX_K + 64 * maxF + 64;
     if (((t + 15) & ~15) + extra > kLdsBudget) L.edges_lds = false;
   }
   L.eA = L.eB = -1;
@@ -89,7 +93,7 @@ __host__ __device__ inline LdsLayout lds_layout(int maxE, int maxF, int block, i
   }
   L.row = o; o += 8 * maxE;
   L.col = o; o += 8 * maxE;
-  L.red = o; o += 2 * 8 * block;
+  L.red = o; o += 2 * 8 * red_n;
   L.top = o; o += 8 * 64;
   L.rec = o;
   L.g1 = o;                      // [group of A's edges][A's faces, B's faces]
@@ -157,9 +161,9 @@ struct PairEngine {
   const GeomRec* GB;
 
   __device__ __forceinline__ PairEngine(PairShared& ps_, char* smem, const Tables& tb_, const BatchDev& bt_, const ParamsDev& prm,
-                        float* slot, int maxV_, int maxE_, int maxF_, int lds_extra = 0)
+                        float* slot, int maxV_, int maxE_, int maxF_, int lds_extra = 0, bool edges_out = false)
       : ps(ps_), tb(tb_), bt(bt_) {
-    const LdsLayout L = lds_layout(maxE_, maxF_, BLOCK, lds_extra);
+    const LdsLayout L = lds_layout(maxE_, maxF_, BLOCK, lds_extra, edges_out);
     double* e = L.edges_lds ? reinterpret_cast<double*>(smem + L.eA)
                             : reinterpret_cast<double*>(slot + scratch_edges_offset(maxV_, maxE_));
     EA = EdgeSoA{e, e + maxE_, e + 2 * maxE_, e + 3 * maxE_, e + 4 * maxE_, e + 5 * maxE_};
@@ -579,35 +583,45 @@ struct PairEngine {
       wave_lse_merge(m, s, T);
       if (lane == 0) sRow[k] = m - T.tl * double(lg2f(s));
     }
-    // column LSE over k (threads over columns, k split in chunks, coalesced)
-    {
-      const int nch = neB >= BLOCK ? 1 : BLOCK / neB;
-      for (int lb = 0; lb < neB; lb += BLOCK) {
-        const int l = lb + (tid % (neB >= BLOCK ? BLOCK : neB));
-        const int ch = neB >= BLOCK ? 0 : tid / neB;
+    // column LSE over k (threads over columns, k split in chunks, coalesced).
+    // The chunking is that of kColSlots virtual threads whatever the block
+    // size (a thread takes slots tid, tid + BLOCK, ...), so the float32 sums
+    // associate alike in every instantiation: columns of width >= kColSlots
+    // run whole, narrower ones in kColSlots / neB chunks of rows merged in
+    // chunk order.
+    if (neB >= kColSlots) {
+      for (int l = tid; l < neB; l += BLOCK) {
         double m = INFINITY;
         float s = 0.f;
-        if (ch < nch && l < neB) {
+        for (int k = 0; k < neA; ++k) lse_push(m, s, Dbuf[k * neB + l], T);
+        sCol[l] = m - T.tl * double(lg2f(s));
+      }
+    } else {
+      const int nch = kColSlots / neB;
+      for (int v = tid; v < kColSlots; v += BLOCK) {
+        const int l = v % neB, ch = v / neB;
+        double m = INFINITY;
+        float s = 0.f;
+        if (ch < nch) {
           const int k0 = (ch * neA) / nch, k1 = ((ch + 1) * neA) / nch;
           for (int k = k0; k < k1; ++k) lse_push(m, s, Dbuf[k * neB + l], T);
         }
-        sRed[tid] = m;
-        sRed[BLOCK + tid] = double(s);
-        __syncthreads();
-        if (ch == 0 && l < neB) {
-          double M = sRed[tid];
-          float S = float(sRed[BLOCK + tid]);
-          for (int c = 1; c < nch; ++c) {
-            const double m2 = sRed[c * neB + tid];
-            const float s2 = float(sRed[BLOCK + c * neB + tid]);
-            const double Mn = fmin(M, m2);
-            const float a = (M == Mn) ? S : S * expn(M - Mn, T);
-            const float bb = (m2 == Mn) ? s2 : s2 * expn(m2 - Mn, T);
-            M = Mn; S = a + bb;
-          }
-          sCol[l] = M - T.tl * double(lg2f(S));
+        sRed[v] = m;
+        sRed[kColSlots + v] = double(s);
+      }
+      __syncthreads();
+      for (int l = tid; l < neB; l += BLOCK) {
+        double M = sRed[l];
+        float S = float(sRed[kColSlots + l]);
+        for (int c = 1; c < nch; ++c) {
+          const double m2 = sRed[c * neB + l];
+          const float s2 = float(sRed[kColSlots + c * neB + l]);
+          const double Mn = fmin(M, m2);
+          const float a = (M == Mn) ? S : S * expn(M - Mn, T);
+          const float bb = (m2 == Mn) ? s2 : s2 * expn(m2 - Mn, T);
+          M = Mn; S = a + bb;
         }
-        __syncthreads();
+        sCol[l] = M - T.tl * double(lg2f(S));
       }
     }
     __syncthreads();

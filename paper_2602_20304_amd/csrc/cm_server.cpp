@@ -221,7 +221,7 @@ void launch_request(cm_server* srv, Request& r) {
   f.block = 256; f.kmax = kmax_for(K); f.order = nullptr; f.range = nullptr; f.queue = nullptr;
   // grid already folded into the footprint: recompute the same value
   f.prm = pd;
-  const int occ = fwd_occupancy(f);
+  const int occ = fwd_place_edges(f);
   f.grid = int(request_grid(ctx, occ, cap));
   f.scratch_stride = fwd_scratch_floats(f.maxV, f.maxE);
   if (hipMallocAsync(&r.dev, size_t(r.footprint), st) != hipSuccess) { r.status = CM_ERR_OOM; return; }
@@ -462,7 +462,7 @@ cm_status cm_server_submit(cm_server* srv, const cm_request* q, uint64_t* ticket
   f.prm.presel_e = presel ? q->params.presel_edges : 0;
   f.prm.sq = ctx->has_sq ? 1 : 0;
   f.prm.refine = q->params.refine_steps;
-  const long long grid = request_grid(ctx, fwd_occupancy(f), cap);
+  const long long grid = request_grid(ctx, fwd_place_edges(f), cap);
   r->footprint = footprint(*r, grid, fwd_scratch_floats(f.maxV, f.maxE));
   r->host_bytes = host_bytes(*r);
   if (r->footprint > srv->budget)

@@ -271,3 +271,39 @@ def test_fused_autotune_sample_and_cache(tmp_path, monkeypatch):
         c.close()
     for k in ("pairs", "offsets", "p", "nu", "d", "w"):
         assert np.array_equal(outs[0][k], outs[1][k]), k
+
+
+def test_fused_any_block_size_matches_plain_bitwise(tmp_path, monkeypatch):
+    """Every reduction whose order could depend on the block size (the column
+    LSE's chunks) is chunked the same way in every instantiation, so the fused
+    path equals the plain kernel bit for bit whichever block size its classes
+    run (forced here through the tuner's cache file: 128 and 256 threads),
+    also on hulls of up to 256 points, whose edge arrays move out of LDS."""
+    from paper_2602_20304_amd.cm import Context
+    for name, b in (("mixed", W.mixed_scenes(64, seed=5)), ("uneven", W.uneven_scenes(40, seed=35, v_max=256))):
+        monkeypatch.setenv("CM_TUNE_CACHE", str(tmp_path / f"{name}_tuned.txt"))
+        c = Context(0)
+        ids = c.create_geometry(b.geoms)
+        db = c.upload_batch(b, ids)
+        plain = c.collide(db, b.tau, b.K).to_numpy()
+        c.collide(db, b.tau, b.K, fused=True)
+        c.check_errors()
+        c.close()
+        keys = [ln.split()[0] for ln in (tmp_path / f"{name}_tuned.txt").read_text().split("\n") if ln.strip()]
+        assert keys
+        for block in (128, 256):
+            path = tmp_path / f"{name}_{block}.txt"
+            path.write_text("".join(f"{k} {block}\n" for k in keys))
+            monkeypatch.setenv("CM_TUNE_CACHE", str(path))
+            _say(f"[gpu] fused at block {block} vs plain: {name}, {b.n_scenes} scenes")
+            c = Context(0)
+            ids = c.create_geometry(b.geoms)
+            db = c.upload_batch(b, ids)
+            fused = c.collide(db, b.tau, b.K, fused=True).to_numpy()
+            c.check_errors()
+            t = c.fused_tuning()
+            used = [i for i in range(3) if t["from_cache"][i]]
+            assert used and all(t["class_blocks"][i] == block for i in used), t
+            for k in ("pairs", "offsets", "p", "nu", "d", "w"):
+                assert np.array_equal(plain[k], fused[k]), (name, block, k)
+            c.close()
