@@ -317,7 +317,18 @@ cm_status cm_collide_noalloc(cm_context* ctx, const cm_batch* batch, const cm_pa
  * activity/score terms, the nearest-neighbour softmaxes, the SDF queries,
  * the witness QP and the rigid transforms (with refine_steps > 0 also the
  * sphere-tracing steps, above).  Broadphase decisions and hull topology are
- * held fixed. */
+ * held fixed.  It runs as two launches on `stream`: the forward kernel
+ * records, per kept pair, s_[k], the SoftSort row sums and the candidates
+ * within the adjoint's window (the adjoint's tape: a context workspace of
+ * capacity x (16 + 80 K) bytes plus a pool holding each pair's window as
+ * candidate indices or, when smaller, one bit per candidate), then the
+ * adjoint kernel recomputes only the distance pass and reverses the rest.
+ * The pool holds 2^28 four-byte entries (1 GiB) by default, fewer when the
+ * context's meshes cannot fill them; the environment variable
+ * CM_ADJOINT_TAPE sets that count, and 0 turns the tape off (the adjoint
+ * then recomputes the whole forward per pair, as it also does for pairs
+ * whose windows no longer fit).  Both ways give the same gradients up to
+ * the order of float32 atomic additions. */
 cm_status cm_collide_backward(cm_context* ctx, const cm_batch* batch, const cm_params* prm,
                               const cm_manifold* fwd, const cm_cotangent* cot, cm_grads* out, void* stream);
 

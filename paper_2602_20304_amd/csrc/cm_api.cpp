@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -611,6 +612,16 @@ extern "C" cm_status cm_kernel_time(cm_context* ctx, int32_t timer, double* tota
   return CM_OK;
 }
 
+// Entries of the adjoint tape's index pool (4 B each): CM_ADJOINT_TAPE
+// (0 turns the tape off: the adjoint recomputes the whole forward per pair),
+// default 2^28.
+static long long tape_pool_entries() {
+  const char* v = std::getenv("CM_ADJOINT_TAPE");
+  if (!v || !*v) return 1LL << 28;
+  const long long n = std::atoll(v);
+  return n <= 0 ? 0 : std::min(n, (1LL << 31) - 1);
+}
+
 extern "C" cm_status cm_collide_backward(cm_context* ctx, const cm_batch* batch, const cm_params* prm,
                                          const cm_manifold* fwd, const cm_cotangent* cot, cm_grads* out,
                                          void* stream) {
@@ -657,11 +668,39 @@ extern "C" cm_status cm_collide_backward(cm_context* ctx, const cm_batch* batch,
   b.f.grid = std::max(1, bwd_occupancy(b) * ctx->num_cus);
   if (b.f.grid > od.capacity) b.f.grid = std::max(1, od.capacity);
   b.f.scratch_stride = fwd_scratch_floats(b.f.maxV, b.f.maxE);
+  // The adjoint's tape: the forward kernel (at its own occupancy) records per
+  // kept pair s_[k], the SoftSort row sums and the candidates within the
+  // adjoint's window, so the adjoint kernel skips the forward's candidate
+  // pass; a pair whose list no longer fits the pool is recomputed whole.
+  // (no more entries than every kept pair's candidates could fill)
+  const long long most = (long long)od.capacity * (2LL * ctx->maxV + 2LL * ctx->maxE * ctx->maxE);
+  const long long pool_cap = std::min(tape_pool_entries(), std::max(most, 1LL));
+  FwdLaunch f1;
+  if (pool_cap > 0 && (s = ctx_prepare_fwd(ctx, bd, pd, od, 256, false, &f1)) != CM_OK) return s;
   const size_t need = size_t(b.f.grid) * size_t(b.f.scratch_stride) * sizeof(float);
   if ((e = ctx_ensure(ctx, reinterpret_cast<void**>(&ctx->d_scratch), &ctx->scratch_cap, need)) != hipSuccess)
     return cm_hip(ctx, e, "backward scratch");
   b.f.scratch = ctx->d_scratch;
+  if (pool_cap > 0) {
+    const size_t hdr = (size_t(od.capacity) * size_t(tape_stride(pd.K)) + 255) & ~size_t(255);
+    if ((e = ctx_ensure(ctx, &ctx->d_bwd, &ctx->bwd_cap, 256 + hdr + 4 * size_t(pool_cap))) != hipSuccess)
+      return cm_hip(ctx, e, "adjoint tape");
+    char* tb = static_cast<char*>(ctx->d_bwd);
+    TapeDev t;
+    t.pool_used = reinterpret_cast<unsigned long long*>(tb);
+    t.base = tb + 256;
+    t.pool = reinterpret_cast<int*>(tb + 256 + hdr);
+    t.pool_cap = pool_cap;
+    if ((e = hipMemsetAsync(t.pool_used, 0, sizeof(unsigned long long), st)) != hipSuccess)
+      return cm_hip(ctx, e, "zero the tape pool counter");
+    f1.scratch = ctx->d_scratch;   // the ensures above may have moved it
+    f1.tape = t;
+    f1.tape.skip_out = 1;
+    t.pool_used = nullptr;
+    b.f.tape = t;
+  }
   hipEvent_t t0 = timer_begin(ctx, st);
+  if (pool_cap > 0 && (s = cm_hip(ctx, launch_collide_fwd(f1, st), "adjoint tape launch")) != CM_OK) return s;
   if ((s = cm_hip(ctx, launch_collide_bwd(b, st), "backward launch")) != CM_OK) return s;
   timer_end(ctx, CM_TIMER_BACKWARD, t0, st);
   ctx_mark(ctx, st);

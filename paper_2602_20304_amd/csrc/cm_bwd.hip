@@ -81,7 +81,7 @@ struct BwdArgs {
 template <int BLOCK, int KMAX, bool PRESEL, bool SQ, bool REFINE = false>
 __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, ParamsDev prm, OutDev fwd, BwdArgs ga,
                                                      float* __restrict__ scratch, long long scratch_stride, int maxV,
-                                                     int maxE, int maxF, unsigned* err) {
+                                                     int maxE, int maxF, unsigned* err, TapeDev tape) {
   extern __shared__ float4 smem4[];
   char* smem = reinterpret_cast<char*>(smem4);
   __shared__ PairShared ps;
@@ -149,14 +149,46 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
     // ------------------------------------------------ recompute the forward
     P.stage();
     if (PRESEL) P.select(selI);
-    P.cull();
     // candidate-space counts (the selection sizes under pre-selection)
     const int nvA = A.nv, neB = B.ne;
     const int steps = REFINE ? min(max(P.refine, 1), CM_MAX_REFINE) : 0;   // sphere-tracing steps
-    double tk[KMAX];
-    P.scores(tk);
-    P.topk(tk);
-    P.softsort();
+    // The forward's tape for this pair, when recorded whole: s_[k], the
+    // SoftSort row sums and the candidates within the adjoint's window.  Then
+    // only the distance pass is recomputed (the candidates' records need the
+    // QP solutions and row / column LSE); otherwise the whole forward is.
+    int ntape = -1;
+    const int* tlist = nullptr;
+    const unsigned long long* tmask = nullptr;
+    const double* tdat = nullptr;
+    if (tape.base) {
+      const char* rec = tape.base + (long long)pi * tape_stride(K);
+      const int c = reinterpret_cast<const int*>(rec)[0], form = reinterpret_cast<const int*>(rec)[1];
+      const long long off = reinterpret_cast<const long long*>(rec)[1];
+      const long long mask_n = 2LL * ((ps.ncand + 63) >> 6);
+      if (c >= 0 && c <= ps.ncand && off >= 0) {
+        if (form == 1 && off + c <= tape.pool_cap) {
+          ntape = c;
+          tlist = tape.pool + off;
+        } else if (form == 2 && (off & 1) == 0 && off + mask_n <= tape.pool_cap) {
+          tmask = reinterpret_cast<const unsigned long long*>(tape.pool + off);
+        }
+      }
+      if (tlist || tmask) tdat = reinterpret_cast<const double*>(rec + 16);
+    }
+    if (tdat) {
+      P.pass1();
+      for (int i = tid; i < 10 * K; i += BLOCK) {
+        if (i < K) P.sTop[i] = tdat[i];
+        else P.sAcc[i - K] = tdat[i];
+      }
+      __syncthreads();
+    } else {
+      P.cull();
+      double tk[KMAX];
+      P.scores(tk);
+      P.topk(tk);
+      P.softsort();
+    }
 
     // ------------------------------------------------ cotangents in the pair frame
     if (tid < K) {
@@ -207,7 +239,7 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
       const bool act = sl < nsl;
       double sbp = 0.0, best = INFINITY;
       int bidx = 0x7fffffff;
-      P.for_filtered([&](int tot) {
+      P.for_window(tlist, ntape, tmask, [&](int tot) {
         if (!act) return;
         const double* F = Fk + 10 * kk;
         const double* c = cotL + 8 * kk;
@@ -268,7 +300,7 @@ __global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, Par
     };
 
     // ------------------------------------------------ A2: per-candidate adjoints
-    P.for_filtered([&](int tot) {
+    P.for_window(tlist, ntape, tmask, [&](int tot) {
       if (wave * 64 >= tot) return;        // whole wave idle (uniform)
       const bool live = tid < tot;
       const Rec R = P.sRec[live ? tid : 0];
@@ -775,7 +807,8 @@ static hipError_t launch_bwd_t(const BwdLaunch& b, hipStream_t st) {
   const int lds = bwd_lds_bytes(b.f.maxV, b.f.maxE, b.f.maxF, BLOCK, PRESEL);
   BwdArgs ga{b.cot, b.gr};
   hipLaunchKernelGGL((collide_bwd<BLOCK, KMAX, PRESEL, SQ, REFINE>), dim3(b.f.grid), dim3(BLOCK), lds, st, b.f.tb, b.f.bt,
-                     b.f.prm, b.f.out, ga, b.f.scratch, b.f.scratch_stride, b.f.maxV, b.f.maxE, b.f.maxF, b.f.err);
+                     b.f.prm, b.f.out, ga, b.f.scratch, b.f.scratch_stride, b.f.maxV, b.f.maxE, b.f.maxF, b.f.err,
+                     b.f.tape);
   return hipGetLastError();
 }
 

@@ -153,7 +153,7 @@ void collide_fwd(Tables tb, BatchDev bt, ParamsDev prm, OutDev out,
                                                      float* __restrict__ scratch, long long scratch_stride, int maxV,
                                                      int maxE, int maxF, const int* __restrict__ order,
                                                      const int* __restrict__ range, int* __restrict__ queue,
-                                                     unsigned* err, int edges_out) {
+                                                     unsigned* err, int edges_out, TapeDev tape) {
   extern __shared__ float4 smem4[];
   __shared__ PairShared ps;
   PairEngine<BLOCK, KMAX, true, PRESEL, SQ, REFINE> P(ps, reinterpret_cast<char*>(smem4), tb, bt, prm,
@@ -183,8 +183,36 @@ void collide_fwd(Tables tb, BatchDev bt, ParamsDev prm, OutDev out,
       P.scores(tk);
       P.topk(tk);
       P.softsort();
+      if (tape.base) {
+        // the adjoint's tape: s_[k], the row sums, the candidates within its window
+        char* rec = tape.base + (long long)pi * tape_stride(K);
+        double* td = reinterpret_cast<double*>(rec + 16);
+        for (int i = tid; i < 10 * K; i += BLOCK) td[i] = i < K ? P.sTop[i] : P.sAcc[i - K];
+        const int tot = P.window(kAdjointTaus);
+        // the smaller form: indices (tot entries) or a mask (2 entries per 64 candidates)
+        const long long mask_n = 2LL * ((P.ps.ncand + 63) >> 6);
+        const bool as_mask = mask_n < (long long)tot;
+        const long long need = as_mask ? mask_n : (long long)tot;
+        if (tid == 0) {
+          // a mask starts on an 8-byte boundary: one spare entry
+          const unsigned long long o = atomicAdd(tape.pool_used, (unsigned long long)(need + (as_mask ? 1 : 0)));
+          const unsigned long long start = as_mask ? (o + 1ull) & ~1ull : o;
+          const bool fits = start + (unsigned long long)need <= (unsigned long long)tape.pool_cap;
+          ps.tape_off = fits ? (long long)start : -1;
+          reinterpret_cast<int*>(rec)[0] = tot;
+          reinterpret_cast<int*>(rec)[1] = fits ? (as_mask ? 2 : 1) : 0;
+          reinterpret_cast<long long*>(rec)[1] = fits ? (long long)start : 0;
+        }
+        __syncthreads();
+        const long long start = ps.tape_off;
+        if (start >= 0) {
+          if (as_mask) P.window_mask(kAdjointTaus, reinterpret_cast<unsigned long long*>(tape.pool + start));
+          else
+            for (int p = tid; p < tot; p += BLOCK) tape.pool[start + p] = P.list_at(p);
+        }
+      }
       // outputs: divide by row sums, rotate to world
-      for (int kk = tid; kk < K; kk += BLOCK) {
+      for (int kk = tid; !tape.skip_out && kk < K; kk += BLOCK) {
         const double* a = P.sAcc + 9 * kk;
         // a row with no candidate (fewer candidates than K) is all zeros
         const bool live = a[0] > 0.0;
@@ -240,7 +268,8 @@ static hipError_t launch_fwd_t(const FwdLaunch& f, hipStream_t st) {
   auto kern = collide_fwd<BLOCK, KMAX, DYN, PRESEL, SQ, REFINE>;
   const int lds = fwd_lds_bytes(f.maxV, f.maxE, f.maxF, BLOCK, KMAX, PRESEL, f.edges_out != 0);
   hipLaunchKernelGGL(kern, dim3(f.grid), dim3(BLOCK), lds, st, f.tb, f.bt, f.prm, f.out, f.scratch,
-                     f.scratch_stride, f.maxV, f.maxE, f.maxF, f.order, f.range, f.queue, f.err, f.edges_out);
+                     f.scratch_stride, f.maxV, f.maxE, f.maxF, f.order, f.range, f.queue, f.err, f.edges_out,
+                     f.tape);
   return hipGetLastError();
 }
 

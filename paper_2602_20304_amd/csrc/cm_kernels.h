@@ -6,6 +6,23 @@
 
 namespace cm {
 
+// Per-pair record the forward kernel leaves for the adjoint (the adjoint's
+// tape), tape_stride(K) bytes per kept pair: int32 count of the candidates
+// within the adjoint's window, int32 form (0: none recorded, the pool was
+// full; 1: their indices, int32 ascending; 2: a mask of one bit per
+// candidate, 64-bit words), int64 offset of that list or mask in the pool
+// (4-byte entries), then the K top scores s_[k] and the K x 9 SoftSort row
+// sums (float64).  Each pair takes the smaller form, carved from the pool by
+// one atomic.
+struct TapeDev {
+  char* base = nullptr;     // null: no tape
+  int* pool = nullptr;      // window indices of every recorded pair
+  unsigned long long* pool_used = nullptr;   // entries carved so far (zeroed before the forward)
+  long long pool_cap = 0;   // entries the pool holds
+  int skip_out = 0;         // 1: the forward kernel writes the tape only, no manifold outputs
+};
+__host__ __device__ inline long long tape_stride(int K) { return 16LL + 80LL * K; }
+
 struct FwdLaunch {
   Tables tb;
   BatchDev bt;
@@ -15,6 +32,7 @@ struct FwdLaunch {
   long long scratch_stride;
   int maxV, maxE, maxF;        // LDS sizing (context-wide maxima)
   int edges_out = 0;           // 1: the edge arrays live in the scratch slot (fwd_place_edges)
+  TapeDev tape;                // optional adjoint tape written by the forward kernel
   const int* order;            // optional pair order (cost-sorted), or null
   const int* range;            // optional device int2 {start, count} into order, or null
   int* queue;                  // dynamic work-queue counter (zeroed), or null for static round robin

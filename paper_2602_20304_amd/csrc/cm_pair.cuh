@@ -23,6 +23,7 @@ struct PairShared {
   int ga, gb, valid, a, b;
   int nvs, nee, ncand;
   int next;              // dynamic work-queue item
+  long long tape_off;    // pool offset of this pair's tape window (-1: the pool is full)
 };
 
 template <int KM>
@@ -545,18 +546,10 @@ struct PairEngine {
   }
 
   // ------------------------------------------------------------ scores
-  __device__ __forceinline__ void scores(double (&tk)[KMAX]) {
-    const int neA = A.ne, neB = B.ne, nee = ps.nee, nvs = ps.nvs;
-#pragma unroll
-    for (int i = 0; i < KMAX; ++i) tk[i] = -INFINITY;
-    // V-S candidates (Sec. IV-C), both ways
-    for (int i = tid; i < nvs; i += BLOCK) {
-      Cand c;
-      vs(i, c);
-      Sbuf[i] = float(c.s);
-      tk_insert<KMAX>(tk, c.s);
-    }
-    // E-E pass 1: unsigned distances D
+  // E-E pass 1: the unsigned distance D and QP solution of every edge pair,
+  // then the row and column LSE of D (ends with a barrier).
+  __device__ __forceinline__ void pass1() {
+    const int neA = A.ne, neB = B.ne, nee = ps.nee;
     {
       int k = tid / neB, l = tid - (tid / neB) * neB;
       const int sk = BLOCK / neB, sl = BLOCK - sk * neB;
@@ -625,6 +618,22 @@ struct PairEngine {
       }
     }
     __syncthreads();
+  }
+
+  // Scores of every candidate into Sbuf and the per-lane top-K lists.
+  __device__ __forceinline__ void scores(double (&tk)[KMAX]) {
+    const int neA = A.ne, neB = B.ne, nee = ps.nee, nvs = ps.nvs;
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) tk[i] = -INFINITY;
+    // V-S candidates (Sec. IV-C), both ways
+    for (int i = tid; i < nvs; i += BLOCK) {
+      Cand c;
+      vs(i, c);
+      Sbuf[i] = float(c.s);
+      tk_insert<KMAX>(tk, c.s);
+    }
+    pass1();
+    if (nee == 0) return;
     // E-E pass 2: candidates, scores, top-K.  The forward kernel gives each
     // wave 8 x 8 tiles of edge pairs (lane = 8 kk + ll), whose witness
     // queries share the tile's face masks (polytope edges are stored in
@@ -697,22 +706,25 @@ struct PairEngine {
   }
 
   // ------------------------------------------------------------ filtered iteration
-  // Visit the candidates whose stored score is within `taus` tau of s_[K].
-  // Each wave first compacts the passing indices of its contiguous share of
-  // the candidates into List (ballot prefix sums, candidate order kept);
-  // the concatenated list is then evaluated densely in chunks of BLOCK, one
-  // candidate record per thread in sRec, and body(n) runs with all threads
-  // after a barrier for each chunk of n records.
-  template <typename F>
-  __device__ __forceinline__ void for_filtered(F&& body, double taus = kFilterTaus) {
-    const float thr = float(sTop[K - 1] - taus * T.tau) - 1e-6f * fabsf(float(sTop[K - 1]));
+  // The window test of candidate idx: its stored score within `taus` tau of
+  // s_[K] (thr from window_thr), or its bit in a recorded mask.
+  __device__ __forceinline__ float window_thr(double taus) const {
+    return float(sTop[K - 1] - taus * T.tau) - 1e-6f * fabsf(float(sTop[K - 1]));
+  }
+  // Compacts the candidates in the window into List: each wave its
+  // contiguous share of the candidates (ballot prefix sums, candidate order
+  // kept); returns their count (after a barrier; the wave counts stay in
+  // sCnt for list_at).  mask: the window as recorded by the forward (one bit
+  // per candidate, device memory) instead of the stored scores.
+  __device__ __forceinline__ int window(double taus, const unsigned long long* __restrict__ mask = nullptr) {
+    const float thr = window_thr(taus);
     const int ncand = ps.ncand;
     const int seg = (ncand + NW - 1) / NW;
     const int lo = min(ncand, wave * seg), hi = min(ncand, lo + seg);
     int n = 0;
     for (int b = lo; b < hi; b += 64) {
       const int idx = b + lane;
-      const bool pass = idx < hi && Sbuf[idx] >= thr;
+      const bool pass = idx < hi && (mask ? ((mask[idx >> 6] >> (idx & 63)) & 1ull) != 0ull : Sbuf[idx] >= thr);
       const unsigned long long ball = __ballot(pass);
       if (pass) List[lo + n + __popcll(ball & ((1ull << lane) - 1ull))] = idx;
       n += __popcll(ball);
@@ -722,32 +734,69 @@ struct PairEngine {
     int tot = 0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) tot += sCnt[w];
-    if (tot == 0) __syncthreads();   // sCnt is rewritten by the next call
+    return tot;
+  }
+  // Writes the window as a bit mask (bit idx & 63 of word idx >> 6), one
+  // ballot per 64 candidates.
+  __device__ __forceinline__ void window_mask(double taus, unsigned long long* __restrict__ mask) const {
+    const float thr = window_thr(taus);
+    const int ncand = ps.ncand;
+    for (int b = wave * 64; b < ncand; b += BLOCK) {
+      const int idx = b + lane;
+      const unsigned long long ball = __ballot(idx < ncand && Sbuf[idx] >= thr);
+      if (lane == 0) mask[b >> 6] = ball;
+    }
+  }
+  // Candidate index at position p (< window's count) of the compacted list.
+  __device__ __forceinline__ int list_at(int p) const {
+    // the wave region holding list position p: the last wave whose start is
+    // <= p (empty regions share the next region's start)
+    int reg = 0, off = 0, acc = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      if (p >= acc) { reg = w; off = acc; }
+      acc += sCnt[w];
+    }
+    const int seg = (ps.ncand + NW - 1) / NW;
+    return List[min(ps.ncand, reg * seg) + (p - off)];
+  }
+  // Candidate idx evaluated into this thread's record.
+  __device__ __forceinline__ void record(int idx) {
+    Cand c;
+    candidate(idx, c);
+    Rec& rr = sRec[tid];
+    rr.s = c.s; rr.d = c.d;
+    rr.px = float(c.p.x); rr.py = float(c.p.y); rr.pz = float(c.p.z);
+    rr.nx = float(c.n.x); rr.ny = float(c.n.y); rr.nz = float(c.n.z);
+    rr.w = ex2f(float(c.lw * kLog2e));
+    rr.idx = idx;
+  }
+  // Visit the candidates whose stored score is within `taus` tau of s_[K]:
+  // the compacted list is evaluated densely in chunks of BLOCK, one
+  // candidate record per thread in sRec, and body(n) runs with all threads
+  // after a barrier for each chunk of n records.  The forward may have
+  // recorded the same window: ntape >= 0 indices at lst, or else a mask
+  // (device memory); otherwise the stored scores are scanned.
+  template <typename F>
+  __device__ __forceinline__ void for_window(const int* __restrict__ lst, int ntape,
+                                             const unsigned long long* __restrict__ mask, F&& body, double taus) {
+    const int tot = ntape >= 0 ? ntape : window(taus, mask);
+    if (ntape < 0 && tot == 0) __syncthreads();   // sCnt is rewritten by the next call
     for (int base = 0; base < tot; base += BLOCK) {
       const int p = base + tid;
       if (p < tot) {
-        // the wave region holding list position p: the last wave whose
-        // start is <= p (empty regions share the next region's start)
-        int reg = 0, off = 0, acc = 0;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) {
-          if (p >= acc) { reg = w; off = acc; }
-          acc += sCnt[w];
-        }
-        const int idx = List[min(ncand, reg * seg) + (p - off)];
-        Cand c;
-        candidate(idx, c);
-        Rec& rr = sRec[tid];
-        rr.s = c.s; rr.d = c.d;
-        rr.px = float(c.p.x); rr.py = float(c.p.y); rr.pz = float(c.p.z);
-        rr.nx = float(c.n.x); rr.ny = float(c.n.y); rr.nz = float(c.n.z);
-        rr.w = ex2f(float(c.lw * kLog2e));
-        rr.idx = idx;
+        int idx = ntape >= 0 ? lst[p] : list_at(p);
+        if (idx < 0 || idx >= ps.ncand) idx = 0;   // a recorded list holds valid indices; never read past the pair
+        record(idx);
       }
       __syncthreads();
       body(min(BLOCK, tot - base));
       __syncthreads();
     }
+  }
+  template <typename F>
+  __device__ __forceinline__ void for_filtered(F&& body, double taus = kFilterTaus) {
+    for_window(nullptr, -1, nullptr, body, taus);
   }
 
   // ------------------------------------------------------------ SoftSort

@@ -221,3 +221,43 @@ def test_adjoint_lds_overflow_reported():
     with pytest.raises(CMError, match="LDS"):
         c.collide_backward(db, m, b.tau, b.K, None, None, g, None)
     c.close()
+
+
+@pytest.mark.parametrize("kind", ["polytopes", "mixed_presel", "refine", "tau0.1"])
+def test_backward_tape_matches_full_recompute(ctx, monkeypatch, kind):
+    """The adjoint with the forward's tape (s_[k], row sums, each pair's
+    window as indices or, at tau 0.1 where it holds every candidate, as a
+    bit mask), with a pool too small for every pair (the rest recompute the
+    whole forward) and with the tape off give the same gradients up to the
+    order of the float32 atomic sums."""
+    b = {"polytopes": W.polytope_scenes(48, seed=51, n_points=40),
+         "mixed_presel": W.mixed_scenes(64, seed=52),
+         "refine": W.polytope_scenes(24, seed=53, n_points=24),
+         "tau0.1": W.polytope_scenes(8, seed=54, n_points=24, tau=0.1)}[kind]
+    presel = (16, 10) if kind == "mixed_presel" else None
+    refine = 2 if kind == "refine" else 0
+    ids = ctx.create_geometry(b.geoms)
+    db = ctx.upload_batch(b, ids)
+    m = ctx.collide(db, b.tau, b.K, presel=presel, refine=refine)
+    ctx.check_errors()
+    n = int(m.n_pairs.item())
+    cap, K = m.capacity, b.K
+    rng = np.random.default_rng(9)
+    tt = {k: torch.as_tensor(rng.standard_normal(s).astype(np.float32)).to(ctx.device)
+          for k, s in (("p", (3, cap * K)), ("nu", (3, cap * K)), ("d", (cap * K,)), ("w", (cap * K,)))}
+    outs = {}
+    for name, env in (("tape", None), ("small_pool", "4000"), ("off", "0")):
+        if env is None:
+            monkeypatch.delenv("CM_ADJOINT_TAPE", raising=False)
+        else:
+            monkeypatch.setenv("CM_ADJOINT_TAPE", env)
+        _say(f"[gpu-bwd] tape {name}: {kind}, {n} pairs")
+        g = ctx.collide_backward(db, m, b.tau, K, tt["p"], tt["nu"], tt["d"], tt["w"], presel=presel, refine=refine)
+        ctx.check_errors()
+        outs[name] = {k: v.cpu().numpy() for k, v in g.items()}
+    monkeypatch.delenv("CM_ADJOINT_TAPE", raising=False)
+    for name in ("small_pool", "off"):
+        for k in ("pose", "vertices", "params", "tau"):
+            a, c = outs["tape"][k], outs[name][k]
+            scale = np.abs(a).max() + 1e-12
+            assert np.abs(a - c).max() <= 2e-5 * scale, (name, k, np.abs(a - c).max(), scale)
