@@ -537,7 +537,7 @@ def main():
         return torch.as_tensor(a).to(ctx.device), torch.as_tensor(b).to(ctx.device)
 
     def fwd_bwd(db, out, tau, K, a, b, fused=False, presel=None):
-        ctx.collide(db, tau, K, out=out, fused=fused, stream=stream, presel=presel)
+        ctx.collide(db, tau, K, out=out, fused=fused, stream=stream, presel=presel, record=True)
         # L = sum_k a_k w_k d_k + b_k . nu_k
         gd = a * out.weight
         gw = a * out.dist

@@ -186,6 +186,8 @@ typedef struct {
   float* normal;         /* [3][capacity * K] pair normals, A -> B */
   float* dist;           /* [capacity * K] signed distances */
   float* weight;         /* [capacity * K] activity weights in [0, 1] */
+  void* tape;            /* optional (NULL = none): the adjoint's tape, cm_tape_bytes bytes, 16-byte aligned */
+  int64_t tape_bytes;    /* size of `tape` */
 } cm_manifold;
 
 /* Cotangents of the manifold outputs (device, same layout as cm_manifold;
@@ -331,6 +333,23 @@ cm_status cm_collide_noalloc(cm_context* ctx, const cm_batch* batch, const cm_pa
  * the order of float32 atomic additions. */
 cm_status cm_collide_backward(cm_context* ctx, const cm_batch* batch, const cm_params* prm,
                               const cm_manifold* fwd, const cm_cotangent* cot, cm_grads* out, void* stream);
+
+/* The adjoint's tape recorded by the forward (device memory the caller owns,
+ * as for the other outputs).  When a manifold's `tape` is non-NULL,
+ * cm_collide and cm_collide_fused also record into it, per kept pair, s_[k],
+ * the SoftSort row sums and the adjoint's window, and cm_collide_backward
+ * given that manifold reverses from it instead of running the recording
+ * forward itself (one launch instead of two).  The tape belongs to the
+ * forward call that recorded it: the batch contents (poses, geometry) and
+ * parameters must be unchanged when the backward uses it, or the gradients
+ * are wrong (the kernels still stay within their buffers).  cm_tape_bytes
+ * gives the size for `capacity` pairs at K with pool_entries four-byte pool
+ * entries (<= 0: the pool cm_collide_backward would use on its own for this
+ * context, see above); pairs whose windows do not fit the pool are
+ * recomputed whole by the backward.  A tape smaller than cm_tape_bytes(...,
+ * 2, ...) or not 16-byte aligned: CM_ERR_INVALID_ARG.  cm_collide_noalloc
+ * does not record one (CM_ERR_INVALID_ARG for a non-NULL tape). */
+cm_status cm_tape_bytes(cm_context* ctx, int32_t capacity, int32_t K, int64_t pool_entries, int64_t* bytes);
 
 /* ---------------------------------------------------------------- E-E witness points
  * The edge-edge witness routine on its own, over n independent edge pairs:

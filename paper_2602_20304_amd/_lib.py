@@ -34,7 +34,7 @@ class cm_batch(C.Structure):
 
 class cm_manifold(C.Structure):
     _fields_ = [("capacity", i32), ("n_pairs", vp), ("pair_offsets", vp), ("pairs", vp), ("point", vp),
-                ("normal", vp), ("dist", vp), ("weight", vp)]
+                ("normal", vp), ("dist", vp), ("weight", vp), ("tape", vp), ("tape_bytes", C.c_int64)]
 
 
 class cm_cotangent(C.Structure):
@@ -84,6 +84,7 @@ SIGNATURES = {
     "cm_collide_backward": (i32, [vp, C.POINTER(cm_batch), C.POINTER(cm_params), C.POINTER(cm_manifold),
                                   C.POINTER(cm_cotangent), C.POINTER(cm_grads), vp]),
     "cm_ee_witness": (i32, [vp, vp, C.c_int64, C.c_float, C.c_float, i32, vp, vp]),
+    "cm_tape_bytes": (i32, [vp, i32, i32, C.c_int64, C.POINTER(C.c_int64)]),
     "cm_set_kernel_timing": (i32, [vp, i32]),
     "cm_kernel_time": (i32, [vp, i32, C.POINTER(C.c_double), i64p]),
     "cm_server_create": (i32, [vp, C.c_uint64, i32, C.POINTER(vp)]),

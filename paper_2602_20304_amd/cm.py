@@ -94,6 +94,7 @@ class Manifold:
     normal: torch.Tensor        # float32 [3, cap*K]
     dist: torch.Tensor          # float32 [cap*K]
     weight: torch.Tensor        # float32 [cap*K]
+    tape: Optional[torch.Tensor] = None   # uint8 [cm_tape_bytes]: the adjoint's tape, when recorded
 
     @staticmethod
     def empty(n_scenes: int, capacity: int, K: int, device) -> "Manifold":
@@ -113,6 +114,8 @@ class Manifold:
         m.normal = _ptr(self.normal)
         m.dist = _ptr(self.dist)
         m.weight = _ptr(self.weight)
+        m.tape = _ptr(self.tape) if self.tape is not None else None
+        m.tape_bytes = int(self.tape.numel()) if self.tape is not None else 0
         return m
 
     def to_numpy(self):
@@ -245,14 +248,24 @@ class Context:
     # ------------------------------------------------------------- forward
     def collide(self, db: DeviceBatch, tau: float, K: int, capacity: Optional[int] = None, out: Manifold = None,
                 fused: bool = False, stream=None, lambda_reg=-1.0, eps_n=-1.0, cull_margin=-1.0,
-                flags: int = 0, presel=None, refine: int = 0, noalloc: bool = False) -> Manifold:
+                flags: int = 0, presel=None, refine: int = 0, noalloc: bool = False,
+                record: bool = False) -> Manifold:
         """fused: cm_collide_fused; noalloc: cm_collide_noalloc (workspace in
-        the library's static device array; the caller allocates `out`)."""
+        the library's static device array; the caller allocates `out`);
+        record: also record the adjoint's tape into out.tape (allocated here
+        when missing or too small), which collide_backward then uses.  A
+        forward without record leaves out.tape None."""
         if fused and noalloc:
             raise ValueError("fused and noalloc are different entry points")
         if out is None:
             cap = db.n_cand_total if capacity is None else capacity
             out = Manifold.empty(db.n_scenes, cap, K, self.device)
+        if record:
+            need = self.tape_bytes(out.capacity, K)
+            if out.tape is None or out.tape.numel() < need:
+                out.tape = torch.empty(need, dtype=torch.uint8, device=self.device)
+        else:
+            out.tape = None
         prm = make_params(tau, K, lambda_reg, eps_n, cull_margin, flags, presel, refine)
         b = db.as_c()
         m = out.as_c()
@@ -267,6 +280,12 @@ class Context:
         self._check(self.lib.cm_fused_tuning(self.h, a[0], a[1], a[2], ms, a[3]))
         return dict(class_max_edges=list(a[0]), class_blocks=list(a[1]), sample_pairs=list(a[2]),
                     sample_ms=[[ms[2 * c], ms[2 * c + 1]] for c in range(3)], from_cache=[bool(x) for x in a[3]])
+
+    def tape_bytes(self, capacity: int, K: int, pool_entries: int = 0) -> int:
+        """Bytes of the adjoint's tape for `capacity` pairs at K (cm_tape_bytes)."""
+        n = C.c_int64(0)
+        self._check(self.lib.cm_tape_bytes(self.h, int(capacity), int(K), int(pool_entries), C.byref(n)))
+        return int(n.value)
 
     # ------------------------------------------------------------- E-E witness points
     def ee_witness(self, edges: torch.Tensor, tau: float, lambda_reg: float = -1.0, hard: bool = False,
@@ -327,7 +346,7 @@ class _CollideFn(torch.autograd.Function):
     @staticmethod
     def forward(fctx, xi, verts, params, tau_t, cmctx, db, K, capacity, fused, flags, presel, refine):
         tau = float(tau_t.item())
-        m = cmctx.collide(db, tau, K, capacity, fused=fused, flags=flags, presel=presel, refine=refine)
+        m = cmctx.collide(db, tau, K, capacity, fused=fused, flags=flags, presel=presel, refine=refine, record=True)
         fctx.cm = (cmctx, db, m, tau, K, flags, presel, refine)
         fctx.mark_non_differentiable(m.n_pairs, m.pairs)
         return m.point, m.normal, m.dist, m.weight, m.n_pairs, m.pairs

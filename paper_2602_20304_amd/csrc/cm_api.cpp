@@ -377,8 +377,12 @@ cm_status resolve_out(cm_context* ctx, const cm_manifold* o, OutDev* od) {
     return cm_fail(ctx, CM_ERR_INVALID_ARG, "bad manifold outputs");
   if (o->capacity > 0 && (!o->pairs || !o->point || !o->normal || !o->dist || !o->weight))
     return cm_fail(ctx, CM_ERR_INVALID_ARG, "manifold output arrays missing");
+  if (o->tape && (reinterpret_cast<uintptr_t>(o->tape) & 15))
+    return cm_fail(ctx, CM_ERR_INVALID_ARG, "the tape must be 16-byte aligned");
   od->capacity = o->capacity; od->n_pairs = o->n_pairs; od->pair_offsets = o->pair_offsets; od->pairs = o->pairs;
   od->point = o->point; od->normal = o->normal; od->dist = o->dist; od->weight = o->weight;
+  od->tape = static_cast<char*>(o->tape);
+  od->tape_bytes = o->tape ? o->tape_bytes : 0;
   return CM_OK;
 }
 
@@ -452,10 +456,13 @@ extern "C" cm_status cm_collide(cm_context* ctx, const cm_batch* batch, const cm
   if ((s = ctx_order(ctx, st)) != CM_OK) return s;
   FwdLaunch f;
   if (od.capacity > 0 && (s = ctx_prepare_fwd(ctx, bd, pd, od, 256, false, &f)) != CM_OK) return s;
+  if (od.tape && od.capacity > 0 && !tape_layout(od.tape, od.tape_bytes, od.capacity, pd.K, &f.tape))
+    return cm_fail(ctx, CM_ERR_INVALID_ARG, "the tape is smaller than cm_tape_bytes gives for this capacity and K");
   hipEvent_t t0 = timer_begin(ctx, st);
   if ((s = ctx_broadphase(ctx, bd, pd, od, st)) != CM_OK) return s;
   timer_end(ctx, CM_TIMER_BROADPHASE, t0, st);
   if (od.capacity > 0) {
+    if (f.tape.base && (s = cm_hip(ctx, launch_tape_reset(f.tape, st), "tape reset")) != CM_OK) return s;
     t0 = timer_begin(ctx, st);
     if ((s = cm_hip(ctx, launch_collide_fwd(f, st), "collide launch")) != CM_OK) return s;
     timer_end(ctx, CM_TIMER_FORWARD, t0, st);
@@ -477,6 +484,7 @@ extern "C" cm_status cm_collide_noalloc(cm_context* ctx, const cm_batch* batch, 
   if ((s = resolve_batch(ctx, batch, &bd)) != CM_OK) return s;
   if ((s = resolve_out(ctx, out, &od)) != CM_OK) return s;
   if (!ctx->noalloc_scratch) return cm_fail(ctx, CM_ERR_DEVICE, ctx->noalloc_error);
+  if (od.tape) return cm_fail(ctx, CM_ERR_INVALID_ARG, "the allocation-free forward records no tape");
   const size_t cap = CM_NOALLOC_SCRATCH_BYTES;
   const size_t tiles = size_t(bd.n_scenes) / 1024 + 2;
   const size_t tile_bytes = (tiles * sizeof(int) + 255) & ~size_t(255);
@@ -622,6 +630,23 @@ static long long tape_pool_entries() {
   return n <= 0 ? 0 : std::min(n, (1LL << 31) - 1);
 }
 
+// The pool the backward records into on its own: no more entries than every
+// pair of the capacity could fill with its candidates' indices.
+static long long tape_default_pool(const cm_context* ctx, long long capacity) {
+  const long long most = capacity * (2LL * ctx->maxV + 2LL * ctx->maxE * ctx->maxE);
+  return std::min(tape_pool_entries(), std::max(most, 1LL));
+}
+
+extern "C" cm_status cm_tape_bytes(cm_context* ctx, int32_t capacity, int32_t K, int64_t pool_entries, int64_t* bytes) {
+  if (!ctx) return CM_ERR_INVALID_ARG;
+  if (!bytes || capacity < 0 || K < 1 || K > CM_MAX_K)
+    return cm_fail(ctx, CM_ERR_INVALID_ARG, "null result, negative capacity or K outside 1..32");
+  long long pool = pool_entries > 0 ? (long long)pool_entries : tape_default_pool(ctx, capacity);
+  pool = std::max(pool, 2LL);
+  *bytes = 256 + tape_records_bytes(capacity, K) + 4 * pool;
+  return CM_OK;
+}
+
 extern "C" cm_status cm_collide_backward(cm_context* ctx, const cm_batch* batch, const cm_params* prm,
                                          const cm_manifold* fwd, const cm_cotangent* cot, cm_grads* out,
                                          void* stream) {
@@ -672,9 +697,12 @@ extern "C" cm_status cm_collide_backward(cm_context* ctx, const cm_batch* batch,
   // kept pair s_[k], the SoftSort row sums and the candidates within the
   // adjoint's window, so the adjoint kernel skips the forward's candidate
   // pass; a pair whose list no longer fits the pool is recomputed whole.
-  // (no more entries than every kept pair's candidates could fill)
-  const long long most = (long long)od.capacity * (2LL * ctx->maxV + 2LL * ctx->maxE * ctx->maxE);
-  const long long pool_cap = std::min(tape_pool_entries(), std::max(most, 1LL));
+  // A tape recorded by the caller's forward is used as it is; without one
+  // the forward kernel records it here, into the context's workspace.
+  TapeDev tv;
+  if (od.tape && !tape_layout(od.tape, od.tape_bytes, od.capacity, pd.K, &tv))
+    return cm_fail(ctx, CM_ERR_INVALID_ARG, "the tape is smaller than cm_tape_bytes gives for this capacity and K");
+  const long long pool_cap = od.tape ? 0 : tape_default_pool(ctx, od.capacity);
   FwdLaunch f1;
   if (pool_cap > 0 && (s = ctx_prepare_fwd(ctx, bd, pd, od, 256, false, &f1)) != CM_OK) return s;
   const size_t need = size_t(b.f.grid) * size_t(b.f.scratch_stride) * sizeof(float);
@@ -682,23 +710,17 @@ extern "C" cm_status cm_collide_backward(cm_context* ctx, const cm_batch* batch,
     return cm_hip(ctx, e, "backward scratch");
   b.f.scratch = ctx->d_scratch;
   if (pool_cap > 0) {
-    const size_t hdr = (size_t(od.capacity) * size_t(tape_stride(pd.K)) + 255) & ~size_t(255);
-    if ((e = ctx_ensure(ctx, &ctx->d_bwd, &ctx->bwd_cap, 256 + hdr + 4 * size_t(pool_cap))) != hipSuccess)
+    const long long bytes = 256 + tape_records_bytes(od.capacity, pd.K) + 4 * pool_cap;
+    if ((e = ctx_ensure(ctx, &ctx->d_bwd, &ctx->bwd_cap, size_t(bytes))) != hipSuccess)
       return cm_hip(ctx, e, "adjoint tape");
-    char* tb = static_cast<char*>(ctx->d_bwd);
-    TapeDev t;
-    t.pool_used = reinterpret_cast<unsigned long long*>(tb);
-    t.base = tb + 256;
-    t.pool = reinterpret_cast<int*>(tb + 256 + hdr);
-    t.pool_cap = pool_cap;
-    if ((e = hipMemsetAsync(t.pool_used, 0, sizeof(unsigned long long), st)) != hipSuccess)
-      return cm_hip(ctx, e, "zero the tape pool counter");
+    tape_layout(static_cast<char*>(ctx->d_bwd), bytes, od.capacity, pd.K, &tv);
+    if ((e = launch_tape_reset(tv, st)) != hipSuccess) return cm_hip(ctx, e, "tape reset");
     f1.scratch = ctx->d_scratch;   // the ensures above may have moved it
-    f1.tape = t;
+    f1.tape = tv;
     f1.tape.skip_out = 1;
-    t.pool_used = nullptr;
-    b.f.tape = t;
   }
+  b.f.tape = tv;
+  b.f.tape.pool_used = nullptr;
   hipEvent_t t0 = timer_begin(ctx, st);
   if (pool_cap > 0 && (s = cm_hip(ctx, launch_collide_fwd(f1, st), "adjoint tape launch")) != CM_OK) return s;
   if ((s = cm_hip(ctx, launch_collide_bwd(b, st), "backward launch")) != CM_OK) return s;

@@ -134,6 +134,9 @@ extern "C" cm_status cm_collide_fused(cm_context* ctx, const cm_batch* batch, co
   if (pd.refine > 0) return cm_fail(ctx, CM_ERR_INVALID_ARG, "the fused path does not support witness sphere tracing");
   if ((s = resolve_batch(ctx, batch, &bd)) != CM_OK) return s;
   if ((s = resolve_out(ctx, out, &od)) != CM_OK) return s;
+  TapeDev tv;   // the adjoint's tape, recorded by the class kernels when given
+  if (od.tape && od.capacity > 0 && !tape_layout(od.tape, od.tape_bytes, od.capacity, pd.K, &tv))
+    return cm_fail(ctx, CM_ERR_INVALID_ARG, "the tape is smaller than cm_tape_bytes gives for this capacity and K");
   hipSetDevice(ctx->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
   if ((s = ctx_order(ctx, st)) != CM_OK) return s;
@@ -172,8 +175,12 @@ extern "C" cm_status cm_collide_fused(cm_context* ctx, const cm_batch* batch, co
     if (e2 != hipSuccess) return e2;
     if (od.capacity == 0) return hipSuccess;
     if ((e2 = launch_fused_prepare(ctx_tables(ctx), bd, od, cmax, w, s2)) != hipSuccess) return e2;
-    for (int c = 0; c < kNumClasses; ++c)
-      if ((e2 = launch_collide_fwd(fl[c], s2)) != hipSuccess) return e2;
+    if (tv.base && (e2 = launch_tape_reset(tv, s2)) != hipSuccess) return e2;
+    for (int c = 0; c < kNumClasses; ++c) {
+      FwdLaunch f = fl[c];
+      f.tape = tv;
+      if ((e2 = launch_collide_fwd(f, s2)) != hipSuccess) return e2;
+    }
     return hipSuccess;
   };
   const size_t tiles = size_t(bd.n_scenes) / 1024 + 2;
@@ -261,7 +268,8 @@ extern "C" cm_status cm_collide_fused(cm_context* ctx, const cm_batch* batch, co
                             uint64_t(uintptr_t(od.point)), uint64_t(uintptr_t(od.normal)),
                             uint64_t(uintptr_t(od.dist)), uint64_t(uintptr_t(od.weight)),
                             uint64_t(uintptr_t(od.pair_offsets)), uint64_t(od.capacity), uint64_t(pd.K), uint64_t(pd.flags),
-                            uint64_t(pd.presel_v), uint64_t(pd.presel_e)};
+                            uint64_t(pd.presel_v), uint64_t(pd.presel_e), uint64_t(uintptr_t(od.tape)),
+                            uint64_t(od.tape_bytes)};
   for (uint64_t v : parts) key = mix(key, v);
   double dv[4] = {pd.tau, pd.lam, pd.eps_n, double(pd.margin)};
   for (double d : dv) { uint64_t b; std::memcpy(&b, &d, 8); key = mix(key, b); }

@@ -240,6 +240,15 @@ void collide_fwd(Tables tb, BatchDev bt, ParamsDev prm, OutDev out,
 
 // ============================================================ launchers
 
+__global__ void tape_reset(unsigned long long* counter) {
+  if (threadIdx.x == 0) *counter = 0ull;
+}
+
+hipError_t launch_tape_reset(const TapeDev& t, hipStream_t st) {
+  hipLaunchKernelGGL(tape_reset, dim3(1), dim3(64), 0, st, t.pool_used);
+  return hipGetLastError();
+}
+
 int fwd_lds_bytes(int maxV, int maxE, int maxF, int block, int kmax, bool presel, bool edges_out) {
   (void)kmax;
   const int extra = presel ? presel_lds_bytes(maxV, maxE) : 0;

@@ -61,6 +61,8 @@ struct OutDev {
   int32_t* pair_offsets;
   int32_t* pairs;
   float* point; float* normal; float* dist; float* weight;
+  char* tape;                   // the adjoint's tape (caller-owned), or null
+  long long tape_bytes;
 };
 
 // Device error bits (sticky until cm_check_errors).

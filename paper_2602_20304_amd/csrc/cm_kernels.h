@@ -78,6 +78,21 @@ int bwd_lds_bytes(int maxV, int maxE, int maxF, int block, bool presel = false);
 int bwd_occupancy(const BwdLaunch& b);
 hipError_t launch_collide_bwd(const BwdLaunch& b, hipStream_t st);
 int fwd_occupancy(const FwdLaunch& f);
+// Zeroes the tape's pool counter (a kernel, so it can sit in a captured graph).
+hipError_t launch_tape_reset(const TapeDev& t, hipStream_t st);
+// Byte layout of a caller-owned tape of `bytes` for `capacity` pairs at K:
+// counter (256 B), records, pool.  Returns false when it is too small.
+inline long long tape_records_bytes(long long capacity, int K) { return (capacity * tape_stride(K) + 255) & ~255LL; }
+inline bool tape_layout(char* base, long long bytes, long long capacity, int K, TapeDev* t) {
+  const long long hdr = tape_records_bytes(capacity, K);
+  if (!base || bytes < 256 + hdr + 8) return false;
+  t->pool_used = reinterpret_cast<unsigned long long*>(base);
+  t->base = base + 256;
+  t->pool = reinterpret_cast<int*>(base + 256 + hdr);
+  t->pool_cap = (bytes - 256 - hdr) / 4;
+  t->skip_out = 0;
+  return true;
+}
 // Sets f.edges_out when keeping the edge arrays in the scratch slot lets more
 // workgroups share a CU than keeping them in LDS (LDS-limited launches);
 // returns the workgroups per CU of the chosen placement.

@@ -261,3 +261,46 @@ def test_backward_tape_matches_full_recompute(ctx, monkeypatch, kind):
             a, c = outs["tape"][k], outs[name][k]
             scale = np.abs(a).max() + 1e-12
             assert np.abs(a - c).max() <= 2e-5 * scale, (name, k, np.abs(a - c).max(), scale)
+
+
+def test_backward_from_recorded_tape(ctx):
+    """A tape recorded by the caller's forward (plain, and fused over two graph
+    replays) gives the adjoint the same gradients as the backward recording
+    its own; a tape that is too small, misaligned or given to the
+    allocation-free forward is rejected."""
+    from paper_2602_20304_amd._lib import CMError
+    b = W.mixed_scenes(48, seed=55, poly_points=24)
+    ids = ctx.create_geometry(b.geoms)
+    db = ctx.upload_batch(b, ids)
+    m = ctx.collide(db, b.tau, b.K)
+    ctx.check_errors()
+    cap, K = m.capacity, b.K
+    rng = np.random.default_rng(10)
+    tt = {k: torch.as_tensor(rng.standard_normal(s).astype(np.float32)).to(ctx.device)
+          for k, s in (("p", (3, cap * K)), ("nu", (3, cap * K)), ("d", (cap * K,)), ("w", (cap * K,)))}
+    grad = lambda mm: {k: v.cpu().numpy() for k, v in
+                       ctx.collide_backward(db, mm, b.tau, K, tt["p"], tt["nu"], tt["d"], tt["w"]).items()}
+    ref = grad(m)
+    runs = [("plain", dict()), ("fused", dict(fused=True)), ("fused replay", dict(fused=True))]
+    for name, kw in runs:
+        _say(f"[gpu-bwd] recorded tape: {name}, {int(m.n_pairs.item())} pairs")
+        mr = ctx.collide(db, b.tau, K, record=True, **kw)
+        ctx.check_errors()
+        assert mr.tape is not None
+        for k in ("point", "normal", "dist", "weight"):
+            assert torch.equal(getattr(mr, k), getattr(m, k)), (name, k)
+        g = grad(mr)
+        ctx.check_errors()
+        for k in ("pose", "vertices", "params", "tau"):
+            scale = np.abs(ref[k]).max() + 1e-12
+            assert np.abs(g[k] - ref[k]).max() <= 2e-5 * scale, (name, k)
+    small = ctx.collide(db, b.tau, K)
+    small.tape = torch.empty(256, dtype=torch.uint8, device=ctx.device)
+    with pytest.raises(CMError, match="tape"):
+        ctx.collide_backward(db, small, b.tau, K, None, None, tt["d"], None)
+    need = ctx.tape_bytes(cap, K)
+    small.tape = torch.empty(need + 16, dtype=torch.uint8, device=ctx.device)[8:8 + need]
+    with pytest.raises(CMError, match="aligned"):
+        ctx.collide_backward(db, small, b.tau, K, None, None, tt["d"], None)
+    with pytest.raises(CMError, match="tape"):
+        ctx.collide(db, b.tau, K, record=True, noalloc=True)
