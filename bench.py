@@ -253,7 +253,7 @@ def serving_leg(ctx_cls, n_requests: int, seed: int = 11):
     # FP64 oracle on a seeded sample of served pairs (4 per request, first 4 requests of the stream)
     from oracle import cm_oracle as O
     cache = O.GeomCache(pool)
-    worst, checked = 0.0, 0
+    worst, checked = -float("inf"), 0
     srng = np.random.default_rng(seed + 2)
     for i, r in sorted(kept_results.items()):
         q = payload[n_cal + i][0]
@@ -272,7 +272,7 @@ def serving_leg(ctx_cls, n_requests: int, seed: int = 11):
     return dict(requests=len(done), rate_per_s=rate, saturated_per_s=sat, burst_pairs_per_s=burst_pairs,
                 plain_sequential_pairs_per_s=plain_pairs, p50_ms=float(np.percentile(lat, 50) * 1e3),
                 p99_ms=float(np.percentile(lat, 99) * 1e3), pairs_per_s=pairs / wall, wall_s=wall,
-                oracle_check={"pairs": checked, "max_excess": worst,
+                oracle_check={"pairs": checked, "max_excess": worst if checked else None,
                               "bar": "|gpu - fp64| <= 1e-6 + 2e-5 |fp64| (max_excess <= 0 passes)"},
                 config=f"{n_requests} Poisson requests at 0.7 x the saturated rate measured on a burst of {n_cal}; "
                        f"256-4096 envs (log-uniform), 2-6 bodies/env from a resident pool of 64 hull-of-64 polytopes, "
@@ -458,7 +458,7 @@ def main():
     ap.add_argument("--ee-trials", type=int, default=20, help="timed launches per size in the E-E sweep")
     ap.add_argument("--only", default=None,
                     choices=[None, "cfg3_fused", "cfg3_plain", "cfg3_bwd", "cfg4_fused", "cfg4_plain", "cfg2_plain",
-                             "cfg2_fused", "cfg2_bwd", "cfg2_refine"],
+                             "cfg2_fused", "cfg2_bwd", "cfg2_refine", "cfg2_all", "ee", "sq"],
                     help="run one leg only, without the headline and the other legs (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (PMC byte calibration)")
@@ -631,7 +631,7 @@ def main():
         serving = serving_leg(Context, args.serve)
         log(f"serving: {serving['rate_per_s']:.2f} req/s (saturated {serving['saturated_per_s']:.2f}), "
             f"p50 {serving['p50_ms']:.1f} ms, p99 {serving['p99_ms']:.1f} ms, oracle sample max excess "
-            f"{serving['oracle_check']['max_excess']:.3g}")
+            f"{serving['oracle_check']['max_excess']}")
     # ------------------------------------------------------------ cfg 2 mixed scenes
     if (only and only.startswith("cfg2")) or (only is None and "2" in wanted and fits("cfg2", 40.0)):
         new_context()
@@ -644,7 +644,7 @@ def main():
                 "cfg2_plain_ne_s_fwd": dict(flags=FLAG_NO_EE | FLAG_ONE_SIDED_VS),
                 "cfg2_plain_refine_fwd": dict(refine=3)}
         pick = {"cfg2_plain": ["cfg2_plain_fwd"], "cfg2_fused": ["cfg2_fused_fwd"], "cfg2_bwd": [],
-                "cfg2_refine": ["cfg2_plain_refine_fwd"]}
+                "cfg2_refine": ["cfg2_plain_refine_fwd"], "cfg2_all": list(cfg2)}
         names = pick[only] if only else [n for n in cfg2 if n != "cfg2_plain_refine_fwd"]
         for name in names:
             kw = cfg2[name]
@@ -680,15 +680,16 @@ def main():
             res = timer.run(lambda: ctx.collide(db1, b1.tau, b1.K, out=out1, fused=fused, stream=stream), 5, 20)
             record(name, res, int(out1.n_pairs.item()), cap1)
     # ------------------------------------------------------------ serving, E-E, extended primitives
-    if only is None and "ee" in wanted and fits("ee_witness", 15.0):
+    if only == "ee" or (only is None and "ee" in wanted and fits("ee_witness", 15.0)):
         log("E-E witness microbenchmark ...")
         ee = ee_witness_leg(ctx, trials=args.ee_trials)
-    if only is None and "sq" in wanted and fits("superquadrics", 10.0):
+    if only == "sq" or (only is None and "sq" in wanted and fits("superquadrics", 10.0)):
         log("superquadric-union leg ...")
         sq = sq_leg(Context, steps=3)
 
     if only:
-        print(json.dumps({"only": only, "legs": legs, "rooflines": rooflines}), flush=True)
+        print(json.dumps({"only": only, "legs": legs, "rooflines": rooflines, "ee_witness": ee, "superquadrics": sq}),
+              flush=True)
         return
     line = {
         "metric": METRIC,
