@@ -278,15 +278,17 @@ cm_status cm_collide_fused(cm_context* ctx, const cm_batch* batch, const cm_para
  * count of their bodies (<= 96, <= 300, above), each with its own LDS sizing
  * and persistent grid.  Once per (geometry set, K) the first
  * cm_collide_fused call classifies its batch, times each class's kernel at
- * 256- and 128-thread blocks on the same evenly strided sample of the
- * class's cost order (about 1/16 of its pairs) and keeps the faster; the
+ * 256-, 128- and 64-thread blocks (those that keep at least 2 waves per
+ * SIMD; 256 always) on the same evenly strided sample of the class's cost
+ * order (about 1/16 of its pairs) and keeps the fastest; the
  * choice is stored in the text file named by CM_TUNE_CACHE (default
  * $HOME/.cache/cm_fused_tune.txt), keyed by device architecture, CU count
  * and the class's largest vertex / edge / face counts and K, and read back
  * by later processes instead of timing.  cm_fused_tuning reports the current
  * plan: per class (arrays of 3, any may be NULL) the largest edge count, the
- * block size, the sample size, the sample timings in ms at 256 and 128
- * ([3][2], 0 when not timed) and whether the choice came from the cache. */
+ * block size, the sample size, the sample timings in ms at 256, 128 and 64
+ * ([3][3], 0 when not timed) and whether the choice came from the cache.
+ * Results do not depend on the block size. */
 cm_status cm_fused_tuning(cm_context* ctx, int32_t* class_max_edges, int32_t* class_blocks, int32_t* sample_pairs,
                           float* sample_ms, int32_t* from_cache);
 

@@ -276,10 +276,11 @@ class Context:
     def fused_tuning(self) -> dict:
         """The fused path's per-size-class plan (cm_fused_tuning)."""
         a = [(C.c_int32 * 3)() for _ in range(4)]
-        ms = (C.c_float * 6)()
+        ms = (C.c_float * 9)()
         self._check(self.lib.cm_fused_tuning(self.h, a[0], a[1], a[2], ms, a[3]))
         return dict(class_max_edges=list(a[0]), class_blocks=list(a[1]), sample_pairs=list(a[2]),
-                    sample_ms=[[ms[2 * c], ms[2 * c + 1]] for c in range(3)], from_cache=[bool(x) for x in a[3]])
+                    sample_ms=[[ms[3 * c + j] for j in range(3)] for c in range(3)],
+                    from_cache=[bool(x) for x in a[3]])
 
     def tape_bytes(self, capacity: int, K: int, pool_entries: int = 0) -> int:
         """Bytes of the adjoint's tape for `capacity` pairs at K (cm_tape_bytes)."""

@@ -31,6 +31,10 @@ struct CmDevCaps {
   size_t recs = 0, vx = 0, vy = 0, vz = 0, e0 = 0, e1 = 0, fnx = 0, fny = 0, fnz = 0, fo = 0, f0 = 0, f1 = 0, f2 = 0;
 };
 
+// Block sizes the fused path's autotuner may time per size class.
+constexpr int kTuneBlocks = 3;
+constexpr int kTuneBlock[kTuneBlocks] = {256, 128, 64};
+
 struct cm_context {
   int device = 0;
   int num_cus = 1;
@@ -59,7 +63,7 @@ struct cm_context {
   bool plan_tuned = false;
   int cls_maxE[3] = {0, 0, 0}, cls_maxV[3] = {0, 0, 0}, cls_maxF[3] = {0, 0, 0}, cls_block[3] = {256, 256, 256};
   int cls_bound[2] = {96, 300};
-  float cls_tuned_ms[3][2] = {};   // autotune sample timings (block 256, 128), 0 = not timed
+  float cls_tuned_ms[3][kTuneBlocks] = {};   // autotune sample timings (kTuneBlock order), 0 = not timed
   int cls_tune_n[3] = {0, 0, 0};   // sample sizes
   int cls_cached[3] = {0, 0, 0};   // choice taken from the cache file
   void* d_fused = nullptr;

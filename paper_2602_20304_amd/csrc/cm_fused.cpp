@@ -100,8 +100,8 @@ int tune_lookup(const std::string& key) {
     std::ifstream in(p);
     std::string k;
     int b;
-    while (in >> k >> b)
-      if (b == 128 || b == 256) g_tune[k] = b;
+    while (in >> k >> b)   // only block sizes the tuner can choose
+      if (std::find(kTuneBlock, kTuneBlock + kTuneBlocks, b) != kTuneBlock + kTuneBlocks) g_tune[k] = b;
   }
   auto it = g_tune.find(key);
   return it == g_tune.end() ? 0 : it->second;
@@ -218,23 +218,33 @@ extern "C" cm_status cm_collide_fused(cm_context* ctx, const cm_batch* batch, co
       for (int c = 0; c < kNumClasses && s == CM_OK; ++c) {
         const int count = ranges[2 * c + 1];
         ctx->cls_tune_n[c] = 0;
-        ctx->cls_tuned_ms[c][0] = ctx->cls_tuned_ms[c][1] = 0.f;
+        for (int bi = 0; bi < kTuneBlocks; ++bi) ctx->cls_tuned_ms[c][bi] = 0.f;
         if (ctx->cls_cached[c] || count <= 0) continue;
         float best = 1e30f;
         int best_block = 256;
-        const int blocks[2] = {256, 128};
-        for (int bi = 0; bi < 2; ++bi) {
-          ctx->cls_block[c] = blocks[bi];
+        // candidates that keep at least 2 waves per SIMD (256 always)
+        bool try_b[kTuneBlocks];
+        int max_grid = 1;
+        for (int bi = 0; bi < kTuneBlocks; ++bi) {
+          const FwdLaunch t = class_launch(ctx, bd, pd, od, c, kTuneBlock[bi], w);
+          try_b[bi] = bi == 0 || (t.grid / std::max(ctx->num_cus, 1)) * (kTuneBlock[bi] / 64) >= 8;
+          if (try_b[bi]) max_grid = std::max(max_grid, t.grid);
+        }
+        {
+          // the same strided sample for every candidate: about 1/16 of the
+          // class, at least 4 pairs per workgroup of the largest grid
+          const int n = std::min(count, std::max(count / 16, 4 * max_grid));
+          ctx->cls_tune_n[c] = n;
+          if ((e = launch_fused_sample(w, c, n, w.sample, w.sample + n + 1, st)) != hipSuccess) {
+            s = cm_hip(ctx, e, "autotune sample");
+            break;
+          }
+        }
+        for (int bi = 0; bi < kTuneBlocks; ++bi) {
+          if (!try_b[bi]) continue;
+          ctx->cls_block[c] = kTuneBlock[bi];
           if ((s = plan_scratch()) != CM_OK) break;
           FwdLaunch t = fl[c];
-          if (bi == 0) {
-            const int n = std::min(count, std::max(count / 16, 4 * 2 * t.grid));
-            ctx->cls_tune_n[c] = n;
-            if ((e = launch_fused_sample(w, c, n, w.sample, w.sample + n + 1, st)) != hipSuccess) {
-              s = cm_hip(ctx, e, "autotune sample");
-              break;
-            }
-          }
           const int n = ctx->cls_tune_n[c];
           t.order = w.sample;
           t.range = w.sample + n + 1;
@@ -247,7 +257,7 @@ extern "C" cm_status cm_collide_fused(cm_context* ctx, const cm_batch* batch, co
           float ms = 0.f;
           (void)hipEventElapsedTime(&ms, e0, e1);
           ctx->cls_tuned_ms[c][bi] = ms;
-          if (ms < best) { best = ms; best_block = blocks[bi]; }
+          if (ms < best) { best = ms; best_block = kTuneBlock[bi]; }
         }
         ctx->cls_block[c] = best_block;
         if (s == CM_OK) tune_store(tune_key(ctx, c, kmax), best_block);
@@ -318,7 +328,8 @@ extern "C" cm_status cm_fused_tuning(cm_context* ctx, int32_t* class_max_edges, 
     if (class_max_edges) class_max_edges[c] = ctx->cls_maxE[c];
     if (class_blocks) class_blocks[c] = ctx->cls_block[c];
     if (sample_pairs) sample_pairs[c] = ctx->cls_tune_n[c];
-    if (sample_ms) { sample_ms[2 * c] = ctx->cls_tuned_ms[c][0]; sample_ms[2 * c + 1] = ctx->cls_tuned_ms[c][1]; }
+    if (sample_ms)
+      for (int bi = 0; bi < kTuneBlocks; ++bi) sample_ms[kTuneBlocks * c + bi] = ctx->cls_tuned_ms[c][bi];
     if (from_cache) from_cache[c] = ctx->cls_cached[c] != 0;
   }
   return CM_OK;

@@ -360,6 +360,11 @@ hipError_t launch_collide_fwd(const FwdLaunch& f, hipStream_t st) {
   }
   if (f.queue) {
     constexpr bool DYNV = true;
+    if (f.block == 64) {   // single-wave workgroups: the fused path's small pairs
+      if (f.kmax == 8) return launch_fwd_t<64, 8, true>(f, st);
+      if (f.kmax == 16) return launch_fwd_t<64, 16, true>(f, st);
+      return launch_fwd_t<64, 32, true>(f, st);
+    }
     CM_FWD_DISPATCH(launch_fwd_t, f, st)
   } else {
     constexpr bool DYNV = false;
@@ -390,6 +395,11 @@ int fwd_occupancy(const FwdLaunch& f) {
   }
   if (f.queue) {
     constexpr bool DYNV = true;
+    if (f.block == 64) {
+      if (f.kmax == 8) return occ_t<64, 8, true>(f.maxV, f.maxE, f.maxF, f.edges_out != 0);
+      if (f.kmax == 16) return occ_t<64, 16, true>(f.maxV, f.maxE, f.maxF, f.edges_out != 0);
+      return occ_t<64, 32, true>(f.maxV, f.maxE, f.maxF, f.edges_out != 0);
+    }
     CM_FWD_DISPATCH(occ_t, f.maxV, f.maxE, f.maxF, f.edges_out != 0)
   } else {
     constexpr bool DYNV = false;
