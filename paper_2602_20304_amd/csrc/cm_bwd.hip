@@ -78,8 +78,11 @@ struct BwdArgs {
   GradDev gr;
 };
 
+// Two waves per SIMD (256 registers a lane, some spilled to private memory)
+// for the kernels without the extended primitives, whose dual-number
+// queries would spill several times more; those take one.
 template <int BLOCK, int KMAX, bool PRESEL, bool SQ, bool REFINE = false>
-__global__ __launch_bounds__(BLOCK) void collide_bwd(Tables tb, BatchDev bt, ParamsDev prm, OutDev fwd, BwdArgs ga,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SQ ? 1 : 2))) void collide_bwd(Tables tb, BatchDev bt, ParamsDev prm, OutDev fwd, BwdArgs ga,
                                                      float* __restrict__ scratch, long long scratch_stride, int maxV,
                                                      int maxE, int maxF, unsigned* err, TapeDev tape) {
   extern __shared__ float4 smem4[];
