@@ -430,6 +430,79 @@ def config_ops(ctx, ids, batch, out):
     return opmodel.batch_ops(lut[:, 0], lut[:, 1], lut[:, 2], lut[:, 3], pairs[0], pairs[1], body_geom)
 
 
+def _geometry_lut(ctx, ids):
+    gids = np.unique(ids)
+    lut = np.zeros((int(gids.max()) + 1, 4), np.int64)
+    for g in gids:
+        i = ctx.geometry_info(int(g))
+        lut[int(g)] = (i["type"], i["n_vertices"], i["n_edges"], i["n_faces"])
+    return lut
+
+
+def tape_windows(out, nvA, nvB):
+    """Per kept pair of `out`: the adjoint-window candidates among A's
+    vertices, B's vertices and the edge-edge witnesses, read from the tape
+    the forward recorded (layout in include/cm.h).  A pair whose window was
+    not recorded counts as all edge-edge."""
+    K, cap = out.K, out.capacity
+    n = min(int(out.n_pairs.item()), cap)
+    stride = 16 + 80 * K
+    hdr = (cap * stride + 255) // 256 * 256
+    t = out.tape
+    used = int(t[:8].cpu().numpy().view(np.uint64)[0])
+    recs = t[256:256 + n * stride].cpu().numpy().reshape(n, stride)
+    count = recs[:, 0:4].copy().view(np.int32)[:, 0].astype(np.int64)
+    form = recs[:, 4:8].copy().view(np.int32)[:, 0]
+    off = recs[:, 8:16].copy().view(np.int64)[:, 0]
+    pool_n = min(used, (t.numel() - 256 - hdr) // 4)
+    pool = t[256 + hdr:256 + hdr + 4 * pool_n].cpu().numpy().view(np.int32)
+    nvs = nvA + nvB
+    w_a = np.zeros(n, np.int64)
+    w_b = np.zeros(n, np.int64)
+    w_e = np.where(form == 0, count, 0)
+    lp = np.nonzero(form == 1)[0]
+    if lp.size:
+        lens = count[lp]
+        first = np.repeat(off[lp] - np.concatenate(([0], np.cumsum(lens)[:-1])), lens)
+        vals = pool[first + np.arange(int(lens.sum()))]
+        owner = np.repeat(lp, lens)
+        in_a = vals < nvA[owner]
+        in_b = ~in_a & (vals < nvs[owner])
+        w_a += np.bincount(owner, weights=in_a, minlength=n).astype(np.int64)
+        w_b += np.bincount(owner, weights=in_b, minlength=n).astype(np.int64)
+        w_e += np.bincount(owner, weights=~(in_a | in_b), minlength=n).astype(np.int64)
+    for p in np.nonzero(form == 2)[0]:
+        words = (int(nvs[p]) + 63) // 64   # the mask words covering the vertex candidates
+        bits = np.unpackbits(pool[off[p]:off[p] + 2 * words].view(np.uint8), bitorder="little")
+        a_, b_ = int(nvA[p]), int(nvs[p])
+        w_a[p] = int(bits[:a_].sum())
+        w_b[p] = int(bits[a_:b_].sum())
+        w_e[p] = int(count[p]) - w_a[p] - w_b[p]
+    return w_a, w_b, w_e
+
+
+def adjoint_ops(ctx, ids, batch, out):
+    """Algorithmic (fma, alu, trans) of the adjoint launch on `out`'s kept
+    pairs, from the op model and each pair's recorded adjoint window."""
+    from paper_2602_20304_amd import opmodel
+    kept = min(int(out.n_pairs.item()), out.capacity)
+    pairs = out.pairs[:, :kept].cpu().numpy()
+    lut = _geometry_lut(ctx, ids)
+    body_geom = ids[batch.body_geom]
+    ga, gb = body_geom[pairs[0]], body_geom[pairs[1]]
+    w_a, w_b, w_e = tape_windows(out, lut[ga, 1], lut[gb, 1])
+    ops = opmodel.adjoint_batch_ops(lut[:, 0], lut[:, 1], lut[:, 2], lut[:, 3], pairs[0], pairs[1], body_geom,
+                                    w_a, w_b, w_e)
+    return ops, dict(window_candidates_per_pair=float((w_a + w_b + w_e).mean()) if kept else 0.0,
+                     vertex_sdf_share=float((w_a + w_b).sum() / max((w_a + w_b + w_e).sum(), 1)))
+
+
+ADJOINT_NOTE = ("algorithmic ops = the adjoint's method on each pair's recorded window (candidates within 18 tau "
+                "of s_[K]): the window candidates evaluated again and swept in reverse, the distance pass and "
+                "nearest-neighbour LSE terms of every edge pair recomputed, the LSE terms swept in reverse "
+                "(opmodel.adjoint_batch_ops); duration = the adjoint launch")
+
+
 def roofline_entry(ops, kernel_ms, kernel, launches, traffic=None, note=None):
     from paper_2602_20304_amd import opmodel
     r = opmodel.roofline(ops, kernel_ms * 1e-3)
@@ -577,11 +650,10 @@ def main():
             res = timer.run(lambda: fwd_bwd(db3, out3, tau, b3.K, a3, bb3), wu, st)
             r = record(name, res, int(out3.n_pairs.item()), cap3)
             if tau == 0.01:
-                ops = config_ops(ctx, ids3, b3, out3)
-                rooflines["cfg3_adjoint"] = roofline_entry(
-                    opmodel.reverse_ops(ops), r["backward_kernel_ms"], "collide_bwd", r["backward_launches"],
-                    note="algorithmic ops = the reverse sweep of the op model (2x the forward's multiply-adds; "
-                         "the kernel's own forward recompute is not counted)")
+                ops, win = adjoint_ops(ctx, ids3, b3, out3)
+                rooflines["cfg3_adjoint"] = roofline_entry(ops, r["backward_kernel_ms"], "collide_bwd",
+                                                           r["backward_launches"], note=ADJOINT_NOTE)
+                rooflines["cfg3_adjoint"].update(win)
         if not only and fits("cfg3_fused_fwd_bwd", 15.0):
             res = timer.run(lambda: fwd_bwd(db3, out3, b3.tau, b3.K, a3, bb3, fused=True), 1, 2)
             record("cfg3_fused_fwd_bwd", res, int(out3.n_pairs.item()), cap3)
@@ -614,9 +686,10 @@ def main():
             a4, bb4 = loss_cotangents(cap4, b4.K, seed=4)
             res = timer.run(lambda: fwd_bwd(db4, out4, b4.tau, b4.K, a4, bb4, fused=True), 0, 1)
             r = record("cfg4_fused_fwd_bwd", res, int(out4.n_pairs.item()), cap4)
-            ops4 = config_ops(ctx, ids4, b4, out4)
-            rooflines["cfg4_adjoint"] = roofline_entry(opmodel.reverse_ops(ops4), r["backward_kernel_ms"],
-                                                       "collide_bwd", r["backward_launches"])
+            ops4, win = adjoint_ops(ctx, ids4, b4, out4)
+            rooflines["cfg4_adjoint"] = roofline_entry(ops4, r["backward_kernel_ms"], "collide_bwd",
+                                                       r["backward_launches"], note=ADJOINT_NOTE)
+            rooflines["cfg4_adjoint"].update(win)
             del a4, bb4
         legs_cfg4 = dict(workload=f"uneven_scenes: {b4.n_scenes} scenes, geometric pairs/scene (mean 12, clip "
                                   f"[1,64]), polytopes of 8-256 points on random ellipsoids, 20% analytic, 30% forced "
@@ -666,9 +739,10 @@ def main():
                 res = timer.run(lambda: fwd_bwd(db2, out2, b2.tau, b2.K, a2, bb2, presel=presel), 1, 2)
                 r = record(name, res, int(out2.n_pairs.item()), cap2)
                 if presel is None:
-                    ops2 = config_ops(ctx, ids2, b2, out2)
-                    rooflines["cfg2_adjoint"] = roofline_entry(opmodel.reverse_ops(ops2), r["backward_kernel_ms"],
-                                                               "collide_bwd", r["backward_launches"])
+                    ops2, win = adjoint_ops(ctx, ids2, b2, out2)
+                    rooflines["cfg2_adjoint"] = roofline_entry(ops2, r["backward_kernel_ms"], "collide_bwd",
+                                                               r["backward_launches"], note=ADJOINT_NOTE)
+                    rooflines["cfg2_adjoint"].update(win)
         del db2, out2, a2, bb2
         torch.cuda.empty_cache()
     # ------------------------------------------------------------ cfg 1 cube pairs

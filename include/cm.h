@@ -276,15 +276,16 @@ cm_status cm_collide_fused(cm_context* ctx, const cm_batch* batch, const cm_para
                            void* stream);
 /* The fused path's autotuner: pairs fall in 3 size classes by the larger edge
  * count of their bodies (<= 96, <= 300, above), each with its own LDS sizing
- * and persistent grid.  Once per (geometry set, K) the first
- * cm_collide_fused call classifies its batch, times each class's kernel at
+ * and persistent grid.  Once per (geometry set, K, batch-size bucket: one
+ * per factor of 4 in candidate pairs) the first cm_collide_fused call
+ * classifies its batch, times each class's kernel at
  * 256-, 128- and 64-thread blocks (those that keep at least 2 waves per
  * SIMD; 256 always) on the same evenly strided sample of the class's cost
  * order (about 1/16 of its pairs) and keeps the fastest; the
  * choice is stored in the text file named by CM_TUNE_CACHE (default
  * $HOME/.cache/cm_fused_tune.txt), keyed by device architecture, CU count
- * and the class's largest vertex / edge / face counts and K, and read back
- * by later processes instead of timing.  cm_fused_tuning reports the current
+ * the class's largest vertex / edge / face counts, K and the batch-size
+ * bucket, and read back by later processes instead of timing.  cm_fused_tuning reports the current
  * plan: per class (arrays of 3, any may be NULL) the largest edge count, the
  * block size, the sample size, the sample timings in ms at 256, 128 and 64
  * ([3][3], 0 when not timed) and whether the choice came from the cache.
@@ -350,7 +351,17 @@ cm_status cm_collide_backward(cm_context* ctx, const cm_batch* batch, const cm_p
  * context, see above); pairs whose windows do not fit the pool are
  * recomputed whole by the backward.  A tape smaller than cm_tape_bytes(...,
  * 2, ...) or not 16-byte aligned: CM_ERR_INVALID_ARG.  cm_collide_noalloc
- * does not record one (CM_ERR_INVALID_ARG for a non-NULL tape). */
+ * does not record one (CM_ERR_INVALID_ARG for a non-NULL tape).
+ * Layout (for callers that inspect the windows): bytes [0, 256) hold the
+ * pool's fill counter (uint64 at 0); kept pair p's record starts at byte
+ * 256 + p (16 + 80 K): int32 count of its window's candidates, int32 form
+ * (0: not recorded, the pool was full; 1: ascending int32 candidate indices;
+ * 2: one bit per candidate, bit i & 63 of uint64 word i >> 6), int64 offset
+ * of that list or mask in the pool in 4-byte entries, float64 s_[1..K], then
+ * the float64 SoftSort row sums [K][9]; the pool starts at byte 256 +
+ * (capacity (16 + 80 K) rounded up to a multiple of 256).  Candidate indices
+ * follow the order A's vertices, B's vertices, then edge pairs (k, l)
+ * row-major with witness 1 before witness 2. */
 cm_status cm_tape_bytes(cm_context* ctx, int32_t capacity, int32_t K, int64_t pool_entries, int64_t* bytes);
 
 /* ---------------------------------------------------------------- E-E witness points

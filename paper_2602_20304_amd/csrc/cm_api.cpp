@@ -690,7 +690,18 @@ extern "C" cm_status cm_collide_backward(cm_context* ctx, const cm_batch* batch,
   if (lds > 160 * 1024)
     return cm_fail(ctx, CM_ERR_INVALID_ARG, "the context's largest geometry needs " + std::to_string(lds) +
                                                 " B of LDS for this adjoint (160 KiB per workgroup)");
-  b.f.grid = std::max(1, bwd_occupancy(b) * ctx->num_cus);
+  int occ = bwd_occupancy(b);
+  // When LDS holds one 256-thread workgroup per CU (one wave per SIMD), a
+  // 512-thread one brings two waves per SIMD to the same LDS (the full
+  // method on the basic primitives has that variant)
+  if (pd.presel_v == 0 && !pd.sq && pd.refine == 0 &&
+      bwd_lds_bytes(b.f.maxV, b.f.maxE, b.f.maxF, 512, false) <= 160 * 1024) {
+    BwdLaunch b5 = b;
+    b5.f.block = 512;
+    const int occ5 = bwd_occupancy(b5);
+    if (occ5 * 8 > occ * 4) { b = b5; occ = occ5; }
+  }
+  b.f.grid = std::max(1, occ * ctx->num_cus);
   if (b.f.grid > od.capacity) b.f.grid = std::max(1, od.capacity);
   b.f.scratch_stride = fwd_scratch_floats(b.f.maxV, b.f.maxE);
   // The adjoint's tape: the forward kernel (at its own occupancy) records per

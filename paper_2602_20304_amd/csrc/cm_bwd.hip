@@ -856,6 +856,12 @@ static int bwd_occ_refine(const BwdLaunch& b) {
 // lane: <= 4096 per set).
 hipError_t launch_collide_bwd(const BwdLaunch& b, hipStream_t st) {
   const bool ps = b.f.prm.presel_v > 0, sq = b.f.prm.sq != 0;
+  if (b.f.block == 512) {   // the full method on the basic primitives only
+    if (ps || sq || b.f.prm.refine > 0) return hipErrorInvalidValue;
+    if (b.f.kmax == 8) return launch_bwd_t<512, 8, false, false>(b, st);
+    if (b.f.kmax == 16) return launch_bwd_t<512, 16, false, false>(b, st);
+    return launch_bwd_t<512, 32, false, false>(b, st);
+  }
   if ((ps || sq || b.f.prm.refine > 0) && (b.f.maxV > 4096 || b.f.maxE > 4096)) return hipErrorInvalidValue;
   if (b.f.prm.refine > 0) {
     if (b.f.kmax > 16) return hipErrorInvalidValue;
@@ -868,6 +874,12 @@ hipError_t launch_collide_bwd(const BwdLaunch& b, hipStream_t st) {
 
 int bwd_occupancy(const BwdLaunch& b) {
   const bool ps = b.f.prm.presel_v > 0, sq = b.f.prm.sq != 0;
+  if (b.f.block == 512) {
+    if (ps || sq || b.f.prm.refine > 0) return 1;
+    if (b.f.kmax == 8) return bwd_occ_t<512, 8, false, false>(b);
+    if (b.f.kmax == 16) return bwd_occ_t<512, 16, false, false>(b);
+    return bwd_occ_t<512, 32, false, false>(b);
+  }
   if (b.f.prm.refine > 0) {
     if (sq) return ps ? bwd_occ_refine<true, true>(b) : bwd_occ_refine<false, true>(b);
     return ps ? bwd_occ_refine<true, false>(b) : bwd_occ_refine<false, false>(b);

@@ -61,6 +61,7 @@ struct cm_context {
   int servers = 0;             // live servers (geometry is frozen while > 0)
   int plan_K = -1, plan_version = -1;
   bool plan_tuned = false;
+  int plan_scale = -1;         // batch-size bucket the block sizes were tuned for
   int cls_maxE[3] = {0, 0, 0}, cls_maxV[3] = {0, 0, 0}, cls_maxF[3] = {0, 0, 0}, cls_block[3] = {256, 256, 256};
   int cls_bound[2] = {96, 300};
   float cls_tuned_ms[3][kTuneBlocks] = {};   // autotune sample timings (kTuneBlock order), 0 = not timed

@@ -83,11 +83,20 @@ std::string tune_path() {
   return std::string();
 }
 
-std::string tune_key(const cm_context* ctx, int c, int kmax) {
+std::string tune_key(const cm_context* ctx, int c, int kmax, int scale) {
   std::ostringstream k;
   k << ctx->arch << ":cu" << ctx->num_cus << ":E" << ctx->cls_maxE[c] << ":V" << ctx->cls_maxV[c] << ":F"
-    << ctx->cls_maxF[c] << ":k" << kmax;
+    << ctx->cls_maxF[c] << ":k" << kmax << ":n" << scale;
   return k.str();
+}
+
+// Batch-size bucket of a tuning: floor(log2(candidate pairs)) / 2, one bucket
+// per factor of 4 (a block size that wins on a few thousand pairs need not
+// win on millions).
+int tune_scale(int capacity) {
+  int l = 0;
+  while ((2LL << l) <= (long long)capacity) ++l;
+  return l / 2;
 }
 
 int tune_lookup(const std::string& key) {
@@ -194,11 +203,12 @@ extern "C" cm_status cm_collide_fused(cm_context* ctx, const cm_batch* batch, co
   // least 4 pairs per workgroup of the larger grid) and the fastest is kept
   // (full-method calls on the basic primitives only: pre-selection and the
   // extended primitives always run 256-thread blocks).
-  if (!ctx->plan_tuned && od.capacity > 0 && pd.presel_v == 0 && !pd.sq) {
+  const int scale = tune_scale(od.capacity);
+  if ((!ctx->plan_tuned || ctx->plan_scale != scale) && od.capacity > 0 && pd.presel_v == 0 && !pd.sq) {
     const int kmax = kmax_for(pd.K);
     bool all_cached = true;
     for (int c = 0; c < kNumClasses; ++c) {
-      const int b = tune_lookup(tune_key(ctx, c, kmax));
+      const int b = tune_lookup(tune_key(ctx, c, kmax, scale));
       ctx->cls_cached[c] = b;
       ctx->cls_block[c] = b ? b : 256;
       all_cached &= b != 0;
@@ -260,13 +270,14 @@ extern "C" cm_status cm_collide_fused(cm_context* ctx, const cm_batch* batch, co
           if (ms < best) { best = ms; best_block = kTuneBlock[bi]; }
         }
         ctx->cls_block[c] = best_block;
-        if (s == CM_OK) tune_store(tune_key(ctx, c, kmax), best_block);
+        if (s == CM_OK) tune_store(tune_key(ctx, c, kmax, scale), best_block);
       }
       (void)hipEventDestroy(e0);
       (void)hipEventDestroy(e1);
       if (s != CM_OK) return s;
     }
     ctx->plan_tuned = true;
+    ctx->plan_scale = scale;
   }
   if ((s = plan_scratch()) != CM_OK) return s;
 

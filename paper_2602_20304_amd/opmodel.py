@@ -92,6 +92,54 @@ def reverse_ops(forward: np.ndarray) -> np.ndarray:
     return np.array([2 * fma, fma + 2 * alu + trans, 0], dtype=np.int64)
 
 
+def _reverse(ops: np.ndarray) -> np.ndarray:
+    """Reverse sweep of a forward count, as in reverse_ops (linear in the count)."""
+    fma, alu, trans = (int(x) for x in ops)
+    return np.array([2 * fma, fma + 2 * alu + trans, 0], dtype=np.int64)
+
+
+def adjoint_pair_ops(kA: int, vA: int, eA: int, fA: int, kB: int, vB: int, eB: int, fB: int,
+                     w_vsA: int, w_vsB: int, w_ee: int) -> np.ndarray:
+    """(fma, alu, trans) the adjoint kernel's method does for one pair whose
+    adjoint window (candidates within 18 tau of s_[K], recorded by the
+    forward) holds w_vsA / w_vsB vertex-SDF candidates of A's / B's vertices
+    and w_ee edge-edge witnesses: each window candidate is evaluated again
+    (its QP from the distance pass's solution, its SDF queries) and swept in
+    reverse; the distance pass (the QP of every edge pair) and the row /
+    column LSE terms are recomputed, and the LSE terms swept in reverse.  The
+    QP adjoints of the nearest-neighbour phase (edge pairs whose row or column
+    softmax weight exceeds e^-28) are not counted: a lower bound."""
+    vs_a = sdf_cost(kB, fB, True, True) + _VS
+    vs_b = sdf_cost(kA, fA, True, False) + _VS
+    ee = (_QP + _WITNESS + _INDICATORS + _NN_LSE
+          + sdf_cost(kB, fB, False, True) + sdf_cost(kA, fA, True, False)
+          + sdf_cost(kA, fA, False, False) + sdf_cost(kB, fB, True, True))
+    visited = w_vsA * vs_a + w_vsB * vs_b + w_ee * ee
+    nn = eA * eB * _NN_LSE
+    return visited + _reverse(visited) + eA * eB * (_QP + _NN_LSE) + _reverse(nn)
+
+
+def adjoint_batch_ops(types, nv, ne, nf, pairs_a, pairs_b, body_geom, w_vsA, w_vsB, w_ee) -> np.ndarray:
+    """adjoint_pair_ops summed over kept pairs (per-pair window counts given)."""
+    ga = body_geom[pairs_a]
+    gb = body_geom[pairs_b]
+    tot = np.zeros(3, dtype=np.int64)
+    keys, inv = np.unique(np.stack([ga, gb]), axis=1, return_inverse=True)
+    inv = inv.reshape(-1)
+    cnt = np.bincount(inv, minlength=keys.shape[1])
+    sa = np.bincount(inv, weights=w_vsA, minlength=keys.shape[1]).astype(np.int64)
+    sb = np.bincount(inv, weights=w_vsB, minlength=keys.shape[1]).astype(np.int64)
+    se = np.bincount(inv, weights=w_ee, minlength=keys.shape[1]).astype(np.int64)
+    for j, (x, y) in enumerate(keys.T):
+        # linear in the window counts and in the pair count
+        base = adjoint_pair_ops(types[x], nv[x], ne[x], nf[x], types[y], nv[y], ne[y], nf[y], 0, 0, 0)
+        per = adjoint_pair_ops(types[x], nv[x], ne[x], nf[x], types[y], nv[y], ne[y], nf[y], 1, 0, 0) - base
+        per_b = adjoint_pair_ops(types[x], nv[x], ne[x], nf[x], types[y], nv[y], ne[y], nf[y], 0, 1, 0) - base
+        per_e = adjoint_pair_ops(types[x], nv[x], ne[x], nf[x], types[y], nv[y], ne[y], nf[y], 0, 0, 1) - base
+        tot += cnt[j] * base + sa[j] * per + sb[j] * per_b + se[j] * per_e
+    return tot
+
+
 # MI355X (gfx950): 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz
 VALU_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9      # full-rate lane operations per second
 TRANS_SLOT_COST = 4                            # transcendental ops issue at a quarter rate

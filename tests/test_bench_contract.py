@@ -43,3 +43,38 @@ def test_committed_traffic_summaries_are_parsable():
         assert re.search(r"source_hash:\s*[0-9a-f]{16}", txt), path
         m = re.search(key + r":\s*([0-9.eE+]+)", txt)
         assert m and float(m.group(1)) > 0, (path, key)
+
+
+def test_tape_window_decoding():
+    """The adjoint-window split the bench prices the adjoint with, decoded
+    from a tape laid out as include/cm.h documents: a pair recorded as
+    indices, one as a bit mask and one not recorded."""
+    import numpy as np
+    import torch
+    from types import SimpleNamespace
+    K, cap = 8, 4
+    stride = 16 + 80 * K
+    hdr = (cap * stride + 255) // 256 * 256
+    nvA = np.array([10, 6, 5])
+    nvB = np.array([8, 4, 5])
+    lists = [np.array([1, 9, 10, 17, 18, 40, 41]), None, None]        # pair 0: 2 of A, 2 of B, 3 E-E
+    ncand1 = 6 + 4 + 2 * 20
+    bits1 = np.zeros(64 * ((ncand1 + 63) // 64), np.uint8)
+    bits1[[0, 5, 6, 9, 10, 11, 12, 30, 31]] = 1                         # pair 1: 2 of A, 2 of B, 5 E-E
+    mask_words = np.packbits(bits1, bitorder="little").view(np.uint64)
+    pool = np.zeros(64, np.int32)
+    pool[0:7] = lists[0]
+    pool[8:8 + 2 * len(mask_words)] = mask_words.view(np.int32)
+    buf = np.zeros(256 + hdr + 4 * pool.size, np.uint8)
+    buf[0:8] = np.array([8 + 2 * len(mask_words)], np.uint64).view(np.uint8)
+    for p, (cnt, form, off) in enumerate(((7, 1, 0), (9, 2, 8), (5, 0, 0))):
+        rec = 256 + p * stride
+        buf[rec:rec + 8] = np.array([cnt, form], np.int32).view(np.uint8)
+        buf[rec + 8:rec + 16] = np.array([off], np.int64).view(np.uint8)
+    buf[256 + hdr:] = pool.view(np.uint8)
+    out = SimpleNamespace(K=K, capacity=cap, n_pairs=torch.tensor([3], dtype=torch.int32),
+                          tape=torch.from_numpy(buf))
+    w_a, w_b, w_e = bench.tape_windows(out, nvA, nvB)
+    assert w_a.tolist() == [2, 2, 0]
+    assert w_b.tolist() == [2, 2, 0]
+    assert w_e.tolist() == [3, 5, 5]
