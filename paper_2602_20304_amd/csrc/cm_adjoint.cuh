@@ -35,10 +35,22 @@ __device__ __forceinline__ double4 unscaled(const double4& q, const Temp& T) {
   return make_double4(q.x * T.tl, q.y * T.tl, q.z * T.tl, q.w * T.tl);
 }
 
-// Wave sum of a float (all 64 lanes must participate).
-__device__ __forceinline__ float wave_sumf(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+// Wave sum of a float into lane 63 (all 64 lanes must participate), with
+// DPP moves only (no LDS permutes): pairs and quads (quad_perm), the two
+// halves of each row of 16 lanes (row_half_mirror, row_mirror), then the row
+// broadcasts: lane 15 of rows 0 / 2 into rows 1 / 3, lane 31 into rows 2, 3.
+// The other lanes end with partial sums.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_add(float x) {
+  return x + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROWS, 0xf, false));
+}
+__device__ __forceinline__ float wave_sum_last(float v) {
+  v = dpp_add<0xb1, 0xf>(v);    // quad_perm [1, 0, 3, 2]
+  v = dpp_add<0x4e, 0xf>(v);    // quad_perm [2, 3, 0, 1]
+  v = dpp_add<0x141, 0xf>(v);   // row_half_mirror
+  v = dpp_add<0x140, 0xf>(v);   // row_mirror
+  v = dpp_add<0x142, 0xa>(v);   // row_bcast:15 into rows 1, 3
+  v = dpp_add<0x143, 0xc>(v);   // row_bcast:31 into rows 2, 3
   return v;
 }
 
@@ -197,7 +209,7 @@ struct BodySink {
 // Adjoint of the body-frame SDF query (phi, g) at l given (phi_bar, g_bar).
 // Returns l_bar; accumulates parameter / plane adjoints and tau_bar.
 // WAVE: all 64 lanes execute this call together (plane adjoints are summed
-// across the wave before one atomic per plane).
+// across the wave, into lane 63, before one atomic per plane).
 // SQ: superquadric unions are handled (kernels built for contexts holding
 // them); ndir: the gradient output g_bar refers to is their V-S normal
 // direction.  Their record adjoints are not accumulated (no geometry
@@ -306,8 +318,8 @@ __device__ __forceinline__ D3 sdf_local_bwd(int type, const float* p, const doub
       float v0 = float(yb * l.x + pi * gb.x), v1 = float(yb * l.y + pi * gb.y), v2 = float(yb * l.z + pi * gb.z),
             v3 = float(-yb);
       if (WAVE) {
-        v0 = wave_sumf(v0); v1 = wave_sumf(v1); v2 = wave_sumf(v2); v3 = wave_sumf(v3);
-        if ((threadIdx.x & 63) == 0) {
+        v0 = wave_sum_last(v0); v1 = wave_sum_last(v1); v2 = wave_sum_last(v2); v3 = wave_sum_last(v3);
+        if ((threadIdx.x & 63) == 63) {
           atomicAdd(&sink.plane[f], v0); atomicAdd(&sink.plane[sink.maxF + f], v1);
           atomicAdd(&sink.plane[2 * sink.maxF + f], v2); atomicAdd(&sink.plane[3 * sink.maxF + f], v3);
         }
