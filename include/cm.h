@@ -355,8 +355,10 @@ cm_status cm_collide_backward(cm_context* ctx, const cm_batch* batch, const cm_p
  * Layout (for callers that inspect the windows): bytes [0, 256) hold the
  * pool's fill counter (uint64 at 0); kept pair p's record starts at byte
  * 256 + p (16 + 80 K): int32 count of its window's candidates, int32 form
- * (0: not recorded, the pool was full; 1: ascending int32 candidate indices;
- * 2: one bit per candidate, bit i & 63 of uint64 word i >> 6), int64 offset
+ * (0: not recorded, the pool was full; 1: int32 candidate indices in three
+ * runs, each ascending: the vertex-SDF candidates, the edge-edge witnesses 1,
+ * the witnesses 2; 2: one bit per candidate, bit i & 63 of uint64 word
+ * i >> 6), int64 offset
  * of that list or mask in the pool in 4-byte entries, float64 s_[1..K], then
  * the float64 SoftSort row sums [K][9]; the pool starts at byte 256 +
  * (capacity (16 + 80 K) rounded up to a multiple of 256).  Candidate indices

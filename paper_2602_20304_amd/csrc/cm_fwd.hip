@@ -207,8 +207,7 @@ void collide_fwd(Tables tb, BatchDev bt, ParamsDev prm, OutDev out,
         const long long start = ps.tape_off;
         if (start >= 0) {
           if (as_mask) P.window_mask(kAdjointTaus, reinterpret_cast<unsigned long long*>(tape.pool + start));
-          else
-            for (int p = tid; p < tot; p += BLOCK) tape.pool[start + p] = P.list_at(p);
+          else P.write_window_runs(tot, tape.pool + start);
         }
       }
       // outputs: divide by row sums, rotate to world

@@ -9,7 +9,8 @@ namespace cm {
 // Per-pair record the forward kernel leaves for the adjoint (the adjoint's
 // tape), tape_stride(K) bytes per kept pair: int32 count of the candidates
 // within the adjoint's window, int32 form (0: none recorded, the pool was
-// full; 1: their indices, int32 ascending; 2: a mask of one bit per
+// full; 1: their indices, int32, in three ascending runs: vertex-SDF
+// candidates, edge-edge witnesses 1, witnesses 2; 2: a mask of one bit per
 // candidate, 64-bit words), int64 offset of that list or mask in the pool
 // (4-byte entries), then the K top scores s_[k] and the K x 9 SoftSort row
 // sums (float64).  Each pair takes the smaller form, carved from the pool by

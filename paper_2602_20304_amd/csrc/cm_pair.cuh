@@ -747,6 +747,50 @@ struct PairEngine {
       if (lane == 0) mask[b >> 6] = ball;
     }
   }
+  // Writes the window compacted by window() (tot candidates) to dst in three
+  // runs, each in candidate order: the vertex-SDF candidates, the edge-edge
+  // witnesses 1, the witnesses 2.  Waves of the adjoint that take one run
+  // then need one penetration query adjoint instead of both.  Uses sRed.
+  __device__ __forceinline__ void write_window_runs(int tot, int* __restrict__ dst) {
+    int* cnt = reinterpret_cast<int*>(sRed);   // [3][NW] per-wave counts of a chunk
+    int* run = cnt + 3 * NW;                   // [3] run sizes
+    const int nvs = ps.nvs;
+    auto cls_of = [&](int idx) __attribute__((always_inline)) { return idx < nvs ? 0 : (((idx - nvs) & 1) ? 2 : 1); };
+    if (tid < 3) run[tid] = 0;
+    __syncthreads();
+    for (int base = 0; base < tot; base += BLOCK) {
+      const int p = base + tid;
+      const int c = p < tot ? cls_of(list_at(p)) : 3;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const unsigned long long b = __ballot(c == k);
+        if (lane == 0 && b) atomicAdd(&run[k], __popcll(b));
+      }
+    }
+    __syncthreads();
+    int off[3] = {0, run[0], run[0] + run[1]};
+    __syncthreads();
+    for (int base = 0; base < tot; base += BLOCK) {
+      const int p = base + tid;
+      const int idx = p < tot ? list_at(p) : 0;
+      const int c = p < tot ? cls_of(idx) : 3;
+      unsigned long long b[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) b[k] = __ballot(c == k);
+      if (lane == 0)
+        for (int k = 0; k < 3; ++k) cnt[k * NW + wave] = __popcll(b[k]);
+      __syncthreads();
+      if (c < 3) {
+        int before = 0;
+        for (int w = 0; w < wave; ++w) before += cnt[c * NW + w];
+        dst[off[c] + before + __popcll(b[c] & ((1ull << lane) - 1ull))] = idx;
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        for (int w = 0; w < NW; ++w) off[k] += cnt[k * NW + w];
+      __syncthreads();
+    }
+  }
   // Candidate index at position p (< window's count) of the compacted list.
   __device__ __forceinline__ int list_at(int p) const {
     // the wave region holding list position p: the last wave whose start is
