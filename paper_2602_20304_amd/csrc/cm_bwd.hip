@@ -192,6 +192,18 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SQ ? 1 : 
       P.topk(tk);
       P.softsort();
     }
+    // A1 and A2 visit the window as three runs (vertex candidates, witnesses
+    // 1, witnesses 2): a recorded list already is; a recorded mask, or the
+    // scores just recomputed, are compacted once here and written in runs
+    // over the stored scores, which nothing reads after this
+    if (!tlist) {
+      const int tot = P.window(kAdjointTaus, tmask);
+      int* runs = reinterpret_cast<int*>(P.Sbuf);
+      P.write_window_runs(tot, runs);
+      tlist = runs;
+      ntape = tot;
+      tmask = nullptr;
+    }
 
     // ------------------------------------------------ cotangents in the pair frame
     if (tid < K) {
