@@ -27,7 +27,7 @@
 namespace cm {
 
 struct BwdLds {
-  int vA, vB, plA, plB, prm, rbar, cbar, cot, F, top, best, tw, sv, se, si, mb, sk, bytes;
+  int vA, vB, plA, plB, prm, rbar, cbar, cot, F, top, best, bt, tw, sv, se, si, mb, sk, bytes;
 };
 
 // presel: the selection adjoint's arrays follow (soft vertex adjoints
@@ -49,6 +49,8 @@ __host__ __device__ inline BwdLds bwd_layout(int base, int maxV, int maxE, int m
   L.F = o; o += 8 * 10 * CM_MAX_K;     // normalised row outputs (8) + Z + Gbar
   L.top = o; o += 8 * CM_MAX_K;        // adjoint of s_[k]
   L.best = o; o += 4 * (CM_MAX_K + block);
+  o = (o + 7) & ~7;
+  L.bt = o; o += 8 * block;            // A1: each slice's own term of its nearest candidate
   L.tw = o; o += 8 * 8;                // output twist terms
   L.sv = L.se = L.si = L.mb = L.sk = o;
   if (presel) {
@@ -106,6 +108,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SQ ? 1 : 
   double* Fk = reinterpret_cast<double*>(smem + L.F);
   double* topb = reinterpret_cast<double*>(smem + L.top);
   int* bestI = reinterpret_cast<int*>(smem + L.best);
+  double* btl = reinterpret_cast<double*>(smem + L.bt);
   double* twOut = reinterpret_cast<double*>(smem + L.tw);
   float* svb = reinterpret_cast<float*>(smem + L.sv);   // PRESEL: soft vertex adjoints
   float* seb = reinterpret_cast<float*>(smem + L.se);   // PRESEL: soft edge endpoint adjoints
@@ -252,7 +255,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SQ ? 1 : 
     {
       const int kk = tid % K, nsl = BLOCK / K, sl = tid / K;
       const bool act = sl < nsl;
-      double sbp = 0.0, best = INFINITY;
+      double sbp = 0.0, best = INFINITY, bterm = 0.0;
       int bidx = 0x7fffffff;
       P.for_window(tlist, ntape, tmask, [&](int tot) {
         if (!act) return;
@@ -269,26 +272,31 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SQ ? 1 : 
           for (int f = 0; f < 8; ++f) gi += c[f] * fv[f];
           const double ab = G * (gi - F[9]);
           const double sg = dl > 0.0 ? 1.0 : (dl < 0.0 ? -1.0 : 0.0);
-          sbp -= ab * sg * T.inv_tau;
+          const double term = -ab * sg * T.inv_tau;
+          sbp += term;
           taub += ab * fabs(dl) * T.inv_tau * T.inv_tau;
-          if (fabs(dl) < best || (fabs(dl) == best && R.idx < bidx)) { best = fabs(dl); bidx = R.idx; }
+          if (fabs(dl) < best || (fabs(dl) == best && R.idx < bidx)) { best = fabs(dl); bidx = R.idx; bterm = term; }
         }
       }, kAdjointTaus);
       P.sRed[tid] = act ? sbp : 0.0;
       P.sRed[BLOCK + tid] = act ? best : INFINITY;
       bestI[CM_MAX_K + tid] = act ? bidx : 0x7fffffff;
+      btl[tid] = act ? bterm : 0.0;
       __syncthreads();
       if (tid < K) {
-        double s = 0.0, b = INFINITY;
+        double s = 0.0, b = INFINITY, bt = 0.0;
         int bi = 0x7fffffff;
         for (int q = 0; q < nsl; ++q) {
           const int t = q * K + tid;
           s += P.sRed[t];
           const double v = P.sRed[BLOCK + t];
           const int vi = bestI[CM_MAX_K + t];
-          if (v < b || (v == b && vi < bi)) { b = v; bi = vi; }
+          if (v < b || (v == b && vi < bi)) { b = v; bi = vi; bt = btl[t]; }
         }
-        topb[tid] = s;
+        // s_[k] is the score of the candidate attaining it, whose own term
+        // |s_[k] - s_j| has derivative 0 there (|x|' = 0 at 0): left out here
+        // and in A2, so both sides agree however its score is recomputed
+        topb[tid] = s - bt;
         bestI[tid] = bi;
       }
       __syncthreads();
@@ -318,6 +326,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SQ ? 1 : 
     P.for_window(tlist, ntape, tmask, [&](int tot) {
       if (wave * 64 >= tot) return;        // whole wave idle (uniform)
       const bool live = tid < tot;
+      // the candidate's record as A1 evaluated it (the same scores, so that
+      // ties and the attaining candidates' signs agree with A1's)
       const Rec R = P.sRec[live ? tid : 0];
       double sb = 0.0;
       double fb[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -332,8 +342,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SQ ? 1 : 
           double gi = 0.0;
           for (int f = 0; f < 8; ++f) { gi += c[f] * fv[f]; fb[f] += G * c[f]; }
           const double ab = G * (gi - F[9]);
-          sb += ab * (dl > 0.0 ? 1.0 : (dl < 0.0 ? -1.0 : 0.0)) * T.inv_tau;
-          if (bestI[k] == R.idx) sb += topb[k];
+          if (bestI[k] == R.idx) sb += topb[k];   // the attaining candidate: its own term is 0 (A1)
+          else sb += ab * (dl > 0.0 ? 1.0 : (dl < 0.0 ? -1.0 : 0.0)) * T.inv_tau;
         }
       }
       const int idx = R.idx;
@@ -383,7 +393,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SQ ? 1 : 
         k = ee_i / neB; l = ee_i - k * neB;
         P.EA.get(k, a0, t1);
         P.EB.get(l, b0, t2);
-        const EEQP q = ee_qp(a0, t1, b0, t2, P.lam, T);
+        // the QP solution the distance pass stored for this edge pair
+        const EEQP q = ee_from_alpha(a0, t1, b0, t2, P.Al1[ee_i], P.Al2[ee_i], P.Lcon[ee_i]);
         al1 = q.al1; al2 = q.al2; de = q.de;
         D3 e1 = axpy(al1, t1, a0), e2 = axpy(al2, t2, b0);
         if (REFINE) {   // each witness traced onto its own body

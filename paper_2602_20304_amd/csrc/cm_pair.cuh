@@ -820,10 +820,13 @@ struct PairEngine {
   // candidate record per thread in sRec, and body(n) runs with all threads
   // after a barrier for each chunk of n records.  The forward may have
   // recorded the same window: ntape >= 0 indices at lst, or else a mask
-  // (device memory); otherwise the stored scores are scanned.
+  // (device memory); otherwise the stored scores are scanned.  full = false:
+  // only the records' candidate indices are written (a body that evaluates
+  // the candidates itself).
   template <typename F>
   __device__ __forceinline__ void for_window(const int* __restrict__ lst, int ntape,
-                                             const unsigned long long* __restrict__ mask, F&& body, double taus) {
+                                             const unsigned long long* __restrict__ mask, F&& body, double taus,
+                                             bool full = true) {
     const int tot = ntape >= 0 ? ntape : window(taus, mask);
     if (ntape < 0 && tot == 0) __syncthreads();   // sCnt is rewritten by the next call
     for (int base = 0; base < tot; base += BLOCK) {
@@ -831,7 +834,8 @@ struct PairEngine {
       if (p < tot) {
         int idx = ntape >= 0 ? lst[p] : list_at(p);
         if (idx < 0 || idx >= ps.ncand) idx = 0;   // a recorded list holds valid indices; never read past the pair
-        record(idx);
+        if (full) record(idx);
+        else sRec[tid].idx = idx;
       }
       __syncthreads();
       body(min(BLOCK, tot - base));
