@@ -309,7 +309,12 @@ __device__ __forceinline__ D3 sdf_local_bwd(int type, const float* p, const doub
   for (int f = 0; f < nf; ++f) {
     const double4 q = unscaled(pl[f], T);
     const double yv = fma(q.x, l.x, fma(q.y, l.y, fma(q.z, l.z, -q.w)));
-    const double pi = double(ex2f(float((yv - m) * T.c))) * iS;
+    const double a = (yv - m) * T.c;
+    // a face whose softmax weight is below 2^-40 for every lane of the wave
+    // (or every active lane) adds nothing the float32 sums could hold: skipped
+    // together (wave-uniform, so the wave sums below stay whole-wave)
+    if (!__any(a > -40.0)) continue;
+    const double pi = double(ex2f(float(a))) * iS;
     const double zb = pi * (gb.x * q.x + gb.y * q.y + gb.z * q.z - gbg);   // softmax adjoint of g
     const double yb = phib * pi + zb * T.inv_tau;
     tz += zb * yv;
