@@ -86,7 +86,8 @@ struct BwdArgs {
 template <int BLOCK, int KMAX, bool PRESEL, bool SQ, bool REFINE = false>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SQ ? 1 : 2))) void collide_bwd(Tables tb, BatchDev bt, ParamsDev prm, OutDev fwd, BwdArgs ga,
                                                      float* __restrict__ scratch, long long scratch_stride, int maxV,
-                                                     int maxE, int maxF, unsigned* err, TapeDev tape) {
+                                                     int maxE, int maxF, unsigned* err, TapeDev tape,
+                                                     int* __restrict__ queue) {
   extern __shared__ float4 smem4[];
   char* smem = reinterpret_cast<char*>(smem4);
   __shared__ PairShared ps;
@@ -124,7 +125,16 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SQ ? 1 : 
   const int n_pairs = min(*fwd.n_pairs, fwd.capacity);
   const long long CK = (long long)fwd.capacity * K;
 
-  for (int pi = blockIdx.x; pi < n_pairs; pi += gridDim.x) {
+  // pairs from a work queue (an atomic counter, zeroed by the launch) when
+  // given, so workgroups that drew cheap pairs take more; else round-robin
+  for (int it = 0;; ++it) {
+    int pi = blockIdx.x + it * gridDim.x;
+    if (queue) {
+      if (tid == 0) ps.next = atomicAdd(queue, 1);
+      __syncthreads();
+      pi = ps.next;
+    }
+    if (pi >= n_pairs) break;
     if (!P.setup(fwd.pairs[pi], fwd.pairs[fwd.capacity + pi], err)) {
       __syncthreads();
       continue;
@@ -834,7 +844,7 @@ static hipError_t launch_bwd_t(const BwdLaunch& b, hipStream_t st) {
   BwdArgs ga{b.cot, b.gr};
   hipLaunchKernelGGL((collide_bwd<BLOCK, KMAX, PRESEL, SQ, REFINE>), dim3(b.f.grid), dim3(BLOCK), lds, st, b.f.tb, b.f.bt,
                      b.f.prm, b.f.out, ga, b.f.scratch, b.f.scratch_stride, b.f.maxV, b.f.maxE, b.f.maxF, b.f.err,
-                     b.f.tape);
+                     b.f.tape, b.f.queue);
   return hipGetLastError();
 }
 

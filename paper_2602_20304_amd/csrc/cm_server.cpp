@@ -275,6 +275,7 @@ void launch_request(cm_server* srv, Request& r) {
     }
     BwdLaunch b;
     b.f = f;
+    b.f.queue = nullptr;   // the forward's queue is spent: pairs round-robin
     b.cot = CotDev{d_cp, d_cn, d_cd, d_cw};
     b.gr = GradDev{d_gpose, d_gvert, d_gpar, d_gtau, (long long)r.pool};
     b.f.grid = int(std::min<long long>(request_grid(ctx, bwd_occupancy(b), cap), f.grid));   // fits the forward's scratch
