@@ -530,7 +530,7 @@ def main():
     ap.add_argument("--serve", type=int, default=24, help="requests in the serving leg")
     ap.add_argument("--ee-trials", type=int, default=20, help="timed launches per size in the E-E sweep")
     ap.add_argument("--only", default=None,
-                    choices=[None, "cfg3_fused", "cfg3_plain", "cfg3_bwd", "cfg4_fused", "cfg4_plain", "cfg2_plain",
+                    choices=[None, "cfg3_fused", "cfg3_plain", "cfg3_bwd", "cfg4_fused", "cfg4_plain", "cfg4_bwd", "cfg2_plain",
                              "cfg2_fused", "cfg2_bwd", "cfg2_refine", "cfg2_all", "ee", "sq"],
                     help="run one leg only, without the headline and the other legs (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -660,7 +660,7 @@ def main():
         del a3, bb3
     # restore the headline manifold (tau 0.01) for anything that reads it
     # ------------------------------------------------------------ cfg 4 uneven batching
-    if (only in ("cfg4_fused", "cfg4_plain")) or (only is None and "4" in wanted and fits("cfg4", 150.0)):
+    if (only in ("cfg4_fused", "cfg4_plain", "cfg4_bwd")) or (only is None and "4" in wanted and fits("cfg4", 150.0)):
         del db3, out3
         new_context()
         t0 = time.perf_counter()
@@ -682,7 +682,7 @@ def main():
             ops4 = config_ops(ctx, ids4, b4, out4)
             rooflines["cfg4_plain_fwd"] = roofline_entry(ops4, r["forward_kernel_ms"], "collide_fwd (plain)",
                                                          r["forward_launches"])
-        if only is None and fits("cfg4_fused_fwd_bwd", 4.0 * est):
+        if only == "cfg4_bwd" or (only is None and fits("cfg4_fused_fwd_bwd", 4.0 * est)):
             a4, bb4 = loss_cotangents(cap4, b4.K, seed=4)
             res = timer.run(lambda: fwd_bwd(db4, out4, b4.tau, b4.K, a4, bb4, fused=True), 0, 1)
             r = record("cfg4_fused_fwd_bwd", res, int(out4.n_pairs.item()), cap4)

@@ -232,7 +232,8 @@ __device__ __forceinline__ D3 sdf_local_bwd(int type, const float* p, const doub
     return d3(o[0], o[1], o[2]);
   }
   if (type == CM_SPHERE) {
-    const double s = dot(l, l), n = sqrt(s), inv = s > 0.0 ? 1.0 / n : 0.0;
+    double n, inv;
+    sqrt_rsq64(dot(l, l), n, inv);
     const D3 g = scl(l, inv);
     g_out = g;
     const double gg = dot(g, gb);
@@ -243,7 +244,8 @@ __device__ __forceinline__ D3 sdf_local_bwd(int type, const float* p, const doub
     const double h = p[1];
     const double zc = fmin(fmax(l.z, -h), h);
     const D3 y = d3(l.x, l.y, l.z - zc);
-    const double s = dot(y, y), n = sqrt(s), inv = s > 0.0 ? 1.0 / n : 0.0;
+    double n, inv;
+    sqrt_rsq64(dot(y, y), n, inv);
     const D3 g = scl(y, inv);
     g_out = g;
     const D3 yb = add(scl(g, phib), scl(sub(gb, scl(g, dot(g, gb))), inv));
@@ -261,8 +263,9 @@ __device__ __forceinline__ D3 sdf_local_bwd(int type, const float* p, const doub
     const double gbv[3] = {gb.x, gb.y, gb.z};
     double qb[3] = {0.0, 0.0, 0.0};
     double rhob = -phib;
-    if (s > 0.0) {
-      const double n = sqrt(s), inv = 1.0 / n;
+    if (s > 0x1p-700) {
+      double n, inv;
+      sqrt_rsq64(s, n, inv);
       g_out = d3(sg[0] * m[0] * inv, sg[1] * m[1] * inv, sg[2] * m[2] * inv);
       // phi = |m| - rho ; g_i = sg_i m_i / |m|
       double sgb = 0.0;
@@ -298,7 +301,7 @@ __device__ __forceinline__ D3 sdf_local_bwd(int type, const float* p, const doub
     S += e; gx = fma(e, q.x, gx); gy = fma(e, q.y, gy); gz = fma(e, q.z, gz);
     py = fma(e, yv, py);
   }
-  const double iS = 1.0 / S;
+  const double iS = rcp64(S);   // S >= 1: the largest plane's term is 1
   const D3 g = d3(gx * iS, gy * iS, gz * iS);
   g_out = g;
   const double phi = m + T.tau * log(S);
@@ -436,9 +439,9 @@ __device__ __forceinline__ void ee_qp_bwd(const D3& a0, const D3& t1, const D3& 
   const double Q11 = dot(t1, t1) + lam, Q22 = dot(t2, t2) + lam, Q12 = -dot(t1, t2);
   const double hl = 0.5 * lam;
   const double c1 = dot(b, t1) - hl, c2 = -dot(b, t2) - hl;
-  const double det = Q11 * Q22 - Q12 * Q12, idet = 1.0 / det;
+  const double det = Q11 * Q22 - Q12 * Q12, idet = rcp64(det);   // as the forward QP
   const double au1 = (Q12 * c2 - c1 * Q22) * idet, au2 = (Q12 * c1 - c2 * Q11) * idet;
-  const double i11 = 1.0 / Q11, i22 = 1.0 / Q22;
+  const double i11 = rcp64(Q11), i22 = rcp64(Q22);
   const double xi[4] = {-(Q12 + c2) * i22, -c2 * i22, -(Q12 + c1) * i11, -c1 * i11};
   double x[4];
   for (int i = 0; i < 4; ++i) x[i] = clip01(xi[i], T);

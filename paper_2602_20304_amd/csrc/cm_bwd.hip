@@ -379,7 +379,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SQ ? 1 : 
         D3 g;
         if (ofA) sdf_body<kFull, false, true, SQ>(B, x, T, phi, g);
         else sdf_body<kFull, true, true, SQ>(A, x, T, phi, g);
-        const double q = T.tau + dot(g, g), in = 1.0 / sqrt(q);
+        const double in = rsq64(T.tau + dot(g, g));
         const double lw = lsig(-phi, T), w = exp(lw);
         const double dtot = fb[6] - sb, lwb = T.tau * sb + w * fb[7];
         taub += sb * lw;
@@ -415,9 +415,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SQ ? 1 : 
           de = sub(e1, e2);
         }
         const double dsq = dot(de, de);
-        dbar = sqrt(dsq);
+        double idum;
+        sqrt_rsq64(dsq, dbar, idum);
         const double dnn = REFINE ? dqp : dbar;   // the nearest-neighbour term's distance
-        rho = 1.0 / sqrt(dsq + P.eps_n);
+        rho = rsq64(dsq + P.eps_n);
         const D3 nb = scl(de, rho);
         double phiB1, phiA2, dum, phiA1 = 0.0, phiB2 = 0.0;
         D3 gA, gB, dg;

@@ -74,6 +74,25 @@ __device__ __forceinline__ double rcp64(double x) {
   return fma(r, e, r);
 }
 
+// 1/sqrt(x) in float64 for x well inside the normal range (as rcp64):
+// v_rsq_f64 plus two Newton steps r <- r (3/2 - x r^2 / 2), eight VALU
+// operations where sqrt and a division take about 28.
+__device__ __forceinline__ double rsq64(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  r = fma(r, fma(-h * r, r, 0.5), r);
+  r = fma(r, fma(-h * r, r, 0.5), r);
+  return r;
+}
+// sqrt(x) and 1/sqrt(x) for x >= 0 through rsq64; x at or below 2^-700 (a
+// length below 1e-105) gives 0 for both.
+__device__ __forceinline__ void sqrt_rsq64(double x, double& s, double& r) {
+  const bool pos = x > 0x1p-700;
+  const double y = rsq64(pos ? x : 1.0);
+  r = pos ? y : 0.0;
+  s = pos ? x * y : 0.0;
+}
+
 // a * b + c as one v_fma_f64 whose addend c is a wave-uniform constant in
 // scalar registers.  Written with fma(), the compiler picks the tied form
 // v_fmac_f64 (addend = destination) and first copies the coefficient into
@@ -173,18 +192,16 @@ __device__ __forceinline__ double dot(const D3& a, const D3& b) { return a.x * b
 // Body-frame SDF of an analytic primitive and its gradient.
 __device__ __forceinline__ void sdf_analytic(int type, const float* p, const D3& l, double& phi, D3& g) {
   if (type == CM_SPHERE) {
-    const double s = dot(l, l);
-    const double n = sqrt(s);
-    const double inv = s > 0.0 ? 1.0 / n : 0.0;
+    double n, inv;
+    sqrt_rsq64(dot(l, l), n, inv);
     phi = n - double(p[0]);
     g = d3(l.x * inv, l.y * inv, l.z * inv);
   } else if (type == CM_CAPSULE) {
     const double h = p[1];
     const double zc = fmin(fmax(l.z, -h), h);
     const D3 y = d3(l.x, l.y, l.z - zc);
-    const double s = dot(y, y);
-    const double n = sqrt(s);
-    const double inv = s > 0.0 ? 1.0 / n : 0.0;
+    double n, inv;
+    sqrt_rsq64(dot(y, y), n, inv);
     phi = n - double(p[0]);
     g = d3(y.x * inv, y.y * inv, y.z * inv);
   } else {  // rounded box: outer half-extents p[0..2], rounding p[3]
@@ -193,8 +210,9 @@ __device__ __forceinline__ void sdf_analytic(int type, const float* p, const D3&
                  qz = fabs(l.z) - (double(p[2]) - rr);
     const double mx = fmax(qx, 0.0), my = fmax(qy, 0.0), mz = fmax(qz, 0.0);
     const double s = mx * mx + my * my + mz * mz;
-    if (s > 0.0) {
-      const double n = sqrt(s), inv = 1.0 / n;
+    if (s > 0x1p-700) {
+      double n, inv;
+      sqrt_rsq64(s, n, inv);
       phi = n - rr;
       g = d3(sgn1(l.x) * mx * inv, sgn1(l.y) * my * inv, sgn1(l.z) * mz * inv);
     } else {
@@ -713,7 +731,8 @@ __device__ __forceinline__ void ee_candidates(const D3& a0, const D3& t1, const 
                                               Cand& c1, Cand& c2, bool safeguard = false, int steps = 0) {
   D3 e1 = d3(a0.x + q.al1 * t1.x, a0.y + q.al1 * t1.y, a0.z + q.al1 * t1.z);
   D3 e2 = d3(b0.x + q.al2 * t2.x, b0.y + q.al2 * t2.y, b0.z + q.al2 * t2.z);
-  const double dqp = sqrt(dot(q.de, q.de));   // the nearest-neighbour term's distance
+  double dqp, idum;   // dqp: the nearest-neighbour term's distance
+  sqrt_rsq64(dot(q.de, q.de), dqp, idum);
   D3 de = q.de;
   if (REFINE) {
     m1 = nullptr;
@@ -738,7 +757,7 @@ __device__ __forceinline__ void ee_candidates(const D3& a0, const D3& t1, const 
   }
   const double dsq = dot(de, de);
   const double dbar = REFINE ? sqrt(dsq) : dqp;
-  const double in = rcp64(sqrt(dsq + eps_n));
+  const double in = rsq64(dsq + eps_n);
   const D3 nb = d3(de.x * in, de.y * in, de.z * in);
   double phiB1, phiA2, dum;
   D3 gA, gB, dg;
@@ -777,7 +796,7 @@ __device__ __forceinline__ void vs_candidate(const D3& v, const BodyView& other,
   double phi;
   D3 g;
   sdf_body<kFull, OTHER_IS_A, true, SQ>(other, v, T, phi, g);
-  const double in = sgn * rcp64(sqrt(T.tau + dot(g, g)));
+  const double in = sgn * rsq64(T.tau + dot(g, g));
   c.p = v;
   c.n = d3(g.x * in, g.y * in, g.z * in);
   c.d = phi;

@@ -558,7 +558,9 @@ struct PairEngine {
         EA.get(k, a0, t1);
         EB.get(l, b0, t2);
         const EEQP q = ee_qp(a0, t1, b0, t2, lam, T);
-        Dbuf[idx] = sqrt(dot(q.de, q.de));
+        double dq, idum;
+        sqrt_rsq64(dot(q.de, q.de), dq, idum);   // as the candidates' nearest-neighbour distance
+        Dbuf[idx] = dq;
         Al1[idx] = q.al1;
         Al2[idx] = q.al2;
         Lcon[idx] = q.log_con;
