@@ -217,7 +217,8 @@ struct BodySink {
 template <bool WAVE, bool SQ = false>
 __device__ __forceinline__ D3 sdf_local_bwd(int type, const float* p, const double4* __restrict__ pl, int nf, const D3& l,
                                             double phib, const D3& gb, const Temp& T, const BodySink& sink,
-                                            double& taub, D3& g_out, bool ndir = false) {
+                                            double& taub, D3& g_out, bool ndir = false, bool surf = false,
+                                            const FaceMask* mk = nullptr) {
   if (SQ && (type == CM_SQ_UNION || type == CM_OPC)) {
     Dual4 ph, gx, gy, gz;
     if (type == CM_SQ_UNION)
@@ -287,36 +288,45 @@ __device__ __forceinline__ D3 sdf_local_bwd(int type, const float* p, const doub
     atomicAdd(&sink.param[3], float(rhob));
     return d3(sg[0] * qb[0], sg[1] * qb[1], sg[2] * qb[2]);
   }
-  // polytope: phi = tau LSE(y / tau), y_f = n_f . l - o_f, g = sum_f pi_f n_f
-  double m = -1e300;
-  for (int f = 0; f < nf; ++f) {
-    const double4 q = unscaled(pl[f], T);
-    m = fmax(m, fma(q.x, l.x, fma(q.y, l.y, fma(q.z, l.z, -q.w))));
+  // polytope: phi = tau LSE(y / tau), y_f = n_f . l - o_f, g = sum_f pi_f n_f.
+  // surf (wave-uniform): every lane's point lies on the body's own boundary
+  // (an E-E witness on its own edge), where the largest plane value is 0 up
+  // to the smoothed witness's overshoot (as the forward's surface-gradient
+  // query): the shift is 0 and the max pass is skipped.  mk: the faces to
+  // visit, shared by every lane of the wave (null: all), as in the forward's
+  // masked queries.
+  double m = surf ? 0.0 : -1e300;
+  if (!surf) {
+    for_faces(mk, nf, [&](int f) __attribute__((always_inline)) {
+      const double4 q = unscaled(pl[f], T);
+      m = fmax(m, fma(q.x, l.x, fma(q.y, l.y, fma(q.z, l.z, -q.w))));
+    });
   }
   double S = 0.0, gx = 0.0, gy = 0.0, gz = 0.0, py = 0.0;
-  for (int f = 0; f < nf; ++f) {
+  for_faces(mk, nf, [&](int f) __attribute__((always_inline)) {
     const double4 q = unscaled(pl[f], T);
     const double yv = fma(q.x, l.x, fma(q.y, l.y, fma(q.z, l.z, -q.w)));
-    const double e = double(ex2f(float((yv - m) * T.c)));
+    const double a = (yv - m) * T.c;
+    if (!__any(a > -40.0)) return;   // below 2^-40 on every lane, as the adjoint pass below
+    const double e = double(ex2f(float(a)));
     S += e; gx = fma(e, q.x, gx); gy = fma(e, q.y, gy); gz = fma(e, q.z, gz);
     py = fma(e, yv, py);
-  }
-  const double iS = rcp64(S);   // S >= 1: the largest plane's term is 1
+  });
+  const double iS = S > 0.0 ? rcp64(S) : 0.0;   // S >= 1 (the largest plane's term is about 1)
   const D3 g = d3(gx * iS, gy * iS, gz * iS);
   g_out = g;
-  const double phi = m + T.tau * log(S);
   const double gbg = dot(gb, g);
-  taub += phib * (phi - py * iS) * T.inv_tau;
+  if (phib != 0.0) taub += phib * ((m + T.tau * log(S)) - py * iS) * T.inv_tau;
   D3 lb = d3(0.0, 0.0, 0.0);
   double tz = 0.0;
-  for (int f = 0; f < nf; ++f) {
+  for_faces(mk, nf, [&](int f) __attribute__((always_inline)) {
     const double4 q = unscaled(pl[f], T);
     const double yv = fma(q.x, l.x, fma(q.y, l.y, fma(q.z, l.z, -q.w)));
     const double a = (yv - m) * T.c;
     // a face whose softmax weight is below 2^-40 for every lane of the wave
     // (or every active lane) adds nothing the float32 sums could hold: skipped
     // together (wave-uniform, so the wave sums below stay whole-wave)
-    if (!__any(a > -40.0)) continue;
+    if (!__any(a > -40.0)) return;
     const double pi = double(ex2f(float(a))) * iS;
     const double zb = pi * (gb.x * q.x + gb.y * q.y + gb.z * q.z - gbg);   // softmax adjoint of g
     const double yb = phib * pi + zb * T.inv_tau;
@@ -336,7 +346,7 @@ __device__ __forceinline__ D3 sdf_local_bwd(int type, const float* p, const doub
         atomicAdd(&sink.plane[2 * sink.maxF + f], v2); atomicAdd(&sink.plane[3 * sink.maxF + f], v3);
       }
     }
-  }
+  });
   taub -= tz * T.inv_tau * T.inv_tau;
   return lb;
 }
@@ -351,15 +361,16 @@ struct Twist {
 // receives rho -= x_bar, omega += g x g_bar - x x x_bar.
 template <bool WAVE, bool IDENT, bool SQ = false>
 __device__ __forceinline__ D3 sdf_body_bwd(const BodyView& V, const D3& x, double phib, const D3& gb, const Temp& T,
-                                           const BodySink& sink, double& taub, Twist& tw, bool ndir = false) {
+                                           const BodySink& sink, double& taub, Twist& tw, bool ndir = false,
+                                           bool surf = false, const FaceMask* mk = nullptr) {
   if (IDENT) {
     D3 g;
-    return sdf_local_bwd<WAVE, SQ>(V.type, V.p, V.planes, V.nf, x, phib, gb, T, sink, taub, g, ndir);
+    return sdf_local_bwd<WAVE, SQ>(V.type, V.p, V.planes, V.nf, x, phib, gb, T, sink, taub, g, ndir, surf, mk);
   }
   const D3 l = rotT(V.R, sub(x, d3(V.t[0], V.t[1], V.t[2])));
   const D3 gbl = rotT(V.R, gb);
   D3 gl;
-  const D3 lb = sdf_local_bwd<WAVE, SQ>(V.type, V.p, V.planes, V.nf, l, phib, gbl, T, sink, taub, gl, ndir);
+  const D3 lb = sdf_local_bwd<WAVE, SQ>(V.type, V.p, V.planes, V.nf, l, phib, gbl, T, sink, taub, gl, ndir, surf, mk);
   const D3 xb = rot(V.R, lb);
   const D3 g = rot(V.R, gl);
   const D3 c1 = cross(g, gb), c2 = cross(x, xb);

@@ -27,7 +27,7 @@
 namespace cm {
 
 struct BwdLds {
-  int vA, vB, plA, plB, prm, rbar, cbar, cot, F, top, best, bt, tw, sv, se, si, mb, sk, bytes;
+  int vA, vB, plA, plB, prm, rbar, cbar, cot, F, top, best, bt, tw, um, sv, se, si, mb, sk, bytes;
 };
 
 // presel: the selection adjoint's arrays follow (soft vertex adjoints
@@ -52,6 +52,7 @@ __host__ __device__ inline BwdLds bwd_layout(int base, int maxV, int maxE, int m
   o = (o + 7) & ~7;
   L.bt = o; o += 8 * block;            // A1: each slice's own term of its nearest candidate
   L.tw = o; o += 8 * 8;                // output twist terms
+  L.um = o; o += 4 * (block / 64) * int(sizeof(FaceMask));   // A2: per wave, the union face masks of its 4 query slots
   L.sv = L.se = L.si = L.mb = L.sk = o;
   if (presel) {
     L.sv = o; o += 4 * 2 * CM_MAX_PRESEL * 3;
@@ -87,7 +88,8 @@ template <int BLOCK, int KMAX, bool PRESEL, bool SQ, bool REFINE = false>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SQ ? 1 : 2))) void collide_bwd(Tables tb, BatchDev bt, ParamsDev prm, OutDev fwd, BwdArgs ga,
                                                      float* __restrict__ scratch, long long scratch_stride, int maxV,
                                                      int maxE, int maxF, unsigned* err, TapeDev tape,
-                                                     int* __restrict__ queue) {
+                                                     int* __restrict__ queue, char* __restrict__ gmask,
+                                                     long long gmask_stride) {
   extern __shared__ float4 smem4[];
   char* smem = reinterpret_cast<char*>(smem4);
   __shared__ PairShared ps;
@@ -111,12 +113,22 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SQ ? 1 : 
   int* bestI = reinterpret_cast<int*>(smem + L.best);
   double* btl = reinterpret_cast<double*>(smem + L.bt);
   double* twOut = reinterpret_cast<double*>(smem + L.tw);
+  FaceMask* umask = reinterpret_cast<FaceMask*>(smem + L.um);
   float* svb = reinterpret_cast<float*>(smem + L.sv);   // PRESEL: soft vertex adjoints
   float* seb = reinterpret_cast<float*>(smem + L.se);   // PRESEL: soft edge endpoint adjoints
   int* selI = reinterpret_cast<int*>(smem + L.si);
   float* mbar = reinterpret_cast<float*>(smem + L.mb);  // PRESEL: metric adjoints, A's vertices then B's
   double* sK = reinterpret_cast<double*>(smem + L.sk);
   const bool safeguard = PRESEL && (prm.flags & CM_FLAG_SAFEGUARD);
+  // Face masks for the window's E-E queries: the candidate pass's group
+  // masks (cull) kept in this workgroup's slot of gmask (the shared LDS
+  // region that holds them is reused by the candidate records), from which
+  // each wave ORs the union over its candidates' groups.  Witnesses lie on
+  // their edges, so not with pre-selection (soft edges), tracing (moved
+  // points) or the extended primitives.
+  const bool use_masks = !PRESEL && !REFINE && !SQ && gmask != nullptr && P.MW > 0;
+  FaceMask* gG1 = use_masks ? reinterpret_cast<FaceMask*>(gmask + (long long)blockIdx.x * gmask_stride) : nullptr;
+  FaceMask* gG2 = use_masks ? gG1 + 2 * ((maxE + 7) >> 3) : nullptr;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   constexpr int NW = BLOCK / 64;
@@ -191,7 +203,24 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SQ ? 1 : 
       }
       if (tlist || tmask) tdat = reinterpret_cast<const double*>(rec + 16);
     }
+    // the group masks of this pair into the workgroup's slot
+    auto keep_masks = [&]() {
+      if (!use_masks || ps.nee == 0) return;
+      const int nA = 2 * ((A.ne + 7) >> 3), nB = 2 * ((neB + 7) >> 3);
+      const int words = int(sizeof(FaceMask) / 8);
+      for (int i = tid; i < (nA + nB) * words; i += BLOCK) {
+        const int m = i / words, w = i - m * words;
+        const unsigned long long* src = reinterpret_cast<const unsigned long long*>(m < nA ? P.sG1 + m : P.sG2 + (m - nA));
+        unsigned long long* dst = reinterpret_cast<unsigned long long*>(m < nA ? gG1 + m : gG2 + (m - nA));
+        dst[w] = src[w];
+      }
+      __syncthreads();
+    };
     if (tdat) {
+      if (use_masks) {
+        P.cull();
+        keep_masks();
+      }
       P.pass1();
       for (int i = tid; i < 10 * K; i += BLOCK) {
         if (i < K) P.sTop[i] = tdat[i];
@@ -200,6 +229,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SQ ? 1 : 
       __syncthreads();
     } else {
       P.cull();
+      keep_masks();
       double tk[KMAX];
       P.scores(tk);
       P.topk(tk);
@@ -358,6 +388,35 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SQ ? 1 : 
       }
       const int idx = R.idx;
       const bool is_vs = idx < ps.nvs;
+      // a wave of E-E candidates queries through the union of its
+      // candidates' group masks: slot 0 A's faces near e1, 1 B's near e1,
+      // 2 A's near e2, 3 B's near e2 (wave-uniform)
+      const bool masked = use_masks && __ballot(live && is_vs) == 0ull;
+      FaceMask* U = umask + 4 * wave;
+      if (masked) {
+        const int MW = P.MW;
+        if (lane < 4 * MW) U[lane / MW].w[lane - (lane / MW) * MW] = 0ull;
+        if (lane < 4) U[lane].n = MW;
+        wave_lds_sync();
+        if (live) {
+          const int ee_i = (idx - ps.nvs) >> 1;
+          const int kq = ee_i / neB, lq = ee_i - kq * neB;
+          const FaceMask* g1 = gG1 + 2 * (kq >> 3);
+          const FaceMask* g2 = gG2 + 2 * (lq >> 3);
+          for (int w = 0; w < MW; ++w) {
+            const unsigned long long a0 = g1[0].w[w], a1 = g1[1].w[w], a2 = g2[0].w[w], a3 = g2[1].w[w];
+            if (a0) atomicOr(&U[0].w[w], a0);
+            if (a1) atomicOr(&U[1].w[w], a1);
+            if (a2) atomicOr(&U[2].w[w], a2);
+            if (a3) atomicOr(&U[3].w[w], a3);
+          }
+        }
+        wave_lds_sync();
+      }
+      const FaceMask* U0 = masked ? U : nullptr;
+      const FaceMask* U1 = masked ? U + 1 : nullptr;
+      const FaceMask* U2 = masked ? U + 2 : nullptr;
+      const FaceMask* U3 = masked ? U + 3 : nullptr;
       // ---- stage 1: forward values and the seeds of four SDF query slots
       // slot 0: A at X0 (gradient adjoint), slot 1: B at X1, slot 2: A at X2, slot 3: B at X3
       D3 X[4];
@@ -422,14 +481,14 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SQ ? 1 : 
         const D3 nb = scl(de, rho);
         double phiB1, phiA2, dum, phiA1 = 0.0, phiB2 = 0.0;
         D3 gA, gB, dg;
-        sdf_body<kValue, false, false, SQ>(B, e1, T, phiB1, dg);
-        sdf_body<kValue, true, false, SQ>(A, e2, T, phiA2, dg);
+        sdf_body<kValue, false, false, SQ>(B, e1, T, phiB1, dg, U1);
+        sdf_body<kValue, true, false, SQ>(A, e2, T, phiA2, dg, U2);
         if (PRESEL || REFINE) {   // soft edges / traced points need not lie on the edges: full queries
           sdf_body<kFull, true, false, SQ>(A, e1, T, phiA1, gA);
           sdf_body<kFull, false, false, SQ>(B, e2, T, phiB2, gB);
         } else {
-          sdf_body<kSurfGrad, true, false, SQ>(A, e1, T, dum, gA);
-          sdf_body<kSurfGrad, false, false, SQ>(B, e2, T, dum, gB);
+          sdf_body<kSurfGrad, true, false, SQ>(A, e1, T, dum, gA, U0);
+          sdf_body<kSurfGrad, false, false, SQ>(B, e2, T, dum, gB, U3);
         }
         const double u1 = dot(gB, nb), u2 = -dot(gA, nb), ucl = -dot(gA, gB);
         const double gam1 = tanh64(u1, T), gam2 = tanh64(u2, T);
@@ -490,10 +549,13 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SQ ? 1 : 
         return __ballot(ph != 0.0 || g.x != 0.0 || g.y != 0.0 || g.z != 0.0) != 0ull;
       };
       const D3 zero = d3(0, 0, 0);
-      const D3 xb0 = used(phib[0], gbar[0]) ? sdf_body_bwd<true, true, SQ>(A, X[0], phib[0], gbar[0], T, sinkA, taub, tw, is_vs) : zero;
-      const D3 xb1 = used(phib[1], gbar[1]) ? sdf_body_bwd<true, false, SQ>(B, X[1], phib[1], gbar[1], T, sinkB, taub, tw, is_vs) : zero;
-      const D3 xb2 = used(phib[2], gbar[2]) ? sdf_body_bwd<true, true, SQ>(A, X[2], phib[2], gbar[2], T, sinkA, taub, tw) : zero;
-      const D3 xb3 = used(phib[3], gbar[3]) ? sdf_body_bwd<true, false, SQ>(B, X[3], phib[3], gbar[3], T, sinkB, taub, tw) : zero;
+      // slots 0 and 3 of E-E candidates query a witness on its own body's
+      // edge (not so for soft pre-selected edges or traced points)
+      const bool surf = !PRESEL && !REFINE && __ballot(live && is_vs) == 0ull;
+      const D3 xb0 = used(phib[0], gbar[0]) ? sdf_body_bwd<true, true, SQ>(A, X[0], phib[0], gbar[0], T, sinkA, taub, tw, is_vs, surf, U0) : zero;
+      const D3 xb1 = used(phib[1], gbar[1]) ? sdf_body_bwd<true, false, SQ>(B, X[1], phib[1], gbar[1], T, sinkB, taub, tw, is_vs, false, U1) : zero;
+      const D3 xb2 = used(phib[2], gbar[2]) ? sdf_body_bwd<true, true, SQ>(A, X[2], phib[2], gbar[2], T, sinkA, taub, tw, false, false, U2) : zero;
+      const D3 xb3 = used(phib[3], gbar[3]) ? sdf_body_bwd<true, false, SQ>(B, X[3], phib[3], gbar[3], T, sinkB, taub, tw, false, surf, U3) : zero;
       // E-E: adjoints of the two witness points (zero on idle lanes, whose
       // seeds are all zero)
       D3 e1b = zero, e2b = zero;
@@ -833,6 +895,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SQ ? 1 : 
   }
 }
 
+long long bwd_mask_bytes(int maxE, int maxF) {
+  if (mask_words(maxF) == 0) return 0;
+  return (2LL * ((maxE + 7) / 8) * 2 * (long long)sizeof(FaceMask) + 255) & ~255LL;
+}
+
 int bwd_lds_bytes(int maxV, int maxE, int maxF, int block, bool presel) {
   const int extra = bwd_extra_bytes(maxV, maxE, maxF, block, presel);
   const int pre = presel ? presel_lds_bytes(maxV, maxE) : 0;
@@ -845,7 +912,7 @@ static hipError_t launch_bwd_t(const BwdLaunch& b, hipStream_t st) {
   BwdArgs ga{b.cot, b.gr};
   hipLaunchKernelGGL((collide_bwd<BLOCK, KMAX, PRESEL, SQ, REFINE>), dim3(b.f.grid), dim3(BLOCK), lds, st, b.f.tb, b.f.bt,
                      b.f.prm, b.f.out, ga, b.f.scratch, b.f.scratch_stride, b.f.maxV, b.f.maxE, b.f.maxF, b.f.err,
-                     b.f.tape, b.f.queue);
+                     b.f.tape, b.f.queue, static_cast<char*>(b.masks), b.mask_stride);
   return hipGetLastError();
 }
 

@@ -326,6 +326,35 @@ __device__ __forceinline__ unsigned long long mask_word(const FaceMask& mk, int 
   return uni64(mk.w[w]) & valid;
 }
 
+// body(f) for each face f of a mask that every lane of the wave shares, in
+// increasing order (a wave-uniform walk over its set bits), or for every one
+// of the nf faces when mk is null or empty.
+template <typename F>
+__device__ __forceinline__ void for_faces(const FaceMask* mk, int nf, F&& body) {
+  const int nw = mk ? __builtin_amdgcn_readfirstlane(mk->n) : 0;
+  if (nw == 0) {
+    for (int f = 0; f < nf; ++f) body(f);
+    return;
+  }
+  for (int w = 0; w < nw; ++w) {
+    unsigned long long bits = mask_word(*mk, w, nf);
+    while (bits) {
+      const int b = __builtin_ctzll(bits);
+      bits &= bits - 1ull;
+      body(64 * w + b);
+    }
+  }
+}
+
+// Orders a wave's LDS accesses before and after it (the wave's LDS
+// operations complete in issue order; this keeps the compiler from moving
+// them across).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // sdf_poly restricted to the faces of a mask that every active lane of the
 // wave shares: a wave-uniform walk over its set bits in increasing face order,
 // two faces per step with both LDS loads issued before either is used (a

@@ -72,7 +72,12 @@ struct BwdLaunch {
   FwdLaunch f;
   CotDev cot;
   GradDev gr;
+  void* masks = nullptr;       // per workgroup, mask_stride bytes: the candidate pass's group face
+  long long mask_stride = 0;   // masks kept for the window's queries (null: every query visits all faces)
 };
+// Bytes of one workgroup's group face masks (bwd_mask_bytes): 0 when the
+// context's polytopes have too many faces to be culled.
+long long bwd_mask_bytes(int maxE, int maxF);
 
 int fwd_lds_bytes(int maxV, int maxE, int maxF, int block, int kmax, bool presel = false, bool edges_out = false);
 int bwd_lds_bytes(int maxV, int maxE, int maxF, int block, bool presel = false);
