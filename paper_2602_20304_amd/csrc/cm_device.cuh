@@ -305,6 +305,8 @@ __device__ __forceinline__ BodyView load_uniform(const BodyView& src, bool with_
 
 // Polytopes of up to 64 * kMaxMaskWords faces are culled.
 constexpr int kMaxMaskWords = 8;
+// No shift given for a masked value query: it runs its max pass.
+constexpr double kNoShift = 1e300;
 // A subset of a polytope's faces, in LDS: the first n words (bit f of word
 // f / 64), shared by every active lane of a wave; n = 0 means all faces.
 struct FaceMask {
@@ -358,13 +360,18 @@ __device__ __forceinline__ void wave_lds_sync() {
 // sdf_poly restricted to the faces of a mask that every active lane of the
 // wave shares: a wave-uniform walk over its set bits in increasing face order,
 // two faces per step with both LDS loads issued before either is used (a
-// one-face step exposes the load latency).
+// one-face step exposes the load latency).  shift (kValue): the lane's
+// shift of the float32 sum when it has one (a lower bound of the largest
+// plane value within 100 of it, so the sum stays in range); the max pass
+// runs only when a lane of the wave has none.
 template <int MODE>
 __device__ __forceinline__ void sdf_poly_masked(const double4* __restrict__ pd, int nf, const FaceMask& mk,
-                                                const D3& x, const Temp& T, double& phi, D3& g) {
+                                                const D3& x, const Temp& T, double& phi, D3& g,
+                                                double shift = kNoShift) {
   const int nw = mk.n;
   double m = 0.0;
-  if (MODE != kSurfGrad) {
+  const bool shifted = MODE == kValue && shift < kNoShift;
+  if (MODE != kSurfGrad && !__all(shifted)) {
     m = -1e300;
     for (int w = 0; w < nw; ++w) {
       const double4* pw = pd + 64 * w;
@@ -386,6 +393,7 @@ __device__ __forceinline__ void sdf_poly_masked(const double4* __restrict__ pd, 
       }
     }
   }
+  if (shifted) m = shift;
   float s = 0.f;
   double S = 0.0, ax = 0.0, ay = 0.0, az = 0.0;
   for (int w = 0; w < nw; ++w) {
@@ -422,7 +430,13 @@ __device__ __forceinline__ void sdf_poly_masked(const double4* __restrict__ pd, 
       }
     }
   }
-  if (MODE != kSurfGrad) phi = T.tl * (m + double(lg2f(s)));
+  if (MODE != kSurfGrad) {
+    // a shifted sum can reach 2^100: its exponent goes in exactly, so that
+    // the float32 logarithm only sees the mantissa
+    int E = 0;
+    const float sm = shifted ? frexpf(s, &E) : s;
+    phi = T.tl * ((m + double(E)) + double(lg2f(sm)));
+  }
   if (MODE != kValue) {
     const double inv = S > 0.0 ? T.tl * rcp64(S) : 0.0;
     g = d3(ax * inv, ay * inv, az * inv);
@@ -615,7 +629,7 @@ __device__ __forceinline__ double sdf_value64(const BodyView& B, const D3& x, co
 // raise every call site's register pressure).
 template <int MODE, bool IDENT, bool NDIR = false, bool SQ = false>
 __device__ __forceinline__ void sdf_body(const BodyView& B, const D3& x, const Temp& T, double& phi, D3& g,
-                                         const FaceMask* mk = nullptr) {
+                                         const FaceMask* mk = nullptr, double shift = kNoShift) {
   D3 l = x;
   if (!IDENT) {
     const double dx = x.x - B.t[0], dy = x.y - B.t[1], dz = x.z - B.t[2];
@@ -624,7 +638,7 @@ __device__ __forceinline__ void sdf_body(const BodyView& B, const D3& x, const T
   }
   D3 lg;
   if (B.type == CM_POLYTOPE) {
-    if (mk && mk->n > 0) sdf_poly_masked<MODE>(B.planes, B.nf, *mk, l, T, phi, lg);
+    if (mk && mk->n > 0) sdf_poly_masked<MODE>(B.planes, B.nf, *mk, l, T, phi, lg, shift);
     else sdf_poly<MODE>(B.planes, B.nf, l, T, phi, lg);
   } else if (SQ && B.type == CM_SQ_UNION) {
     sdf_squnion<MODE != kValue, NDIR>(B.planes, B.nf, l, T, phi, lg);
@@ -757,7 +771,8 @@ template <bool OWN_FULL = false, bool SQ = false, bool REFINE = false>
 __device__ __forceinline__ void ee_candidates(const D3& a0, const D3& t1, const D3& b0, const D3& t2, const EEQP& q,
                                               double row_lse, double col_lse, const BodyView& A, const BodyView& B,
                                               double eps_n, const Temp& T, const FaceMask* m1, const FaceMask* m2,
-                                              Cand& c1, Cand& c2, bool safeguard = false, int steps = 0) {
+                                              Cand& c1, Cand& c2, bool safeguard = false, int steps = 0,
+                                              double sh1 = kNoShift, double sh2 = kNoShift) {
   D3 e1 = d3(a0.x + q.al1 * t1.x, a0.y + q.al1 * t1.y, a0.z + q.al1 * t1.z);
   D3 e2 = d3(b0.x + q.al2 * t2.x, b0.y + q.al2 * t2.y, b0.z + q.al2 * t2.z);
   double dqp, idum;   // dqp: the nearest-neighbour term's distance
@@ -791,10 +806,10 @@ __device__ __forceinline__ void ee_candidates(const D3& a0, const D3& t1, const 
   double phiB1, phiA2, dum;
   D3 gA, gB, dg;
   double phiA1 = 0.0, phiB2 = 0.0;
-  sdf_body<kValue, false, false, SQ>(B, e1, T, phiB1, dg, m1 ? m1 + 1 : nullptr);
+  sdf_body<kValue, false, false, SQ>(B, e1, T, phiB1, dg, m1 ? m1 + 1 : nullptr, sh1);
   if (OWN_FULL || REFINE) sdf_body<kFull, true, false, SQ>(A, e1, T, phiA1, gA, m1);
   else sdf_body<kSurfGrad, true, false, SQ>(A, e1, T, dum, gA, m1);                   // e1 lies on an edge of A
-  sdf_body<kValue, true, false, SQ>(A, e2, T, phiA2, dg, m2);
+  sdf_body<kValue, true, false, SQ>(A, e2, T, phiA2, dg, m2, sh2);
   if (OWN_FULL || REFINE) sdf_body<kFull, false, false, SQ>(B, e2, T, phiB2, gB, m2 ? m2 + 1 : nullptr);
   else sdf_body<kSurfGrad, false, false, SQ>(B, e2, T, dum, gB, m2 ? m2 + 1 : nullptr);   // e2 lies on an edge of B
   const double gam1 = tanh64(dot(gB, nb), T);

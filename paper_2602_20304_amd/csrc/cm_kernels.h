@@ -45,12 +45,16 @@ struct FwdLaunch {
 // QP solution (al1, al2, ln con) in float64, then the float32 candidate
 // scores and the int32 list of filtered candidates (both nvs + 2 nee long),
 // then room for both bodies' edge arrays (float64, used when they do not fit
-// in LDS).
+// in LDS), then per edge the float64 value-query shift of the other body
+// along its segment (A's edges, then B's; see PairEngine::cull).
 __host__ __device__ inline long long scratch_edges_offset(int maxV, int maxE) {
   return 8LL * maxE * maxE + 2 * (2LL * maxE * maxE + 2LL * maxV) + 128;
 }
-__host__ __device__ inline long long fwd_scratch_floats(int maxV, int maxE) {
+__host__ __device__ inline long long scratch_shift_offset(int maxV, int maxE) {
   return scratch_edges_offset(maxV, maxE) + 24LL * maxE;
+}
+__host__ __device__ inline long long fwd_scratch_floats(int maxV, int maxE) {
+  return scratch_shift_offset(maxV, maxE) + 4LL * maxE;
 }
 
 struct CotDev {

@@ -140,6 +140,8 @@ struct PairEngine {
   int* sCnt;
   FaceMask* sG1;             // [ceil(maxE / 8)][2] face masks of groups of 8 edges of A, see cull()
   FaceMask* sG2;             // [ceil(maxE / 8)][2] the same for B's edges
+  double* gShift;            // scratch [2][maxE]: per edge of A the shift of B's value queries on it, then
+                             // per edge of B that of A's (kNoShift: none), see cull()
   int MW;
   double* Dbuf;   // [maxE^2] unsigned distance of edge pair (k, l) at k * neB + l
   double* Al1;    // [maxE^2] QP solution al1, al2 and ln con of the same edge pair
@@ -195,6 +197,7 @@ struct PairEngine {
     Lcon = Al2 + mm;
     Sbuf = reinterpret_cast<float*>(Lcon + mm);
     List = reinterpret_cast<int*>(Sbuf + 2 * mm + 2LL * maxV_);
+    gShift = reinterpret_cast<double*>(slot + scratch_shift_offset(maxV_, maxE_));
     T = make_temp(prm);
     lam = prm.lam;
     flags = prm.flags;
@@ -458,17 +461,25 @@ struct PairEngine {
       const D3 p0 = d3(a0.x - ext * t1.x, a0.y - ext * t1.y, a0.z - ext * t1.z);
       const D3 p1 = d3(a0.x + (1.0 + ext) * t1.x, a0.y + (1.0 + ext) * t1.y, a0.z + (1.0 + ext) * t1.z);
       FaceMask* grp = (onA ? sG1 : sG2) + 2 * (k >> 3);
-      seg_mask_or(A, false, p0, p1, grp[0].w);
-      seg_mask_or(B, true, p0, p1, grp[1].w);
+      const double sA = seg_mask_or(A, false, p0, p1, grp[0].w);
+      const double sB = seg_mask_or(B, true, p0, p1, grp[1].w);
+      gShift[i] = onA ? sB : sA;   // the other body's (the own body's queries are surface ones)
     }
     __syncthreads();
   }
-  // OR the faces of V near segment [p0w, p1w] (pair frame) into out[MW]
-  __device__ __forceinline__ void seg_mask_or(const BodyView& V, bool moved, const D3& p0w, const D3& p1w,
-                                              unsigned long long* out) const {
+  // OR the faces of V near segment [p0w, p1w] (pair frame) into out[MW];
+  // returns a shift for V's value queries at points of the segment, or
+  // kNoShift.  With y_f the scaled plane values, L = max_f min(y_f(p0),
+  // y_f(p1)) and U = max_f max(y_f(p0), y_f(p1)), every point x of the
+  // segment has L <= max_f y_f(x) <= U (y_f is affine along it), and the
+  // face attaining L is in the mask; so L shifts the masked float32 sum of
+  // 2^(y_f - L) into [1, nf 2^(U - L)] and replaces the max pass when
+  // U - L <= 100.
+  __device__ __forceinline__ double seg_mask_or(const BodyView& V, bool moved, const D3& p0w, const D3& p1w,
+                                                unsigned long long* out) const {
     if (V.type != CM_POLYTOPE) {
       for (int w = 0; w < MW; ++w) atomicOr(out + w, ~0ull);
-      return;
+      return kNoShift;
     }
     D3 p0 = p0w, p1 = p1w;
     if (moved) {
@@ -487,16 +498,19 @@ struct PairEngine {
       L = fmax(L, fmin(y0, y1));
     }
     unsigned long long m = 0ull;
+    double U = -1e300;
     for (int f = 0; f < V.nf; ++f) {
       const double4 q = V.planes[f];
       const double y0 = fma(q.x, p0.x, fma(q.y, p0.y, fma(q.z, p0.z, -q.w)));
       const double y1 = fma(q.x, p1.x, fma(q.y, p1.y, fma(q.z, p1.z, -q.w)));
+      U = fmax(U, fmax(y0, y1));
       if (fmax(y0, y1) >= L - 38.0) m |= 1ull << (f & 63);
       if ((f & 63) == 63 || f == V.nf - 1) {
         if (m) atomicOr(out + (f >> 6), m);
         m = 0ull;
       }
     }
+    return U - L <= 100.0 ? L : kNoShift;
   }
 
   // ------------------------------------------------------------ candidates
@@ -521,14 +535,15 @@ struct PairEngine {
   // lanes hold unrelated edge pairs; the two differ by less than 2^-38
   // relative).
   __device__ __forceinline__ void ee(int k, int l, Cand& c1, Cand& c2, const FaceMask* m1 = nullptr,
-                                     const FaceMask* m2 = nullptr) const {
+                                     const FaceMask* m2 = nullptr, double sh1 = kNoShift,
+                                     double sh2 = kNoShift) const {
     D3 a0, t1, b0, t2;
     EA.get(k, a0, t1);
     EB.get(l, b0, t2);
     const int i = k * B.ne + l;
     const EEQP q = ee_from_alpha(a0, t1, b0, t2, Al1[i], Al2[i], Lcon[i]);
     ee_candidates<PRESEL, SQ, REFINE>(a0, t1, b0, t2, q, sRow[k], sCol[l], A, B, eps_n, T, m1, m2, c1, c2,
-                                      PRESEL && (flags & CM_FLAG_SAFEGUARD), refine);
+                                      PRESEL && (flags & CM_FLAG_SAFEGUARD), refine, sh1, sh2);
   }
   // candidate idx in the fixed order: A's vertices, B's vertices, E-E (k, l)
   // row-major with witness 1 before witness 2
@@ -654,7 +669,9 @@ struct PairEngine {
         if (k < neA && l < neB) {
           const int idx = k * neB + l;
           Cand c1, c2;
-          ee(k, l, c1, c2, m1, m2);
+          // the value queries' shifts along the lane's segments (cull)
+          const double sh1 = MW > 0 ? gShift[k] : kNoShift, sh2 = MW > 0 ? gShift[neA + l] : kNoShift;
+          ee(k, l, c1, c2, m1, m2, sh1, sh2);
           Sbuf[nvs + 2 * idx] = float(c1.s);
           Sbuf[nvs + 2 * idx + 1] = float(c2.s);
           tk_insert<KMAX>(tk, c1.s);
