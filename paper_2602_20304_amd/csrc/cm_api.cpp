@@ -721,21 +721,15 @@ extern "C" cm_status cm_collide_backward(cm_context* ctx, const cm_batch* batch,
     return cm_hip(ctx, e, "backward scratch");
   b.f.scratch = ctx->d_scratch;
   // The workspace's first 256 B hold the tape's pool counter (byte 0) and
-  // the adjoint's work-queue counter (byte 128); the recorded tape follows,
-  // then each workgroup's group face masks.
-  const long long tape_end = 256 + (pool_cap > 0 ? tape_records_bytes(od.capacity, pd.K) + 4 * pool_cap : 0);
-  const long long mbytes = (pd.presel_v == 0 && pd.refine == 0) ? bwd_mask_bytes(b.f.maxE, b.f.maxF) : 0;
-  const long long mask_off = (tape_end + 255) & ~255LL;
-  const long long bytes = mask_off + mbytes * b.f.grid;
+  // the adjoint's work-queue counter (byte 128); the recorded tape follows.
+  const long long bytes = 256 + (pool_cap > 0 ? tape_records_bytes(od.capacity, pd.K) + 4 * pool_cap : 0);
   if ((e = ctx_ensure(ctx, &ctx->d_bwd, &ctx->bwd_cap, size_t(bytes))) != hipSuccess)
     return cm_hip(ctx, e, "adjoint workspace");
   int* queue = reinterpret_cast<int*>(static_cast<char*>(ctx->d_bwd) + 128);
   if ((e = hipMemsetAsync(queue, 0, sizeof(int), st)) != hipSuccess) return cm_hip(ctx, e, "zero work queue");
   b.f.queue = queue;
-  b.masks = mbytes > 0 ? static_cast<char*>(ctx->d_bwd) + mask_off : nullptr;
-  b.mask_stride = mbytes;
   if (pool_cap > 0) {
-    tape_layout(static_cast<char*>(ctx->d_bwd), tape_end, od.capacity, pd.K, &tv);
+    tape_layout(static_cast<char*>(ctx->d_bwd), bytes, od.capacity, pd.K, &tv);
     if ((e = launch_tape_reset(tv, st)) != hipSuccess) return cm_hip(ctx, e, "tape reset");
     f1.scratch = ctx->d_scratch;   // the ensures above may have moved it
     f1.tape = tv;

@@ -88,8 +88,7 @@ template <int BLOCK, int KMAX, bool PRESEL, bool SQ, bool REFINE = false>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SQ ? 1 : 2))) void collide_bwd(Tables tb, BatchDev bt, ParamsDev prm, OutDev fwd, BwdArgs ga,
                                                      float* __restrict__ scratch, long long scratch_stride, int maxV,
                                                      int maxE, int maxF, unsigned* err, TapeDev tape,
-                                                     int* __restrict__ queue, char* __restrict__ gmask,
-                                                     long long gmask_stride) {
+                                                     int* __restrict__ queue) {
   extern __shared__ float4 smem4[];
   char* smem = reinterpret_cast<char*>(smem4);
   __shared__ PairShared ps;
@@ -120,15 +119,13 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SQ ? 1 : 
   float* mbar = reinterpret_cast<float*>(smem + L.mb);  // PRESEL: metric adjoints, A's vertices then B's
   double* sK = reinterpret_cast<double*>(smem + L.sk);
   const bool safeguard = PRESEL && (prm.flags & CM_FLAG_SAFEGUARD);
-  // Face masks for the window's E-E queries: the candidate pass's group
-  // masks (cull) kept in this workgroup's slot of gmask (the shared LDS
-  // region that holds them is reused by the candidate records), from which
-  // each wave ORs the union over its candidates' groups.  Witnesses lie on
-  // their edges, so not with pre-selection (soft edges), tracing (moved
-  // points) or the extended primitives.
-  const bool use_masks = !PRESEL && !REFINE && !SQ && gmask != nullptr && P.MW > 0;
-  FaceMask* gG1 = use_masks ? reinterpret_cast<FaceMask*>(gmask + (long long)blockIdx.x * gmask_stride) : nullptr;
-  FaceMask* gG2 = use_masks ? gG1 + 2 * ((maxE + 7) >> 3) : nullptr;
+  // Face masks for the window's E-E queries: each wave of E-E candidates
+  // queries through the union of its candidates' group masks (the candidate
+  // pass's, kept by cull in the scratch slot), for the pairs the engine's
+  // union_masks() takes.  Witnesses lie on their edges, so not with
+  // pre-selection (soft edges), tracing (moved points) or the extended
+  // primitives.
+  const bool use_masks_k = !PRESEL && !REFINE && !SQ;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   constexpr int NW = BLOCK / 64;
@@ -153,6 +150,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SQ ? 1 : 
     }
     const BodyView& A = P.A;
     const BodyView& B = P.B;
+    const bool use_masks = use_masks_k && P.union_masks();   // this pair's (uniform)
+    FaceMask* const um = use_masks ? umask : nullptr;
     if (!SQ && (A.type >= CM_SQ_UNION || B.type >= CM_SQ_UNION)) {   // not built for these: flagged, skipped
       if (tid == 0) atomicOr(err, ERR_NO_ADJOINT);
       __syncthreads();
@@ -203,24 +202,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SQ ? 1 : 
       }
       if (tlist || tmask) tdat = reinterpret_cast<const double*>(rec + 16);
     }
-    // the group masks of this pair into the workgroup's slot
-    auto keep_masks = [&]() {
-      if (!use_masks || ps.nee == 0) return;
-      const int nA = 2 * ((A.ne + 7) >> 3), nB = 2 * ((neB + 7) >> 3);
-      const int words = int(sizeof(FaceMask) / 8);
-      for (int i = tid; i < (nA + nB) * words; i += BLOCK) {
-        const int m = i / words, w = i - m * words;
-        const unsigned long long* src = reinterpret_cast<const unsigned long long*>(m < nA ? P.sG1 + m : P.sG2 + (m - nA));
-        unsigned long long* dst = reinterpret_cast<unsigned long long*>(m < nA ? gG1 + m : gG2 + (m - nA));
-        dst[w] = src[w];
-      }
-      __syncthreads();
-    };
     if (tdat) {
-      if (use_masks) {
-        P.cull();
-        keep_masks();
-      }
+      if (use_masks) P.cull();   // the group masks (and their scratch copy) for the window's queries
       P.pass1();
       for (int i = tid; i < 10 * K; i += BLOCK) {
         if (i < K) P.sTop[i] = tdat[i];
@@ -229,7 +212,6 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SQ ? 1 : 
       __syncthreads();
     } else {
       P.cull();
-      keep_masks();
       double tk[KMAX];
       P.scores(tk);
       P.topk(tk);
@@ -317,7 +299,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SQ ? 1 : 
           taub += ab * fabs(dl) * T.inv_tau * T.inv_tau;
           if (fabs(dl) < best || (fabs(dl) == best && R.idx < bidx)) { best = fabs(dl); bidx = R.idx; bterm = term; }
         }
-      }, kAdjointTaus);
+      }, kAdjointTaus, true, um);
       P.sRed[tid] = act ? sbp : 0.0;
       P.sRed[BLOCK + tid] = act ? best : INFINITY;
       bestI[CM_MAX_K + tid] = act ? bidx : 0x7fffffff;
@@ -388,31 +370,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SQ ? 1 : 
       }
       const int idx = R.idx;
       const bool is_vs = idx < ps.nvs;
-      // a wave of E-E candidates queries through the union of its
-      // candidates' group masks: slot 0 A's faces near e1, 1 B's near e1,
-      // 2 A's near e2, 3 B's near e2 (wave-uniform)
+      // a wave of E-E candidates queries through the union masks the
+      // records were evaluated with (for_window): slot 0 A's faces near e1,
+      // 1 B's near e1, 2 A's near e2, 3 B's near e2 (wave-uniform)
       const bool masked = use_masks && __ballot(live && is_vs) == 0ull;
-      FaceMask* U = umask + 4 * wave;
-      if (masked) {
-        const int MW = P.MW;
-        if (lane < 4 * MW) U[lane / MW].w[lane - (lane / MW) * MW] = 0ull;
-        if (lane < 4) U[lane].n = MW;
-        wave_lds_sync();
-        if (live) {
-          const int ee_i = (idx - ps.nvs) >> 1;
-          const int kq = ee_i / neB, lq = ee_i - kq * neB;
-          const FaceMask* g1 = gG1 + 2 * (kq >> 3);
-          const FaceMask* g2 = gG2 + 2 * (lq >> 3);
-          for (int w = 0; w < MW; ++w) {
-            const unsigned long long a0 = g1[0].w[w], a1 = g1[1].w[w], a2 = g2[0].w[w], a3 = g2[1].w[w];
-            if (a0) atomicOr(&U[0].w[w], a0);
-            if (a1) atomicOr(&U[1].w[w], a1);
-            if (a2) atomicOr(&U[2].w[w], a2);
-            if (a3) atomicOr(&U[3].w[w], a3);
-          }
-        }
-        wave_lds_sync();
-      }
+      const FaceMask* U = umask + 4 * wave;
       const FaceMask* U0 = masked ? U : nullptr;
       const FaceMask* U1 = masked ? U + 1 : nullptr;
       const FaceMask* U2 = masked ? U + 2 : nullptr;
@@ -600,7 +562,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SQ ? 1 : 
         ee_qp_bwd(a0, t1, b0, t2, P.lam, T, dot(e1b, t1), dot(e2b, t2), lcb, a0b, t1b, b0b, t2b, taub);
         edge_adj(k, l, sub(a0b, t1b), t1b, sub(b0b, t2b), t2b);
       }
-    }, kAdjointTaus);
+    }, kAdjointTaus, true, um);
     __syncthreads();
 
     // ------------------------------------------------ N: nearest-neighbour LSE adjoint
@@ -895,11 +857,6 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SQ ? 1 : 
   }
 }
 
-long long bwd_mask_bytes(int maxE, int maxF) {
-  if (mask_words(maxF) == 0) return 0;
-  return (2LL * ((maxE + 7) / 8) * 2 * (long long)sizeof(FaceMask) + 255) & ~255LL;
-}
-
 int bwd_lds_bytes(int maxV, int maxE, int maxF, int block, bool presel) {
   const int extra = bwd_extra_bytes(maxV, maxE, maxF, block, presel);
   const int pre = presel ? presel_lds_bytes(maxV, maxE) : 0;
@@ -912,7 +869,7 @@ static hipError_t launch_bwd_t(const BwdLaunch& b, hipStream_t st) {
   BwdArgs ga{b.cot, b.gr};
   hipLaunchKernelGGL((collide_bwd<BLOCK, KMAX, PRESEL, SQ, REFINE>), dim3(b.f.grid), dim3(BLOCK), lds, st, b.f.tb, b.f.bt,
                      b.f.prm, b.f.out, ga, b.f.scratch, b.f.scratch_stride, b.f.maxV, b.f.maxE, b.f.maxF, b.f.err,
-                     b.f.tape, b.f.queue, static_cast<char*>(b.masks), b.mask_stride);
+                     b.f.tape, b.f.queue);
   return hipGetLastError();
 }
 

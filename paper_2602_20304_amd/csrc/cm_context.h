@@ -54,7 +54,7 @@ struct cm_context {
   std::string noalloc_error;
   void* d_work = nullptr;      // fused path: queue counter, order, keys
   size_t work_cap = 0;
-  void* d_bwd = nullptr;       // backward workspace: pool and work-queue counters, the adjoint's tape (records, index pool), group face masks
+  void* d_bwd = nullptr;       // backward workspace: pool and work-queue counters, the adjoint's tape (records, index pool)
   size_t bwd_cap = 0;
   // fused path: size-class plan (per K), tuned block sizes, captured graphs
   int geom_version = 0;

@@ -46,15 +46,21 @@ struct FwdLaunch {
 // scores and the int32 list of filtered candidates (both nvs + 2 nee long),
 // then room for both bodies' edge arrays (float64, used when they do not fit
 // in LDS), then per edge the float64 value-query shift of the other body
-// along its segment (A's edges, then B's; see PairEngine::cull).
+// along its segment (A's edges, then B's; see PairEngine::cull), then a copy
+// of the candidate pass's group face masks (for the queries of filtered
+// candidates, after the LDS that holds them has been reused).
 __host__ __device__ inline long long scratch_edges_offset(int maxV, int maxE) {
   return 8LL * maxE * maxE + 2 * (2LL * maxE * maxE + 2LL * maxV) + 128;
 }
 __host__ __device__ inline long long scratch_shift_offset(int maxV, int maxE) {
   return scratch_edges_offset(maxV, maxE) + 24LL * maxE;
 }
-__host__ __device__ inline long long fwd_scratch_floats(int maxV, int maxE) {
+constexpr int kFaceMaskBytes = 72;   // a face mask: 8 words and a count
+__host__ __device__ inline long long scratch_mask_offset(int maxV, int maxE) {
   return scratch_shift_offset(maxV, maxE) + 4LL * maxE;
+}
+__host__ __device__ inline long long fwd_scratch_floats(int maxV, int maxE) {
+  return scratch_mask_offset(maxV, maxE) + 4LL * ((maxE + 7) / 8) * kFaceMaskBytes / 4;
 }
 
 struct CotDev {
@@ -76,12 +82,7 @@ struct BwdLaunch {
   FwdLaunch f;
   CotDev cot;
   GradDev gr;
-  void* masks = nullptr;       // per workgroup, mask_stride bytes: the candidate pass's group face
-  long long mask_stride = 0;   // masks kept for the window's queries (null: every query visits all faces)
 };
-// Bytes of one workgroup's group face masks (bwd_mask_bytes): 0 when the
-// context's polytopes have too many faces to be culled.
-long long bwd_mask_bytes(int maxE, int maxF);
 
 int fwd_lds_bytes(int maxV, int maxE, int maxF, int block, int kmax, bool presel = false, bool edges_out = false);
 int bwd_lds_bytes(int maxV, int maxE, int maxF, int block, bool presel = false);

@@ -55,6 +55,7 @@ struct LdsLayout {
 constexpr int kLdsBudget = 160 * 1024 - 1024;
 // Virtual threads of the column LSE's chunking (the same in every block size).
 constexpr int kColSlots = 256;
+static_assert(sizeof(FaceMask) == kFaceMaskBytes, "the scratch copy of the group masks is sized for this");
 
 // 64-bit words of a face mask (0: culling off): the fewest powers of two
 // covering maxF faces, up to kMaxMaskWords (512 faces); larger polytopes
@@ -142,6 +143,7 @@ struct PairEngine {
   FaceMask* sG2;             // [ceil(maxE / 8)][2] the same for B's edges
   double* gShift;            // scratch [2][maxE]: per edge of A the shift of B's value queries on it, then
                              // per edge of B that of A's (kNoShift: none), see cull()
+  FaceMask* gMask;           // scratch copy of sG1 ([ceil(maxE / 8)][2]) then sG2, made by cull()
   int MW;
   double* Dbuf;   // [maxE^2] unsigned distance of edge pair (k, l) at k * neB + l
   double* Al1;    // [maxE^2] QP solution al1, al2 and ln con of the same edge pair
@@ -198,6 +200,7 @@ struct PairEngine {
     Sbuf = reinterpret_cast<float*>(Lcon + mm);
     List = reinterpret_cast<int*>(Sbuf + 2 * mm + 2LL * maxV_);
     gShift = reinterpret_cast<double*>(slot + scratch_shift_offset(maxV_, maxE_));
+    gMask = reinterpret_cast<FaceMask*>(slot + scratch_mask_offset(maxV_, maxE_));
     T = make_temp(prm);
     lam = prm.lam;
     flags = prm.flags;
@@ -466,6 +469,46 @@ struct PairEngine {
       gShift[i] = onA ? sB : sA;   // the other body's (the own body's queries are surface ones)
     }
     __syncthreads();
+    // a copy for the filtered candidates' queries (records overwrite sG1 / sG2)
+    if (!union_masks()) return;
+    const int gw = int(sizeof(FaceMask) / 8), nA = 2 * ngA, nB = 2 * ngB, gB0 = 2 * ((maxE + 7) >> 3);
+    for (int i = tid; i < (nA + nB) * gw; i += BLOCK) {
+      const int m = i / gw, w = i - m * gw;
+      const unsigned long long* src = reinterpret_cast<const unsigned long long*>(m < nA ? sG1 + m : sG2 + (m - nA));
+      reinterpret_cast<unsigned long long*>(m < nA ? gMask + m : gMask + gB0 + (m - nA))[w] = src[w];
+    }
+  }
+  // The union of the group masks of a wave's candidates idx (lanes with act)
+  // into U[0..3]: A's and B's faces near witness 1, A's and B's near witness
+  // 2 (LDS, this wave's), for queries that all the wave's lanes share;
+  // returns U, or null when a lane holds a vertex candidate (or none is
+  // active, or union_masks() is false).  Every lane of the wave calls it.
+  // For pairs whose polytopes have at most 64 faces the walks save less
+  // than the union costs (measured on hulls of 32 points); a property of the
+  // pair, so that every launch shape decides alike.
+  __device__ __forceinline__ bool union_masks() const { return MW > 0 && (A.nf > 64 || B.nf > 64); }
+  __device__ __forceinline__ const FaceMask* wave_union(bool act, int idx, FaceMask* U) const {
+    if (!union_masks() || ps.nee == 0) return nullptr;
+    const bool eecand = act && idx >= ps.nvs;
+    if (__ballot(act && !eecand) != 0ull || __ballot(eecand) == 0ull) return nullptr;
+    if (lane < 4 * MW) U[lane / MW].w[lane - (lane / MW) * MW] = 0ull;
+    if (lane < 4) U[lane].n = MW;
+    wave_lds_sync();
+    if (eecand) {
+      const int ee_i = (idx - ps.nvs) >> 1;
+      const int k = ee_i / B.ne, l = ee_i - k * B.ne;
+      const FaceMask* g1 = gMask + 2 * (k >> 3);
+      const FaceMask* g2 = gMask + 2 * ((maxE + 7) >> 3) + 2 * (l >> 3);
+      for (int w = 0; w < MW; ++w) {
+        const unsigned long long a0 = g1[0].w[w], a1 = g1[1].w[w], a2 = g2[0].w[w], a3 = g2[1].w[w];
+        if (a0) atomicOr(&U[0].w[w], a0);
+        if (a1) atomicOr(&U[1].w[w], a1);
+        if (a2) atomicOr(&U[2].w[w], a2);
+        if (a3) atomicOr(&U[3].w[w], a3);
+      }
+    }
+    wave_lds_sync();
+    return U;
   }
   // OR the faces of V near segment [p0w, p1w] (pair frame) into out[MW];
   // returns a shift for V's value queries at points of the segment, or
@@ -547,7 +590,8 @@ struct PairEngine {
   }
   // candidate idx in the fixed order: A's vertices, B's vertices, E-E (k, l)
   // row-major with witness 1 before witness 2
-  __device__ __forceinline__ void candidate(int idx, Cand& c) const {
+  // U: the wave's union masks (wave_union) for an E-E candidate, or null.
+  __device__ __forceinline__ void candidate(int idx, Cand& c, const FaceMask* U = nullptr) const {
     if (idx < ps.nvs) {
       vs(idx, c);
     } else {
@@ -555,7 +599,7 @@ struct PairEngine {
       const int ee_i = e >> 1;
       const int k = ee_i / B.ne, l = ee_i - k * B.ne;
       Cand c1, c2;
-      ee(k, l, c1, c2);
+      ee(k, l, c1, c2, U, U ? U + 2 : nullptr, U ? gShift[k] : kNoShift, U ? gShift[A.ne + l] : kNoShift);
       c = (e & 1) ? c2 : c1;
     }
   }
@@ -824,9 +868,9 @@ struct PairEngine {
     return List[min(ps.ncand, reg * seg) + (p - off)];
   }
   // Candidate idx evaluated into this thread's record.
-  __device__ __forceinline__ void record(int idx) {
+  __device__ __forceinline__ void record(int idx, const FaceMask* U = nullptr) {
     Cand c;
-    candidate(idx, c);
+    candidate(idx, c, U);
     Rec& rr = sRec[tid];
     rr.s = c.s; rr.d = c.d;
     rr.px = float(c.p.x); rr.py = float(c.p.y); rr.pz = float(c.p.z);
@@ -842,18 +886,25 @@ struct PairEngine {
   // (device memory); otherwise the stored scores are scanned.  full = false:
   // only the records' candidate indices are written (a body that evaluates
   // the candidates itself).
+  // um: LDS for 4 face masks per wave, through which the records of a wave
+  // of E-E candidates query (wave_union; the values differ from the
+  // all-faces ones by less than 2^-38 relative), or null.
   template <typename F>
   __device__ __forceinline__ void for_window(const int* __restrict__ lst, int ntape,
                                              const unsigned long long* __restrict__ mask, F&& body, double taus,
-                                             bool full = true) {
+                                             bool full = true, FaceMask* um = nullptr) {
     const int tot = ntape >= 0 ? ntape : window(taus, mask);
     if (ntape < 0 && tot == 0) __syncthreads();   // sCnt is rewritten by the next call
     for (int base = 0; base < tot; base += BLOCK) {
       const int p = base + tid;
+      int idx = 0;
       if (p < tot) {
-        int idx = ntape >= 0 ? lst[p] : list_at(p);
+        idx = ntape >= 0 ? lst[p] : list_at(p);
         if (idx < 0 || idx >= ps.ncand) idx = 0;   // a recorded list holds valid indices; never read past the pair
-        if (full) record(idx);
+      }
+      const FaceMask* U = (full && um != nullptr) ? wave_union(p < tot, idx, um + 4 * wave) : nullptr;
+      if (p < tot) {
+        if (full) record(idx, U);
         else sRec[tid].idx = idx;
       }
       __syncthreads();
@@ -862,8 +913,8 @@ struct PairEngine {
     }
   }
   template <typename F>
-  __device__ __forceinline__ void for_filtered(F&& body, double taus = kFilterTaus) {
-    for_window(nullptr, -1, nullptr, body, taus);
+  __device__ __forceinline__ void for_filtered(F&& body, double taus = kFilterTaus, FaceMask* um = nullptr) {
+    for_window(nullptr, -1, nullptr, body, taus, true, um);
   }
 
   // ------------------------------------------------------------ SoftSort
@@ -881,6 +932,8 @@ struct PairEngine {
     double a[9];
 #pragma unroll
     for (int f = 0; f < 9; ++f) a[f] = 0.0;
+    // the per-wave union masks of the records live in the reduction slots,
+    // which nothing else uses here (topk is done)
     for_filtered([&](int tot) {
       if (!act) return;
       for (int r = j0; r < tot; r += G) {
@@ -896,7 +949,7 @@ struct PairEngine {
         a[7] = fma(e, rr.d, a[7]);
         a[8] = fma(e, double(rr.w), a[8]);
       }
-    });
+    }, kFilterTaus, CULL ? reinterpret_cast<FaceMask*>(sRed) : nullptr);
     for (int off = G >> 1; off > 0; off >>= 1) {
 #pragma unroll
       for (int f = 0; f < 9; ++f) a[f] += __shfl_xor(a[f], off);
