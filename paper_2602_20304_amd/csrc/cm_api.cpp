@@ -426,6 +426,8 @@ cm_status ctx_prepare_fwd(cm_context* ctx, const BatchDev& bd, const ParamsDev& 
   f->block = block;
   f->kmax = kmax_for(pd.K);
   f->order = nullptr; f->range = nullptr; f->queue = dynamic ? reinterpret_cast<int*>(1) : nullptr;   // dispatch hint
+  // (dynamic: the caller gives the launch a work-queue counter; the grid and
+  // occupancy are those of the work-queue instantiation)
   const int lds = fwd_lds_bytes(f->maxV, f->maxE, f->maxF, block, f->kmax, pd.presel_v > 0);
   if (lds > 160 * 1024)
     return cm_fail(ctx, CM_ERR_INVALID_ARG, "the context's largest geometry needs " + std::to_string(lds) +
@@ -434,7 +436,7 @@ cm_status ctx_prepare_fwd(cm_context* ctx, const BatchDev& bd, const ParamsDev& 
   const int occ = fwd_place_edges(*f);
   f->queue = nullptr;
   f->grid = std::max(1, occ * ctx->num_cus);
-  if (od.capacity > 0 && f->grid > od.capacity && !dynamic) f->grid = std::max(1, od.capacity);
+  if (od.capacity > 0 && f->grid > od.capacity) f->grid = std::max(1, od.capacity);
   f->scratch_stride = fwd_scratch_floats(f->maxV, f->maxE);
   const size_t need = size_t(f->grid) * size_t(f->scratch_stride) * sizeof(float);
   hipError_t e = ctx_ensure(ctx, reinterpret_cast<void**>(&ctx->d_scratch), &ctx->scratch_cap, need);
@@ -455,14 +457,24 @@ extern "C" cm_status cm_collide(cm_context* ctx, const cm_batch* batch, const cm
   hipStream_t st = static_cast<hipStream_t>(stream);
   if ((s = ctx_order(ctx, st)) != CM_OK) return s;
   FwdLaunch f;
-  if (od.capacity > 0 && (s = ctx_prepare_fwd(ctx, bd, pd, od, 256, false, &f)) != CM_OK) return s;
+  // workgroups take pairs from a work queue (an atomic counter) so that
+  // uneven pair costs do not leave a tail; traced witnesses keep the
+  // static order
+  const bool dyn = pd.refine == 0;
+  if (od.capacity > 0 && (s = ctx_prepare_fwd(ctx, bd, pd, od, 256, dyn, &f)) != CM_OK) return s;
   if (od.tape && od.capacity > 0 && !tape_layout(od.tape, od.tape_bytes, od.capacity, pd.K, &f.tape))
     return cm_fail(ctx, CM_ERR_INVALID_ARG, "the tape is smaller than cm_tape_bytes gives for this capacity and K");
+  if (od.capacity > 0 && dyn) {
+    hipError_t e = ctx_ensure(ctx, reinterpret_cast<void**>(&ctx->d_fwd_queue), &ctx->fwd_queue_cap, 256);
+    if (e != hipSuccess) return cm_hip(ctx, e, "forward work queue");
+    f.queue = ctx->d_fwd_queue;
+  }
   hipEvent_t t0 = timer_begin(ctx, st);
   if ((s = ctx_broadphase(ctx, bd, pd, od, st)) != CM_OK) return s;
   timer_end(ctx, CM_TIMER_BROADPHASE, t0, st);
   if (od.capacity > 0) {
     if (f.tape.base && (s = cm_hip(ctx, launch_tape_reset(f.tape, st), "tape reset")) != CM_OK) return s;
+    if (f.queue && (s = cm_hip(ctx, launch_counter_reset(f.queue, st), "work queue reset")) != CM_OK) return s;
     t0 = timer_begin(ctx, st);
     if ((s = cm_hip(ctx, launch_collide_fwd(f, st), "collide launch")) != CM_OK) return s;
     timer_end(ctx, CM_TIMER_FORWARD, t0, st);
@@ -715,7 +727,14 @@ extern "C" cm_status cm_collide_backward(cm_context* ctx, const cm_batch* batch,
     return cm_fail(ctx, CM_ERR_INVALID_ARG, "the tape is smaller than cm_tape_bytes gives for this capacity and K");
   const long long pool_cap = od.tape ? 0 : tape_default_pool(ctx, od.capacity);
   FwdLaunch f1;
-  if (pool_cap > 0 && (s = ctx_prepare_fwd(ctx, bd, pd, od, 256, false, &f1)) != CM_OK) return s;
+  const bool dyn1 = pd.refine == 0;   // the tape forward takes pairs from a work queue too
+  if (pool_cap > 0 && (s = ctx_prepare_fwd(ctx, bd, pd, od, 256, dyn1, &f1)) != CM_OK) return s;
+  if (pool_cap > 0 && dyn1) {
+    if ((e = ctx_ensure(ctx, reinterpret_cast<void**>(&ctx->d_fwd_queue), &ctx->fwd_queue_cap, 256)) != hipSuccess)
+      return cm_hip(ctx, e, "forward work queue");
+    if ((e = launch_counter_reset(ctx->d_fwd_queue, st)) != hipSuccess) return cm_hip(ctx, e, "work queue reset");
+    f1.queue = ctx->d_fwd_queue;
+  }
   const size_t need = size_t(b.f.grid) * size_t(b.f.scratch_stride) * sizeof(float);
   if ((e = ctx_ensure(ctx, reinterpret_cast<void**>(&ctx->d_scratch), &ctx->scratch_cap, need)) != hipSuccess)
     return cm_hip(ctx, e, "backward scratch");
@@ -726,7 +745,7 @@ extern "C" cm_status cm_collide_backward(cm_context* ctx, const cm_batch* batch,
   if ((e = ctx_ensure(ctx, &ctx->d_bwd, &ctx->bwd_cap, size_t(bytes))) != hipSuccess)
     return cm_hip(ctx, e, "adjoint workspace");
   int* queue = reinterpret_cast<int*>(static_cast<char*>(ctx->d_bwd) + 128);
-  if ((e = hipMemsetAsync(queue, 0, sizeof(int), st)) != hipSuccess) return cm_hip(ctx, e, "zero work queue");
+  if ((e = launch_counter_reset(queue, st)) != hipSuccess) return cm_hip(ctx, e, "work queue reset");
   b.f.queue = queue;
   if (pool_cap > 0) {
     tape_layout(static_cast<char*>(ctx->d_bwd), bytes, od.capacity, pd.K, &tv);

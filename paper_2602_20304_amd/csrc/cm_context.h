@@ -54,6 +54,8 @@ struct cm_context {
   std::string noalloc_error;
   void* d_work = nullptr;      // fused path: queue counter, order, keys
   size_t work_cap = 0;
+  int* d_fwd_queue = nullptr;  // the plain forward's work-queue counter
+  size_t fwd_queue_cap = 0;
   void* d_bwd = nullptr;       // backward workspace: pool and work-queue counters, the adjoint's tape (records, index pool)
   size_t bwd_cap = 0;
   // fused path: size-class plan (per K), tuned block sizes, captured graphs
@@ -98,7 +100,7 @@ struct cm_context {
     auto F = [](void* p) { if (p) hipFree(p); };
     F(d.recs); F(d.vx); F(d.vy); F(d.vz); F(d.e0); F(d.e1); F(d.fnx); F(d.fny); F(d.fnz); F(d.fo);
     F(d.f0); F(d.f1); F(d.f2);
-    F(d_err); F(d_tile_sums); F(d_scratch); F(d_work); F(d_bwd); F(d_fused);
+    F(d_err); F(d_tile_sums); F(d_scratch); F(d_work); F(d_bwd); F(d_fwd_queue); F(d_fused);
     drop_graphs();
     for (auto& t : timers) {
       for (auto& pr : t.pending) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }

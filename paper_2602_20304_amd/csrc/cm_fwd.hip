@@ -243,6 +243,15 @@ __global__ void tape_reset(unsigned long long* counter) {
   if (threadIdx.x == 0) *counter = 0ull;
 }
 
+__global__ void counter_reset(int* counter) {
+  if (threadIdx.x == 0) *counter = 0;
+}
+
+hipError_t launch_counter_reset(int* counter, hipStream_t st) {
+  hipLaunchKernelGGL(counter_reset, dim3(1), dim3(64), 0, st, counter);
+  return hipGetLastError();
+}
+
 hipError_t launch_tape_reset(const TapeDev& t, hipStream_t st) {
   hipLaunchKernelGGL(tape_reset, dim3(1), dim3(64), 0, st, t.pool_used);
   return hipGetLastError();

@@ -91,6 +91,8 @@ hipError_t launch_collide_bwd(const BwdLaunch& b, hipStream_t st);
 int fwd_occupancy(const FwdLaunch& f);
 // Zeroes the tape's pool counter (a kernel, so it can sit in a captured graph).
 hipError_t launch_tape_reset(const TapeDev& t, hipStream_t st);
+// Zeroes a work-queue counter (a kernel, likewise).
+hipError_t launch_counter_reset(int* counter, hipStream_t st);
 // Byte layout of a caller-owned tape of `bytes` for `capacity` pairs at K:
 // counter (256 B), records, pool.  Returns false when it is too small.
 inline long long tape_records_bytes(long long capacity, int K) { return (capacity * tape_stride(K) + 255) & ~255LL; }
