@@ -54,6 +54,7 @@ struct Request {
   bool want_bwd = false, want_geom = false;
   int32_t n_scenes = 0, n_bodies = 0, capacity = 0;
   int64_t pool = 0, n_geoms = 0;   // vertex pool and geometry count the gradients are laid out for
+  int64_t tape_pool = 0;           // index-pool entries of a backward request's adjoint tape
   uint64_t footprint = 0, host_bytes = 0;
   double t_submit = 0, t_start = 0, t_done = 0;
   enum State { PENDING, RUNNING, DONE, FAILED } state = PENDING;
@@ -187,11 +188,22 @@ uint64_t footprint(const Request& r, long long grid, long long stride) {
   b += 8ull + 8ull * cap + 32ull * cap * K;                                        // error, n_pairs, pairs, outputs
   b += 4ull * (r.n_scenes / 1024 + 2);                                             // scan tiles
   b += 4ull * uint64_t(grid) * uint64_t(stride);                                   // per-workgroup scratch
+  b += 512;                                                                       // work-queue counters
   if (r.want_bwd) {
     b += 32ull * cap * K + 24ull * r.n_bodies + 4ull;                              // cotangents, g_pose, g_tau
     if (r.want_geom) b += 12ull * uint64_t(r.pool) + 16ull * uint64_t(r.n_geoms);   // g_vertices, g_params
+    b += 256ull + uint64_t(tape_records_bytes(int64_t(cap), K)) + 4ull * uint64_t(r.tape_pool);   // adjoint tape
   }
   return b + 64 * 256;
+}
+
+// Index-pool entries of a served backward request's adjoint tape: what every
+// pair's window could fill, at most 4,096 entries a pair on average and the
+// pool limit of the direct backward (a pair whose window no longer fits is
+// recomputed whole by the adjoint, so the bound costs time, not results).
+int64_t served_tape_pool(const cm_context* ctx, size_t cap) {
+  const int64_t per_pair = std::min<int64_t>(2LL * ctx->maxV + 2LL * ctx->maxE * ctx->maxE, 4096);
+  return std::max<int64_t>(2, std::min<int64_t>(int64_t(cap) * per_pair, 1LL << 28));
 }
 
 void launch_request(cm_server* srv, Request& r) {
@@ -218,10 +230,15 @@ void launch_request(cm_server* srv, Request& r) {
   FwdLaunch f;
   f.tb = ctx_tables(ctx);
   f.maxV = std::max(ctx->maxV, 1); f.maxE = std::max(ctx->maxE, 1); f.maxF = std::max(ctx->maxF, 1);
-  f.block = 256; f.kmax = kmax_for(K); f.order = nullptr; f.range = nullptr; f.queue = nullptr;
+  f.block = 256; f.kmax = kmax_for(K); f.order = nullptr; f.range = nullptr;
+  // workgroups take pairs from a work queue (traced witnesses keep the
+  // static order); the hint selects the work-queue kernel's occupancy
+  const bool dyn = pd.refine == 0;
+  f.queue = dyn ? reinterpret_cast<int*>(1) : nullptr;
   // grid already folded into the footprint: recompute the same value
   f.prm = pd;
   const int occ = fwd_place_edges(f);
+  f.queue = nullptr;
   f.grid = int(request_grid(ctx, occ, cap));
   f.scratch_stride = fwd_scratch_floats(f.maxV, f.maxE);
   if (hipMallocAsync(&r.dev, size_t(r.footprint), st) != hipSuccess) { r.status = CM_ERR_OOM; return; }
@@ -236,6 +253,16 @@ void launch_request(cm_server* srv, Request& r) {
   float* d_out = c.take<float>(8 * cap * K);
   int32_t* d_tiles = c.take<int32_t>(r.n_scenes / 1024 + 2);
   float* d_scr = c.take<float>(size_t(f.grid) * size_t(f.scratch_stride));
+  int* d_fq = c.take<int>(64);   // forward work-queue counter
+  int* d_bq = c.take<int>(64);   // adjoint work-queue counter
+  TapeDev tv;
+  if (r.want_bwd) {
+    // the forward records the adjoint's tape (s_[k], SoftSort row sums, each
+    // pair's window) beside its outputs; the adjoint reads it back
+    const long long tb = 256 + tape_records_bytes((long long)cap, K) + 4LL * r.tape_pool;
+    char* d_tape = c.take<char>(size_t(tb));
+    tape_layout(d_tape, tb, (long long)cap, K, &tv);
+  }
   f.err = d_err;
   (void)hipMemsetAsync(d_err, 0, sizeof(uint32_t), st);
   (void)hipMemcpyAsync(d_bo, r.body_offsets.data(), 4 * r.body_offsets.size(), hipMemcpyHostToDevice, st);
@@ -244,7 +271,11 @@ void launch_request(cm_server* srv, Request& r) {
   BatchDev bd{r.n_scenes, r.n_bodies, 0, d_bo, d_bg, d_pose, nullptr, nullptr};
   OutDev od{int32_t(cap), d_np, d_off, d_pairs, d_out, d_out + 3 * cap * K, d_out + 6 * cap * K, d_out + 7 * cap * K};
   f.bt = bd; f.out = od; f.scratch = d_scr;
+  if (dyn) f.queue = d_fq;
+  if (r.want_bwd) f.tape = tv;
   if (launch_broadphase(f.tb, bd, pd.margin, od, d_tiles, d_err, st) != hipSuccess ||
+      (dyn && launch_counter_reset(d_fq, st) != hipSuccess) ||
+      (r.want_bwd && launch_tape_reset(tv, st) != hipSuccess) ||
       launch_collide_fwd(f, st) != hipSuccess) {
     r.status = CM_ERR_DEVICE;
     return;
@@ -275,11 +306,16 @@ void launch_request(cm_server* srv, Request& r) {
     }
     BwdLaunch b;
     b.f = f;
-    b.f.queue = nullptr;   // the forward's queue is spent: pairs round-robin
+    b.f.queue = d_bq;      // the adjoint's own work queue
+    b.f.tape = tv;
+    b.f.tape.pool_used = nullptr;
     b.cot = CotDev{d_cp, d_cn, d_cd, d_cw};
     b.gr = GradDev{d_gpose, d_gvert, d_gpar, d_gtau, (long long)r.pool};
     b.f.grid = int(std::min<long long>(request_grid(ctx, bwd_occupancy(b), cap), f.grid));   // fits the forward's scratch
-    if (launch_collide_bwd(b, st) != hipSuccess) { r.status = CM_ERR_DEVICE; return; }
+    if (launch_counter_reset(d_bq, st) != hipSuccess || launch_collide_bwd(b, st) != hipSuccess) {
+      r.status = CM_ERR_DEVICE;
+      return;
+    }
     (void)hipMemcpyAsync(r.h_gpose, d_gpose, 24 * size_t(r.n_bodies), hipMemcpyDeviceToHost, st);
     (void)hipMemcpyAsync(r.h_gtau, d_gtau, 4, hipMemcpyDeviceToHost, st);
     if (r.want_geom) {
@@ -458,12 +494,14 @@ cm_status cm_server_submit(cm_server* srv, const cm_request* q, uint64_t* ticket
   FwdLaunch f{};
   f.tb = ctx_tables(ctx);
   f.maxV = std::max(ctx->maxV, 1); f.maxE = std::max(ctx->maxE, 1); f.maxF = std::max(ctx->maxF, 1);
-  f.block = 256; f.kmax = kmax_for(K); f.queue = nullptr;
+  f.block = 256; f.kmax = kmax_for(K);
+  f.queue = q->params.refine_steps == 0 ? reinterpret_cast<int*>(1) : nullptr;   // work-queue kernel's occupancy
   f.prm.presel_v = presel ? q->params.presel_vertices : 0;   // selects the kernel whose occupancy applies
   f.prm.presel_e = presel ? q->params.presel_edges : 0;
   f.prm.sq = ctx->has_sq ? 1 : 0;
   f.prm.refine = q->params.refine_steps;
   const long long grid = request_grid(ctx, fwd_place_edges(f), cap);
+  if (r->want_bwd) r->tape_pool = served_tape_pool(ctx, cap);
   r->footprint = footprint(*r, grid, fwd_scratch_floats(f.maxV, f.maxE));
   r->host_bytes = host_bytes(*r);
   if (r->footprint > srv->budget)
