@@ -262,7 +262,8 @@ cm_status cm_geometry_destroy(cm_context* ctx, const int32_t* ids, int32_t n);
  * Broadphase (keep a candidate pair iff its float32 bounding spheres overlap
  * within cull_margin), per-scene compaction, then the contact manifold of
  * every kept pair (Sec. IV-C, IV-D, soft top-K of Sec. III).  The plain
- * kernel: one workgroup per pair, static round-robin over pairs. */
+ * kernel: one workgroup per pair; workgroups take pairs in batch order from a
+ * work queue (static round-robin with traced witnesses, refine_steps > 0). */
 cm_status cm_collide(cm_context* ctx, const cm_batch* batch, const cm_params* prm, cm_manifold* out,
                      void* stream);
 
