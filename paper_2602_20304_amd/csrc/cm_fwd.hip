@@ -144,11 +144,15 @@ __global__ __launch_bounds__(256) void bp_emit(Tables tb, BatchDev bt, float mar
 
 // ============================================================ per-pair manifold
 
-// Occupancy target: 3 waves per SIMD (<= 168 VGPRs) for K <= 8, where the
-// per-lane top-K list is short enough to fit with a handful of spills; 2
-// otherwise.
+// Occupancy target: 4 waves per SIMD (<= 128 VGPRs, the rest spilled to
+// private memory) for K <= 8, where the per-lane top-K list is short; 2
+// otherwise.  At K <= 8 the extra waves hide more of the float64 latency
+// than the spills cost (hulls of 64 points: 709 ms at 3 waves, 623 at 4;
+// 5 waves gave 600 there but 122 ms against 97 on the mixed scenes, whose
+// LDS holds no fifth wave).  At K = 16 the largest uneven pairs fill a CU's
+// LDS with two workgroups, so a tighter register budget only adds spills.
 template <int BLOCK, int KMAX, bool DYN, bool PRESEL = false, bool SQ = false, bool REFINE = false>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu((KMAX <= 8 && !SQ && !REFINE) ? 3 : 2)))
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu((KMAX <= 8 && !SQ && !REFINE) ? 4 : 2)))
 void collide_fwd(Tables tb, BatchDev bt, ParamsDev prm, OutDev out,
                                                      float* __restrict__ scratch, long long scratch_stride, int maxV,
                                                      int maxE, int maxF, const int* __restrict__ order,
