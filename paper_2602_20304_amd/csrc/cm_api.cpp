@@ -702,7 +702,7 @@ extern "C" cm_status cm_collide_backward(cm_context* ctx, const cm_batch* batch,
   if (lds > 160 * 1024)
     return cm_fail(ctx, CM_ERR_INVALID_ARG, "the context's largest geometry needs " + std::to_string(lds) +
                                                 " B of LDS for this adjoint (160 KiB per workgroup)");
-  int occ = bwd_occupancy(b);
+  int occ = bwd_place(b);
   // When LDS holds one 256-thread workgroup per CU (one wave per SIMD), a
   // 512-thread one brings two waves per SIMD to the same LDS (the full
   // method on the basic primitives has that variant)
@@ -710,6 +710,8 @@ extern "C" cm_status cm_collide_backward(cm_context* ctx, const cm_batch* batch,
       bwd_lds_bytes(b.f.maxV, b.f.maxE, b.f.maxF, 512, false) <= 160 * 1024) {
     BwdLaunch b5 = b;
     b5.f.block = 512;
+    b5.f.hi_occ = 0;
+    b5.f.edges_out = 0;
     const int occ5 = bwd_occupancy(b5);
     if (occ5 * 8 > occ * 4) { b = b5; occ = occ5; }
   }

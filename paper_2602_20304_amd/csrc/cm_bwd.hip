@@ -84,19 +84,23 @@ struct BwdArgs {
 // Two waves per SIMD (256 registers a lane, some spilled to private memory)
 // for the kernels without the extended primitives, whose dual-number
 // queries would spill several times more; those take one.
-template <int BLOCK, int KMAX, bool PRESEL, bool SQ, bool REFINE = false>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SQ ? 1 : 2))) void collide_bwd(Tables tb, BatchDev bt, ParamsDev prm, OutDev fwd, BwdArgs ga,
-                                                     float* __restrict__ scratch, long long scratch_stride, int maxV,
-                                                     int maxE, int maxF, unsigned* err, TapeDev tape,
-                                                     int* __restrict__ queue) {
+// WAVES > 0 overrides the target: the full method's 256-thread kernel has a
+// 3-wave variant, taken where LDS (edge arrays in the scratch slot) leaves
+// room for a third workgroup per CU.
+template <int BLOCK, int KMAX, bool PRESEL, bool SQ, bool REFINE = false, int WAVES = 0>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WAVES > 0 ? WAVES : (SQ ? 1 : 2))))
+void collide_bwd(Tables tb, BatchDev bt, ParamsDev prm, OutDev fwd, BwdArgs ga, float* __restrict__ scratch,
+                 long long scratch_stride, int maxV, int maxE, int maxF, unsigned* err, TapeDev tape,
+                 int* __restrict__ queue, int edges_out) {
   extern __shared__ float4 smem4[];
   char* smem = reinterpret_cast<char*>(smem4);
   __shared__ PairShared ps;
   const int extra = bwd_extra_bytes(maxV, maxE, maxF, BLOCK, PRESEL);
   PairEngine<BLOCK, KMAX, true, PRESEL, SQ, REFINE> P(ps, smem, tb, bt, prm, scratch + (long long)blockIdx.x * scratch_stride,
-                                                  maxV, maxE, maxF, extra);
+                                                  maxV, maxE, maxF, extra, edges_out != 0);
   // the engine's pre-selection arrays sit right after its own layout
-  const BwdLds L = bwd_layout(lds_layout(maxE, maxF, BLOCK, extra).bytes + (PRESEL ? presel_lds_bytes(maxV, maxE) : 0),
+  const BwdLds L = bwd_layout(lds_layout(maxE, maxF, BLOCK, extra, edges_out != 0).bytes +
+                                  (PRESEL ? presel_lds_bytes(maxV, maxE) : 0),
                               maxV, maxE, maxF, BLOCK, PRESEL);
   float* vA3 = reinterpret_cast<float*>(smem + L.vA);
   float* vB3 = reinterpret_cast<float*>(smem + L.vB);
@@ -857,33 +861,38 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SQ ? 1 : 
   }
 }
 
-int bwd_lds_bytes(int maxV, int maxE, int maxF, int block, bool presel) {
+int bwd_lds_bytes(int maxV, int maxE, int maxF, int block, bool presel, bool edges_out) {
   const int extra = bwd_extra_bytes(maxV, maxE, maxF, block, presel);
   const int pre = presel ? presel_lds_bytes(maxV, maxE) : 0;
-  return bwd_layout(lds_layout(maxE, maxF, block, extra).bytes + pre, maxV, maxE, maxF, block, presel).bytes;
+  return bwd_layout(lds_layout(maxE, maxF, block, extra, edges_out).bytes + pre, maxV, maxE, maxF, block, presel).bytes;
 }
 
-template <int BLOCK, int KMAX, bool PRESEL, bool SQ, bool REFINE = false>
+template <int BLOCK, int KMAX, bool PRESEL, bool SQ, bool REFINE = false, int WAVES = 0>
 static hipError_t launch_bwd_t(const BwdLaunch& b, hipStream_t st) {
-  const int lds = bwd_lds_bytes(b.f.maxV, b.f.maxE, b.f.maxF, BLOCK, PRESEL);
+  const int lds = bwd_lds_bytes(b.f.maxV, b.f.maxE, b.f.maxF, BLOCK, PRESEL, b.f.edges_out != 0);
   BwdArgs ga{b.cot, b.gr};
-  hipLaunchKernelGGL((collide_bwd<BLOCK, KMAX, PRESEL, SQ, REFINE>), dim3(b.f.grid), dim3(BLOCK), lds, st, b.f.tb, b.f.bt,
-                     b.f.prm, b.f.out, ga, b.f.scratch, b.f.scratch_stride, b.f.maxV, b.f.maxE, b.f.maxF, b.f.err,
-                     b.f.tape, b.f.queue);
+  hipLaunchKernelGGL((collide_bwd<BLOCK, KMAX, PRESEL, SQ, REFINE, WAVES>), dim3(b.f.grid), dim3(BLOCK), lds, st, b.f.tb,
+                     b.f.bt, b.f.prm, b.f.out, ga, b.f.scratch, b.f.scratch_stride, b.f.maxV, b.f.maxE, b.f.maxF,
+                     b.f.err, b.f.tape, b.f.queue, b.f.edges_out);
   return hipGetLastError();
 }
 
-template <int BLOCK, int KMAX, bool PRESEL, bool SQ, bool REFINE = false>
+template <int BLOCK, int KMAX, bool PRESEL, bool SQ, bool REFINE = false, int WAVES = 0>
 static int bwd_occ_t(const BwdLaunch& b) {
   int nb = 0;
-  const int lds = bwd_lds_bytes(b.f.maxV, b.f.maxE, b.f.maxF, BLOCK, PRESEL);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, collide_bwd<BLOCK, KMAX, PRESEL, SQ, REFINE>, BLOCK, lds) != hipSuccess)
+  const int lds = bwd_lds_bytes(b.f.maxV, b.f.maxE, b.f.maxF, BLOCK, PRESEL, b.f.edges_out != 0);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, collide_bwd<BLOCK, KMAX, PRESEL, SQ, REFINE, WAVES>, BLOCK,
+                                                   lds) != hipSuccess)
     return 1;
   return nb > 0 ? nb : 1;
 }
 
 template <bool PRESEL, bool SQ>
 static hipError_t launch_bwd_k(const BwdLaunch& b, hipStream_t st) {
+  if (!PRESEL && !SQ && b.f.hi_occ) {   // the 3-wave variant (K <= 16)
+    if (b.f.kmax == 8) return launch_bwd_t<256, 8, false, false, false, 3>(b, st);
+    if (b.f.kmax == 16) return launch_bwd_t<256, 16, false, false, false, 3>(b, st);
+  }
   if (b.f.kmax == 8) return launch_bwd_t<256, 8, PRESEL, SQ>(b, st);
   if (b.f.kmax == 16) return launch_bwd_t<256, 16, PRESEL, SQ>(b, st);
   return launch_bwd_t<256, 32, PRESEL, SQ>(b, st);
@@ -891,6 +900,10 @@ static hipError_t launch_bwd_k(const BwdLaunch& b, hipStream_t st) {
 
 template <bool PRESEL, bool SQ>
 static int bwd_occ_k(const BwdLaunch& b) {
+  if (!PRESEL && !SQ && b.f.hi_occ) {
+    if (b.f.kmax == 8) return bwd_occ_t<256, 8, false, false, false, 3>(b);
+    if (b.f.kmax == 16) return bwd_occ_t<256, 16, false, false, false, 3>(b);
+  }
   if (b.f.kmax == 8) return bwd_occ_t<256, 8, PRESEL, SQ>(b);
   if (b.f.kmax == 16) return bwd_occ_t<256, 16, PRESEL, SQ>(b);
   return bwd_occ_t<256, 32, PRESEL, SQ>(b);
@@ -928,6 +941,24 @@ hipError_t launch_collide_bwd(const BwdLaunch& b, hipStream_t st) {
   }
   if (sq) return ps ? launch_bwd_k<true, true>(b, st) : launch_bwd_k<false, true>(b, st);
   return ps ? launch_bwd_k<true, false>(b, st) : launch_bwd_k<false, false>(b, st);
+}
+
+int bwd_place(BwdLaunch& b) {
+  b.f.hi_occ = 0;
+  b.f.edges_out = 0;
+  const int base = bwd_occupancy(b);
+  // the full method at K <= 16 in 256-thread blocks: the edge arrays in the
+  // scratch slot and the 3-wave register budget, where that fits more
+  // workgroups per CU
+  if (b.f.block == 256 && b.f.kmax <= 16 && b.f.prm.presel_v == 0 && !b.f.prm.sq && b.f.prm.refine == 0) {
+    b.f.hi_occ = 1;
+    b.f.edges_out = 1;
+    const int hi = bwd_occupancy(b);
+    if (hi > base) return hi;
+    b.f.hi_occ = 0;
+    b.f.edges_out = 0;
+  }
+  return base;
 }
 
 int bwd_occupancy(const BwdLaunch& b) {

@@ -147,12 +147,15 @@ __global__ __launch_bounds__(256) void bp_emit(Tables tb, BatchDev bt, float mar
 // Occupancy target: 4 waves per SIMD (<= 128 VGPRs, the rest spilled to
 // private memory) for K <= 8, where the per-lane top-K list is short; 2
 // otherwise.  At K <= 8 the extra waves hide more of the float64 latency
-// than the spills cost (hulls of 64 points: 709 ms at 3 waves, 623 at 4;
-// 5 waves gave 600 there but 122 ms against 97 on the mixed scenes, whose
-// LDS holds no fifth wave).  At K = 16 the largest uneven pairs fill a CU's
-// LDS with two workgroups, so a tighter register budget only adds spills.
-template <int BLOCK, int KMAX, bool DYN, bool PRESEL = false, bool SQ = false, bool REFINE = false>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu((KMAX <= 8 && !SQ && !REFINE) ? 4 : 2)))
+// than the spills cost (hulls of 64 points: 709 ms at 3 waves, 623 at 4).
+// At K = 16 the largest uneven pairs fill a CU's LDS with two workgroups,
+// so a tighter register budget only adds spills (4 waves: 7.64 -> 7.81 s
+// for that class).
+// WAVES > 0 overrides the target (the work-queue kernel of the full method at
+// K 8 has a 5-wave variant, chosen where LDS leaves room for the fifth wave).
+template <int BLOCK, int KMAX, bool DYN, bool PRESEL = false, bool SQ = false, bool REFINE = false, int WAVES = 0>
+__global__ __launch_bounds__(BLOCK)
+__attribute__((amdgpu_waves_per_eu(WAVES > 0 ? WAVES : ((KMAX <= 8 && !SQ && !REFINE) ? 4 : 2))))
 void collide_fwd(Tables tb, BatchDev bt, ParamsDev prm, OutDev out,
                                                      float* __restrict__ scratch, long long scratch_stride, int maxV,
                                                      int maxE, int maxF, const int* __restrict__ order,
@@ -284,9 +287,9 @@ hipError_t launch_broadphase(const Tables& tb, const BatchDev& bt, float margin,
   return hipGetLastError();
 }
 
-template <int BLOCK, int KMAX, bool DYN, bool PRESEL = false, bool SQ = false, bool REFINE = false>
+template <int BLOCK, int KMAX, bool DYN, bool PRESEL = false, bool SQ = false, bool REFINE = false, int WAVES = 0>
 static hipError_t launch_fwd_t(const FwdLaunch& f, hipStream_t st) {
-  auto kern = collide_fwd<BLOCK, KMAX, DYN, PRESEL, SQ, REFINE>;
+  auto kern = collide_fwd<BLOCK, KMAX, DYN, PRESEL, SQ, REFINE, WAVES>;
   const int lds = fwd_lds_bytes(f.maxV, f.maxE, f.maxF, BLOCK, KMAX, PRESEL, f.edges_out != 0);
   hipLaunchKernelGGL(kern, dim3(f.grid), dim3(BLOCK), lds, st, f.tb, f.bt, f.prm, f.out, f.scratch,
                      f.scratch_stride, f.maxV, f.maxE, f.maxF, f.order, f.range, f.queue, f.err, f.edges_out,
@@ -294,11 +297,12 @@ static hipError_t launch_fwd_t(const FwdLaunch& f, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <int BLOCK, int KMAX, bool DYN, bool PRESEL = false, bool SQ = false, bool REFINE = false>
+template <int BLOCK, int KMAX, bool DYN, bool PRESEL = false, bool SQ = false, bool REFINE = false, int WAVES = 0>
 static int occ_t(int maxV, int maxE, int maxF, bool edges_out) {
   int nb = 0;
   const int lds = fwd_lds_bytes(maxV, maxE, maxF, BLOCK, KMAX, PRESEL, edges_out);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, collide_fwd<BLOCK, KMAX, DYN, PRESEL, SQ, REFINE>, BLOCK, lds) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, collide_fwd<BLOCK, KMAX, DYN, PRESEL, SQ, REFINE, WAVES>, BLOCK,
+                                                   lds) != hipSuccess)
     return 1;
   return nb > 0 ? nb : 1;
 }
@@ -372,6 +376,7 @@ hipError_t launch_collide_fwd(const FwdLaunch& f, hipStream_t st) {
   }
   if (f.queue) {
     constexpr bool DYNV = true;
+    if (f.hi_occ && f.block == 256 && f.kmax == 8) return launch_fwd_t<256, 8, true, false, false, false, 5>(f, st);
     if (f.block == 64) {   // single-wave workgroups: the fused path's small pairs
       if (f.kmax == 8) return launch_fwd_t<64, 8, true>(f, st);
       if (f.kmax == 16) return launch_fwd_t<64, 16, true>(f, st);
@@ -412,6 +417,8 @@ int fwd_occupancy(const FwdLaunch& f) {
       if (f.kmax == 16) return occ_t<64, 16, true>(f.maxV, f.maxE, f.maxF, f.edges_out != 0);
       return occ_t<64, 32, true>(f.maxV, f.maxE, f.maxF, f.edges_out != 0);
     }
+    if (f.hi_occ && f.block == 256 && f.kmax == 8)
+      return occ_t<256, 8, true, false, false, false, 5>(f.maxV, f.maxE, f.maxF, f.edges_out != 0);
     CM_FWD_DISPATCH(occ_t, f.maxV, f.maxE, f.maxF, f.edges_out != 0)
   } else {
     constexpr bool DYNV = false;
@@ -420,12 +427,34 @@ int fwd_occupancy(const FwdLaunch& f) {
 }
 
 int fwd_place_edges(FwdLaunch& f) {
+  f.hi_occ = 0;
   f.edges_out = 0;
   const int in = fwd_occupancy(f);
   f.edges_out = 1;
   const int out = fwd_occupancy(f);
   f.edges_out = out > in ? 1 : 0;
-  return out > in ? out : in;
+  const int best = out > in ? out : in;
+  // the full method's work-queue kernel at K 8 in 256-thread blocks, for
+  // polytopes of at least 128 edges: take the 5-wave variant where it fits
+  // more workgroups per CU than the default (hulls of 64 points, 186 edges:
+  // 623 -> 613 ms; the mixed scenes, at most 90 edges, lost 99 -> 110 ms)
+  if (f.queue && f.block == 256 && f.kmax == 8 && f.maxE >= 128 && f.prm.presel_v == 0 && !f.prm.sq &&
+      f.prm.refine == 0) {
+    const int edges_out = f.edges_out;
+    f.hi_occ = 1;
+    f.edges_out = 0;
+    const int in5 = fwd_occupancy(f);
+    f.edges_out = 1;
+    const int out5 = fwd_occupancy(f);
+    const int best5 = out5 > in5 ? out5 : in5;
+    if (best5 > best) {
+      f.edges_out = out5 > in5 ? 1 : 0;
+      return best5;
+    }
+    f.hi_occ = 0;
+    f.edges_out = edges_out;
+  }
+  return best;
 }
 
 }  // namespace cm

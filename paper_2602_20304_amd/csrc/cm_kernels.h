@@ -33,6 +33,7 @@ struct FwdLaunch {
   long long scratch_stride;
   int maxV, maxE, maxF;        // LDS sizing (context-wide maxima)
   int edges_out = 0;           // 1: the edge arrays live in the scratch slot (fwd_place_edges)
+  int hi_occ = 0;              // 1: the kernel's higher-occupancy variant (fwd_place_edges, bwd_place)
   TapeDev tape;                // optional adjoint tape written by the forward kernel
   const int* order;            // optional pair order (cost-sorted), or null
   const int* range;            // optional device int2 {start, count} into order, or null
@@ -85,8 +86,12 @@ struct BwdLaunch {
 };
 
 int fwd_lds_bytes(int maxV, int maxE, int maxF, int block, int kmax, bool presel = false, bool edges_out = false);
-int bwd_lds_bytes(int maxV, int maxE, int maxF, int block, bool presel = false);
+int bwd_lds_bytes(int maxV, int maxE, int maxF, int block, bool presel = false, bool edges_out = false);
 int bwd_occupancy(const BwdLaunch& b);
+// Chooses the adjoint's edge placement (LDS or scratch slot) and register
+// budget (b.f.edges_out, b.f.hi_occ) for the most waves per SIMD; returns
+// the workgroups per CU of the choice.
+int bwd_place(BwdLaunch& b);
 hipError_t launch_collide_bwd(const BwdLaunch& b, hipStream_t st);
 int fwd_occupancy(const FwdLaunch& f);
 // Zeroes the tape's pool counter (a kernel, so it can sit in a captured graph).

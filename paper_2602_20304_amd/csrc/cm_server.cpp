@@ -311,7 +311,7 @@ void launch_request(cm_server* srv, Request& r) {
     b.f.tape.pool_used = nullptr;
     b.cot = CotDev{d_cp, d_cn, d_cd, d_cw};
     b.gr = GradDev{d_gpose, d_gvert, d_gpar, d_gtau, (long long)r.pool};
-    b.f.grid = int(std::min<long long>(request_grid(ctx, bwd_occupancy(b), cap), f.grid));   // fits the forward's scratch
+    b.f.grid = int(std::min<long long>(request_grid(ctx, bwd_place(b), cap), f.grid));   // fits the forward's scratch
     if (launch_counter_reset(d_bq, st) != hipSuccess || launch_collide_bwd(b, st) != hipSuccess) {
       r.status = CM_ERR_DEVICE;
       return;
