@@ -151,8 +151,9 @@ __global__ __launch_bounds__(256) void bp_emit(Tables tb, BatchDev bt, float mar
 // At K = 16 the largest uneven pairs fill a CU's LDS with two workgroups,
 // so a tighter register budget only adds spills (4 waves: 7.64 -> 7.81 s
 // for that class).
-// WAVES > 0 overrides the target (the work-queue kernel of the full method at
-// K 8 has a 5-wave variant, chosen where LDS leaves room for the fifth wave).
+// WAVES > 0 overrides the target (the work-queue kernel of the full method has
+// a 5-wave variant at K 8 and a 4-wave one at K 16, chosen where LDS leaves
+// room for the extra workgroups).
 template <int BLOCK, int KMAX, bool DYN, bool PRESEL = false, bool SQ = false, bool REFINE = false, int WAVES = 0>
 __global__ __launch_bounds__(BLOCK)
 __attribute__((amdgpu_waves_per_eu(WAVES > 0 ? WAVES : ((KMAX <= 8 && !SQ && !REFINE) ? 4 : 2))))
@@ -377,6 +378,7 @@ hipError_t launch_collide_fwd(const FwdLaunch& f, hipStream_t st) {
   if (f.queue) {
     constexpr bool DYNV = true;
     if (f.hi_occ && f.block == 256 && f.kmax == 8) return launch_fwd_t<256, 8, true, false, false, false, 5>(f, st);
+    if (f.hi_occ && f.block == 256 && f.kmax == 16) return launch_fwd_t<256, 16, true, false, false, false, 4>(f, st);
     if (f.block == 64) {   // single-wave workgroups: the fused path's small pairs
       if (f.kmax == 8) return launch_fwd_t<64, 8, true>(f, st);
       if (f.kmax == 16) return launch_fwd_t<64, 16, true>(f, st);
@@ -419,6 +421,8 @@ int fwd_occupancy(const FwdLaunch& f) {
     }
     if (f.hi_occ && f.block == 256 && f.kmax == 8)
       return occ_t<256, 8, true, false, false, false, 5>(f.maxV, f.maxE, f.maxF, f.edges_out != 0);
+    if (f.hi_occ && f.block == 256 && f.kmax == 16)
+      return occ_t<256, 16, true, false, false, false, 4>(f.maxV, f.maxE, f.maxF, f.edges_out != 0);
     CM_FWD_DISPATCH(occ_t, f.maxV, f.maxE, f.maxF, f.edges_out != 0)
   } else {
     constexpr bool DYNV = false;
@@ -434,12 +438,15 @@ int fwd_place_edges(FwdLaunch& f) {
   const int out = fwd_occupancy(f);
   f.edges_out = out > in ? 1 : 0;
   const int best = out > in ? out : in;
-  // the full method's work-queue kernel at K 8 in 256-thread blocks, for
-  // polytopes of at least 128 edges: take the 5-wave variant where it fits
-  // more workgroups per CU than the default (hulls of 64 points, 186 edges:
-  // 623 -> 613 ms; the mixed scenes, at most 90 edges, lost 99 -> 110 ms)
-  if (f.queue && f.block == 256 && f.kmax == 8 && f.maxE >= 128 && f.prm.presel_v == 0 && !f.prm.sq &&
-      f.prm.refine == 0) {
+  // the full method's work-queue kernel in 256-thread blocks: take the
+  // higher-occupancy variant where it fits more workgroups per CU than the
+  // default; at K 8 (5 waves) for polytopes of at least 128 edges only
+  // (hulls of 64 points, 186 edges: 623 -> 613 ms; the mixed scenes, at most
+  // 90 edges, lost 99 -> 110 ms), at K 16 (4 waves) whatever the size (the
+  // uneven workload's middle class: 698 -> 480 ms; its largest class, two
+  // workgroups per CU either way, keeps the default)
+  if (f.queue && f.block == 256 && ((f.kmax == 8 && f.maxE >= 128) || f.kmax == 16) && f.prm.presel_v == 0 &&
+      !f.prm.sq && f.prm.refine == 0) {
     const int edges_out = f.edges_out;
     f.hi_occ = 1;
     f.edges_out = 0;
