@@ -6,7 +6,10 @@
   than 300 edges (the fused path's largest size class, no face culling above
   128 faces, edge arrays outside LDS);
 * the forward, plain and fused, on uneven-workload pairs whose bodies both
-  have more than 200 vertices (up to 762 edges), beside a random sample.
+  have more than 200 vertices (up to 762 edges), beside a random sample;
+* the forward, plain and fused, on the differentiation, mixed and uneven
+  workloads at their full benchmark sizes (the launch shapes the benchmark
+  times), checked on a seeded sample of kept pairs.
 
 The FP64 oracle is the reference throughout (gradients: its autograd).
 """
@@ -99,3 +102,50 @@ def test_forward_uneven_both_bodies_above_200_vertices(ctx):
         ok, rep = compare_outputs(got, ref, idx=sel)
         _say(f"   parity uneven (fused={fused}): {rep}")
         assert ok, rep
+
+
+def _full_size_forward(ctx, b, n_sample, seed, extra=(), bp=None):
+    """The workload as the benchmark runs it (plain and fused launches over
+    the whole batch), then the FP64 oracle on a seeded sample of kept pairs
+    (the first, the last, any listed ones and n_sample random ones):
+    broadphase and offsets bit-exact, sampled outputs within the bar."""
+    pairs, off = bp if bp is not None else O.broadphase(b)
+    rng = np.random.default_rng(seed)
+    sel = np.unique(np.concatenate([[0, pairs.shape[1] - 1], np.asarray(extra, dtype=np.int64),
+                                    rng.choice(pairs.shape[1], n_sample, replace=False)]))
+    _say(f"[gpu] full size {b.name}: {pairs.shape[1]} kept pairs, {len(sel)} sampled for the oracle")
+    _, _, ref = O.collide_batch(b, pair_list=pairs[:, sel])
+    ids = ctx.create_geometry(b.geoms)
+    db = ctx.upload_batch(b, ids)
+    for fused in (False, True):
+        _say(f"   launch {b.name} fused={fused}")
+        m = ctx.collide(db, b.tau, b.K, fused=fused)
+        ctx.check_errors()
+        got = m.to_numpy()
+        assert np.array_equal(got["pairs"], pairs) and np.array_equal(got["offsets"], off)
+        ok, rep = compare_outputs(got, ref, idx=sel)
+        _say(f"   parity {b.name} (fused={fused}): {rep}")
+        assert ok, rep
+
+
+def test_forward_full_size_differentiation_workload(ctx):
+    """16,384 scenes x 4 hulls of 64 points, tau 0.01, K 8 (the headline
+    workload, same seed as the benchmark): 30 sampled pairs."""
+    _full_size_forward(ctx, W.polytope_scenes(16384, seed=0, tau=0.01), 28, seed=70)
+
+
+def test_forward_full_size_mixed_workload(ctx):
+    """65,536 scenes x 8 mixed bodies (same seed as the benchmark): 34
+    sampled pairs."""
+    _full_size_forward(ctx, W.mixed_scenes(65536, seed=0), 32, seed=71)
+
+
+def test_forward_full_size_uneven_workload(ctx):
+    """100,000 uneven scenes at K 16 (same seed as the benchmark): the pair
+    of the two largest hulls (256 points each for this seed), the first and
+    last kept pairs and 8 random ones."""
+    b = W.uneven_scenes(100_000, seed=0)
+    pairs, off = O.broadphase(b)
+    nv = _vertex_counts(b)
+    big = int(np.argmax(nv[pairs[0]].astype(np.int64) * nv[pairs[1]]))
+    _full_size_forward(ctx, b, 8, seed=72, extra=[big], bp=(pairs, off))
