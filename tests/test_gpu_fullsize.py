@@ -9,7 +9,9 @@
   have more than 200 vertices (up to 762 edges), beside a random sample;
 * the forward, plain and fused, on the differentiation, mixed and uneven
   workloads at their full benchmark sizes (the launch shapes the benchmark
-  times), checked on a seeded sample of kept pairs.
+  times), checked on a seeded sample of kept pairs;
+* the adjoint over the whole differentiation workload, with cotangents on
+  the pairs of two sampled scenes only.
 
 The FP64 oracle is the reference throughout (gradients: its autograd).
 """
@@ -22,6 +24,7 @@ import workloads as W
 from oracle import cm_oracle as O
 from tests.parity import compare_outputs
 from tests.test_gpu_backward import check as check_grads
+from tests.test_gpu_backward import close, oracle_grads
 
 pytestmark = pytest.mark.gpu
 
@@ -149,3 +152,66 @@ def test_forward_full_size_uneven_workload(ctx):
     nv = _vertex_counts(b)
     big = int(np.argmax(nv[pairs[0]].astype(np.int64) * nv[pairs[1]]))
     _full_size_forward(ctx, b, 8, seed=72, extra=[big], bp=(pairs, off))
+
+
+def test_backward_full_size_differentiation_workload(ctx):
+    """The adjoint over the whole headline workload (16,384 scenes x 4 hulls
+    of 64 points, tau 0.01, K 8, the benchmark's seed and launch shapes),
+    with cotangents that are nonzero only on the kept pairs of two sampled
+    scenes: the pose, hull-vertex and tau gradients of those scenes' bodies
+    equal the FP64 oracle's autograd of those pairs, and every other body's
+    gradients are exactly zero (the adjoint is linear in the cotangents)."""
+    import torch
+    b = W.polytope_scenes(16384, seed=0, tau=0.01)
+    K = b.K
+    ids = ctx.create_geometry(b.geoms)
+    db = ctx.upload_batch(b, ids)
+    _say("[gpu-bwd] full size differentiation workload: forward")
+    m = ctx.collide(db, b.tau, K)
+    ctx.check_errors()
+    fwd = m.to_numpy()
+    pairs, off = fwd["pairs"], fwd["offsets"]
+    rng = np.random.default_rng(73)
+    scenes = np.sort(rng.choice(b.n_scenes, 2, replace=False))
+    sel = np.concatenate([np.arange(off[s], off[s + 1]) for s in scenes])
+    cap = m.capacity
+    cot = {k: np.zeros(s, np.float32) for k, s in
+           (("p", (3, cap * K)), ("nu", (3, cap * K)), ("d", (cap * K,)), ("w", (cap * K,)))}
+    for i in sel:
+        sl = slice(int(i) * K, (int(i) + 1) * K)
+        cot["p"][:, sl] = rng.standard_normal((3, K))
+        cot["nu"][:, sl] = rng.standard_normal((3, K))
+        cot["d"][sl] = rng.standard_normal(K)
+        cot["w"][sl] = rng.standard_normal(K)
+    tt = {k: torch.as_tensor(v).to(ctx.device) for k, v in cot.items()}
+    _say(f"[gpu-bwd] adjoint over {pairs.shape[1]} pairs, cotangents on scenes {list(scenes)} ({len(sel)} pairs)")
+    g = ctx.collide_backward(db, m, b.tau, K, tt["p"], tt["nu"], tt["d"], tt["w"])
+    ctx.check_errors()
+    g = {k: (v.cpu().numpy() if v is not None else None) for k, v in g.items()}
+    sub = {k: (v[:, np.concatenate([np.arange(int(i) * K, (int(i) + 1) * K) for i in sel])] if v.ndim == 2
+               else v[np.concatenate([np.arange(int(i) * K, (int(i) + 1) * K) for i in sel])]) for k, v in cot.items()}
+    g_pose, g_geom, g_tau, _ = oracle_grads(b, pairs[:, sel], sub, K)
+    bodies = np.unique(pairs[:, sel])
+    rep = {"pose": close(g["pose"][:, bodies], g_pose[:, bodies])}
+    vx, vr = [], []
+    for gid, ref in g_geom.items():
+        info = ctx.geometry_info(int(ids[gid]))
+        o = info["vertex_offset"]
+        vx.append(g["vertices"][:, o:o + info["n_vertices"]].T)
+        vr.append(ref)
+    rep["vertices"] = close(np.concatenate(vx), np.concatenate(vr))
+    rep["tau"] = close([g["tau"][0]], [g_tau])
+    _say("   full-size grad parity: " +
+         ", ".join(f"{k}: excess {v[0]:.2e} maxabs {v[1]:.2e} scale {v[2]:.2e}" for k, v in rep.items()))
+    for k, v in rep.items():
+        assert v[0] <= 0, (k, v)
+    others = np.setdiff1d(np.arange(b.n_bodies), bodies)
+    assert not np.any(g["pose"][:, others]), "pose gradients outside the sampled scenes"
+    touched = set(int(ids[b.body_geom[x]]) for x in bodies)
+    for x in others[:: max(1, len(others) // 64)]:
+        gid = int(ids[b.body_geom[x]])
+        if gid in touched:
+            continue
+        info = ctx.geometry_info(gid)
+        o = info["vertex_offset"]
+        assert not np.any(g["vertices"][:, o:o + info["n_vertices"]]), "vertex gradients outside the sampled scenes"
